@@ -1,0 +1,480 @@
+/*
+ * FP64 CPU oracle for moving-source image-source synthesis.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the GPU library; it is written from the paper's
+ * definitions, plainly and slowly, in double precision.
+ *
+ * What it computes (paper: "Fast Algorithm for Moving Sound Source",
+ * arXiv 2508.03065):
+ *   - Image sources of a shoebox room (image-source method, Sec. II-A, the
+ *     static RIR of Eq. (1)); gain A_i = beta_i / (4 pi d_i) with beta_i the
+ *     product of the wall coefficients along the path (Sec. II-A, the text
+ *     after Eq. (2)).
+ *   - Moving-image output v(t) = sum_i A_i(t) s(t - tau_i(t))  (Eq. (2), Eq. (8)),
+ *     with tau_i = d_i / c (Sec. II-C-3) taken at the emission time (retarded
+ *     reading) or at the reception time (instantaneous reading).
+ *   - The fractional delay is an FIR truncation of the ideal sinc response
+ *     (Sec. II-B); here a T-tap Kaiser-windowed sinc, evaluated exactly from
+ *     its formula at every tap (no table).
+ *   - Order-tiered trajectory sampling (Sec. II-C-3): delays solved exactly on a
+ *     decimated grid and brought back to the audio rate by uniform Catmull-Rom
+ *     interpolation of tau ("tier-emulating" mode).  With no tiers every
+ *     image's exact delay is solved at every output sample ("full-rate" mode).
+ *   - Adjoints: the exact transpose of the time-varying delay (d loss / d x) and
+ *     d loss / d beta_w via the product structure of beta_i.
+ *
+ * Parity pins live in tests/test_oracle_pins.py.  Every function is pinned
+ * there by a closed form, a library routine, an independent brute force or an
+ * invariant; none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ types */
+
+typedef struct {
+    int32_t kind;        /* 0: piecewise linear through knots (1 knot = static), 1: horizontal circle */
+    int32_t n_points;    /* number of knots (kind 0) */
+    const double* t;     /* [n_points] knot times in s, strictly increasing */
+    const double* p;     /* [n_points*3] knot positions in m */
+    double center[3];    /* circle centre (kind 1); motion in the plane z = center[2] */
+    double radius;       /* circle radius, m */
+    double speed;        /* speed along the circle, m/s */
+    double phase0;       /* angle at t = 0, rad */
+} orc_traj;
+
+typedef struct {
+    double size[3];          /* room Lx, Ly, Lz in m */
+    double beta[6];          /* wall coefficients: x=0, x=Lx, y=0, y=Ly, z=0, z=Lz */
+    orc_traj src, rcv;
+    int32_t n_mics;
+    const double* mic_offset;    /* [n_mics*3], added to the receiver position */
+    int64_t n_in, n_out;
+} orc_scene;
+
+typedef struct {
+    double c, fs;
+    int32_t max_order;       /* K: images with |mx|+|my|+|mz| <= K */
+    int32_t taps;            /* T (even) */
+    double kaiser_beta;
+    double cutoff;           /* normalised cutoff f_c in cycles/sample (0.5 = full band) */
+    int32_t n_tiers;         /* 0: full rate; else tiers as below */
+    int32_t tier_max_order[4];
+    int32_t tier_decim[4];
+    int32_t delay_model;     /* 0: retarded (emission-time) delay, 1: instantaneous */
+} orc_params;
+
+/* ----------------------------------------------------- image enumeration */
+
+/* Number of integer triples with |mx|+|my|+|mz| <= K, counted one by one. */
+int64_t orc_count_images(int32_t K)
+{
+    int64_t n = 0;
+    for (int mx = -K; mx <= K; ++mx)
+        for (int my = -K; my <= K; ++my)
+            for (int mz = -K; mz <= K; ++mz)
+                if (abs(mx) + abs(my) + abs(mz) <= K) ++n;
+    return n;
+}
+
+/* Wall hits of an axis index m: the image at index m along an axis is reached
+ * after |m| reflections alternating between the two walls of that axis.  For
+ * m > 0 the first reflection is on the far wall (coordinate L), for m < 0 on
+ * the near wall (coordinate 0). */
+static void axis_hits(int m, int* n_near, int* n_far)
+{
+    int a = abs(m);
+    if (m >= 0) { *n_far = (a + 1) / 2; *n_near = a / 2; }
+    else        { *n_near = (a + 1) / 2; *n_far = a / 2; }
+}
+
+/* Fills m[n*3] and hits[n*6] (wall order x0,xL,y0,yL,z0,zL) and beta_i[n];
+ * returns the image count.  Any of the output pointers may be NULL. */
+int64_t orc_images(const double* beta, int32_t K, int32_t* m, int32_t* hits, double* beta_i)
+{
+    int64_t n = 0;
+    for (int mx = -K; mx <= K; ++mx)
+        for (int my = -K; my <= K; ++my)
+            for (int mz = -K; mz <= K; ++mz) {
+                if (abs(mx) + abs(my) + abs(mz) > K) continue;
+                int mm[3] = {mx, my, mz};
+                int h[6];
+                for (int a = 0; a < 3; ++a) axis_hits(mm[a], &h[2 * a], &h[2 * a + 1]);
+                double b = 1.0;
+                for (int w = 0; w < 6; ++w)
+                    for (int r = 0; r < h[w]; ++r) b *= beta[w];
+                if (m) { m[3 * n] = mx; m[3 * n + 1] = my; m[3 * n + 2] = mz; }
+                if (hits) for (int w = 0; w < 6; ++w) hits[6 * n + w] = h[w];
+                if (beta_i) beta_i[n] = b;
+                ++n;
+            }
+    return n;
+}
+
+/* Position of image m of a point q: per axis, the mirrored copy in cell m. */
+static void image_point(const double L[3], const int m[3], const double q[3], double out[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (m[a] % 2 == 0) out[a] = m[a] * L[a] + q[a];
+        else               out[a] = (m[a] + 1) * L[a] - q[a];
+    }
+}
+
+/* Exported for the tests: image of point q in cell m. */
+void orc_image_pos(const double* size, const int32_t* m, const double* q, double* out)
+{
+    int mm[3] = {m[0], m[1], m[2]};
+    image_point(size, mm, q, out);
+}
+
+/* ---------------------------------------------------------- trajectories */
+
+void orc_traj_pos(const orc_traj* tr, double t, double out[3])
+{
+    if (tr->kind == 1) {
+        double w = tr->speed / tr->radius;
+        out[0] = tr->center[0] + tr->radius * cos(w * t + tr->phase0);
+        out[1] = tr->center[1] + tr->radius * sin(w * t + tr->phase0);
+        out[2] = tr->center[2];
+        return;
+    }
+    int np = tr->n_points;
+    const double* P = tr->p;
+    if (np == 1 || t <= tr->t[0]) { out[0] = P[0]; out[1] = P[1]; out[2] = P[2]; return; }
+    if (t >= tr->t[np - 1]) {
+        out[0] = P[3 * (np - 1)]; out[1] = P[3 * (np - 1) + 1]; out[2] = P[3 * (np - 1) + 2];
+        return;
+    }
+    int a = 0;
+    while (!(t >= tr->t[a] && t < tr->t[a + 1])) ++a;
+    double lam = (t - tr->t[a]) / (tr->t[a + 1] - tr->t[a]);
+    for (int k = 0; k < 3; ++k) out[k] = P[3 * a + k] + lam * (P[3 * (a + 1) + k] - P[3 * a + k]);
+}
+
+static void mic_pos(const orc_scene* s, int mic, double t, double out[3])
+{
+    orc_traj_pos(&s->rcv, t, out);
+    for (int k = 0; k < 3; ++k) out[k] += s->mic_offset[3 * mic + k];
+}
+
+/* Distance from mic (at reception time t) to the image of the source at time te. */
+static double image_dist(const orc_scene* s, const int m[3], const double r[3], double te)
+{
+    double q[3], pi[3];
+    orc_traj_pos(&s->src, te, q);
+    image_point(s->size, m, q, pi);
+    double dx = pi[0] - r[0], dy = pi[1] - r[1], dz = pi[2] - r[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Propagation delay (s) of image m to mic `mic` for sound received at time t.
+ * Retarded: the unique tau > 0 with c tau = |p_i(t - tau) - r(t)| (the wave
+ * received at t left the image at t - tau); solved by fixed-point iteration,
+ * which contracts with factor |source speed| / c.  Instantaneous:
+ * tau = |p_i(t) - r(t)| / c. */
+double orc_tau(const orc_scene* s, const orc_params* p, const int32_t m[3], int mic, double t)
+{
+    double r[3];
+    mic_pos(s, mic, t, r);
+    int mm[3] = {m[0], m[1], m[2]};
+    double tau = image_dist(s, mm, r, t) / p->c;
+    if (p->delay_model == 1) return tau;
+    for (int it = 0; it < 200; ++it) {
+        double nt = image_dist(s, mm, r, t - tau) / p->c;
+        double d = fabs(nt - tau);
+        tau = nt;
+        if (d <= 2e-15 * tau) break;
+    }
+    return tau;
+}
+
+/* ------------------------------------------------- fractional delay kernel */
+
+/* Modified Bessel function of the first kind, order 0: sum_k ((x/2)^k / k!)^2. */
+double orc_i0(double x)
+{
+    double q = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+/* Kaiser-windowed sinc: h(u) = 2 fc sinc(2 fc u) w(u), with
+ * w(u) = I0(beta sqrt(1 - (2u/T)^2)) / I0(beta) on |u| <= T/2, zero outside. */
+double orc_kernel(double u, int32_t T, double kbeta, double fc)
+{
+    double half = 0.5 * T;
+    if (fabs(u) > half) return 0.0;
+    double z = 2.0 * fc * u;
+    double sinc = (z == 0.0) ? 1.0 : sin(M_PI * z) / (M_PI * z);
+    double r = 2.0 * u / T;
+    double arg = 1.0 - r * r;
+    if (arg < 0.0) arg = 0.0;
+    double w = orc_i0(kbeta * sqrt(arg)) / orc_i0(kbeta);
+    return 2.0 * fc * sinc * w;
+}
+
+/* ----------------------------------------------------------- tiered delays */
+
+/* Uniform Catmull-Rom through v[0..3] (knots at -1, 0, 1, 2), evaluated at u in [0,1). */
+double orc_catmull_rom(const double v[4], double u)
+{
+    double a = v[0], b = v[1], c = v[2], d = v[3];
+    return 0.5 * (2.0 * b + (c - a) * u + (2.0 * a - 5.0 * b + 4.0 * c - d) * u * u
+                  + (3.0 * b - a - 3.0 * c + d) * u * u * u);
+}
+
+static int order_of(const int32_t m[3]) { return abs(m[0]) + abs(m[1]) + abs(m[2]); }
+
+/* Decimation factor of an image: the first tier whose max order covers it. */
+static int decim_of(const orc_params* p, const int32_t m[3])
+{
+    if (p->n_tiers <= 0) return 0;
+    int o = order_of(m);
+    for (int k = 0; k < p->n_tiers; ++k)
+        if (o <= p->tier_max_order[k]) return p->tier_decim[k];
+    return p->tier_decim[p->n_tiers - 1];
+}
+
+/* Delay of image m at output sample n: exact (full rate) or Catmull-Rom of the
+ * exact delays at grid samples kR (tier-emulating). */
+static double tau_at(const orc_scene* s, const orc_params* p, const int32_t m[3], int mic, int64_t n)
+{
+    int R = decim_of(p, m);
+    if (R <= 1) return orc_tau(s, p, m, mic, (double)n / p->fs);
+    int64_t k = n / R;
+    double u = (double)(n - k * R) / (double)R;
+    double v[4];
+    for (int q = 0; q < 4; ++q) v[q] = orc_tau(s, p, m, mic, (double)((k - 1 + q) * R) / p->fs);
+    return orc_catmull_rom(v, u);
+}
+
+/* Grid of exact delays for one (image, mic): g[k+1] = tau(kR/fs), k = -1 .. nk+1. */
+static double* tau_grid(const orc_scene* s, const orc_params* p, const int32_t m[3], int mic, int R, int64_t* len)
+{
+    int64_t nk = (s->n_out + R - 1) / R;
+    int64_t L = nk + 3;
+    double* g = (double*)malloc(sizeof(double) * L);
+    for (int64_t k = -1; k <= nk + 1; ++k) g[k + 1] = orc_tau(s, p, m, mic, (double)(k * R) / p->fs);
+    *len = L;
+    return g;
+}
+
+/* ------------------------------------------------------------- synthesis */
+
+typedef struct {
+    int64_t n_img;
+    int32_t* m;
+    int32_t* hits;
+    double* beta;
+} img_set;
+
+static img_set make_images(const orc_scene* s, const orc_params* p)
+{
+    img_set I;
+    I.n_img = orc_count_images(p->max_order);
+    I.m = (int32_t*)malloc(sizeof(int32_t) * 3 * I.n_img);
+    I.hits = (int32_t*)malloc(sizeof(int32_t) * 6 * I.n_img);
+    I.beta = (double*)malloc(sizeof(double) * I.n_img);
+    orc_images(s->beta, p->max_order, I.m, I.hits, I.beta);
+    return I;
+}
+
+static void free_images(img_set* I) { free(I->m); free(I->hits); free(I->beta); }
+
+/* Per-(image, mic) delay source: cached grid (tiered, all outputs) or on the fly. */
+typedef struct {
+    const orc_scene* s;
+    const orc_params* p;
+    double** grid;   /* [n_img] or NULL */
+    int* R;          /* [n_img] */
+} delay_src;
+
+static double delay_of(const delay_src* ds, const img_set* I, int64_t i, int mic, int64_t n)
+{
+    const int32_t* m = I->m + 3 * i;
+    if (ds->grid && ds->grid[i]) {
+        int R = ds->R[i];
+        int64_t k = n / R;
+        double u = (double)(n - k * R) / (double)R;
+        return orc_catmull_rom(ds->grid[i] + k, u);   /* grid[k] holds tau at (k-1)R */
+    }
+    return tau_at(ds->s, ds->p, m, mic, n);
+}
+
+static void build_grids(delay_src* ds, const img_set* I, int mic)
+{
+    ds->grid = (double**)calloc(I->n_img, sizeof(double*));
+    ds->R = (int*)calloc(I->n_img, sizeof(int));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < I->n_img; ++i) {
+        int R = decim_of(ds->p, I->m + 3 * i);
+        ds->R[i] = R;
+        if (R > 1) {
+            int64_t len;
+            ds->grid[i] = tau_grid(ds->s, ds->p, I->m + 3 * i, mic, R, &len);
+        }
+    }
+}
+
+static void free_grids(delay_src* ds, int64_t n)
+{
+    if (!ds->grid) return;
+    for (int64_t i = 0; i < n; ++i) free(ds->grid[i]);
+    free(ds->grid); free(ds->R);
+    ds->grid = NULL; ds->R = NULL;
+}
+
+/* Contribution of image i to output n of one mic: gain and filtered signal.
+ * s_i(n) = sum_j h(j - mu) x[n - floor(D) - j], j = -T/2+1 .. T/2, D = fs tau, mu = D - floor(D). */
+static double filtered(const orc_params* p, const double* x, int64_t n_in, int64_t n, double tau)
+{
+    double D = p->fs * tau;
+    double Kf = floor(D);
+    double mu = D - Kf;
+    int64_t K = (int64_t)Kf;
+    int T = p->taps;
+    double acc = 0.0;
+    for (int j = -T / 2 + 1; j <= T / 2; ++j) {
+        int64_t idx = n - K - j;
+        if (idx < 0 || idx >= n_in) continue;
+        acc += orc_kernel((double)j - mu, T, p->kaiser_beta, p->cutoff) * x[idx];
+    }
+    return acc;
+}
+
+/* y[mic][k] for output samples idx[k] (or all n_out samples when idx is NULL). */
+int orc_forward(const orc_scene* s, const orc_params* p, const double* x,
+                int64_t n_idx, const int64_t* idx, double* y)
+{
+    img_set I = make_images(s, p);
+    int64_t ny = idx ? n_idx : s->n_out;
+    for (int mic = 0; mic < s->n_mics; ++mic) {
+        delay_src ds = {s, p, NULL, NULL};
+        if (!idx && p->n_tiers > 0) build_grids(&ds, &I, mic);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < ny; ++k) {
+            int64_t n = idx ? idx[k] : k;
+            double acc = 0.0;
+            for (int64_t i = 0; i < I.n_img; ++i) {
+                if (I.beta[i] == 0.0) continue;
+                double tau = delay_of(&ds, &I, i, mic, n);
+                double g = I.beta[i] / (4.0 * M_PI * p->c * tau);
+                acc += g * filtered(p, x, s->n_in, n, tau);
+            }
+            y[(int64_t)mic * ny + k] = acc;
+        }
+        free_grids(&ds, I.n_img);
+    }
+    free_images(&I);
+    return 0;
+}
+
+/* Exact transpose of the forward map x -> y:
+ * gx[m] = sum_{mic,i,n} gy[mic][n] g_i(n) h(j - mu_i(n)) where m = n - floor(D_i(n)) - j. */
+int orc_adjoint_x(const orc_scene* s, const orc_params* p, const double* gy, double* gx)
+{
+    img_set I = make_images(s, p);
+    int T = p->taps;
+    memset(gx, 0, sizeof(double) * s->n_in);
+    for (int mic = 0; mic < s->n_mics; ++mic) {
+        delay_src ds = {s, p, NULL, NULL};
+        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
+        const double* g_y = gy + (int64_t)mic * s->n_out;
+#pragma omp parallel
+        {
+            double* part = (double*)calloc(s->n_in, sizeof(double));
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t i = 0; i < I.n_img; ++i) {
+                if (I.beta[i] == 0.0) continue;
+                for (int64_t n = 0; n < s->n_out; ++n) {
+                    if (g_y[n] == 0.0) continue;
+                    double tau = delay_of(&ds, &I, i, mic, n);
+                    double g = I.beta[i] / (4.0 * M_PI * p->c * tau);
+                    double D = p->fs * tau;
+                    double Kf = floor(D), mu = D - Kf;
+                    int64_t K = (int64_t)Kf;
+                    for (int j = -T / 2 + 1; j <= T / 2; ++j) {
+                        int64_t m = n - K - j;
+                        if (m < 0 || m >= s->n_in) continue;
+                        part[m] += g_y[n] * g * orc_kernel((double)j - mu, T, p->kaiser_beta, p->cutoff);
+                    }
+                }
+            }
+#pragma omp critical
+            for (int64_t m = 0; m < s->n_in; ++m) gx[m] += part[m];
+            free(part);
+        }
+        free_grids(&ds, I.n_img);
+    }
+    free_images(&I);
+    return 0;
+}
+
+/* d loss / d beta_w for loss gradient gy = dL/dy.  The output is linear in each
+ * image gain, and beta_i = prod_w beta_w^{n_w}; so
+ * dL/dbeta_w = sum_i (d beta_i / d beta_w) * sum_{mic,n} gy[n] s_i(n) / (4 pi c tau_i(n)),
+ * with d beta_i / d beta_w = n_w beta_w^{n_w-1} prod_{w' != w} beta_w'^{n_w'}. */
+int orc_grad_beta(const orc_scene* s, const orc_params* p, const double* x, const double* gy, double* gbeta)
+{
+    img_set I = make_images(s, p);
+    double* G = (double*)calloc(I.n_img, sizeof(double));
+    for (int mic = 0; mic < s->n_mics; ++mic) {
+        delay_src ds = {s, p, NULL, NULL};
+        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
+        const double* g_y = gy + (int64_t)mic * s->n_out;
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t i = 0; i < I.n_img; ++i) {
+            double acc = 0.0;
+            for (int64_t n = 0; n < s->n_out; ++n) {
+                if (g_y[n] == 0.0) continue;
+                double tau = delay_of(&ds, &I, i, mic, n);
+                acc += g_y[n] * filtered(p, x, s->n_in, n, tau) / (4.0 * M_PI * p->c * tau);
+            }
+            G[i] += acc;
+        }
+        free_grids(&ds, I.n_img);
+    }
+    for (int w = 0; w < 6; ++w) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < I.n_img; ++i) {
+            const int32_t* h = I.hits + 6 * i;
+            if (h[w] == 0) continue;
+            double d = (double)h[w];
+            for (int r = 0; r < h[w] - 1; ++r) d *= s->beta[w];
+            for (int v = 0; v < 6; ++v) {
+                if (v == w) continue;
+                for (int r = 0; r < h[v]; ++r) d *= s->beta[v];
+            }
+            acc += d * G[i];
+        }
+        gbeta[w] = acc;
+    }
+    free(G);
+    free_images(&I);
+    return 0;
+}
+
+/* Exact delays of every image at the given output samples for one mic:
+ * tau[i * n_idx + k].  Used to time and inspect the delay model alone. */
+int orc_delays(const orc_scene* s, const orc_params* p, int mic, int64_t n_idx, const int64_t* idx, double* tau)
+{
+    img_set I = make_images(s, p);
+    delay_src ds = {s, p, NULL, NULL};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < I.n_img; ++i)
+        for (int64_t k = 0; k < n_idx; ++k) tau[i * n_idx + k] = delay_of(&ds, &I, i, mic, idx[k]);
+    free_images(&I);
+    return 0;
+}
