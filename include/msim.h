@@ -1,0 +1,162 @@
+/*
+ * msim: moving-source image-source synthesis on MI355X (gfx950).
+ *
+ * C-ABI of the synthesis library.  Implements the moving image-source model of
+ * "Fast Algorithm for Moving Sound Source" (arXiv 2508.03065):
+ *
+ *   y_c[n] = sum_i g_i(n) * (x fractionally delayed by D_i(n) samples)       (Eq. 2, Eq. 8)
+ *
+ * over every image source i of a shoebox room with total reflection order
+ * |mx|+|my|+|mz| <= K (image-source method, Sec. II-A, Eq. 1), with
+ *   D_i(n) = fs * tau_i(n),  tau_i = d_i / c                                   (Sec. II-C-3)
+ *   g_i(n) = beta_i / (4 pi c tau_i(n)),  beta_i = prod of wall coefficients   (Sec. II-A, after Eq. 2)
+ * The delay is sampled on an order-tiered grid (low orders at the audio rate,
+ * high orders decimated) and interpolated back to the audio rate (Sec. II-C-3).
+ * The fractional delay is a T-tap Kaiser-windowed sinc, an FIR truncation of the
+ * ideal sinc response of Sec. II-B, read from an oversampled table.
+ *
+ * Conventions
+ *  - Geometry in FP64, SI units; signals in FP32.
+ *  - Walls are ordered x=0, x=Lx, y=0, y=Ly, z=0, z=Lz.
+ *  - Taps j = -T/2+1 .. T/2 around floor(D); x is zero outside [0, n_in).
+ *  - Signal buffers are DEVICE pointers.  All scenes of a plan are packed back to
+ *    back: x holds scene 0's n_in samples, then scene 1's, ...; y holds, per
+ *    scene in order, n_mics rows of n_out samples (scene-major, mic, time).
+ *    msim_plan_layout() returns the offsets.
+ *  - Every entry point returns a status; nothing is thrown across the ABI.  On a
+ *    non-OK status msim_last_error() describes the failure (thread-local string).
+ *  - msim_forward / msim_backward enqueue work on the caller's stream and return
+ *    without synchronising; they allocate no device memory (all scratch lives in
+ *    the caller's workspace).  Plan creation allocates and synchronises.
+ */
+#ifndef MSIM_H
+#define MSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSIM_OK = 0,
+    MSIM_E_INVALID_ARG = 1,   /* a NULL pointer, a size <= 0, beta outside [0,1], T odd or outside 8..128, ... */
+    MSIM_E_OUTSIDE_ROOM = 2,  /* a knot or circle of a trajectory (or a mic) lies outside the room */
+    MSIM_E_TOO_CLOSE = 3,     /* source and a mic closer than 1 mm at a knot time */
+    MSIM_E_SUPERSONIC = 4,    /* a trajectory segment faster than c/10 */
+    MSIM_E_WORKSPACE = 5,     /* workspace NULL or smaller than msim_workspace_size() */
+    MSIM_E_UNSUPPORTED = 6,   /* a valid request this build does not implement */
+    MSIM_E_HIP = 7,           /* a HIP runtime call failed */
+    MSIM_E_DEVICE = 8         /* a device-side check failed (see msim_device_status) */
+} msim_status;
+
+enum { MSIM_TRAJ_PWL = 0, MSIM_TRAJ_CIRCLE = 1 };
+enum { MSIM_DELAY_RETARDED = 0, MSIM_DELAY_INSTANTANEOUS = 1 };
+
+/* A trajectory.  PWL: positions p[3k..3k+2] at strictly increasing times t[k],
+ * linear in between, held constant before t[0] and after t[n_points-1]; one knot
+ * is a static point.  CIRCLE: center + radius (cos(w t + phase0), sin(w t + phase0), 0),
+ * w = speed / radius.  Pointers are host memory, read during msim_plan_create only. */
+typedef struct {
+    int32_t kind;
+    int32_t n_points;
+    const double* t;
+    const double* p;
+    double center[3];
+    double radius;
+    double speed;
+    double phase0;
+} msim_traj;
+
+/* One scene: a room, a source path, a receiver path with n_mics microphones at
+ * fixed offsets from the receiver point, and the signal lengths. */
+typedef struct {
+    double size[3];             /* Lx, Ly, Lz (m) */
+    double beta[6];             /* wall reflection coefficients in [0, 1] */
+    msim_traj src;
+    msim_traj rcv;
+    int32_t n_mics;
+    const double* mic_offset;   /* host, [n_mics*3] */
+    int32_t max_order;          /* K >= 0 */
+    int64_t n_in;               /* source samples */
+    int64_t n_out;              /* output samples per mic */
+} msim_scene;
+
+/* Synthesis parameters shared by every scene of a plan. */
+typedef struct {
+    double c;                   /* speed of sound, m/s */
+    double fs;                  /* sample rate, Hz */
+    int32_t taps;               /* T: even, 8..128, multiple of 8 */
+    double kaiser_beta;         /* Kaiser window shape */
+    double cutoff;              /* normalised cutoff in (0, 0.5] cycles/sample */
+    int32_t table_phases;       /* L: table phases per unit delay (power of two, 64..4096) */
+    int32_t n_tiers;            /* 0: every image at the audio rate; 1..4 tiers below */
+    int32_t tier_max_order[4];  /* tier k holds orders <= tier_max_order[k] not in an earlier tier */
+    int32_t tier_decim[4];      /* decimation of tier k's delay grid (1 = audio rate), 1..4096 */
+    int32_t delay_model;        /* MSIM_DELAY_RETARDED (emission-time delay) or _INSTANTANEOUS */
+} msim_params;
+
+typedef struct msim_plan msim_plan;
+
+/* Fills defaults: c 343, fs 16000, T 64, Kaiser beta 8, cutoff 0.5, L 512,
+ * three tiers (orders <=2 at the audio rate, 3-6 decimated by 16, the rest by 160),
+ * retarded delays. */
+msim_status msim_default_params(msim_params* p);
+
+/* Number of images with |mx|+|my|+|mz| <= max_order. */
+msim_status msim_count_images(int32_t max_order, int64_t* n);
+
+/* An output length that holds every contribution: n_in + ceil(fs * d_max / c) + T,
+ * with d_max the largest distance from the room to an image cell of order <= K. */
+msim_status msim_suggest_n_out(const msim_scene* scene, const msim_params* p, int64_t* n_out);
+
+/* Validates the scenes, enumerates their images, sorts them by delay, builds the
+ * fractional-delay table and uploads the plan's device descriptors.  Runs on the
+ * current HIP device and synchronises.  *plan is owned by the caller and released
+ * with msim_plan_destroy. */
+msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const msim_params* p, msim_plan** plan);
+
+msim_status msim_plan_destroy(msim_plan* plan);
+
+/* Packed layout: x_off[s], y_off[s] (element offsets) for each scene, and totals. */
+msim_status msim_plan_layout(const msim_plan* plan, int64_t* x_off, int64_t* y_off, int64_t* x_total, int64_t* y_total);
+
+/* Image count of every scene, and the forward tap count
+ * sum over scenes, mics, images of (n_in + T - 1) * T. */
+msim_status msim_plan_stats(const msim_plan* plan, int64_t* n_images, double* forward_taps);
+
+/* Bytes of device workspace msim_forward (with_grad = 0) or msim_backward
+ * (with_grad = 1) needs; the caller allocates it (256-byte aligned). */
+msim_status msim_workspace_size(const msim_plan* plan, int32_t with_grad, size_t* bytes);
+
+/* Forward synthesis, one scene after another with ordinary launches.
+ * x: device [x_total] FP32; y: device [y_total] FP32, fully overwritten. */
+msim_status msim_forward(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reads and clears the plan's device-side status flags (synchronises the stream).
+ * Bit 0: a delay left the window the plan bounded for it (output not trusted). */
+msim_status msim_device_status(msim_plan* plan, hipStream_t stream, int32_t* flags);
+
+/* Per-kernel timing.  Between msim_profile_begin and msim_profile_end every
+ * kernel the plan launches is bracketed by HIP events on its stream;
+ * msim_profile_end waits for them and returns the summed durations (ms) and
+ * launch counts per kernel kind.  Profiling adds host work per launch only. */
+typedef struct {
+    double tracks_ms, synth_ms, reduce_ms, adjoint_ms, params_ms;
+    int32_t tracks_launches, synth_launches, reduce_launches, adjoint_launches, params_launches;
+} msim_profile;
+
+msim_status msim_profile_begin(msim_plan* plan);
+msim_status msim_profile_end(msim_plan* plan, msim_profile* out);
+
+/* Thread-local description of the last failure. */
+const char* msim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSIM_H */

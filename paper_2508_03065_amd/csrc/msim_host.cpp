@@ -1,0 +1,757 @@
+// Host side of the msim C-ABI: validation, image enumeration, delay-sorted
+// grouping, the fractional-delay table, workspace sizing and launch order.
+#include "../../include/msim.h"
+#include "msim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace msim;
+
+namespace {
+
+thread_local std::string g_err;
+
+msim_status fail(msim_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(MSIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxOut = int64_t(1) << 23;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^k / k!)^2.
+double bessel_i0(double x)
+{
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 1000 && term > 1e-17 * sum; ++k) {
+        term *= q / (double(k) * double(k));
+        sum += term;
+    }
+    return sum;
+}
+
+// Kaiser-windowed sinc fractional-delay kernel, h(v) on |v| <= T/2.
+double fd_kernel(double v, int T, double kbeta, double fc, double i0b)
+{
+    if (std::fabs(v) > 0.5 * T) return 0.0;
+    const double z = 2.0 * fc * v;
+    const double sinc = (z == 0.0) ? 1.0 : std::sin(kPi * z) / (kPi * z);
+    const double r = 2.0 * v / T;
+    const double w = bessel_i0(kbeta * std::sqrt(std::max(0.0, 1.0 - r * r))) / i0b;
+    return 2.0 * fc * sinc * w;
+}
+
+struct Box {
+    double lo[3], hi[3];
+};
+
+Box traj_box(const msim_traj& tr)
+{
+    Box b;
+    if (tr.kind == MSIM_TRAJ_CIRCLE) {
+        for (int a = 0; a < 2; ++a) {
+            b.lo[a] = tr.center[a] - tr.radius;
+            b.hi[a] = tr.center[a] + tr.radius;
+        }
+        b.lo[2] = b.hi[2] = tr.center[2];
+        return b;
+    }
+    for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = tr.p[a];
+    for (int k = 1; k < tr.n_points; ++k)
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = std::min(b.lo[a], tr.p[3 * k + a]);
+            b.hi[a] = std::max(b.hi[a], tr.p[3 * k + a]);
+        }
+    return b;
+}
+
+bool inside(const double p[3], const double L[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(p[a] > 0.0 && p[a] < L[a])) return false;
+    return true;
+}
+
+void traj_at(const msim_traj& tr, double t, double out[3])
+{
+    if (tr.kind == MSIM_TRAJ_CIRCLE) {
+        const double w = tr.speed / tr.radius;
+        out[0] = tr.center[0] + tr.radius * std::cos(w * t + tr.phase0);
+        out[1] = tr.center[1] + tr.radius * std::sin(w * t + tr.phase0);
+        out[2] = tr.center[2];
+        return;
+    }
+    const int n = tr.n_points;
+    if (n == 1 || t <= tr.t[0]) {
+        for (int a = 0; a < 3; ++a) out[a] = tr.p[a];
+        return;
+    }
+    if (t >= tr.t[n - 1]) {
+        for (int a = 0; a < 3; ++a) out[a] = tr.p[3 * (n - 1) + a];
+        return;
+    }
+    int k = 0;
+    while (k + 2 < n && t >= tr.t[k + 1]) ++k;
+    const double lam = (t - tr.t[k]) / (tr.t[k + 1] - tr.t[k]);
+    for (int a = 0; a < 3; ++a) out[a] = tr.p[3 * k + a] + lam * (tr.p[3 * (k + 1) + a] - tr.p[3 * k + a]);
+}
+
+msim_status check_traj(const msim_traj& tr, const double L[3], double c, const char* what)
+{
+    if (tr.kind == MSIM_TRAJ_PWL) {
+        if (tr.n_points < 1 || !tr.t || !tr.p) return fail(MSIM_E_INVALID_ARG, "%s: PWL needs >= 1 knot", what);
+        for (int k = 0; k < tr.n_points; ++k) {
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(tr.p[3 * k + a])) return fail(MSIM_E_INVALID_ARG, "%s: non-finite knot", what);
+            if (!std::isfinite(tr.t[k])) return fail(MSIM_E_INVALID_ARG, "%s: non-finite knot time", what);
+            if (k > 0) {
+                const double dt = tr.t[k] - tr.t[k - 1];
+                if (!(dt > 0.0)) return fail(MSIM_E_INVALID_ARG, "%s: knot times must increase strictly", what);
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double e = tr.p[3 * k + a] - tr.p[3 * (k - 1) + a];
+                    d2 += e * e;
+                }
+                if (std::sqrt(d2) / dt >= 0.1 * c)
+                    return fail(MSIM_E_SUPERSONIC, "%s: segment %d moves at >= c/10", what, k - 1);
+            }
+        }
+        return MSIM_OK;
+    }
+    if (tr.kind == MSIM_TRAJ_CIRCLE) {
+        if (!(tr.radius > 0.0) || !(tr.speed >= 0.0) || !std::isfinite(tr.phase0))
+            return fail(MSIM_E_INVALID_ARG, "%s: circle needs radius > 0 and speed >= 0", what);
+        if (tr.speed >= 0.1 * c) return fail(MSIM_E_SUPERSONIC, "%s: circle speed >= c/10", what);
+        return MSIM_OK;
+    }
+    return fail(MSIM_E_INVALID_ARG, "%s: unknown trajectory kind %d", what, tr.kind);
+}
+
+msim_status check_params(const msim_params* p)
+{
+    if (!p) return fail(MSIM_E_INVALID_ARG, "params is NULL");
+    if (!(p->c > 0.0) || !(p->fs > 0.0)) return fail(MSIM_E_INVALID_ARG, "c and fs must be > 0");
+    if (p->taps < 8 || p->taps > 128 || p->taps % 8 != 0)
+        return fail(MSIM_E_INVALID_ARG, "taps must be a multiple of 8 in 8..128 (got %d)", p->taps);
+    if (p->taps != 32 && p->taps != 64 && p->taps != 96 && p->taps != 128)
+        return fail(MSIM_E_UNSUPPORTED, "this build is compiled for taps 32, 64, 96, 128 (got %d)", p->taps);
+    if (!(p->kaiser_beta >= 0.0) || !(p->cutoff > 0.0 && p->cutoff <= 0.5))
+        return fail(MSIM_E_INVALID_ARG, "kaiser_beta >= 0 and cutoff in (0, 0.5] required");
+    const int L = p->table_phases;
+    if (L < 64 || L > 4096 || (L & (L - 1)) != 0)
+        return fail(MSIM_E_INVALID_ARG, "table_phases must be a power of two in 64..4096");
+    if (p->n_tiers < 0 || p->n_tiers > 4) return fail(MSIM_E_INVALID_ARG, "n_tiers must be 0..4");
+    for (int k = 0; k < p->n_tiers; ++k) {
+        if (p->tier_decim[k] < 1 || p->tier_decim[k] > 4096)
+            return fail(MSIM_E_INVALID_ARG, "tier_decim must be 1..4096");
+        if (k > 0 && p->tier_max_order[k] < p->tier_max_order[k - 1])
+            return fail(MSIM_E_INVALID_ARG, "tier_max_order must not decrease");
+    }
+    if (p->delay_model != MSIM_DELAY_RETARDED && p->delay_model != MSIM_DELAY_INSTANTANEOUS)
+        return fail(MSIM_E_INVALID_ARG, "unknown delay_model");
+    return MSIM_OK;
+}
+
+msim_status check_scene(const msim_scene& s, const msim_params* p, int idx)
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(s.size[a] > 0.0) || !std::isfinite(s.size[a]))
+            return fail(MSIM_E_INVALID_ARG, "scene %d: room size must be > 0", idx);
+    for (int w = 0; w < 6; ++w)
+        if (!(s.beta[w] >= 0.0 && s.beta[w] <= 1.0))
+            return fail(MSIM_E_INVALID_ARG, "scene %d: beta[%d] outside [0, 1]", idx, w);
+    if (s.n_mics < 1 || !s.mic_offset) return fail(MSIM_E_INVALID_ARG, "scene %d: needs >= 1 mic", idx);
+    if (s.max_order < 0 || s.max_order > 64) return fail(MSIM_E_INVALID_ARG, "scene %d: max_order in 0..64", idx);
+    if (s.n_in < 1 || s.n_out < 1) return fail(MSIM_E_INVALID_ARG, "scene %d: n_in and n_out must be >= 1", idx);
+    if (s.n_out > kMaxOut) return fail(MSIM_E_UNSUPPORTED, "scene %d: n_out above 2^23", idx);
+    msim_status st;
+    if ((st = check_traj(s.src, s.size, p->c, "source")) != MSIM_OK) return st;
+    if ((st = check_traj(s.rcv, s.size, p->c, "receiver")) != MSIM_OK) return st;
+    // every knot (or the circle's extent) inside the room; mics too
+    auto traj_inside = [&](const msim_traj& tr, const double* off) {
+        double q[3];
+        if (tr.kind == MSIM_TRAJ_CIRCLE) {
+            for (int k = 0; k < 4; ++k) {
+                const double ang = k * 0.5 * kPi;
+                q[0] = tr.center[0] + tr.radius * std::cos(ang) + (off ? off[0] : 0.0);
+                q[1] = tr.center[1] + tr.radius * std::sin(ang) + (off ? off[1] : 0.0);
+                q[2] = tr.center[2] + (off ? off[2] : 0.0);
+                if (!inside(q, s.size)) return false;
+            }
+            return true;
+        }
+        for (int k = 0; k < tr.n_points; ++k) {
+            for (int a = 0; a < 3; ++a) q[a] = tr.p[3 * k + a] + (off ? off[a] : 0.0);
+            if (!inside(q, s.size)) return false;
+        }
+        return true;
+    };
+    if (!traj_inside(s.src, nullptr)) return fail(MSIM_E_OUTSIDE_ROOM, "scene %d: source leaves the room", idx);
+    for (int c = 0; c < s.n_mics; ++c)
+        if (!traj_inside(s.rcv, s.mic_offset + 3 * c))
+            return fail(MSIM_E_OUTSIDE_ROOM, "scene %d: mic %d leaves the room", idx, c);
+    // source-mic separation at every knot time of either path (and t = 0)
+    std::vector<double> times{0.0};
+    if (s.src.kind == MSIM_TRAJ_PWL) times.insert(times.end(), s.src.t, s.src.t + s.src.n_points);
+    if (s.rcv.kind == MSIM_TRAJ_PWL) times.insert(times.end(), s.rcv.t, s.rcv.t + s.rcv.n_points);
+    for (double t : times) {
+        double ps[3], pr[3];
+        traj_at(s.src, t, ps);
+        traj_at(s.rcv, t, pr);
+        for (int c = 0; c < s.n_mics; ++c) {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double e = ps[a] - pr[a] - s.mic_offset[3 * c + a];
+                d2 += e * e;
+            }
+            if (std::sqrt(d2) < 1e-3) return fail(MSIM_E_TOO_CLOSE, "scene %d: source within 1 mm of mic %d", idx, c);
+        }
+    }
+    return MSIM_OK;
+}
+
+int64_t count_images(int K)
+{
+    // points of the L1 ball: sum over |mx| of the 2D diamond of radius K-|mx|
+    int64_t n = 0;
+    for (int a = -K; a <= K; ++a) {
+        const int r = K - std::abs(a);
+        n += 2 * int64_t(r) * r + 2 * r + 1;
+    }
+    return n;
+}
+
+struct HostImage {
+    int m[3];
+    int hits[6];
+    double beta;
+    int tier;
+    int R;
+    double dlo, dhi;   // delay bounds in samples over every mic and time
+};
+
+int tier_of(const msim_params* p, int order, int* R)
+{
+    if (p->n_tiers == 0) {
+        *R = 1;
+        return 0;
+    }
+    for (int k = 0; k < p->n_tiers; ++k)
+        if (order <= p->tier_max_order[k]) {
+            *R = p->tier_decim[k];
+            return k;
+        }
+    *R = p->tier_decim[p->n_tiers - 1];
+    return p->n_tiers - 1;
+}
+
+// Interval of image coordinates along one axis for source coordinates in [lo, hi].
+void image_interval(int m, double L, double lo, double hi, double* out_lo, double* out_hi)
+{
+    if (m & 1) {
+        *out_lo = (m + 1) * L - hi;
+        *out_hi = (m + 1) * L - lo;
+    } else {
+        *out_lo = m * L + lo;
+        *out_hi = m * L + hi;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- the plan
+
+struct msim_plan {
+    msim_params par{};
+    int n_scenes = 0;
+    int threads = 512;                    // outputs per workgroup
+    std::vector<DScene> scenes;           // host copies
+    std::vector<DImage> images;
+    std::vector<DGroup> groups;
+    std::vector<double> knots, mics;
+    std::vector<float> table;             // float4 groups, flattened
+    std::vector<int64_t> n_img;
+    double fwd_taps = 0.0;
+    int64_t x_total = 0, y_total = 0;
+    // device
+    DScene* d_scenes = nullptr;
+    DImage* d_images = nullptr;
+    DGroup* d_groups = nullptr;
+    double* d_knots = nullptr;
+    double* d_mics = nullptr;
+    float4* d_table = nullptr;
+    int32_t* d_status = nullptr;
+    int device = 0;
+    // profiling: (kind, start, stop) per launch while enabled
+    bool profiling = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKinds };
+
+hipEvent_t pool_event(msim_plan* P)
+{
+    if (!P->pool.empty()) {
+        hipEvent_t e = P->pool.back();
+        P->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when the plan is profiling.
+struct LaunchTimer {
+    msim_plan* P;
+    hipStream_t st;
+    msim_plan::Rec r{};
+    bool on;
+    LaunchTimer(msim_plan* p, int kind, hipStream_t s) : P(p), st(s), on(p->profiling)
+    {
+        if (!on) return;
+        r.kind = kind;
+        r.a = pool_event(P);
+        r.b = pool_event(P);
+        on = r.a && r.b && hipEventRecord(r.a, st) == hipSuccess;
+    }
+    ~LaunchTimer()
+    {
+        if (on && hipEventRecord(r.b, st) == hipSuccess) P->recs.push_back(r);
+    }
+};
+
+}  // namespace
+
+namespace {
+
+void build_table(msim_plan* P)
+{
+    const int T = P->par.taps, L = P->par.table_phases, NG = T / 8;
+    const double i0b = bessel_i0(P->par.kaiser_beta);
+    P->table.assign((size_t)NG * (L + 1) * 4, 0.0f);
+    for (int g = 0; g < NG; ++g)
+        for (int row = 0; row <= L; ++row)
+            for (int e = 0; e < 4; ++e) {
+                const double v = (4 * g + e) + double(row) / L;
+                P->table[((size_t)g * (L + 1) + row) * 4 + e] =
+                    (float)fd_kernel(v, T, P->par.kaiser_beta, P->par.cutoff, i0b);
+            }
+}
+
+int push_traj(msim_plan* P, const msim_traj& tr, DTraj* d)
+{
+    d->kind = tr.kind;
+    d->n_points = tr.kind == MSIM_TRAJ_PWL ? tr.n_points : 0;
+    d->knot_off = (int)P->knots.size();
+    if (tr.kind == MSIM_TRAJ_PWL) {
+        P->knots.insert(P->knots.end(), tr.t, tr.t + tr.n_points);
+        d->pos_off = (int)P->knots.size();
+        P->knots.insert(P->knots.end(), tr.p, tr.p + 3 * tr.n_points);
+    } else {
+        d->pos_off = d->knot_off;
+    }
+    for (int a = 0; a < 3; ++a) d->center[a] = tr.center[a];
+    d->radius = tr.radius;
+    d->omega = tr.kind == MSIM_TRAJ_CIRCLE ? tr.speed / tr.radius : 0.0;
+    d->phase0 = tr.phase0;
+    return 0;
+}
+
+template <typename TT>
+msim_status upload(TT** dst, const std::vector<TT>& v)
+{
+    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(TT);
+    HIP_OK(hipMalloc((void**)dst, bytes));
+    if (!v.empty()) HIP_OK(hipMemcpy(*dst, v.data(), v.size() * sizeof(TT), hipMemcpyHostToDevice));
+    return MSIM_OK;
+}
+
+// Plan one scene: images sorted by their lower delay bound, split into groups
+// of consecutive delays; the group count is raised until the source window of a
+// group fits LDS beside the table, and to give enough workgroups.
+msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off, int64_t y_off)
+{
+    const msim_params& p = P->par;
+    const int K = s.max_order;
+    std::vector<HostImage> imgs;
+    imgs.reserve((size_t)count_images(K));
+    Box sb = traj_box(s.src), rb = traj_box(s.rcv);
+    // receiver box grown by the mic offsets
+    Box mb = rb;
+    for (int a = 0; a < 3; ++a) {
+        double lo = 1e300, hi = -1e300;
+        for (int c = 0; c < s.n_mics; ++c) {
+            lo = std::min(lo, s.mic_offset[3 * c + a]);
+            hi = std::max(hi, s.mic_offset[3 * c + a]);
+        }
+        mb.lo[a] = rb.lo[a] + lo;
+        mb.hi[a] = rb.hi[a] + hi;
+    }
+    for (int mx = -K; mx <= K; ++mx)
+        for (int my = -(K - std::abs(mx)); my <= K - std::abs(mx); ++my) {
+            const int rz = K - std::abs(mx) - std::abs(my);
+            for (int mz = -rz; mz <= rz; ++mz) {
+                HostImage h;
+                h.m[0] = mx; h.m[1] = my; h.m[2] = mz;
+                double b = 1.0;
+                for (int a = 0; a < 3; ++a) {
+                    const int m = h.m[a], am = std::abs(m);
+                    const int far = m >= 0 ? (am + 1) / 2 : am / 2;
+                    const int near = am - far;
+                    h.hits[2 * a] = near;
+                    h.hits[2 * a + 1] = far;
+                    b *= std::pow(s.beta[2 * a], near) * std::pow(s.beta[2 * a + 1], far);
+                }
+                h.beta = b;
+                h.tier = tier_of(&p, std::abs(mx) + std::abs(my) + std::abs(mz), &h.R);
+                double dmin2 = 0.0, dmax2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double lo, hi;
+                    image_interval(h.m[a], s.size[a], sb.lo[a], sb.hi[a], &lo, &hi);
+                    const double gap = std::max(0.0, std::max(lo - mb.hi[a], mb.lo[a] - hi));
+                    const double far = std::max(std::fabs(hi - mb.lo[a]), std::fabs(mb.hi[a] - lo));
+                    dmin2 += gap * gap;
+                    dmax2 += far * far;
+                }
+                h.dlo = p.fs * std::sqrt(dmin2) / p.c;
+                h.dhi = p.fs * std::sqrt(dmax2) / p.c;
+                imgs.push_back(h);
+            }
+        }
+    std::stable_sort(imgs.begin(), imgs.end(), [](const HostImage& a, const HostImage& b) {
+        return a.dlo < b.dlo || (a.dlo == b.dlo && a.dhi < b.dhi);
+    });
+    const int I = (int)imgs.size();
+    DScene d{};
+    for (int a = 0; a < 3; ++a) d.size[a] = s.size[a];
+    push_traj(P, s.src, &d.src);
+    push_traj(P, s.rcv, &d.rcv);
+    d.n_mics = s.n_mics;
+    d.mic_off = (int)(P->mics.size() / 3);
+    P->mics.insert(P->mics.end(), s.mic_offset, s.mic_offset + 3 * s.n_mics);
+    d.n_in = s.n_in;
+    d.n_out = s.n_out;
+    d.x_off = x_off;
+    d.y_off = y_off;
+    d.img_begin = (int)P->images.size();
+    d.n_img = I;
+    int64_t seg = 0;
+    for (const HostImage& h : imgs) {
+        DImage di{};
+        for (int a = 0; a < 3; ++a) di.m[a] = (int16_t)h.m[a];
+        di.tier = (int16_t)h.tier;
+        di.R = h.R;
+        di.invR = 1.0f / (float)h.R;
+        di.gfac = (float)(h.beta * p.fs / (4.0 * kPi * p.c));
+        di.seg_off = (int32_t)seg;
+        di.n_seg = (int32_t)((s.n_out + h.R - 1) / h.R);
+        seg += di.n_seg;
+        P->images.push_back(di);
+    }
+    if (seg > INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "scene %d: track too long", si);
+    d.seg_per_mic = seg;
+    const int NT = P->threads, T = p.taps, L = p.table_phases;
+    d.n_tiles = (int)((s.n_out + NT - 1) / NT);
+    const size_t table_bytes = synth_lds_bytes(T, L, 0);
+    // enough workgroups to fill the chip several times over
+    int G = std::max(1, std::min(I, (int)((4 * 256 + (int64_t)d.n_tiles * s.n_mics - 1) / ((int64_t)d.n_tiles * s.n_mics))));
+    std::vector<DGroup> gr;
+    int window = 0;
+    for (;;) {
+        gr.clear();
+        window = 0;
+        for (int g = 0; g < G; ++g) {
+            const int b = (int)((int64_t)I * g / G), e = (int)((int64_t)I * (g + 1) / G);
+            if (b == e) continue;
+            double lo = 1e300, hi = -1e300;
+            for (int i = b; i < e; ++i) {
+                lo = std::min(lo, imgs[i].dlo);
+                hi = std::max(hi, imgs[i].dhi);
+            }
+            DGroup dg{b, e, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4};
+            gr.push_back(dg);
+            window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
+        }
+        if (table_bytes + (size_t)window * sizeof(float4) <= kLdsLimit) break;
+        if (G >= I) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", si);
+        G = std::min(I, G * 2);
+    }
+    d.grp_begin = (int)P->groups.size();
+    d.n_grp = (int)gr.size();
+    d.window = window;
+    P->groups.insert(P->groups.end(), gr.begin(), gr.end());
+    P->scenes.push_back(d);
+    P->n_img.push_back(I);
+    P->fwd_taps += (double)s.n_mics * I * double(s.n_in + T - 1) * T;
+    return MSIM_OK;
+}
+
+size_t fwd_ws_bytes(const msim_plan* P, const DScene& d)
+{
+    const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
+    return align_up(segs * sizeof(Seg)) + align_up(segs * sizeof(int32_t)) +
+           align_up((size_t)d.n_mics * d.n_grp * d.n_out * sizeof(float));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+const char* msim_last_error(void) { return g_err.c_str(); }
+
+msim_status msim_default_params(msim_params* p)
+{
+    if (!p) return fail(MSIM_E_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->c = 343.0;
+    p->fs = 16000.0;
+    p->taps = 64;
+    p->kaiser_beta = 8.0;
+    p->cutoff = 0.5;
+    p->table_phases = 512;
+    p->n_tiers = 3;
+    p->tier_max_order[0] = 2;
+    p->tier_decim[0] = 1;
+    p->tier_max_order[1] = 6;
+    p->tier_decim[1] = 16;
+    p->tier_max_order[2] = 1 << 20;
+    p->tier_decim[2] = 160;
+    p->delay_model = MSIM_DELAY_RETARDED;
+    return MSIM_OK;
+}
+
+msim_status msim_count_images(int32_t max_order, int64_t* n)
+{
+    if (!n || max_order < 0 || max_order > 64) return fail(MSIM_E_INVALID_ARG, "max_order in 0..64, n non-NULL");
+    *n = count_images(max_order);
+    return MSIM_OK;
+}
+
+msim_status msim_suggest_n_out(const msim_scene* s, const msim_params* p, int64_t* n_out)
+{
+    if (!s || !n_out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    msim_status st = check_params(p);
+    if (st != MSIM_OK) return st;
+    if (s->max_order < 0 || s->n_in < 1) return fail(MSIM_E_INVALID_ARG, "max_order >= 0 and n_in >= 1 required");
+    // farthest image cell of order <= K: all of the order on the longest axis
+    double L[3] = {s->size[0], s->size[1], s->size[2]};
+    std::sort(L, L + 3);
+    const double d = std::sqrt(std::pow(L[2] * (s->max_order + 1), 2) + L[1] * L[1] + L[0] * L[0]);
+    *n_out = s->n_in + (int64_t)std::ceil(p->fs * d / p->c) + p->taps;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const msim_params* p, msim_plan** out)
+{
+    if (!out) return fail(MSIM_E_INVALID_ARG, "plan pointer is NULL");
+    *out = nullptr;
+    if (!scenes || n_scenes < 1) return fail(MSIM_E_INVALID_ARG, "need >= 1 scene");
+    msim_status st = check_params(p);
+    if (st != MSIM_OK) return st;
+    for (int s = 0; s < n_scenes; ++s)
+        if ((st = check_scene(scenes[s], p, s)) != MSIM_OK) return st;
+    msim_plan* P = new msim_plan();
+    P->par = *p;
+    P->n_scenes = n_scenes;
+    int64_t xo = 0, yo = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        if ((st = plan_scene(P, scenes[s], s, xo, yo)) != MSIM_OK) {
+            delete P;
+            return st;
+        }
+        xo += scenes[s].n_in;
+        yo += (int64_t)scenes[s].n_mics * scenes[s].n_out;
+    }
+    P->x_total = xo;
+    P->y_total = yo;
+    build_table(P);
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(MSIM_E_HIP, "no HIP device");
+    }
+    std::vector<float4> tab4(P->table.size() / 4);
+    std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
+    std::vector<int32_t> zero(1, 0);
+    if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
+        (st = upload(&P->d_groups, P->groups)) != MSIM_OK || (st = upload(&P->d_knots, P->knots)) != MSIM_OK ||
+        (st = upload(&P->d_mics, P->mics)) != MSIM_OK || (st = upload(&P->d_table, tab4)) != MSIM_OK ||
+        (st = upload(&P->d_status, zero)) != MSIM_OK) {
+        msim_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_destroy(msim_plan* P)
+{
+    if (!P) return MSIM_OK;
+    for (auto& r : P->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : P->pool) (void)hipEventDestroy(e);
+    (void)hipFree(P->d_scenes);
+    (void)hipFree(P->d_images);
+    (void)hipFree(P->d_groups);
+    (void)hipFree(P->d_knots);
+    (void)hipFree(P->d_mics);
+    (void)hipFree(P->d_table);
+    (void)hipFree(P->d_status);
+    delete P;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_layout(const msim_plan* P, int64_t* x_off, int64_t* y_off, int64_t* x_total, int64_t* y_total)
+{
+    if (!P) return fail(MSIM_E_INVALID_ARG, "plan is NULL");
+    for (int s = 0; s < P->n_scenes; ++s) {
+        if (x_off) x_off[s] = P->scenes[s].x_off;
+        if (y_off) y_off[s] = P->scenes[s].y_off;
+    }
+    if (x_total) *x_total = P->x_total;
+    if (y_total) *y_total = P->y_total;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_stats(const msim_plan* P, int64_t* n_images, double* forward_taps)
+{
+    if (!P) return fail(MSIM_E_INVALID_ARG, "plan is NULL");
+    if (n_images)
+        for (int s = 0; s < P->n_scenes; ++s) n_images[s] = P->n_img[s];
+    if (forward_taps) *forward_taps = P->fwd_taps;
+    return MSIM_OK;
+}
+
+msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* bytes)
+{
+    if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    if (with_grad) return fail(MSIM_E_UNSUPPORTED, "backward is not in this build");
+    size_t m = 0;
+    for (const DScene& d : P->scenes) m = std::max(m, fwd_ws_bytes(P, d));
+    *bytes = m;
+    return MSIM_OK;
+}
+
+msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!P || !x || !y) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    msim_workspace_size(P, 0, &need);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
+        return fail(MSIM_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned", need);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    for (int s = 0; s < P->n_scenes; ++s) {
+        const DScene& d = P->scenes[s];
+        char* w = (char*)ws;
+        const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
+        Seg* seg = (Seg*)w;
+        w += align_up(segs * sizeof(Seg));
+        int32_t* segK = (int32_t*)w;
+        w += align_up(segs * sizeof(int32_t));
+        float* part = (float*)w;
+        {
+            LaunchTimer t(P, kKindTracks, stream);
+            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, seg, segK, P->par.c,
+                                 P->par.fs, P->par.delay_model, stream));
+        }
+        {
+            LaunchTimer t(P, kKindSynth, stream);
+            HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
+                                    P->par.table_phases, seg, segK, x, part, P->d_status, stream));
+        }
+        {
+            LaunchTimer t(P, kKindReduce, stream);
+            HIP_OK(launch_reduce_groups(d, part, y, stream));
+        }
+    }
+    return MSIM_OK;
+}
+
+msim_status msim_profile_begin(msim_plan* P)
+{
+    if (!P) return fail(MSIM_E_INVALID_ARG, "plan is NULL");
+    P->profiling = true;
+    return MSIM_OK;
+}
+
+msim_status msim_profile_end(msim_plan* P, msim_profile* out)
+{
+    if (!P || !out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    P->profiling = false;
+    double ms[kKinds] = {0};
+    int32_t cnt[kKinds] = {0};
+    msim_status st = MSIM_OK;
+    for (auto& r : P->recs) {
+        float v = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&v, r.a, r.b) != hipSuccess)
+            st = fail(MSIM_E_HIP, "profiling event failed");
+        ms[r.kind] += v;
+        cnt[r.kind] += 1;
+        P->pool.push_back(r.a);
+        P->pool.push_back(r.b);
+    }
+    P->recs.clear();
+    out->tracks_ms = ms[kKindTracks];
+    out->synth_ms = ms[kKindSynth];
+    out->reduce_ms = ms[kKindReduce];
+    out->adjoint_ms = ms[kKindAdjoint];
+    out->params_ms = ms[kKindParams];
+    out->tracks_launches = cnt[kKindTracks];
+    out->synth_launches = cnt[kKindSynth];
+    out->reduce_launches = cnt[kKindReduce];
+    out->adjoint_launches = cnt[kKindAdjoint];
+    out->params_launches = cnt[kKindParams];
+    return st;
+}
+
+msim_status msim_device_status(msim_plan* P, hipStream_t stream, int32_t* flags)
+{
+    if (!P || !flags) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    int32_t v = 0;
+    HIP_OK(hipMemcpyAsync(&v, P->d_status, sizeof v, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    HIP_OK(hipMemsetAsync(P->d_status, 0, sizeof v, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    *flags = v;
+    return v ? fail(MSIM_E_DEVICE, "device status flags 0x%x", v) : MSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal structures shared by the host planner and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace msim {
+
+// A trajectory as the kernels see it: knot times and positions live in the
+// plan's knot array (times at knot_off, xyz triples at pos_off).
+struct DTraj {
+    int32_t kind;
+    int32_t n_points;
+    int32_t knot_off;
+    int32_t pos_off;
+    double center[3];
+    double radius;
+    double omega;     // angular rate speed/radius (circle)
+    double phase0;
+};
+
+struct DScene {
+    double size[3];
+    DTraj src;
+    DTraj rcv;
+    int32_t n_mics;
+    int32_t mic_off;      // index of this scene's first offset triple in the mic array
+    int64_t n_in;
+    int64_t n_out;
+    int64_t x_off;        // packed signal offsets
+    int64_t y_off;
+    int32_t img_begin;    // this scene's images in the plan's image table
+    int32_t n_img;
+    int32_t grp_begin;    // this scene's delay groups
+    int32_t n_grp;
+    int64_t seg_per_mic;  // track segments of one mic (sum over images)
+    int32_t n_tiles;
+    int32_t window;       // LDS source window (positions) the plan sized for this scene
+};
+
+// One image source.  Position of image m of point q, per axis a:
+//   m_a even: m_a L_a + q_a ;  m_a odd: (m_a + 1) L_a - q_a.
+struct DImage {
+    int16_t m[3];
+    int16_t tier;
+    int32_t R;            // decimation of its delay grid
+    float invR;
+    float gfac;           // beta_i * fs / (4 pi c): gain = gfac / D
+    int32_t seg_off;      // first track segment within one mic's track
+    int32_t n_seg;        // ceil(n_out / R)
+};
+
+// Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
+// samples, are bounded by [dmin, dmax] for every mic at every time.
+struct DGroup {
+    int32_t img_begin;
+    int32_t img_end;
+    int32_t dmin;
+    int32_t dmax;
+};
+
+// Delay of an image over one grid segment [kR, (k+1)R):
+//   D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)),  v = 0 .. R-1,
+// the uniform Catmull-Rom cubic through the exact delays at (k-1)R .. (k+2)R.
+struct Seg {
+    float a0, b1, b2, b3;
+};
+
+constexpr int kStatusWindow = 1;
+
+// ---- kernel launchers (msim_kernels.hip) ----
+hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                         const double* d_knots, const double* d_mics, Seg* seg, int32_t* segK,
+                         double c, double fs, int delay_model, hipStream_t st);
+
+hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                            const float4* d_table, int L, const Seg* seg, const int32_t* segK,
+                            const float* x, float* part, int32_t* d_status, hipStream_t st);
+
+hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st);
+
+size_t synth_lds_bytes(int taps, int L, int window);
+
+}  // namespace msim

@@ -1,0 +1,319 @@
+// gfx950 kernels of the moving image-source synthesis.
+//
+//   tracks      : exact delays of every image on its tier's grid (FP64 retarded
+//                 solve), turned into per-segment Catmull-Rom cubics stored as an
+//                 integer base plus FP32 offsets (Sec. II-C-3: decimated delays
+//                 of high-order images, upsampled to the audio rate).
+//   synth_fwd   : the gather-reduce y[n] = sum_i g_i(n) sum_j h(j - mu_i(n)) x[n - K_i(n) - j]
+//                 (Eq. 2 / Eq. 8 with the FIR fractional delay of Sec. II-B), one
+//                 output sample per lane, images of one delay group per
+//                 workgroup, source window and fractional-delay table in LDS.
+//   reduce      : fixed-order sum of the per-group partial outputs.
+#include "msim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace msim {
+
+// ------------------------------------------------------------------ geometry
+
+__device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
+{
+    if (tr.kind == 1) {
+        double s, c;
+        sincos(tr.omega * t + tr.phase0, &s, &c);
+        out[0] = tr.center[0] + tr.radius * c;
+        out[1] = tr.center[1] + tr.radius * s;
+        out[2] = tr.center[2];
+        return;
+    }
+    const double* T = knots + tr.knot_off;
+    const double* P = knots + tr.pos_off;
+    const int n = tr.n_points;
+    int a;
+    double lam;
+    if (n == 1 || t <= T[0]) {
+        a = 0;
+        lam = 0.0;
+    } else if (t >= T[n - 1]) {
+        a = n - 1;
+        lam = 0.0;
+    } else {
+        a = 0;
+        while (a + 2 < n && t >= T[a + 1]) ++a;
+        lam = (t - T[a]) / (T[a + 1] - T[a]);
+    }
+    const int b = (lam > 0.0) ? a + 1 : a;
+    for (int k = 0; k < 3; ++k) out[k] = P[3 * a + k] + lam * (P[3 * b + k] - P[3 * a + k]);
+}
+
+__device__ inline double image_coord(int m, double L, double q)
+{
+    return (m & 1) ? (double)(m + 1) * L - q : (double)m * L + q;
+}
+
+__device__ inline double dist_to(const DScene& S, const int16_t m[3], const double* knots, const double r[3], double te)
+{
+    double q[3];
+    traj_pos(S.src, knots, te, q);
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
+        d2 += e * e;
+    }
+    return sqrt(d2);
+}
+
+// Propagation delay (s) for sound received at time t by mic position r.
+// Retarded: c tau = |p_i(t - tau) - r(t)|, fixed-point iteration (contraction
+// factor |v_source|/c < 0.1 by validation).  Instantaneous: |p_i(t) - r(t)| / c.
+__device__ inline double solve_tau(const DScene& S, const int16_t m[3], const double* knots, const double* mics,
+                                   int mic, double t, double inv_c, int model)
+{
+    double r[3];
+    traj_pos(S.rcv, knots, t, r);
+    const double* off = mics + 3 * (S.mic_off + mic);
+    r[0] += off[0];
+    r[1] += off[1];
+    r[2] += off[2];
+    double tau = dist_to(S, m, knots, r, t) * inv_c;
+    if (model == 0) {
+        for (int it = 0; it < 60; ++it) {
+            const double nt = dist_to(S, m, knots, r, t - tau) * inv_c;
+            const double d = fabs(nt - tau);
+            tau = nt;
+            if (d <= 1e-15 * tau) break;
+        }
+    }
+    return tau;
+}
+
+// ------------------------------------------------------------------- tracks
+
+// One thread per (mic, segment).  Segment k of image i covers outputs
+// [kR, (k+1)R); its cubic interpolates the exact delays at (k-1)R .. (k+2)R.
+__global__ __launch_bounds__(256) void k_tracks(const DScene* __restrict__ scenes, int scene,
+                                                const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                                const double* __restrict__ mics, Seg* __restrict__ seg,
+                                                int32_t* __restrict__ segK, double c, double fs, int model)
+{
+    const DScene& S = scenes[scene];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_mic = S.seg_per_mic;
+    if (gid >= per_mic * S.n_mics) return;
+    const int mic = (int)(gid / per_mic);
+    const int64_t sidx = gid - (int64_t)mic * per_mic;
+    // image owning this segment: last image with seg_off <= sidx
+    const DImage* I = imgs + S.img_begin;
+    int lo = 0, hi = S.n_img - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (I[mid].seg_off <= sidx) lo = mid; else hi = mid - 1;
+    }
+    const DImage im = I[lo];
+    const int64_t k = sidx - im.seg_off;
+    const double inv_c = 1.0 / c;
+    const int R = im.R;
+    Seg out;
+    int32_t K;
+    if (R == 1) {
+        const double D = fs * solve_tau(S, im.m, knots, mics, mic, (double)k / fs, inv_c, model);
+        const double Kd = floor(D);
+        K = (int32_t)Kd;
+        out.a0 = (float)(D - Kd);
+        out.b1 = out.b2 = out.b3 = 0.0f;
+    } else {
+        double D[4];
+        for (int q = 0; q < 4; ++q)
+            D[q] = fs * solve_tau(S, im.m, knots, mics, mic, (double)((k - 1 + q) * R) / fs, inv_c, model);
+        const double Kd = floor(D[1]);
+        K = (int32_t)Kd;
+        const double a1 = 0.5 * (D[2] - D[0]);
+        const double a2 = 0.5 * (2.0 * D[0] - 5.0 * D[1] + 4.0 * D[2] - D[3]);
+        const double a3 = 0.5 * (3.0 * D[1] - D[0] - 3.0 * D[2] + D[3]);
+        const double iR = 1.0 / (double)R;
+        out.a0 = (float)(D[1] - Kd);
+        out.b1 = (float)(a1 * iR);
+        out.b2 = (float)(a2 * iR * iR);
+        out.b3 = (float)(a3 * iR * iR * iR);
+    }
+    seg[gid] = out;
+    segK[gid] = K;
+}
+
+hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                         const double* d_knots, const double* d_mics, Seg* seg, int32_t* segK,
+                         double c, double fs, int delay_model, hipStream_t st)
+{
+    const int64_t n = hs.seg_per_mic * hs.n_mics;
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_tracks, dim3((unsigned)blocks), dim3(256), 0, st, d_scenes, scene, d_imgs, d_knots,
+                       d_mics, seg, segK, c, fs, delay_model);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- forward synth
+
+// LDS: the half table of h(v) = h(-v), v in [0, T/2], sampled at v = r/L and
+// grouped by four taps: tab[g*(L+1) + row] = (h((4g+e) + row/L)), e = 0..3;
+// then the source window as overlapping quads xw[p] = x[ws+p .. ws+p+3].
+size_t synth_lds_bytes(int taps, int L, int window)
+{
+    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) + (size_t)window * sizeof(float4);
+}
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
+                                                   const DGroup* __restrict__ groups,
+                                                   const float4* __restrict__ table, int L,
+                                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                                   const float* __restrict__ x, float* __restrict__ part,
+                                                   int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    constexpr int NG = T / 8;          // tap quads per side
+    const int rows = L + 1;
+    float4* tab = lds;
+    float4* xw = lds + NG * rows;
+
+    const int tile = blockIdx.x;
+    const int g = blockIdx.y;
+    const int mic = blockIdx.z;
+    const int tid = threadIdx.x;
+    const DGroup G = groups[S.grp_begin + g];
+    const int64_t n0 = (int64_t)tile * NT;
+    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int W = NT + (G.dmax - G.dmin) + T + 8;
+
+    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
+    const float* xs = x + S.x_off;
+    const int64_t n_in = S.n_in;
+    for (int p = tid; p < W; p += NT) {
+        const int64_t q = ws + p;
+        float4 v;
+        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
+        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
+        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
+        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
+        xw[p] = v;
+    }
+    __syncthreads();
+
+    const int64_t n = n0 + tid;
+    if (n >= S.n_out) return;
+    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const float fn = (float)n + 0.5f;
+    const float Lf = (float)L;
+    float acc = 0.0f;
+    int bad = 0;
+
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = I[ii];
+        int k = (int)(fn * im.invR);
+        k = min(max(k, 0), im.n_seg - 1);
+        const int64_t sidx = trk + im.seg_off + k;
+        const Seg sg = seg[sidx];
+        const int Ks = segK[sidx];
+        const float v = (float)(n - (int64_t)k * im.R);
+        const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
+        const float fl = floorf(d);
+        const int K = Ks + (int)fl;
+        const float mu = d - fl;
+        const float gain = im.gfac * __builtin_amdgcn_rcpf((float)Ks + d);
+        const float q = mu * Lf;
+        const int kq = min((int)q, L - 1);
+        const float f = q - (float)kq;
+        int p0 = (int)(n - K - ws);
+        if (p0 < T / 2 || p0 > W - T / 2 + 3) {
+            bad = 1;
+            continue;
+        }
+        const float4* tn = tab + kq;
+        const float4* tp = tab + (L - 1 - kq);
+        const float4* xq = xw + p0;
+        float A = 0.0f, B = 0.0f;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> rows kq (1-f), kq+1 (f)
+            const float4 xn = xq[4 * gi];
+            const float4 P = tn[gi * rows];
+            const float4 Q = tn[gi * rows + 1];
+            A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
+            A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
+            A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
+            A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
+            // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
+            //   -> rows L-1-kq (weight f), L-kq (weight 1-f)
+            const float4 xp = xq[-4 - 4 * gi];
+            const float4 P2 = tp[gi * rows];
+            const float4 Q2 = tp[gi * rows + 1];
+            B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
+            B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
+            B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
+            B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
+        }
+        acc = fmaf(gain, fmaf(f, B - A, A), acc);
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+    part[((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
+}
+
+template <int T, int NT>
+static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups, const float4* d_table,
+                               int L, const Seg* seg, const int32_t* segK, const float* x, float* part,
+                               int32_t* d_status, hipStream_t st)
+{
+    const size_t lds = synth_lds_bytes(T, L, hs.window);
+    auto kern = k_synth_fwd<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                            const float4* d_table, int L, const Seg* seg, const int32_t* segK,
+                            const float* x, float* part, int32_t* d_status, hipStream_t st)
+{
+#define MSIM_FWD_CASE(TT, NN)                                                                                  \
+    if (taps == TT && nthreads == NN)                                                                          \
+        return launch_fwd_t<TT, NN>(hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status, st);
+    MSIM_FWD_CASE(32, 512)
+    MSIM_FWD_CASE(64, 512)
+    MSIM_FWD_CASE(96, 512)
+    MSIM_FWD_CASE(128, 512)
+    MSIM_FWD_CASE(32, 1024)
+    MSIM_FWD_CASE(64, 1024)
+    MSIM_FWD_CASE(96, 1024)
+    MSIM_FWD_CASE(128, 1024)
+#undef MSIM_FWD_CASE
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ reduction
+
+__global__ __launch_bounds__(256) void k_reduce_groups(int64_t n_out, int n_grp, int n_mics,
+                                                       const float* __restrict__ part, float* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out * n_mics) return;
+    const int mic = (int)(i / n_out);
+    const int64_t n = i - (int64_t)mic * n_out;
+    const float* p = part + (int64_t)mic * n_grp * n_out + n;
+    float s = 0.0f;
+    for (int g = 0; g < n_grp; ++g) s += p[(int64_t)g * n_out];
+    y[i] = s;
+}
+
+hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st)
+{
+    const int64_t n = hs.n_out * hs.n_mics;
+    hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hs.n_out, hs.n_grp,
+                       hs.n_mics, part, y + hs.y_off);
+    return hipGetLastError();
+}
+
+}  // namespace msim

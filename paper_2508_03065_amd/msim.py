@@ -1,0 +1,178 @@
+"""Python binding of the msim library: a Plan over one or more scenes.
+
+Argument marshalling only.  PyTorch supplies device memory and the current HIP
+stream; every step of the synthesis runs in libmsim.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MsimError, check
+
+
+def _d(a, keep: list):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    keep.append(a)
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _traj(tr, keep) -> _lib.Traj:
+    s = _lib.Traj()
+    s.kind = int(tr.kind)
+    s.n_points = int(np.asarray(tr.t).shape[0])
+    s.t = _d(tr.t, keep)
+    s.p = _d(np.asarray(tr.p).reshape(-1), keep)
+    s.center = (C.c_double * 3)(*[float(v) for v in tr.center])
+    s.radius = float(tr.radius)
+    s.speed = float(tr.speed)
+    s.phase0 = float(tr.phase0)
+    return s
+
+
+def _scene(sc, keep) -> _lib.Scene:
+    s = _lib.Scene()
+    s.size = (C.c_double * 3)(*[float(v) for v in sc.size])
+    s.beta = (C.c_double * 6)(*[float(v) for v in sc.beta])
+    s.src = _traj(sc.src, keep)
+    s.rcv = _traj(sc.rcv, keep)
+    s.n_mics = int(np.asarray(sc.mic_offset).shape[0])
+    s.mic_offset = _d(np.asarray(sc.mic_offset).reshape(-1), keep)
+    s.max_order = int(sc.max_order)
+    s.n_in = int(sc.n_in)
+    s.n_out = int(sc.n_out)
+    return s
+
+
+def params_struct(par, table_phases: int = 512) -> _lib.Params:
+    p = _lib.Params()
+    p.c = float(par.c)
+    p.fs = float(par.fs)
+    p.taps = int(par.taps)
+    p.kaiser_beta = float(par.kaiser_beta)
+    p.cutoff = float(par.cutoff)
+    p.table_phases = int(table_phases)
+    tiers = list(par.tiers)
+    p.n_tiers = len(tiers)
+    mo, de = [0] * 4, [1] * 4
+    for k, (o, d) in enumerate(tiers):
+        mo[k], de[k] = int(min(o, 2 ** 30)), int(d)
+    p.tier_max_order = (C.c_int32 * 4)(*mo)
+    p.tier_decim = (C.c_int32 * 4)(*de)
+    p.delay_model = int(par.delay_model)
+    return p
+
+
+def count_images(max_order: int) -> int:
+    n = C.c_int64()
+    check(_lib.load().msim_count_images(int(max_order), C.byref(n)))
+    return n.value
+
+
+def suggest_n_out(sc, par) -> int:
+    keep: list = []
+    s = _scene(sc, keep)
+    p = params_struct(par)
+    n = C.c_int64()
+    check(_lib.load().msim_suggest_n_out(C.byref(s), C.byref(p), C.byref(n)))
+    return n.value
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+class Plan:
+    """A validated, uploaded synthesis plan for a list of scenes."""
+
+    def __init__(self, scenes: Sequence, par, table_phases: int = 512):
+        L = _lib.load()
+        self._keep: list = []
+        arr = (_lib.Scene * len(scenes))()
+        for i, sc in enumerate(scenes):
+            arr[i] = _scene(sc, self._keep)
+        self.params = params_struct(par, table_phases)
+        self._ptr = C.c_void_p()
+        check(L.msim_plan_create(arr, len(scenes), C.byref(self.params), C.byref(self._ptr)))
+        self.n_scenes = len(scenes)
+        n = self.n_scenes
+        xo, yo = (C.c_int64 * n)(), (C.c_int64 * n)()
+        xt, yt = C.c_int64(), C.c_int64()
+        check(L.msim_plan_layout(self._ptr, xo, yo, C.byref(xt), C.byref(yt)))
+        self.x_off = np.array(list(xo), np.int64)
+        self.y_off = np.array(list(yo), np.int64)
+        self.x_total, self.y_total = xt.value, yt.value
+        ni = (C.c_int64 * n)()
+        taps = C.c_double()
+        check(L.msim_plan_stats(self._ptr, ni, C.byref(taps)))
+        self.n_images = np.array(list(ni), np.int64)
+        self.forward_taps = taps.value
+        self.n_in = [int(sc.n_in) for sc in scenes]
+        self.n_out = [int(sc.n_out) for sc in scenes]
+        self.n_mics = [int(np.asarray(sc.mic_offset).shape[0]) for sc in scenes]
+        self._ws = {}
+
+    # -------------------------------------------------------------- memory
+    def workspace_bytes(self, with_grad: bool = False) -> int:
+        b = C.c_size_t()
+        check(_lib.load().msim_workspace_size(self._ptr, int(with_grad), C.byref(b)))
+        return b.value
+
+    def workspace(self, with_grad: bool = False, device=None) -> torch.Tensor:
+        key = bool(with_grad)
+        nb = self.workspace_bytes(with_grad)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device or "cuda")
+            self._ws[key] = ws
+        return ws
+
+    def pack_x(self, xs: Sequence, device="cuda") -> torch.Tensor:
+        flat = np.concatenate([np.asarray(x, np.float32).reshape(-1) for x in xs])
+        assert flat.shape[0] == self.x_total
+        return torch.from_numpy(flat).to(device)
+
+    def unpack_y(self, y: torch.Tensor) -> List[torch.Tensor]:
+        return [y[o:o + m * n].view(m, n) for o, m, n in zip(self.y_off, self.n_mics, self.n_out)]
+
+    # ------------------------------------------------------------- compute
+    def forward(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
+        if y is None:
+            y = torch.empty(self.y_total, dtype=torch.float32, device=x.device)
+        assert y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.numel() == self.y_total
+        ws = self.workspace(False, x.device)
+        check(_lib.load().msim_forward(self._ptr, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        return y
+
+    def device_status(self, stream=None) -> int:
+        f = C.c_int32()
+        st = _lib.load().msim_device_status(self._ptr, _stream_handle(stream), C.byref(f))
+        if st not in (0, 8):
+            check(st)
+        return f.value
+
+    def profile_begin(self):
+        check(_lib.load().msim_profile_begin(self._ptr))
+
+    def profile_end(self) -> dict:
+        pr = _lib.Profile()
+        check(_lib.load().msim_profile_end(self._ptr, C.byref(pr)))
+        return {k: getattr(pr, k) for k, _ in _lib.Profile._fields_}
+
+    def close(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            _lib.load().msim_plan_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

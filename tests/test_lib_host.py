@@ -1,0 +1,143 @@
+"""Host-side checks of libmsim.so that need no GPU: it loads, exports every
+entry point include/msim.h declares, and rejects invalid input with the
+documented status before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2508_03065_amd import _lib, scenegen as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2508_03065_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:msim_status|const char\*)\s+(msim_\w+)\s*\(", src, re.M))
+    return sorted(names)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_symbols()
+    assert "msim_forward" in names and "msim_plan_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares all of them
+    for n in names:
+        assert n in _lib.SIGNATURES or n == "msim_last_error", n
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libmsim.so")
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def test_count_images_closed_form(lib):
+    n = C.c_int64()
+    for K in range(0, 33):
+        assert lib.msim_count_images(K, C.byref(n)) == 0
+        assert n.value == (2 * K + 1) * (2 * K * K + 2 * K + 3) // 3
+    assert lib.msim_count_images(-1, C.byref(n)) == 1
+
+
+def test_default_params(lib):
+    p = _lib.Params()
+    assert lib.msim_default_params(C.byref(p)) == 0
+    assert p.taps == 64 and p.table_phases == 512 and p.n_tiers == 3
+    assert list(p.tier_decim)[:3] == [1, 16, 160] and list(p.tier_max_order)[:2] == [2, 6]
+
+
+def _structs(sc, par):
+    from paper_2508_03065_amd import msim
+    keep = []
+    s = msim._scene(sc, keep)
+    p = msim.params_struct(par)
+    return s, p, keep
+
+
+def test_suggest_n_out_matches_generator(lib):
+    for cfg in (G.config1, G.config2):
+        scenes, par = cfg()
+        s, p, keep = _structs(scenes[0], par)
+        n = C.c_int64()
+        assert lib.msim_suggest_n_out(C.byref(s), C.byref(p), C.byref(n)) == 0
+        assert n.value == scenes[0].n_out
+
+
+def _create(lib, sc, par, mutate_params=None):
+    s, p, keep = _structs(sc, par)
+    if mutate_params:
+        mutate_params(p)
+    arr = (_lib.Scene * 1)(s)
+    plan = C.c_void_p()
+    st = lib.msim_plan_create(arr, 1, C.byref(p), C.byref(plan))
+    msg = lib.msim_last_error().decode()
+    if st == 0:
+        lib.msim_plan_destroy(plan)
+    return st, msg
+
+
+@pytest.mark.parametrize("mut,code", [
+    (lambda p: setattr(p, "taps", 33), 1),
+    (lambda p: setattr(p, "taps", 40), 6),
+    (lambda p: setattr(p, "cutoff", 0.7), 1),
+    (lambda p: setattr(p, "table_phases", 500), 1),
+    (lambda p: setattr(p, "c", -1.0), 1),
+    (lambda p: setattr(p, "n_tiers", 5), 1),
+    (lambda p: setattr(p, "delay_model", 3), 1),
+])
+def test_invalid_params(lib, mut, code):
+    sc, par = G.small_scene(seed=1)
+    st, msg = _create(lib, sc, par, mut)
+    assert st == code, msg
+
+
+def test_invalid_scenes(lib):
+    sc, par = G.small_scene(seed=1)
+    bad = sc.copy()
+    bad.beta[3] = 1.5
+    assert _create(lib, bad, par)[0] == 1
+    bad = sc.copy()
+    bad.src = G.Traj.pwl([0.0, 1.0], [[1, 1, 1], [7, 1, 1]])        # leaves a 5 m room
+    assert _create(lib, bad, par)[0] == 2
+    bad = sc.copy()
+    r = bad.rcv.p[0]
+    bad.src = G.Traj.static(r + 1e-4)
+    assert _create(lib, bad, par)[0] == 3
+    bad = sc.copy()
+    bad.src = G.Traj.pwl([0.0, 0.01], [[1, 1, 1], [2, 1, 1]])       # 100 m/s
+    assert _create(lib, bad, par)[0] == 4
+    bad = sc.copy()
+    bad.src = G.Traj.pwl([0.0, 0.0], [[1, 1, 1], [1.1, 1, 1]])      # knot times not increasing
+    assert _create(lib, bad, par)[0] == 1
+    bad = sc.copy()
+    bad.mic_offset = np.array([[10.0, 0.0, 0.0]])                    # mic outside the room
+    assert _create(lib, bad, par)[0] == 2
+    bad = sc.copy()
+    bad.max_order = -1
+    assert _create(lib, bad, par)[0] == 1
+
+
+def test_null_arguments(lib):
+    plan = C.c_void_p()
+    p = _lib.Params()
+    lib.msim_default_params(C.byref(p))
+    assert lib.msim_plan_create(None, 1, C.byref(p), C.byref(plan)) == 1
+    assert lib.msim_forward(None, None, None, None, 0, None) == 1
+    assert lib.msim_workspace_size(None, 0, None) == 1
+    assert lib.msim_plan_destroy(None) == 0
