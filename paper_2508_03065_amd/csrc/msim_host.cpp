@@ -289,7 +289,7 @@ void image_interval(int m, double L, double lo, double hi, double* out_lo, doubl
 struct msim_plan {
     msim_params par{};
     int n_scenes = 0;
-    int threads = 512;                    // outputs per workgroup
+    int threads = 1024;                   // outputs per workgroup
     std::vector<DScene> scenes;           // host copies
     std::vector<DImage> images;
     std::vector<DGroup> groups;
@@ -486,8 +486,20 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     const int NT = P->threads, T = p.taps, L = p.table_phases;
     d.n_tiles = (int)((s.n_out + NT - 1) / NT);
     const size_t table_bytes = synth_lds_bytes(T, L, 0);
-    // enough workgroups to fill the chip several times over
-    int G = std::max(1, std::min(I, (int)((4 * 256 + (int64_t)d.n_tiles * s.n_mics - 1) / ((int64_t)d.n_tiles * s.n_mics))));
+    // Enough workgroups to fill the 256 CUs several times, in nearly whole rounds.
+    const int64_t base = (int64_t)d.n_tiles * s.n_mics;
+    int G = 1;
+    double best = -1.0;
+    for (int g = 1; g <= std::min(I, 128); ++g) {
+        const int64_t wgs = base * g;
+        const double rounds = std::ceil(wgs / 256.0);
+        const double eff = wgs / (rounds * 256.0) - (wgs < 3 * 256 ? 1.0 : 0.0);
+        if (eff > best + 1e-9) {
+            best = eff;
+            G = g;
+        }
+        if (wgs >= 16 * 256) break;
+    }
     std::vector<DGroup> gr;
     int window = 0;
     for (;;) {
@@ -519,12 +531,38 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     return MSIM_OK;
 }
 
-size_t fwd_ws_bytes(const msim_plan* P, const DScene& d)
+// Forward scratch of one scene, carved from the caller's workspace.
+struct FwdWs {
+    double* grid;     // exact delays on each image's grid, per mic
+    Seg* seg;         // per-segment cubic offsets
+    int32_t* segK;    // per-segment integer base
+    float* part;      // per-group partial outputs [mic][group][n_out]
+};
+
+size_t carve_fwd(const DScene& d, char* base, FwdWs* w)
 {
     const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
-    return align_up(segs * sizeof(Seg)) + align_up(segs * sizeof(int32_t)) +
-           align_up((size_t)d.n_mics * d.n_grp * d.n_out * sizeof(float));
+    const size_t grid = ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    char* g = take(grid * sizeof(double));
+    char* s = take(segs * sizeof(Seg));
+    char* k = take(segs * sizeof(int32_t));
+    char* p = take((size_t)d.n_mics * d.n_grp * d.n_out * sizeof(float));
+    if (w) {
+        w->grid = (double*)g;
+        w->seg = (Seg*)s;
+        w->segK = (int32_t*)k;
+        w->part = (float*)p;
+    }
+    return off;
 }
+
+size_t fwd_ws_bytes(const msim_plan*, const DScene& d) { return carve_fwd(d, nullptr, nullptr); }
 
 }  // namespace
 
@@ -680,26 +718,21 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
     if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
-        char* w = (char*)ws;
-        const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
-        Seg* seg = (Seg*)w;
-        w += align_up(segs * sizeof(Seg));
-        int32_t* segK = (int32_t*)w;
-        w += align_up(segs * sizeof(int32_t));
-        float* part = (float*)w;
+        FwdWs w;
+        carve_fwd(d, (char*)ws, &w);
         {
             LaunchTimer t(P, kKindTracks, stream);
-            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, seg, segK, P->par.c,
-                                 P->par.fs, P->par.delay_model, stream));
+            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, w.grid, w.seg, w.segK,
+                                 P->par.c, P->par.fs, P->par.delay_model, stream));
         }
         {
             LaunchTimer t(P, kKindSynth, stream);
             HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
-                                    P->par.table_phases, seg, segK, x, part, P->d_status, stream));
+                                    P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status, stream));
         }
         {
             LaunchTimer t(P, kKindReduce, stream);
-            HIP_OK(launch_reduce_groups(d, part, y, stream));
+            HIP_OK(launch_reduce_groups(d, w.part, y, stream));
         }
     }
     return MSIM_OK;

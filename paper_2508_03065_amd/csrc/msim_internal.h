@@ -72,7 +72,7 @@ constexpr int kStatusWindow = 1;
 
 // ---- kernel launchers (msim_kernels.hip) ----
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                         const double* d_knots, const double* d_mics, Seg* seg, int32_t* segK,
+                         const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st);
 
 hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,

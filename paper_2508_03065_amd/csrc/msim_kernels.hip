@@ -90,12 +90,45 @@ __device__ inline double solve_tau(const DScene& S, const int16_t m[3], const do
 
 // ------------------------------------------------------------------- tracks
 
-// One thread per (mic, segment).  Segment k of image i covers outputs
-// [kR, (k+1)R); its cubic interpolates the exact delays at (k-1)R .. (k+2)R.
-__global__ __launch_bounds__(256) void k_tracks(const DScene* __restrict__ scenes, int scene,
-                                                const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                                const double* __restrict__ mics, Seg* __restrict__ seg,
-                                                int32_t* __restrict__ segK, double c, double fs, int model)
+// Image owning flat index `idx` within one mic's track, where image ii owns
+// [off(ii), off(ii+1)) and off(ii) = seg_off + extra * ii.
+__device__ inline int owner(const DImage* __restrict__ I, int n_img, int64_t idx, int extra)
+{
+    int lo = 0, hi = n_img - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)I[mid].seg_off + (int64_t)extra * mid <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pass 1: exact delay of every image at every grid point kR, k = -1 .. n_seg+1,
+// one thread per (mic, image, grid point).  Grid of image ii starts at
+// seg_off + 3 ii within the mic's grid.
+__global__ __launch_bounds__(256) void k_grid(const DScene* __restrict__ scenes, int scene,
+                                              const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                              const double* __restrict__ mics, double* __restrict__ grid,
+                                              double c, double fs, int model)
+{
+    const DScene& S = scenes[scene];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_mic = S.seg_per_mic + 3 * (int64_t)S.n_img;
+    if (gid >= per_mic * S.n_mics) return;
+    const int mic = (int)(gid / per_mic);
+    const int64_t idx = gid - (int64_t)mic * per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const int ii = owner(I, S.n_img, idx, 3);
+    const DImage im = I[ii];
+    const int64_t k = idx - ((int64_t)im.seg_off + 3 * (int64_t)ii) - 1;
+    grid[gid] = fs * solve_tau(S, im.m, knots, mics, mic, (double)(k * im.R) / fs, 1.0 / c, model);
+}
+
+// Pass 2: one thread per (mic, segment): segment k of image i covers outputs
+// [kR, (k+1)R); its cubic is the uniform Catmull-Rom through the delays at
+// (k-1)R .. (k+2)R, stored as an integer base and FP32 offsets.
+__global__ __launch_bounds__(256) void k_segs(const DScene* __restrict__ scenes, int scene,
+                                              const DImage* __restrict__ imgs, const double* __restrict__ grid,
+                                              Seg* __restrict__ seg, int32_t* __restrict__ segK)
 {
     const DScene& S = scenes[scene];
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,53 +136,43 @@ __global__ __launch_bounds__(256) void k_tracks(const DScene* __restrict__ scene
     if (gid >= per_mic * S.n_mics) return;
     const int mic = (int)(gid / per_mic);
     const int64_t sidx = gid - (int64_t)mic * per_mic;
-    // image owning this segment: last image with seg_off <= sidx
     const DImage* I = imgs + S.img_begin;
-    int lo = 0, hi = S.n_img - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (I[mid].seg_off <= sidx) lo = mid; else hi = mid - 1;
-    }
-    const DImage im = I[lo];
+    const int ii = owner(I, S.n_img, sidx, 0);
+    const DImage im = I[ii];
     const int64_t k = sidx - im.seg_off;
-    const double inv_c = 1.0 / c;
-    const int R = im.R;
+    const double* D = grid + (int64_t)mic * (per_mic + 3 * (int64_t)S.n_img) + im.seg_off + 3 * (int64_t)ii + k;
+    const double d0 = D[0], d1 = D[1], d2 = D[2], d3 = D[3];
+    const double Kd = floor(d1);
     Seg out;
-    int32_t K;
-    if (R == 1) {
-        const double D = fs * solve_tau(S, im.m, knots, mics, mic, (double)k / fs, inv_c, model);
-        const double Kd = floor(D);
-        K = (int32_t)Kd;
-        out.a0 = (float)(D - Kd);
+    out.a0 = (float)(d1 - Kd);
+    if (im.R == 1) {
         out.b1 = out.b2 = out.b3 = 0.0f;
     } else {
-        double D[4];
-        for (int q = 0; q < 4; ++q)
-            D[q] = fs * solve_tau(S, im.m, knots, mics, mic, (double)((k - 1 + q) * R) / fs, inv_c, model);
-        const double Kd = floor(D[1]);
-        K = (int32_t)Kd;
-        const double a1 = 0.5 * (D[2] - D[0]);
-        const double a2 = 0.5 * (2.0 * D[0] - 5.0 * D[1] + 4.0 * D[2] - D[3]);
-        const double a3 = 0.5 * (3.0 * D[1] - D[0] - 3.0 * D[2] + D[3]);
-        const double iR = 1.0 / (double)R;
-        out.a0 = (float)(D[1] - Kd);
+        const double a1 = 0.5 * (d2 - d0);
+        const double a2 = 0.5 * (2.0 * d0 - 5.0 * d1 + 4.0 * d2 - d3);
+        const double a3 = 0.5 * (3.0 * d1 - d0 - 3.0 * d2 + d3);
+        const double iR = 1.0 / (double)im.R;
         out.b1 = (float)(a1 * iR);
         out.b2 = (float)(a2 * iR * iR);
         out.b3 = (float)(a3 * iR * iR * iR);
     }
     seg[gid] = out;
-    segK[gid] = K;
+    segK[gid] = (int32_t)Kd;
 }
 
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                         const double* d_knots, const double* d_mics, Seg* seg, int32_t* segK,
+                         const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st)
 {
-    const int64_t n = hs.seg_per_mic * hs.n_mics;
-    if (n == 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_tracks, dim3((unsigned)blocks), dim3(256), 0, st, d_scenes, scene, d_imgs, d_knots,
-                       d_mics, seg, segK, c, fs, delay_model);
+    const int64_t ng = (hs.seg_per_mic + 3 * (int64_t)hs.n_img) * hs.n_mics;
+    const int64_t ns = hs.seg_per_mic * hs.n_mics;
+    if (ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs,
+                       d_knots, d_mics, grid, c, fs, delay_model);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_segs, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs, grid,
+                       seg, segK);
     return hipGetLastError();
 }
 
@@ -209,17 +232,36 @@ __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __rest
     float acc = 0.0f;
     int bad = 0;
 
-    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = I[ii];
+    // the next image's track segment is fetched while the current one is filtered
+    auto seg_index = [&](const DImage& im, int* kout) {
         int k = (int)(fn * im.invR);
         k = min(max(k, 0), im.n_seg - 1);
-        const int64_t sidx = trk + im.seg_off + k;
-        const Seg sg = seg[sidx];
-        const int Ks = segK[sidx];
+        *kout = k;
+        return trk + im.seg_off + k;
+    };
+    DImage nim = I[G.img_begin];
+    int nk;
+    int64_t nsidx = seg_index(nim, &nk);
+    Seg nsg = seg[nsidx];
+    int nKs = segK[nsidx];
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = nim;
+        const int k = nk;
+        const Seg sg = nsg;
+        const int Ks = nKs;
+        if (ii + 1 < G.img_end) {
+            nim = I[ii + 1];
+            nsidx = seg_index(nim, &nk);
+            nsg = seg[nsidx];
+            nKs = segK[nsidx];
+        }
         const float v = (float)(n - (int64_t)k * im.R);
         const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
         const float fl = floorf(d);
         const int K = Ks + (int)fl;
+        // skip the image when no lane's taps reach a source sample
+        const int64_t xlo = n - K - T / 2, xhi = n - K + T / 2 - 1;
+        if (!__any(xhi >= 0 && xlo < n_in)) continue;
         const float mu = d - fl;
         const float gain = im.gfac * __builtin_amdgcn_rcpf((float)Ks + d);
         const float q = mu * Lf;
