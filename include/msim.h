@@ -136,6 +136,26 @@ msim_status msim_workspace_size(const msim_plan* plan, int32_t with_grad, size_t
  * x: device [x_total] FP32; y: device [y_total] FP32, fully overwritten. */
 msim_status msim_forward(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Reverse mode of msim_forward for a scalar loss L, given gy = dL/dy (device,
+ * [y_total] FP32).  Recomputes the delay tracks (nothing is kept from the
+ * forward) and writes, each only when its pointer is non-NULL (device memory):
+ *   gx    [x_total] FP32: dL/dx, the transpose time-varying fractional delay;
+ *   gbeta [n_scenes*6] FP64: dL/dbeta_w through beta_i = prod_w beta_w^hits_w;
+ *   gsrc  [src_total*3] FP64: dL/d(source knot position) for PWL sources, through
+ *         the Catmull-Rom delay interpolation and the implicit derivative of the
+ *         retarded delay (Sec. II-A, II-C-3); knots are packed per scene as
+ *         msim_plan_grad_layout reports (circle sources have none).
+ * Knot times, mic and receiver positions get no gradient.  ws holds
+ * msim_workspace_size(plan, 1) bytes.  dL/dx accumulates in LDS with atomic adds,
+ * so its last bits may differ from run to run; the other outputs are summed in
+ * a fixed order.  MSIM_E_UNSUPPORTED: a scene whose delay groups leave no LDS for
+ * the adjoint, or a source with more than 32 knots when gsrc is requested. */
+msim_status msim_backward(msim_plan* plan, const float* x, const float* gy, float* gx, double* gbeta,
+                          double* gsrc, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Offsets (in knots) of each scene's source knots in gsrc, and their total. */
+msim_status msim_plan_grad_layout(const msim_plan* plan, int64_t* src_off, int64_t* src_total);
+
 /* Reads and clears the plan's device-side status flags (synchronises the stream).
  * Bit 0: a delay left the window the plan bounded for it (output not trusted). */
 msim_status msim_device_status(msim_plan* plan, hipStream_t stream, int32_t* flags);

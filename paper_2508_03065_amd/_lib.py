@@ -61,6 +61,9 @@ SIGNATURES = {
     "msim_workspace_size": [_PLAN, C.c_int32, C.POINTER(C.c_size_t)],
     "msim_forward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     "msim_device_status": [_PLAN, C.c_void_p, C.POINTER(C.c_int32)],
+    "msim_backward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                      C.c_size_t, C.c_void_p],
+    "msim_plan_grad_layout": [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "msim_profile_begin": [_PLAN],
     "msim_profile_end": [_PLAN, C.POINTER(Profile)],
 }

@@ -1,0 +1,663 @@
+// gfx950 adjoint (reverse-mode) kernels of the moving image-source synthesis.
+//
+// The forward map is y_c[n] = sum_i g_i(n) s_i(n),  s_i(n) = sum_j h(j - mu_i(n)) x[n - K_i(n) - j],
+// with D_i(n) = K_i(n) + mu_i(n) the Catmull-Rom interpolated delay and
+// g_i(n) = beta_i fs / (4 pi c D_i(n))  (Eq. 2 / Eq. 8, Sec. II-B, Sec. II-C-3).
+// Given gy = dL/dy:
+//   adj_x      : dL/dx[m] = sum_{c,i,n} gy_c[n] g_i(n) h(n - D_i(n) - m), the transpose
+//                time-varying fractional delay, scattered into an LDS window per
+//                (mic, output tile, delay group) and gathered in fixed order.
+//   adj_track  : per image sample, s and s' = sum_j h'(j - mu) x[...]:
+//                dL/dbeta_i += gy s fs / (4 pi c D),  dL/dD_i(n) = -gy g (s' + s / D).
+//   seg/grid   : transpose of the Catmull-Rom interpolation (dL/dD on the delay
+//                grid), then the implicit-function derivative of the retarded
+//                delay c tau = |S_i p(t - tau) + O_i - r(t)| with respect to the
+//                source position at the emission time, split onto the two
+//                knots of its path segment.
+//   reduce     : fixed-order reductions to dL/dbeta_w and dL/dP_knot.
+#include "msim_device.h"
+#include "msim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace msim {
+
+namespace {
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Delay of image `im` at output n from its track segment.
+struct ImageSample {
+    int K;        // integer delay
+    float mu;     // fractional delay in [0, 1)
+    float D;      // delay in samples (FP32, for the gain)
+};
+
+__device__ inline ImageSample sample_of(const DImage& im, int k, const Seg& sg, int Ks, int64_t n)
+{
+    const float v = (float)(n - (int64_t)k * im.R);
+    const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
+    const float fl = floorf(d);
+    ImageSample r;
+    r.K = Ks + (int)fl;
+    r.mu = d - fl;
+    r.D = (float)Ks + d;
+    return r;
+}
+
+__device__ inline int64_t floordiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+}  // namespace
+
+size_t adj_x_lds_bytes(int taps, int L, int window)
+{
+    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) + (size_t)window * sizeof(float);
+}
+
+size_t adj_track_lds_bytes(int taps, int L, int window)
+{
+    const int L2 = L / 2;
+    return (size_t)(taps / 8) * ((size_t)(L + 1) + (size_t)(L2 + 1)) * sizeof(float4) +
+           (size_t)window * sizeof(float4);
+}
+
+// ------------------------------------------------------------ transpose delay
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict__ imgs,
+                                               const DGroup* __restrict__ groups, const float4* __restrict__ table,
+                                               int L, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                               const float* __restrict__ gy, float* __restrict__ xpart,
+                                               int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    constexpr int NG = T / 8;
+    const int rows = L + 1;
+    float4* tab = lds;
+    float* xb = (float*)(lds + NG * rows);
+
+    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const DGroup G = groups[S.grp_begin + g];
+    const int64_t n0 = (int64_t)tile * NT;
+    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int W = NT + (G.dmax - G.dmin) + T + 8;
+    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
+    for (int p = tid; p < W; p += NT) xb[p] = 0.0f;
+    __syncthreads();
+
+    const int64_t n = n0 + tid;
+    const bool valid = n < S.n_out;
+    const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
+    const int64_t nc = valid ? n : S.n_out - 1;
+    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const float fn = (float)nc + 0.5f;
+    const float Lf = (float)L;
+    const int64_t n_in = S.n_in;
+    int bad = 0;
+    auto seg_index = [&](const DImage& im, int* kout) {
+        int k = (int)(fn * im.invR);
+        k = min(max(k, 0), im.n_seg - 1);
+        *kout = k;
+        return trk + im.seg_off + k;
+    };
+    DImage nim = I[G.img_begin];
+    int nk;
+    int64_t nsidx = seg_index(nim, &nk);
+    Seg nsg = seg[nsidx];
+    int nKs = segK[nsidx];
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = nim;
+        const int k = nk;
+        const Seg sg = nsg;
+        const int Ks = nKs;
+        if (ii + 1 < G.img_end) {
+            nim = I[ii + 1];
+            nsidx = seg_index(nim, &nk);
+            nsg = seg[nsidx];
+            nKs = segK[nsidx];
+        }
+        const ImageSample smp = sample_of(im, k, sg, Ks, nc);
+        const int64_t xlo = nc - smp.K - T / 2, xhi = nc - smp.K + T / 2 - 1;
+        const bool act = valid && wy != 0.0f && xhi >= 0 && xlo < n_in;
+        if (!__any(act)) continue;
+        const int p0 = (int)(nc - smp.K - ws);
+        if (act && (p0 < T / 2 || p0 > W - T / 2)) bad = 1;
+        if (!act || p0 < T / 2 || p0 > W - T / 2) continue;
+        const float w = wy * im.gfac * __builtin_amdgcn_rcpf(smp.D);
+        const float q = smp.mu * Lf;
+        const int kq = min((int)q, L - 1);
+        const float f = q - (float)kq;
+        const float a = w * (1.0f - f), b = w * f;
+        const float4* tn = tab + kq;
+        const float4* tp = tab + (L - 1 - kq);
+        float* xq = xb + p0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            const float4 P = tn[gi * rows];
+            const float4 Q = tn[gi * rows + 1];
+            atomicAdd(xq + 4 * gi + 0, fmaf(a, P.x, b * Q.x));
+            atomicAdd(xq + 4 * gi + 1, fmaf(a, P.y, b * Q.y));
+            atomicAdd(xq + 4 * gi + 2, fmaf(a, P.z, b * Q.z));
+            atomicAdd(xq + 4 * gi + 3, fmaf(a, P.w, b * Q.w));
+            const float4 P2 = tp[gi * rows];
+            const float4 Q2 = tp[gi * rows + 1];
+            atomicAdd(xq - 1 - 4 * gi - 0, fmaf(b, P2.x, a * Q2.x));
+            atomicAdd(xq - 1 - 4 * gi - 1, fmaf(b, P2.y, a * Q2.y));
+            atomicAdd(xq - 1 - 4 * gi - 2, fmaf(b, P2.z, a * Q2.z));
+            atomicAdd(xq - 1 - 4 * gi - 3, fmaf(b, P2.w, a * Q2.w));
+        }
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+    __syncthreads();
+    float* out = xpart + (((int64_t)mic * S.n_grp + g) * S.n_tiles + tile) * S.window;
+    for (int p = tid; p < W; p += NT) out[p] = xb[p];
+}
+
+template <int T, int NT>
+static hipError_t launch_adj_x_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                                 const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                                 float* xpart, int32_t* d_status, hipStream_t st)
+{
+    const size_t lds = adj_x_lds_bytes(T, L, hs.window);
+    auto kern = k_adj_x<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, L, seg, segK, gy, xpart,
+                       d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                        const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                        float* xpart, int32_t* d_status, hipStream_t st)
+{
+#define MSIM_ADJX_CASE(TT, NN)                                                                                 \
+    if (taps == TT && nthreads == NN)                                                                          \
+        return launch_adj_x_t<TT, NN>(hs, d_imgs, d_groups, d_table, L, seg, segK, gy, xpart, d_status, st);
+    MSIM_ADJX_CASE(32, 1024)
+    MSIM_ADJX_CASE(64, 1024)
+    MSIM_ADJX_CASE(96, 1024)
+    MSIM_ADJX_CASE(128, 1024)
+    MSIM_ADJX_CASE(32, 512)
+    MSIM_ADJX_CASE(64, 512)
+    MSIM_ADJX_CASE(96, 512)
+    MSIM_ADJX_CASE(128, 512)
+#undef MSIM_ADJX_CASE
+    return hipErrorInvalidValue;
+}
+
+// Gathers the partial windows that cover each input sample, in a fixed order
+// (mic, group, tile).  Window (mic, g, tile) covers inputs
+// [tile*NT - c_g, tile*NT - c_g + W_g),  c_g = dmax_g + T/2 + 4.
+__global__ __launch_bounds__(256) void k_reduce_x(DScene S, const DGroup* __restrict__ groups, int NT, int T,
+                                                  const float* __restrict__ xpart, float* __restrict__ gx)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= S.n_in) return;
+    float acc = 0.0f;
+    for (int mic = 0; mic < S.n_mics; ++mic)
+        for (int g = 0; g < S.n_grp; ++g) {
+            const DGroup G = groups[S.grp_begin + g];
+            const int64_t cg = G.dmax + T / 2 + 4;
+            const int64_t Wg = NT + (G.dmax - G.dmin) + T + 8;
+            int64_t t_lo = floordiv(m + cg - Wg + 1 + NT - 1, NT);
+            int64_t t_hi = floordiv(m + cg, NT);
+            t_lo = t_lo < 0 ? 0 : t_lo;
+            t_hi = t_hi > S.n_tiles - 1 ? S.n_tiles - 1 : t_hi;
+            for (int64_t t = t_lo; t <= t_hi; ++t) {
+                const int64_t p = m - (t * NT - cg);
+                acc += xpart[(((int64_t)mic * S.n_grp + g) * S.n_tiles + t) * S.window + p];
+            }
+        }
+    gx[S.x_off + m] = acc;
+}
+
+hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
+                           float* gx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)((hs.n_in + 255) / 256)), dim3(256), 0, st, hs, d_groups,
+                       nthreads, taps, xpart, gx);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------- gain and delay adjoints
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __restrict__ imgs,
+                                                   const DGroup* __restrict__ groups,
+                                                   const float4* __restrict__ table,
+                                                   const float4* __restrict__ dtable, int L,
+                                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                                   const float* __restrict__ x, const float* __restrict__ gy,
+                                                   float ghat, float* __restrict__ dbar, float* __restrict__ gpart,
+                                                   int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    constexpr int NG = T / 8;
+    constexpr int WAVES = NT / 64;
+    const int rows = L + 1;
+    const int L2 = L / 2;
+    const int rows2 = L2 + 1;
+    float4* tab = lds;
+    float4* dtab = lds + NG * rows;
+    float4* xw = dtab + NG * rows2;
+
+    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const DGroup G = groups[S.grp_begin + g];
+    const int64_t n0 = (int64_t)tile * NT;
+    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int W = NT + (G.dmax - G.dmin) + T + 8;
+    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
+    for (int i = tid; i < NG * rows2; i += NT) dtab[i] = dtable[i];
+    const float* xs = x + S.x_off;
+    const int64_t n_in = S.n_in;
+    for (int p = tid; p < W; p += NT) {
+        const int64_t q = ws + p;
+        float4 v;
+        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
+        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
+        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
+        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
+        xw[p] = v;
+    }
+    __syncthreads();
+
+    const int64_t n = n0 + tid;
+    const bool valid = n < S.n_out;
+    const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
+    const int64_t nc = valid ? n : S.n_out - 1;
+    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const float fn = (float)nc + 0.5f;
+    const float Lf = (float)L, L2f = (float)L2;
+    float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
+    float* gout = gpart + (((int64_t)mic * S.n_tiles + tile) * WAVES + wave) * S.n_img;
+    int bad = 0;
+    auto seg_index = [&](const DImage& im, int* kout) {
+        int k = (int)(fn * im.invR);
+        k = min(max(k, 0), im.n_seg - 1);
+        *kout = k;
+        return trk + im.seg_off + k;
+    };
+    DImage nim = I[G.img_begin];
+    int nk;
+    int64_t nsidx = seg_index(nim, &nk);
+    Seg nsg = seg[nsidx];
+    int nKs = segK[nsidx];
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = nim;
+        const int k = nk;
+        const Seg sg = nsg;
+        const int Ks = nKs;
+        if (ii + 1 < G.img_end) {
+            nim = I[ii + 1];
+            nsidx = seg_index(nim, &nk);
+            nsg = seg[nsidx];
+            nKs = segK[nsidx];
+        }
+        const ImageSample smp = sample_of(im, k, sg, Ks, nc);
+        const int64_t xlo = nc - smp.K - T / 2, xhi = nc - smp.K + T / 2 - 1;
+        const bool act = valid && xhi >= 0 && xlo < n_in;
+        float E = 0.0f, Db = 0.0f;
+        if (__any(act)) {
+            const int p0 = (int)(nc - smp.K - ws);
+            const bool inb = p0 >= T / 2 && p0 <= W - T / 2 + 3;
+            if (act && !inb) bad = 1;
+            if (act && inb) {
+                const float q = smp.mu * Lf;
+                const int kq = min((int)q, L - 1);
+                const float f = q - (float)kq;
+                const float q2 = smp.mu * L2f;
+                const int kq2 = min((int)q2, L2 - 1);
+                const float f2 = q2 - (float)kq2;
+                const float4* tn = tab + kq;
+                const float4* tp = tab + (L - 1 - kq);
+                const float4* dn = dtab + kq2;
+                const float4* dp = dtab + (L2 - 1 - kq2);
+                const float4* xq = xw + p0;
+                float A = 0.f, B = 0.f, A2 = 0.f, B2 = 0.f;
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    const float4 xn = xq[4 * gi];
+                    const float4 xp = xq[-4 - 4 * gi];
+                    const float4 P = tn[gi * rows], Q = tn[gi * rows + 1];
+                    const float4 P2 = tp[gi * rows], Q2 = tp[gi * rows + 1];
+                    A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
+                    A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
+                    A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
+                    A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
+                    B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
+                    B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
+                    B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
+                    B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
+                    // h' is odd: the taps left of the delay take -h'(|u|)
+                    const float4 R = dn[gi * rows2], U = dn[gi * rows2 + 1];
+                    const float4 R2 = dp[gi * rows2], U2 = dp[gi * rows2 + 1];
+                    A2 = fmaf(-R.x, xn.x, A2); B2 = fmaf(-U.x, xn.x, B2);
+                    A2 = fmaf(-R.y, xn.y, A2); B2 = fmaf(-U.y, xn.y, B2);
+                    A2 = fmaf(-R.z, xn.z, A2); B2 = fmaf(-U.z, xn.z, B2);
+                    A2 = fmaf(-R.w, xn.w, A2); B2 = fmaf(-U.w, xn.w, B2);
+                    B2 = fmaf(R2.x, xp.w, B2); A2 = fmaf(U2.x, xp.w, A2);
+                    B2 = fmaf(R2.y, xp.z, B2); A2 = fmaf(U2.y, xp.z, A2);
+                    B2 = fmaf(R2.z, xp.y, B2); A2 = fmaf(U2.z, xp.y, A2);
+                    B2 = fmaf(R2.w, xp.x, B2); A2 = fmaf(U2.w, xp.x, A2);
+                }
+                const float s = fmaf(f, B - A, A);
+                const float sp = fmaf(f2, B2 - A2, A2);
+                const float iD = __builtin_amdgcn_rcpf(smp.D);
+                const float gain = im.gfac * iD;
+                E = wy * s * ghat * iD;
+                Db = -wy * gain * fmaf(s, iD, sp);
+            }
+        }
+        if (valid) dout[(int64_t)ii * S.n_out] = Db;
+        E = wave_sum(E);
+        if (lane == 0) gout[ii] = E;
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+}
+
+template <int T, int NT>
+static hipError_t launch_adj_track_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                                     const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
+                                     const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
+                                     float* gpart, int32_t* d_status, hipStream_t st)
+{
+    const size_t lds = adj_track_lds_bytes(T, L, hs.window);
+    auto kern = k_adj_track<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, d_dtable, L, seg, segK, x, gy,
+                       ghat, dbar, gpart, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                            const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
+                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
+                            float* gpart, int32_t* d_status, hipStream_t st)
+{
+#define MSIM_ADJT_CASE(TT, NN)                                                                                 \
+    if (taps == TT && nthreads == NN)                                                                          \
+        return launch_adj_track_t<TT, NN>(hs, d_imgs, d_groups, d_table, d_dtable, L, seg, segK, x, gy, ghat,   \
+                                          dbar, gpart, d_status, st);
+    MSIM_ADJT_CASE(32, 1024)
+    MSIM_ADJT_CASE(64, 1024)
+    MSIM_ADJT_CASE(96, 1024)
+    MSIM_ADJT_CASE(128, 1024)
+    MSIM_ADJT_CASE(32, 512)
+    MSIM_ADJT_CASE(64, 512)
+    MSIM_ADJT_CASE(96, 512)
+    MSIM_ADJT_CASE(128, 512)
+#undef MSIM_ADJT_CASE
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------- Catmull-Rom transpose, retarded delay
+
+// Per (mic, segment): the segment's outputs n = kR + v weight the grid delays
+// D_{k-1..k+2} by the Catmull-Rom basis at u = v/R; sum dL/dD(n) times each weight.
+__global__ __launch_bounds__(256) void k_seg_adj(DScene S, const DImage* __restrict__ imgs,
+                                                 const float* __restrict__ dbar, float4* __restrict__ dseg)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_mic = S.seg_per_mic;
+    if (gid >= per_mic * S.n_mics) return;
+    const int mic = (int)(gid / per_mic);
+    const int64_t sidx = gid - (int64_t)mic * per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const int ii = owner(I, S.n_img, sidx, 0);
+    const DImage im = I[ii];
+    const int64_t k = sidx - im.seg_off;
+    const float* Db = dbar + ((int64_t)mic * S.n_img + ii) * S.n_out;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t nb = k * im.R;
+    const double iR = 1.0 / (double)im.R;
+    for (int v = 0; v < im.R; ++v) {
+        const int64_t n = nb + v;
+        if (n >= S.n_out) break;
+        const double d = Db[n];
+        const double u = v * iR, u2 = u * u, u3 = u2 * u;
+        s0 += d * 0.5 * (-u + 2.0 * u2 - u3);
+        s1 += d * 0.5 * (2.0 - 5.0 * u2 + 3.0 * u3);
+        s2 += d * 0.5 * (u + 4.0 * u2 - 3.0 * u3);
+        s3 += d * 0.5 * (-u2 + u3);
+    }
+    dseg[gid] = make_float4((float)s0, (float)s1, (float)s2, (float)s3);
+}
+
+// Per (mic, grid point k of an image): dL/dtau_k = fs * sum of the segment
+// weights that reference D_k; then dtau_k / d p(t_e) for the source position
+// at the emission time t_e = t_k - tau_k:
+//   retarded:       S^T u / (c + u . S p'(t_e)),  u = unit vector mic -> image
+//   instantaneous:  S^T u / c
+// and the knot a of t_e's path segment with the weight lam of knot a+1.
+__global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ scenes, int scene,
+                                                  const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                                  const double* __restrict__ mics, const double* __restrict__ grid,
+                                                  const float4* __restrict__ dseg, double4* __restrict__ pgc,
+                                                  int32_t* __restrict__ pga, double c, double fs, int model)
+{
+    const DScene& S = scenes[scene];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_mic = S.seg_per_mic + 3 * (int64_t)S.n_img;
+    if (gid >= per_mic * S.n_mics) return;
+    const int mic = (int)(gid / per_mic);
+    const int64_t idx = gid - (int64_t)mic * per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const int ii = owner(I, S.n_img, idx, 3);
+    const DImage im = I[ii];
+    const int64_t k = idx - ((int64_t)im.seg_off + 3 * (int64_t)ii) - 1;
+    const float4* ds = dseg + (int64_t)mic * S.seg_per_mic + im.seg_off;
+    double dD = 0.0;
+    // segment s uses grid point k with basis index q = k - s + 1
+    for (int q = 0; q < 4; ++q) {
+        const int64_t s = k + 1 - q;
+        if (s < 0 || s >= im.n_seg) continue;
+        const float4 w = ds[s];
+        dD += (q == 0) ? w.x : (q == 1) ? w.y : (q == 2) ? w.z : w.w;
+    }
+    const double taubar = fs * dD;
+    double4 out = make_double4(0.0, 0.0, 0.0, 0.0);
+    int a = -1;
+    if (S.src.kind == 0 && taubar != 0.0) {
+        const double tk = (double)(k * im.R) / fs;
+        const double tau = grid[gid] / fs;
+        const double te = model == 0 ? tk - tau : tk;
+        double q[3], r[3], v[3];
+        traj_pos(S.src, knots, te, q);
+        mic_pos(S, knots, mics, mic, tk, r);
+        double e[3], d2 = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            e[ax] = image_coord(im.m[ax], S.size[ax], q[ax]) - r[ax];
+            d2 += e[ax] * e[ax];
+        }
+        const double id = 1.0 / sqrt(d2);
+        double denom = c;
+        traj_vel(S.src, knots, te, v);
+        double sgn[3];
+        for (int ax = 0; ax < 3; ++ax) sgn[ax] = (im.m[ax] & 1) ? -1.0 : 1.0;
+        if (model == 0)
+            for (int ax = 0; ax < 3; ++ax) denom += e[ax] * id * sgn[ax] * v[ax];
+        const double sc = taubar * id / denom;
+        out.x = sc * sgn[0] * e[0];
+        out.y = sc * sgn[1] * e[1];
+        out.z = sc * sgn[2] * e[2];
+        double lam;
+        pwl_locate(S.src, knots, te, &a, &lam);
+        out.w = lam;
+    }
+    pgc[gid] = out;
+    pga[gid] = a;
+}
+
+hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                             const double* d_knots, const double* d_mics, const double* grid, const float* dbar,
+                             float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,
+                             int want_src, hipStream_t st)
+{
+    const int64_t ns = hs.seg_per_mic * hs.n_mics;
+    hipLaunchKernelGGL(k_seg_adj, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, hs, d_imgs, dbar, dseg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !want_src) return e;
+    const int64_t ng = (hs.seg_per_mic + 3 * (int64_t)hs.n_img) * hs.n_mics;
+    hipLaunchKernelGGL(k_grid_adj, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs,
+                       d_knots, d_mics, grid, dseg, pgc, pga, c, fs, delay_model);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- reductions
+
+constexpr int kMaxGradKnots = 32;
+constexpr int kRedThreads = 256;
+
+// Fixed-order block sum of one double per thread; every thread returns the total.
+__device__ inline double block_sum(double v, double* sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Block b of NB: images ii = b*256 + t (+ k*NB*256) give dL/dbeta_w partials,
+// sum_i (d beta_i / d beta_w) G_i with G_i = dL/dbeta_i summed over mics, tiles
+// and waves; grid points i = b*256 + t (+ k*NB*256) give dL/dP_a partials.
+// partial: [NB][6 + 3*kMaxGradKnots].
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __restrict__ scenes, int scene,
+                                                                const DImage* __restrict__ imgs,
+                                                                const float* __restrict__ gpart, int gstride,
+                                                                const double4* __restrict__ pgc,
+                                                                const int32_t* __restrict__ pga, int want_beta,
+                                                                int want_src, double* __restrict__ partial)
+{
+    __shared__ double sh[kRedThreads];
+    const DScene& S = scenes[scene];
+    const int t = threadIdx.x, b = blockIdx.x, NB = gridDim.x;
+    const int64_t stride = (int64_t)NB * kRedThreads;
+    double* out = partial + (int64_t)b * (6 + 3 * kMaxGradKnots);
+    const DImage* I = imgs + S.img_begin;
+    if (want_beta) {
+        double bw[6] = {0, 0, 0, 0, 0, 0};
+        const int64_t nrow = (int64_t)S.n_mics * gstride;
+        for (int64_t ii = (int64_t)b * kRedThreads + t; ii < S.n_img; ii += stride) {
+            double Gi = 0.0;
+            for (int64_t r = 0; r < nrow; ++r) Gi += gpart[r * S.n_img + ii];
+            const DImage im = I[ii];
+            for (int w = 0; w < 6; ++w) {
+                const int h = im.hits[w];
+                if (h == 0) continue;
+                double d = (double)h;
+                for (int r = 0; r < h - 1; ++r) d *= S.beta[w];
+                for (int v = 0; v < 6; ++v) {
+                    if (v == w) continue;
+                    for (int r = 0; r < im.hits[v]; ++r) d *= S.beta[v];
+                }
+                bw[w] += d * Gi;
+            }
+        }
+        for (int w = 0; w < 6; ++w) {
+            const double tot = block_sum(bw[w], sh);
+            if (t == 0) out[w] = tot;
+        }
+    }
+    if (want_src && S.src_knots > 0) {
+        const int nk = min(S.src_knots, kMaxGradKnots);
+        double acc[kMaxGradKnots][3];
+#pragma unroll
+        for (int j = 0; j < kMaxGradKnots; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+        const int64_t total = (S.seg_per_mic + 3 * (int64_t)S.n_img) * S.n_mics;
+        for (int64_t i = (int64_t)b * kRedThreads + t; i < total; i += stride) {
+            const int a = pga[i];
+            if (a < 0) continue;
+            const double4 v = pgc[i];
+            const double wa = 1.0 - v.w, wb = v.w;
+#pragma unroll
+            for (int j = 0; j < kMaxGradKnots; ++j) {
+                const double f = (j == a) ? wa : (j == a + 1) ? wb : 0.0;
+                acc[j][0] += f * v.x;
+                acc[j][1] += f * v.y;
+                acc[j][2] += f * v.z;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxGradKnots; ++j) {
+            if (j >= nk) break;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double tot = block_sum(acc[j][ax], sh);
+                if (t == 0) out[6 + 3 * j + ax] = tot;
+            }
+        }
+    }
+}
+
+// Sums the NB block partials in block order.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const DScene* __restrict__ scenes, int scene, int NB,
+                                                              const double* __restrict__ partial, int want_beta,
+                                                              int want_src, double* __restrict__ gbeta,
+                                                              double* __restrict__ gsrc)
+{
+    const DScene& S = scenes[scene];
+    const int t = threadIdx.x;
+    const int row = 6 + 3 * kMaxGradKnots;
+    if (t < 6 && want_beta) {
+        double v = 0.0;
+        for (int b = 0; b < NB; ++b) v += partial[(int64_t)b * row + t];
+        gbeta[(int64_t)scene * 6 + t] = v;
+    }
+    const int nk = min(S.src_knots, kMaxGradKnots);
+    if (want_src && t < 3 * nk) {
+        double v = 0.0;
+        for (int b = 0; b < NB; ++b) v += partial[(int64_t)b * row + 6 + t];
+        gsrc[(int64_t)S.src_grad_off * 3 + t] = v;
+    }
+}
+
+int reduce_blocks(const DScene& hs)
+{
+    const int64_t total = (hs.seg_per_mic + 3 * (int64_t)hs.n_img) * hs.n_mics;
+    int64_t nb = (total + 8191) / 8192;
+    nb = nb < 1 ? 1 : nb > 512 ? 512 : nb;
+    return (int)nb;
+}
+
+size_t reduce_partial_bytes(const DScene& hs) { return (size_t)reduce_blocks(hs) * (6 + 3 * kMaxGradKnots) * 8; }
+
+int max_grad_knots() { return kMaxGradKnots; }
+
+hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                                const float* gpart, int gpart_stride, const double4* pgc, const int32_t* pga,
+                                double* partial, double* gbeta, double* gsrc, hipStream_t st)
+{
+    const int NB = reduce_blocks(hs);
+    const int wb = gbeta != nullptr, wsrc = gsrc != nullptr && hs.src_knots > 0;
+    hipLaunchKernelGGL(k_reduce_partial, dim3(NB), dim3(kRedThreads), 0, st, d_scenes, scene, d_imgs, gpart,
+                       gpart_stride, pgc, pga, wb, wsrc, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, d_scenes, scene, NB, partial, wb, wsrc,
+                       gbeta, gsrc);
+    return hipGetLastError();
+}
+
+}  // namespace msim

@@ -1,0 +1,152 @@
+// Device-side geometry shared by the forward and adjoint kernels: trajectories,
+// image positions and the retarded-delay solve.
+#pragma once
+
+#include "msim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace msim {
+
+// ------------------------------------------------------------------ geometry
+
+__device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
+{
+    if (tr.kind == 1) {
+        double s, c;
+        sincos(tr.omega * t + tr.phase0, &s, &c);
+        out[0] = tr.center[0] + tr.radius * c;
+        out[1] = tr.center[1] + tr.radius * s;
+        out[2] = tr.center[2];
+        return;
+    }
+    const double* T = knots + tr.knot_off;
+    const double* P = knots + tr.pos_off;
+    const int n = tr.n_points;
+    int a;
+    double lam;
+    if (n == 1 || t <= T[0]) {
+        a = 0;
+        lam = 0.0;
+    } else if (t >= T[n - 1]) {
+        a = n - 1;
+        lam = 0.0;
+    } else {
+        a = 0;
+        while (a + 2 < n && t >= T[a + 1]) ++a;
+        lam = (t - T[a]) / (T[a + 1] - T[a]);
+    }
+    const int b = (lam > 0.0) ? a + 1 : a;
+    for (int k = 0; k < 3; ++k) out[k] = P[3 * a + k] + lam * (P[3 * b + k] - P[3 * a + k]);
+}
+
+__device__ inline double image_coord(int m, double L, double q)
+{
+    return (m & 1) ? (double)(m + 1) * L - q : (double)m * L + q;
+}
+
+__device__ inline double dist_to(const DScene& S, const int16_t m[3], const double* knots, const double r[3], double te)
+{
+    double q[3];
+    traj_pos(S.src, knots, te, q);
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
+        d2 += e * e;
+    }
+    return sqrt(d2);
+}
+
+// Propagation delay (s) for sound received at time t by mic position r.
+// Retarded: c tau = |p_i(t - tau) - r(t)|, fixed-point iteration (contraction
+// factor |v_source|/c < 0.1 by validation).  Instantaneous: |p_i(t) - r(t)| / c.
+__device__ inline double solve_tau(const DScene& S, const int16_t m[3], const double* knots, const double* mics,
+                                   int mic, double t, double inv_c, int model)
+{
+    double r[3];
+    traj_pos(S.rcv, knots, t, r);
+    const double* off = mics + 3 * (S.mic_off + mic);
+    r[0] += off[0];
+    r[1] += off[1];
+    r[2] += off[2];
+    double tau = dist_to(S, m, knots, r, t) * inv_c;
+    if (model == 0) {
+        for (int it = 0; it < 60; ++it) {
+            const double nt = dist_to(S, m, knots, r, t - tau) * inv_c;
+            const double d = fabs(nt - tau);
+            tau = nt;
+            if (d <= 1e-15 * tau) break;
+        }
+    }
+    return tau;
+}
+
+// ------------------------------------------------------------------- tracks
+
+// Image owning flat index `idx` within one mic's track, where image ii owns
+// [off(ii), off(ii+1)) and off(ii) = seg_off + extra * ii.
+__device__ inline int owner(const DImage* __restrict__ I, int n_img, int64_t idx, int extra)
+{
+    int lo = 0, hi = n_img - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)I[mid].seg_off + (int64_t)extra * mid <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// PWL segment of time t: knot a and weight lam of knot a+1 (lam = 0 when t is
+// outside the knot range or the path is static; then only knot a moves it).
+__device__ inline void pwl_locate(const DTraj& tr, const double* __restrict__ knots, double t, int* a_out,
+                                  double* lam_out)
+{
+    const double* T = knots + tr.knot_off;
+    const int n = tr.n_points;
+    int a = 0;
+    double lam = 0.0;
+    if (n == 1 || t <= T[0]) {
+        a = 0;
+    } else if (t >= T[n - 1]) {
+        a = n - 1;
+    } else {
+        while (a + 2 < n && t >= T[a + 1]) ++a;
+        lam = (t - T[a]) / (T[a + 1] - T[a]);
+    }
+    *a_out = a;
+    *lam_out = lam;
+}
+
+// Velocity of a trajectory at time t (zero outside a PWL path's knot range).
+__device__ inline void traj_vel(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
+{
+    if (tr.kind == 1) {
+        double s, c;
+        sincos(tr.omega * t + tr.phase0, &s, &c);
+        const double v = tr.radius * tr.omega;
+        out[0] = -v * s;
+        out[1] = v * c;
+        out[2] = 0.0;
+        return;
+    }
+    const double* T = knots + tr.knot_off;
+    const double* P = knots + tr.pos_off;
+    const int n = tr.n_points;
+    out[0] = out[1] = out[2] = 0.0;
+    if (n == 1 || t <= T[0] || t >= T[n - 1]) return;
+    int a = 0;
+    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const double idt = 1.0 / (T[a + 1] - T[a]);
+    for (int k = 0; k < 3; ++k) out[k] = (P[3 * (a + 1) + k] - P[3 * a + k]) * idt;
+}
+
+__device__ inline void mic_pos(const DScene& S, const double* __restrict__ knots, const double* __restrict__ mics,
+                               int mic, double t, double r[3])
+{
+    traj_pos(S.rcv, knots, t, r);
+    const double* off = mics + 3 * (S.mic_off + mic);
+    r[0] += off[0];
+    r[1] += off[1];
+    r[2] += off[2];
+}
+
+}  // namespace msim

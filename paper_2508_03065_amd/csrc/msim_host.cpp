@@ -295,7 +295,10 @@ struct msim_plan {
     std::vector<DGroup> groups;
     std::vector<double> knots, mics;
     std::vector<float> table;             // float4 groups, flattened
+    std::vector<float> dtable;            // derivative table (L/2 phases), same layout
     std::vector<int64_t> n_img;
+    int64_t src_grad_total = 0;           // knots in the packed d/dsource array
+    std::vector<bool> grad_ok;            // the adjoint's LDS fits this scene's windows
     double fwd_taps = 0.0;
     int64_t x_total = 0, y_total = 0;
     // device
@@ -305,6 +308,7 @@ struct msim_plan {
     double* d_knots = nullptr;
     double* d_mics = nullptr;
     float4* d_table = nullptr;
+    float4* d_dtable = nullptr;
     int32_t* d_status = nullptr;
     int device = 0;
     // profiling: (kind, start, stop) per launch while enabled
@@ -357,18 +361,59 @@ struct LaunchTimer {
 
 namespace {
 
-void build_table(msim_plan* P)
+// I1(b s) / s by its power series (b/2) sum_k (b^2 s^2 / 4)^k / (k! (k+1)!), finite at s = 0.
+double bessel_i1_over(double b, double s)
 {
-    const int T = P->par.taps, L = P->par.table_phases, NG = T / 8;
-    const double i0b = bessel_i0(P->par.kaiser_beta);
-    P->table.assign((size_t)NG * (L + 1) * 4, 0.0f);
+    const double q = 0.25 * b * b * s * s;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 1000 && term > 1e-17 * sum; ++k) {
+        term *= q / (double(k) * double(k + 1));
+        sum += term;
+    }
+    return 0.5 * b * sum;
+}
+
+// Derivative h'(v) of the Kaiser-windowed sinc h(v) = 2 fc sinc(2 fc v) w(v).
+double fd_kernel_deriv(double v, int T, double kbeta, double fc, double i0b)
+{
+    if (std::fabs(v) > 0.5 * T) return 0.0;
+    const double z = 2.0 * fc * v;
+    double sinc, dsinc;   // sinc(z) and d sinc / dz
+    if (std::fabs(z) < 1e-8) {
+        sinc = 1.0;
+        dsinc = -kPi * kPi * z / 3.0;
+    } else {
+        sinc = std::sin(kPi * z) / (kPi * z);
+        dsinc = (std::cos(kPi * z) - sinc) / z;
+    }
+    const double r = 2.0 * v / T;
+    const double s = std::sqrt(std::max(0.0, 1.0 - r * r));
+    const double w = bessel_i0(kbeta * s) / i0b;
+    // d/dv I0(b s(v)) = I1(b s) b s'(v),  s' = -r (2/T) / s
+    const double dw = -kbeta * (2.0 / T) * r * bessel_i1_over(kbeta, s) / i0b;
+    return 2.0 * fc * (2.0 * fc * dsinc * w + sinc * dw);
+}
+
+// Half tables grouped by tap quads: tab[g][row] = h((4g+e) + row/L), e = 0..3.
+void build_quads(std::vector<float>& out, int T, int L, double kbeta, double fc, bool deriv)
+{
+    const int NG = T / 8;
+    const double i0b = bessel_i0(kbeta);
+    out.assign((size_t)NG * (L + 1) * 4, 0.0f);
     for (int g = 0; g < NG; ++g)
         for (int row = 0; row <= L; ++row)
             for (int e = 0; e < 4; ++e) {
                 const double v = (4 * g + e) + double(row) / L;
-                P->table[((size_t)g * (L + 1) + row) * 4 + e] =
-                    (float)fd_kernel(v, T, P->par.kaiser_beta, P->par.cutoff, i0b);
+                out[((size_t)g * (L + 1) + row) * 4 + e] =
+                    (float)(deriv ? fd_kernel_deriv(v, T, kbeta, fc, i0b) : fd_kernel(v, T, kbeta, fc, i0b));
             }
+}
+
+void build_table(msim_plan* P)
+{
+    build_quads(P->table, P->par.taps, P->par.table_phases, P->par.kaiser_beta, P->par.cutoff, false);
+    // the derivative table is read only by the adjoint, at half the phase density
+    build_quads(P->dtable, P->par.taps, P->par.table_phases / 2, P->par.kaiser_beta, P->par.cutoff, true);
 }
 
 int push_traj(msim_plan* P, const msim_traj& tr, DTraj* d)
@@ -478,14 +523,24 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
         di.gfac = (float)(h.beta * p.fs / (4.0 * kPi * p.c));
         di.seg_off = (int32_t)seg;
         di.n_seg = (int32_t)((s.n_out + h.R - 1) / h.R);
+        for (int w = 0; w < 6; ++w) di.hits[w] = (int8_t)h.hits[w];
         seg += di.n_seg;
         P->images.push_back(di);
     }
+    for (int w = 0; w < 6; ++w) d.beta[w] = s.beta[w];
+    d.src_grad_off = (int32_t)P->src_grad_total;
+    d.src_knots = s.src.kind == MSIM_TRAJ_PWL ? s.src.n_points : 0;
+    P->src_grad_total += d.src_knots;
     if (seg > INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "scene %d: track too long", si);
     d.seg_per_mic = seg;
     const int NT = P->threads, T = p.taps, L = p.table_phases;
     d.n_tiles = (int)((s.n_out + NT - 1) / NT);
-    const size_t table_bytes = synth_lds_bytes(T, L, 0);
+    // Group windows are sized so the adjoint's LDS (value and derivative tables
+    // beside the source window) fits too; failing that, the forward's alone.
+    bool grad_fit = true;
+    auto fits = [&](int window) {
+        return (grad_fit ? adj_track_lds_bytes(T, L, window) : synth_lds_bytes(T, L, window)) <= kLdsLimit;
+    };
     // Enough workgroups to fill the 256 CUs several times, in nearly whole rounds.
     const int64_t base = (int64_t)d.n_tiles * s.n_mics;
     int G = 1;
@@ -517,10 +572,15 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
             gr.push_back(dg);
             window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
         }
-        if (table_bytes + (size_t)window * sizeof(float4) <= kLdsLimit) break;
-        if (G >= I) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", si);
+        if (fits(window)) break;
+        if (G >= I) {
+            if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", si);
+            grad_fit = false;
+            continue;
+        }
         G = std::min(I, G * 2);
     }
+    P->grad_ok.push_back(grad_fit);
     d.grp_begin = (int)P->groups.size();
     d.n_grp = (int)gr.size();
     d.window = window;
@@ -563,6 +623,37 @@ size_t carve_fwd(const DScene& d, char* base, FwdWs* w)
 }
 
 size_t fwd_ws_bytes(const msim_plan*, const DScene& d) { return carve_fwd(d, nullptr, nullptr); }
+
+// Adjoint scratch of one scene, after the forward's (whose tracks it reuses).
+size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, AdjBufs* aw, double** partial)
+{
+    size_t off = carve_fwd(d, base, fw);
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
+    const size_t gpts = ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics;
+    const size_t waves = (size_t)P->threads / 64;
+    char* xp = take((size_t)d.n_mics * d.n_grp * d.n_tiles * d.window * sizeof(float));
+    char* db = take((size_t)d.n_mics * d.n_img * d.n_out * sizeof(float));
+    char* gp = take((size_t)d.n_mics * d.n_tiles * waves * d.n_img * sizeof(float));
+    char* ds = take(segs * sizeof(float4));
+    char* pc = take(gpts * sizeof(double4));
+    char* pa = take(gpts * sizeof(int32_t));
+    char* pr = take(reduce_partial_bytes(d));
+    if (aw) {
+        aw->xpart = (float*)xp;
+        aw->dbar = (float*)db;
+        aw->gpart = (float*)gp;
+        aw->dseg = (float4*)ds;
+        aw->pgc = (double4*)pc;
+        aw->pga = (int32_t*)pa;
+    }
+    if (partial) *partial = (double*)pr;
+    return off;
+}
 
 }  // namespace
 
@@ -642,8 +733,13 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
     }
-    std::vector<float4> tab4(P->table.size() / 4);
+    std::vector<float4> tab4(P->table.size() / 4), dtab4(P->dtable.size() / 4);
     std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
+    std::memcpy(dtab4.data(), P->dtable.data(), P->dtable.size() * sizeof(float));
+    if ((st = upload(&P->d_dtable, dtab4)) != MSIM_OK) {
+        msim_plan_destroy(P);
+        return st;
+    }
     std::vector<int32_t> zero(1, 0);
     if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_groups, P->groups)) != MSIM_OK || (st = upload(&P->d_knots, P->knots)) != MSIM_OK ||
@@ -670,6 +766,7 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_knots);
     (void)hipFree(P->d_mics);
     (void)hipFree(P->d_table);
+    (void)hipFree(P->d_dtable);
     (void)hipFree(P->d_status);
     delete P;
     return MSIM_OK;
@@ -699,10 +796,76 @@ msim_status msim_plan_stats(const msim_plan* P, int64_t* n_images, double* forwa
 msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* bytes)
 {
     if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    if (with_grad) return fail(MSIM_E_UNSUPPORTED, "backward is not in this build");
     size_t m = 0;
-    for (const DScene& d : P->scenes) m = std::max(m, fwd_ws_bytes(P, d));
+    for (const DScene& d : P->scenes)
+        m = std::max(m, with_grad ? carve_adj(P, d, nullptr, nullptr, nullptr, nullptr) : fwd_ws_bytes(P, d));
     *bytes = m;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_grad_layout(const msim_plan* P, int64_t* src_off, int64_t* src_total)
+{
+    if (!P) return fail(MSIM_E_INVALID_ARG, "plan is NULL");
+    for (int s = 0; s < P->n_scenes; ++s)
+        if (src_off) src_off[s] = P->scenes[s].src_grad_off;
+    if (src_total) *src_total = P->src_grad_total;
+    return MSIM_OK;
+}
+
+msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* gx, double* gbeta, double* gsrc,
+                          void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!P || !x || !gy) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    msim_workspace_size(P, 1, &need);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
+        return fail(MSIM_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned", need);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    for (int s = 0; s < P->n_scenes; ++s) {
+        if (!P->grad_ok[s]) return fail(MSIM_E_UNSUPPORTED, "scene %d: adjoint LDS does not fit its delay groups", s);
+        if (gsrc && P->scenes[s].src_knots > max_grad_knots())
+            return fail(MSIM_E_UNSUPPORTED, "scene %d: more than %d source knots", s, max_grad_knots());
+    }
+    const int T = P->par.taps, L = P->par.table_phases;
+    const float ghat = (float)(P->par.fs / (4.0 * kPi * P->par.c));
+    for (int s = 0; s < P->n_scenes; ++s) {
+        const DScene& d = P->scenes[s];
+        FwdWs fw;
+        AdjBufs aw;
+        double* partial = nullptr;
+        carve_adj(P, d, (char*)ws, &fw, &aw, &partial);
+        {
+            LaunchTimer t(P, kKindTracks, stream);
+            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, fw.seg, fw.segK,
+                                 P->par.c, P->par.fs, P->par.delay_model, stream));
+        }
+        if (gx) {
+            {
+                LaunchTimer t(P, kKindAdjoint, stream);
+                HIP_OK(launch_adj_x(T, P->threads, d, P->d_images, P->d_groups, P->d_table, L, fw.seg, fw.segK, gy,
+                                    aw.xpart, P->d_status, stream));
+            }
+            LaunchTimer t(P, kKindReduce, stream);
+            HIP_OK(launch_reduce_x(d, P->d_groups, P->threads, T, aw.xpart, gx, stream));
+        }
+        const bool want_src = gsrc && d.src_knots > 0;
+        if (gbeta || want_src) {
+            {
+                LaunchTimer t(P, kKindAdjoint, stream);
+                HIP_OK(launch_adj_track(T, P->threads, d, P->d_images, P->d_groups, P->d_table, P->d_dtable, L,
+                                        fw.seg, fw.segK, x, gy, ghat, aw.dbar, aw.gpart, P->d_status, stream));
+            }
+            LaunchTimer t(P, kKindParams, stream);
+            if (want_src)
+                HIP_OK(launch_adj_params(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, aw.dbar,
+                                         aw.dseg, aw.pgc, aw.pga, P->par.c, P->par.fs, P->par.delay_model, 1,
+                                         stream));
+            HIP_OK(launch_reduce_params(P->d_scenes, s, d, P->d_images, aw.gpart, d.n_tiles * (P->threads / 64),
+                                        aw.pgc, aw.pga, partial, gbeta, want_src ? gsrc : nullptr, stream));
+        }
+    }
     return MSIM_OK;
 }
 

@@ -38,6 +38,9 @@ struct DScene {
     int64_t seg_per_mic;  // track segments of one mic (sum over images)
     int32_t n_tiles;
     int32_t window;       // LDS source window (positions) the plan sized for this scene
+    double beta[6];       // wall coefficients (for d/dbeta)
+    int32_t src_grad_off; // this scene's first knot in the packed d/dsource array
+    int32_t src_knots;    // source knots with a gradient (PWL sources; 0 for circles)
 };
 
 // One image source.  Position of image m of point q, per axis a:
@@ -50,6 +53,8 @@ struct DImage {
     float gfac;           // beta_i * fs / (4 pi c): gain = gfac / D
     int32_t seg_off;      // first track segment within one mic's track
     int32_t n_seg;        // ceil(n_out / R)
+    int8_t hits[6];       // reflections on each wall (beta_i = prod beta_w^hits_w)
+    int8_t pad[2];
 };
 
 // Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
@@ -82,5 +87,38 @@ hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DIma
 hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st);
 
 size_t synth_lds_bytes(int taps, int L, int window);
+
+// ---- adjoint launchers (msim_adjoint.hip) ----
+// Scratch of the adjoint of one scene (all carved from the caller's workspace).
+struct AdjBufs {
+    float* xpart;     // [mic][group][tile][window]: transpose-delay partial windows
+    float* dbar;      // [mic][image][n_out]: d loss / d D_i(n)
+    float* gpart;     // [mic][tile * waves][image]: partial sums of d loss / d beta_i
+    float4* dseg;     // [mic][segment]: Catmull-Rom transpose weights summed per segment
+    double4* pgc;     // [mic][grid point]: d loss / d source position at emission time, and lambda
+    int32_t* pga;     // [mic][grid point]: knot index of that emission time
+};
+
+size_t adj_x_lds_bytes(int taps, int L, int window);
+size_t adj_track_lds_bytes(int taps, int L, int window);
+
+hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                        const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                        float* xpart, int32_t* d_status, hipStream_t st);
+hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
+                           float* gx, hipStream_t st);
+hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                            const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
+                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
+                            float* gpart, int32_t* d_status, hipStream_t st);
+hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                             const double* d_knots, const double* d_mics, const double* grid, const float* dbar,
+                             float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,
+                             int want_src, hipStream_t st);
+hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
+                                const float* gpart, int gpart_stride, const double4* pgc, const int32_t* pga,
+                                double* partial, double* gbeta, double* gsrc, hipStream_t st);
+size_t reduce_partial_bytes(const DScene& hs);
+int max_grad_knots();
 
 }  // namespace msim

@@ -115,6 +115,10 @@ class Plan:
         self.n_in = [int(sc.n_in) for sc in scenes]
         self.n_out = [int(sc.n_out) for sc in scenes]
         self.n_mics = [int(np.asarray(sc.mic_offset).shape[0]) for sc in scenes]
+        so, st = (C.c_int64 * n)(), C.c_int64()
+        check(L.msim_plan_grad_layout(self._ptr, so, C.byref(st)))
+        self.src_off = np.array(list(so), np.int64)
+        self.src_total = st.value
         self._ws = {}
 
     # -------------------------------------------------------------- memory
@@ -150,6 +154,25 @@ class Plan:
         check(_lib.load().msim_forward(self._ptr, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return y
+
+    def backward(self, x: torch.Tensor, gy: torch.Tensor, want_x: bool = True, want_beta: bool = True,
+                 want_src: bool = True, stream=None):
+        """(dL/dx [x_total] f32, dL/dbeta [n_scenes, 6] f64, dL/dknots [src_total, 3] f64) for
+        gy = dL/dy; entries not requested are None."""
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
+        assert gy.is_cuda and gy.dtype == torch.float32 and gy.is_contiguous() and gy.numel() == self.y_total
+        dev = x.device
+        gx = torch.empty(self.x_total, dtype=torch.float32, device=dev) if want_x else None
+        gb = torch.empty((self.n_scenes, 6), dtype=torch.float64, device=dev) if want_beta else None
+        gs = (torch.zeros((max(self.src_total, 1), 3), dtype=torch.float64, device=dev)
+              if want_src else None)
+        ws = self.workspace(True, dev)
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        check(_lib.load().msim_backward(self._ptr, ptr(x), ptr(gy), ptr(gx), ptr(gb), ptr(gs),
+                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        if gs is not None:
+            gs = gs[: self.src_total]
+        return gx, gb, gs
 
     def device_status(self, stream=None) -> int:
         f = C.c_int32()
