@@ -136,6 +136,41 @@ msim_status msim_workspace_size(const msim_plan* plan, int32_t with_grad, size_t
  * x: device [x_total] FP32; y: device [y_total] FP32, fully overwritten. */
 msim_status msim_forward(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Batched forward: the same result as msim_forward (bit for bit: both sum every
+ * delay group in the same order), computed by three launches over all scenes
+ * at once: the delay tracks of every scene, one persistent synthesis kernel
+ * whose fixed grid of workgroups loads the fractional-delay table once and then
+ * takes (scene, mic, tile, delay group) work items in decreasing-cost order from
+ * a ticket counter, and the group reduction.  With use_graph != 0 the three
+ * launches are captured once into a HIP graph (per x, y, ws triple) and replayed
+ * on `stream`; use_graph = 0 launches them directly.  ws holds
+ * msim_batched_workspace_size() bytes (all scenes' tracks at once). */
+msim_status msim_batched_workspace_size(const msim_plan* plan, size_t* bytes);
+msim_status msim_forward_batched(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes,
+                                 hipStream_t stream, int32_t use_graph);
+
+/* Launch shape: output samples per workgroup (512 or 1024), images per delay
+ * group (0: chosen from the tile count), and the persistent grid size it implies. */
+typedef struct {
+    int32_t threads;
+    int32_t group_cap;
+    int32_t workgroups;   /* output only */
+    double ms;            /* output only: the batched forward time that chose it */
+} msim_tuning;
+
+msim_status msim_get_tuning(const msim_plan* plan, msim_tuning* t);
+/* Regroups the plan for a launch shape; workspace sizes change with it. */
+msim_status msim_set_tuning(msim_plan* plan, const msim_tuning* t);
+/* Largest batched workspace over the shapes msim_autotune tries. */
+msim_status msim_autotune_workspace_size(msim_plan* plan, size_t* bytes);
+/* Times the batched forward (direct launches, 3 runs after 1 warm-up) for each
+ * launch shape that fits ws and keeps the fastest; the choice is read from and
+ * appended to the JSON-lines file cache_path (may be NULL), keyed by table
+ * shape, scene count, image count and output size.  Synchronises `stream`;
+ * x and y are scratch for the timing runs (y is overwritten). */
+msim_status msim_autotune(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes,
+                          hipStream_t stream, const char* cache_path, msim_tuning* best);
+
 /* Reverse mode of msim_forward for a scalar loss L, given gy = dL/dy (device,
  * [y_total] FP32).  Recomputes the delay tracks (nothing is kept from the
  * forward) and writes, each only when its pointer is non-NULL (device memory):
@@ -167,6 +202,8 @@ msim_status msim_device_status(msim_plan* plan, hipStream_t stream, int32_t* fla
 typedef struct {
     double tracks_ms, synth_ms, reduce_ms, adjoint_ms, params_ms;
     int32_t tracks_launches, synth_launches, reduce_launches, adjoint_launches, params_launches;
+    double graph_ms;           /* replays of the batched forward's graph */
+    int32_t graph_launches;
 } msim_profile;
 
 msim_status msim_profile_begin(msim_plan* plan);

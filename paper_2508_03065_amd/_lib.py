@@ -44,7 +44,12 @@ class Profile(C.Structure):
     _fields_ = [("tracks_ms", C.c_double), ("synth_ms", C.c_double), ("reduce_ms", C.c_double),
                 ("adjoint_ms", C.c_double), ("params_ms", C.c_double),
                 ("tracks_launches", C.c_int32), ("synth_launches", C.c_int32), ("reduce_launches", C.c_int32),
-                ("adjoint_launches", C.c_int32), ("params_launches", C.c_int32)]
+                ("adjoint_launches", C.c_int32), ("params_launches", C.c_int32),
+                ("graph_ms", C.c_double), ("graph_launches", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("group_cap", C.c_int32), ("workgroups", C.c_int32), ("ms", C.c_double)]
 
 
 # name -> (argtypes); every function returns msim_status (int) except msim_last_error
@@ -64,6 +69,13 @@ SIGNATURES = {
     "msim_backward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                       C.c_size_t, C.c_void_p],
     "msim_plan_grad_layout": [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "msim_batched_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
+    "msim_forward_batched": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32],
+    "msim_get_tuning": [_PLAN, C.POINTER(Tuning)],
+    "msim_set_tuning": [_PLAN, C.POINTER(Tuning)],
+    "msim_autotune_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
+    "msim_autotune": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_char_p,
+                      C.POINTER(Tuning)],
     "msim_profile_begin": [_PLAN],
     "msim_profile_end": [_PLAN, C.POINTER(Profile)],
 }

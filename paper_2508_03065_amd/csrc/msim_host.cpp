@@ -299,6 +299,24 @@ struct msim_plan {
     std::vector<int64_t> n_img;
     int64_t src_grad_total = 0;           // knots in the packed d/dsource array
     std::vector<bool> grad_ok;            // the adjoint's LDS fits this scene's windows
+    std::vector<std::vector<std::pair<double, double>>> bounds;   // per scene, per sorted image: delay bounds
+    int group_cap = 0;                    // images per delay group (0: chosen from the tile count)
+    // batched path
+    std::vector<DScene> scenes_b;         // with workspace bases set
+    std::vector<int64_t> grid_prefix, seg_prefix, y_prefix;
+    std::vector<WorkItem> items;
+    int64_t b_grid_total = 0, b_seg_total = 0, b_part_total = 0;
+    int b_window = 0, b_wgs = 0;
+    DScene* d_scenes_b = nullptr;
+    int64_t* d_grid_prefix = nullptr;
+    int64_t* d_seg_prefix = nullptr;
+    int64_t* d_y_prefix = nullptr;
+    WorkItem* d_items = nullptr;
+    // graph of the batched forward, valid for one (x, y, workspace) triple
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_valid = false;
+    const void* graph_key[3] = {nullptr, nullptr, nullptr};
     double fwd_taps = 0.0;
     int64_t x_total = 0, y_total = 0;
     // device
@@ -323,7 +341,7 @@ struct msim_plan {
 
 namespace {
 
-enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKinds };
+enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKindGraph, kKinds };
 
 hipEvent_t pool_event(msim_plan* P)
 {
@@ -533,61 +551,159 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     P->src_grad_total += d.src_knots;
     if (seg > INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "scene %d: track too long", si);
     d.seg_per_mic = seg;
-    const int NT = P->threads, T = p.taps, L = p.table_phases;
-    d.n_tiles = (int)((s.n_out + NT - 1) / NT);
-    // Group windows are sized so the adjoint's LDS (value and derivative tables
-    // beside the source window) fits too; failing that, the forward's alone.
-    bool grad_fit = true;
-    auto fits = [&](int window) {
-        return (grad_fit ? adj_track_lds_bytes(T, L, window) : synth_lds_bytes(T, L, window)) <= kLdsLimit;
-    };
-    // Enough workgroups to fill the 256 CUs several times, in nearly whole rounds.
-    const int64_t base = (int64_t)d.n_tiles * s.n_mics;
-    int G = 1;
-    double best = -1.0;
-    for (int g = 1; g <= std::min(I, 128); ++g) {
-        const int64_t wgs = base * g;
-        const double rounds = std::ceil(wgs / 256.0);
-        const double eff = wgs / (rounds * 256.0) - (wgs < 3 * 256 ? 1.0 : 0.0);
-        if (eff > best + 1e-9) {
-            best = eff;
-            G = g;
-        }
-        if (wgs >= 16 * 256) break;
-    }
-    std::vector<DGroup> gr;
-    int window = 0;
-    for (;;) {
-        gr.clear();
-        window = 0;
-        for (int g = 0; g < G; ++g) {
-            const int b = (int)((int64_t)I * g / G), e = (int)((int64_t)I * (g + 1) / G);
-            if (b == e) continue;
-            double lo = 1e300, hi = -1e300;
-            for (int i = b; i < e; ++i) {
-                lo = std::min(lo, imgs[i].dlo);
-                hi = std::max(hi, imgs[i].dhi);
-            }
-            DGroup dg{b, e, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4};
-            gr.push_back(dg);
-            window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
-        }
-        if (fits(window)) break;
-        if (G >= I) {
-            if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", si);
-            grad_fit = false;
-            continue;
-        }
-        G = std::min(I, G * 2);
-    }
-    P->grad_ok.push_back(grad_fit);
-    d.grp_begin = (int)P->groups.size();
-    d.n_grp = (int)gr.size();
-    d.window = window;
-    P->groups.insert(P->groups.end(), gr.begin(), gr.end());
     P->scenes.push_back(d);
     P->n_img.push_back(I);
-    P->fwd_taps += (double)s.n_mics * I * double(s.n_in + T - 1) * T;
+    std::vector<std::pair<double, double>> bnd((size_t)I);
+    for (int i = 0; i < I; ++i) bnd[i] = {imgs[i].dlo, imgs[i].dhi};
+    P->bounds.push_back(std::move(bnd));
+    P->fwd_taps += (double)s.n_mics * I * double(s.n_in + p.taps - 1) * p.taps;
+    return MSIM_OK;
+}
+
+// Splits every scene's delay-sorted images into groups for the current tile
+// size (threads) and group cap, sizes the LDS windows, and lays out the batched
+// path: workspace bases, prefix arrays and the cost-ordered work list.
+msim_status regroup(msim_plan* P)
+{
+    const int NT = P->threads, T = P->par.taps, L = P->par.table_phases;
+    P->groups.clear();
+    P->grad_ok.clear();
+    for (int s = 0; s < P->n_scenes; ++s) {
+        DScene& d = P->scenes[s];
+        const auto& bnd = P->bounds[s];
+        const int I = d.n_img;
+        d.n_tiles = (int)((d.n_out + NT - 1) / NT);
+        // Group windows are sized so the adjoint's LDS (value and derivative tables
+        // beside the source window) fits too; failing that, the forward's alone.
+        bool grad_fit = true;
+        auto fits = [&](int window) {
+            return (grad_fit ? adj_track_lds_bytes(T, L, window) : synth_lds_bytes(T, L, window)) <= kLdsLimit;
+        };
+        int G = 1;
+        if (P->group_cap > 0) {
+            G = std::max(1, (I + P->group_cap - 1) / P->group_cap);
+        } else {
+            // enough workgroups to fill the 256 CUs several times, in nearly whole rounds
+            const int64_t base = (int64_t)d.n_tiles * d.n_mics;
+            double best = -1.0;
+            for (int g = 1; g <= std::min(I, 128); ++g) {
+                const int64_t wgs = base * g;
+                const double rounds = std::ceil(wgs / 256.0);
+                const double eff = wgs / (rounds * 256.0) - (wgs < 3 * 256 ? 1.0 : 0.0);
+                if (eff > best + 1e-9) {
+                    best = eff;
+                    G = g;
+                }
+                if (wgs >= 16 * 256) break;
+            }
+        }
+        std::vector<DGroup> gr;
+        int window = 0;
+        for (;;) {
+            gr.clear();
+            window = 0;
+            for (int g = 0; g < G; ++g) {
+                const int b = (int)((int64_t)I * g / G), e = (int)((int64_t)I * (g + 1) / G);
+                if (b == e) continue;
+                double lo = 1e300, hi = -1e300;
+                for (int i = b; i < e; ++i) {
+                    lo = std::min(lo, bnd[i].first);
+                    hi = std::max(hi, bnd[i].second);
+                }
+                DGroup dg{b, e, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4};
+                gr.push_back(dg);
+                window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
+            }
+            if (fits(window)) break;
+            if (G >= I) {
+                if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                grad_fit = false;
+                continue;
+            }
+            G = std::min(I, G * 2);
+        }
+        P->grad_ok.push_back(grad_fit);
+        d.grp_begin = (int)P->groups.size();
+        d.n_grp = (int)gr.size();
+        d.window = window;
+        P->groups.insert(P->groups.end(), gr.begin(), gr.end());
+    }
+    // batched layout
+    P->scenes_b = P->scenes;
+    P->grid_prefix.assign(P->n_scenes, 0);
+    P->seg_prefix.assign(P->n_scenes, 0);
+    P->y_prefix.assign(P->n_scenes, 0);
+    int64_t go = 0, so = 0, po = 0;
+    int wmax = 0;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        DScene& b = P->scenes_b[s];
+        b.grid_base = go;
+        b.trk_base = so;
+        b.part_base = po;
+        P->grid_prefix[s] = go;
+        P->seg_prefix[s] = so;
+        P->y_prefix[s] = b.y_off;
+        go += (b.seg_per_mic + 3 * (int64_t)b.n_img) * b.n_mics;
+        so += b.seg_per_mic * b.n_mics;
+        po += (int64_t)b.n_mics * b.n_grp * b.n_out;
+        wmax = std::max(wmax, b.window);
+    }
+    P->b_grid_total = go;
+    P->b_seg_total = so;
+    P->b_part_total = po;
+    P->b_window = wmax;
+    std::vector<std::pair<double, WorkItem>> it;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        const DScene& d = P->scenes[s];
+        for (int g = 0; g < d.n_grp; ++g) {
+            const DGroup& G = P->groups[d.grp_begin + g];
+            const int W = NT + (G.dmax - G.dmin) + T + 8;
+            for (int m = 0; m < d.n_mics; ++m)
+                for (int t = 0; t < d.n_tiles; ++t) {
+                    const int64_t len = std::min<int64_t>(NT, d.n_out - (int64_t)t * NT);
+                    const double cost = (double)(G.img_end - G.img_begin) * len * T + 4.0 * W;
+                    it.push_back({cost, WorkItem{s, m, t, g}});
+                }
+        }
+    }
+    std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    P->items.resize(it.size());
+    for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
+    const size_t lds = synth_lds_bytes(T, L, wmax);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / NT, kLdsLimit / lds));
+    P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
+    P->graph_valid = false;
+    return MSIM_OK;
+}
+
+void free_layout(msim_plan* P)
+{
+    (void)hipFree(P->d_scenes);
+    (void)hipFree(P->d_groups);
+    (void)hipFree(P->d_scenes_b);
+    (void)hipFree(P->d_grid_prefix);
+    (void)hipFree(P->d_seg_prefix);
+    (void)hipFree(P->d_y_prefix);
+    (void)hipFree(P->d_items);
+    P->d_scenes = nullptr;
+    P->d_groups = nullptr;
+    P->d_scenes_b = nullptr;
+    P->d_grid_prefix = P->d_seg_prefix = P->d_y_prefix = nullptr;
+    P->d_items = nullptr;
+}
+
+// (Re)uploads everything regroup() decides: scene descriptors, groups, the
+// batched descriptors, prefix arrays and the work list.
+msim_status upload_layout(msim_plan* P)
+{
+    free_layout(P);
+    msim_status st;
+    if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_groups, P->groups)) != MSIM_OK ||
+        (st = upload(&P->d_scenes_b, P->scenes_b)) != MSIM_OK ||
+        (st = upload(&P->d_grid_prefix, P->grid_prefix)) != MSIM_OK ||
+        (st = upload(&P->d_seg_prefix, P->seg_prefix)) != MSIM_OK ||
+        (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK)
+        return st;
     return MSIM_OK;
 }
 
@@ -728,6 +844,10 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     }
     P->x_total = xo;
     P->y_total = yo;
+    if ((st = regroup(P)) != MSIM_OK) {
+        delete P;
+        return st;
+    }
     build_table(P);
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
@@ -736,15 +856,11 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     std::vector<float4> tab4(P->table.size() / 4), dtab4(P->dtable.size() / 4);
     std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
     std::memcpy(dtab4.data(), P->dtable.data(), P->dtable.size() * sizeof(float));
-    if ((st = upload(&P->d_dtable, dtab4)) != MSIM_OK) {
-        msim_plan_destroy(P);
-        return st;
-    }
     std::vector<int32_t> zero(1, 0);
-    if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
-        (st = upload(&P->d_groups, P->groups)) != MSIM_OK || (st = upload(&P->d_knots, P->knots)) != MSIM_OK ||
-        (st = upload(&P->d_mics, P->mics)) != MSIM_OK || (st = upload(&P->d_table, tab4)) != MSIM_OK ||
-        (st = upload(&P->d_status, zero)) != MSIM_OK) {
+    if ((st = upload(&P->d_dtable, dtab4)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
+        (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
+        (st = upload(&P->d_table, tab4)) != MSIM_OK || (st = upload(&P->d_status, zero)) != MSIM_OK ||
+        (st = upload_layout(P)) != MSIM_OK) {
         msim_plan_destroy(P);
         return st;
     }
@@ -760,9 +876,10 @@ msim_status msim_plan_destroy(msim_plan* P)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : P->pool) (void)hipEventDestroy(e);
-    (void)hipFree(P->d_scenes);
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    free_layout(P);
     (void)hipFree(P->d_images);
-    (void)hipFree(P->d_groups);
     (void)hipFree(P->d_knots);
     (void)hipFree(P->d_mics);
     (void)hipFree(P->d_table);
@@ -935,7 +1052,266 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
     out->reduce_launches = cnt[kKindReduce];
     out->adjoint_launches = cnt[kKindAdjoint];
     out->params_launches = cnt[kKindParams];
+    out->graph_ms = ms[kKindGraph];
+    out->graph_launches = cnt[kKindGraph];
     return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BatchWs {
+    double* grid;
+    Seg* seg;
+    int32_t* segK;
+    float* part;
+    int32_t* ticket;
+};
+
+size_t carve_batched(const msim_plan* P, char* base, BatchWs* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    char* g = take((size_t)P->b_grid_total * sizeof(double));
+    char* s = take((size_t)P->b_seg_total * sizeof(Seg));
+    char* k = take((size_t)P->b_seg_total * sizeof(int32_t));
+    char* p = take((size_t)P->b_part_total * sizeof(float));
+    char* t = take(sizeof(int32_t));
+    if (w) {
+        w->grid = (double*)g;
+        w->seg = (Seg*)s;
+        w->segK = (int32_t*)k;
+        w->part = (float*)p;
+        w->ticket = (int32_t*)t;
+    }
+    return off;
+}
+
+msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchWs& w, hipStream_t st)
+{
+    {
+        LaunchTimer t(P, kKindTracks, st);
+        HIP_OK(launch_tracks_all(P->d_scenes_b, P->n_scenes, P->d_grid_prefix, P->b_grid_total, P->d_seg_prefix,
+                                 P->b_seg_total, P->d_images, P->d_knots, P->d_mics, w.grid, w.seg, w.segK,
+                                 P->par.c, P->par.fs, P->par.delay_model, st));
+    }
+    {
+        LaunchTimer t(P, kKindSynth, st);
+        HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b, P->d_images,
+                                       P->d_groups, P->d_table, P->par.table_phases, P->d_items,
+                                       (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status, st));
+    }
+    LaunchTimer t(P, kKindReduce, st);
+    HIP_OK(launch_reduce_all(P->d_scenes_b, P->n_scenes, P->d_y_prefix, P->y_total, w.part, y, st));
+    return MSIM_OK;
+}
+
+msim_status check_batched_call(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes)
+{
+    if (!P || !x || !y) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    const size_t need = carve_batched(P, nullptr, nullptr);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
+        return fail(MSIM_E_WORKSPACE, "batched workspace needs %zu bytes, 256-byte aligned", need);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    return MSIM_OK;
+}
+
+const int kTuneThreads[] = {512, 1024};
+const int kTuneCaps[] = {0, 32, 64, 128, 256, 512};
+
+std::string tune_key(const msim_plan* P)
+{
+    int64_t imgs = 0;
+    for (int64_t v : P->n_img) imgs += v;
+    char buf[256];
+    snprintf(buf, sizeof buf, "gfx950/T%d/L%d/S%d/I%lld/Y%lld", P->par.taps, P->par.table_phases, P->n_scenes,
+             (long long)imgs, (long long)P->y_total);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* threads, int* cap)
+{
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[256];
+        int t = 0, c = 0;
+        // {"key": "...", "threads": N, "group_cap": N, ...}
+        if (sscanf(line, " {\"key\": \"%255[^\"]\", \"threads\": %d, \"group_cap\": %d", k, &t, &c) == 3 &&
+            key == k && (t == 512 || t == 1024) && c >= 0) {
+            *threads = t;
+            *cap = c;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+msim_status msim_batched_workspace_size(const msim_plan* P, size_t* bytes)
+{
+    if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    *bytes = carve_batched(P, nullptr, nullptr);
+    return MSIM_OK;
+}
+
+msim_status msim_forward_batched(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes,
+                                 hipStream_t stream, int32_t use_graph)
+{
+    msim_status st = check_batched_call(P, x, y, ws, ws_bytes);
+    if (st != MSIM_OK) return st;
+    BatchWs w;
+    carve_batched(P, (char*)ws, &w);
+    if (!use_graph) return enqueue_batched(P, x, y, w, stream);
+    const void* key[3] = {x, y, ws};
+    if (!P->graph_valid || std::memcmp(key, P->graph_key, sizeof key) != 0) {
+        if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        if (P->graph_exec) {
+            HIP_OK(hipGraphExecDestroy(P->graph_exec));
+            P->graph_exec = nullptr;
+        }
+        P->graph_valid = false;
+        const bool prof = P->profiling;
+        P->profiling = false;
+        HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+        st = enqueue_batched(P, x, y, w, P->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+        P->profiling = prof;
+        if (st != MSIM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(MSIM_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&P->graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(MSIM_E_HIP, "graph instantiate: %s", hipGetErrorString(e2));
+        std::memcpy(P->graph_key, key, sizeof key);
+        P->graph_valid = true;
+    }
+    LaunchTimer t(P, kKindGraph, stream);
+    HIP_OK(hipGraphLaunch(P->graph_exec, stream));
+    return MSIM_OK;
+}
+
+msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
+{
+    if (!P || !out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    out->threads = P->threads;
+    out->group_cap = P->group_cap;
+    out->workgroups = P->b_wgs;
+    out->ms = 0.0;
+    return MSIM_OK;
+}
+
+msim_status msim_set_tuning(msim_plan* P, const msim_tuning* t)
+{
+    if (!P || !t) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    if (t->threads != 512 && t->threads != 1024) return fail(MSIM_E_INVALID_ARG, "threads must be 512 or 1024");
+    if (t->group_cap < 0) return fail(MSIM_E_INVALID_ARG, "group_cap must be >= 0");
+    const int ot = P->threads, oc = P->group_cap;
+    P->threads = t->threads;
+    P->group_cap = t->group_cap;
+    msim_status st = regroup(P);
+    if (st != MSIM_OK) {
+        P->threads = ot;
+        P->group_cap = oc;
+        regroup(P);
+        return st;
+    }
+    return upload_layout(P);
+}
+
+msim_status msim_autotune_workspace_size(msim_plan* P, size_t* bytes)
+{
+    if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    const int ot = P->threads, oc = P->group_cap;
+    size_t m = 0;
+    for (int t : kTuneThreads)
+        for (int c : kTuneCaps) {
+            P->threads = t;
+            P->group_cap = c;
+            if (regroup(P) == MSIM_OK) m = std::max(m, carve_batched(P, nullptr, nullptr));
+        }
+    P->threads = ot;
+    P->group_cap = oc;
+    msim_status st = regroup(P);
+    if (st != MSIM_OK) return st;
+    *bytes = m;
+    return MSIM_OK;
+}
+
+msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream,
+                          const char* cache_path, msim_tuning* best_out)
+{
+    if (!P || !x || !y || !ws) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    const std::string key = tune_key(P);
+    int bt = 0, bc = 0;
+    double best = 1e300;
+    if (!cache_lookup(cache_path, key, &bt, &bc)) {
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        const bool prof = P->profiling;
+        P->profiling = false;
+        for (int t : kTuneThreads)
+            for (int c : kTuneCaps) {
+                P->threads = t;
+                P->group_cap = c;
+                if (regroup(P) != MSIM_OK || carve_batched(P, nullptr, nullptr) > ws_bytes) continue;
+                msim_status st = upload_layout(P);
+                if (st != MSIM_OK) return st;
+                BatchWs w;
+                carve_batched(P, (char*)ws, &w);
+                if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
+                HIP_OK(hipEventRecord(e0, stream));
+                for (int r = 0; r < 3; ++r)
+                    if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
+                HIP_OK(hipEventRecord(e1, stream));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / 3.0 < best) {
+                    best = ms / 3.0;
+                    bt = t;
+                    bc = c;
+                }
+            }
+        P->profiling = prof;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (bt == 0) return fail(MSIM_E_WORKSPACE, "no tuning candidate fits the workspace");
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"group_cap\": %d, \"ms\": %.4f}\n", key.c_str(), bt,
+                        bc, best);
+                fclose(f);
+            }
+        }
+    }
+    msim_tuning t{bt, bc, 0, best < 1e299 ? best : 0.0};
+    msim_status st = msim_set_tuning(P, &t);
+    if (st != MSIM_OK) return st;
+    if (best_out) {
+        msim_get_tuning(P, best_out);
+        best_out->ms = t.ms;
+    }
+    return MSIM_OK;
 }
 
 msim_status msim_device_status(msim_plan* P, hipStream_t stream, int32_t* flags)

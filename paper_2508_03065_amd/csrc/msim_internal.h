@@ -41,6 +41,17 @@ struct DScene {
     double beta[6];       // wall coefficients (for d/dbeta)
     int32_t src_grad_off; // this scene's first knot in the packed d/dsource array
     int32_t src_knots;    // source knots with a gradient (PWL sources; 0 for circles)
+    int64_t grid_base;    // offsets of this scene's delay grid, track segments and partial
+    int64_t trk_base;     //   outputs in the workspace (0 when scenes run one at a time)
+    int64_t part_base;
+};
+
+// One unit of the batched forward: an output tile of one delay group of one mic.
+struct WorkItem {
+    int32_t scene;
+    int32_t mic;
+    int32_t tile;
+    int32_t group;
 };
 
 // One image source.  Position of image m of point q, per axis a:
@@ -85,6 +96,18 @@ hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DIma
                             const float* x, float* part, int32_t* d_status, hipStream_t st);
 
 hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st);
+
+hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_grid_prefix, int64_t grid_total,
+                             const int64_t* d_seg_prefix, int64_t seg_total, const DImage* d_imgs,
+                             const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
+                             double c, double fs, int delay_model, hipStream_t st);
+hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window, const DScene* d_scenes,
+                                   const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
+                                   const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
+                                   const int32_t* segK, const float* x, float* part, int32_t* d_status,
+                                   hipStream_t st);
+hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
+                             const float* part, float* y, hipStream_t st);
 
 size_t synth_lds_bytes(int taps, int L, int window);
 

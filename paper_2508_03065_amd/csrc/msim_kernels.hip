@@ -19,44 +19,37 @@ namespace msim {
 // ------------------------------------------------------------------- tracks
 
 // Pass 1: exact delay of every image at every grid point kR, k = -1 .. n_seg+1,
-// one thread per (mic, image, grid point).  Grid of image ii starts at
-// seg_off + 3 ii within the mic's grid.
-__global__ __launch_bounds__(256) void k_grid(const DScene* __restrict__ scenes, int scene,
-                                              const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                              const double* __restrict__ mics, double* __restrict__ grid,
-                                              double c, double fs, int model)
+// one thread per (mic, image, grid point) of a scene.  Grid of image ii starts
+// at seg_off + 3 ii within the mic's grid.
+__device__ inline void grid_point(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
+                                  const double* __restrict__ knots, const double* __restrict__ mics,
+                                  double* __restrict__ grid, double c, double fs, int model)
 {
-    const DScene& S = scenes[scene];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per_mic = S.seg_per_mic + 3 * (int64_t)S.n_img;
-    if (gid >= per_mic * S.n_mics) return;
     const int mic = (int)(gid / per_mic);
     const int64_t idx = gid - (int64_t)mic * per_mic;
     const DImage* I = imgs + S.img_begin;
     const int ii = owner(I, S.n_img, idx, 3);
     const DImage im = I[ii];
     const int64_t k = idx - ((int64_t)im.seg_off + 3 * (int64_t)ii) - 1;
-    grid[gid] = fs * solve_tau(S, im.m, knots, mics, mic, (double)(k * im.R) / fs, 1.0 / c, model);
+    grid[S.grid_base + gid] = fs * solve_tau(S, im.m, knots, mics, mic, (double)(k * im.R) / fs, 1.0 / c, model);
 }
 
 // Pass 2: one thread per (mic, segment): segment k of image i covers outputs
 // [kR, (k+1)R); its cubic is the uniform Catmull-Rom through the delays at
 // (k-1)R .. (k+2)R, stored as an integer base and FP32 offsets.
-__global__ __launch_bounds__(256) void k_segs(const DScene* __restrict__ scenes, int scene,
-                                              const DImage* __restrict__ imgs, const double* __restrict__ grid,
-                                              Seg* __restrict__ seg, int32_t* __restrict__ segK)
+__device__ inline void segment(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
+                               const double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK)
 {
-    const DScene& S = scenes[scene];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per_mic = S.seg_per_mic;
-    if (gid >= per_mic * S.n_mics) return;
     const int mic = (int)(gid / per_mic);
     const int64_t sidx = gid - (int64_t)mic * per_mic;
     const DImage* I = imgs + S.img_begin;
     const int ii = owner(I, S.n_img, sidx, 0);
     const DImage im = I[ii];
     const int64_t k = sidx - im.seg_off;
-    const double* D = grid + (int64_t)mic * (per_mic + 3 * (int64_t)S.n_img) + im.seg_off + 3 * (int64_t)ii + k;
+    const double* D = grid + S.grid_base + (int64_t)mic * (per_mic + 3 * (int64_t)S.n_img) + im.seg_off +
+                      3 * (int64_t)ii + k;
     const double d0 = D[0], d1 = D[1], d2 = D[2], d3 = D[3];
     const double Kd = floor(d1);
     Seg out;
@@ -72,8 +65,66 @@ __global__ __launch_bounds__(256) void k_segs(const DScene* __restrict__ scenes,
         out.b2 = (float)(a2 * iR * iR);
         out.b3 = (float)(a3 * iR * iR * iR);
     }
-    seg[gid] = out;
-    segK[gid] = (int32_t)Kd;
+    seg[S.trk_base + gid] = out;
+    segK[S.trk_base + gid] = (int32_t)Kd;
+}
+
+__device__ inline int64_t grid_count(const DScene& S) { return (S.seg_per_mic + 3 * (int64_t)S.n_img) * S.n_mics; }
+__device__ inline int64_t seg_count(const DScene& S) { return S.seg_per_mic * S.n_mics; }
+
+__global__ __launch_bounds__(256) void k_grid(const DScene* __restrict__ scenes, int scene,
+                                              const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                              const double* __restrict__ mics, double* __restrict__ grid,
+                                              double c, double fs, int model)
+{
+    const DScene& S = scenes[scene];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < grid_count(S)) grid_point(S, gid, imgs, knots, mics, grid, c, fs, model);
+}
+
+__global__ __launch_bounds__(256) void k_segs(const DScene* __restrict__ scenes, int scene,
+                                              const DImage* __restrict__ imgs, const double* __restrict__ grid,
+                                              Seg* __restrict__ seg, int32_t* __restrict__ segK)
+{
+    const DScene& S = scenes[scene];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < seg_count(S)) segment(S, gid, imgs, grid, seg, segK);
+}
+
+// Last scene whose prefix start is <= i (prefix[0] = 0, ascending).
+__device__ inline int scene_of(const int64_t* __restrict__ prefix, int n, int64_t i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched forms: one launch over every scene; prefix arrays give each scene's
+// first flattened index (grid points, segments).
+__global__ __launch_bounds__(256) void k_grid_all(const DScene* __restrict__ scenes, int n_scenes,
+                                                  const int64_t* __restrict__ prefix, int64_t total,
+                                                  const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                                  const double* __restrict__ mics, double* __restrict__ grid,
+                                                  double c, double fs, int model)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int s = scene_of(prefix, n_scenes, i);
+    grid_point(scenes[s], i - prefix[s], imgs, knots, mics, grid, c, fs, model);
+}
+
+__global__ __launch_bounds__(256) void k_segs_all(const DScene* __restrict__ scenes, int n_scenes,
+                                                  const int64_t* __restrict__ prefix, int64_t total,
+                                                  const DImage* __restrict__ imgs, const double* __restrict__ grid,
+                                                  Seg* __restrict__ seg, int32_t* __restrict__ segK)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int s = scene_of(prefix, n_scenes, i);
+    segment(scenes[s], i - prefix[s], imgs, grid, seg, segK);
 }
 
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
@@ -92,6 +143,20 @@ hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, co
     return hipGetLastError();
 }
 
+hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_grid_prefix, int64_t grid_total,
+                             const int64_t* d_seg_prefix, int64_t seg_total, const DImage* d_imgs,
+                             const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
+                             double c, double fs, int delay_model, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grid_all, dim3((unsigned)((grid_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
+                       d_grid_prefix, grid_total, d_imgs, d_knots, d_mics, grid, c, fs, delay_model);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_segs_all, dim3((unsigned)((seg_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
+                       d_seg_prefix, seg_total, d_imgs, grid, seg, segK);
+    return hipGetLastError();
+}
+
 // -------------------------------------------------------------- forward synth
 
 // LDS: the half table of h(v) = h(-v), v in [0, T/2], sampled at v = r/L and
@@ -102,30 +167,23 @@ size_t synth_lds_bytes(int taps, int L, int window)
     return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) + (size_t)window * sizeof(float4);
 }
 
+// One output tile of one delay group for one mic: stages the group's source
+// window in LDS (the table must already be there), then one output sample per
+// lane sums every image of the group; writes the group's partial outputs.
+// Ends with a barrier, so the caller may restage LDS right after.
 template <int T, int NT>
-__global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                   const DGroup* __restrict__ groups,
-                                                   const float4* __restrict__ table, int L,
-                                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                                   const float* __restrict__ x, float* __restrict__ part,
-                                                   int32_t* __restrict__ status)
+__device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int tile, int mic,
+                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int L,
+                                  const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                  const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
 {
-    extern __shared__ float4 lds[];
     constexpr int NG = T / 8;          // tap quads per side
     const int rows = L + 1;
-    float4* tab = lds;
-    float4* xw = lds + NG * rows;
-
-    const int tile = blockIdx.x;
-    const int g = blockIdx.y;
-    const int mic = blockIdx.z;
     const int tid = threadIdx.x;
-    const DGroup G = groups[S.grp_begin + g];
     const int64_t n0 = (int64_t)tile * NT;
     const int64_t ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
 
-    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
     const float* xs = x + S.x_off;
     const int64_t n_in = S.n_in;
     for (int p = tid; p < W; p += NT) {
@@ -140,82 +198,148 @@ __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __rest
     __syncthreads();
 
     const int64_t n = n0 + tid;
-    if (n >= S.n_out) return;
-    const int64_t trk = (int64_t)mic * S.seg_per_mic;
-    const DImage* I = imgs + S.img_begin;
-    const float fn = (float)n + 0.5f;
-    const float Lf = (float)L;
-    float acc = 0.0f;
-    int bad = 0;
+    if (n < S.n_out) {
+        const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic;
+        const DImage* I = imgs + S.img_begin;
+        const float fn = (float)n + 0.5f;
+        const float Lf = (float)L;
+        float acc = 0.0f;
+        int bad = 0;
 
-    // the next image's track segment is fetched while the current one is filtered
-    auto seg_index = [&](const DImage& im, int* kout) {
-        int k = (int)(fn * im.invR);
-        k = min(max(k, 0), im.n_seg - 1);
-        *kout = k;
-        return trk + im.seg_off + k;
-    };
-    DImage nim = I[G.img_begin];
-    int nk;
-    int64_t nsidx = seg_index(nim, &nk);
-    Seg nsg = seg[nsidx];
-    int nKs = segK[nsidx];
-    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = nim;
-        const int k = nk;
-        const Seg sg = nsg;
-        const int Ks = nKs;
-        if (ii + 1 < G.img_end) {
-            nim = I[ii + 1];
-            nsidx = seg_index(nim, &nk);
-            nsg = seg[nsidx];
-            nKs = segK[nsidx];
-        }
-        const float v = (float)(n - (int64_t)k * im.R);
-        const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
-        const float fl = floorf(d);
-        const int K = Ks + (int)fl;
-        // skip the image when no lane's taps reach a source sample
-        const int64_t xlo = n - K - T / 2, xhi = n - K + T / 2 - 1;
-        if (!__any(xhi >= 0 && xlo < n_in)) continue;
-        const float mu = d - fl;
-        const float gain = im.gfac * __builtin_amdgcn_rcpf((float)Ks + d);
-        const float q = mu * Lf;
-        const int kq = min((int)q, L - 1);
-        const float f = q - (float)kq;
-        int p0 = (int)(n - K - ws);
-        if (p0 < T / 2 || p0 > W - T / 2 + 3) {
-            bad = 1;
-            continue;
-        }
-        const float4* tn = tab + kq;
-        const float4* tp = tab + (L - 1 - kq);
-        const float4* xq = xw + p0;
-        float A = 0.0f, B = 0.0f;
+        // the next image's track segment is fetched while the current one is filtered
+        auto seg_index = [&](const DImage& im, int* kout) {
+            int k = (int)(fn * im.invR);
+            k = min(max(k, 0), im.n_seg - 1);
+            *kout = k;
+            return trk + im.seg_off + k;
+        };
+        DImage nim = I[G.img_begin];
+        int nk;
+        int64_t nsidx = seg_index(nim, &nk);
+        Seg nsg = seg[nsidx];
+        int nKs = segK[nsidx];
+        for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+            const DImage im = nim;
+            const int k = nk;
+            const Seg sg = nsg;
+            const int Ks = nKs;
+            if (ii + 1 < G.img_end) {
+                nim = I[ii + 1];
+                nsidx = seg_index(nim, &nk);
+                nsg = seg[nsidx];
+                nKs = segK[nsidx];
+            }
+            const float v = (float)(n - (int64_t)k * im.R);
+            const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
+            const float fl = floorf(d);
+            const int K = Ks + (int)fl;
+            // skip the image when no lane's taps reach a source sample
+            const int64_t xlo = n - K - T / 2, xhi = n - K + T / 2 - 1;
+            if (!__any(xhi >= 0 && xlo < n_in)) continue;
+            const float mu = d - fl;
+            const float gain = im.gfac * __builtin_amdgcn_rcpf((float)Ks + d);
+            const float q = mu * Lf;
+            const int kq = min((int)q, L - 1);
+            const float f = q - (float)kq;
+            int p0 = (int)(n - K - ws);
+            if (p0 < T / 2 || p0 > W - T / 2 + 3) {
+                bad = 1;
+                continue;
+            }
+            const float4* tn = tab + kq;
+            const float4* tp = tab + (L - 1 - kq);
+            const float4* xq = xw + p0;
+            float A = 0.0f, B = 0.0f;
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-            // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> rows kq (1-f), kq+1 (f)
-            const float4 xn = xq[4 * gi];
-            const float4 P = tn[gi * rows];
-            const float4 Q = tn[gi * rows + 1];
-            A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
-            A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
-            A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
-            A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
-            // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
-            //   -> rows L-1-kq (weight f), L-kq (weight 1-f)
-            const float4 xp = xq[-4 - 4 * gi];
-            const float4 P2 = tp[gi * rows];
-            const float4 Q2 = tp[gi * rows + 1];
-            B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
-            B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
-            B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
-            B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
+            for (int gi = 0; gi < NG; ++gi) {
+                // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> rows kq (1-f), kq+1 (f)
+                const float4 xn = xq[4 * gi];
+                const float4 P = tn[gi * rows];
+                const float4 Q = tn[gi * rows + 1];
+                A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
+                A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
+                A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
+                A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
+                // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
+                //   -> rows L-1-kq (weight f), L-kq (weight 1-f)
+                const float4 xp = xq[-4 - 4 * gi];
+                const float4 P2 = tp[gi * rows];
+                const float4 Q2 = tp[gi * rows + 1];
+                B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
+                B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
+                B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
+                B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
+            }
+            acc = fmaf(gain, fmaf(f, B - A, A), acc);
         }
-        acc = fmaf(gain, fmaf(f, B - A, A), acc);
+        if (bad) atomicOr(status, kStatusWindow);
+        part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
     }
-    if (bad) atomicOr(status, kStatusWindow);
-    part[((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
+    __syncthreads();
+}
+
+template <int T>
+__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int L)
+{
+    const int n = (T / 8) * (L + 1);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = table[i];
+}
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
+                                                   const DGroup* __restrict__ groups,
+                                                   const float4* __restrict__ table, int L,
+                                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                                   const float* __restrict__ x, float* __restrict__ part,
+                                                   int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    float4* tab = lds;
+    float4* xw = lds + (T / 8) * (L + 1);
+    load_table<T>(table, tab, L);
+    const int g = blockIdx.y;
+    synth_tile<T, NT>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x, part,
+                      status);
+}
+
+// Persistent form: a fixed grid of workgroups loads the table once, then takes
+// work items (scene, mic, tile, group), ordered by decreasing cost, from a
+// ticket counter until the list is exhausted.  Items write disjoint partial
+// outputs, so the result does not depend on which workgroup ran which item.
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restrict__ scenes,
+                                                          const DImage* __restrict__ imgs,
+                                                          const DGroup* __restrict__ groups,
+                                                          const float4* __restrict__ table, int L,
+                                                          const WorkItem* __restrict__ items, int n_items,
+                                                          int32_t* __restrict__ ticket,
+                                                          const Seg* __restrict__ seg,
+                                                          const int32_t* __restrict__ segK,
+                                                          const float* __restrict__ x, float* __restrict__ part,
+                                                          int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    __shared__ int s_item;
+    float4* tab = lds;
+    float4* xw = lds + (T / 8) * (L + 1);
+    load_table<T>(table, tab, L);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const DScene& S = scenes[w.scene];
+        synth_tile<T, NT>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg, segK, x,
+                          part, status);
+    }
+}
+
+__global__ void k_zero_i32(int32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 template <int T, int NT>
@@ -229,6 +353,22 @@ static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGr
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status);
+    return hipGetLastError();
+}
+
+template <int T, int NT>
+static hipError_t launch_persistent_t(int n_wg, int window, const DScene* d_scenes, const DImage* d_imgs,
+                                      const DGroup* d_groups, const float4* d_table, int L, const WorkItem* items,
+                                      int n_items, int32_t* ticket, const Seg* seg, const int32_t* segK,
+                                      const float* x, float* part, int32_t* d_status, hipStream_t st)
+{
+    const size_t lds = synth_lds_bytes(T, L, window);
+    auto kern = k_synth_persistent<T, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, ticket, 1);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, d_scenes, d_imgs, d_groups, d_table, L, items,
+                       n_items, ticket, seg, segK, x, part, d_status);
     return hipGetLastError();
 }
 
@@ -248,6 +388,28 @@ hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DIma
     MSIM_FWD_CASE(96, 1024)
     MSIM_FWD_CASE(128, 1024)
 #undef MSIM_FWD_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window, const DScene* d_scenes,
+                                   const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
+                                   const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
+                                   const int32_t* segK, const float* x, float* part, int32_t* d_status,
+                                   hipStream_t st)
+{
+#define MSIM_PERS_CASE(TT, NN)                                                                                 \
+    if (taps == TT && nthreads == NN)                                                                          \
+        return launch_persistent_t<TT, NN>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items,        \
+                                           n_items, ticket, seg, segK, x, part, d_status, st);
+    MSIM_PERS_CASE(32, 512)
+    MSIM_PERS_CASE(64, 512)
+    MSIM_PERS_CASE(96, 512)
+    MSIM_PERS_CASE(128, 512)
+    MSIM_PERS_CASE(32, 1024)
+    MSIM_PERS_CASE(64, 1024)
+    MSIM_PERS_CASE(96, 1024)
+    MSIM_PERS_CASE(128, 1024)
+#undef MSIM_PERS_CASE
     return hipErrorInvalidValue;
 }
 
@@ -271,6 +433,32 @@ hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, h
     const int64_t n = hs.n_out * hs.n_mics;
     hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hs.n_out, hs.n_grp,
                        hs.n_mics, part, y + hs.y_off);
+    return hipGetLastError();
+}
+
+// Batched: one thread per output sample of every scene (y packed scene-major).
+__global__ __launch_bounds__(256) void k_reduce_all(const DScene* __restrict__ scenes, int n_scenes,
+                                                    const int64_t* __restrict__ y_prefix, int64_t y_total,
+                                                    const float* __restrict__ part, float* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= y_total) return;
+    const int s = scene_of(y_prefix, n_scenes, i);
+    const DScene& S = scenes[s];
+    const int64_t j = i - y_prefix[s];
+    const int mic = (int)(j / S.n_out);
+    const int64_t n = j - (int64_t)mic * S.n_out;
+    const float* p = part + S.part_base + (int64_t)mic * S.n_grp * S.n_out + n;
+    float acc = 0.0f;
+    for (int g = 0; g < S.n_grp; ++g) acc += p[(int64_t)g * S.n_out];
+    y[i] = acc;
+}
+
+hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
+                             const float* part, float* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_all, dim3((unsigned)((y_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
+                       d_y_prefix, y_total, part, y);
     return hipGetLastError();
 }
 

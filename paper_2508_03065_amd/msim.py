@@ -155,6 +155,51 @@ class Plan:
                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return y
 
+    def batched_workspace(self, device=None) -> torch.Tensor:
+        b = C.c_size_t()
+        check(_lib.load().msim_batched_workspace_size(self._ptr, C.byref(b)))
+        ws = self._ws.get("batched")
+        if ws is None or ws.numel() < b.value:
+            ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=device or "cuda")
+            self._ws["batched"] = ws
+        return ws
+
+    def forward_batched(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, graph: bool = True,
+                        stream=None) -> torch.Tensor:
+        """All scenes in one persistent launch (captured in a HIP graph when graph=True)."""
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
+        if y is None:
+            y = torch.empty(self.y_total, dtype=torch.float32, device=x.device)
+        assert y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.numel() == self.y_total
+        ws = self.batched_workspace(x.device)
+        check(_lib.load().msim_forward_batched(self._ptr, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream),
+                                               int(graph)))
+        return y
+
+    def tuning(self) -> dict:
+        t = _lib.Tuning()
+        check(_lib.load().msim_get_tuning(self._ptr, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
+
+    def set_tuning(self, threads: int, group_cap: int = 0):
+        t = _lib.Tuning(threads, group_cap, 0, 0.0)
+        check(_lib.load().msim_set_tuning(self._ptr, C.byref(t)))
+
+    def autotune(self, x: torch.Tensor, cache_path: Optional[str] = None, stream=None) -> dict:
+        """Chooses the launch shape of the batched forward by timing it (see msim_autotune)."""
+        b = C.c_size_t()
+        check(_lib.load().msim_autotune_workspace_size(self._ptr, C.byref(b)))
+        ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=x.device)
+        y = torch.empty(self.y_total, dtype=torch.float32, device=x.device)
+        t = _lib.Tuning()
+        check(_lib.load().msim_autotune(self._ptr, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream),
+                                        cache_path.encode() if cache_path else None, C.byref(t)))
+        del ws
+        self._ws.clear()
+        return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
+
     def backward(self, x: torch.Tensor, gy: torch.Tensor, want_x: bool = True, want_beta: bool = True,
                  want_src: bool = True, stream=None):
         """(dL/dx [x_total] f32, dL/dbeta [n_scenes, 6] f64, dL/dknots [src_total, 3] f64) for

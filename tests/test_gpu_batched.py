@@ -1,0 +1,118 @@
+"""GPU tests of the batched forward: one persistent ticket-scheduled launch over
+every scene, replayed from a HIP graph, and the autotuner that picks its launch
+shape.  It must equal the plain per-scene path bit for bit and the FP64 oracle to
+relative L2 <= 1e-5."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_03065_amd import scenegen as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def mixed_scenes(n=9, taps=64):
+    out = []
+    par = None
+    for s in range(n):
+        sc, par = G.small_scene(seed=100 + s, max_order=2 + s % 5, seconds=0.03 + 0.02 * (s % 4), taps=taps,
+                                n_mics=1 + s % 3, circle=(s % 3 == 1), moving_rcv=(s % 4 == 3))
+        out.append(sc)
+    return out, par
+
+
+def test_batched_equals_plain_and_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes()
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    y_plain = plan.forward(x).clone()
+    y_direct = plan.forward_batched(x, graph=False).clone()
+    y_graph = plan.forward_batched(x, graph=True).clone()
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert torch.equal(y_plain, y_direct)
+    assert torch.equal(y_plain, y_graph)
+    for s, yv in enumerate(plan.unpack_y(y_graph)):
+        assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5
+
+
+def test_graph_replays_with_eager_work_between(torch_cuda):
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes(5, taps=32)
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    ref = plan.forward(x).clone()
+    y = torch.empty_like(ref)
+    for r in range(4):
+        y.fill_(float(r + 1))                       # eager work on the same buffers between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        plan.forward_batched(x, y, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), r
+        assert torch.isfinite(junk)
+
+
+def test_autotune_keeps_result(torch_cuda, tmp_path):
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes(7)
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    cache = str(tmp_path / "tune.jsonl")
+    best = plan.autotune(x, cache_path=cache)
+    assert best["threads"] in (512, 1024) and best["ms"] > 0
+    assert os.path.exists(cache)
+    again = Plan(scenes, par).autotune(x, cache_path=cache)     # read back from the cache
+    assert (again["threads"], again["group_cap"]) == (best["threads"], best["group_cap"])
+    y_b = plan.forward_batched(x).clone()
+    y_p = plan.forward(x).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(y_b, y_p)
+    for s, yv in enumerate(plan.unpack_y(y_b)):
+        assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5
+
+
+@pytest.mark.parametrize("threads,cap", [(512, 0), (1024, 64), (512, 256)])
+def test_launch_shapes(torch_cuda, threads, cap):
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes(4)
+    plan = Plan(scenes, par)
+    plan.set_tuning(threads, cap)
+    x = plan.pack_x([s.x for s in scenes])
+    y = plan.forward_batched(x)
+    for s, yv in enumerate(plan.unpack_y(y)):
+        assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5
+
+
+def test_config3_sampled(torch_cuda):
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = G.config3()
+    print("config3: 256 scenes, Sabine orders, lines and circles", flush=True)
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    y = plan.forward_batched(x)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    ys = plan.unpack_y(y)
+    rng = np.random.default_rng(5)
+    for s in (0, 1, 97, 255):
+        idx = np.sort(rng.choice(scenes[s].n_out, 60, replace=False))
+        assert rel(ys[s][:, idx].cpu().numpy(), O.forward(scenes[s], par, idx=idx)) <= 1e-5, s
