@@ -59,9 +59,12 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b)
 
 }  // namespace
 
-size_t adj_x_lds_bytes(int taps, int L, int window)
+// Each wave owns a window of (window - NT + 64) samples: its 64 outputs' taps
+// under every delay of the group.
+size_t adj_x_lds_bytes(int taps, int L, int window, int nthreads)
 {
-    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) + (size_t)window * sizeof(float);
+    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) +
+           (size_t)(nthreads / 64) * (size_t)(window - nthreads + 64) * sizeof(float);
 }
 
 size_t adj_track_lds_bytes(int taps, int L, int window)
@@ -73,6 +76,14 @@ size_t adj_track_lds_bytes(int taps, int L, int window)
 
 // ------------------------------------------------------------ transpose delay
 
+// Scatter of gy g h(j - mu) onto source positions n - K - j.  Every wave adds
+// into its own LDS window with plain read-add-write steps, one tap at a time
+// (the window is volatile, so the steps stay in order): within a step the 64
+// lanes touch 64 distinct positions unless two neighbouring outputs share
+// n - K (the integer delay stepped up between them); those lanes take a second
+// pass.  The wave windows are then summed in wave order: no atomics (LDS float
+// atomics measured several times slower here), and the result does not depend
+// on scheduling.
 template <int T, int NT>
 __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict__ imgs,
                                                const DGroup* __restrict__ groups, const float4* __restrict__ table,
@@ -82,19 +93,25 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
 {
     extern __shared__ float4 lds[];
     constexpr int NG = T / 8;
+    constexpr int WAVES = NT / 64;
     const int rows = L + 1;
     float4* tab = lds;
-    float* xb = (float*)(lds + NG * rows);
+    float* wbase = (float*)(lds + NG * rows);
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const DGroup G = groups[S.grp_begin + g];
     const int64_t n0 = (int64_t)tile * NT;
     const int64_t ws = n0 - G.dmax - T / 2 - 4;
-    const int W = NT + (G.dmax - G.dmin) + T + 8;
+    const int W = NT + (G.dmax - G.dmin) + T + 8;       // the tile's window
+    const int Wstride = S.window - NT + 64;             // per-wave window slot
+    const int Ww = W - NT + 64;                         // per-wave window used by this group
     for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
-    for (int p = tid; p < W; p += NT) xb[p] = 0.0f;
+    for (int p = tid; p < WAVES * Wstride; p += NT) wbase[p] = 0.0f;
     __syncthreads();
 
+    volatile float* xb = wbase + wave * Wstride;        // covers source positions ws + 64 wave + [0, Ww)
+    const int64_t wsw = ws + 64 * wave;
     const int64_t n = n0 + tid;
     const bool valid = n < S.n_out;
     const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
@@ -129,11 +146,18 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
         }
         const ImageSample smp = sample_of(im, k, sg, Ks, nc);
         const int64_t xlo = nc - smp.K - T / 2, xhi = nc - smp.K + T / 2 - 1;
-        const bool act = valid && wy != 0.0f && xhi >= 0 && xlo < n_in;
+        bool act = valid && wy != 0.0f && xhi >= 0 && xlo < n_in;
         if (!__any(act)) continue;
-        const int p0 = (int)(nc - smp.K - ws);
-        if (act && (p0 < T / 2 || p0 > W - T / 2)) bad = 1;
-        if (!act || p0 < T / 2 || p0 > W - T / 2) continue;
+        const int p0 = (int)(nc - smp.K - wsw);
+        if (act && (p0 < T / 2 || p0 > Ww - T / 2)) {
+            bad = 1;
+            act = false;
+        }
+        // neighbouring lanes with the same source position collide within a step
+        const int P = (int)(nc - smp.K);
+        const int prevP = __shfl_up(P, 1, 64);
+        const int prevA = __shfl_up((int)act, 1, 64);
+        const bool dup = act && lane > 0 && prevA && prevP == P;
         const float w = wy * im.gfac * __builtin_amdgcn_rcpf(smp.D);
         const float q = smp.mu * Lf;
         const int kq = min((int)q, L - 1);
@@ -141,27 +165,40 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
         const float a = w * (1.0f - f), b = w * f;
         const float4* tn = tab + kq;
         const float4* tp = tab + (L - 1 - kq);
-        float* xq = xb + p0;
+        volatile float* xq = xb + (act ? p0 : T / 2);
+        const bool any_dup = __any(dup);
+        for (int pass = 0; pass < (any_dup ? 2 : 1); ++pass) {
+            const bool on = act && (pass == 0 ? !dup : dup);
+            if (!on) continue;
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) {
-            const float4 P = tn[gi * rows];
-            const float4 Q = tn[gi * rows + 1];
-            atomicAdd(xq + 4 * gi + 0, fmaf(a, P.x, b * Q.x));
-            atomicAdd(xq + 4 * gi + 1, fmaf(a, P.y, b * Q.y));
-            atomicAdd(xq + 4 * gi + 2, fmaf(a, P.z, b * Q.z));
-            atomicAdd(xq + 4 * gi + 3, fmaf(a, P.w, b * Q.w));
-            const float4 P2 = tp[gi * rows];
-            const float4 Q2 = tp[gi * rows + 1];
-            atomicAdd(xq - 1 - 4 * gi - 0, fmaf(b, P2.x, a * Q2.x));
-            atomicAdd(xq - 1 - 4 * gi - 1, fmaf(b, P2.y, a * Q2.y));
-            atomicAdd(xq - 1 - 4 * gi - 2, fmaf(b, P2.z, a * Q2.z));
-            atomicAdd(xq - 1 - 4 * gi - 3, fmaf(b, P2.w, a * Q2.w));
+            for (int gi = 0; gi < NG; ++gi) {
+                const float4 Pv = tn[gi * rows];
+                const float4 Qv = tn[gi * rows + 1];
+                xq[4 * gi + 0] = xq[4 * gi + 0] + fmaf(a, Pv.x, b * Qv.x);
+                xq[4 * gi + 1] = xq[4 * gi + 1] + fmaf(a, Pv.y, b * Qv.y);
+                xq[4 * gi + 2] = xq[4 * gi + 2] + fmaf(a, Pv.z, b * Qv.z);
+                xq[4 * gi + 3] = xq[4 * gi + 3] + fmaf(a, Pv.w, b * Qv.w);
+                const float4 P2 = tp[gi * rows];
+                const float4 Q2 = tp[gi * rows + 1];
+                xq[-1 - 4 * gi - 0] = xq[-1 - 4 * gi - 0] + fmaf(b, P2.x, a * Q2.x);
+                xq[-1 - 4 * gi - 1] = xq[-1 - 4 * gi - 1] + fmaf(b, P2.y, a * Q2.y);
+                xq[-1 - 4 * gi - 2] = xq[-1 - 4 * gi - 2] + fmaf(b, P2.z, a * Q2.z);
+                xq[-1 - 4 * gi - 3] = xq[-1 - 4 * gi - 3] + fmaf(b, P2.w, a * Q2.w);
+            }
         }
     }
     if (bad) atomicOr(status, kStatusWindow);
     __syncthreads();
+    // tile window position p = wave window position p - 64 w, summed in wave order
     float* out = xpart + (((int64_t)mic * S.n_grp + g) * S.n_tiles + tile) * S.window;
-    for (int p = tid; p < W; p += NT) out[p] = xb[p];
+    for (int p = tid; p < W; p += NT) {
+        float acc = 0.0f;
+        for (int w2 = 0; w2 < WAVES; ++w2) {
+            const int pw = p - 64 * w2;
+            if (pw >= 0 && pw < Ww) acc += wbase[w2 * Wstride + pw];
+        }
+        out[p] = acc;
+    }
 }
 
 template <int T, int NT>
@@ -169,7 +206,7 @@ static hipError_t launch_adj_x_t(const DScene& hs, const DImage* d_imgs, const D
                                  const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
                                  float* xpart, int32_t* d_status, hipStream_t st)
 {
-    const size_t lds = adj_x_lds_bytes(T, L, hs.window);
+    const size_t lds = adj_x_lds_bytes(T, L, hs.window, NT);
     auto kern = k_adj_x<T, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -284,7 +321,8 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     const float fn = (float)nc + 0.5f;
     const float Lf = (float)L, L2f = (float)L2;
     float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
-    float* gout = gpart + (((int64_t)mic * S.n_tiles + tile) * WAVES + wave) * S.n_img;
+    const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * WAVES;
+    float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * WAVES + wave;
     int bad = 0;
     auto seg_index = [&](const DImage& im, int* kout) {
         int k = (int)(fn * im.invR);
@@ -365,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
         }
         if (valid) dout[(int64_t)ii * S.n_out] = Db;
         E = wave_sum(E);
-        if (lane == 0) gout[ii] = E;
+        if (lane == 0) gout[(int64_t)ii * nrow] = E;
     }
     if (bad) atomicOr(status, kStatusWindow);
 }
@@ -540,10 +578,17 @@ __device__ inline double block_sum(double v, double* sh)
     return r;
 }
 
-// Block b of NB: images ii = b*256 + t (+ k*NB*256) give dL/dbeta_w partials,
-// sum_i (d beta_i / d beta_w) G_i with G_i = dL/dbeta_i summed over mics, tiles
-// and waves; grid points i = b*256 + t (+ k*NB*256) give dL/dP_a partials.
-// partial: [NB][6 + 3*kMaxGradKnots].
+__device__ inline double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block b of NB (4 waves): images ii = 4b + wave (+ k*4*NB), one wave per image,
+// give dL/dbeta_w partials sum_i (d beta_i / d beta_w) G_i, G_i = dL/dbeta_i summed
+// over its [mic][tile][wave] rows; grid points i = b*256 + t (+ k*NB*256) give
+// dL/dP_a partials.  partial: [NB][6 + 3*kMaxGradKnots].
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __restrict__ scenes, int scene,
                                                                 const DImage* __restrict__ imgs,
                                                                 const float* __restrict__ gpart, int gstride,
@@ -554,15 +599,18 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
     __shared__ double sh[kRedThreads];
     const DScene& S = scenes[scene];
     const int t = threadIdx.x, b = blockIdx.x, NB = gridDim.x;
+    const int wave = t >> 6, lane = t & 63;
+    constexpr int WPB = kRedThreads / 64;
     const int64_t stride = (int64_t)NB * kRedThreads;
     double* out = partial + (int64_t)b * (6 + 3 * kMaxGradKnots);
     const DImage* I = imgs + S.img_begin;
     if (want_beta) {
         double bw[6] = {0, 0, 0, 0, 0, 0};
         const int64_t nrow = (int64_t)S.n_mics * gstride;
-        for (int64_t ii = (int64_t)b * kRedThreads + t; ii < S.n_img; ii += stride) {
+        for (int64_t ii = (int64_t)b * WPB + wave; ii < S.n_img; ii += (int64_t)NB * WPB) {
             double Gi = 0.0;
-            for (int64_t r = 0; r < nrow; ++r) Gi += gpart[r * S.n_img + ii];
+            for (int64_t r = lane; r < nrow; r += 64) Gi += gpart[ii * nrow + r];
+            Gi = wave_sum_d(Gi);
             const DImage im = I[ii];
             for (int w = 0; w < 6; ++w) {
                 const int h = im.hits[w];
@@ -576,9 +624,16 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
                 bw[w] += d * Gi;
             }
         }
+        // every lane of a wave holds the same bw; combine the waves in order
         for (int w = 0; w < 6; ++w) {
-            const double tot = block_sum(bw[w], sh);
-            if (t == 0) out[w] = tot;
+            if (lane == 0) sh[wave] = bw[w];
+            __syncthreads();
+            if (t == 0) {
+                double v = 0.0;
+                for (int k = 0; k < WPB; ++k) v += sh[k];
+                out[w] = v;
+            }
+            __syncthreads();
         }
     }
     if (want_src && S.src_knots > 0) {
@@ -611,25 +666,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
     }
 }
 
-// Sums the NB block partials in block order.
-__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const DScene* __restrict__ scenes, int scene, int NB,
-                                                              const double* __restrict__ partial, int want_beta,
-                                                              int want_src, double* __restrict__ gbeta,
-                                                              double* __restrict__ gsrc)
+// One wave per output value: the NB block partials, lane-strided, then a
+// fixed butterfly.
+__global__ __launch_bounds__(64) void k_reduce_final(const DScene* __restrict__ scenes, int scene, int NB,
+                                                     const double* __restrict__ partial, int want_beta,
+                                                     int want_src, double* __restrict__ gbeta,
+                                                     double* __restrict__ gsrc)
 {
     const DScene& S = scenes[scene];
-    const int t = threadIdx.x;
+    const int v = blockIdx.x, lane = threadIdx.x;
     const int row = 6 + 3 * kMaxGradKnots;
-    if (t < 6 && want_beta) {
-        double v = 0.0;
-        for (int b = 0; b < NB; ++b) v += partial[(int64_t)b * row + t];
-        gbeta[(int64_t)scene * 6 + t] = v;
-    }
     const int nk = min(S.src_knots, kMaxGradKnots);
-    if (want_src && t < 3 * nk) {
-        double v = 0.0;
-        for (int b = 0; b < NB; ++b) v += partial[(int64_t)b * row + 6 + t];
-        gsrc[(int64_t)S.src_grad_off * 3 + t] = v;
+    const bool is_beta = v < 6;
+    if (is_beta ? !want_beta : (!want_src || v - 6 >= 3 * nk)) return;
+    double acc = 0.0;
+    for (int b = lane; b < NB; b += 64) acc += partial[(int64_t)b * row + v];
+    acc = wave_sum_d(acc);
+    if (lane == 0) {
+        if (is_beta) gbeta[(int64_t)scene * 6 + v] = acc;
+        else gsrc[(int64_t)S.src_grad_off * 3 + (v - 6)] = acc;
     }
 }
 
@@ -655,8 +710,8 @@ hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene&
                        gpart_stride, pgc, pga, wb, wsrc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, d_scenes, scene, NB, partial, wb, wsrc,
-                       gbeta, gsrc);
+    hipLaunchKernelGGL(k_reduce_final, dim3(6 + 3 * kMaxGradKnots), dim3(64), 0, st, d_scenes, scene, NB, partial,
+                       wb, wsrc, gbeta, gsrc);
     return hipGetLastError();
 }
 

@@ -303,13 +303,12 @@ struct msim_plan {
     int group_cap = 0;                    // images per delay group (0: chosen from the tile count)
     // batched path
     std::vector<DScene> scenes_b;         // with workspace bases set
-    std::vector<int64_t> grid_prefix, seg_prefix, y_prefix;
+    std::vector<int64_t> run_prefix, y_prefix;
     std::vector<WorkItem> items;
-    int64_t b_grid_total = 0, b_seg_total = 0, b_part_total = 0;
+    int64_t b_run_total = 0, b_seg_total = 0, b_part_total = 0;
     int b_window = 0, b_wgs = 0;
     DScene* d_scenes_b = nullptr;
-    int64_t* d_grid_prefix = nullptr;
-    int64_t* d_seg_prefix = nullptr;
+    int64_t* d_run_prefix = nullptr;
     int64_t* d_y_prefix = nullptr;
     WorkItem* d_items = nullptr;
     // graph of the batched forward, valid for one (x, y, workspace) triple
@@ -531,7 +530,7 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     d.y_off = y_off;
     d.img_begin = (int)P->images.size();
     d.n_img = I;
-    int64_t seg = 0;
+    int64_t seg = 0, runs = 0;
     for (const HostImage& h : imgs) {
         DImage di{};
         for (int a = 0; a < 3; ++a) di.m[a] = (int16_t)h.m[a];
@@ -542,9 +541,12 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
         di.seg_off = (int32_t)seg;
         di.n_seg = (int32_t)((s.n_out + h.R - 1) / h.R);
         for (int w = 0; w < 6; ++w) di.hits[w] = (int8_t)h.hits[w];
+        di.run_off = (int32_t)runs;
         seg += di.n_seg;
+        runs += (di.n_seg + kTrackRun - 1) / kTrackRun;
         P->images.push_back(di);
     }
+    d.runs_per_mic = runs;
     for (int w = 0; w < 6; ++w) d.beta[w] = s.beta[w];
     d.src_grad_off = (int32_t)P->src_grad_total;
     d.src_knots = s.src.kind == MSIM_TRAJ_PWL ? s.src.n_points : 0;
@@ -577,7 +579,9 @@ msim_status regroup(msim_plan* P)
         // beside the source window) fits too; failing that, the forward's alone.
         bool grad_fit = true;
         auto fits = [&](int window) {
-            return (grad_fit ? adj_track_lds_bytes(T, L, window) : synth_lds_bytes(T, L, window)) <= kLdsLimit;
+            if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
+            return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
+                   adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
         };
         int G = 1;
         if (P->group_cap > 0) {
@@ -630,25 +634,23 @@ msim_status regroup(msim_plan* P)
     }
     // batched layout
     P->scenes_b = P->scenes;
-    P->grid_prefix.assign(P->n_scenes, 0);
-    P->seg_prefix.assign(P->n_scenes, 0);
+    P->run_prefix.assign(P->n_scenes, 0);
     P->y_prefix.assign(P->n_scenes, 0);
-    int64_t go = 0, so = 0, po = 0;
+    int64_t ro = 0, so = 0, po = 0;
     int wmax = 0;
     for (int s = 0; s < P->n_scenes; ++s) {
         DScene& b = P->scenes_b[s];
-        b.grid_base = go;
+        b.grid_base = 0;            // the batched forward keeps no delay grid
         b.trk_base = so;
         b.part_base = po;
-        P->grid_prefix[s] = go;
-        P->seg_prefix[s] = so;
+        P->run_prefix[s] = ro;
         P->y_prefix[s] = b.y_off;
-        go += (b.seg_per_mic + 3 * (int64_t)b.n_img) * b.n_mics;
+        ro += b.runs_per_mic * b.n_mics;
         so += b.seg_per_mic * b.n_mics;
         po += (int64_t)b.n_mics * b.n_grp * b.n_out;
         wmax = std::max(wmax, b.window);
     }
-    P->b_grid_total = go;
+    P->b_run_total = ro;
     P->b_seg_total = so;
     P->b_part_total = po;
     P->b_window = wmax;
@@ -681,14 +683,13 @@ void free_layout(msim_plan* P)
     (void)hipFree(P->d_scenes);
     (void)hipFree(P->d_groups);
     (void)hipFree(P->d_scenes_b);
-    (void)hipFree(P->d_grid_prefix);
-    (void)hipFree(P->d_seg_prefix);
+    (void)hipFree(P->d_run_prefix);
     (void)hipFree(P->d_y_prefix);
     (void)hipFree(P->d_items);
     P->d_scenes = nullptr;
     P->d_groups = nullptr;
     P->d_scenes_b = nullptr;
-    P->d_grid_prefix = P->d_seg_prefix = P->d_y_prefix = nullptr;
+    P->d_run_prefix = P->d_y_prefix = nullptr;
     P->d_items = nullptr;
 }
 
@@ -700,8 +701,7 @@ msim_status upload_layout(msim_plan* P)
     msim_status st;
     if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_groups, P->groups)) != MSIM_OK ||
         (st = upload(&P->d_scenes_b, P->scenes_b)) != MSIM_OK ||
-        (st = upload(&P->d_grid_prefix, P->grid_prefix)) != MSIM_OK ||
-        (st = upload(&P->d_seg_prefix, P->seg_prefix)) != MSIM_OK ||
+        (st = upload(&P->d_run_prefix, P->run_prefix)) != MSIM_OK ||
         (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK)
         return st;
     return MSIM_OK;
@@ -715,10 +715,10 @@ struct FwdWs {
     float* part;      // per-group partial outputs [mic][group][n_out]
 };
 
-size_t carve_fwd(const DScene& d, char* base, FwdWs* w)
+size_t carve_fwd(const DScene& d, char* base, FwdWs* w, bool with_grid = false)
 {
     const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
-    const size_t grid = ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics;
+    const size_t grid = with_grid ? ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics : 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -743,7 +743,7 @@ size_t fwd_ws_bytes(const msim_plan*, const DScene& d) { return carve_fwd(d, nul
 // Adjoint scratch of one scene, after the forward's (whose tracks it reuses).
 size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, AdjBufs* aw, double** partial)
 {
-    size_t off = carve_fwd(d, base, fw);
+    size_t off = carve_fwd(d, base, fw, true);
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
         off += align_up(bytes);
@@ -1002,7 +1002,7 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
         carve_fwd(d, (char*)ws, &w);
         {
             LaunchTimer t(P, kKindTracks, stream);
-            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, w.grid, w.seg, w.segK,
+            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, nullptr, w.seg, w.segK,
                                  P->par.c, P->par.fs, P->par.delay_model, stream));
         }
         {
@@ -1062,7 +1062,6 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
 namespace {
 
 struct BatchWs {
-    double* grid;
     Seg* seg;
     int32_t* segK;
     float* part;
@@ -1077,13 +1076,11 @@ size_t carve_batched(const msim_plan* P, char* base, BatchWs* w)
         off += align_up(bytes);
         return p;
     };
-    char* g = take((size_t)P->b_grid_total * sizeof(double));
     char* s = take((size_t)P->b_seg_total * sizeof(Seg));
     char* k = take((size_t)P->b_seg_total * sizeof(int32_t));
     char* p = take((size_t)P->b_part_total * sizeof(float));
     char* t = take(sizeof(int32_t));
     if (w) {
-        w->grid = (double*)g;
         w->seg = (Seg*)s;
         w->segK = (int32_t*)k;
         w->part = (float*)p;
@@ -1096,9 +1093,8 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
 {
     {
         LaunchTimer t(P, kKindTracks, st);
-        HIP_OK(launch_tracks_all(P->d_scenes_b, P->n_scenes, P->d_grid_prefix, P->b_grid_total, P->d_seg_prefix,
-                                 P->b_seg_total, P->d_images, P->d_knots, P->d_mics, w.grid, w.seg, w.segK,
-                                 P->par.c, P->par.fs, P->par.delay_model, st));
+        HIP_OK(launch_tracks_all(P->d_scenes_b, P->n_scenes, P->d_run_prefix, P->b_run_total, P->d_images,
+                                 P->d_knots, P->d_mics, w.seg, w.segK, P->par.c, P->par.fs, P->par.delay_model, st));
     }
     {
         LaunchTimer t(P, kKindSynth, st);

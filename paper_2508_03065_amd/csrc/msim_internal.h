@@ -36,6 +36,7 @@ struct DScene {
     int32_t grp_begin;    // this scene's delay groups
     int32_t n_grp;
     int64_t seg_per_mic;  // track segments of one mic (sum over images)
+    int64_t runs_per_mic; // track-kernel runs of one mic
     int32_t n_tiles;
     int32_t window;       // LDS source window (positions) the plan sized for this scene
     double beta[6];       // wall coefficients (for d/dbeta)
@@ -66,7 +67,11 @@ struct DImage {
     int32_t n_seg;        // ceil(n_out / R)
     int8_t hits[6];       // reflections on each wall (beta_i = prod beta_w^hits_w)
     int8_t pad[2];
+    int32_t run_off;      // first track run (kTrackRun segments) within one mic
 };
+
+// Grid segments one thread of the track kernel walks in time order.
+constexpr int kTrackRun = 32;
 
 // Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
 // samples, are bounded by [dmin, dmax] for every mic at every time.
@@ -97,10 +102,9 @@ hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DIma
 
 hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st);
 
-hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_grid_prefix, int64_t grid_total,
-                             const int64_t* d_seg_prefix, int64_t seg_total, const DImage* d_imgs,
-                             const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
-                             double c, double fs, int delay_model, hipStream_t st);
+hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_run_prefix, int64_t run_total,
+                             const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
+                             int32_t* segK, double c, double fs, int delay_model, hipStream_t st);
 hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window, const DScene* d_scenes,
                                    const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
@@ -122,7 +126,7 @@ struct AdjBufs {
     int32_t* pga;     // [mic][grid point]: knot index of that emission time
 };
 
-size_t adj_x_lds_bytes(int taps, int L, int window);
+size_t adj_x_lds_bytes(int taps, int L, int window, int nthreads);
 size_t adj_track_lds_bytes(int taps, int L, int window);
 
 hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,

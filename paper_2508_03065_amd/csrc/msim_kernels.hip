@@ -18,77 +18,114 @@ namespace msim {
 
 // ------------------------------------------------------------------- tracks
 
-// Pass 1: exact delay of every image at every grid point kR, k = -1 .. n_seg+1,
-// one thread per (mic, image, grid point) of a scene.  Grid of image ii starts
-// at seg_off + 3 ii within the mic's grid.
-__device__ inline void grid_point(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
-                                  const double* __restrict__ knots, const double* __restrict__ mics,
-                                  double* __restrict__ grid, double c, double fs, int model)
+// Newton's method for the retarded delay from a guess, at reception time t for
+// mic position r: the root of f(tau) = tau - |p_i(t - tau) - r| / c, with
+// f' = 1 + u . S p'(t - tau) / c in [0.9, 1.1].  Stops once a step is below
+// 1e-9 s: the quadratic convergence leaves an error far below that step (at
+// most about 1e-11 s where a step straddles a kink of the path).
+__device__ inline double newton_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                    const double r[3], double t, double inv_c, double tau)
 {
-    const int64_t per_mic = S.seg_per_mic + 3 * (int64_t)S.n_img;
-    const int mic = (int)(gid / per_mic);
-    const int64_t idx = gid - (int64_t)mic * per_mic;
-    const DImage* I = imgs + S.img_begin;
-    const int ii = owner(I, S.n_img, idx, 3);
-    const DImage im = I[ii];
-    const int64_t k = idx - ((int64_t)im.seg_off + 3 * (int64_t)ii) - 1;
-    grid[S.grid_base + gid] = fs * solve_tau(S, im.m, knots, mics, mic, (double)(k * im.R) / fs, 1.0 / c, model);
-}
-
-// Pass 2: one thread per (mic, segment): segment k of image i covers outputs
-// [kR, (k+1)R); its cubic is the uniform Catmull-Rom through the delays at
-// (k-1)R .. (k+2)R, stored as an integer base and FP32 offsets.
-__device__ inline void segment(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
-                               const double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK)
-{
-    const int64_t per_mic = S.seg_per_mic;
-    const int mic = (int)(gid / per_mic);
-    const int64_t sidx = gid - (int64_t)mic * per_mic;
-    const DImage* I = imgs + S.img_begin;
-    const int ii = owner(I, S.n_img, sidx, 0);
-    const DImage im = I[ii];
-    const int64_t k = sidx - im.seg_off;
-    const double* D = grid + S.grid_base + (int64_t)mic * (per_mic + 3 * (int64_t)S.n_img) + im.seg_off +
-                      3 * (int64_t)ii + k;
-    const double d0 = D[0], d1 = D[1], d2 = D[2], d3 = D[3];
-    const double Kd = floor(d1);
-    Seg out;
-    out.a0 = (float)(d1 - Kd);
-    if (im.R == 1) {
-        out.b1 = out.b2 = out.b3 = 0.0f;
-    } else {
-        const double a1 = 0.5 * (d2 - d0);
-        const double a2 = 0.5 * (2.0 * d0 - 5.0 * d1 + 4.0 * d2 - d3);
-        const double a3 = 0.5 * (3.0 * d1 - d0 - 3.0 * d2 + d3);
-        const double iR = 1.0 / (double)im.R;
-        out.b1 = (float)(a1 * iR);
-        out.b2 = (float)(a2 * iR * iR);
-        out.b3 = (float)(a3 * iR * iR * iR);
+    for (int it = 0; it < 30; ++it) {
+        double q[3], v[3];
+        traj_pos_vel(S.src, knots, t - tau, q, v);
+        double d2 = 0.0, ev = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
+            d2 += e * e;
+            ev += e * ((m[a] & 1) ? -v[a] : v[a]);
+        }
+        const double d = sqrt(d2);
+        const double step = (tau - d * inv_c) / (1.0 + ev * inv_c / d);
+        tau -= step;
+        if (fabs(step) <= 1e-9) break;
     }
-    seg[S.trk_base + gid] = out;
-    segK[S.trk_base + gid] = (int32_t)Kd;
+    return tau;
 }
 
-__device__ inline int64_t grid_count(const DScene& S) { return (S.seg_per_mic + 3 * (int64_t)S.n_img) * S.n_mics; }
-__device__ inline int64_t seg_count(const DScene& S) { return S.seg_per_mic * S.n_mics; }
+// One thread per (mic, image, run of kTrackRun grid segments).  The thread walks
+// the delay grid of its run in time order -- kR for k = k0 .. k1-1 at the audio
+// rate (R = 1), k0-1 .. k1+1 otherwise -- solving each delay from the linear
+// extrapolation of the two before, and emits segment k as soon as the four
+// delays (k-1)R .. (k+2)R of its Catmull-Rom cubic are known.  Segment k covers
+// outputs [kR, (k+1)R): D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)), integer
+// base K and FP32 offsets.  With grid != NULL the delays the thread owns are
+// also stored (grid index k+1 within the image's n_seg+3 slots), for the adjoint.
+__device__ inline void track_run(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
+                                 const double* __restrict__ knots, const double* __restrict__ mics,
+                                 double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK,
+                                 double c, double fs, int model)
+{
+    const int64_t per_mic = S.runs_per_mic;
+    const int mic = (int)(gid / per_mic);
+    const int64_t ridx = gid - (int64_t)mic * per_mic;
+    const DImage* I = imgs + S.img_begin;
+    int lo = 0, hi = S.n_img - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (I[mid].run_off <= ridx) lo = mid; else hi = mid - 1;
+    }
+    const int ii = lo;
+    const DImage im = I[ii];
+    const int64_t k0 = (ridx - im.run_off) * kTrackRun;
+    const int64_t k1 = min((int64_t)im.n_seg, k0 + kTrackRun);
+    const int R = im.R;
+    const double inv_c = 1.0 / c;
+    const int64_t gfirst = (R == 1) ? k0 : k0 - 1;
+    const int64_t glast = (R == 1) ? k1 - 1 : k1 + 1;
+    const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic + im.seg_off;
+    double* gout = grid ? grid + S.grid_base + (int64_t)mic * (S.seg_per_mic + 3 * (int64_t)S.n_img) +
+                              im.seg_off + 3 * (int64_t)ii + 1
+                        : nullptr;
+    double tp1 = 0.0, tp2 = 0.0;          // the two previous delays (s)
+    double D0 = 0.0, D1 = 0.0, D2 = 0.0;  // the three previous delays (samples)
+    for (int64_t g = gfirst; g <= glast; ++g) {
+        const double t = (double)(g * R) / fs;
+        double r[3];
+        mic_pos(S, knots, mics, mic, t, r);
+        double tau;
+        if (model == 1 || g == gfirst) {
+            tau = dist_to(S, im.m, knots, r, t) * inv_c;
+            if (model == 0) tau = newton_tau(S, im.m, knots, r, t, inv_c, tau);
+        } else {
+            const double guess = (g >= gfirst + 2) ? 2.0 * tp1 - tp2 : tp1;
+            tau = newton_tau(S, im.m, knots, r, t, inv_c, guess);
+        }
+        tp2 = tp1;
+        tp1 = tau;
+        const double D = fs * tau;
+        const bool own = (g >= k0 && g < k1) || (k0 == 0 && g < 0) || (k1 == im.n_seg && g >= k1);
+        if (gout && own) gout[g] = D;
+        if (R == 1) {
+            const double Kd = floor(D);
+            seg[trk + g] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
+            segK[trk + g] = (int32_t)Kd;
+        } else if (g >= k0 + 2) {
+            // segment k = g - 2 from D_{k-1} = D0, D_k = D1, D_{k+1} = D2, D_{k+2} = D
+            const int64_t k = g - 2;
+            const double Kd = floor(D1);
+            const double a1 = 0.5 * (D2 - D0);
+            const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D);
+            const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D);
+            const double iR = 1.0 / (double)R;
+            seg[trk + k] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
+            segK[trk + k] = (int32_t)Kd;
+        }
+        D0 = D1;
+        D1 = D2;
+        D2 = D;
+    }
+}
 
-__global__ __launch_bounds__(256) void k_grid(const DScene* __restrict__ scenes, int scene,
-                                              const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                              const double* __restrict__ mics, double* __restrict__ grid,
-                                              double c, double fs, int model)
+__global__ __launch_bounds__(256) void k_tracks(const DScene* __restrict__ scenes, int scene,
+                                                const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                                const double* __restrict__ mics, double* __restrict__ grid,
+                                                Seg* __restrict__ seg, int32_t* __restrict__ segK, double c,
+                                                double fs, int model)
 {
     const DScene& S = scenes[scene];
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < grid_count(S)) grid_point(S, gid, imgs, knots, mics, grid, c, fs, model);
-}
-
-__global__ __launch_bounds__(256) void k_segs(const DScene* __restrict__ scenes, int scene,
-                                              const DImage* __restrict__ imgs, const double* __restrict__ grid,
-                                              Seg* __restrict__ seg, int32_t* __restrict__ segK)
-{
-    const DScene& S = scenes[scene];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < seg_count(S)) segment(S, gid, imgs, grid, seg, segK);
+    if (gid < S.runs_per_mic * S.n_mics) track_run(S, gid, imgs, knots, mics, grid, seg, segK, c, fs, model);
 }
 
 // Last scene whose prefix start is <= i (prefix[0] = 0, ascending).
@@ -102,58 +139,36 @@ __device__ inline int scene_of(const int64_t* __restrict__ prefix, int n, int64_
     return lo;
 }
 
-// Batched forms: one launch over every scene; prefix arrays give each scene's
-// first flattened index (grid points, segments).
-__global__ __launch_bounds__(256) void k_grid_all(const DScene* __restrict__ scenes, int n_scenes,
-                                                  const int64_t* __restrict__ prefix, int64_t total,
-                                                  const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                                  const double* __restrict__ mics, double* __restrict__ grid,
-                                                  double c, double fs, int model)
+// Batched form: one launch over every scene; prefix[s] is scene s's first run.
+__global__ __launch_bounds__(256) void k_tracks_all(const DScene* __restrict__ scenes, int n_scenes,
+                                                    const int64_t* __restrict__ prefix, int64_t total,
+                                                    const DImage* __restrict__ imgs, const double* __restrict__ knots,
+                                                    const double* __restrict__ mics, Seg* __restrict__ seg,
+                                                    int32_t* __restrict__ segK, double c, double fs, int model)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const int s = scene_of(prefix, n_scenes, i);
-    grid_point(scenes[s], i - prefix[s], imgs, knots, mics, grid, c, fs, model);
-}
-
-__global__ __launch_bounds__(256) void k_segs_all(const DScene* __restrict__ scenes, int n_scenes,
-                                                  const int64_t* __restrict__ prefix, int64_t total,
-                                                  const DImage* __restrict__ imgs, const double* __restrict__ grid,
-                                                  Seg* __restrict__ seg, int32_t* __restrict__ segK)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int s = scene_of(prefix, n_scenes, i);
-    segment(scenes[s], i - prefix[s], imgs, grid, seg, segK);
+    track_run(scenes[s], i - prefix[s], imgs, knots, mics, nullptr, seg, segK, c, fs, model);
 }
 
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
                          const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st)
 {
-    const int64_t ng = (hs.seg_per_mic + 3 * (int64_t)hs.n_img) * hs.n_mics;
-    const int64_t ns = hs.seg_per_mic * hs.n_mics;
-    if (ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grid, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs,
-                       d_knots, d_mics, grid, c, fs, delay_model);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_segs, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs, grid,
-                       seg, segK);
+    const int64_t n = hs.runs_per_mic * hs.n_mics;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tracks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs,
+                       d_knots, d_mics, grid, seg, segK, c, fs, delay_model);
     return hipGetLastError();
 }
 
-hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_grid_prefix, int64_t grid_total,
-                             const int64_t* d_seg_prefix, int64_t seg_total, const DImage* d_imgs,
-                             const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
-                             double c, double fs, int delay_model, hipStream_t st)
+hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_run_prefix, int64_t run_total,
+                             const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
+                             int32_t* segK, double c, double fs, int delay_model, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_grid_all, dim3((unsigned)((grid_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
-                       d_grid_prefix, grid_total, d_imgs, d_knots, d_mics, grid, c, fs, delay_model);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_segs_all, dim3((unsigned)((seg_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
-                       d_seg_prefix, seg_total, d_imgs, grid, seg, segK);
+    hipLaunchKernelGGL(k_tracks_all, dim3((unsigned)((run_total + 255) / 256)), dim3(256), 0, st, d_scenes,
+                       n_scenes, d_run_prefix, run_total, d_imgs, d_knots, d_mics, seg, segK, c, fs, delay_model);
     return hipGetLastError();
 }
 

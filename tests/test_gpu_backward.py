@@ -124,3 +124,17 @@ def test_autograd_function(torch_cuda):
     assert rel(x.grad.cpu().numpy(), O.adjoint_x(sc, par, gy)) <= 1e-5
     assert rel(beta.grad[0].numpy(), O.grad_beta(sc, par, gy)) <= 1e-4
     assert rel(knots.grad.numpy(), fd_knots(sc, par, gy)) <= 1e-3
+
+
+def test_backward_deterministic(torch_cuda):
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    sc, par = G.small_scene(seed=39, max_order=5, seconds=0.15, taps=64, n_mics=2, moving_rcv=True)
+    plan = Plan([sc], par)
+    x = plan.pack_x([sc.x])
+    gy = torch.randn(plan.y_total, generator=torch.Generator().manual_seed(5)).cuda()
+    a = [t.clone() for t in plan.backward(x, gy)]
+    b = [t.clone() for t in plan.backward(x, gy)]
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
