@@ -97,7 +97,21 @@ typedef struct {
     int32_t tier_max_order[4];  /* tier k holds orders <= tier_max_order[k] not in an earlier tier */
     int32_t tier_decim[4];      /* decimation of tier k's delay grid (1 = audio rate), 1..4096 */
     int32_t delay_model;        /* MSIM_DELAY_RETARDED (emission-time delay) or _INSTANTANEOUS */
+    int32_t fd_kind;            /* MSIM_FD_TABLE (default) or MSIM_FD_FARROW */
+    int32_t farrow_order;       /* M, 4..11: degree of the Farrow polynomial in the fractional delay */
 } msim_params;
+
+/* How the T-tap Kaiser-windowed sinc h(j - mu) is applied.
+ *  MSIM_FD_TABLE:  an oversampled table of h in LDS, linearly interpolated between
+ *                  phases, one gather of T taps per image sample.
+ *  MSIM_FD_FARROW: the Farrow structure of Sec. II-B (Eq. 3-5): h(j - mu) is fitted
+ *                  by a degree-M polynomial in s = 2 mu - 1 for every tap j
+ *                  (Chebyshev interpolation of the same kernel), the M+1 filtered
+ *                  signals v_k = x * c_k are computed once per source, and each image
+ *                  sample reads v_0..v_M at n - floor(D) and evaluates the polynomial
+ *                  by Horner's rule.  Both approximate the same h; with M = 9 the
+ *                  polynomial's error is below FP32 rounding of the output. */
+enum { MSIM_FD_TABLE = 0, MSIM_FD_FARROW = 1 };
 
 typedef struct msim_plan msim_plan;
 
@@ -204,6 +218,8 @@ typedef struct {
     int32_t tracks_launches, synth_launches, reduce_launches, adjoint_launches, params_launches;
     double graph_ms;           /* replays of the batched forward's graph */
     int32_t graph_launches;
+    double filter_ms;          /* the Farrow filter bank v_k = x * c_k */
+    int32_t filter_launches;
 } msim_profile;
 
 msim_status msim_profile_begin(msim_plan* plan);

@@ -37,7 +37,8 @@ class Scene(C.Structure):
 class Params(C.Structure):
     _fields_ = [("c", C.c_double), ("fs", C.c_double), ("taps", C.c_int32), ("kaiser_beta", C.c_double),
                 ("cutoff", C.c_double), ("table_phases", C.c_int32), ("n_tiers", C.c_int32),
-                ("tier_max_order", C.c_int32 * 4), ("tier_decim", C.c_int32 * 4), ("delay_model", C.c_int32)]
+                ("tier_max_order", C.c_int32 * 4), ("tier_decim", C.c_int32 * 4), ("delay_model", C.c_int32),
+                ("fd_kind", C.c_int32), ("farrow_order", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -45,7 +46,8 @@ class Profile(C.Structure):
                 ("adjoint_ms", C.c_double), ("params_ms", C.c_double),
                 ("tracks_launches", C.c_int32), ("synth_launches", C.c_int32), ("reduce_launches", C.c_int32),
                 ("adjoint_launches", C.c_int32), ("params_launches", C.c_int32),
-                ("graph_ms", C.c_double), ("graph_launches", C.c_int32)]
+                ("graph_ms", C.c_double), ("graph_launches", C.c_int32),
+                ("filter_ms", C.c_double), ("filter_launches", C.c_int32)]
 
 
 class Tuning(C.Structure):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsim.so")
-SOURCES = ["msim_kernels.hip", "msim_adjoint.hip", "msim_host.cpp"]
+SOURCES = ["msim_kernels.hip", "msim_adjoint.hip", "msim_farrow.hip", "msim_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -174,6 +174,9 @@ msim_status check_params(const msim_params* p)
     }
     if (p->delay_model != MSIM_DELAY_RETARDED && p->delay_model != MSIM_DELAY_INSTANTANEOUS)
         return fail(MSIM_E_INVALID_ARG, "unknown delay_model");
+    if (p->fd_kind != MSIM_FD_TABLE && p->fd_kind != MSIM_FD_FARROW) return fail(MSIM_E_INVALID_ARG, "unknown fd_kind");
+    if (p->fd_kind == MSIM_FD_FARROW && (p->farrow_order < 4 || p->farrow_order > 11))
+        return fail(MSIM_E_INVALID_ARG, "farrow_order must be 4..11");
     return MSIM_OK;
 }
 
@@ -326,6 +329,11 @@ struct msim_plan {
     double* d_mics = nullptr;
     float4* d_table = nullptr;
     float4* d_dtable = nullptr;
+    std::vector<float> fcoef;             // Farrow coefficients [kFarrowStride][T]
+    std::vector<int64_t> vpos_prefix;     // first Farrow source position of each scene
+    int64_t vpos_total = 0;
+    float* d_fcoef = nullptr;
+    int64_t* d_vpos_prefix = nullptr;
     int32_t* d_status = nullptr;
     int device = 0;
     // profiling: (kind, start, stop) per launch while enabled
@@ -340,7 +348,7 @@ struct msim_plan {
 
 namespace {
 
-enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKindGraph, kKinds };
+enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKindGraph, kKindFilter, kKinds };
 
 hipEvent_t pool_event(msim_plan* P)
 {
@@ -431,6 +439,40 @@ void build_table(msim_plan* P)
     build_quads(P->table, P->par.taps, P->par.table_phases, P->par.kaiser_beta, P->par.cutoff, false);
     // the derivative table is read only by the adjoint, at half the phase density
     build_quads(P->dtable, P->par.taps, P->par.table_phases / 2, P->par.kaiser_beta, P->par.cutoff, true);
+}
+
+// Farrow coefficients: for every tap j = -T/2+1 .. T/2, the degree-M polynomial in
+// s = 2 mu - 1 interpolating h(j - mu) at the M+1 Chebyshev points of [-1, 1],
+// converted to monomials.  coef[k*T + t], t = j + T/2 - 1; rows k > M are zero.
+void build_farrow(msim_plan* P)
+{
+    const int T = P->par.taps, M = P->par.farrow_order, N = M + 1;
+    const double i0b = bessel_i0(P->par.kaiser_beta);
+    P->fcoef.assign((size_t)kFarrowStride * T, 0.0f);
+    std::vector<std::vector<double>> mono(N, std::vector<double>(N, 0.0));   // T_l(s) = sum_k mono[l][k] s^k
+    mono[0][0] = 1.0;
+    if (N > 1) mono[1][1] = 1.0;
+    for (int l = 2; l < N; ++l)
+        for (int k = 0; k < N; ++k)
+            mono[l][k] = (k > 0 ? 2.0 * mono[l - 1][k - 1] : 0.0) - mono[l - 2][k];
+    std::vector<double> f(N), a(N);
+    for (int t = 0; t < T; ++t) {
+        const int j = t - T / 2 + 1;
+        for (int i = 0; i < N; ++i) {
+            const double s = std::cos(kPi * (i + 0.5) / N);
+            f[i] = fd_kernel(j - 0.5 * (s + 1.0), T, P->par.kaiser_beta, P->par.cutoff, i0b);
+        }
+        for (int l = 0; l < N; ++l) {
+            double acc = 0.0;
+            for (int i = 0; i < N; ++i) acc += f[i] * std::cos(kPi * l * (i + 0.5) / N);
+            a[l] = (l == 0 ? 1.0 : 2.0) * acc / N;
+        }
+        for (int k = 0; k < N; ++k) {
+            double c = 0.0;
+            for (int l = k; l < N; ++l) c += a[l] * mono[l][k];
+            P->fcoef[(size_t)k * T + t] = (float)c;
+        }
+    }
 }
 
 int push_traj(msim_plan* P, const msim_traj& tr, DTraj* d)
@@ -579,6 +621,7 @@ msim_status regroup(msim_plan* P)
         // beside the source window) fits too; failing that, the forward's alone.
         bool grad_fit = true;
         auto fits = [&](int window) {
+            if (P->par.fd_kind == MSIM_FD_FARROW) return farrow_lds_bytes(window) <= kLdsLimit;
             if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
             return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
                    adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
@@ -671,7 +714,7 @@ msim_status regroup(msim_plan* P)
     std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     P->items.resize(it.size());
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
-    const size_t lds = synth_lds_bytes(T, L, wmax);
+    const size_t lds = P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L, wmax);
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / NT, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
     P->graph_valid = false;
@@ -740,6 +783,12 @@ size_t carve_fwd(const DScene& d, char* base, FwdWs* w, bool with_grid = false)
 
 size_t fwd_ws_bytes(const msim_plan*, const DScene& d) { return carve_fwd(d, nullptr, nullptr); }
 
+// Farrow-filtered source signals of every scene, ahead of the per-scene scratch.
+size_t farrow_v_bytes(const msim_plan* P)
+{
+    return P->par.fd_kind == MSIM_FD_FARROW ? align_up((size_t)P->vpos_total * kFarrowStride * sizeof(float)) : 0;
+}
+
 // Adjoint scratch of one scene, after the forward's (whose tracks it reuses).
 size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, AdjBufs* aw, double** partial)
 {
@@ -797,6 +846,8 @@ msim_status msim_default_params(msim_params* p)
     p->tier_max_order[2] = 1 << 20;
     p->tier_decim[2] = 160;
     p->delay_model = MSIM_DELAY_RETARDED;
+    p->fd_kind = MSIM_FD_TABLE;
+    p->farrow_order = 9;
     return MSIM_OK;
 }
 
@@ -844,11 +895,21 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     }
     P->x_total = xo;
     P->y_total = yo;
+    // Farrow-filtered source positions [-T/2, n_in + T/2) of every scene, packed
+    int64_t vo = 0;
+    P->vpos_prefix.assign(n_scenes, 0);
+    for (int s = 0; s < n_scenes; ++s) {
+        P->vpos_prefix[s] = vo;
+        P->scenes[s].v_off = vo * kFarrowStride;
+        vo += P->scenes[s].n_in + p->taps;
+    }
+    P->vpos_total = vo;
     if ((st = regroup(P)) != MSIM_OK) {
         delete P;
         return st;
     }
     build_table(P);
+    build_farrow(P);
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
@@ -857,7 +918,8 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
     std::memcpy(dtab4.data(), P->dtable.data(), P->dtable.size() * sizeof(float));
     std::vector<int32_t> zero(1, 0);
-    if ((st = upload(&P->d_dtable, dtab4)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
+    if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
+        (st = upload(&P->d_dtable, dtab4)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
         (st = upload(&P->d_table, tab4)) != MSIM_OK || (st = upload(&P->d_status, zero)) != MSIM_OK ||
         (st = upload_layout(P)) != MSIM_OK) {
@@ -884,6 +946,8 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_mics);
     (void)hipFree(P->d_table);
     (void)hipFree(P->d_dtable);
+    (void)hipFree(P->d_fcoef);
+    (void)hipFree(P->d_vpos_prefix);
     (void)hipFree(P->d_status);
     delete P;
     return MSIM_OK;
@@ -916,7 +980,7 @@ msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* b
     size_t m = 0;
     for (const DScene& d : P->scenes)
         m = std::max(m, with_grad ? carve_adj(P, d, nullptr, nullptr, nullptr, nullptr) : fwd_ws_bytes(P, d));
-    *bytes = m;
+    *bytes = m + (with_grad ? 0 : farrow_v_bytes(P));
     return MSIM_OK;
 }
 
@@ -942,6 +1006,7 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
     if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
     for (int s = 0; s < P->n_scenes; ++s) {
         if (!P->grad_ok[s]) return fail(MSIM_E_UNSUPPORTED, "scene %d: adjoint LDS does not fit its delay groups", s);
+        if (P->par.fd_kind != MSIM_FD_TABLE) return fail(MSIM_E_UNSUPPORTED, "the adjoint is built for the table kernel");
         if (gsrc && P->scenes[s].src_knots > max_grad_knots())
             return fail(MSIM_E_UNSUPPORTED, "scene %d: more than %d source knots", s, max_grad_knots());
     }
@@ -996,10 +1061,18 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
     int dev = -1;
     HIP_OK(hipGetDevice(&dev));
     if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    float* v = (float*)ws;                       // Farrow-filtered sources, all scenes
+    char* scratch = (char*)ws + farrow_v_bytes(P);
+    if (farrow) {
+        LaunchTimer t(P, kKindFilter, stream);
+        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps, P->d_fcoef, x,
+                                  v, stream));
+    }
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
         FwdWs w;
-        carve_fwd(d, (char*)ws, &w);
+        carve_fwd(d, scratch, &w);
         {
             LaunchTimer t(P, kKindTracks, stream);
             HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, nullptr, w.seg, w.segK,
@@ -1007,8 +1080,12 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
         }
         {
             LaunchTimer t(P, kKindSynth, stream);
-            HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
-                                    P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status, stream));
+            if (farrow)
+                HIP_OK(launch_farrow_fwd(P->threads, P->par.taps, d, P->d_images, P->d_groups, w.seg, w.segK, v, w.part,
+                                         P->d_status, stream));
+            else
+                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
+                                        P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status, stream));
         }
         {
             LaunchTimer t(P, kKindReduce, stream);
@@ -1054,6 +1131,8 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
     out->params_launches = cnt[kKindParams];
     out->graph_ms = ms[kKindGraph];
     out->graph_launches = cnt[kKindGraph];
+    out->filter_ms = ms[kKindFilter];
+    out->filter_launches = cnt[kKindFilter];
     return st;
 }
 
@@ -1062,6 +1141,7 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
 namespace {
 
 struct BatchWs {
+    float* v;
     Seg* seg;
     int32_t* segK;
     float* part;
@@ -1076,11 +1156,13 @@ size_t carve_batched(const msim_plan* P, char* base, BatchWs* w)
         off += align_up(bytes);
         return p;
     };
+    char* v = take((size_t)farrow_v_bytes(P));
     char* s = take((size_t)P->b_seg_total * sizeof(Seg));
     char* k = take((size_t)P->b_seg_total * sizeof(int32_t));
     char* p = take((size_t)P->b_part_total * sizeof(float));
     char* t = take(sizeof(int32_t));
     if (w) {
+        w->v = (float*)v;
         w->seg = (Seg*)s;
         w->segK = (int32_t*)k;
         w->part = (float*)p;
@@ -1091,6 +1173,12 @@ size_t carve_batched(const msim_plan* P, char* base, BatchWs* w)
 
 msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchWs& w, hipStream_t st)
 {
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    if (farrow) {
+        LaunchTimer t(P, kKindFilter, st);
+        HIP_OK(launch_farrow_conv(P->d_scenes_b, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps,
+                                  P->d_fcoef, x, w.v, st));
+    }
     {
         LaunchTimer t(P, kKindTracks, st);
         HIP_OK(launch_tracks_all(P->d_scenes_b, P->n_scenes, P->d_run_prefix, P->b_run_total, P->d_images,
@@ -1098,9 +1186,15 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
     }
     {
         LaunchTimer t(P, kKindSynth, st);
-        HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b, P->d_images,
-                                       P->d_groups, P->d_table, P->par.table_phases, P->d_items,
-                                       (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status, st));
+        if (farrow)
+            HIP_OK(launch_farrow_persistent(P->threads, P->b_wgs, P->b_window, P->par.taps, P->d_scenes_b,
+                                            P->d_images, P->d_groups, P->d_items, (int)P->items.size(), w.ticket,
+                                            w.seg, w.segK, w.v, w.part, P->d_status, st));
+        else
+            HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b,
+                                           P->d_images, P->d_groups, P->d_table, P->par.table_phases, P->d_items,
+                                           (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status,
+                                           st));
     }
     LaunchTimer t(P, kKindReduce, st);
     HIP_OK(launch_reduce_all(P->d_scenes_b, P->n_scenes, P->d_y_prefix, P->y_total, w.part, y, st));

@@ -42,6 +42,7 @@ struct DScene {
     double beta[6];       // wall coefficients (for d/dbeta)
     int32_t src_grad_off; // this scene's first knot in the packed d/dsource array
     int32_t src_knots;    // source knots with a gradient (PWL sources; 0 for circles)
+    int64_t v_off;        // this scene's Farrow-filtered source v_k in the workspace (floats)
     int64_t grid_base;    // offsets of this scene's delay grid, track segments and partial
     int64_t trk_base;     //   outputs in the workspace (0 when scenes run one at a time)
     int64_t part_base;
@@ -69,6 +70,9 @@ struct DImage {
     int8_t pad[2];
     int32_t run_off;      // first track run (kTrackRun segments) within one mic
 };
+
+// Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
+constexpr int kFarrowStride = 12;
 
 // Grid segments one thread of the track kernel walks in time order.
 constexpr int kTrackRun = 32;
@@ -147,5 +151,17 @@ hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene&
                                 double* partial, double* gbeta, double* gsrc, hipStream_t st);
 size_t reduce_partial_bytes(const DScene& hs);
 int max_grad_knots();
+
+// ---- Farrow launchers (msim_farrow.hip) ----
+size_t farrow_lds_bytes(int window);
+hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_t* d_vprefix, int64_t total, int taps,
+                              const float* d_coef, const float* x, float* v, hipStream_t st);
+hipError_t launch_farrow_fwd(int nthreads, int taps, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+                             const Seg* seg, const int32_t* segK, const float* v, float* part, int32_t* d_status,
+                             hipStream_t st);
+hipError_t launch_farrow_persistent(int nthreads, int n_wg, int window, int taps, const DScene* d_scenes,
+                                    const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
+                                    int32_t* ticket, const Seg* seg, const int32_t* segK, const float* v, float* part,
+                                    int32_t* d_status, hipStream_t st);
 
 }  // namespace msim

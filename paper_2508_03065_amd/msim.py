@@ -64,6 +64,8 @@ def params_struct(par, table_phases: int = 512) -> _lib.Params:
     p.tier_max_order = (C.c_int32 * 4)(*mo)
     p.tier_decim = (C.c_int32 * 4)(*de)
     p.delay_model = int(par.delay_model)
+    p.fd_kind = int(getattr(par, "fd_kind", 0))
+    p.farrow_order = int(getattr(par, "farrow_order", 9))
     return p
 
 

@@ -86,6 +86,8 @@ class Params:
     cutoff: float = 0.5
     tiers: Tuple[Tuple[int, int], ...] = ()   # ((max_order, decimation), ...); () = full rate
     delay_model: int = 0                      # 0 retarded, 1 instantaneous
+    fd_kind: int = 0                          # how the library applies the kernel: 0 table, 1 Farrow
+    farrow_order: int = 9
 
 
 PAPER_TIERS = ((2, 1), (6, 16), (1 << 20, 160))
