@@ -195,10 +195,14 @@ msim_status msim_autotune(msim_plan* plan, const float* x, float* y, void* ws, s
  *         retarded delay (Sec. II-A, II-C-3); knots are packed per scene as
  *         msim_plan_grad_layout reports (circle sources have none).
  * Knot times, mic and receiver positions get no gradient.  ws holds
- * msim_workspace_size(plan, 1) bytes.  dL/dx accumulates in LDS with atomic adds,
- * so its last bits may differ from run to run; the other outputs are summed in
- * a fixed order.  MSIM_E_UNSUPPORTED: a scene whose delay groups leave no LDS for
- * the adjoint, or a source with more than 32 knots when gsrc is requested. */
+ * msim_workspace_size(plan, 1) bytes.  Both fractional-delay forms have their
+ * adjoint: with MSIM_FD_TABLE dL/dx is scattered tap by tap into per-wave LDS
+ * windows; with MSIM_FD_FARROW each source position gathers the sums
+ * u_k = sum gy g s^k of the image samples that read it, and dL/dx is the
+ * transposed filter bank sum_k c_k (x) u_k.  Every output is summed in a fixed
+ * order, so repeated calls give identical bits.  MSIM_E_UNSUPPORTED: a scene
+ * whose delay groups leave no LDS for the adjoint, or a source with more than
+ * 32 knots when gsrc is requested. */
 msim_status msim_backward(msim_plan* plan, const float* x, const float* gy, float* gx, double* gbeta,
                           double* gsrc, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -245,4 +245,293 @@ hipError_t launch_farrow_persistent(int nthreads, int n_wg, int window, int taps
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ adjoints
+
+// Reverse of the Farrow forward y_c[n] = sum_i g_i(n) sum_k s^k v_k[P_i(n)],
+// P_i(n) = n - floor(D_i(n)), s = 2 mu - 1, v_k = x * c_k:
+//   u_k[P]  = sum over (mic, i, n) with P_i(n) = P of gy_c[n] g_i(n) s^k,
+//   dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j]          (the filter bank's transpose),
+//   dL/dbeta_i = sum gy s_i(n) fs/(4 pi c D),  dL/dD = gy g (ds/dD - s/D),  ds/dD = 2 dr/ds.
+
+// Delay of image im at output n from its track: integer part and offset in [0, 1).
+__device__ inline void delay_at(const DImage& im, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                int64_t trk, int64_t n, int* K, float* off, float* D)
+{
+    int k = (int)(((float)n + 0.5f) * im.invR);
+    k = min(max(k, 0), im.n_seg - 1);
+    const Seg sg = seg[trk + im.seg_off + k];
+    const int Ks = segK[trk + im.seg_off + k];
+    const float v = (float)(n - (int64_t)k * im.R);
+    const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
+    const float fl = floorf(d);
+    *K = Ks + (int)fl;
+    *off = d - fl;
+    *D = (float)Ks + d;
+}
+
+// One lane per source position P of a tile [P0, P0 + NT) of the positions
+// [-T/2, n_in + T/2), one delay group, one mic.  n - floor(D_i(n)) is
+// nondecreasing in n for a subsonic image (the integer delay moves by at most
+// one per sample), so the outputs that read P form a run of at most two
+// samples (none where the integer delay steps down).  The lane reaches it by the
+// fixed-point iteration n <- P + floor(D_i(n)), a contraction with factor
+// |dD/dn| < 1 up to the floor, then tests n-2 .. n+2 and accumulates
+// u_k += gy g s^k in registers.  gy is staged in LDS.
+// upart[((mic*n_grp + g) * (n_in + T) + P + T/2) * 12 + k].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_farrow_adj_u(DScene S, const DImage* __restrict__ imgs,
+                                                      const DGroup* __restrict__ groups, int T,
+                                                      const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                                      const float* __restrict__ gy, float* __restrict__ upart,
+                                                      int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    float* gw = (float*)lds;
+    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const DGroup G = groups[S.grp_begin + g];
+    const int64_t npos = S.n_in + T;
+    const int64_t P0 = (int64_t)tile * NT - T / 2;
+    const int64_t nw = P0 + G.dmin - 4;                 // output sample of gy window slot 0
+    const int W = NT + (G.dmax - G.dmin) + 9;
+    const float* gys = gy + S.y_off + (int64_t)mic * S.n_out;
+    for (int p = tid; p < W; p += NT) {
+        const int64_t n = nw + p;
+        gw[p] = (n >= 0 && n < S.n_out) ? gys[n] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t P = P0 + tid;
+    if (P >= S.n_in + T / 2) return;
+    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const int64_t nlast = S.n_out - 1;
+    float u[kFarrowStride];
+#pragma unroll
+    for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
+    int bad = 0;
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = I[ii];
+        int K;
+        float off, D;
+        int64_t n = min(max(P + (G.dmin + G.dmax) / 2, (int64_t)0), nlast);
+        for (int it = 0; it < 16; ++it) {
+            delay_at(im, seg, segK, trk, n, &K, &off, &D);
+            const int64_t nn = min(max(P + K, (int64_t)0), nlast);
+            if (nn == n) break;
+            n = nn;
+        }
+        for (int dn = -2; dn <= 2; ++dn) {
+            const int64_t c = n + dn;
+            if (c < 0 || c > nlast) continue;
+            delay_at(im, seg, segK, trk, c, &K, &off, &D);
+            if (c - K != P) continue;
+            const int64_t p = c - nw;
+            if (p < 0 || p >= W) {
+                bad = 1;
+                continue;
+            }
+            const float gv = gw[p];
+            const float s = 2.0f * off - 1.0f;
+            float w = gv * im.gfac * __builtin_amdgcn_rcpf(D);
+#pragma unroll
+            for (int k = 0; k < kFarrowStride; ++k) {
+                u[k] += w;
+                w *= s;
+            }
+        }
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+    float4* out = (float4*)(upart + (((int64_t)mic * S.n_grp + g) * npos + (P + T / 2)) * kFarrowStride);
+    out[0] = make_float4(u[0], u[1], u[2], u[3]);
+    out[1] = make_float4(u[4], u[5], u[6], u[7]);
+    out[2] = make_float4(u[8], u[9], u[10], u[11]);
+}
+
+// u = sum over (mic, group) of the partials, in that order.
+__global__ __launch_bounds__(256) void k_farrow_u_reduce(DScene S, int T, const float* __restrict__ upart,
+                                                         float* __restrict__ u)
+{
+    const int64_t npos = S.n_in + T;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npos * kFarrowStride) return;
+    const int64_t rows = (int64_t)S.n_mics * S.n_grp;
+    float acc = 0.0f;
+    for (int64_t r = 0; r < rows; ++r) acc += upart[r * npos * kFarrowStride + i];
+    u[i] = acc;
+}
+
+// dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j], taps j = -T/2+1 .. T/2.
+__global__ __launch_bounds__(256) void k_farrow_corr(DScene S, int T, const float* __restrict__ coef,
+                                                     const float* __restrict__ u, float* __restrict__ gx)
+{
+    __shared__ float c[kFarrowStride * 128];
+    __shared__ float4 us[(256 + 128) * 3];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFarrowStride * T; i += blockDim.x) c[i] = coef[i];
+    const int64_t m0 = (int64_t)blockIdx.x * 256;
+    // positions m0 + j for j in [-T/2+1, 256 + T/2): stored index m + j + T/2
+    const int span = 256 + T;
+    const int64_t npos = S.n_in + T;
+    const float4* u4 = (const float4*)u;
+    for (int i = tid; i < span; i += blockDim.x) {
+        const int64_t q = m0 + 1 + i;                   // stored index of position m0 - T/2 + 1 + i
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, d = a;
+        if (q >= 0 && q < npos) {
+            a = u4[q * 3];
+            b = u4[q * 3 + 1];
+            d = u4[q * 3 + 2];
+        }
+        us[3 * i] = a;
+        us[3 * i + 1] = b;
+        us[3 * i + 2] = d;
+    }
+    __syncthreads();
+    const int64_t m = m0 + tid;
+    if (m >= S.n_in) return;
+    float acc = 0.0f;
+    for (int t = 0; t < T; ++t) {
+        // tap j = t - T/2 + 1 reads u at m + j = m0 - T/2 + 1 + (tid + t)
+        const float4 a = us[3 * (tid + t)], b = us[3 * (tid + t) + 1], d = us[3 * (tid + t) + 2];
+        acc = fmaf(c[0 * T + t], a.x, acc);
+        acc = fmaf(c[1 * T + t], a.y, acc);
+        acc = fmaf(c[2 * T + t], a.z, acc);
+        acc = fmaf(c[3 * T + t], a.w, acc);
+        acc = fmaf(c[4 * T + t], b.x, acc);
+        acc = fmaf(c[5 * T + t], b.y, acc);
+        acc = fmaf(c[6 * T + t], b.z, acc);
+        acc = fmaf(c[7 * T + t], b.w, acc);
+        acc = fmaf(c[8 * T + t], d.x, acc);
+        acc = fmaf(c[9 * T + t], d.y, acc);
+        acc = fmaf(c[10 * T + t], d.z, acc);
+        acc = fmaf(c[11 * T + t], d.w, acc);
+    }
+    gx[S.x_off + m] = acc;
+}
+
+// Gain and delay adjoints, Farrow form: per image sample r = sum_k v_k s^k and
+// dr/ds by Horner's rule for value and derivative.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage* __restrict__ imgs,
+                                                          const DGroup* __restrict__ groups, int T,
+                                                          const Seg* __restrict__ seg,
+                                                          const int32_t* __restrict__ segK,
+                                                          const float* __restrict__ v, const float* __restrict__ gy,
+                                                          float ghat, float* __restrict__ dbar,
+                                                          float* __restrict__ gpart, int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    float4* vw = lds;
+    constexpr int WAVES = NT / 64;
+    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const DGroup G = groups[S.grp_begin + g];
+    const int64_t n0 = (int64_t)tile * NT;
+    const int64_t ws = n0 - G.dmax - 4;
+    const int W = NT + (G.dmax - G.dmin) + 9;
+    const int64_t plo = -T / 2, phi = S.n_in + T / 2;
+    const float4* vs = (const float4*)(v + S.v_off);
+    for (int p = tid; p < W; p += NT) {
+        const int64_t Pp = ws + p;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+        if (Pp >= plo && Pp < phi) {
+            a = vs[(Pp + T / 2) * 3];
+            b = vs[(Pp + T / 2) * 3 + 1];
+            c = vs[(Pp + T / 2) * 3 + 2];
+        }
+        vw[3 * p] = a;
+        vw[3 * p + 1] = b;
+        vw[3 * p + 2] = c;
+    }
+    __syncthreads();
+    const int64_t n = n0 + tid;
+    const bool valid = n < S.n_out;
+    const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
+    const int64_t nc = valid ? n : S.n_out - 1;
+    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
+    const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * WAVES;
+    float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * WAVES + wave;
+    int bad = 0;
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = I[ii];
+        int K;
+        float off, D;
+        delay_at(im, seg, segK, trk, nc, &K, &off, &D);
+        const int64_t P = nc - K;
+        const int p = (int)(P - ws);
+        const bool inb = p >= 0 && p < W;
+        if (valid && !inb) bad = 1;
+        float E = 0.0f, Db = 0.0f;
+        if (valid && inb && wy != 0.0f) {
+            const float s = 2.0f * off - 1.0f;
+            const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
+            const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+            float r = cf[kFarrowStride - 1], dr = 0.0f;
+#pragma unroll
+            for (int k = kFarrowStride - 2; k >= 0; --k) {
+                dr = fmaf(dr, s, r);
+                r = fmaf(r, s, cf[k]);
+            }
+            const float iD = __builtin_amdgcn_rcpf(D);
+            const float gain = im.gfac * iD;
+            E = wy * r * ghat * iD;
+            Db = wy * gain * fmaf(2.0f, dr, -r * iD);
+        }
+        if (valid) dout[(int64_t)ii * S.n_out] = Db;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, 64);
+        if (lane == 0) gout[(int64_t)ii * nrow] = E;
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+}
+
+template <int NT>
+static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, const DImage* d_imgs, const DGroup* d_groups,
+                                      const Seg* seg, const int32_t* segK, const float* d_coef, const float* v,
+                                      const float* gy, float ghat, float* upart, float* u, float* gx, float* dbar,
+                                      float* gpart, int32_t* d_status, hipStream_t st)
+{
+    if (gx) {
+        const int64_t npos = hs.n_in + taps;
+        const int ptiles = (int)((npos + NT - 1) / NT);
+        const size_t lds = (size_t)hs.window * sizeof(float);
+        auto ku = k_farrow_adj_u<NT>;
+        hipError_t e = hipFuncSetAttribute((const void*)ku, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ku, dim3((unsigned)ptiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics), dim3(NT), lds, st, hs,
+                           d_imgs, d_groups, taps, seg, segK, gy, upart, d_status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t nu = npos * kFarrowStride;
+        hipLaunchKernelGGL(k_farrow_u_reduce, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st, hs, taps, upart, u);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_farrow_corr, dim3((unsigned)((hs.n_in + 255) / 256)), dim3(256), 0, st, hs, taps, d_coef, u,
+                           gx);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (dbar) {
+        const size_t lds = farrow_lds_bytes(hs.window);
+        auto kt = k_farrow_adj_track<NT>;
+        hipError_t e = hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kt, dim3((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics), dim3(NT), lds, st,
+                           hs, d_imgs, d_groups, taps, seg, segK, v, gy, ghat, dbar, gpart, d_status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_farrow_adjoint(int nthreads, int taps, const DScene& hs, const DImage* d_imgs,
+                                 const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
+                                 const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
+                                 float* dbar, float* gpart, int32_t* d_status, hipStream_t st)
+{
+    if (nthreads == 1024)
+        return launch_farrow_adj_t<1024>(hs, taps, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u, gx, dbar,
+                                         gpart, d_status, st);
+    if (nthreads == 512)
+        return launch_farrow_adj_t<512>(hs, taps, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u, gx, dbar,
+                                        gpart, d_status, st);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace msim

@@ -801,7 +801,11 @@ size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, Adj
     const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
     const size_t gpts = ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics;
     const size_t waves = (size_t)P->threads / 64;
-    char* xp = take((size_t)d.n_mics * d.n_grp * d.n_tiles * d.window * sizeof(float));
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    const size_t npos = (size_t)(d.n_in + P->par.taps);
+    char* xp = take(farrow ? (size_t)d.n_mics * d.n_grp * npos * kFarrowStride * sizeof(float)
+                           : (size_t)d.n_mics * d.n_grp * d.n_tiles * d.window * sizeof(float));
+    char* uu = take(farrow ? npos * kFarrowStride * sizeof(float) : 0);
     char* db = take((size_t)d.n_mics * d.n_img * d.n_out * sizeof(float));
     char* gp = take((size_t)d.n_mics * d.n_tiles * waves * d.n_img * sizeof(float));
     char* ds = take(segs * sizeof(float4));
@@ -810,6 +814,7 @@ size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, Adj
     char* pr = take(reduce_partial_bytes(d));
     if (aw) {
         aw->xpart = (float*)xp;
+        aw->u = (float*)uu;
         aw->dbar = (float*)db;
         aw->gpart = (float*)gp;
         aw->dseg = (float4*)ds;
@@ -980,7 +985,7 @@ msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* b
     size_t m = 0;
     for (const DScene& d : P->scenes)
         m = std::max(m, with_grad ? carve_adj(P, d, nullptr, nullptr, nullptr, nullptr) : fwd_ws_bytes(P, d));
-    *bytes = m + (with_grad ? 0 : farrow_v_bytes(P));
+    *bytes = m + farrow_v_bytes(P);
     return MSIM_OK;
 }
 
@@ -1006,22 +1011,48 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
     if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
     for (int s = 0; s < P->n_scenes; ++s) {
         if (!P->grad_ok[s]) return fail(MSIM_E_UNSUPPORTED, "scene %d: adjoint LDS does not fit its delay groups", s);
-        if (P->par.fd_kind != MSIM_FD_TABLE) return fail(MSIM_E_UNSUPPORTED, "the adjoint is built for the table kernel");
         if (gsrc && P->scenes[s].src_knots > max_grad_knots())
             return fail(MSIM_E_UNSUPPORTED, "scene %d: more than %d source knots", s, max_grad_knots());
     }
     const int T = P->par.taps, L = P->par.table_phases;
     const float ghat = (float)(P->par.fs / (4.0 * kPi * P->par.c));
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    float* v = (float*)ws;                       // Farrow-filtered sources, all scenes
+    char* scratch = (char*)ws + farrow_v_bytes(P);
+    if (farrow && (gbeta || gsrc)) {
+        LaunchTimer t(P, kKindFilter, stream);
+        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, T, P->d_fcoef, x, v,
+                                  stream));
+    }
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
         FwdWs fw;
         AdjBufs aw;
         double* partial = nullptr;
-        carve_adj(P, d, (char*)ws, &fw, &aw, &partial);
+        carve_adj(P, d, scratch, &fw, &aw, &partial);
         {
             LaunchTimer t(P, kKindTracks, stream);
             HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, fw.seg, fw.segK,
                                  P->par.c, P->par.fs, P->par.delay_model, stream));
+        }
+        const bool want_src = gsrc && d.src_knots > 0;
+        if (farrow) {
+            {
+                LaunchTimer t(P, kKindAdjoint, stream);
+                HIP_OK(launch_farrow_adjoint(P->threads, T, d, P->d_images, P->d_groups, fw.seg, fw.segK, P->d_fcoef,
+                                             v, gy, ghat, aw.xpart, aw.u, gx, (gbeta || want_src) ? aw.dbar : nullptr,
+                                             aw.gpart, P->d_status, stream));
+            }
+            if (gbeta || want_src) {
+                LaunchTimer t(P, kKindParams, stream);
+                if (want_src)
+                    HIP_OK(launch_adj_params(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, aw.dbar,
+                                             aw.dseg, aw.pgc, aw.pga, P->par.c, P->par.fs, P->par.delay_model, 1,
+                                             stream));
+                HIP_OK(launch_reduce_params(P->d_scenes, s, d, P->d_images, aw.gpart, d.n_tiles * (P->threads / 64),
+                                            aw.pgc, aw.pga, partial, gbeta, want_src ? gsrc : nullptr, stream));
+            }
+            continue;
         }
         if (gx) {
             {
@@ -1032,7 +1063,6 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
             LaunchTimer t(P, kKindReduce, stream);
             HIP_OK(launch_reduce_x(d, P->d_groups, P->threads, T, aw.xpart, gx, stream));
         }
-        const bool want_src = gsrc && d.src_knots > 0;
         if (gbeta || want_src) {
             {
                 LaunchTimer t(P, kKindAdjoint, stream);

@@ -122,7 +122,9 @@ size_t synth_lds_bytes(int taps, int L, int window);
 // ---- adjoint launchers (msim_adjoint.hip) ----
 // Scratch of the adjoint of one scene (all carved from the caller's workspace).
 struct AdjBufs {
-    float* xpart;     // [mic][group][tile][window]: transpose-delay partial windows
+    float* xpart;     // table: [mic][group][tile][window], transpose-delay partial windows;
+                      // Farrow: [mic][group][position][12], per-group sums u_k
+    float* u;         // Farrow: [position][12], u_k summed over mics and groups
     float* dbar;      // [mic][image][n_out]: d loss / d D_i(n)
     float* gpart;     // [mic][tile * waves][image]: partial sums of d loss / d beta_i
     float4* dseg;     // [mic][segment]: Catmull-Rom transpose weights summed per segment
@@ -163,5 +165,9 @@ hipError_t launch_farrow_persistent(int nthreads, int n_wg, int window, int taps
                                     const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
                                     int32_t* ticket, const Seg* seg, const int32_t* segK, const float* v, float* part,
                                     int32_t* d_status, hipStream_t st);
+hipError_t launch_farrow_adjoint(int nthreads, int taps, const DScene& hs, const DImage* d_imgs,
+                                 const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
+                                 const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
+                                 float* dbar, float* gpart, int32_t* d_status, hipStream_t st);
 
 }  // namespace msim
