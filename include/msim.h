@@ -164,10 +164,14 @@ msim_status msim_forward_batched(msim_plan* plan, const float* x, float* y, void
                                  hipStream_t stream, int32_t use_graph);
 
 /* Launch shape: output samples per workgroup (512 or 1024), images per delay
- * group (0: chosen from the tile count), and the persistent grid size it implies. */
+ * group (0: chosen from the tile count), output samples per lane of the Farrow
+ * forward (1, 2 or 4; a lane's samples share one track segment, so every tier
+ * decimation must be 1 or a multiple of it; 0: one),
+ * and the persistent grid size it implies. */
 typedef struct {
     int32_t threads;
     int32_t group_cap;
+    int32_t outputs_per_lane;
     int32_t workgroups;   /* output only */
     double ms;            /* output only: the batched forward time that chose it */
 } msim_tuning;
@@ -179,8 +183,8 @@ msim_status msim_set_tuning(msim_plan* plan, const msim_tuning* t);
 msim_status msim_autotune_workspace_size(msim_plan* plan, size_t* bytes);
 /* Times the batched forward (direct launches, 3 runs after 1 warm-up) for each
  * launch shape that fits ws and keeps the fastest; the choice is read from and
- * appended to the JSON-lines file cache_path (may be NULL), keyed by table
- * shape, scene count, image count and output size.  Synchronises `stream`;
+ * appended to the JSON-lines file cache_path (may be NULL), keyed by the
+ * fractional-delay form, table shape, scene count, image count and output size.  Synchronises `stream`;
  * x and y are scratch for the timing runs (y is overwritten). */
 msim_status msim_autotune(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes,
                           hipStream_t stream, const char* cache_path, msim_tuning* best);

@@ -51,7 +51,8 @@ class Profile(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("group_cap", C.c_int32), ("workgroups", C.c_int32), ("ms", C.c_double)]
+    _fields_ = [("threads", C.c_int32), ("group_cap", C.c_int32), ("outputs_per_lane", C.c_int32),
+                ("workgroups", C.c_int32), ("ms", C.c_double)]
 
 
 # name -> (argtypes); every function returns msim_status (int) except msim_last_error

@@ -40,6 +40,59 @@ __device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knot
     for (int k = 0; k < 3; ++k) out[k] = P[3 * a + k] + lam * (P[3 * b + k] - P[3 * a + k]);
 }
 
+// Position and velocity of a trajectory at time t, and the index of the PWL
+// segment holding t (-1 before the first knot, n-1 after the last; 0 for circles).
+__device__ inline int traj_pos_vel_seg(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
+                                       double v[3])
+{
+    if (tr.kind == 1) {
+        double s, c;
+        sincos(tr.omega * t + tr.phase0, &s, &c);
+        p[0] = tr.center[0] + tr.radius * c;
+        p[1] = tr.center[1] + tr.radius * s;
+        p[2] = tr.center[2];
+        const double sp = tr.radius * tr.omega;
+        v[0] = -sp * s;
+        v[1] = sp * c;
+        v[2] = 0.0;
+        return 0;
+    }
+    const double* T = knots + tr.knot_off;
+    const double* P = knots + tr.pos_off;
+    const int n = tr.n_points;
+    if (n == 1 || t <= T[0] || t >= T[n - 1]) {
+        const int a = (n == 1 || t <= T[0]) ? 0 : n - 1;
+        for (int k = 0; k < 3; ++k) {
+            p[k] = P[3 * a + k];
+            v[k] = 0.0;
+        }
+        return (n == 1 || t <= T[0]) ? -1 : n - 1;
+    }
+    int a = 0;
+    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const double idt = 1.0 / (T[a + 1] - T[a]);
+    const double lam = (t - T[a]) * idt;
+    for (int k = 0; k < 3; ++k) {
+        const double dp = P[3 * (a + 1) + k] - P[3 * a + k];
+        p[k] = P[3 * a + k] + lam * dp;
+        v[k] = dp * idt;
+    }
+    return a;
+}
+
+// The PWL segment holding t, numbered as traj_pos_vel_seg does (0 for circles).
+__device__ inline int traj_seg(const DTraj& tr, const double* __restrict__ knots, double t)
+{
+    if (tr.kind == 1) return 0;
+    const double* T = knots + tr.knot_off;
+    const int n = tr.n_points;
+    if (n == 1 || t <= T[0]) return -1;
+    if (t >= T[n - 1]) return n - 1;
+    int a = 0;
+    while (a + 2 < n && t >= T[a + 1]) ++a;
+    return a;
+}
+
 __device__ inline double image_coord(int m, double L, double q)
 {
     return (m & 1) ? (double)(m + 1) * L - q : (double)m * L + q;

@@ -59,26 +59,32 @@ hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_
 
 size_t farrow_lds_bytes(int window) { return (size_t)window * kFarrowStride * sizeof(float); }
 
-// One output tile of one delay group for one mic, Farrow form: stages v_k over the
-// group's source-position window in LDS, then one output sample per lane sums the
-// group's images.  Ends with a barrier.
-template <int NT>
-__device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int tile, int mic, int T,
+// One output tile (TO samples) of one delay group for one mic, Farrow form:
+// stages v_k over the group's source-position window in LDS, then each of the
+// TO/RB lanes sums the group's images for RB consecutive outputs.  The RB
+// outputs of a lane share one track segment when the image is decimated (the
+// planner only picks RB > 1 when every decimation is a multiple of RB), so the
+// segment fetch and its index arithmetic are paid once per RB image samples.
+// `hi` selects Horner over all 12 stored coefficients (orders 10-11) instead of
+// the first 10.  Ends with a barrier.
+template <int TO, int RB>
+__device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int tile, int mic, int T, bool hi,
                                    const DImage* __restrict__ imgs, float4* vw, const Seg* __restrict__ seg,
                                    const int32_t* __restrict__ segK, const float* __restrict__ v,
                                    float* __restrict__ part, int32_t* __restrict__ status)
 {
+    constexpr int NT = TO / RB;
     const int tid = threadIdx.x;
-    const int64_t n0 = (int64_t)tile * NT;
-    const int64_t ws = n0 - G.dmax - 4;                 // source position of window slot 0
-    const int W = NT + (G.dmax - G.dmin) + 9;
-    const int64_t plo = -T / 2, phi = S.n_in + T / 2;    // positions with stored v
+    const int n0 = tile * TO;
+    const int ws = n0 - G.dmax - 4;                    // source position of window slot 0
+    const int W = TO + (G.dmax - G.dmin) + 9;
+    const int plo = -T / 2, phi = (int)S.n_in + T / 2;   // positions with stored v
     const float4* vs = (const float4*)(v + S.v_off);
     for (int p = tid; p < W; p += NT) {
-        const int64_t P = ws + p;
+        const int P = ws + p;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
         if (P >= plo && P < phi) {
-            const float4* q = vs + (P + T / 2) * 3;
+            const float4* q = vs + (int64_t)(P + T / 2) * 3;
             a = q[0];
             b = q[1];
             c = q[2];
@@ -89,88 +95,137 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
     }
     __syncthreads();
 
-    const int64_t n = n0 + tid;
-    if (n < S.n_out) {
-        const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic;
+    const int nf = n0 + RB * tid;                       // first output of this lane
+    const int n_out = (int)S.n_out;
+    if (nf < n_out) {
+        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
+        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
         const DImage* I = imgs + S.img_begin;
-        const float fn = (float)n + 0.5f;
-        float acc = 0.0f;
+        const float fn = (float)nf + 0.5f;
+        float acc[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[j] = 0.0f;
         int bad = 0;
-        auto seg_index = [&](const DImage& im, int* kout) {
-            int k = (int)(fn * im.invR);
-            k = min(max(k, 0), im.n_seg - 1);
-            *kout = k;
-            return trk + im.seg_off + k;
+        // Track data of the next image is fetched while the current one is summed;
+        // two buffers in turn, so no registers are copied between images.
+        auto fetch = [&](const DImage& im, Seg (&q)[RB], int (&K)[RB], int& kseg) {
+            if (im.R == 1) {
+#pragma unroll
+                for (int j = 0; j < RB; ++j) {
+                    const int k = min(nf + j, im.n_seg - 1);
+                    q[j] = sgm[im.seg_off + k];
+                    K[j] = sgk[im.seg_off + k];
+                }
+            } else {
+                const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+                q[0] = sgm[im.seg_off + k];
+                K[0] = sgk[im.seg_off + k];
+                kseg = k;
+            }
         };
-        DImage nim = I[G.img_begin];
-        int nk;
-        int64_t nsidx = seg_index(nim, &nk);
-        Seg nsg = seg[nsidx];
-        int nKs = segK[nsidx];
-        for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-            const DImage im = nim;
-            const int k = nk;
-            const Seg sg = nsg;
-            const int Ks = nKs;
-            if (ii + 1 < G.img_end) {
-                nim = I[ii + 1];
-                nsidx = seg_index(nim, &nk);
-                nsg = seg[nsidx];
-                nKs = segK[nsidx];
+        auto body = [&](const DImage& im, const Seg (&q)[RB], const int (&Kq)[RB], int kq) {
+            float d[RB];
+            int Ks[RB];
+            if (im.R == 1) {
+#pragma unroll
+                for (int j = 0; j < RB; ++j) {
+                    d[j] = q[j].a0;
+                    Ks[j] = Kq[j];
+                }
+            } else {
+                const Seg sg = q[0];
+                const float v0 = (float)(nf - __mul24(kq, im.R));
+#pragma unroll
+                for (int j = 0; j < RB; ++j) {
+                    const float vv = v0 + (float)j;
+                    d[j] = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+                    Ks[j] = Kq[0];
+                }
             }
-            const float vv = (float)(n - (int64_t)k * im.R);
-            const float d = sg.a0 + vv * (sg.b1 + vv * (sg.b2 + vv * sg.b3));
-            const float fl = floorf(d);
-            const int64_t P = n - (Ks + (int)fl);
-            if (!__any(P >= plo && P < phi)) continue;
-            const int p = (int)(P - ws);
-            if (p < 0 || p >= W) {
-                bad = 1;
-                continue;
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+                // positions outside the stored range read the window's zeros
+                const float fl = floorf(d[j]);
+                const int p = nf + j - (Ks[j] + (int)fl) - ws;
+                if ((unsigned)p >= (unsigned)W) {
+                    bad = 1;
+                    continue;
+                }
+                const float s = 2.0f * (d[j] - fl) - 1.0f;
+                const float4* vp = vw + __mul24(p, 3);
+                const float4 a = vp[0], b = vp[1];
+                float r;
+                if (hi) {
+                    const float4 c = vp[2];
+                    r = fmaf(c.w, s, c.z);
+                    r = fmaf(r, s, c.y);
+                    r = fmaf(r, s, c.x);
+                    r = fmaf(r, s, b.w);
+                } else {
+                    const float2 c = *(const float2*)&vp[2];
+                    r = fmaf(c.y, s, c.x);
+                    r = fmaf(r, s, b.w);
+                }
+                r = fmaf(r, s, b.z);
+                r = fmaf(r, s, b.y);
+                r = fmaf(r, s, b.x);
+                r = fmaf(r, s, a.w);
+                r = fmaf(r, s, a.z);
+                r = fmaf(r, s, a.y);
+                r = fmaf(r, s, a.x);
+                acc[j] = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)Ks[j] + d[j]), r, acc[j]);
             }
-            const float s = 2.0f * (d - fl) - 1.0f;
-            const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
-            float r = c.w;
-            r = fmaf(r, s, c.z);
-            r = fmaf(r, s, c.y);
-            r = fmaf(r, s, c.x);
-            r = fmaf(r, s, b.w);
-            r = fmaf(r, s, b.z);
-            r = fmaf(r, s, b.y);
-            r = fmaf(r, s, b.x);
-            r = fmaf(r, s, a.w);
-            r = fmaf(r, s, a.z);
-            r = fmaf(r, s, a.y);
-            r = fmaf(r, s, a.x);
-            acc = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)Ks + d), r, acc);
+        };
+        Seg qa[RB] = {}, qb[RB] = {};
+        int Ka[RB] = {}, Kb[RB] = {};
+        int ka = 0, kb = 0;
+        DImage ia = I[G.img_begin], ib;
+        fetch(ia, qa, Ka, ka);
+        int ii = G.img_begin;
+        for (; ii + 1 < G.img_end; ii += 2) {
+            ib = I[ii + 1];
+            fetch(ib, qb, Kb, kb);
+            body(ia, qa, Ka, ka);
+            if (ii + 2 < G.img_end) {
+                ia = I[ii + 2];
+                fetch(ia, qa, Ka, ka);
+            }
+            body(ib, qb, Kb, kb);
         }
+        if (ii < G.img_end) body(ia, qa, Ka, ka);
         if (bad) atomicOr(status, kStatusWindow);
-        part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
+        float* out = part + S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if (nf + j < n_out) out[nf + j] = acc[j];
     }
     __syncthreads();
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_farrow_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                    const DGroup* __restrict__ groups, int T,
-                                                    const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                                    const float* __restrict__ v, float* __restrict__ part,
-                                                    int32_t* __restrict__ status)
+template <int TO, int RB>
+__global__ __launch_bounds__(TO / RB) void k_farrow_fwd(DScene S, const DImage* __restrict__ imgs,
+                                                         const DGroup* __restrict__ groups, int T, int hi,
+                                                         const Seg* __restrict__ seg,
+                                                         const int32_t* __restrict__ segK,
+                                                         const float* __restrict__ v, float* __restrict__ part,
+                                                         int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     const int g = blockIdx.y;
-    farrow_tile<NT>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, imgs, lds, seg, segK, v, part, status);
+    farrow_tile<TO, RB>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, hi != 0, imgs, lds, seg, segK, v,
+                        part, status);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_farrow_persistent(const DScene* __restrict__ scenes,
-                                                           const DImage* __restrict__ imgs,
-                                                           const DGroup* __restrict__ groups, int T,
-                                                           const WorkItem* __restrict__ items, int n_items,
-                                                           int32_t* __restrict__ ticket, const Seg* __restrict__ seg,
-                                                           const int32_t* __restrict__ segK,
-                                                           const float* __restrict__ v, float* __restrict__ part,
-                                                           int32_t* __restrict__ status)
+template <int TO, int RB>
+__global__ __launch_bounds__(TO / RB) void k_farrow_persistent(const DScene* __restrict__ scenes,
+                                                                const DImage* __restrict__ imgs,
+                                                                const DGroup* __restrict__ groups, int T, int hi,
+                                                                const WorkItem* __restrict__ items, int n_items,
+                                                                int32_t* __restrict__ ticket,
+                                                                const Seg* __restrict__ seg,
+                                                                const int32_t* __restrict__ segK,
+                                                                const float* __restrict__ v, float* __restrict__ part,
+                                                                int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     __shared__ int s_item;
@@ -182,8 +237,8 @@ __global__ __launch_bounds__(NT) void k_farrow_persistent(const DScene* __restri
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        farrow_tile<NT>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, imgs, lds, seg, segK, v, part,
-                        status);
+        farrow_tile<TO, RB>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, hi != 0, imgs, lds, seg,
+                            segK, v, part, status);
     }
 }
 
@@ -192,56 +247,83 @@ __global__ void k_zero_ticket(int32_t* p)
     if (threadIdx.x == 0) p[0] = 0;
 }
 
-template <int NT>
-static hipError_t launch_farrow_fwd_t(const DScene& hs, int taps, const DImage* d_imgs, const DGroup* d_groups,
-                                      const Seg* seg, const int32_t* segK, const float* v, float* part,
-                                      int32_t* d_status, hipStream_t st)
+template <int TO, int RB>
+static hipError_t launch_farrow_fwd_t(const DScene& hs, int taps, int hi, const DImage* d_imgs,
+                                      const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v,
+                                      float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(hs.window);
-    auto kern = k_farrow_fwd<NT>;
+    auto kern = k_farrow_fwd<TO, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, taps, seg, segK, v, part, d_status);
+    hipLaunchKernelGGL(kern, grid, dim3(TO / RB), lds, st, hs, d_imgs, d_groups, taps, hi, seg, segK, v, part,
+                       d_status);
     return hipGetLastError();
 }
 
-template <int NT>
-static hipError_t launch_farrow_pers_t(int n_wg, int window, int taps, const DScene* d_scenes, const DImage* d_imgs,
-                                       const DGroup* d_groups, const WorkItem* items, int n_items, int32_t* ticket,
-                                       const Seg* seg, const int32_t* segK, const float* v, float* part,
-                                       int32_t* d_status, hipStream_t st)
+template <int TO, int RB>
+static hipError_t launch_farrow_pers_t(int n_wg, int window, int taps, int hi, const DScene* d_scenes,
+                                       const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items,
+                                       int n_items, int32_t* ticket, const Seg* seg, const int32_t* segK,
+                                       const float* v, float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(window);
-    auto kern = k_farrow_persistent<NT>;
+    auto kern = k_farrow_persistent<TO, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, d_scenes, d_imgs, d_groups, taps, items, n_items,
-                       ticket, seg, segK, v, part, d_status);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, d_scenes, d_imgs, d_groups, taps, hi, items,
+                       n_items, ticket, seg, segK, v, part, d_status);
     return hipGetLastError();
 }
 
-hipError_t launch_farrow_fwd(int nthreads, int taps, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                             const Seg* seg, const int32_t* segK, const float* v, float* part, int32_t* d_status,
-                             hipStream_t st)
+// Outputs per lane the Farrow forward may use: every decimation must be 1 or a
+// multiple of it (so a lane's outputs share a segment), and tiles must split evenly.
+int farrow_outputs_per_lane(const int32_t* decim, int n_tiers)
 {
-    if (nthreads == 1024) return launch_farrow_fwd_t<1024>(hs, taps, d_imgs, d_groups, seg, segK, v, part, d_status, st);
-    if (nthreads == 512) return launch_farrow_fwd_t<512>(hs, taps, d_imgs, d_groups, seg, segK, v, part, d_status, st);
+    for (int rb : {4, 2}) {
+        bool ok = true;
+        for (int t = 0; t < n_tiers; ++t) ok = ok && (decim[t] == 1 || decim[t] % rb == 0);
+        if (ok) return rb;
+    }
+    return 1;
+}
+
+hipError_t launch_farrow_fwd(int nthreads, int rb, int taps, int order, const DScene& hs, const DImage* d_imgs,
+                             const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v, float* part,
+                             int32_t* d_status, hipStream_t st)
+{
+    const int hi = order > 9;
+#define MSIM_CALL(TO, RB) \
+    launch_farrow_fwd_t<TO, RB>(hs, taps, hi, d_imgs, d_groups, seg, segK, v, part, d_status, st)
+    if (nthreads == 1024 && rb == 4) return MSIM_CALL(1024, 4);
+    if (nthreads == 1024 && rb == 2) return MSIM_CALL(1024, 2);
+    if (nthreads == 1024 && rb == 1) return MSIM_CALL(1024, 1);
+    if (nthreads == 512 && rb == 4) return MSIM_CALL(512, 4);
+    if (nthreads == 512 && rb == 2) return MSIM_CALL(512, 2);
+    if (nthreads == 512 && rb == 1) return MSIM_CALL(512, 1);
+#undef MSIM_CALL
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_farrow_persistent(int nthreads, int n_wg, int window, int taps, const DScene* d_scenes,
-                                    const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
-                                    int32_t* ticket, const Seg* seg, const int32_t* segK, const float* v, float* part,
-                                    int32_t* d_status, hipStream_t st)
+hipError_t launch_farrow_persistent(int nthreads, int rb, int n_wg, int window, int taps, int order,
+                                    const DScene* d_scenes, const DImage* d_imgs, const DGroup* d_groups,
+                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
+                                    const int32_t* segK, const float* v, float* part, int32_t* d_status,
+                                    hipStream_t st)
 {
-    if (nthreads == 1024)
-        return launch_farrow_pers_t<1024>(n_wg, window, taps, d_scenes, d_imgs, d_groups, items, n_items, ticket, seg,
-                                          segK, v, part, d_status, st);
-    if (nthreads == 512)
-        return launch_farrow_pers_t<512>(n_wg, window, taps, d_scenes, d_imgs, d_groups, items, n_items, ticket, seg,
-                                         segK, v, part, d_status, st);
+    const int hi = order > 9;
+#define MSIM_CALL(TO, RB)                                                                                    \
+    launch_farrow_pers_t<TO, RB>(n_wg, window, taps, hi, d_scenes, d_imgs, d_groups, items, n_items, ticket, \
+                                 seg, segK, v, part, d_status, st)
+    if (nthreads == 1024 && rb == 4) return MSIM_CALL(1024, 4);
+    if (nthreads == 1024 && rb == 2) return MSIM_CALL(1024, 2);
+    if (nthreads == 1024 && rb == 1) return MSIM_CALL(1024, 1);
+    if (nthreads == 512 && rb == 4) return MSIM_CALL(512, 4);
+    if (nthreads == 512 && rb == 2) return MSIM_CALL(512, 2);
+    if (nthreads == 512 && rb == 1) return MSIM_CALL(512, 1);
+#undef MSIM_CALL
     return hipErrorInvalidValue;
 }
 

@@ -191,7 +191,8 @@ msim_status check_scene(const msim_scene& s, const msim_params* p, int idx)
     if (s.n_mics < 1 || !s.mic_offset) return fail(MSIM_E_INVALID_ARG, "scene %d: needs >= 1 mic", idx);
     if (s.max_order < 0 || s.max_order > 64) return fail(MSIM_E_INVALID_ARG, "scene %d: max_order in 0..64", idx);
     if (s.n_in < 1 || s.n_out < 1) return fail(MSIM_E_INVALID_ARG, "scene %d: n_in and n_out must be >= 1", idx);
-    if (s.n_out > kMaxOut) return fail(MSIM_E_UNSUPPORTED, "scene %d: n_out above 2^23", idx);
+    if (s.n_out > kMaxOut || s.n_in > kMaxOut)
+        return fail(MSIM_E_UNSUPPORTED, "scene %d: n_in or n_out above 2^23", idx);
     msim_status st;
     if ((st = check_traj(s.src, s.size, p->c, "source")) != MSIM_OK) return st;
     if ((st = check_traj(s.rcv, s.size, p->c, "receiver")) != MSIM_OK) return st;
@@ -292,7 +293,10 @@ void image_interval(int m, double L, double lo, double hi, double* out_lo, doubl
 struct msim_plan {
     msim_params par{};
     int n_scenes = 0;
-    int threads = 1024;                   // outputs per workgroup
+    int threads = 1024;                   // outputs per workgroup (the tile)
+    int farrow_rb = 1;                    // outputs per lane of the Farrow forward (one by default:
+    int farrow_rb_max = 1;                //   occupancy wins over shared segment fetches), and the
+                                          //   largest the tier decimations allow
     std::vector<DScene> scenes;           // host copies
     std::vector<DImage> images;
     std::vector<DGroup> groups;
@@ -585,7 +589,7 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
         for (int w = 0; w < 6; ++w) di.hits[w] = (int8_t)h.hits[w];
         di.run_off = (int32_t)runs;
         seg += di.n_seg;
-        runs += (di.n_seg + kTrackRun - 1) / kTrackRun;
+        runs += (di.n_seg + track_block_segs(di.R) - 1) / track_block_segs(di.R);
         P->images.push_back(di);
     }
     d.runs_per_mic = runs;
@@ -715,7 +719,8 @@ msim_status regroup(msim_plan* P)
     P->items.resize(it.size());
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
     const size_t lds = P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L, wmax);
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / NT, kLdsLimit / lds));
+    const int wg_threads = P->par.fd_kind == MSIM_FD_FARROW ? NT / P->farrow_rb : NT;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / wg_threads, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
     P->graph_valid = false;
     return MSIM_OK;
@@ -888,6 +893,7 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         if ((st = check_scene(scenes[s], p, s)) != MSIM_OK) return st;
     msim_plan* P = new msim_plan();
     P->par = *p;
+    P->farrow_rb_max = farrow_outputs_per_lane(p->tier_decim, p->n_tiers);
     P->n_scenes = n_scenes;
     int64_t xo = 0, yo = 0;
     for (int s = 0; s < n_scenes; ++s) {
@@ -1111,8 +1117,8 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
         {
             LaunchTimer t(P, kKindSynth, stream);
             if (farrow)
-                HIP_OK(launch_farrow_fwd(P->threads, P->par.taps, d, P->d_images, P->d_groups, w.seg, w.segK, v, w.part,
-                                         P->d_status, stream));
+                HIP_OK(launch_farrow_fwd(P->threads, P->farrow_rb, P->par.taps, P->par.farrow_order, d, P->d_images,
+                                         P->d_groups, w.seg, w.segK, v, w.part, P->d_status, stream));
             else
                 HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
                                         P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status, stream));
@@ -1217,7 +1223,8 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
     {
         LaunchTimer t(P, kKindSynth, st);
         if (farrow)
-            HIP_OK(launch_farrow_persistent(P->threads, P->b_wgs, P->b_window, P->par.taps, P->d_scenes_b,
+            HIP_OK(launch_farrow_persistent(P->threads, P->farrow_rb, P->b_wgs, P->b_window, P->par.taps,
+                                            P->par.farrow_order, P->d_scenes_b,
                                             P->d_images, P->d_groups, P->d_items, (int)P->items.size(), w.ticket,
                                             w.seg, w.segK, w.v, w.part, P->d_status, st));
         else
@@ -1251,12 +1258,12 @@ std::string tune_key(const msim_plan* P)
     int64_t imgs = 0;
     for (int64_t v : P->n_img) imgs += v;
     char buf[256];
-    snprintf(buf, sizeof buf, "gfx950/T%d/L%d/S%d/I%lld/Y%lld", P->par.taps, P->par.table_phases, P->n_scenes,
-             (long long)imgs, (long long)P->y_total);
+    snprintf(buf, sizeof buf, "gfx950/F%d/M%d/T%d/L%d/S%d/I%lld/Y%lld", P->par.fd_kind, P->par.farrow_order,
+             P->par.taps, P->par.table_phases, P->n_scenes, (long long)imgs, (long long)P->y_total);
     return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* threads, int* cap)
+bool cache_lookup(const char* path, const std::string& key, int* threads, int* cap, int* rb)
 {
     if (!path) return false;
     FILE* f = fopen(path, "r");
@@ -1265,12 +1272,14 @@ bool cache_lookup(const char* path, const std::string& key, int* threads, int* c
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[256];
-        int t = 0, c = 0;
-        // {"key": "...", "threads": N, "group_cap": N, ...}
-        if (sscanf(line, " {\"key\": \"%255[^\"]\", \"threads\": %d, \"group_cap\": %d", k, &t, &c) == 3 &&
-            key == k && (t == 512 || t == 1024) && c >= 0) {
+        int t = 0, c = 0, r = 0;
+        // {"key": "...", "threads": N, "group_cap": N, "outputs_per_lane": N, ...}
+        if (sscanf(line, " {\"key\": \"%255[^\"]\", \"threads\": %d, \"group_cap\": %d, \"outputs_per_lane\": %d",
+                   k, &t, &c, &r) == 4 &&
+            key == k && (t == 512 || t == 1024) && c >= 0 && (r == 1 || r == 2 || r == 4)) {
             *threads = t;
             *cap = c;
+            *rb = r;
             found = true;
         }
     }
@@ -1333,6 +1342,7 @@ msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
     if (!P || !out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     out->threads = P->threads;
     out->group_cap = P->group_cap;
+    out->outputs_per_lane = P->farrow_rb;
     out->workgroups = P->b_wgs;
     out->ms = 0.0;
     return MSIM_OK;
@@ -1343,13 +1353,20 @@ msim_status msim_set_tuning(msim_plan* P, const msim_tuning* t)
     if (!P || !t) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     if (t->threads != 512 && t->threads != 1024) return fail(MSIM_E_INVALID_ARG, "threads must be 512 or 1024");
     if (t->group_cap < 0) return fail(MSIM_E_INVALID_ARG, "group_cap must be >= 0");
-    const int ot = P->threads, oc = P->group_cap;
+    const int rb = t->outputs_per_lane == 0 ? 1 : t->outputs_per_lane;
+    if (rb != 1 && rb != 2 && rb != 4) return fail(MSIM_E_INVALID_ARG, "outputs_per_lane must be 0, 1, 2 or 4");
+    if (P->farrow_rb_max % rb != 0)
+        return fail(MSIM_E_INVALID_ARG, "outputs_per_lane %d: the tier decimations allow at most %d", rb,
+                    P->farrow_rb_max);
+    const int ot = P->threads, oc = P->group_cap, orb = P->farrow_rb;
     P->threads = t->threads;
     P->group_cap = t->group_cap;
+    P->farrow_rb = rb;
     msim_status st = regroup(P);
     if (st != MSIM_OK) {
         P->threads = ot;
         P->group_cap = oc;
+        P->farrow_rb = orb;
         regroup(P);
         return st;
     }
@@ -1380,37 +1397,41 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
 {
     if (!P || !x || !y || !ws) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     const std::string key = tune_key(P);
-    int bt = 0, bc = 0;
+    int bt = 0, bc = 0, brb = 1;
     double best = 1e300;
-    if (!cache_lookup(cache_path, key, &bt, &bc)) {
+    if (!cache_lookup(cache_path, key, &bt, &bc, &brb)) {
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
         const bool prof = P->profiling;
         P->profiling = false;
         for (int t : kTuneThreads)
-            for (int c : kTuneCaps) {
-                P->threads = t;
-                P->group_cap = c;
-                if (regroup(P) != MSIM_OK || carve_batched(P, nullptr, nullptr) > ws_bytes) continue;
-                msim_status st = upload_layout(P);
-                if (st != MSIM_OK) return st;
-                BatchWs w;
-                carve_batched(P, (char*)ws, &w);
-                if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
-                HIP_OK(hipEventRecord(e0, stream));
-                for (int r = 0; r < 3; ++r)
+            for (int c : kTuneCaps)
+                for (int rb : {1, 2, 4}) {
+                    if (P->farrow_rb_max % rb != 0 || (P->par.fd_kind != MSIM_FD_FARROW && rb != 1)) continue;
+                    P->threads = t;
+                    P->group_cap = c;
+                    P->farrow_rb = rb;
+                    if (regroup(P) != MSIM_OK || carve_batched(P, nullptr, nullptr) > ws_bytes) continue;
+                    msim_status st = upload_layout(P);
+                    if (st != MSIM_OK) return st;
+                    BatchWs w;
+                    carve_batched(P, (char*)ws, &w);
                     if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
-                HIP_OK(hipEventRecord(e1, stream));
-                HIP_OK(hipEventSynchronize(e1));
-                float ms = 0.0f;
-                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms / 3.0 < best) {
-                    best = ms / 3.0;
-                    bt = t;
-                    bc = c;
+                    HIP_OK(hipEventRecord(e0, stream));
+                    for (int r = 0; r < 3; ++r)
+                        if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
+                    HIP_OK(hipEventRecord(e1, stream));
+                    HIP_OK(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms / 3.0 < best) {
+                        best = ms / 3.0;
+                        bt = t;
+                        bc = c;
+                        brb = rb;
+                    }
                 }
-            }
         P->profiling = prof;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1418,13 +1439,13 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
         if (cache_path) {
             FILE* f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"group_cap\": %d, \"ms\": %.4f}\n", key.c_str(), bt,
-                        bc, best);
+                fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"group_cap\": %d, \"outputs_per_lane\": %d, "
+                        "\"ms\": %.4f}\n", key.c_str(), bt, bc, brb, best);
                 fclose(f);
             }
         }
     }
-    msim_tuning t{bt, bc, 0, best < 1e299 ? best : 0.0};
+    msim_tuning t{bt, bc, brb, 0, best < 1e299 ? best : 0.0};
     msim_status st = msim_set_tuning(P, &t);
     if (st != MSIM_OK) return st;
     if (best_out) {

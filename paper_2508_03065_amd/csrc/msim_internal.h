@@ -36,7 +36,7 @@ struct DScene {
     int32_t grp_begin;    // this scene's delay groups
     int32_t n_grp;
     int64_t seg_per_mic;  // track segments of one mic (sum over images)
-    int64_t runs_per_mic; // track-kernel runs of one mic
+    int64_t runs_per_mic; // track-kernel blocks of one mic
     int32_t n_tiles;
     int32_t window;       // LDS source window (positions) the plan sized for this scene
     double beta[6];       // wall coefficients (for d/dbeta)
@@ -68,14 +68,20 @@ struct DImage {
     int32_t n_seg;        // ceil(n_out / R)
     int8_t hits[6];       // reflections on each wall (beta_i = prod beta_w^hits_w)
     int8_t pad[2];
-    int32_t run_off;      // first track run (kTrackRun segments) within one mic
+    int32_t run_off;      // first track-kernel block within one mic
 };
 
 // Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
 constexpr int kFarrowStride = 12;
 
-// Grid segments one thread of the track kernel walks in time order.
-constexpr int kTrackRun = 32;
+// A track-kernel block: kTrackThreads threads, each solving kTrackWalk
+// consecutive grid points in time order.  A block emits every segment of an
+// audio-rate image (R = 1) it solves, and all but three of a decimated image's,
+// whose cubics also need the next two grid points and the one before.
+constexpr int kTrackThreads = 256;
+constexpr int kTrackWalk = 4;
+constexpr int kTrackPoints = kTrackThreads * kTrackWalk;
+__host__ __device__ constexpr int track_block_segs(int R) { return R == 1 ? kTrackPoints : kTrackPoints - 3; }
 
 // Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
 // samples, are bounded by [dmin, dmax] for every mic at every time.
@@ -158,13 +164,15 @@ int max_grad_knots();
 size_t farrow_lds_bytes(int window);
 hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_t* d_vprefix, int64_t total, int taps,
                               const float* d_coef, const float* x, float* v, hipStream_t st);
-hipError_t launch_farrow_fwd(int nthreads, int taps, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                             const Seg* seg, const int32_t* segK, const float* v, float* part, int32_t* d_status,
-                             hipStream_t st);
-hipError_t launch_farrow_persistent(int nthreads, int n_wg, int window, int taps, const DScene* d_scenes,
-                                    const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
-                                    int32_t* ticket, const Seg* seg, const int32_t* segK, const float* v, float* part,
-                                    int32_t* d_status, hipStream_t st);
+int farrow_outputs_per_lane(const int32_t* decim, int n_tiers);
+hipError_t launch_farrow_fwd(int nthreads, int rb, int taps, int order, const DScene& hs, const DImage* d_imgs,
+                             const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v, float* part,
+                             int32_t* d_status, hipStream_t st);
+hipError_t launch_farrow_persistent(int nthreads, int rb, int n_wg, int window, int taps, int order,
+                                    const DScene* d_scenes, const DImage* d_imgs, const DGroup* d_groups,
+                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
+                                    const int32_t* segK, const float* v, float* part, int32_t* d_status,
+                                    hipStream_t st);
 hipError_t launch_farrow_adjoint(int nthreads, int taps, const DScene& hs, const DImage* d_imgs,
                                  const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
                                  const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,

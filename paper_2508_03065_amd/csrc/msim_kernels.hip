@@ -18,47 +18,77 @@ namespace msim {
 
 // ------------------------------------------------------------------- tracks
 
-// Newton's method for the retarded delay from a guess, at reception time t for
-// mic position r: the root of f(tau) = tau - |p_i(t - tau) - r| / c, with
-// f' = 1 + u . S p'(t - tau) / c in [0.9, 1.1].  Stops once a step is below
-// 1e-9 s: the quadratic convergence leaves an error far below that step (at
-// most about 1e-11 s where a step straddles a kink of the path).
-__device__ inline double newton_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
-                                    const double r[3], double t, double inv_c, double tau)
+// Distance term of the retarded-delay equation at emission time te: returns
+// |p_i(te) - r| and sets ev = (p_i(te) - r) . S p'(te) and the PWL segment of te.
+__device__ __forceinline__ double image_dist(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                    const double r[3], double te, double* ev, int* seg)
+{
+    double q[3], v[3];
+    *seg = traj_pos_vel_seg(S.src, knots, te, q, v);
+    double d2 = 0.0, e_v = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
+        d2 += e * e;
+        e_v += e * ((m[a] & 1) ? -v[a] : v[a]);
+    }
+    *ev = e_v;
+    return sqrt(d2);
+}
+
+// Retarded delay at reception time t for mic position r: the root of
+// f(tau) = tau - |p_i(t - tau) - r| / c, by Newton's method from `tau`
+// (f' = 1 + u . S p'(t - tau) / c, in [0.9, 1.1] for speeds below c/10).  A step
+// below 1e-9 s ends it; so does one below 1e-5 s whose emission time stayed on
+// the same piece of the path: the error left is then the curvature of
+// |p_i(t - tau) - r| (below 0.02 / s for the validated speeds and distances)
+// times the step squared, under 1e-11 s.
+__device__ __forceinline__ double newton_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                    const double r[3], double t, double c, double tau)
 {
     for (int it = 0; it < 30; ++it) {
-        double q[3], v[3];
-        traj_pos_vel(S.src, knots, t - tau, q, v);
-        double d2 = 0.0, ev = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
-            d2 += e * e;
-            ev += e * ((m[a] & 1) ? -v[a] : v[a]);
-        }
-        const double d = sqrt(d2);
-        const double step = (tau - d * inv_c) / (1.0 + ev * inv_c / d);
+        double ev;
+        int sg0;
+        const double d = image_dist(S, m, knots, r, t - tau, &ev, &sg0);
+        const double step = (c * tau - d) * d / (c * d + ev);
         tau -= step;
-        if (fabs(step) <= 1e-9) break;
+        const double as = fabs(step);
+        if (as <= 1e-9) break;
+        if (as <= 1e-5 && traj_seg(S.src, knots, t - tau) == sg0) break;
     }
     return tau;
 }
 
-// One thread per (mic, image, run of kTrackRun grid segments).  The thread walks
-// the delay grid of its run in time order -- kR for k = k0 .. k1-1 at the audio
-// rate (R = 1), k0-1 .. k1+1 otherwise -- solving each delay from the linear
-// extrapolation of the two before, and emits segment k as soon as the four
-// delays (k-1)R .. (k+2)R of its Catmull-Rom cubic are known.  Segment k covers
-// outputs [kR, (k+1)R): D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)), integer
-// base K and FP32 offsets.  With grid != NULL the delays the thread owns are
-// also stored (grid index k+1 within the image's n_seg+3 slots), for the adjoint.
-__device__ inline void track_run(const DScene& S, int64_t gid, const DImage* __restrict__ imgs,
-                                 const double* __restrict__ knots, const double* __restrict__ mics,
-                                 double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK,
-                                 double c, double fs, int model)
+// First guess of the retarded delay: the equation solved with the image moving on
+// its tangent at time t, c tau = d - (u . S p'(t)) tau, which is off by
+// O((v/c)^2) tau.  Instantaneous model: d / c exactly.
+__device__ __forceinline__ double first_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                   const double r[3], double t, double c, int model)
+{
+    double ev;
+    int sg;
+    const double d = image_dist(S, m, knots, r, t, &ev, &sg);
+    return model == 1 ? d / c : d * d / (c * d + ev);
+}
+
+// One block of kTrackThreads threads per (mic, image, block of segments); thread
+// j solves the kTrackWalk consecutive grid points 4j .. 4j+3 of the block in time
+// order, each from the linear extrapolation of the two before (the first from
+// first_tau), the block shares the delays through LDS and writes its segments
+// with consecutive threads on consecutive segments.  Segment k covers outputs
+// [kR, (k+1)R): D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)), integer base K and
+// FP32 offsets: the exact delay at the audio rate (R = 1), else the uniform
+// Catmull-Rom cubic through the grid delays D_{k-1} .. D_{k+2} (grid point g at
+// output gR, g = -1 .. n_seg + 1).  With grid != NULL the block also stores the
+// delays it owns (grid index g + 1 within the image's n_seg + 3 slots), for the
+// adjoint.
+__device__ __forceinline__ void track_block(const DScene& S, int64_t bid, const DImage* __restrict__ imgs,
+                                   const double* __restrict__ knots, const double* __restrict__ mics,
+                                   double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK,
+                                   double c, double fs, int model, double* Dl)
 {
     const int64_t per_mic = S.runs_per_mic;
-    const int mic = (int)(gid / per_mic);
-    const int64_t ridx = gid - (int64_t)mic * per_mic;
+    const int mic = (int)(bid / per_mic);
+    const int64_t ridx = bid - (int64_t)mic * per_mic;
     const DImage* I = imgs + S.img_begin;
     int lo = 0, hi = S.n_img - 1;
     while (lo < hi) {
@@ -67,65 +97,75 @@ __device__ inline void track_run(const DScene& S, int64_t gid, const DImage* __r
     }
     const int ii = lo;
     const DImage im = I[ii];
-    const int64_t k0 = (ridx - im.run_off) * kTrackRun;
-    const int64_t k1 = min((int64_t)im.n_seg, k0 + kTrackRun);
     const int R = im.R;
-    const double inv_c = 1.0 / c;
-    const int64_t gfirst = (R == 1) ? k0 : k0 - 1;
+    const int per = track_block_segs(R);
+    const int64_t k0 = (ridx - im.run_off) * per;
+    const int64_t k1 = min((int64_t)im.n_seg, k0 + per);
+    const int64_t gbase = (R == 1) ? k0 : k0 - 1;       // grid point of LDS slot 0
     const int64_t glast = (R == 1) ? k1 - 1 : k1 + 1;
     const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic + im.seg_off;
-    double* gout = grid ? grid + S.grid_base + (int64_t)mic * (S.seg_per_mic + 3 * (int64_t)S.n_img) +
-                              im.seg_off + 3 * (int64_t)ii + 1
+    double* gout = grid ? grid + S.grid_base + (int64_t)mic * (S.seg_per_mic + 3 * (int64_t)S.n_img) + im.seg_off +
+                              3 * (int64_t)ii + 1
                         : nullptr;
-    double tp1 = 0.0, tp2 = 0.0;          // the two previous delays (s)
-    double D0 = 0.0, D1 = 0.0, D2 = 0.0;  // the three previous delays (samples)
-    for (int64_t g = gfirst; g <= glast; ++g) {
-        const double t = (double)(g * R) / fs;
-        double r[3];
-        mic_pos(S, knots, mics, mic, t, r);
-        double tau;
-        if (model == 1 || g == gfirst) {
-            tau = dist_to(S, im.m, knots, r, t) * inv_c;
-            if (model == 0) tau = newton_tau(S, im.m, knots, r, t, inv_c, tau);
-        } else {
-            const double guess = (g >= gfirst + 2) ? 2.0 * tp1 - tp2 : tp1;
-            tau = newton_tau(S, im.m, knots, r, t, inv_c, guess);
+    const double inv_fs = 1.0 / fs;
+    double tp1 = 0.0, tp2 = 0.0;
+    for (int w = 0; w < kTrackWalk; ++w) {
+        const int slot = kTrackWalk * (int)threadIdx.x + w;
+        const int64_t g = gbase + slot;
+        double D = 0.0;
+        if (g <= glast) {
+            const double t = (double)(g * R) * inv_fs;
+            double r[3];
+            mic_pos(S, knots, mics, mic, t, r);
+            double tau;
+            if (model == 1 || w == 0) {
+                tau = first_tau(S, im.m, knots, r, t, c, model);
+                if (model == 0) tau = newton_tau(S, im.m, knots, r, t, c, tau);
+            } else {
+                tau = newton_tau(S, im.m, knots, r, t, c, w >= 2 ? 2.0 * tp1 - tp2 : tp1);
+            }
+            tp2 = tp1;
+            tp1 = tau;
+            D = fs * tau;
+            if (gout) {
+                const bool own = (g >= k0 && g < k1) || (R > 1 && k0 == 0 && g < 0) ||
+                                 (R > 1 && k1 == im.n_seg && g >= k1);
+                if (own) gout[g] = D;
+            }
         }
-        tp2 = tp1;
-        tp1 = tau;
-        const double D = fs * tau;
-        const bool own = (g >= k0 && g < k1) || (k0 == 0 && g < 0) || (k1 == im.n_seg && g >= k1);
-        if (gout && own) gout[g] = D;
+        Dl[slot] = D;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < per; q += kTrackThreads) {
+        const int64_t k = k0 + q;
+        if (k >= k1) break;
         if (R == 1) {
+            const double D = Dl[q];
             const double Kd = floor(D);
-            seg[trk + g] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
-            segK[trk + g] = (int32_t)Kd;
-        } else if (g >= k0 + 2) {
-            // segment k = g - 2 from D_{k-1} = D0, D_k = D1, D_{k+1} = D2, D_{k+2} = D
-            const int64_t k = g - 2;
+            seg[trk + k] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
+            segK[trk + k] = (int32_t)Kd;
+        } else {
+            const double D0 = Dl[q], D1 = Dl[q + 1], D2 = Dl[q + 2], D3 = Dl[q + 3];
             const double Kd = floor(D1);
             const double a1 = 0.5 * (D2 - D0);
-            const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D);
-            const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D);
+            const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D3);
+            const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D3);
             const double iR = 1.0 / (double)R;
             seg[trk + k] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
             segK[trk + k] = (int32_t)Kd;
         }
-        D0 = D1;
-        D1 = D2;
-        D2 = D;
     }
 }
 
-__global__ __launch_bounds__(256) void k_tracks(const DScene* __restrict__ scenes, int scene,
-                                                const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                                const double* __restrict__ mics, double* __restrict__ grid,
-                                                Seg* __restrict__ seg, int32_t* __restrict__ segK, double c,
-                                                double fs, int model)
+__global__ __launch_bounds__(kTrackThreads) void k_tracks(const DScene* __restrict__ scenes, int scene,
+                                                          const DImage* __restrict__ imgs,
+                                                          const double* __restrict__ knots,
+                                                          const double* __restrict__ mics, double* __restrict__ grid,
+                                                          Seg* __restrict__ seg, int32_t* __restrict__ segK, double c,
+                                                          double fs, int model)
 {
-    const DScene& S = scenes[scene];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < S.runs_per_mic * S.n_mics) track_run(S, gid, imgs, knots, mics, grid, seg, segK, c, fs, model);
+    __shared__ double Dl[kTrackPoints];
+    track_block(scenes[scene], blockIdx.x, imgs, knots, mics, grid, seg, segK, c, fs, model, Dl);
 }
 
 // Last scene whose prefix start is <= i (prefix[0] = 0, ascending).
@@ -139,17 +179,19 @@ __device__ inline int scene_of(const int64_t* __restrict__ prefix, int n, int64_
     return lo;
 }
 
-// Batched form: one launch over every scene; prefix[s] is scene s's first run.
-__global__ __launch_bounds__(256) void k_tracks_all(const DScene* __restrict__ scenes, int n_scenes,
-                                                    const int64_t* __restrict__ prefix, int64_t total,
-                                                    const DImage* __restrict__ imgs, const double* __restrict__ knots,
-                                                    const double* __restrict__ mics, Seg* __restrict__ seg,
-                                                    int32_t* __restrict__ segK, double c, double fs, int model)
+// Batched form: one launch over every scene; prefix[s] is scene s's first block.
+__global__ __launch_bounds__(kTrackThreads) void k_tracks_all(const DScene* __restrict__ scenes, int n_scenes,
+                                                              const int64_t* __restrict__ prefix,
+                                                              const DImage* __restrict__ imgs,
+                                                              const double* __restrict__ knots,
+                                                              const double* __restrict__ mics, Seg* __restrict__ seg,
+                                                              int32_t* __restrict__ segK, double c, double fs,
+                                                              int model)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int s = scene_of(prefix, n_scenes, i);
-    track_run(scenes[s], i - prefix[s], imgs, knots, mics, nullptr, seg, segK, c, fs, model);
+    __shared__ double Dl[kTrackPoints];
+    const int64_t b = blockIdx.x;
+    const int s = scene_of(prefix, n_scenes, b);
+    track_block(scenes[s], b - prefix[s], imgs, knots, mics, nullptr, seg, segK, c, fs, model, Dl);
 }
 
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
@@ -158,8 +200,8 @@ hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, co
 {
     const int64_t n = hs.runs_per_mic * hs.n_mics;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tracks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d_scenes, scene, d_imgs,
-                       d_knots, d_mics, grid, seg, segK, c, fs, delay_model);
+    hipLaunchKernelGGL(k_tracks, dim3((unsigned)n), dim3(kTrackThreads), 0, st, d_scenes, scene, d_imgs, d_knots,
+                       d_mics, grid, seg, segK, c, fs, delay_model);
     return hipGetLastError();
 }
 
@@ -167,8 +209,9 @@ hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t
                              const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
                              int32_t* segK, double c, double fs, int delay_model, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tracks_all, dim3((unsigned)((run_total + 255) / 256)), dim3(256), 0, st, d_scenes,
-                       n_scenes, d_run_prefix, run_total, d_imgs, d_knots, d_mics, seg, segK, c, fs, delay_model);
+    if (run_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tracks_all, dim3((unsigned)run_total), dim3(kTrackThreads), 0, st, d_scenes, n_scenes,
+                       d_run_prefix, d_imgs, d_knots, d_mics, seg, segK, c, fs, delay_model);
     return hipGetLastError();
 }
 

@@ -184,8 +184,8 @@ class Plan:
         check(_lib.load().msim_get_tuning(self._ptr, C.byref(t)))
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
 
-    def set_tuning(self, threads: int, group_cap: int = 0):
-        t = _lib.Tuning(threads, group_cap, 0, 0.0)
+    def set_tuning(self, threads: int, group_cap: int = 0, outputs_per_lane: int = 0):
+        t = _lib.Tuning(threads, group_cap, outputs_per_lane, 0, 0.0)
         check(_lib.load().msim_set_tuning(self._ptr, C.byref(t)))
 
     def autotune(self, x: torch.Tensor, cache_path: Optional[str] = None, stream=None) -> dict:
