@@ -302,6 +302,7 @@ struct msim_plan {
     std::vector<DGroup> groups;
     std::vector<double> knots, mics;
     std::vector<float> table;             // float4 groups, flattened
+    std::vector<float> qtable;            // the forward's quadratic table, flattened
     std::vector<float> dtable;            // derivative table (L/2 phases), same layout
     std::vector<int64_t> n_img;
     int64_t src_grad_total = 0;           // knots in the packed d/dsource array
@@ -333,6 +334,7 @@ struct msim_plan {
     double* d_mics = nullptr;
     float4* d_table = nullptr;
     float4* d_dtable = nullptr;
+    float4* d_qtable = nullptr;
     std::vector<float> fcoef;             // Farrow coefficients [kFarrowStride][T]
     std::vector<int64_t> vpos_prefix;     // first Farrow source position of each scene
     int64_t vpos_total = 0;
@@ -438,8 +440,29 @@ void build_quads(std::vector<float>& out, int T, int L, double kbeta, double fc,
             }
 }
 
+// Quadratic-interpolation half table of the forward, grouped by tap quads: for
+// row r < Lq, three quads Y(r), Y(r+1) - Y(r), Y(r+2) - 2 Y(r+1) + Y(r) with
+// Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences taken in double).
+void build_qtable(std::vector<float>& out, int T, int Lq, double kbeta, double fc)
+{
+    const int NG = T / 8;
+    const double i0b = bessel_i0(kbeta);
+    out.assign((size_t)NG * Lq * 12, 0.0f);
+    for (int g = 0; g < NG; ++g)
+        for (int row = 0; row < Lq; ++row)
+            for (int e = 0; e < 4; ++e) {
+                double y[3];
+                for (int i = 0; i < 3; ++i) y[i] = fd_kernel((4 * g + e) + double(row + i) / Lq, T, kbeta, fc, i0b);
+                float* o = &out[(((size_t)g * Lq + row) * 3) * 4 + e];
+                o[0] = (float)y[0];
+                o[4] = (float)(y[1] - y[0]);
+                o[8] = (float)(y[2] - 2.0 * y[1] + y[0]);
+            }
+}
+
 void build_table(msim_plan* P)
 {
+    build_qtable(P->qtable, P->par.taps, P->par.table_phases / kQuadDiv, P->par.kaiser_beta, P->par.cutoff);
     build_quads(P->table, P->par.taps, P->par.table_phases, P->par.kaiser_beta, P->par.cutoff, false);
     // the derivative table is read only by the adjoint, at half the phase density
     build_quads(P->dtable, P->par.taps, P->par.table_phases / 2, P->par.kaiser_beta, P->par.cutoff, true);
@@ -626,7 +649,7 @@ msim_status regroup(msim_plan* P)
         bool grad_fit = true;
         auto fits = [&](int window) {
             if (P->par.fd_kind == MSIM_FD_FARROW) return farrow_lds_bytes(window) <= kLdsLimit;
-            if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
+            if (!grad_fit) return synth_lds_bytes(T, L / kQuadDiv, window) <= kLdsLimit;
             return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
                    adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
         };
@@ -718,7 +741,8 @@ msim_status regroup(msim_plan* P)
     std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     P->items.resize(it.size());
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
-    const size_t lds = P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L, wmax);
+    const size_t lds =
+        P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L / kQuadDiv, wmax);
     const int wg_threads = P->par.fd_kind == MSIM_FD_FARROW ? NT / P->farrow_rb : NT;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / wg_threads, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
@@ -925,14 +949,16 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
     }
-    std::vector<float4> tab4(P->table.size() / 4), dtab4(P->dtable.size() / 4);
+    std::vector<float4> tab4(P->table.size() / 4), dtab4(P->dtable.size() / 4), qtab4(P->qtable.size() / 4);
     std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
     std::memcpy(dtab4.data(), P->dtable.data(), P->dtable.size() * sizeof(float));
+    std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size() * sizeof(float));
     std::vector<int32_t> zero(1, 0);
     if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
         (st = upload(&P->d_dtable, dtab4)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
         (st = upload(&P->d_table, tab4)) != MSIM_OK || (st = upload(&P->d_status, zero)) != MSIM_OK ||
+        (st = upload(&P->d_qtable, qtab4)) != MSIM_OK ||
         (st = upload_layout(P)) != MSIM_OK) {
         msim_plan_destroy(P);
         return st;
@@ -957,6 +983,7 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_mics);
     (void)hipFree(P->d_table);
     (void)hipFree(P->d_dtable);
+    (void)hipFree(P->d_qtable);
     (void)hipFree(P->d_fcoef);
     (void)hipFree(P->d_vpos_prefix);
     (void)hipFree(P->d_status);
@@ -1120,8 +1147,9 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
                 HIP_OK(launch_farrow_fwd(P->threads, P->farrow_rb, P->par.taps, P->par.farrow_order, d, P->d_images,
                                          P->d_groups, w.seg, w.segK, v, w.part, P->d_status, stream));
             else
-                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_table,
-                                        P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status, stream));
+                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_qtable,
+                                        P->par.table_phases / kQuadDiv, w.seg, w.segK, x, w.part, P->d_status,
+                                        stream));
         }
         {
             LaunchTimer t(P, kKindReduce, stream);
@@ -1229,7 +1257,8 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
                                             w.seg, w.segK, w.v, w.part, P->d_status, st));
         else
             HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b,
-                                           P->d_images, P->d_groups, P->d_table, P->par.table_phases, P->d_items,
+                                           P->d_images, P->d_groups, P->d_qtable, P->par.table_phases / kQuadDiv,
+                                           P->d_items,
                                            (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status,
                                            st));
     }

@@ -123,7 +123,10 @@ hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window,
 hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
                              const float* part, float* y, hipStream_t st);
 
-size_t synth_lds_bytes(int taps, int L, int window);
+// The forward reads a quadratic-interpolation table of table_phases / kQuadDiv
+// phases; the adjoint reads linear-interpolation tables of table_phases phases.
+constexpr int kQuadDiv = 4;
+size_t synth_lds_bytes(int taps, int Lq, int window);
 
 // ---- adjoint launchers (msim_adjoint.hip) ----
 // Scratch of the adjoint of one scene (all carved from the caller's workspace).

@@ -217,35 +217,44 @@ hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t
 
 // -------------------------------------------------------------- forward synth
 
-// LDS: the half table of h(v) = h(-v), v in [0, T/2], sampled at v = r/L and
-// grouped by four taps: tab[g*(L+1) + row] = (h((4g+e) + row/L)), e = 0..3;
-// then the source window as overlapping quads xw[p] = x[ws+p .. ws+p+3].
-size_t synth_lds_bytes(int taps, int L, int window)
+// LDS: the forward's half table of h(v) = h(-v), v in [0, T/2], for quadratic
+// interpolation between Lq phases, grouped by four taps: for row r < Lq,
+//   tab[(g*Lq + r)*3 + 0] = Y(r),  [.. + 1] = Y(r+1) - Y(r),  [.. + 2] = Y(r+2) - 2 Y(r+1) + Y(r),
+// Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as overlapping
+// quads xw[p] = x[ws+p .. ws+p+3].
+size_t synth_lds_bytes(int taps, int Lq, int window)
 {
-    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) + (size_t)window * sizeof(float4);
+    return (size_t)(taps / 8) * (size_t)Lq * 3 * sizeof(float4) + (size_t)window * sizeof(float4);
 }
 
 // One output tile of one delay group for one mic: stages the group's source
 // window in LDS (the table must already be there), then one output sample per
 // lane sums every image of the group; writes the group's partial outputs.
-// Ends with a barrier, so the caller may restage LDS right after.
-template <int T, int NT>
+// The tap weights come from the quadratic table: with q = mu Lq = k + f, the
+// taps on the delay's near side (|u| = 4g+e + mu) read base row k at fraction f,
+// the mirrored ones (|u| = 4g+e + 1 - mu) base row Lq-1-k at fraction 1-f, and
+// both second-difference terms carry the same weight f (f - 1) / 2.  LC is Lq
+// when known at compile time (then every table read has an immediate offset),
+// else 0 and Lr is used.  Ends with a barrier, so the caller may restage LDS
+// right after.
+template <int T, int NT, int LC>
 __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int tile, int mic,
-                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int L,
+                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
                                   const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
 {
     constexpr int NG = T / 8;          // tap quads per side
-    const int rows = L + 1;
+    const int L = LC > 0 ? LC : Lr;
+    const int rows3 = 3 * L;
     const int tid = threadIdx.x;
-    const int64_t n0 = (int64_t)tile * NT;
-    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int n0 = tile * NT;
+    const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
 
     const float* xs = x + S.x_off;
-    const int64_t n_in = S.n_in;
+    const int n_in = (int)S.n_in;
     for (int p = tid; p < W; p += NT) {
-        const int64_t q = ws + p;
+        const int q = ws + p;
         float4 v;
         v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
         v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
@@ -255,81 +264,82 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
     }
     __syncthreads();
 
-    const int64_t n = n0 + tid;
-    if (n < S.n_out) {
-        const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic;
+    const int n = n0 + tid;
+    if (n < (int)S.n_out) {
+        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
+        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
         const DImage* I = imgs + S.img_begin;
         const float fn = (float)n + 0.5f;
         const float Lf = (float)L;
         float acc = 0.0f;
         int bad = 0;
 
-        // the next image's track segment is fetched while the current one is filtered
-        auto seg_index = [&](const DImage& im, int* kout) {
-            int k = (int)(fn * im.invR);
-            k = min(max(k, 0), im.n_seg - 1);
-            *kout = k;
-            return trk + im.seg_off + k;
+        // Track data of the next image is fetched while the current one is
+        // filtered; two buffers in turn, so no registers are copied between images.
+        auto fetch = [&](const DImage& im, Seg& q, int& K, int& kseg) {
+            const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+            q = sgm[im.seg_off + k];
+            K = sgk[im.seg_off + k];
+            kseg = k;
         };
-        DImage nim = I[G.img_begin];
-        int nk;
-        int64_t nsidx = seg_index(nim, &nk);
-        Seg nsg = seg[nsidx];
-        int nKs = segK[nsidx];
-        for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-            const DImage im = nim;
-            const int k = nk;
-            const Seg sg = nsg;
-            const int Ks = nKs;
-            if (ii + 1 < G.img_end) {
-                nim = I[ii + 1];
-                nsidx = seg_index(nim, &nk);
-                nsg = seg[nsidx];
-                nKs = segK[nsidx];
-            }
-            const float v = (float)(n - (int64_t)k * im.R);
-            const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
+        auto body = [&](const DImage& im, const Seg& sg, int Ks, int k) {
+            const float v = (float)(n - __mul24(k, im.R));
+            const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
             const float fl = floorf(d);
             const int K = Ks + (int)fl;
             // skip the image when no lane's taps reach a source sample
-            const int64_t xlo = n - K - T / 2, xhi = n - K + T / 2 - 1;
-            if (!__any(xhi >= 0 && xlo < n_in)) continue;
+            if (!__any(n - K + T / 2 - 1 >= 0 && n - K - T / 2 < n_in)) return;
+            const int p0 = n - K - ws;
+            if (p0 < T / 2 || p0 > W - T / 2 + 3) {
+                bad = 1;
+                return;
+            }
             const float mu = d - fl;
             const float gain = im.gfac * __builtin_amdgcn_rcpf((float)Ks + d);
             const float q = mu * Lf;
             const int kq = min((int)q, L - 1);
             const float f = q - (float)kq;
-            int p0 = (int)(n - K - ws);
-            if (p0 < T / 2 || p0 > W - T / 2 + 3) {
-                bad = 1;
-                continue;
-            }
-            const float4* tn = tab + kq;
-            const float4* tp = tab + (L - 1 - kq);
+            const float4* tn = tab + 3 * kq;
+            const float4* tp = tab + 3 * (L - 1 - kq);
             const float4* xq = xw + p0;
-            float A = 0.0f, B = 0.0f;
+            float A = 0.0f, B = 0.0f, Bm = 0.0f, C = 0.0f;
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
-                // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> rows kq (1-f), kq+1 (f)
+                // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> base row kq, fraction f
                 const float4 xn = xq[4 * gi];
-                const float4 P = tn[gi * rows];
-                const float4 Q = tn[gi * rows + 1];
-                A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
-                A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
-                A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
-                A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
+                const float4 Y = tn[gi * rows3], D1 = tn[gi * rows3 + 1], D2 = tn[gi * rows3 + 2];
+                A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(D2.x, xn.x, C);
+                A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(D2.y, xn.y, C);
+                A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(D2.z, xn.z, C);
+                A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(D2.w, xn.w, C);
                 // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
-                //   -> rows L-1-kq (weight f), L-kq (weight 1-f)
+                //   -> base row L-1-kq, fraction 1-f
                 const float4 xp = xq[-4 - 4 * gi];
-                const float4 P2 = tp[gi * rows];
-                const float4 Q2 = tp[gi * rows + 1];
-                B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
-                B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
-                B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
-                B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
+                const float4 Ym = tp[gi * rows3], E1 = tp[gi * rows3 + 1], E2 = tp[gi * rows3 + 2];
+                A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(E2.x, xp.w, C);
+                A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(E2.y, xp.z, C);
+                A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(E2.z, xp.y, C);
+                A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm); C = fmaf(E2.w, xp.x, C);
             }
-            acc = fmaf(gain, fmaf(f, B - A, A), acc);
+            const float s = fmaf(0.5f * f * (f - 1.0f), C, fmaf(1.0f - f, Bm, fmaf(f, B, A)));
+            acc = fmaf(gain, s, acc);
+        };
+        Seg qa{}, qb{};
+        int Ka = 0, Kb = 0, ka = 0, kb = 0;
+        DImage ia = I[G.img_begin], ib;
+        fetch(ia, qa, Ka, ka);
+        int ii = G.img_begin;
+        for (; ii + 1 < G.img_end; ii += 2) {
+            ib = I[ii + 1];
+            fetch(ib, qb, Kb, kb);
+            body(ia, qa, Ka, ka);
+            if (ii + 2 < G.img_end) {
+                ia = I[ii + 2];
+                fetch(ia, qa, Ka, ka);
+            }
+            body(ib, qb, Kb, kb);
         }
+        if (ii < G.img_end) body(ia, qa, Ka, ka);
         if (bad) atomicOr(status, kStatusWindow);
         part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
     }
@@ -337,13 +347,13 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
 }
 
 template <int T>
-__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int L)
+__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int Lq)
 {
-    const int n = (T / 8) * (L + 1);
+    const int n = (T / 8) * Lq * 3;
     for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = table[i];
 }
 
-template <int T, int NT>
+template <int T, int NT, int LC>
 __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
                                                    const DGroup* __restrict__ groups,
                                                    const float4* __restrict__ table, int L,
@@ -353,18 +363,18 @@ __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __rest
 {
     extern __shared__ float4 lds[];
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * (L + 1);
+    float4* xw = lds + (T / 8) * L * 3;
     load_table<T>(table, tab, L);
     const int g = blockIdx.y;
-    synth_tile<T, NT>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x, part,
-                      status);
+    synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
+                          part, status);
 }
 
 // Persistent form: a fixed grid of workgroups loads the table once, then takes
 // work items (scene, mic, tile, group), ordered by decreasing cost, from a
 // ticket counter until the list is exhausted.  Items write disjoint partial
 // outputs, so the result does not depend on which workgroup ran which item.
-template <int T, int NT>
+template <int T, int NT, int LC>
 __global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restrict__ scenes,
                                                           const DImage* __restrict__ imgs,
                                                           const DGroup* __restrict__ groups,
@@ -379,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restric
     extern __shared__ float4 lds[];
     __shared__ int s_item;
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * (L + 1);
+    float4* xw = lds + (T / 8) * L * 3;
     load_table<T>(table, tab, L);
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
@@ -389,8 +399,8 @@ __global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restric
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        synth_tile<T, NT>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg, segK, x,
-                          part, status);
+        synth_tile<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg, segK,
+                              x, part, status);
     }
 }
 
@@ -400,13 +410,17 @@ __global__ void k_zero_i32(int32_t* p, int n)
     if (i < n) p[i] = 0;
 }
 
+// The default phase count of the quadratic table is compiled in (immediate table
+// offsets); others run the same kernel with the phase count read at run time.
+constexpr int kPhasesCompiled = 128;
+
 template <int T, int NT>
 static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups, const float4* d_table,
                                int L, const Seg* seg, const int32_t* segK, const float* x, float* part,
                                int32_t* d_status, hipStream_t st)
 {
     const size_t lds = synth_lds_bytes(T, L, hs.window);
-    auto kern = k_synth_fwd<T, NT>;
+    auto kern = L == kPhasesCompiled ? k_synth_fwd<T, NT, kPhasesCompiled> : k_synth_fwd<T, NT, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
@@ -421,7 +435,7 @@ static hipError_t launch_persistent_t(int n_wg, int window, const DScene* d_scen
                                       const float* x, float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = synth_lds_bytes(T, L, window);
-    auto kern = k_synth_persistent<T, NT>;
+    auto kern = L == kPhasesCompiled ? k_synth_persistent<T, NT, kPhasesCompiled> : k_synth_persistent<T, NT, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, ticket, 1);
