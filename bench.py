@@ -29,7 +29,14 @@ sys.path.insert(0, ROOT)
 from paper_2508_03065_amd import scenegen as G  # noqa: E402
 
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
-FLOPS_PER_TAP = 4         # table form: two FMAs per tap (the two interpolation rows, each multiply-added)
+PEAK_LDS = 256 * 256 * 2.4e9   # LDS reads, B/s: 256 CUs x 256 B/clk (b128) x 2.4 GHz
+FLOPS_PER_TAP = 4         # table form: two FMAs per tap (the interpolated coefficient, the multiply-add)
+LDS_PER_TAP = 16          # table form: the source sample and three quadratic-table values per tap
+
+
+def farrow_lds_per_sample(order: int) -> int:
+    """Farrow form: the M+1 filtered values read per image sample (40 B for M <= 9)."""
+    return 40 if order <= 9 else 48
 
 
 def farrow_flops_per_sample(order: int) -> int:
@@ -121,13 +128,17 @@ def synth_roofline(plan, prof, steps, fd, par, workload):
     per_step = prof["synth_launches"] / steps
     if fd == "table":
         flops = taps / per_step * FLOPS_PER_TAP
+        lds = taps / per_step * LDS_PER_TAP
     else:
         flops = taps / par.taps / per_step * farrow_flops_per_sample(par.farrow_order)
+        lds = taps / par.taps / per_step * farrow_lds_per_sample(par.farrow_order)
     achieved = flops / (kms * 1e-3)
     traffic = pmc_traffic(kernel, workload, src)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kernel, "kernel_ms": kms,
-            "flops_per_launch": flops}
+            "flops_per_launch": flops,
+            "lds": {"achieved": lds / (kms * 1e-3) / 1e12, "peak": PEAK_LDS / 1e12, "unit": "TB/s",
+                    "frac": lds / (kms * 1e-3) / PEAK_LDS, "bytes_per_launch": lds}}
 
 
 def measure_fwd_bwd(plan, x, y, steps, torch):
@@ -165,6 +176,34 @@ def measure_batched(scenes, par, steps, torch):
            "plain_value": t / sec_p, "plain_ms_per_step": sec_p * 1e3, "speedup_vs_plain": sec_p / sec_b,
            "persistent_kernel_ms": pb["synth_ms"] / max(1, pb["synth_launches"]), "tuning": tune}
     del plan, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_differentiation(fd, steps, torch):
+    """Forward (batched, graph-replayed) + backward of the 32-scene differentiation
+    workload with L = 0.5 ||y - target||^2: gradients for x, the 6 wall
+    coefficients of every scene and the 8 source knots of every scene."""
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = G.config4()
+    plan = Plan(scenes, with_fd(par, fd))
+    x = plan.pack_x([s.x for s in scenes])
+    g = torch.Generator().manual_seed(4)
+    target = (0.01 * torch.randn(plan.y_total, generator=g)).cuda()
+    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+
+    def step():
+        plan.forward_batched(x, y)
+        plan.backward(x, y - target)
+    step()
+    plan.profile_begin()
+    sec = timed(step, steps, torch)
+    pb = plan.profile_end()
+    out = {"value": 4 * plan.forward_taps / sec, "unit": "taps/s", "ms_per_step": sec * 1e3,
+           "scenes": len(scenes), "images": int(plan.n_images.sum()), "taps_per_step": 4 * plan.forward_taps,
+           "phases_ms_per_step": {k[:-3]: pb[k] / steps for k in
+                                  ("graph_ms", "tracks_ms", "adjoint_ms", "params_ms", "reduce_ms", "filter_ms")}}
+    del plan, x, y, target
     torch.cuda.empty_cache()
     return out
 
@@ -252,6 +291,11 @@ def main():
         for fd in (args.fd, other):
             rec["batched"][fd] = measure_batched(s3, with_fd(p3, fd), nfb, torch)
         del s3
+        rec["differentiation"] = {"workload": "config4: 32 scenes, 6x5x3 m, K=10 (1561 images), 2 s at 16 kHz, "
+                                              "8-knot source paths, tiers, T=64; batched forward + backward "
+                                              "(dL/dx, dL/dbeta_w, dL/dknots)"}
+        for fd in (args.fd, other):
+            rec["differentiation"][fd] = measure_differentiation(fd, 3, torch)
 
     if args.copy_mib > 0:
         a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda")

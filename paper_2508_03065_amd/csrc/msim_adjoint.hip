@@ -448,34 +448,53 @@ hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DIma
 // ------------------------------------------- Catmull-Rom transpose, retarded delay
 
 // Per (mic, segment): the segment's outputs n = kR + v weight the grid delays
-// D_{k-1..k+2} by the Catmull-Rom basis at u = v/R; sum dL/dD(n) times each weight.
-__global__ __launch_bounds__(256) void k_seg_adj(DScene S, const DImage* __restrict__ imgs,
-                                                 const float* __restrict__ dbar, float4* __restrict__ dseg)
+// D_{k-1..k+2} by the Catmull-Rom basis at u = v/R; sum dL/dD(n) times each
+// weight.  One block per run of seg_adj_block_segs(R) segments of one image:
+// the run's outputs are loaded coalesced into LDS (segment stride R+1, so the
+// per-segment reads below fall in distinct banks), then one thread per segment
+// sums its R outputs in order.
+__global__ __launch_bounds__(kSegAdjThreads) void k_seg_adj(DScene S, const DImage* __restrict__ imgs,
+                                                            const float* __restrict__ dbar,
+                                                            float4* __restrict__ dseg)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per_mic = S.seg_per_mic;
-    if (gid >= per_mic * S.n_mics) return;
-    const int mic = (int)(gid / per_mic);
-    const int64_t sidx = gid - (int64_t)mic * per_mic;
+    __shared__ float st[kSegAdjStage + kSegAdjStage / 16 + kSegAdjThreads];
+    const int64_t bid = blockIdx.x;
+    const int mic = (int)(bid / S.sadj_per_mic);
+    const int ridx = (int)(bid - (int64_t)mic * S.sadj_per_mic);
     const DImage* I = imgs + S.img_begin;
-    const int ii = owner(I, S.n_img, sidx, 0);
-    const DImage im = I[ii];
-    const int64_t k = sidx - im.seg_off;
-    const float* Db = dbar + ((int64_t)mic * S.n_img + ii) * S.n_out;
+    int lo = 0, hi = S.n_img - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (I[mid].sadj_off <= ridx) lo = mid; else hi = mid - 1;
+    }
+    const DImage im = I[lo];
+    const int R = im.R;
+    const int per = seg_adj_block_segs(R);
+    const int k0 = (ridx - im.sadj_off) * per;
+    const int nseg = min(per, im.n_seg - k0);
+    const int n0 = k0 * R;
+    const int nv = min(nseg * R, (int)S.n_out - n0);       // outputs of this run
+    const float* Db = dbar + ((int64_t)mic * S.n_img + lo) * S.n_out + n0;
+    for (int i = threadIdx.x; i < nseg * R; i += kSegAdjThreads) {
+        const int kk = i / R, v = i - kk * R;
+        st[kk * (R + 1) + v] = i < nv ? Db[i] : 0.0f;
+    }
+    __syncthreads();
+    const int kk = threadIdx.x;
+    if (kk >= nseg) return;
+    const float* row = st + kk * (R + 1);
+    const double iR = 1.0 / (double)R;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const int64_t nb = k * im.R;
-    const double iR = 1.0 / (double)im.R;
-    for (int v = 0; v < im.R; ++v) {
-        const int64_t n = nb + v;
-        if (n >= S.n_out) break;
-        const double d = Db[n];
+    for (int v = 0; v < R; ++v) {
+        const double d = row[v];
         const double u = v * iR, u2 = u * u, u3 = u2 * u;
         s0 += d * 0.5 * (-u + 2.0 * u2 - u3);
         s1 += d * 0.5 * (2.0 - 5.0 * u2 + 3.0 * u3);
         s2 += d * 0.5 * (u + 4.0 * u2 - 3.0 * u3);
         s3 += d * 0.5 * (-u2 + u3);
     }
-    dseg[gid] = make_float4((float)s0, (float)s1, (float)s2, (float)s3);
+    dseg[(int64_t)mic * S.seg_per_mic + im.seg_off + k0 + kk] =
+        make_float4((float)s0, (float)s1, (float)s2, (float)s3);
 }
 
 // Per (mic, grid point k of an image): dL/dtau_k = fs * sum of the segment
@@ -548,8 +567,8 @@ hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs
                              float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,
                              int want_src, hipStream_t st)
 {
-    const int64_t ns = hs.seg_per_mic * hs.n_mics;
-    hipLaunchKernelGGL(k_seg_adj, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, hs, d_imgs, dbar, dseg);
+    const int64_t nb = hs.sadj_per_mic * hs.n_mics;
+    hipLaunchKernelGGL(k_seg_adj, dim3((unsigned)nb), dim3(kSegAdjThreads), 0, st, hs, d_imgs, dbar, dseg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !want_src) return e;
     const int64_t ng = (hs.seg_per_mic + 3 * (int64_t)hs.n_img) * hs.n_mics;
@@ -588,7 +607,9 @@ __device__ inline double wave_sum_d(double v)
 // Block b of NB (4 waves): images ii = 4b + wave (+ k*4*NB), one wave per image,
 // give dL/dbeta_w partials sum_i (d beta_i / d beta_w) G_i, G_i = dL/dbeta_i summed
 // over its [mic][tile][wave] rows; grid points i = b*256 + t (+ k*NB*256) give
-// dL/dP_a partials.  partial: [NB][6 + 3*kMaxGradKnots].
+// dL/dP_a partials, accumulated in NK >= src_knots registers per axis.
+// partial: [NB][6 + 3*kMaxGradKnots].
+template <int NK>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __restrict__ scenes, int scene,
                                                                 const DImage* __restrict__ imgs,
                                                                 const float* __restrict__ gpart, int gstride,
@@ -637,10 +658,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
         }
     }
     if (want_src && S.src_knots > 0) {
-        const int nk = min(S.src_knots, kMaxGradKnots);
-        double acc[kMaxGradKnots][3];
+        const int nk = min(S.src_knots, NK);
+        double acc[NK][3];
 #pragma unroll
-        for (int j = 0; j < kMaxGradKnots; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+        for (int j = 0; j < NK; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
         const int64_t total = (S.seg_per_mic + 3 * (int64_t)S.n_img) * S.n_mics;
         for (int64_t i = (int64_t)b * kRedThreads + t; i < total; i += stride) {
             const int a = pga[i];
@@ -648,7 +669,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
             const double4 v = pgc[i];
             const double wa = 1.0 - v.w, wb = v.w;
 #pragma unroll
-            for (int j = 0; j < kMaxGradKnots; ++j) {
+            for (int j = 0; j < NK; ++j) {
                 const double f = (j == a) ? wa : (j == a + 1) ? wb : 0.0;
                 acc[j][0] += f * v.x;
                 acc[j][1] += f * v.y;
@@ -656,7 +677,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
             }
         }
 #pragma unroll
-        for (int j = 0; j < kMaxGradKnots; ++j) {
+        for (int j = 0; j < NK; ++j) {
             if (j >= nk) break;
             for (int ax = 0; ax < 3; ++ax) {
                 const double tot = block_sum(acc[j][ax], sh);
@@ -706,8 +727,11 @@ hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene&
 {
     const int NB = reduce_blocks(hs);
     const int wb = gbeta != nullptr, wsrc = gsrc != nullptr && hs.src_knots > 0;
-    hipLaunchKernelGGL(k_reduce_partial, dim3(NB), dim3(kRedThreads), 0, st, d_scenes, scene, d_imgs, gpart,
-                       gpart_stride, pgc, pga, wb, wsrc, partial);
+    const int nk = hs.src_knots;
+    auto kern = nk <= 4 ? k_reduce_partial<4> : nk <= 8 ? k_reduce_partial<8> : nk <= 16 ? k_reduce_partial<16>
+                                                                                          : k_reduce_partial<kMaxGradKnots>;
+    hipLaunchKernelGGL(kern, dim3(NB), dim3(kRedThreads), 0, st, d_scenes, scene, d_imgs, gpart, gpart_stride, pgc,
+                       pga, wb, wsrc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(6 + 3 * kMaxGradKnots), dim3(64), 0, st, d_scenes, scene, NB, partial,

@@ -392,33 +392,59 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_u(DScene S, const DImage* __r
     int bad = 0;
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
         const DImage im = I[ii];
-        int K;
-        float off, D;
-        int64_t n = min(max(P + (G.dmin + G.dmax) / 2, (int64_t)0), nlast);
-        for (int it = 0; it < 16; ++it) {
-            delay_at(im, seg, segK, trk, n, &K, &off, &D);
-            const int64_t nn = min(max(P + K, (int64_t)0), nlast);
-            if (nn == n) break;
-            n = nn;
-        }
-        for (int dn = -2; dn <= 2; ++dn) {
-            const int64_t c = n + dn;
-            if (c < 0 || c > nlast) continue;
-            delay_at(im, seg, segK, trk, c, &K, &off, &D);
-            if (c - K != P) continue;
+        // delay at output c, re-reading the track segment only when c leaves it
+        int kc = -1, Kseg = 0;
+        Seg sg{};
+        auto eval = [&](int64_t c, int* K, float* off, float* D) {
+            const int k = min(max((int)(((float)c + 0.5f) * im.invR), 0), im.n_seg - 1);
+            if (k != kc) {
+                kc = k;
+                sg = seg[trk + im.seg_off + k];
+                Kseg = segK[trk + im.seg_off + k];
+            }
+            const float v = (float)(c - (int64_t)k * im.R);
+            const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+            const float fl = floorf(d);
+            *K = Kseg + (int)fl;
+            *off = d - fl;
+            *D = (float)Kseg + d;
+        };
+        auto add = [&](int64_t c, float off, float D) {
             const int64_t p = c - nw;
             if (p < 0 || p >= W) {
                 bad = 1;
-                continue;
+                return;
             }
-            const float gv = gw[p];
             const float s = 2.0f * off - 1.0f;
-            float w = gv * im.gfac * __builtin_amdgcn_rcpf(D);
+            float w = gw[p] * im.gfac * __builtin_amdgcn_rcpf(D);
 #pragma unroll
             for (int k = 0; k < kFarrowStride; ++k) {
                 u[k] += w;
                 w *= s;
             }
+        };
+        int K;
+        float off, D;
+        int64_t n = min(max(P + (G.dmin + G.dmax) / 2, (int64_t)0), nlast);
+        eval(n, &K, &off, &D);
+        for (int it = 0; it < 16; ++it) {
+            const int64_t nn = min(max(P + K, (int64_t)0), nlast);
+            if (nn == n) break;
+            n = nn;
+            eval(n, &K, &off, &D);
+        }
+        // n - K(n) is nondecreasing with steps of 0, 1 or 2, so the outputs
+        // reading P are n itself (when it solves the equation) and its neighbours
+        const bool hit = (n - K == P);
+        const float off_n = off, D_n = D;
+        if (n > 0) {
+            eval(n - 1, &K, &off, &D);
+            if (n - 1 - K == P) add(n - 1, off, D);
+        }
+        if (hit) add(n, off_n, D_n);
+        if (n < nlast) {
+            eval(n + 1, &K, &off, &D);
+            if (n + 1 - K == P) add(n + 1, off, D);
         }
     }
     if (bad) atomicOr(status, kStatusWindow);

@@ -599,7 +599,7 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     d.y_off = y_off;
     d.img_begin = (int)P->images.size();
     d.n_img = I;
-    int64_t seg = 0, runs = 0;
+    int64_t seg = 0, runs = 0, sadj = 0;
     for (const HostImage& h : imgs) {
         DImage di{};
         for (int a = 0; a < 3; ++a) di.m[a] = (int16_t)h.m[a];
@@ -611,11 +611,14 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
         di.n_seg = (int32_t)((s.n_out + h.R - 1) / h.R);
         for (int w = 0; w < 6; ++w) di.hits[w] = (int8_t)h.hits[w];
         di.run_off = (int32_t)runs;
+        di.sadj_off = (int32_t)sadj;
         seg += di.n_seg;
         runs += (di.n_seg + track_block_segs(di.R) - 1) / track_block_segs(di.R);
+        sadj += (di.n_seg + seg_adj_block_segs(di.R) - 1) / seg_adj_block_segs(di.R);
         P->images.push_back(di);
     }
     d.runs_per_mic = runs;
+    d.sadj_per_mic = sadj;
     for (int w = 0; w < 6; ++w) d.beta[w] = s.beta[w];
     d.src_grad_off = (int32_t)P->src_grad_total;
     d.src_knots = s.src.kind == MSIM_TRAJ_PWL ? s.src.n_points : 0;

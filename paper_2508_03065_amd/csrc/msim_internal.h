@@ -37,6 +37,7 @@ struct DScene {
     int32_t n_grp;
     int64_t seg_per_mic;  // track segments of one mic (sum over images)
     int64_t runs_per_mic; // track-kernel blocks of one mic
+    int64_t sadj_per_mic; // Catmull-Rom-transpose blocks of one mic
     int32_t n_tiles;
     int32_t window;       // LDS source window (positions) the plan sized for this scene
     double beta[6];       // wall coefficients (for d/dbeta)
@@ -69,6 +70,7 @@ struct DImage {
     int8_t hits[6];       // reflections on each wall (beta_i = prod beta_w^hits_w)
     int8_t pad[2];
     int32_t run_off;      // first track-kernel block within one mic
+    int32_t sadj_off;     // first Catmull-Rom-transpose block within one mic
 };
 
 // Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
@@ -82,6 +84,15 @@ constexpr int kTrackThreads = 256;
 constexpr int kTrackWalk = 4;
 constexpr int kTrackPoints = kTrackThreads * kTrackWalk;
 __host__ __device__ constexpr int track_block_segs(int R) { return R == 1 ? kTrackPoints : kTrackPoints - 3; }
+
+// Segments one block of the Catmull-Rom transpose sums: its outputs (segments x R)
+// are staged in LDS, at most kSegAdjStage of them.
+constexpr int kSegAdjThreads = 256;
+constexpr int kSegAdjStage = 8192;
+__host__ __device__ constexpr int seg_adj_block_segs(int R)
+{
+    return R * kSegAdjThreads <= kSegAdjStage ? kSegAdjThreads : (kSegAdjStage / R > 0 ? kSegAdjStage / R : 1);
+}
 
 // Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
 // samples, are bounded by [dmin, dmax] for every mic at every time.

@@ -47,6 +47,8 @@ def test_config1_full_rate(torch_cuda):
     dict(seed=3, max_order=5, taps=96, circle=True, tiers=((2, 1), (4, 16), (99, 160))),
     dict(seed=4, max_order=6, taps=64, n_knots=5, tiers=((2, 1), (6, 16), (99, 160))),
     dict(seed=5, max_order=3, taps=128, fs=48000.0, seconds=0.05),
+    # the paper's own two-tier split: audio rate up to order 2, ratio 3200 above
+    dict(seed=6, max_order=4, taps=64, seconds=0.6, tiers=((2, 1), (99, 3200))),
 ])
 def test_small_tiered_scenes(torch_cuda, case):
     kw = dict(seconds=0.12)
