@@ -92,7 +92,8 @@ typedef struct {
     int32_t taps;               /* T: even, 8..128, multiple of 8 */
     double kaiser_beta;         /* Kaiser window shape */
     double cutoff;              /* normalised cutoff in (0, 0.5] cycles/sample */
-    int32_t table_phases;       /* L: table phases per unit delay (power of two, 64..4096) */
+    int32_t table_phases;       /* L: phases per unit delay of the FD table, interpolated
+                                   quadratically (power of two, 16..1024; 128 by default) */
     int32_t n_tiers;            /* 0: every image at the audio rate; 1..4 tiers below */
     int32_t tier_max_order[4];  /* tier k holds orders <= tier_max_order[k] not in an earlier tier */
     int32_t tier_decim[4];      /* decimation of tier k's delay grid (1 = audio rate), 1..4096 */
@@ -102,8 +103,9 @@ typedef struct {
 } msim_params;
 
 /* How the T-tap Kaiser-windowed sinc h(j - mu) is applied.
- *  MSIM_FD_TABLE:  an oversampled table of h in LDS, linearly interpolated between
- *                  phases, one gather of T taps per image sample.
+ *  MSIM_FD_TABLE:  an oversampled table of h in LDS, interpolated quadratically
+ *                  between phases, one gather of T taps per image sample; the
+ *                  adjoint is the exact transpose and derivative of that interpolant.
  *  MSIM_FD_FARROW: the Farrow structure of Sec. II-B (Eq. 3-5): h(j - mu) is fitted
  *                  by a degree-M polynomial in s = 2 mu - 1 for every tap j
  *                  (Chebyshev interpolation of the same kernel), the M+1 filtered
@@ -115,7 +117,7 @@ enum { MSIM_FD_TABLE = 0, MSIM_FD_FARROW = 1 };
 
 typedef struct msim_plan msim_plan;
 
-/* Fills defaults: c 343, fs 16000, T 64, Kaiser beta 8, cutoff 0.5, L 512,
+/* Fills defaults: c 343, fs 16000, T 64, Kaiser beta 8, cutoff 0.5, L 128,
  * three tiers (orders <=2 at the audio rate, 3-6 decimated by 16, the rest by 160),
  * retarded delays. */
 msim_status msim_default_params(msim_params* p);

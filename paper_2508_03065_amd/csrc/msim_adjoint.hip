@@ -4,11 +4,13 @@
 // with D_i(n) = K_i(n) + mu_i(n) the Catmull-Rom interpolated delay and
 // g_i(n) = beta_i fs / (4 pi c D_i(n))  (Eq. 2 / Eq. 8, Sec. II-B, Sec. II-C-3).
 // Given gy = dL/dy:
+// with h the forward's quadratic interpolation of the Kaiser-windowed sinc.  Given gy = dL/dy:
 //   adj_x      : dL/dx[m] = sum_{c,i,n} gy_c[n] g_i(n) h(n - D_i(n) - m), the transpose
-//                time-varying fractional delay, scattered into an LDS window per
-//                (mic, output tile, delay group) and gathered in fixed order.
-//   adj_track  : per image sample, s and s' = sum_j h'(j - mu) x[...]:
-//                dL/dbeta_i += gy s fs / (4 pi c D),  dL/dD_i(n) = -gy g (s' + s / D).
+//                time-varying fractional delay, accumulated per wave in a shifting
+//                register accumulator, per (mic, output tile, delay group) in LDS,
+//                and gathered in fixed order.
+//   adj_track  : per image sample, s and ds/dmu from the same table sums:
+//                dL/dbeta_i += gy s fs / (4 pi c D),  dL/dD_i(n) = gy g (ds/dmu - s / D).
 //   seg/grid   : transpose of the Catmull-Rom interpolation (dL/dD on the delay
 //                grid), then the implicit-function derivative of the retarded
 //                delay c tau = |S_i p(t - tau) + O_i - r(t)| with respect to the
@@ -59,170 +61,215 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b)
 
 }  // namespace
 
-// Each wave owns a window of (window - NT + 64) samples: its 64 outputs' taps
-// under every delay of the group.
-size_t adj_x_lds_bytes(int taps, int L, int window, int nthreads)
+// The transpose reads the forward's quadratic table, rearranged tap-major:
+// three arrays Y, D1, D2 of [T/2][Lq] floats; then each wave owns a window of
+// (window - NT + 64) samples: its 64 outputs' taps under every delay of the group.
+size_t adj_x_lds_bytes(int taps, int Lq, int window, int nthreads)
 {
-    return (size_t)(taps / 8) * (size_t)(L + 1) * sizeof(float4) +
+    return (size_t)3 * (taps / 2) * (size_t)Lq * sizeof(float) +
            (size_t)(nthreads / 64) * (size_t)(window - nthreads + 64) * sizeof(float);
 }
 
-size_t adj_track_lds_bytes(int taps, int L, int window)
+size_t adj_track_lds_bytes(int taps, int Lq, int window)
 {
-    const int L2 = L / 2;
-    return (size_t)(taps / 8) * ((size_t)(L + 1) + (size_t)(L2 + 1)) * sizeof(float4) +
-           (size_t)window * sizeof(float4);
+    return (size_t)(taps / 8) * (size_t)Lq * 3 * sizeof(float4) + (size_t)window * sizeof(float4);
 }
 
 // ------------------------------------------------------------ transpose delay
 
-// Scatter of gy g h(j - mu) onto source positions n - K - j.  Every wave adds
-// into its own LDS window with plain read-add-write steps, one tap at a time
-// (the window is volatile, so the steps stay in order): within a step the 64
-// lanes touch 64 distinct positions unless two neighbouring outputs share
-// n - K (the integer delay stepped up between them); those lanes take a second
-// pass.  The wave windows are then summed in wave order: no atomics (LDS float
-// atomics measured several times slower here), and the result does not depend
-// on scheduling.
-template <int T, int NT>
+// Transpose of the time-varying fractional delay of the table form:
+//   dL/dx[m] += w h_q(j - mu)  for every image sample (w = gy g) and tap j, m = n - K - j,
+// with h_q the forward's quadratic interpolation of h, so this is its exact transpose.
+//
+// Systolic form.  A wave holds 64 consecutive outputs of one image; their integer
+// delays differ by at most one (K_ref = the smallest, dK = K - K_ref in {0, 1}),
+// so at step s (s = 0 .. T) lane l's tap lands on relative source position
+// l + s - T/2 - 1 (relative to n0 - K_ref).  The wave keeps one register
+// accumulator per lane for that position; between steps it moves one lane down
+// (DPP wave_shl:1, fused into the add), the value leaving lane 0 is complete and
+// is parked in a second register that shifts the same way.  Each image's 64 + T
+// positions then reach the wave's LDS window with two read-add-writes per lane
+// (the old per-tap scatter needed one per tap).  Waves whose integer delay spans
+// more than one sample (relative speeds above ~fs/64 samples per sample) take a
+// per-tap scatter instead.  The wave windows are summed in wave order: no
+// atomics, and the result does not depend on scheduling.
+template <int T, int NT, int LQC>
 __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict__ imgs,
-                                               const DGroup* __restrict__ groups, const float4* __restrict__ table,
-                                               int L, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                               const DGroup* __restrict__ groups, const float* __restrict__ atab,
+                                               int Lr, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
                                                const float* __restrict__ gy, float* __restrict__ xpart,
                                                int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
-    constexpr int NG = T / 8;
     constexpr int WAVES = NT / 64;
-    const int rows = L + 1;
-    float4* tab = lds;
-    float* wbase = (float*)(lds + NG * rows);
+    constexpr int H = T / 2;
+    const int LQ = LQC > 0 ? LQC : Lr;
+    float* tY = (float*)lds;
+    float* tD1 = tY + H * LQ;
+    float* tD2 = tD1 + H * LQ;
+    float* wbase = tD2 + H * LQ;
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const DGroup G = groups[S.grp_begin + g];
-    const int64_t n0 = (int64_t)tile * NT;
-    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int n0 = tile * NT;
+    const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;       // the tile's window
     const int Wstride = S.window - NT + 64;             // per-wave window slot
     const int Ww = W - NT + 64;                         // per-wave window used by this group
-    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
+    for (int i = tid; i < 3 * H * LQ; i += NT) tY[i] = atab[i];
     for (int p = tid; p < WAVES * Wstride; p += NT) wbase[p] = 0.0f;
     __syncthreads();
 
+    // read-add-writes of successive images stay in program order (lanes of one
+    // wave may touch the same position for different images)
     volatile float* xb = wbase + wave * Wstride;        // covers source positions ws + 64 wave + [0, Ww)
-    const int64_t wsw = ws + 64 * wave;
-    const int64_t n = n0 + tid;
-    const bool valid = n < S.n_out;
+    const int wsw = ws + 64 * wave;
+    const int n0w = n0 + 64 * wave;
+    const int n = n0w + lane;
+    const int n_out = (int)S.n_out;
+    const bool valid = n < n_out;
     const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
-    const int64_t nc = valid ? n : S.n_out - 1;
-    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const int nc = valid ? n : n_out - 1;
+    const Seg* sgm = seg + (int64_t)mic * S.seg_per_mic;
+    const int32_t* sgk = segK + (int64_t)mic * S.seg_per_mic;
     const DImage* I = imgs + S.img_begin;
     const float fn = (float)nc + 0.5f;
-    const float Lf = (float)L;
-    const int64_t n_in = S.n_in;
+    const float LQf = (float)LQ;
+    const int n_in = (int)S.n_in;
     int bad = 0;
-    auto seg_index = [&](const DImage& im, int* kout) {
-        int k = (int)(fn * im.invR);
-        k = min(max(k, 0), im.n_seg - 1);
-        *kout = k;
-        return trk + im.seg_off + k;
-    };
-    DImage nim = I[G.img_begin];
-    int nk;
-    int64_t nsidx = seg_index(nim, &nk);
-    Seg nsg = seg[nsidx];
-    int nKs = segK[nsidx];
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = nim;
-        const int k = nk;
-        const Seg sg = nsg;
-        const int Ks = nKs;
-        if (ii + 1 < G.img_end) {
-            nim = I[ii + 1];
-            nsidx = seg_index(nim, &nk);
-            nsg = seg[nsidx];
-            nKs = segK[nsidx];
-        }
-        const ImageSample smp = sample_of(im, k, sg, Ks, nc);
-        const int64_t xlo = nc - smp.K - T / 2, xhi = nc - smp.K + T / 2 - 1;
-        bool act = valid && wy != 0.0f && xhi >= 0 && xlo < n_in;
-        if (!__any(act)) continue;
-        const int p0 = (int)(nc - smp.K - wsw);
-        if (act && (p0 < T / 2 || p0 > Ww - T / 2)) {
+        const DImage im = I[ii];
+        const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+        const Seg sg = sgm[im.seg_off + k];
+        const int Ks = sgk[im.seg_off + k];
+        const float v = (float)(nc - __mul24(k, im.R));
+        const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+        const float fl = floorf(d);
+        const int K = Ks + (int)fl;
+        const int P = nc - K;
+        const bool reach = valid && wy != 0.0f && P + T / 2 - 1 >= 0 && P - T / 2 < n_in;
+        if (!__any(reach)) continue;
+        // every lane's taps must fall inside the wave's window
+        const int p0 = P - wsw;
+        if (__any(valid && (p0 < T / 2 + 1 || p0 > Ww - T / 2 - 1))) {
             bad = 1;
-            act = false;
+            continue;
         }
-        // neighbouring lanes with the same source position collide within a step
-        const int P = (int)(nc - smp.K);
-        const int prevP = __shfl_up(P, 1, 64);
-        const int prevA = __shfl_up((int)act, 1, 64);
-        const bool dup = act && lane > 0 && prevA && prevP == P;
-        const float w = wy * im.gfac * __builtin_amdgcn_rcpf(smp.D);
-        const float q = smp.mu * Lf;
-        const int kq = min((int)q, L - 1);
+        const float w = reach ? wy * im.gfac * __builtin_amdgcn_rcpf((float)Ks + d) : 0.0f;
+        const float mu = d - fl;
+        const float q = mu * LQf;
+        const int kq = min((int)q, LQ - 1);
         const float f = q - (float)kq;
-        const float a = w * (1.0f - f), b = w * f;
-        const float4* tn = tab + kq;
-        const float4* tp = tab + (L - 1 - kq);
-        volatile float* xq = xb + (act ? p0 : T / 2);
-        const bool any_dup = __any(dup);
-        for (int pass = 0; pass < (any_dup ? 2 : 1); ++pass) {
-            const bool on = act && (pass == 0 ? !dup : dup);
-            if (!on) continue;
+        const float A = w, Bn = w * f, Bf = w * (1.0f - f), C = w * (0.5f * f * (f - 1.0f));
+        const int rf = LQ - 1 - kq;
+        int kmin = K, kmax = K;
 #pragma unroll
-            for (int gi = 0; gi < NG; ++gi) {
-                const float4 Pv = tn[gi * rows];
-                const float4 Qv = tn[gi * rows + 1];
-                xq[4 * gi + 0] = xq[4 * gi + 0] + fmaf(a, Pv.x, b * Qv.x);
-                xq[4 * gi + 1] = xq[4 * gi + 1] + fmaf(a, Pv.y, b * Qv.y);
-                xq[4 * gi + 2] = xq[4 * gi + 2] + fmaf(a, Pv.z, b * Qv.z);
-                xq[4 * gi + 3] = xq[4 * gi + 3] + fmaf(a, Pv.w, b * Qv.w);
-                const float4 P2 = tp[gi * rows];
-                const float4 Q2 = tp[gi * rows + 1];
-                xq[-1 - 4 * gi - 0] = xq[-1 - 4 * gi - 0] + fmaf(b, P2.x, a * Q2.x);
-                xq[-1 - 4 * gi - 1] = xq[-1 - 4 * gi - 1] + fmaf(b, P2.y, a * Q2.y);
-                xq[-1 - 4 * gi - 2] = xq[-1 - 4 * gi - 2] + fmaf(b, P2.z, a * Q2.z);
-                xq[-1 - 4 * gi - 3] = xq[-1 - 4 * gi - 3] + fmaf(b, P2.w, a * Q2.w);
-            }
+        for (int o = 32; o > 0; o >>= 1) {
+            kmin = min(kmin, __shfl_xor(kmin, o, 64));
+            kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        if (kmax - kmin > 1) {
+            // per-tap scatter; lanes sharing a source position (the integer delay
+            // stepped between them) take a second pass
+            const int prevP = __shfl_up(P, 1, 64);
+            const bool dup = lane > 0 && prevP == P;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (!reach || (pass == 0 ? dup : !dup)) continue;
+                for (int dd = 0; dd < H; ++dd) {
+                    const int in = dd * LQ + kq, ifr = dd * LQ + rf;
+                    xb[p0 + dd] += fmaf(A, tY[in], fmaf(Bn, tD1[in], C * tD2[in]));
+                    xb[p0 - 1 - dd] += fmaf(A, tY[ifr], fmaf(Bf, tD1[ifr], C * tD2[ifr]));
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            continue;
+        }
+        const int dK = K - kmin;
+        // table indices at step s: far side (d = H - s - dK) pF + (H-1-s) LQ; near side
+        // (d = s - H - 1 + dK) pN + (s-H-1) LQ
+        const int pF = (1 - dK) * LQ + rf;
+        const int pN = dK * LQ + kq;
+        auto far = [&](int s) {
+            const int i = pF + (H - 1 - s) * LQ;
+            return fmaf(A, tY[i], fmaf(Bf, tD1[i], C * tD2[i]));
+        };
+        auto near = [&](int s) {
+            const int i = pN + (s - H - 1) * LQ;
+            return fmaf(A, tY[i], fmaf(Bn, tD1[i], C * tD2[i]));
+        };
+        // relative position (to n0w - kmin) of lane l at step s: l + s - H - 1
+        const int rel0 = n0w - kmin - wsw;               // window index of relative position 0
+        float acc, out = 0.0f;
+        int ndep = 0;                                    // departures parked in `out`
+        auto step = [&](int s, float c) {
+            if (s == 0) {
+                acc = c;
+                return;
+            }
+            const float dep = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 0));
+            acc = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x130, 0xF, 0xF, true)) + c;
+            out = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(out), 0x130, 0xF, 0xF, true));
+            out = lane == 63 ? dep : out;
+            if (++ndep == 64) {
+                // departures of steps s-64 .. s-1 sit in lanes 0..63
+                const int pw = rel0 + (s - 64 + lane) - H - 1;
+                xb[pw] += out;
+                out = 0.0f;
+                ndep = 0;
+            }
+        };
+        step(0, dK ? far(0) : 0.0f);
+#pragma unroll
+        for (int s = 1; s < H; ++s) step(s, far(s));
+        {
+            const int i = dK ? kq : rf;
+            step(H, fmaf(A, tY[i], fmaf(dK ? Bn : Bf, tD1[i], C * tD2[i])));
+        }
+#pragma unroll
+        for (int s = H + 1; s < T; ++s) step(s, near(s));
+        step(T, dK ? 0.0f : near(T));
+        // remaining departures (steps T-ndep .. T-1) in lanes 64-ndep .. 63
+        if (ndep > 0 && lane >= 64 - ndep) xb[rel0 + (T - 64 + lane) - H - 1] += out;
+        xb[rel0 + lane + T - H - 1] += acc;
+        __builtin_amdgcn_wave_barrier();
     }
     if (bad) atomicOr(status, kStatusWindow);
     __syncthreads();
     // tile window position p = wave window position p - 64 w, summed in wave order
-    float* out = xpart + (((int64_t)mic * S.n_grp + g) * S.n_tiles + tile) * S.window;
+    float* outp = xpart + (((int64_t)mic * S.n_grp + g) * S.n_tiles + tile) * S.window;
     for (int p = tid; p < W; p += NT) {
-        float acc = 0.0f;
+        float a = 0.0f;
         for (int w2 = 0; w2 < WAVES; ++w2) {
             const int pw = p - 64 * w2;
-            if (pw >= 0 && pw < Ww) acc += wbase[w2 * Wstride + pw];
+            if (pw >= 0 && pw < Ww) a += wbase[w2 * Wstride + pw];
         }
-        out[p] = acc;
+        outp[p] = a;
     }
 }
 
 template <int T, int NT>
 static hipError_t launch_adj_x_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                                 const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                                 const float* d_atab, int Lq, const Seg* seg, const int32_t* segK, const float* gy,
                                  float* xpart, int32_t* d_status, hipStream_t st)
 {
-    const size_t lds = adj_x_lds_bytes(T, L, hs.window, NT);
-    auto kern = k_adj_x<T, NT>;
+    const size_t lds = adj_x_lds_bytes(T, Lq, hs.window, NT);
+    auto kern = Lq == 128 ? k_adj_x<T, NT, 128> : k_adj_x<T, NT, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, L, seg, segK, gy, xpart,
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_atab, Lq, seg, segK, gy, xpart,
                        d_status);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                        const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                        const float* d_atab, int Lq, const Seg* seg, const int32_t* segK, const float* gy,
                         float* xpart, int32_t* d_status, hipStream_t st)
 {
 #define MSIM_ADJX_CASE(TT, NN)                                                                                 \
     if (taps == TT && nthreads == NN)                                                                          \
-        return launch_adj_x_t<TT, NN>(hs, d_imgs, d_groups, d_table, L, seg, segK, gy, xpart, d_status, st);
+        return launch_adj_x_t<TT, NN>(hs, d_imgs, d_groups, d_atab, Lq, seg, segK, gy, xpart, d_status, st);
     MSIM_ADJX_CASE(32, 1024)
     MSIM_ADJX_CASE(64, 1024)
     MSIM_ADJX_CASE(96, 1024)
@@ -271,11 +318,19 @@ hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthread
 
 // --------------------------------------------------- gain and delay adjoints
 
-template <int T, int NT>
+// Per image sample the forward's quadratic-table sums give the filtered value
+//   s = A + f B + (1-f) Bm + f (f-1)/2 C
+// (A over both sides' Y, B and Bm over the near and far sides' first differences,
+// C over both sides' second differences), and its derivative in mu, the exact
+// derivative of the same interpolant:
+//   ds/dmu = Lq (B - Bm + (f - 1/2) C)
+// (the near side's fraction is f, the far side's 1 - f and runs the other way).
+// Then dL/dbeta_i += gy s fs / (4 pi c D) and dL/dD = gy g (ds/dmu - s / D).
+// dbar [mic][image][n_out]; gpart [image][(mic*n_tiles + tile)*waves + wave].
+template <int T, int NT, int LC>
 __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __restrict__ imgs,
                                                    const DGroup* __restrict__ groups,
-                                                   const float4* __restrict__ table,
-                                                   const float4* __restrict__ dtable, int L,
+                                                   const float4* __restrict__ table, int Lr,
                                                    const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
                                                    const float* __restrict__ x, const float* __restrict__ gy,
                                                    float ghat, float* __restrict__ dbar, float* __restrict__ gpart,
@@ -284,25 +339,22 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     extern __shared__ float4 lds[];
     constexpr int NG = T / 8;
     constexpr int WAVES = NT / 64;
-    const int rows = L + 1;
-    const int L2 = L / 2;
-    const int rows2 = L2 + 1;
+    const int L = LC > 0 ? LC : Lr;
+    const int rows3 = 3 * L;
     float4* tab = lds;
-    float4* dtab = lds + NG * rows;
-    float4* xw = dtab + NG * rows2;
+    float4* xw = lds + NG * rows3;
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const DGroup G = groups[S.grp_begin + g];
-    const int64_t n0 = (int64_t)tile * NT;
-    const int64_t ws = n0 - G.dmax - T / 2 - 4;
+    const int n0 = tile * NT;
+    const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
-    for (int i = tid; i < NG * rows; i += NT) tab[i] = table[i];
-    for (int i = tid; i < NG * rows2; i += NT) dtab[i] = dtable[i];
+    for (int i = tid; i < NG * rows3; i += NT) tab[i] = table[i];
     const float* xs = x + S.x_off;
-    const int64_t n_in = S.n_in;
+    const int n_in = (int)S.n_in;
     for (int p = tid; p < W; p += NT) {
-        const int64_t q = ws + p;
+        const int q = ws + p;
         float4 v;
         v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
         v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
@@ -312,93 +364,65 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     }
     __syncthreads();
 
-    const int64_t n = n0 + tid;
-    const bool valid = n < S.n_out;
+    const int n = n0 + tid;
+    const int n_out = (int)S.n_out;
+    const bool valid = n < n_out;
     const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
-    const int64_t nc = valid ? n : S.n_out - 1;
-    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const int nc = valid ? n : n_out - 1;
+    const Seg* sgm = seg + (int64_t)mic * S.seg_per_mic;
+    const int32_t* sgk = segK + (int64_t)mic * S.seg_per_mic;
     const DImage* I = imgs + S.img_begin;
     const float fn = (float)nc + 0.5f;
-    const float Lf = (float)L, L2f = (float)L2;
+    const float Lf = (float)L;
     float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
     const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * WAVES;
     float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * WAVES + wave;
     int bad = 0;
-    auto seg_index = [&](const DImage& im, int* kout) {
-        int k = (int)(fn * im.invR);
-        k = min(max(k, 0), im.n_seg - 1);
-        *kout = k;
-        return trk + im.seg_off + k;
-    };
-    DImage nim = I[G.img_begin];
-    int nk;
-    int64_t nsidx = seg_index(nim, &nk);
-    Seg nsg = seg[nsidx];
-    int nKs = segK[nsidx];
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = nim;
-        const int k = nk;
-        const Seg sg = nsg;
-        const int Ks = nKs;
-        if (ii + 1 < G.img_end) {
-            nim = I[ii + 1];
-            nsidx = seg_index(nim, &nk);
-            nsg = seg[nsidx];
-            nKs = segK[nsidx];
-        }
-        const ImageSample smp = sample_of(im, k, sg, Ks, nc);
-        const int64_t xlo = nc - smp.K - T / 2, xhi = nc - smp.K + T / 2 - 1;
-        const bool act = valid && xhi >= 0 && xlo < n_in;
+        const DImage im = I[ii];
+        const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+        const Seg sg = sgm[im.seg_off + k];
+        const int Ks = sgk[im.seg_off + k];
+        const float v = (float)(nc - __mul24(k, im.R));
+        const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+        const float fl = floorf(d);
+        const int K = Ks + (int)fl;
+        const bool act = valid && wy != 0.0f && nc - K + T / 2 - 1 >= 0 && nc - K - T / 2 < n_in;
         float E = 0.0f, Db = 0.0f;
         if (__any(act)) {
-            const int p0 = (int)(nc - smp.K - ws);
+            const int p0 = nc - K - ws;
             const bool inb = p0 >= T / 2 && p0 <= W - T / 2 + 3;
             if (act && !inb) bad = 1;
             if (act && inb) {
-                const float q = smp.mu * Lf;
+                const float mu = d - fl;
+                const float q = mu * Lf;
                 const int kq = min((int)q, L - 1);
                 const float f = q - (float)kq;
-                const float q2 = smp.mu * L2f;
-                const int kq2 = min((int)q2, L2 - 1);
-                const float f2 = q2 - (float)kq2;
-                const float4* tn = tab + kq;
-                const float4* tp = tab + (L - 1 - kq);
-                const float4* dn = dtab + kq2;
-                const float4* dp = dtab + (L2 - 1 - kq2);
+                const float4* tn = tab + 3 * kq;
+                const float4* tp = tab + 3 * (L - 1 - kq);
                 const float4* xq = xw + p0;
-                float A = 0.f, B = 0.f, A2 = 0.f, B2 = 0.f;
+                float A = 0.0f, B = 0.0f, Bm = 0.0f, C = 0.0f;
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     const float4 xn = xq[4 * gi];
+                    const float4 Y = tn[gi * rows3], D1 = tn[gi * rows3 + 1], D2 = tn[gi * rows3 + 2];
+                    A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(D2.x, xn.x, C);
+                    A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(D2.y, xn.y, C);
+                    A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(D2.z, xn.z, C);
+                    A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(D2.w, xn.w, C);
                     const float4 xp = xq[-4 - 4 * gi];
-                    const float4 P = tn[gi * rows], Q = tn[gi * rows + 1];
-                    const float4 P2 = tp[gi * rows], Q2 = tp[gi * rows + 1];
-                    A = fmaf(P.x, xn.x, A); B = fmaf(Q.x, xn.x, B);
-                    A = fmaf(P.y, xn.y, A); B = fmaf(Q.y, xn.y, B);
-                    A = fmaf(P.z, xn.z, A); B = fmaf(Q.z, xn.z, B);
-                    A = fmaf(P.w, xn.w, A); B = fmaf(Q.w, xn.w, B);
-                    B = fmaf(P2.x, xp.w, B); A = fmaf(Q2.x, xp.w, A);
-                    B = fmaf(P2.y, xp.z, B); A = fmaf(Q2.y, xp.z, A);
-                    B = fmaf(P2.z, xp.y, B); A = fmaf(Q2.z, xp.y, A);
-                    B = fmaf(P2.w, xp.x, B); A = fmaf(Q2.w, xp.x, A);
-                    // h' is odd: the taps left of the delay take -h'(|u|)
-                    const float4 R = dn[gi * rows2], U = dn[gi * rows2 + 1];
-                    const float4 R2 = dp[gi * rows2], U2 = dp[gi * rows2 + 1];
-                    A2 = fmaf(-R.x, xn.x, A2); B2 = fmaf(-U.x, xn.x, B2);
-                    A2 = fmaf(-R.y, xn.y, A2); B2 = fmaf(-U.y, xn.y, B2);
-                    A2 = fmaf(-R.z, xn.z, A2); B2 = fmaf(-U.z, xn.z, B2);
-                    A2 = fmaf(-R.w, xn.w, A2); B2 = fmaf(-U.w, xn.w, B2);
-                    B2 = fmaf(R2.x, xp.w, B2); A2 = fmaf(U2.x, xp.w, A2);
-                    B2 = fmaf(R2.y, xp.z, B2); A2 = fmaf(U2.y, xp.z, A2);
-                    B2 = fmaf(R2.z, xp.y, B2); A2 = fmaf(U2.z, xp.y, A2);
-                    B2 = fmaf(R2.w, xp.x, B2); A2 = fmaf(U2.w, xp.x, A2);
+                    const float4 Ym = tp[gi * rows3], E1 = tp[gi * rows3 + 1], E2 = tp[gi * rows3 + 2];
+                    A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(E2.x, xp.w, C);
+                    A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(E2.y, xp.z, C);
+                    A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(E2.z, xp.y, C);
+                    A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm); C = fmaf(E2.w, xp.x, C);
                 }
-                const float s = fmaf(f, B - A, A);
-                const float sp = fmaf(f2, B2 - A2, A2);
-                const float iD = __builtin_amdgcn_rcpf(smp.D);
+                const float s = fmaf(0.5f * f * (f - 1.0f), C, fmaf(1.0f - f, Bm, fmaf(f, B, A)));
+                const float sd = Lf * fmaf(f - 0.5f, C, B - Bm);
+                const float iD = __builtin_amdgcn_rcpf((float)Ks + d);
                 const float gain = im.gfac * iD;
                 E = wy * s * ghat * iD;
-                Db = -wy * gain * fmaf(s, iD, sp);
+                Db = wy * gain * fmaf(-s, iD, sd);
             }
         }
         if (valid) dout[(int64_t)ii * S.n_out] = Db;
@@ -410,29 +434,29 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
 
 template <int T, int NT>
 static hipError_t launch_adj_track_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                                     const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
-                                     const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
-                                     float* gpart, int32_t* d_status, hipStream_t st)
+                                     const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK,
+                                     const float* x, const float* gy, float ghat, float* dbar, float* gpart,
+                                     int32_t* d_status, hipStream_t st)
 {
-    const size_t lds = adj_track_lds_bytes(T, L, hs.window);
-    auto kern = k_adj_track<T, NT>;
+    const size_t lds = adj_track_lds_bytes(T, Lq, hs.window);
+    auto kern = Lq == 128 ? k_adj_track<T, NT, 128> : k_adj_track<T, NT, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, d_dtable, L, seg, segK, x, gy,
-                       ghat, dbar, gpart, d_status);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_qtable, Lq, seg, segK, x, gy, ghat,
+                       dbar, gpart, d_status);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
-                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
-                            float* gpart, int32_t* d_status, hipStream_t st)
+                            const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK, const float* x,
+                            const float* gy, float ghat, float* dbar, float* gpart, int32_t* d_status,
+                            hipStream_t st)
 {
 #define MSIM_ADJT_CASE(TT, NN)                                                                                 \
     if (taps == TT && nthreads == NN)                                                                          \
-        return launch_adj_track_t<TT, NN>(hs, d_imgs, d_groups, d_table, d_dtable, L, seg, segK, x, gy, ghat,   \
-                                          dbar, gpart, d_status, st);
+        return launch_adj_track_t<TT, NN>(hs, d_imgs, d_groups, d_qtable, Lq, seg, segK, x, gy, ghat, dbar,     \
+                                          gpart, d_status, st);
     MSIM_ADJT_CASE(32, 1024)
     MSIM_ADJT_CASE(64, 1024)
     MSIM_ADJT_CASE(96, 1024)

@@ -163,8 +163,8 @@ msim_status check_params(const msim_params* p)
     if (!(p->kaiser_beta >= 0.0) || !(p->cutoff > 0.0 && p->cutoff <= 0.5))
         return fail(MSIM_E_INVALID_ARG, "kaiser_beta >= 0 and cutoff in (0, 0.5] required");
     const int L = p->table_phases;
-    if (L < 64 || L > 4096 || (L & (L - 1)) != 0)
-        return fail(MSIM_E_INVALID_ARG, "table_phases must be a power of two in 64..4096");
+    if (L < 16 || L > 1024 || (L & (L - 1)) != 0)
+        return fail(MSIM_E_INVALID_ARG, "table_phases must be a power of two in 16..1024");
     if (p->n_tiers < 0 || p->n_tiers > 4) return fail(MSIM_E_INVALID_ARG, "n_tiers must be 0..4");
     for (int k = 0; k < p->n_tiers; ++k) {
         if (p->tier_decim[k] < 1 || p->tier_decim[k] > 4096)
@@ -301,9 +301,8 @@ struct msim_plan {
     std::vector<DImage> images;
     std::vector<DGroup> groups;
     std::vector<double> knots, mics;
-    std::vector<float> table;             // float4 groups, flattened
-    std::vector<float> qtable;            // the forward's quadratic table, flattened
-    std::vector<float> dtable;            // derivative table (L/2 phases), same layout
+    std::vector<float> qtable;            // the quadratic FD table, flattened
+    std::vector<float> atable;            // the same values tap-major (Y, D1, D2 of [T/2][Lq]) for the transpose
     std::vector<int64_t> n_img;
     int64_t src_grad_total = 0;           // knots in the packed d/dsource array
     std::vector<bool> grad_ok;            // the adjoint's LDS fits this scene's windows
@@ -332,9 +331,8 @@ struct msim_plan {
     DGroup* d_groups = nullptr;
     double* d_knots = nullptr;
     double* d_mics = nullptr;
-    float4* d_table = nullptr;
-    float4* d_dtable = nullptr;
     float4* d_qtable = nullptr;
+    float* d_atable = nullptr;
     std::vector<float> fcoef;             // Farrow coefficients [kFarrowStride][T]
     std::vector<int64_t> vpos_prefix;     // first Farrow source position of each scene
     int64_t vpos_total = 0;
@@ -392,54 +390,6 @@ struct LaunchTimer {
 
 namespace {
 
-// I1(b s) / s by its power series (b/2) sum_k (b^2 s^2 / 4)^k / (k! (k+1)!), finite at s = 0.
-double bessel_i1_over(double b, double s)
-{
-    const double q = 0.25 * b * b * s * s;
-    double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 1000 && term > 1e-17 * sum; ++k) {
-        term *= q / (double(k) * double(k + 1));
-        sum += term;
-    }
-    return 0.5 * b * sum;
-}
-
-// Derivative h'(v) of the Kaiser-windowed sinc h(v) = 2 fc sinc(2 fc v) w(v).
-double fd_kernel_deriv(double v, int T, double kbeta, double fc, double i0b)
-{
-    if (std::fabs(v) > 0.5 * T) return 0.0;
-    const double z = 2.0 * fc * v;
-    double sinc, dsinc;   // sinc(z) and d sinc / dz
-    if (std::fabs(z) < 1e-8) {
-        sinc = 1.0;
-        dsinc = -kPi * kPi * z / 3.0;
-    } else {
-        sinc = std::sin(kPi * z) / (kPi * z);
-        dsinc = (std::cos(kPi * z) - sinc) / z;
-    }
-    const double r = 2.0 * v / T;
-    const double s = std::sqrt(std::max(0.0, 1.0 - r * r));
-    const double w = bessel_i0(kbeta * s) / i0b;
-    // d/dv I0(b s(v)) = I1(b s) b s'(v),  s' = -r (2/T) / s
-    const double dw = -kbeta * (2.0 / T) * r * bessel_i1_over(kbeta, s) / i0b;
-    return 2.0 * fc * (2.0 * fc * dsinc * w + sinc * dw);
-}
-
-// Half tables grouped by tap quads: tab[g][row] = h((4g+e) + row/L), e = 0..3.
-void build_quads(std::vector<float>& out, int T, int L, double kbeta, double fc, bool deriv)
-{
-    const int NG = T / 8;
-    const double i0b = bessel_i0(kbeta);
-    out.assign((size_t)NG * (L + 1) * 4, 0.0f);
-    for (int g = 0; g < NG; ++g)
-        for (int row = 0; row <= L; ++row)
-            for (int e = 0; e < 4; ++e) {
-                const double v = (4 * g + e) + double(row) / L;
-                out[((size_t)g * (L + 1) + row) * 4 + e] =
-                    (float)(deriv ? fd_kernel_deriv(v, T, kbeta, fc, i0b) : fd_kernel(v, T, kbeta, fc, i0b));
-            }
-}
-
 // Quadratic-interpolation half table of the forward, grouped by tap quads: for
 // row r < Lq, three quads Y(r), Y(r+1) - Y(r), Y(r+2) - 2 Y(r+1) + Y(r) with
 // Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences taken in double).
@@ -462,10 +412,14 @@ void build_qtable(std::vector<float>& out, int T, int Lq, double kbeta, double f
 
 void build_table(msim_plan* P)
 {
-    build_qtable(P->qtable, P->par.taps, P->par.table_phases / kQuadDiv, P->par.kaiser_beta, P->par.cutoff);
-    build_quads(P->table, P->par.taps, P->par.table_phases, P->par.kaiser_beta, P->par.cutoff, false);
-    // the derivative table is read only by the adjoint, at half the phase density
-    build_quads(P->dtable, P->par.taps, P->par.table_phases / 2, P->par.kaiser_beta, P->par.cutoff, true);
+    const int T = P->par.taps, Lq = P->par.table_phases;
+    build_qtable(P->qtable, T, Lq, P->par.kaiser_beta, P->par.cutoff);
+    P->atable.assign((size_t)3 * (T / 2) * Lq, 0.0f);
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < T / 2; ++d)
+            for (int r = 0; r < Lq; ++r)
+                P->atable[((size_t)c * (T / 2) + d) * Lq + r] = P->qtable[((((size_t)(d / 4) * Lq + r) * 3 + c) * 4) + d % 4];
+
 }
 
 // Farrow coefficients: for every tap j = -T/2+1 .. T/2, the degree-M polynomial in
@@ -647,12 +601,12 @@ msim_status regroup(msim_plan* P)
         const auto& bnd = P->bounds[s];
         const int I = d.n_img;
         d.n_tiles = (int)((d.n_out + NT - 1) / NT);
-        // Group windows are sized so the adjoint's LDS (value and derivative tables
-        // beside the source window) fits too; failing that, the forward's alone.
+        // Group windows are sized so the adjoint's LDS (the table beside the source
+        // window, or beside the per-wave windows) fits too; failing that, the forward's alone.
         bool grad_fit = true;
         auto fits = [&](int window) {
             if (P->par.fd_kind == MSIM_FD_FARROW) return farrow_lds_bytes(window) <= kLdsLimit;
-            if (!grad_fit) return synth_lds_bytes(T, L / kQuadDiv, window) <= kLdsLimit;
+            if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
             return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
                    adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
         };
@@ -745,7 +699,7 @@ msim_status regroup(msim_plan* P)
     P->items.resize(it.size());
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
     const size_t lds =
-        P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L / kQuadDiv, wmax);
+        P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L, wmax);
     const int wg_threads = P->par.fd_kind == MSIM_FD_FARROW ? NT / P->farrow_rb : NT;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / wg_threads, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
@@ -874,7 +828,7 @@ msim_status msim_default_params(msim_params* p)
     p->taps = 64;
     p->kaiser_beta = 8.0;
     p->cutoff = 0.5;
-    p->table_phases = 512;
+    p->table_phases = 128;
     p->n_tiers = 3;
     p->tier_max_order[0] = 2;
     p->tier_decim[0] = 1;
@@ -952,16 +906,14 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
     }
-    std::vector<float4> tab4(P->table.size() / 4), dtab4(P->dtable.size() / 4), qtab4(P->qtable.size() / 4);
-    std::memcpy(tab4.data(), P->table.data(), P->table.size() * sizeof(float));
-    std::memcpy(dtab4.data(), P->dtable.data(), P->dtable.size() * sizeof(float));
+    std::vector<float4> qtab4(P->qtable.size() / 4);
     std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size() * sizeof(float));
     std::vector<int32_t> zero(1, 0);
     if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
-        (st = upload(&P->d_dtable, dtab4)) != MSIM_OK || (st = upload(&P->d_images, P->images)) != MSIM_OK ||
+        (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
-        (st = upload(&P->d_table, tab4)) != MSIM_OK || (st = upload(&P->d_status, zero)) != MSIM_OK ||
-        (st = upload(&P->d_qtable, qtab4)) != MSIM_OK ||
+        (st = upload(&P->d_status, zero)) != MSIM_OK ||
+        (st = upload(&P->d_qtable, qtab4)) != MSIM_OK || (st = upload(&P->d_atable, P->atable)) != MSIM_OK ||
         (st = upload_layout(P)) != MSIM_OK) {
         msim_plan_destroy(P);
         return st;
@@ -984,9 +936,8 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_images);
     (void)hipFree(P->d_knots);
     (void)hipFree(P->d_mics);
-    (void)hipFree(P->d_table);
-    (void)hipFree(P->d_dtable);
     (void)hipFree(P->d_qtable);
+    (void)hipFree(P->d_atable);
     (void)hipFree(P->d_fcoef);
     (void)hipFree(P->d_vpos_prefix);
     (void)hipFree(P->d_status);
@@ -1093,8 +1044,8 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
         if (gx) {
             {
                 LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_adj_x(T, P->threads, d, P->d_images, P->d_groups, P->d_table, L, fw.seg, fw.segK, gy,
-                                    aw.xpart, P->d_status, stream));
+                HIP_OK(launch_adj_x(T, P->threads, d, P->d_images, P->d_groups, P->d_atable, L, fw.seg,
+                                    fw.segK, gy, aw.xpart, P->d_status, stream));
             }
             LaunchTimer t(P, kKindReduce, stream);
             HIP_OK(launch_reduce_x(d, P->d_groups, P->threads, T, aw.xpart, gx, stream));
@@ -1102,8 +1053,8 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
         if (gbeta || want_src) {
             {
                 LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_adj_track(T, P->threads, d, P->d_images, P->d_groups, P->d_table, P->d_dtable, L,
-                                        fw.seg, fw.segK, x, gy, ghat, aw.dbar, aw.gpart, P->d_status, stream));
+                HIP_OK(launch_adj_track(T, P->threads, d, P->d_images, P->d_groups, P->d_qtable, L, fw.seg, fw.segK,
+                                        x, gy, ghat, aw.dbar, aw.gpart, P->d_status, stream));
             }
             LaunchTimer t(P, kKindParams, stream);
             if (want_src)
@@ -1151,7 +1102,7 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
                                          P->d_groups, w.seg, w.segK, v, w.part, P->d_status, stream));
             else
                 HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_qtable,
-                                        P->par.table_phases / kQuadDiv, w.seg, w.segK, x, w.part, P->d_status,
+                                        P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status,
                                         stream));
         }
         {
@@ -1260,7 +1211,7 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
                                             w.seg, w.segK, w.v, w.part, P->d_status, st));
         else
             HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b,
-                                           P->d_images, P->d_groups, P->d_qtable, P->par.table_phases / kQuadDiv,
+                                           P->d_images, P->d_groups, P->d_qtable, P->par.table_phases,
                                            P->d_items,
                                            (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status,
                                            st));

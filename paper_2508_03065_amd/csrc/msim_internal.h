@@ -89,6 +89,7 @@ __host__ __device__ constexpr int track_block_segs(int R) { return R == 1 ? kTra
 // are staged in LDS, at most kSegAdjStage of them.
 constexpr int kSegAdjThreads = 256;
 constexpr int kSegAdjStage = 8192;
+static_assert(kSegAdjStage >= 4096, "a segment of the largest decimation (4096) must fit the stage");
 __host__ __device__ constexpr int seg_adj_block_segs(int R)
 {
     return R * kSegAdjThreads <= kSegAdjStage ? kSegAdjThreads : (kSegAdjStage / R > 0 ? kSegAdjStage / R : 1);
@@ -134,9 +135,6 @@ hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window,
 hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
                              const float* part, float* y, hipStream_t st);
 
-// The forward reads a quadratic-interpolation table of table_phases / kQuadDiv
-// phases; the adjoint reads linear-interpolation tables of table_phases phases.
-constexpr int kQuadDiv = 4;
 size_t synth_lds_bytes(int taps, int Lq, int window);
 
 // ---- adjoint launchers (msim_adjoint.hip) ----
@@ -153,17 +151,17 @@ struct AdjBufs {
 };
 
 size_t adj_x_lds_bytes(int taps, int L, int window, int nthreads);
-size_t adj_track_lds_bytes(int taps, int L, int window);
+size_t adj_track_lds_bytes(int taps, int Lq, int window);
 
 hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                        const float4* d_table, int L, const Seg* seg, const int32_t* segK, const float* gy,
+                        const float* d_atab, int Lq, const Seg* seg, const int32_t* segK, const float* gy,
                         float* xpart, int32_t* d_status, hipStream_t st);
 hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
                            float* gx, hipStream_t st);
 hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_table, const float4* d_dtable, int L, const Seg* seg,
-                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
-                            float* gpart, int32_t* d_status, hipStream_t st);
+                            const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK, const float* x,
+                            const float* gy, float ghat, float* dbar, float* gpart, int32_t* d_status,
+                            hipStream_t st);
 hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
                              const double* d_knots, const double* d_mics, const double* grid, const float* dbar,
                              float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,
