@@ -106,8 +106,8 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
 #pragma unroll
         for (int j = 0; j < RB; ++j) acc[j] = 0.0f;
         int bad = 0;
-        // Track data of the next image is fetched while the current one is summed;
-        // two buffers in turn, so no registers are copied between images.
+        // Track data of later images is fetched while the current one is summed;
+        // buffers are used in turn, so no registers are copied between images.
         auto fetch = [&](const DImage& im, Seg (&q)[RB], int (&K)[RB], int& kseg) {
             if (im.R == 1) {
 #pragma unroll
@@ -176,23 +176,35 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
                 acc[j] = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)Ks[j] + d[j]), r, acc[j]);
             }
         };
-        Seg qa[RB] = {}, qb[RB] = {};
-        int Ka[RB] = {}, Kb[RB] = {};
-        int ka = 0, kb = 0;
-        DImage ia = I[G.img_begin], ib;
-        fetch(ia, qa, Ka, ka);
-        int ii = G.img_begin;
-        for (; ii + 1 < G.img_end; ii += 2) {
-            ib = I[ii + 1];
-            fetch(ib, qb, Kb, kb);
-            body(ia, qa, Ka, ka);
-            if (ii + 2 < G.img_end) {
-                ia = I[ii + 2];
-                fetch(ia, qa, Ka, ka);
-            }
-            body(ib, qb, Kb, kb);
+        // three buffers in turn: image ii is summed while ii+1 and ii+2 are in flight
+        Seg q0[RB] = {}, q1[RB] = {}, q2[RB] = {};
+        int K0[RB] = {}, K1[RB] = {}, K2[RB] = {};
+        int k0 = 0, k1 = 0, k2 = 0;
+        const int e = G.img_end;
+        DImage i0 = I[G.img_begin], i1 = i0, i2 = i0;
+        fetch(i0, q0, K0, k0);
+        if (G.img_begin + 1 < e) {
+            i1 = I[G.img_begin + 1];
+            fetch(i1, q1, K1, k1);
         }
-        if (ii < G.img_end) body(ia, qa, Ka, ka);
+        int ii = G.img_begin;
+        for (; ii + 2 < e; ii += 3) {
+            i2 = I[ii + 2];
+            fetch(i2, q2, K2, k2);
+            body(i0, q0, K0, k0);
+            if (ii + 3 < e) {
+                i0 = I[ii + 3];
+                fetch(i0, q0, K0, k0);
+            }
+            body(i1, q1, K1, k1);
+            if (ii + 4 < e) {
+                i1 = I[ii + 4];
+                fetch(i1, q1, K1, k1);
+            }
+            body(i2, q2, K2, k2);
+        }
+        if (ii < e) body(i0, q0, K0, k0);
+        if (ii + 1 < e) body(i1, q1, K1, k1);
         if (bad) atomicOr(status, kStatusWindow);
         float* out = part + S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out;
 #pragma unroll
