@@ -31,7 +31,7 @@ from paper_2508_03065_amd import scenegen as G  # noqa: E402
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
 PEAK_LDS = 256 * 256 * 2.4e9   # LDS reads, B/s: 256 CUs x 256 B/clk (b128) x 2.4 GHz
 FLOPS_PER_TAP = 4         # table form: two FMAs per tap (the interpolated coefficient, the multiply-add)
-LDS_PER_TAP = 16          # table form: the source sample and three quadratic-table values per tap
+LDS_PER_TAP = 14          # table form: the source sample, two FP32 and one FP16 quadratic-table values per tap
 
 
 def farrow_lds_per_sample(order: int) -> int:

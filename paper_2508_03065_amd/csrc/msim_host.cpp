@@ -301,7 +301,7 @@ struct msim_plan {
     std::vector<DImage> images;
     std::vector<DGroup> groups;
     std::vector<double> knots, mics;
-    std::vector<float> qtable;            // the quadratic FD table, flattened
+    std::vector<uint8_t> qtable;          // the quadratic FD table: [Y | D1 | D2] bytes
     std::vector<float> atable;            // the same values tap-major (Y, D1, D2 of [T/2][Lq]) for the transpose
     std::vector<int64_t> n_img;
     int64_t src_grad_total = 0;           // knots in the packed d/dsource array
@@ -331,7 +331,7 @@ struct msim_plan {
     DGroup* d_groups = nullptr;
     double* d_knots = nullptr;
     double* d_mics = nullptr;
-    float4* d_qtable = nullptr;
+    float4* d_qtable = nullptr;           // (16-byte aligned bytes of qtable)
     float* d_atable = nullptr;
     std::vector<float> fcoef;             // Farrow coefficients [kFarrowStride][T]
     std::vector<int64_t> vpos_prefix;     // first Farrow source position of each scene
@@ -390,36 +390,51 @@ struct LaunchTimer {
 
 namespace {
 
-// Quadratic-interpolation half table of the forward, grouped by tap quads: for
-// row r < Lq, three quads Y(r), Y(r+1) - Y(r), Y(r+2) - 2 Y(r+1) + Y(r) with
-// Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences taken in double).
-void build_qtable(std::vector<float>& out, int T, int Lq, double kbeta, double fc)
+// Quadratic-interpolation half table, grouped by tap quads, as three arrays:
+// for quad g and row r < Lq, Y(r), Y(r+1) - Y(r) (float4 each) and
+// Y(r+2) - 2 Y(r+1) + Y(r) (four fp16: it is below 1e-3, so fp16 keeps it to
+// ~3e-7 absolute), with Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences in double).
+// qtable holds the bytes [Y | D1 | D2]; d2 returns the fp16 values as floats.
+void build_qtable(std::vector<uint8_t>& out, std::vector<float>& y_out, std::vector<float>& d1_out,
+                  std::vector<float>& d2_out, int T, int Lq, double kbeta, double fc)
 {
     const int NG = T / 8;
+    const size_t n = (size_t)NG * Lq * 4;
     const double i0b = bessel_i0(kbeta);
-    out.assign((size_t)NG * Lq * 12, 0.0f);
+    y_out.assign(n, 0.0f);
+    d1_out.assign(n, 0.0f);
+    d2_out.assign(n, 0.0f);
+    std::vector<uint16_t> d2h(n, 0);
     for (int g = 0; g < NG; ++g)
         for (int row = 0; row < Lq; ++row)
             for (int e = 0; e < 4; ++e) {
                 double y[3];
                 for (int i = 0; i < 3; ++i) y[i] = fd_kernel((4 * g + e) + double(row + i) / Lq, T, kbeta, fc, i0b);
-                float* o = &out[(((size_t)g * Lq + row) * 3) * 4 + e];
-                o[0] = (float)y[0];
-                o[4] = (float)(y[1] - y[0]);
-                o[8] = (float)(y[2] - 2.0 * y[1] + y[0]);
+                const size_t o = ((size_t)g * Lq + row) * 4 + e;
+                y_out[o] = (float)y[0];
+                d1_out[o] = (float)(y[1] - y[0]);
+                const _Float16 h = (_Float16)(y[2] - 2.0 * y[1] + y[0]);
+                d2_out[o] = (float)h;
+                std::memcpy(&d2h[o], &h, sizeof h);
             }
+    out.resize(n * 4 * 2 + n * 2);
+    std::memcpy(out.data(), y_out.data(), n * 4);
+    std::memcpy(out.data() + n * 4, d1_out.data(), n * 4);
+    std::memcpy(out.data() + n * 8, d2h.data(), n * 2);
 }
 
 void build_table(msim_plan* P)
 {
     const int T = P->par.taps, Lq = P->par.table_phases;
-    build_qtable(P->qtable, T, Lq, P->par.kaiser_beta, P->par.cutoff);
+    std::vector<float> y, d1, d2;
+    build_qtable(P->qtable, y, d1, d2, T, Lq, P->par.kaiser_beta, P->par.cutoff);
+    // the same values tap-major for the transpose: [Y | D1 | D2] of [T/2][Lq] floats
     P->atable.assign((size_t)3 * (T / 2) * Lq, 0.0f);
+    const std::vector<float>* src[3] = {&y, &d1, &d2};
     for (int c = 0; c < 3; ++c)
         for (int d = 0; d < T / 2; ++d)
             for (int r = 0; r < Lq; ++r)
-                P->atable[((size_t)c * (T / 2) + d) * Lq + r] = P->qtable[((((size_t)(d / 4) * Lq + r) * 3 + c) * 4) + d % 4];
-
+                P->atable[((size_t)c * (T / 2) + d) * Lq + r] = (*src[c])[((size_t)(d / 4) * Lq + r) * 4 + d % 4];
 }
 
 // Farrow coefficients: for every tap j = -T/2+1 .. T/2, the degree-M polynomial in
@@ -906,8 +921,8 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
     }
-    std::vector<float4> qtab4(P->qtable.size() / 4);
-    std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size() * sizeof(float));
+    std::vector<float4> qtab4((P->qtable.size() + 15) / 16);
+    std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size());
     std::vector<int32_t> zero(1, 0);
     if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
         (st = upload(&P->d_images, P->images)) != MSIM_OK ||

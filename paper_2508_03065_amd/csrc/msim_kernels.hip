@@ -32,7 +32,7 @@ __device__ __forceinline__ double image_dist(const DScene& S, const int16_t m[3]
         e_v += e * ((m[a] & 1) ? -v[a] : v[a]);
     }
     *ev = e_v;
-    return sqrt(d2);
+    return sqrt_nr(d2);
 }
 
 // Retarded delay at reception time t for mic position r: the root of
@@ -49,7 +49,7 @@ __device__ __forceinline__ double newton_tau(const DScene& S, const int16_t m[3]
         double ev;
         int sg0;
         const double d = image_dist(S, m, knots, r, t - tau, &ev, &sg0);
-        const double step = (c * tau - d) * d / (c * d + ev);
+        const double step = (c * tau - d) * d * rcp_nr(c * d + ev);
         tau -= step;
         const double as = fabs(step);
         if (as <= 1e-9) break;
@@ -67,7 +67,7 @@ __device__ __forceinline__ double first_tau(const DScene& S, const int16_t m[3],
     double ev;
     int sg;
     const double d = image_dist(S, m, knots, r, t, &ev, &sg);
-    return model == 1 ? d / c : d * d / (c * d + ev);
+    return model == 1 ? d / c : d * d * rcp_nr(c * d + ev);
 }
 
 // One block of kTrackThreads threads per (mic, image, block of segments); thread
@@ -217,14 +217,14 @@ hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t
 
 // -------------------------------------------------------------- forward synth
 
-// LDS: the forward's half table of h(v) = h(-v), v in [0, T/2], for quadratic
-// interpolation between Lq phases, grouped by four taps: for row r < Lq,
-//   tab[(g*Lq + r)*3 + 0] = Y(r),  [.. + 1] = Y(r+1) - Y(r),  [.. + 2] = Y(r+2) - 2 Y(r+1) + Y(r),
-// Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as overlapping
-// quads xw[p] = x[ws+p .. ws+p+3].
+// LDS: the half table of h(v) = h(-v), v in [0, T/2], for quadratic
+// interpolation between Lq phases, grouped by four taps, as three arrays over
+// (g, r), r < Lq: Y(r) (float4), Y(r+1) - Y(r) (float4), Y(r+2) - 2 Y(r+1) + Y(r)
+// (four fp16), Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as
+// overlapping quads xw[p] = x[ws+p .. ws+p+3].
 size_t synth_lds_bytes(int taps, int Lq, int window)
 {
-    return (size_t)(taps / 8) * (size_t)Lq * 3 * sizeof(float4) + (size_t)window * sizeof(float4);
+    return (size_t)(taps / 8) * (size_t)Lq * 40 + (size_t)window * sizeof(float4);
 }
 
 // One output tile of one delay group for one mic: stages the group's source
@@ -239,13 +239,14 @@ size_t synth_lds_bytes(int taps, int Lq, int window)
 // right after.
 template <int T, int NT, int LC>
 __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int tile, int mic,
-                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
+                                  const DImage* __restrict__ imgs, const float4* tabY, float4* xw, int Lr,
                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
                                   const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
 {
     constexpr int NG = T / 8;          // tap quads per side
     const int L = LC > 0 ? LC : Lr;
-    const int rows3 = 3 * L;
+    const float4* tabD1 = tabY + NG * L;
+    const uint2* tabD2 = (const uint2*)(tabD1 + NG * L);
     const int tid = threadIdx.x;
     const int n0 = tile * NT;
     const int ws = n0 - G.dmax - T / 2 - 4;
@@ -299,27 +300,28 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
             const float q = mu * Lf;
             const int kq = min((int)q, L - 1);
             const float f = q - (float)kq;
-            const float4* tn = tab + 3 * kq;
-            const float4* tp = tab + 3 * (L - 1 - kq);
+            const int kp = L - 1 - kq;
             const float4* xq = xw + p0;
             float A = 0.0f, B = 0.0f, Bm = 0.0f, C = 0.0f;
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> base row kq, fraction f
                 const float4 xn = xq[4 * gi];
-                const float4 Y = tn[gi * rows3], D1 = tn[gi * rows3 + 1], D2 = tn[gi * rows3 + 2];
-                A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(D2.x, xn.x, C);
-                A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(D2.y, xn.y, C);
-                A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(D2.z, xn.z, C);
-                A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(D2.w, xn.w, C);
+                const float4 Y = tabY[gi * L + kq], D1 = tabD1[gi * L + kq];
+                const uint2 D2 = tabD2[gi * L + kq];
+                A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(h16_lo(D2.x), xn.x, C);
+                A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(h16_hi(D2.x), xn.y, C);
+                A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(h16_lo(D2.y), xn.z, C);
+                A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(h16_hi(D2.y), xn.w, C);
                 // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
                 //   -> base row L-1-kq, fraction 1-f
                 const float4 xp = xq[-4 - 4 * gi];
-                const float4 Ym = tp[gi * rows3], E1 = tp[gi * rows3 + 1], E2 = tp[gi * rows3 + 2];
-                A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(E2.x, xp.w, C);
-                A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(E2.y, xp.z, C);
-                A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(E2.z, xp.y, C);
-                A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm); C = fmaf(E2.w, xp.x, C);
+                const float4 Ym = tabY[gi * L + kp], E1 = tabD1[gi * L + kp];
+                const uint2 E2 = tabD2[gi * L + kp];
+                A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(h16_lo(E2.x), xp.w, C);
+                A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(h16_hi(E2.x), xp.z, C);
+                A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(h16_lo(E2.y), xp.y, C);
+                A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm); C = fmaf(h16_hi(E2.y), xp.x, C);
             }
             const float s = fmaf(0.5f * f * (f - 1.0f), C, fmaf(1.0f - f, Bm, fmaf(f, B, A)));
             acc = fmaf(gain, s, acc);
@@ -349,12 +351,12 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
 template <int T>
 __device__ inline void load_table(const float4* __restrict__ table, float4* tab, int Lq)
 {
-    const int n = (T / 8) * Lq * 3;
+    const int n = (T / 8) * Lq * 40 / 16;
     for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = table[i];
 }
 
 template <int T, int NT, int LC>
-__global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
+__global__ __launch_bounds__(NT, 8) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
                                                    const DGroup* __restrict__ groups,
                                                    const float4* __restrict__ table, int L,
                                                    const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __rest
 {
     extern __shared__ float4 lds[];
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * L * 3;
+    float4* xw = lds + (T / 8) * L * 40 / 16;
     load_table<T>(table, tab, L);
     const int g = blockIdx.y;
     synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_synth_fwd(DScene S, const DImage* __rest
 // ticket counter until the list is exhausted.  Items write disjoint partial
 // outputs, so the result does not depend on which workgroup ran which item.
 template <int T, int NT, int LC>
-__global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restrict__ scenes,
+__global__ __launch_bounds__(NT, 8) void k_synth_persistent(const DScene* __restrict__ scenes,
                                                           const DImage* __restrict__ imgs,
                                                           const DGroup* __restrict__ groups,
                                                           const float4* __restrict__ table, int L,
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_synth_persistent(const DScene* __restric
     extern __shared__ float4 lds[];
     __shared__ int s_item;
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * L * 3;
+    float4* xw = lds + (T / 8) * L * 40 / 16;
     load_table<T>(table, tab, L);
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
