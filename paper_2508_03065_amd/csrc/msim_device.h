@@ -44,6 +44,18 @@ __device__ __forceinline__ float h16_hi(unsigned v)
 
 // ------------------------------------------------------------------ geometry
 
+// Segment of a PWL path holding t, T[0] <= t: the largest a <= n-2 with T[a] <= t
+// (binary search, so dense band-limited paths cost log2 of their knot count).
+__device__ __forceinline__ int pwl_find(const double* __restrict__ T, int n, double t)
+{
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
 {
     if (tr.kind == 1) {
@@ -66,8 +78,7 @@ __device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knot
         a = n - 1;
         lam = 0.0;
     } else {
-        a = 0;
-        while (a + 2 < n && t >= T[a + 1]) ++a;
+        a = pwl_find(T, n, t);
         lam = (t - T[a]) / (T[a + 1] - T[a]);
     }
     const int b = (lam > 0.0) ? a + 1 : a;
@@ -102,8 +113,7 @@ __device__ inline int traj_pos_vel_seg(const DTraj& tr, const double* __restrict
         }
         return (n == 1 || t <= T[0]) ? -1 : n - 1;
     }
-    int a = 0;
-    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const int a = pwl_find(T, n, t);
     const double idt = rcp_nr(T[a + 1] - T[a]);
     const double lam = (t - T[a]) * idt;
     for (int k = 0; k < 3; ++k) {
@@ -122,8 +132,7 @@ __device__ inline int traj_seg(const DTraj& tr, const double* __restrict__ knots
     const int n = tr.n_points;
     if (n == 1 || t <= T[0]) return -1;
     if (t >= T[n - 1]) return n - 1;
-    int a = 0;
-    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const int a = pwl_find(T, n, t);
     return a;
 }
 
@@ -172,8 +181,7 @@ __device__ inline void traj_pos_vel(const DTraj& tr, const double* __restrict__ 
         }
         return;
     }
-    int a = 0;
-    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const int a = pwl_find(T, n, t);
     const double dt = T[a + 1] - T[a];
     const double lam = (t - T[a]) / dt;
     for (int k = 0; k < 3; ++k) {
@@ -247,7 +255,7 @@ __device__ inline void pwl_locate(const DTraj& tr, const double* __restrict__ kn
     } else if (t >= T[n - 1]) {
         a = n - 1;
     } else {
-        while (a + 2 < n && t >= T[a + 1]) ++a;
+        a = pwl_find(T, n, t);
         lam = (t - T[a]) / (T[a + 1] - T[a]);
     }
     *a_out = a;
@@ -271,8 +279,7 @@ __device__ inline void traj_vel(const DTraj& tr, const double* __restrict__ knot
     const int n = tr.n_points;
     out[0] = out[1] = out[2] = 0.0;
     if (n == 1 || t <= T[0] || t >= T[n - 1]) return;
-    int a = 0;
-    while (a + 2 < n && t >= T[a + 1]) ++a;
+    const int a = pwl_find(T, n, t);
     const double idt = 1.0 / (T[a + 1] - T[a]);
     for (int k = 0; k < 3; ++k) out[k] = (P[3 * (a + 1) + k] - P[3 * a + k]) * idt;
 }

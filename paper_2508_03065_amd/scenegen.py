@@ -261,6 +261,79 @@ def config5(seed: int = 5, n_scenes: int = 64, seconds: float = 10.0, max_order:
     return scenes, par
 
 
+def bandlimited_pwl(rng, size, seconds: float, max_speed: float, bandwidth: float = 1.0, knot_rate: float = 8.0,
+                    margin: float = 0.5, n_tones: int = 3, z_range: Tuple[float, float] = (1.2, 1.8)) -> Traj:
+    """A random band-limited path (Sec. II-C: trajectories are band-limited,
+    their spectrum falling with the square of the motion frequency), as a PWL
+    path with knot_rate knots per second: per horizontal axis a sum of n_tones
+    sinusoids with frequencies U(0.1, bandwidth) Hz and random phases, the height
+    a slower sinusoid inside z_range; amplitudes are scaled so the speed between
+    knots stays below max_speed and every knot stays margin inside the walls."""
+    t = np.arange(0.0, seconds + 1e-12, 1.0 / knot_rate)
+    if t[-1] < seconds:
+        t = np.append(t, seconds)
+    lo = np.array([margin, margin, z_range[0]])
+    hi = np.array([size[0] - margin, size[1] - margin, z_range[1]])
+    centre = 0.5 * (lo + hi)
+    half = 0.5 * (hi - lo)
+    shape = np.zeros((t.shape[0], 3))
+    for a in range(3):
+        f = rng.uniform(0.1, bandwidth if a < 2 else 0.5 * bandwidth, n_tones)
+        ph = rng.uniform(0, 2 * math.pi, n_tones)
+        w = rng.uniform(0.5, 1.0, n_tones)
+        shape[:, a] = np.sum(w[None, :] * np.sin(2 * math.pi * f[None, :] * t[:, None] + ph[None, :]), axis=1)
+    shape /= np.maximum(np.abs(shape).max(axis=0), 1e-12)     # each axis in [-1, 1]
+    amp = half * rng.uniform(0.3, 0.9, 3)
+    p = centre + shape * amp
+    v = np.linalg.norm(np.diff(p, axis=0), axis=1) / np.diff(t)
+    if v.max() > max_speed:
+        p = centre + (p - centre) * (max_speed / v.max())
+    return Traj.pwl(t, p)
+
+
+def e2_scenes(seed: int = 7, n_scenes: int = 12, seconds: float = 2.0, static_every: int = 11,
+              spacing: float = 0.15, sector_deg: float = 30.0, max_speed: float = 1.5,
+              max_order: Optional[int] = None) -> Tuple[List[Scene], Params, List[str]]:
+    """Data generation in the spirit of the paper's dynamic training set (Sec. III):
+    random rooms, a two-microphone pair 15 cm apart at a fixed receiver, sources
+    that are static in one scene out of every `static_every` (1:10 static to
+    dynamic) and otherwise follow band-limited random paths.  Each scene carries a
+    label: 'in' when the source starts within +-sector_deg of the pair's
+    broadside direction, else 'out' (the D_in / D_out split).  Orders come from
+    Sabine's rule unless max_order is given; tiers as in the paper-scale workload."""
+    rng = np.random.default_rng(seed)
+    par = Params(fs=16000.0, taps=64, tiers=PAPER_TIERS)
+    scenes, labels = [], []
+    n_in = int(round(seconds * par.fs))
+    for s in range(n_scenes):
+        size = np.array([rng.uniform(4, 8), rng.uniform(3, 6), rng.uniform(2.5, 3.5)])
+        beta = rng.uniform(0.7, 0.95, 6)
+        K = sabine_order(size, beta, par.c) if max_order is None else max_order
+        phi = rng.uniform(0, math.pi)                       # pair axis, horizontal
+        axis = np.array([math.cos(phi), math.sin(phi), 0.0])
+        mics = np.stack([-0.5 * spacing * axis, 0.5 * spacing * axis])
+        if s % static_every == 0:
+            src = Traj.static([rng.uniform(0.5, size[0] - 0.5), rng.uniform(0.5, size[1] - 0.5),
+                               rng.uniform(1.2, 1.8)])
+        else:
+            src = bandlimited_pwl(rng, size, seconds, max_speed)
+        # the receiver stays 0.5 m from the path (knots and segment midpoints)
+        pts = src.p if src.p.shape[0] == 1 else np.concatenate([src.p, 0.5 * (src.p[1:] + src.p[:-1])])
+        for _ in range(1000):
+            rcv = np.array([rng.uniform(1.0, size[0] - 1.0), rng.uniform(1.0, size[1] - 1.0), 1.5])
+            if np.min(np.linalg.norm(pts - rcv, axis=1)) > 0.5:
+                break
+        else:
+            raise RuntimeError("no receiver position 0.5 m away from the path")
+        d0 = src.p[0] - rcv
+        broadside = np.array([-axis[1], axis[0], 0.0])
+        cosang = abs(np.dot(d0[:2], broadside[:2])) / max(np.linalg.norm(d0[:2]), 1e-12)
+        labels.append("in" if cosang >= math.cos(math.radians(sector_deg)) else "out")
+        scenes.append(Scene(size, beta, src, Traj.static(rcv), mics, noise(rng, n_in),
+                            n_out_for(size, K, n_in, par.fs, par.c, par.taps), K))
+    return scenes, par, labels
+
+
 def small_scene(seed: int = 0, max_order: int = 3, seconds: float = 0.25, fs: float = 16000.0,
                 taps: int = 32, tiers=((1, 1), (2, 4), (1 << 20, 16)), n_mics: int = 1,
                 moving_rcv: bool = False, circle: bool = False, n_knots: int = 3,
