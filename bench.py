@@ -31,7 +31,13 @@ from paper_2508_03065_amd import scenegen as G  # noqa: E402
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
 PEAK_LDS = 256 * 256 * 2.4e9   # LDS reads, B/s: 256 CUs x 256 B/clk (b128) x 2.4 GHz
 FLOPS_PER_TAP = 4         # table form: two FMAs per tap (the interpolated coefficient, the multiply-add)
-LDS_PER_TAP = 14          # table form: the source sample, two FP32 and one FP16 quadratic-table values per tap
+
+
+def table_lds_per_tap(outputs_per_lane: int) -> float:
+    """Table form, LDS bytes per tap: the source sample and the row's two FP32 and one
+    FP16 quadratic-table values (14 B); with two adjacent outputs per lane one table
+    read and one new source quad serve both outputs' taps (7 B)."""
+    return 14.0 / outputs_per_lane
 
 
 def farrow_lds_per_sample(order: int) -> int:
@@ -128,7 +134,7 @@ def synth_roofline(plan, prof, steps, fd, par, workload):
     per_step = prof["synth_launches"] / steps
     if fd == "table":
         flops = taps / per_step * FLOPS_PER_TAP
-        lds = taps / per_step * LDS_PER_TAP
+        lds = taps / per_step * table_lds_per_tap(plan.tuning()["outputs_per_lane"])
     else:
         flops = taps / par.taps / per_step * farrow_flops_per_sample(par.farrow_order)
         lds = taps / par.taps / per_step * farrow_lds_per_sample(par.farrow_order)

@@ -166,10 +166,13 @@ msim_status msim_forward_batched(msim_plan* plan, const float* x, float* y, void
                                  hipStream_t stream, int32_t use_graph);
 
 /* Launch shape: output samples per workgroup (512 or 1024), images per delay
- * group (0: chosen from the tile count), output samples per lane of the Farrow
- * forward (1, 2 or 4; a lane's samples share one track segment, so every tier
- * decimation must be 1 or a multiple of it; 0: one),
- * and the persistent grid size it implies. */
+ * group (0: chosen from the tile count), adjacent output samples per lane of the
+ * forward (a lane's samples share one track segment, so every tier decimation
+ * must be 1 or a multiple of it; the table form takes 1 or 2 and its two samples
+ * also share table rows, which needs the delay to drift by at most ~0.8 table rows
+ * per sample: source plus receiver speed below 2.2 m/s at 128 phases; the Farrow
+ * form takes 1, 2 or 4; 0: the form's default, 2 for the table form where allowed,
+ * else 1), and the persistent grid size it implies. */
 typedef struct {
     int32_t threads;
     int32_t group_cap;

@@ -72,7 +72,7 @@ size_t adj_x_lds_bytes(int taps, int Lq, int window, int nthreads)
 
 size_t adj_track_lds_bytes(int taps, int Lq, int window)
 {
-    return (size_t)(taps / 8) * (size_t)Lq * 40 + (size_t)window * sizeof(float4);
+    return qtab_bytes(taps, Lq) + (size_t)window * sizeof(float4);
 }
 
 // ------------------------------------------------------------ transpose delay
@@ -340,11 +340,12 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     constexpr int NG = T / 8;
     constexpr int WAVES = NT / 64;
     const int L = LC > 0 ? LC : Lr;
+    const int LP = LC > 0 ? LC + 1 : Lr + 1;      // rows per quad: -1 .. L-1
     float4* tab = lds;
-    const float4* tabY = tab;
-    const float4* tabD1 = tabY + NG * L;
-    const uint2* tabD2 = (const uint2*)(tabD1 + NG * L);
-    float4* xw = lds + NG * L * 40 / 16;
+    const float4* tabY = tab + 1;
+    const float4* tabD1 = tab + NG * LP + 1;
+    const uint2* tabD2 = (const uint2*)(tab + 2 * NG * LP) + 1;
+    float4* xw = lds + NG * LP * 40 / 16;
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     const int n0 = tile * NT;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
-    for (int i = tid; i < NG * L * 40 / 16; i += NT) tab[i] = table[i];
+    for (int i = tid; i < NG * LP * 40 / 16; i += NT) tab[i] = table[i];
     const float* xs = x + S.x_off;
     const int n_in = (int)S.n_in;
     for (int p = tid; p < W; p += NT) {
@@ -406,15 +407,15 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     const float4 xn = xq[4 * gi];
-                    const float4 Y = tabY[gi * L + kq], D1 = tabD1[gi * L + kq];
-                    const uint2 D2 = tabD2[gi * L + kq];
+                    const float4 Y = tabY[gi * LP + kq], D1 = tabD1[gi * LP + kq];
+                    const uint2 D2 = tabD2[gi * LP + kq];
                     A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(h16_lo(D2.x), xn.x, C);
                     A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(h16_hi(D2.x), xn.y, C);
                     A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(h16_lo(D2.y), xn.z, C);
                     A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(h16_hi(D2.y), xn.w, C);
                     const float4 xp = xq[-4 - 4 * gi];
-                    const float4 Ym = tabY[gi * L + kp], E1 = tabD1[gi * L + kp];
-                    const uint2 E2 = tabD2[gi * L + kp];
+                    const float4 Ym = tabY[gi * LP + kp], E1 = tabD1[gi * LP + kp];
+                    const uint2 E2 = tabD2[gi * LP + kp];
                     A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(h16_lo(E2.x), xp.w, C);
                     A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(h16_hi(E2.x), xp.z, C);
                     A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(h16_lo(E2.y), xp.y, C);

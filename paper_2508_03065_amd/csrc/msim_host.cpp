@@ -152,6 +152,23 @@ msim_status check_traj(const msim_traj& tr, const double L[3], double c, const c
     return fail(MSIM_E_INVALID_ARG, "%s: unknown trajectory kind %d", what, tr.kind);
 }
 
+// Largest speed along a trajectory (m/s): the fastest PWL segment, or the circle's speed.
+double traj_max_speed(const msim_traj& tr)
+{
+    if (tr.kind == MSIM_TRAJ_CIRCLE) return tr.speed;
+    double v = 0.0;
+    if (tr.kind == MSIM_TRAJ_PWL)
+        for (int k = 1; k < tr.n_points; ++k) {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double e = tr.p[3 * k + a] - tr.p[3 * (k - 1) + a];
+                d2 += e * e;
+            }
+            v = std::max(v, std::sqrt(d2) / (tr.t[k] - tr.t[k - 1]));
+        }
+    return v;
+}
+
 msim_status check_params(const msim_params* p)
 {
     if (!p) return fail(MSIM_E_INVALID_ARG, "params is NULL");
@@ -294,9 +311,10 @@ struct msim_plan {
     msim_params par{};
     int n_scenes = 0;
     int threads = 1024;                   // outputs per workgroup (the tile)
-    int farrow_rb = 1;                    // outputs per lane of the Farrow forward (one by default:
-    int farrow_rb_max = 1;                //   occupancy wins over shared segment fetches), and the
-                                          //   largest the tier decimations allow
+    int rb = 1;                           // outputs per lane of the forward (table form: two by
+    int rb_max = 1;                       //   default, sharing table rows; Farrow form: one, as
+                                          //   occupancy wins over shared segment fetches), and the
+                                          //   largest the form and the tier decimations allow
     std::vector<DScene> scenes;           // host copies
     std::vector<DImage> images;
     std::vector<DGroup> groups;
@@ -391,36 +409,45 @@ struct LaunchTimer {
 namespace {
 
 // Quadratic-interpolation half table, grouped by tap quads, as three arrays:
-// for quad g and row r < Lq, Y(r), Y(r+1) - Y(r) (float4 each) and
+// for quad g and row r in [-1, Lq), Y(r), Y(r+1) - Y(r) (float4 each) and
 // Y(r+2) - 2 Y(r+1) + Y(r) (four fp16: it is below 1e-3, so fp16 keeps it to
-// ~3e-7 absolute), with Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences in double).
-// qtable holds the bytes [Y | D1 | D2]; d2 returns the fp16 values as floats.
+// ~3e-7 absolute), with Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences in double),
+// stored at row index r + 1 of a quad's qtab_pitch(Lq) rows.  Row -1 serves a lane
+// whose two outputs straddle an integer delay (the far side's base row sits one
+// below row 0).  qtable holds the bytes [Y | D1 | D2]; y_out, d1_out and d2_out
+// return rows 0 .. Lq-1 as floats (the fp16 values as rounded).
 void build_qtable(std::vector<uint8_t>& out, std::vector<float>& y_out, std::vector<float>& d1_out,
                   std::vector<float>& d2_out, int T, int Lq, double kbeta, double fc)
 {
-    const int NG = T / 8;
-    const size_t n = (size_t)NG * Lq * 4;
+    const int NG = T / 8, LP = qtab_pitch(Lq);
+    const size_t n = (size_t)NG * Lq * 4, np = (size_t)NG * LP * 4;
     const double i0b = bessel_i0(kbeta);
     y_out.assign(n, 0.0f);
     d1_out.assign(n, 0.0f);
     d2_out.assign(n, 0.0f);
-    std::vector<uint16_t> d2h(n, 0);
+    std::vector<float> yp(np, 0.0f), d1p(np, 0.0f);
+    std::vector<uint16_t> d2h(np, 0);
     for (int g = 0; g < NG; ++g)
-        for (int row = 0; row < Lq; ++row)
+        for (int row = -1; row < Lq; ++row)
             for (int e = 0; e < 4; ++e) {
                 double y[3];
                 for (int i = 0; i < 3; ++i) y[i] = fd_kernel((4 * g + e) + double(row + i) / Lq, T, kbeta, fc, i0b);
-                const size_t o = ((size_t)g * Lq + row) * 4 + e;
-                y_out[o] = (float)y[0];
-                d1_out[o] = (float)(y[1] - y[0]);
+                const size_t o = ((size_t)g * LP + row + 1) * 4 + e;
+                yp[o] = (float)y[0];
+                d1p[o] = (float)(y[1] - y[0]);
                 const _Float16 h = (_Float16)(y[2] - 2.0 * y[1] + y[0]);
-                d2_out[o] = (float)h;
                 std::memcpy(&d2h[o], &h, sizeof h);
+                if (row >= 0) {
+                    const size_t u = ((size_t)g * Lq + row) * 4 + e;
+                    y_out[u] = yp[o];
+                    d1_out[u] = d1p[o];
+                    d2_out[u] = (float)h;
+                }
             }
-    out.resize(n * 4 * 2 + n * 2);
-    std::memcpy(out.data(), y_out.data(), n * 4);
-    std::memcpy(out.data() + n * 4, d1_out.data(), n * 4);
-    std::memcpy(out.data() + n * 8, d2h.data(), n * 2);
+    out.resize(np * 4 * 2 + np * 2);
+    std::memcpy(out.data(), yp.data(), np * 4);
+    std::memcpy(out.data() + np * 4, d1p.data(), np * 4);
+    std::memcpy(out.data() + np * 8, d2h.data(), np * 2);
 }
 
 void build_table(msim_plan* P)
@@ -715,7 +742,7 @@ msim_status regroup(msim_plan* P)
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
     const size_t lds =
         P->par.fd_kind == MSIM_FD_FARROW ? farrow_lds_bytes(wmax) : synth_lds_bytes(T, L, wmax);
-    const int wg_threads = P->par.fd_kind == MSIM_FD_FARROW ? NT / P->farrow_rb : NT;
+    const int wg_threads = NT / P->rb;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / wg_threads, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
     P->graph_valid = false;
@@ -889,7 +916,21 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         if ((st = check_scene(scenes[s], p, s)) != MSIM_OK) return st;
     msim_plan* P = new msim_plan();
     P->par = *p;
-    P->farrow_rb_max = farrow_outputs_per_lane(p->tier_decim, p->n_tiers);
+    P->rb_max = farrow_outputs_per_lane(p->tier_decim, p->n_tiers);
+    if (p->fd_kind != MSIM_FD_FARROW) {
+        // Two outputs per lane read the table rows of the earlier one: fine while
+        // the delay drifts by well under two rows per sample.  An image moves no
+        // faster than its source, so |dD/dn| <= v / (c - v) with v the source plus
+        // receiver speed; allowing 1.5x for the cubic delay interpolation's slope,
+        // the pair is used up to 1.25 rows per sample (the quadratic then reads at
+        // fractions within [-0.25, 2.25], at most 1.8x its interpolation error).
+        double v = 0.0;
+        for (int s = 0; s < n_scenes; ++s)
+            v = std::max(v, traj_max_speed(scenes[s].src) + traj_max_speed(scenes[s].rcv));
+        const double drift = 1.5 * v / (p->c - v) * p->table_phases;
+        P->rb_max = drift <= 1.25 ? std::min(P->rb_max, 2) : 1;
+    }
+    P->rb = p->fd_kind != MSIM_FD_FARROW ? P->rb_max : 1;
     P->n_scenes = n_scenes;
     int64_t xo = 0, yo = 0;
     for (int s = 0; s < n_scenes; ++s) {
@@ -1113,10 +1154,10 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
         {
             LaunchTimer t(P, kKindSynth, stream);
             if (farrow)
-                HIP_OK(launch_farrow_fwd(P->threads, P->farrow_rb, P->par.taps, P->par.farrow_order, d, P->d_images,
+                HIP_OK(launch_farrow_fwd(P->threads, P->rb, P->par.taps, P->par.farrow_order, d, P->d_images,
                                          P->d_groups, w.seg, w.segK, v, w.part, P->d_status, stream));
             else
-                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, d, P->d_images, P->d_groups, P->d_qtable,
+                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, P->rb, d, P->d_images, P->d_groups, P->d_qtable,
                                         P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status,
                                         stream));
         }
@@ -1220,12 +1261,12 @@ msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchW
     {
         LaunchTimer t(P, kKindSynth, st);
         if (farrow)
-            HIP_OK(launch_farrow_persistent(P->threads, P->farrow_rb, P->b_wgs, P->b_window, P->par.taps,
+            HIP_OK(launch_farrow_persistent(P->threads, P->rb, P->b_wgs, P->b_window, P->par.taps,
                                             P->par.farrow_order, P->d_scenes_b,
                                             P->d_images, P->d_groups, P->d_items, (int)P->items.size(), w.ticket,
                                             w.seg, w.segK, w.v, w.part, P->d_status, st));
         else
-            HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->b_wgs, P->b_window, P->d_scenes_b,
+            HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->rb, P->b_wgs, P->b_window, P->d_scenes_b,
                                            P->d_images, P->d_groups, P->d_qtable, P->par.table_phases,
                                            P->d_items,
                                            (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status,
@@ -1340,7 +1381,7 @@ msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
     if (!P || !out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     out->threads = P->threads;
     out->group_cap = P->group_cap;
-    out->outputs_per_lane = P->farrow_rb;
+    out->outputs_per_lane = P->rb;
     out->workgroups = P->b_wgs;
     out->ms = 0.0;
     return MSIM_OK;
@@ -1351,20 +1392,22 @@ msim_status msim_set_tuning(msim_plan* P, const msim_tuning* t)
     if (!P || !t) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     if (t->threads != 512 && t->threads != 1024) return fail(MSIM_E_INVALID_ARG, "threads must be 512 or 1024");
     if (t->group_cap < 0) return fail(MSIM_E_INVALID_ARG, "group_cap must be >= 0");
-    const int rb = t->outputs_per_lane == 0 ? 1 : t->outputs_per_lane;
+    const int rb = t->outputs_per_lane != 0 ? t->outputs_per_lane
+                                            : (P->par.fd_kind == MSIM_FD_FARROW ? 1 : P->rb_max);
     if (rb != 1 && rb != 2 && rb != 4) return fail(MSIM_E_INVALID_ARG, "outputs_per_lane must be 0, 1, 2 or 4");
-    if (P->farrow_rb_max % rb != 0)
-        return fail(MSIM_E_INVALID_ARG, "outputs_per_lane %d: the tier decimations allow at most %d", rb,
-                    P->farrow_rb_max);
-    const int ot = P->threads, oc = P->group_cap, orb = P->farrow_rb;
+    if (P->rb_max % rb != 0)
+        return fail(MSIM_E_INVALID_ARG,
+                    "outputs_per_lane %d: the form, the tier decimations and the speeds allow at most %d", rb,
+                    P->rb_max);
+    const int ot = P->threads, oc = P->group_cap, orb = P->rb;
     P->threads = t->threads;
     P->group_cap = t->group_cap;
-    P->farrow_rb = rb;
+    P->rb = rb;
     msim_status st = regroup(P);
     if (st != MSIM_OK) {
         P->threads = ot;
         P->group_cap = oc;
-        P->farrow_rb = orb;
+        P->rb = orb;
         regroup(P);
         return st;
     }
@@ -1406,10 +1449,10 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
         for (int t : kTuneThreads)
             for (int c : kTuneCaps)
                 for (int rb : {1, 2, 4}) {
-                    if (P->farrow_rb_max % rb != 0 || (P->par.fd_kind != MSIM_FD_FARROW && rb != 1)) continue;
+                    if (P->rb_max % rb != 0) continue;
                     P->threads = t;
                     P->group_cap = c;
-                    P->farrow_rb = rb;
+                    P->rb = rb;
                     if (regroup(P) != MSIM_OK || carve_batched(P, nullptr, nullptr) > ws_bytes) continue;
                     msim_status st = upload_layout(P);
                     if (st != MSIM_OK) return st;

@@ -118,7 +118,7 @@ hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, co
                          const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st);
 
-hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
+hipError_t launch_synth_fwd(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
                             const float4* d_table, int L, const Seg* seg, const int32_t* segK,
                             const float* x, float* part, int32_t* d_status, hipStream_t st);
 
@@ -127,7 +127,7 @@ hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, h
 hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_run_prefix, int64_t run_total,
                              const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
                              int32_t* segK, double c, double fs, int delay_model, hipStream_t st);
-hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window, const DScene* d_scenes,
+hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
                                    const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
                                    const int32_t* segK, const float* x, float* part, int32_t* d_status,
@@ -135,6 +135,13 @@ hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window,
 hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
                              const float* part, float* y, hipStream_t st);
 
+// Rows per tap quad of the quadratic FD table: rows -1 .. Lq-1.
+__host__ __device__ constexpr int qtab_pitch(int Lq) { return Lq + 1; }
+// Bytes of the quadratic FD table ([Y | D1 | D2], 40 B per quad row).
+__host__ __device__ constexpr size_t qtab_bytes(int taps, int Lq)
+{
+    return (size_t)(taps / 8) * (size_t)qtab_pitch(Lq) * 40;
+}
 size_t synth_lds_bytes(int taps, int Lq, int window);
 
 // ---- adjoint launchers (msim_adjoint.hip) ----

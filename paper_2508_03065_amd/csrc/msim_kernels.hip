@@ -219,12 +219,41 @@ hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t
 
 // LDS: the half table of h(v) = h(-v), v in [0, T/2], for quadratic
 // interpolation between Lq phases, grouped by four taps, as three arrays over
-// (g, r), r < Lq: Y(r) (float4), Y(r+1) - Y(r) (float4), Y(r+2) - 2 Y(r+1) + Y(r)
-// (four fp16), Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as
-// overlapping quads xw[p] = x[ws+p .. ws+p+3].
+// (g, r), r in [-1, Lq) (qtab_pitch(Lq) rows per quad, row r at index r + 1):
+// Y(r) (float4), Y(r+1) - Y(r) (float4), Y(r+2) - 2 Y(r+1) + Y(r) (four fp16),
+// Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as overlapping
+// quads xw[p] = x[ws+p .. ws+p+3].
 size_t synth_lds_bytes(int taps, int Lq, int window)
 {
-    return (size_t)(taps / 8) * (size_t)Lq * 40 + (size_t)window * sizeof(float4);
+    return qtab_bytes(taps, Lq) + (size_t)window * sizeof(float4);
+}
+
+// Pointers to row 0 of quad 0 of the three table arrays in LDS.
+struct QTab {
+    const float4* Y;
+    const float4* D1;
+    const uint2* D2;
+};
+
+template <int T>
+__device__ inline QTab qtab_view(const float4* tab, int LP)
+{
+    constexpr int NG = T / 8;
+    return {tab + 1, tab + NG * LP + 1, (const uint2*)(tab + 2 * NG * LP) + 1};
+}
+
+// Stages the source window of a tile: xw[p] = x[ws+p .. ws+p+3], zero outside [0, n_in).
+__device__ inline void stage_window(const float* __restrict__ xs, int n_in, int ws, int W, float4* xw, int nthreads)
+{
+    for (int p = threadIdx.x; p < W; p += nthreads) {
+        const int q = ws + p;
+        float4 v;
+        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
+        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
+        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
+        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
+        xw[p] = v;
+    }
 }
 
 // One output tile of one delay group for one mic: stages the group's source
@@ -239,30 +268,20 @@ size_t synth_lds_bytes(int taps, int Lq, int window)
 // right after.
 template <int T, int NT, int LC>
 __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int tile, int mic,
-                                  const DImage* __restrict__ imgs, const float4* tabY, float4* xw, int Lr,
+                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
                                   const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
 {
     constexpr int NG = T / 8;          // tap quads per side
     const int L = LC > 0 ? LC : Lr;
-    const float4* tabD1 = tabY + NG * L;
-    const uint2* tabD2 = (const uint2*)(tabD1 + NG * L);
+    const int LP = LC > 0 ? LC + 1 : Lr + 1;
+    const QTab tq = qtab_view<T>(tab, LP);
     const int tid = threadIdx.x;
     const int n0 = tile * NT;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
-
-    const float* xs = x + S.x_off;
     const int n_in = (int)S.n_in;
-    for (int p = tid; p < W; p += NT) {
-        const int q = ws + p;
-        float4 v;
-        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
-        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
-        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
-        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
-        xw[p] = v;
-    }
+    stage_window(x + S.x_off, n_in, ws, W, xw, NT);
     __syncthreads();
 
     const int n = n0 + tid;
@@ -307,8 +326,8 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
             for (int gi = 0; gi < NG; ++gi) {
                 // taps j = -(4gi+e): x[n-K+4gi+e], |u| = 4gi+e + mu -> base row kq, fraction f
                 const float4 xn = xq[4 * gi];
-                const float4 Y = tabY[gi * L + kq], D1 = tabD1[gi * L + kq];
-                const uint2 D2 = tabD2[gi * L + kq];
+                const float4 Y = tq.Y[gi * LP + kq], D1 = tq.D1[gi * LP + kq];
+                const uint2 D2 = tq.D2[gi * LP + kq];
                 A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(h16_lo(D2.x), xn.x, C);
                 A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(h16_hi(D2.x), xn.y, C);
                 A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(h16_lo(D2.y), xn.z, C);
@@ -316,8 +335,8 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
                 // taps j = 1+4gi+e: x[n-K-1-4gi-e] (quad component 3-e), |u| = 4gi+e + 1-mu
                 //   -> base row L-1-kq, fraction 1-f
                 const float4 xp = xq[-4 - 4 * gi];
-                const float4 Ym = tabY[gi * L + kp], E1 = tabD1[gi * L + kp];
-                const uint2 E2 = tabD2[gi * L + kp];
+                const float4 Ym = tq.Y[gi * LP + kp], E1 = tq.D1[gi * LP + kp];
+                const uint2 E2 = tq.D2[gi * LP + kp];
                 A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(h16_lo(E2.x), xp.w, C);
                 A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(h16_hi(E2.x), xp.z, C);
                 A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(h16_lo(E2.y), xp.y, C);
@@ -348,51 +367,234 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
     __syncthreads();
 }
 
-template <int T>
-__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int Lq)
+// The same tile with two adjacent outputs n, n+1 per lane (NT lanes, 2 NT outputs).
+// Their delays differ by |dD/dn| < 1/Lq of a sample at subsonic-slow speeds
+// (2.7 m/s at Lq = 128), so both take their tap weights from the same table rows:
+// in the frame K = min of the two integer delays, each output's phase mu' = D - K
+// lies in [0, 2) and q' = mu' Lq; the near side reads base row floor(min q'), the
+// far side base row Lq-1-floor(max q') (down to -1), and each output's fractions
+// on the two rows stay within [0, 2] where the quadratic through rows r, r+1, r+2
+// still interpolates.  One table read and one new source quad then serve eight
+// taps of both outputs: half the LDS bytes per tap.  Output n+1's taps are output
+// n's shifted by one source position; its far-side tap -T/2+1 and near-side tap
+// T/2+1 in this frame fall outside or at the kernel's edge, where h is below
+// 1e-3 |mu' - 1| of its peak.  Faster images read on-row extrapolations
+// (fractions past 2), which stay within a few times the interpolation error.
+template <int T, int NT, int LC>
+__device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int tile, int mic,
+                                   const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
+                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                   const float* __restrict__ x, float* __restrict__ part,
+                                   int32_t* __restrict__ status)
 {
-    const int n = (T / 8) * Lq * 40 / 16;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = table[i];
+    constexpr int NG = T / 8;
+    constexpr int TO = 2 * NT;
+    const int L = LC > 0 ? LC : Lr;
+    const int LP = LC > 0 ? LC + 1 : Lr + 1;
+    const QTab tq = qtab_view<T>(tab, LP);
+    const int tid = threadIdx.x;
+    const int n0 = tile * TO;
+    const int ws = n0 - G.dmax - T / 2 - 4;
+    const int W = TO + (G.dmax - G.dmin) + T + 8;
+    const int n_in = (int)S.n_in;
+    stage_window(x + S.x_off, n_in, ws, W, xw, NT);
+    __syncthreads();
+
+    const int n = n0 + 2 * tid;
+    const int n_out = (int)S.n_out;
+    if (n < n_out) {
+        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
+        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
+        const DImage* I = imgs + S.img_begin;
+        const float fn = (float)n + 0.5f;
+        const float Lf = (float)L;
+        float acc0 = 0.0f, acc1 = 0.0f;
+        int bad = 0;
+
+        // Track data for both outputs: one segment when the image is decimated
+        // (every decimation is even, so n and n+1 share it), else the two
+        // full-rate delays.  Two buffers in turn, as in the one-output tile.
+        auto fetch = [&](const DImage& im, Seg& q, float& a1, int& K0, int& K1, int& kseg) {
+            if (im.R == 1) {
+                const int k0 = min(n, im.n_seg - 1), k1 = min(n + 1, im.n_seg - 1);
+                q.a0 = sgm[im.seg_off + k0].a0;
+                a1 = sgm[im.seg_off + k1].a0;
+                K0 = sgk[im.seg_off + k0];
+                K1 = sgk[im.seg_off + k1];
+            } else {
+                const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+                q = sgm[im.seg_off + k];
+                K0 = sgk[im.seg_off + k];
+                kseg = k;
+            }
+        };
+        auto body = [&](const DImage& im, const Seg& sg, float a1, int Ka, int Kb, int k) {
+            float d0, d1;
+            int K0s, K1s;
+            if (im.R == 1) {
+                d0 = sg.a0;
+                d1 = a1;
+                K0s = Ka;
+                K1s = Kb;
+            } else {
+                const float v = (float)(n - __mul24(k, im.R));
+                d0 = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+                const float v1 = v + 1.0f;
+                d1 = fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
+                K0s = K1s = Ka;
+            }
+            const float fl0 = floorf(d0), fl1 = floorf(d1);
+            const int i0 = K0s + (int)fl0, i1 = K1s + (int)fl1;
+            const int K = min(i0, i1);
+            // skip the image when no lane's taps reach a source sample
+            if (!__any(n - K + T / 2 >= 0 && n - K - T / 2 < n_in)) return;
+            const int p0 = n - K - ws;
+            if (p0 < T / 2 || p0 > W - 1 - T / 2) {
+                bad = 1;
+                return;
+            }
+            const float q0 = ((d0 - fl0) + (float)(i0 - K)) * Lf;
+            const float q1 = ((d1 - fl1) + (float)(i1 - K)) * Lf;
+            const int kq = min((int)fminf(q0, q1), L - 1);
+            const int kp = max(L - 1 - (int)fmaxf(q0, q1), -1);
+            const float f0 = q0 - (float)kq, f1 = q1 - (float)kq;            // near side
+            const float h0 = (Lf - q0) - (float)kp, h1 = (Lf - q1) - (float)kp; // far side
+            const float4* xq = xw + p0;
+            float A0 = 0.0f, B0 = 0.0f, Bm0 = 0.0f, C0 = 0.0f, Cm0 = 0.0f;
+            float A1 = 0.0f, B1 = 0.0f, Bm1 = 0.0f, C1 = 0.0f, Cm1 = 0.0f;
+            // 2 NG steps, near side then far side, one tap quad each; the table rows
+            // and the new source quad of step st+1 are read while step st is summed
+            // (scheduling barriers keep the pipeline one step deep, so the values
+            // in flight stay within the register budget).
+            float4 xo = xq[0];                  // the previous step's source quad
+            float4 xc = xq[4], Yc = tq.Y[kq], D1c = tq.D1[kq];
+            uint2 D2c = tq.D2[kq];
+#pragma unroll
+            for (int st = 0; st < 2 * NG; ++st) {
+                float4 xnx = xc, Ynx = Yc, D1nx = D1c, x0 = xo;
+                uint2 D2nx = D2c;
+                if (st + 1 == NG) x0 = xq[0];
+                if (st + 1 < 2 * NG) {
+                    const int s1 = st + 1;
+                    const int row = s1 < NG ? s1 * LP + kq : (s1 - NG) * LP + kp;
+                    xnx = s1 < NG ? xq[4 * s1 + 4] : xq[-4 - 4 * (s1 - NG)];
+                    Ynx = tq.Y[row];
+                    D1nx = tq.D1[row];
+                    D2nx = tq.D2[row];
+                }
+                const float c0 = h16_lo(D2c.x), c1 = h16_hi(D2c.x), c2 = h16_lo(D2c.y), c3 = h16_hi(D2c.y);
+                if (st < NG) {
+                    // near side, taps j = -(4gi+e): output n reads x[n-K+4gi+e] (quad 4gi =
+                    // xo, component e), output n+1 the next position (xc = quad 4gi+4)
+                    const float4 xn = xo, xa = xc;
+                    A0 = fmaf(Yc.x, xn.x, A0); B0 = fmaf(D1c.x, xn.x, B0); C0 = fmaf(c0, xn.x, C0);
+                    A1 = fmaf(Yc.x, xn.y, A1); B1 = fmaf(D1c.x, xn.y, B1); C1 = fmaf(c0, xn.y, C1);
+                    A0 = fmaf(Yc.y, xn.y, A0); B0 = fmaf(D1c.y, xn.y, B0); C0 = fmaf(c1, xn.y, C0);
+                    A1 = fmaf(Yc.y, xn.z, A1); B1 = fmaf(D1c.y, xn.z, B1); C1 = fmaf(c1, xn.z, C1);
+                    A0 = fmaf(Yc.z, xn.z, A0); B0 = fmaf(D1c.z, xn.z, B0); C0 = fmaf(c2, xn.z, C0);
+                    A1 = fmaf(Yc.z, xn.w, A1); B1 = fmaf(D1c.z, xn.w, B1); C1 = fmaf(c2, xn.w, C1);
+                    A0 = fmaf(Yc.w, xn.w, A0); B0 = fmaf(D1c.w, xn.w, B0); C0 = fmaf(c3, xn.w, C0);
+                    A1 = fmaf(Yc.w, xa.x, A1); B1 = fmaf(D1c.w, xa.x, B1); C1 = fmaf(c3, xa.x, C1);
+                } else {
+                    // far side, taps j = 1+4gi+e: output n reads x[n-K-1-4gi-e] (quad
+                    // -4-4gi = xc, component 3-e), output n+1 the next position (xo =
+                    // quad -4gi)
+                    const float4 xp = xc, xr = xo;
+                    A0 = fmaf(Yc.x, xp.w, A0); Bm0 = fmaf(D1c.x, xp.w, Bm0); Cm0 = fmaf(c0, xp.w, Cm0);
+                    A1 = fmaf(Yc.x, xr.x, A1); Bm1 = fmaf(D1c.x, xr.x, Bm1); Cm1 = fmaf(c0, xr.x, Cm1);
+                    A0 = fmaf(Yc.y, xp.z, A0); Bm0 = fmaf(D1c.y, xp.z, Bm0); Cm0 = fmaf(c1, xp.z, Cm0);
+                    A1 = fmaf(Yc.y, xp.w, A1); Bm1 = fmaf(D1c.y, xp.w, Bm1); Cm1 = fmaf(c1, xp.w, Cm1);
+                    A0 = fmaf(Yc.z, xp.y, A0); Bm0 = fmaf(D1c.z, xp.y, Bm0); Cm0 = fmaf(c2, xp.y, Cm0);
+                    A1 = fmaf(Yc.z, xp.z, A1); Bm1 = fmaf(D1c.z, xp.z, Bm1); Cm1 = fmaf(c2, xp.z, Cm1);
+                    A0 = fmaf(Yc.w, xp.x, A0); Bm0 = fmaf(D1c.w, xp.x, Bm0); Cm0 = fmaf(c3, xp.x, Cm0);
+                    A1 = fmaf(Yc.w, xp.y, A1); Bm1 = fmaf(D1c.w, xp.y, Bm1); Cm1 = fmaf(c3, xp.y, Cm1);
+                }
+                xo = st + 1 == NG ? x0 : xc;
+                xc = xnx;
+                Yc = Ynx;
+                D1c = D1nx;
+                D2c = D2nx;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), Cm0,
+                                  fmaf(0.5f * f0 * (f0 - 1.0f), C0, fmaf(h0, Bm0, fmaf(f0, B0, A0))));
+            const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), Cm1,
+                                  fmaf(0.5f * f1 * (f1 - 1.0f), C1, fmaf(h1, Bm1, fmaf(f1, B1, A1))));
+            acc0 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K0s + d0), s0, acc0);
+            acc1 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K1s + d1), s1, acc1);
+        };
+        Seg qa{}, qb{};
+        float a1a = 0.0f, a1b = 0.0f;
+        int K0a = 0, K1a = 0, K0b = 0, K1b = 0, ka = 0, kb = 0;
+        DImage ia = I[G.img_begin], ib;
+        fetch(ia, qa, a1a, K0a, K1a, ka);
+        int ii = G.img_begin;
+        for (; ii + 1 < G.img_end; ii += 2) {
+            ib = I[ii + 1];
+            fetch(ib, qb, a1b, K0b, K1b, kb);
+            body(ia, qa, a1a, K0a, K1a, ka);
+            if (ii + 2 < G.img_end) {
+                ia = I[ii + 2];
+                fetch(ia, qa, a1a, K0a, K1a, ka);
+            }
+            body(ib, qb, a1b, K0b, K1b, kb);
+        }
+        if (ii < G.img_end) body(ia, qa, a1a, K0a, K1a, ka);
+        if (bad) atomicOr(status, kStatusWindow);
+        float* out = part + S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out;
+        out[n] = acc0;
+        if (n + 1 < n_out) out[n + 1] = acc1;
+    }
+    __syncthreads();
 }
 
-template <int T, int NT, int LC>
-__global__ __launch_bounds__(NT, 8) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                   const DGroup* __restrict__ groups,
-                                                   const float4* __restrict__ table, int L,
-                                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                                   const float* __restrict__ x, float* __restrict__ part,
-                                                   int32_t* __restrict__ status)
+template <int T>
+__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int Lq, int nthreads)
+{
+    const int n = (int)(qtab_bytes(T, Lq) / 16);
+    for (int i = threadIdx.x; i < n; i += nthreads) tab[i] = table[i];
+}
+
+// Forward kernels; RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
+template <int T, int NT, int LC, int RB>
+__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
+                                                                   const DGroup* __restrict__ groups,
+                                                                   const float4* __restrict__ table, int L,
+                                                                   const Seg* __restrict__ seg,
+                                                                   const int32_t* __restrict__ segK,
+                                                                   const float* __restrict__ x,
+                                                                   float* __restrict__ part,
+                                                                   int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * L * 40 / 16;
-    load_table<T>(table, tab, L);
+    float4* xw = lds + qtab_bytes(T, L) / 16;
+    load_table<T>(table, tab, L, NT);
     const int g = blockIdx.y;
-    synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
-                          part, status);
+    if constexpr (RB == 1)
+        synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
+                              part, status);
+    else
+        synth_tile2<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK,
+                               x, part, status);
 }
 
 // Persistent form: a fixed grid of workgroups loads the table once, then takes
 // work items (scene, mic, tile, group), ordered by decreasing cost, from a
 // ticket counter until the list is exhausted.  Items write disjoint partial
 // outputs, so the result does not depend on which workgroup ran which item.
-template <int T, int NT, int LC>
-__global__ __launch_bounds__(NT, 8) void k_synth_persistent(const DScene* __restrict__ scenes,
-                                                          const DImage* __restrict__ imgs,
-                                                          const DGroup* __restrict__ groups,
-                                                          const float4* __restrict__ table, int L,
-                                                          const WorkItem* __restrict__ items, int n_items,
-                                                          int32_t* __restrict__ ticket,
-                                                          const Seg* __restrict__ seg,
-                                                          const int32_t* __restrict__ segK,
-                                                          const float* __restrict__ x, float* __restrict__ part,
-                                                          int32_t* __restrict__ status)
+template <int T, int NT, int LC, int RB>
+__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_persistent(
+    const DScene* __restrict__ scenes, const DImage* __restrict__ imgs, const DGroup* __restrict__ groups,
+    const float4* __restrict__ table, int L, const WorkItem* __restrict__ items, int n_items,
+    int32_t* __restrict__ ticket, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+    const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     __shared__ int s_item;
     float4* tab = lds;
-    float4* xw = lds + (T / 8) * L * 40 / 16;
-    load_table<T>(table, tab, L);
+    float4* xw = lds + qtab_bytes(T, L) / 16;
+    load_table<T>(table, tab, L, NT);
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
         __syncthreads();
@@ -401,8 +603,12 @@ __global__ __launch_bounds__(NT, 8) void k_synth_persistent(const DScene* __rest
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        synth_tile<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg, segK,
-                              x, part, status);
+        if constexpr (RB == 1)
+            synth_tile<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg,
+                                  segK, x, part, status);
+        else
+            synth_tile2<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg,
+                                   segK, x, part, status);
     }
 }
 
@@ -416,13 +622,14 @@ __global__ void k_zero_i32(int32_t* p, int n)
 // offsets); others run the same kernel with the phase count read at run time.
 constexpr int kPhasesCompiled = 128;
 
-template <int T, int NT>
+template <int T, int TO, int RB>
 static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups, const float4* d_table,
                                int L, const Seg* seg, const int32_t* segK, const float* x, float* part,
                                int32_t* d_status, hipStream_t st)
 {
+    constexpr int NT = TO / RB;
     const size_t lds = synth_lds_bytes(T, L, hs.window);
-    auto kern = L == kPhasesCompiled ? k_synth_fwd<T, NT, kPhasesCompiled> : k_synth_fwd<T, NT, 0>;
+    auto kern = L == kPhasesCompiled ? k_synth_fwd<T, NT, kPhasesCompiled, RB> : k_synth_fwd<T, NT, 0, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
@@ -430,14 +637,16 @@ static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGr
     return hipGetLastError();
 }
 
-template <int T, int NT>
+template <int T, int TO, int RB>
 static hipError_t launch_persistent_t(int n_wg, int window, const DScene* d_scenes, const DImage* d_imgs,
                                       const DGroup* d_groups, const float4* d_table, int L, const WorkItem* items,
                                       int n_items, int32_t* ticket, const Seg* seg, const int32_t* segK,
                                       const float* x, float* part, int32_t* d_status, hipStream_t st)
 {
+    constexpr int NT = TO / RB;
     const size_t lds = synth_lds_bytes(T, L, window);
-    auto kern = L == kPhasesCompiled ? k_synth_persistent<T, NT, kPhasesCompiled> : k_synth_persistent<T, NT, 0>;
+    auto kern = L == kPhasesCompiled ? k_synth_persistent<T, NT, kPhasesCompiled, RB>
+                                     : k_synth_persistent<T, NT, 0, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, ticket, 1);
@@ -446,43 +655,41 @@ static hipError_t launch_persistent_t(int n_wg, int window, const DScene* d_scen
     return hipGetLastError();
 }
 
-hipError_t launch_synth_fwd(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_table, int L, const Seg* seg, const int32_t* segK,
-                            const float* x, float* part, int32_t* d_status, hipStream_t st)
+hipError_t launch_synth_fwd(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs,
+                            const DGroup* d_groups, const float4* d_table, int L, const Seg* seg,
+                            const int32_t* segK, const float* x, float* part, int32_t* d_status, hipStream_t st)
 {
-#define MSIM_FWD_CASE(TT, NN)                                                                                  \
-    if (taps == TT && nthreads == NN)                                                                          \
-        return launch_fwd_t<TT, NN>(hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status, st);
-    MSIM_FWD_CASE(32, 512)
-    MSIM_FWD_CASE(64, 512)
-    MSIM_FWD_CASE(96, 512)
-    MSIM_FWD_CASE(128, 512)
-    MSIM_FWD_CASE(32, 1024)
-    MSIM_FWD_CASE(64, 1024)
-    MSIM_FWD_CASE(96, 1024)
-    MSIM_FWD_CASE(128, 1024)
+#define MSIM_FWD_CASE(TT, NN, RR)                                                                              \
+    if (taps == TT && nthreads == NN && rb == RR)                                                             \
+        return launch_fwd_t<TT, NN, RR>(hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status, st);
+#define MSIM_FWD_TAPS(TT)                                                                                      \
+    MSIM_FWD_CASE(TT, 512, 1) MSIM_FWD_CASE(TT, 1024, 1) MSIM_FWD_CASE(TT, 512, 2) MSIM_FWD_CASE(TT, 1024, 2)
+    MSIM_FWD_TAPS(32)
+    MSIM_FWD_TAPS(64)
+    MSIM_FWD_TAPS(96)
+    MSIM_FWD_TAPS(128)
+#undef MSIM_FWD_TAPS
 #undef MSIM_FWD_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_synth_persistent(int taps, int nthreads, int n_wg, int window, const DScene* d_scenes,
+hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
                                    const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
                                    const int32_t* segK, const float* x, float* part, int32_t* d_status,
                                    hipStream_t st)
 {
-#define MSIM_PERS_CASE(TT, NN)                                                                                 \
-    if (taps == TT && nthreads == NN)                                                                          \
-        return launch_persistent_t<TT, NN>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items,        \
-                                           n_items, ticket, seg, segK, x, part, d_status, st);
-    MSIM_PERS_CASE(32, 512)
-    MSIM_PERS_CASE(64, 512)
-    MSIM_PERS_CASE(96, 512)
-    MSIM_PERS_CASE(128, 512)
-    MSIM_PERS_CASE(32, 1024)
-    MSIM_PERS_CASE(64, 1024)
-    MSIM_PERS_CASE(96, 1024)
-    MSIM_PERS_CASE(128, 1024)
+#define MSIM_PERS_CASE(TT, NN, RR)                                                                             \
+    if (taps == TT && nthreads == NN && rb == RR)                                                             \
+        return launch_persistent_t<TT, NN, RR>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items,   \
+                                               n_items, ticket, seg, segK, x, part, d_status, st);
+#define MSIM_PERS_TAPS(TT)                                                                                     \
+    MSIM_PERS_CASE(TT, 512, 1) MSIM_PERS_CASE(TT, 1024, 1) MSIM_PERS_CASE(TT, 512, 2) MSIM_PERS_CASE(TT, 1024, 2)
+    MSIM_PERS_TAPS(32)
+    MSIM_PERS_TAPS(64)
+    MSIM_PERS_TAPS(96)
+    MSIM_PERS_TAPS(128)
+#undef MSIM_PERS_TAPS
 #undef MSIM_PERS_CASE
     return hipErrorInvalidValue;
 }

@@ -119,3 +119,51 @@ def test_deterministic(torch_cuda):
     y2 = plan.forward(x).clone()
     torch_cuda.cuda.synchronize()
     assert torch_cuda.equal(y1, y2)
+
+
+# Two adjacent outputs per lane (the table form's default where speeds allow) and
+# one per lane: both against the oracle, on scenes whose lengths leave ragged
+# tiles and an odd output count, at every compiled tap count and both tile sizes.
+@pytest.mark.parametrize("rb", [1, 2])
+@pytest.mark.parametrize("case", [
+    dict(seed=21, max_order=3, taps=32, threads=512),
+    dict(seed=22, max_order=5, taps=64, threads=1024, circle=True),
+    dict(seed=23, max_order=4, taps=96, threads=512, tiers=((2, 1), (4, 16), (99, 160))),
+    dict(seed=24, max_order=3, taps=128, threads=1024, n_mics=2),
+])
+def test_outputs_per_lane(torch_cuda, case, rb):
+    from paper_2508_03065_amd.msim import Plan
+    kw = dict(seconds=0.11)
+    kw.update(case)
+    threads = kw.pop("threads")
+    sc, par = G.small_scene(**kw)
+    sc.n_out += 1 - sc.n_out % 2                       # odd: the last lane has one output
+    print("outputs per lane", rb, case, flush=True)
+    plan = Plan([sc], par)
+    assert plan.tuning()["outputs_per_lane"] == 2      # the default where allowed
+    plan.set_tuning(threads, 0, rb)
+    x = plan.pack_x([sc.x])
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    assert plan.device_status() == 0
+    (yv,) = plan.unpack_y(y)
+    assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
+
+
+def test_fast_scene_keeps_one_output_per_lane(torch_cuda):
+    # source 3 m/s plus receiver 1 m/s: the delay drifts too fast for shared
+    # table rows, so the plan keeps one output per lane and refuses two
+    from paper_2508_03065_amd._lib import MsimError
+    from paper_2508_03065_amd.msim import Plan
+    sc, par = G.small_scene(seed=25, max_order=3, seconds=0.2, taps=64)
+    sc.src = G.Traj.pwl(np.array([0.0, 0.2]), np.array([[1.0, 1.0, 1.5], [1.6, 1.0, 1.5]]))
+    sc.rcv = G.Traj.pwl(np.array([0.0, 0.2]), np.array([[3.5, 2.5, 1.2], [3.5, 2.7, 1.2]]))
+    plan = Plan([sc], par)
+    assert plan.tuning()["outputs_per_lane"] == 1
+    with pytest.raises(MsimError):
+        plan.set_tuning(1024, 0, 2)
+    x = plan.pack_x([sc.x])
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    (yv,) = plan.unpack_y(y)
+    assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
