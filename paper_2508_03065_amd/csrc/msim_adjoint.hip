@@ -2,8 +2,7 @@
 //
 // The forward map is y_c[n] = sum_i g_i(n) s_i(n),  s_i(n) = sum_j h(j - mu_i(n)) x[n - K_i(n) - j],
 // with D_i(n) = K_i(n) + mu_i(n) the Catmull-Rom interpolated delay and
-// g_i(n) = beta_i fs / (4 pi c D_i(n))  (Eq. 2 / Eq. 8, Sec. II-B, Sec. II-C-3).
-// Given gy = dL/dy:
+// g_i(n) = beta_i fs / (4 pi c D_i(n))  (Eq. 2 / Eq. 8, Sec. II-B, Sec. II-C-3),
 // with h the forward's quadratic interpolation of the Kaiser-windowed sinc.  Given gy = dL/dy:
 //   adj_x      : dL/dx[m] = sum_{c,i,n} gy_c[n] g_i(n) h(n - D_i(n) - m), the transpose
 //                time-varying fractional delay, accumulated per wave in a shifting
@@ -19,6 +18,7 @@
 //   reduce     : fixed-order reductions to dL/dbeta_w and dL/dP_knot.
 #include "msim_device.h"
 #include "msim_internal.h"
+#include "msim_pair.h"
 
 #include <hip/hip_runtime.h>
 
@@ -62,8 +62,10 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b)
 }  // namespace
 
 // The transpose reads the forward's quadratic table, rearranged tap-major:
-// three arrays Y, D1, D2 of [T/2][Lq] floats; then each wave owns a window of
-// (window - NT + 64) samples: its 64 outputs' taps under every delay of the group.
+// three arrays Y, D1, D2 of [T/2][Lq] floats (a packed {Y, D1, D2, 0} per tap and
+// row, one b96 read instead of three b32, measured 25 % slower); then each wave
+// owns a window of (window - NT + 64) samples: its 64 outputs' taps under every
+// delay of the group.
 size_t adj_x_lds_bytes(int taps, int Lq, int window, int nthreads)
 {
     return (size_t)3 * (taps / 2) * (size_t)Lq * sizeof(float) +
@@ -108,6 +110,8 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
     float* tD1 = tY + H * LQ;
     float* tD2 = tD1 + H * LQ;
     float* wbase = tD2 + H * LQ;
+    // the interpolated tap weight a Y + b D1 + c D2 at table index i (tap-major)
+    auto wt = [&](int i, float a, float b, float c) { return fmaf(a, tY[i], fmaf(b, tD1[i], c * tD2[i])); };
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -178,8 +182,8 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
                 if (!reach || (pass == 0 ? dup : !dup)) continue;
                 for (int dd = 0; dd < H; ++dd) {
                     const int in = dd * LQ + kq, ifr = dd * LQ + rf;
-                    xb[p0 + dd] += fmaf(A, tY[in], fmaf(Bn, tD1[in], C * tD2[in]));
-                    xb[p0 - 1 - dd] += fmaf(A, tY[ifr], fmaf(Bf, tD1[ifr], C * tD2[ifr]));
+                    xb[p0 + dd] += wt(in, A, Bn, C);
+                    xb[p0 - 1 - dd] += wt(ifr, A, Bf, C);
                     __builtin_amdgcn_wave_barrier();
                 }
             }
@@ -190,14 +194,8 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
         // (d = s - H - 1 + dK) pN + (s-H-1) LQ
         const int pF = (1 - dK) * LQ + rf;
         const int pN = dK * LQ + kq;
-        auto far = [&](int s) {
-            const int i = pF + (H - 1 - s) * LQ;
-            return fmaf(A, tY[i], fmaf(Bf, tD1[i], C * tD2[i]));
-        };
-        auto near = [&](int s) {
-            const int i = pN + (s - H - 1) * LQ;
-            return fmaf(A, tY[i], fmaf(Bn, tD1[i], C * tD2[i]));
-        };
+        auto far = [&](int s) { return wt(pF + (H - 1 - s) * LQ, A, Bf, C); };
+        auto near = [&](int s) { return wt(pN + (s - H - 1) * LQ, A, Bn, C); };
         // relative position (to n0w - kmin) of lane l at step s: l + s - H - 1
         const int rel0 = n0w - kmin - wsw;               // window index of relative position 0
         float acc, out = 0.0f;
@@ -207,30 +205,28 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
                 acc = c;
                 return;
             }
-            const float dep = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 0));
+            // the value leaving lane 0 is parked in lane (s-1) mod 64 of `out`
+            // (v_writelane takes the lane from a scalar and ignores EXEC; every
+            // lane of the wave runs this path)
+            const int dep = __builtin_amdgcn_readlane(__float_as_int(acc), 0);
             acc = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x130, 0xF, 0xF, true)) + c;
-            out = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(out), 0x130, 0xF, 0xF, true));
-            out = lane == 63 ? dep : out;
+            asm("v_writelane_b32 %0, %1, %2" : "+v"(out) : "s"(dep), "i"((s - 1) & 63));
             if (++ndep == 64) {
                 // departures of steps s-64 .. s-1 sit in lanes 0..63
                 const int pw = rel0 + (s - 64 + lane) - H - 1;
                 xb[pw] += out;
-                out = 0.0f;
                 ndep = 0;
             }
         };
         step(0, dK ? far(0) : 0.0f);
 #pragma unroll
         for (int s = 1; s < H; ++s) step(s, far(s));
-        {
-            const int i = dK ? kq : rf;
-            step(H, fmaf(A, tY[i], fmaf(dK ? Bn : Bf, tD1[i], C * tD2[i])));
-        }
+        step(H, wt(dK ? kq : rf, A, dK ? Bn : Bf, C));
 #pragma unroll
         for (int s = H + 1; s < T; ++s) step(s, near(s));
         step(T, dK ? 0.0f : near(T));
-        // remaining departures (steps T-ndep .. T-1) in lanes 64-ndep .. 63
-        if (ndep > 0 && lane >= 64 - ndep) xb[rel0 + (T - 64 + lane) - H - 1] += out;
+        // remaining departures (steps T-ndep .. T-1) in lanes 0 .. ndep-1
+        if (lane < ndep) xb[rel0 + (T - ndep + lane) - H - 1] += out;
         xb[rel0 + lane + T - H - 1] += acc;
         __builtin_amdgcn_wave_barrier();
     }
@@ -436,14 +432,127 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     if (bad) atomicOr(status, kStatusWindow);
 }
 
-template <int T, int NT>
+// The same with two adjacent outputs per lane (NT lanes, 2 NT outputs per tile),
+// on the forward's shared-row tap sums (pair_frame, pair_sums).  With f and h the
+// near and far fractions,
+//   s     = A + f B + h Bm + f (f-1)/2 C + h (h-1)/2 Cm,
+//   ds/dmu = Lq (B + (f - 1/2) C - Bm - (h - 1/2) Cm)
+// (h runs against mu).  gpart keeps its 2 NT / 64 slots per tile: each wave
+// writes its sum to the first of its two slots and zero to the second.
+template <int T, int NT, int LC>
+__global__ __launch_bounds__(NT, 4) void k_adj_track2(DScene S, const DImage* __restrict__ imgs,
+                                                      const DGroup* __restrict__ groups,
+                                                      const float4* __restrict__ table, int Lr,
+                                                      const Seg* __restrict__ seg,
+                                                      const int32_t* __restrict__ segK, const float* __restrict__ x,
+                                                      const float* __restrict__ gy, float ghat,
+                                                      float* __restrict__ dbar, float* __restrict__ gpart,
+                                                      int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    constexpr int NG = T / 8;
+    constexpr int TO = 2 * NT;
+    constexpr int SLOTS = TO / 64;
+    const int L = LC > 0 ? LC : Lr;
+    const int LP = LC > 0 ? LC + 1 : Lr + 1;
+    float4* tab = lds;
+    const QTab tq = qtab_view<T>(tab, LP);
+    float4* xw = lds + qtab_bytes(T, L) / 16;
+
+    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const DGroup G = groups[S.grp_begin + g];
+    const int n0 = tile * TO;
+    const int ws = n0 - G.dmax - T / 2 - 4;
+    const int W = TO + (G.dmax - G.dmin) + T + 8;
+    const int n_in = (int)S.n_in;
+    load_qtab<T>(table, tab, L, NT);
+    stage_window(x + S.x_off, n_in, ws, W, xw, NT);
+    __syncthreads();
+
+    const int n_out = (int)S.n_out;
+    const int n = n0 + 2 * tid;
+    const bool ok0 = n < n_out, ok1 = n + 1 < n_out;
+    const float* gyc = gy + S.y_off + (int64_t)mic * S.n_out;
+    const float wy0 = ok0 ? gyc[n] : 0.0f, wy1 = ok1 ? gyc[n + 1] : 0.0f;
+    const int nc = ok0 ? n : n_out - 1;           // lanes past the end follow the last output
+    const Seg* sgm = seg + (int64_t)mic * S.seg_per_mic;
+    const int32_t* sgk = segK + (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    const float fn = (float)nc + 0.5f;
+    const float Lf = (float)L;
+    float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
+    const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * SLOTS;
+    float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * SLOTS + 2 * wave;
+    int bad = 0;
+    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+        const DImage im = I[ii];
+        float d0, d1;
+        int K0s, K1s;
+        if (im.R == 1) {
+            const int k0 = min(nc, im.n_seg - 1), k1 = min(nc + 1, im.n_seg - 1);
+            d0 = sgm[im.seg_off + k0].a0;
+            d1 = sgm[im.seg_off + k1].a0;
+            K0s = sgk[im.seg_off + k0];
+            K1s = sgk[im.seg_off + k1];
+        } else {
+            const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+            const Seg sg = sgm[im.seg_off + k];
+            K0s = K1s = sgk[im.seg_off + k];
+            const float v = (float)(nc - __mul24(k, im.R)), v1 = v + 1.0f;
+            d0 = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+            d1 = fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
+        }
+        const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
+        const int K = fr.K;
+        const bool act = (wy0 != 0.0f || wy1 != 0.0f) && nc - K + T / 2 >= 0 && nc - K - T / 2 < n_in;
+        float E = 0.0f, Db0 = 0.0f, Db1 = 0.0f;
+        if (__any(act)) {
+            const int p0 = nc - K - ws;
+            const bool inb = p0 >= T / 2 && p0 <= W - 1 - T / 2;
+            if (act && !inb) bad = 1;
+            if (act && inb) {
+                PairSums ps;
+            pair_sums<NG>(tq, LP, fr.kq, fr.kp, xw + p0, ps);
+                const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;
+                const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;
+                const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,
+                                      fmaf(0.5f * f0 * (f0 - 1.0f), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
+                const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), ps.Cm1,
+                                      fmaf(0.5f * f1 * (f1 - 1.0f), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
+                const float sd0 = Lf * (fmaf(f0 - 0.5f, ps.C0, ps.B0) - fmaf(h0 - 0.5f, ps.Cm0, ps.Bm0));
+                const float sd1 = Lf * (fmaf(f1 - 0.5f, ps.C1, ps.B1) - fmaf(h1 - 0.5f, ps.Cm1, ps.Bm1));
+                const float iD0 = __builtin_amdgcn_rcpf((float)K0s + d0);
+                const float iD1 = __builtin_amdgcn_rcpf((float)K1s + d1);
+                E = ghat * fmaf(wy0 * s0, iD0, wy1 * s1 * iD1);
+                Db0 = wy0 * im.gfac * iD0 * fmaf(-s0, iD0, sd0);
+                Db1 = wy1 * im.gfac * iD1 * fmaf(-s1, iD1, sd1);
+            }
+        }
+        if (ok0) dout[(int64_t)ii * S.n_out] = Db0;
+        if (ok1) dout[(int64_t)ii * S.n_out + 1] = Db1;
+        E = wave_sum(E);
+        if (lane == 0) {
+            gout[(int64_t)ii * nrow] = E;
+            gout[(int64_t)ii * nrow + 1] = 0.0f;
+        }
+    }
+    if (bad) atomicOr(status, kStatusWindow);
+}
+
+template <int T, int TO, int RB>
 static hipError_t launch_adj_track_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
                                      const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK,
                                      const float* x, const float* gy, float ghat, float* dbar, float* gpart,
                                      int32_t* d_status, hipStream_t st)
 {
+    constexpr int NT = TO / RB;
     const size_t lds = adj_track_lds_bytes(T, Lq, hs.window);
-    auto kern = Lq == 128 ? k_adj_track<T, NT, 128> : k_adj_track<T, NT, 0>;
+    decltype(&k_adj_track<T, NT, 0>) kern;
+    if constexpr (RB == 2)
+        kern = Lq == 128 ? k_adj_track2<T, NT, 128> : k_adj_track2<T, NT, 0>;
+    else
+        kern = Lq == 128 ? k_adj_track<T, NT, 128> : k_adj_track<T, NT, 0>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
@@ -452,23 +561,22 @@ static hipError_t launch_adj_track_t(const DScene& hs, const DImage* d_imgs, con
     return hipGetLastError();
 }
 
-hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK, const float* x,
-                            const float* gy, float ghat, float* dbar, float* gpart, int32_t* d_status,
-                            hipStream_t st)
+hipError_t launch_adj_track(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs,
+                            const DGroup* d_groups, const float4* d_qtable, int Lq, const Seg* seg,
+                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
+                            float* gpart, int32_t* d_status, hipStream_t st)
 {
-#define MSIM_ADJT_CASE(TT, NN)                                                                                 \
-    if (taps == TT && nthreads == NN)                                                                          \
-        return launch_adj_track_t<TT, NN>(hs, d_imgs, d_groups, d_qtable, Lq, seg, segK, x, gy, ghat, dbar,     \
-                                          gpart, d_status, st);
-    MSIM_ADJT_CASE(32, 1024)
-    MSIM_ADJT_CASE(64, 1024)
-    MSIM_ADJT_CASE(96, 1024)
-    MSIM_ADJT_CASE(128, 1024)
-    MSIM_ADJT_CASE(32, 512)
-    MSIM_ADJT_CASE(64, 512)
-    MSIM_ADJT_CASE(96, 512)
-    MSIM_ADJT_CASE(128, 512)
+#define MSIM_ADJT_CASE(TT, NN, RR)                                                                             \
+    if (taps == TT && nthreads == NN && rb == RR)                                                             \
+        return launch_adj_track_t<TT, NN, RR>(hs, d_imgs, d_groups, d_qtable, Lq, seg, segK, x, gy, ghat, dbar, \
+                                              gpart, d_status, st);
+#define MSIM_ADJT_TAPS(TT)                                                                                     \
+    MSIM_ADJT_CASE(TT, 512, 1) MSIM_ADJT_CASE(TT, 1024, 1) MSIM_ADJT_CASE(TT, 512, 2) MSIM_ADJT_CASE(TT, 1024, 2)
+    MSIM_ADJT_TAPS(32)
+    MSIM_ADJT_TAPS(64)
+    MSIM_ADJT_TAPS(96)
+    MSIM_ADJT_TAPS(128)
+#undef MSIM_ADJT_TAPS
 #undef MSIM_ADJT_CASE
     return hipErrorInvalidValue;
 }

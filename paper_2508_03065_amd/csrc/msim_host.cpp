@@ -656,7 +656,11 @@ msim_status regroup(msim_plan* P)
         if (P->group_cap > 0) {
             G = std::max(1, (I + P->group_cap - 1) / P->group_cap);
         } else {
-            // enough workgroups to fill the 256 CUs several times, in nearly whole rounds
+            // enough workgroups to fill the 256 CUs several times, in nearly whole
+            // rounds; the table form also keeps groups to at most 24 images (it
+            // measured fastest at 16-40 on the paper-scale scene: smaller groups
+            // balance tiles of uneven cost), the Farrow form, whose per-group
+            // window costs three times the LDS and staging, does not.
             const int64_t base = (int64_t)d.n_tiles * d.n_mics;
             double best = -1.0;
             for (int g = 1; g <= std::min(I, 128); ++g) {
@@ -669,14 +673,15 @@ msim_status regroup(msim_plan* P)
                 }
                 if (wgs >= 16 * 256) break;
             }
+            if (P->par.fd_kind != MSIM_FD_FARROW) G = std::max(G, (I + 23) / 24);
         }
         std::vector<DGroup> gr;
         int window = 0;
-        for (;;) {
+        auto split = [&](int ng) {
             gr.clear();
             window = 0;
-            for (int g = 0; g < G; ++g) {
-                const int b = (int)((int64_t)I * g / G), e = (int)((int64_t)I * (g + 1) / G);
+            for (int g = 0; g < ng; ++g) {
+                const int b = (int)((int64_t)I * g / ng), e = (int)((int64_t)I * (g + 1) / ng);
                 if (b == e) continue;
                 double lo = 1e300, hi = -1e300;
                 for (int i = b; i < e; ++i) {
@@ -687,6 +692,9 @@ msim_status regroup(msim_plan* P)
                 gr.push_back(dg);
                 window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
             }
+        };
+        for (;;) {
+            split(G);
             if (fits(window)) break;
             if (G >= I) {
                 if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
@@ -694,6 +702,33 @@ msim_status regroup(msim_plan* P)
                 continue;
             }
             G = std::min(I, G * 2);
+        }
+        // Table form: an automatic group count is raised (by 25 % steps, to groups
+        // of at least four images and at most 1 GB of partial outputs) to the first
+        // that lets two workgroups share one CU's LDS: at one per CU the kernel is
+        // latency-bound.  When no such count exists the first is kept.  (The Farrow
+        // form restages its 48-byte window per group, which more groups cost more
+        // than its occupancy gains.)
+        if (P->group_cap == 0 && P->par.fd_kind != MSIM_FD_FARROW) {
+            auto lds_of = [&](int w) { return synth_lds_bytes(T, L, w); };
+            const int g_mem = (int)std::min<int64_t>(I, ((int64_t)1 << 30) / ((int64_t)d.n_mics * d.n_out * 4 + 1));
+            const int g_max = std::min(std::max(1, I / 4), std::max(g_mem, G));
+            if (lds_of(window) > kLdsLimit / 2 && G < g_max) {
+                const int g0 = G;
+                bool ok = false;
+                while (G < g_max) {
+                    G = std::min(g_max, G + std::max(1, G / 4));
+                    split(G);
+                    if (lds_of(window) <= kLdsLimit / 2 && fits(window)) {
+                        ok = true;
+                        break;
+                    }
+                }
+                if (!ok) {
+                    G = g0;
+                    split(G);
+                }
+            }
         }
         P->grad_ok.push_back(grad_fit);
         d.grp_begin = (int)P->groups.size();
@@ -1109,7 +1144,7 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
         if (gbeta || want_src) {
             {
                 LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_adj_track(T, P->threads, d, P->d_images, P->d_groups, P->d_qtable, L, fw.seg, fw.segK,
+                HIP_OK(launch_adj_track(T, P->threads, P->rb, d, P->d_images, P->d_groups, P->d_qtable, L, fw.seg, fw.segK,
                                         x, gy, ghat, aw.dbar, aw.gpart, P->d_status, stream));
             }
             LaunchTimer t(P, kKindParams, stream);
@@ -1290,7 +1325,7 @@ msim_status check_batched_call(msim_plan* P, const float* x, float* y, void* ws,
 }
 
 const int kTuneThreads[] = {512, 1024};
-const int kTuneCaps[] = {0, 32, 64, 128, 256, 512};
+const int kTuneCaps[] = {0, 16, 32, 64, 128, 256, 512};
 
 std::string tune_key(const msim_plan* P)
 {

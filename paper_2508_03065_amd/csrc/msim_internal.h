@@ -165,10 +165,10 @@ hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* 
                         float* xpart, int32_t* d_status, hipStream_t st);
 hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
                            float* gx, hipStream_t st);
-hipError_t launch_adj_track(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_qtable, int Lq, const Seg* seg, const int32_t* segK, const float* x,
-                            const float* gy, float ghat, float* dbar, float* gpart, int32_t* d_status,
-                            hipStream_t st);
+hipError_t launch_adj_track(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs,
+                            const DGroup* d_groups, const float4* d_qtable, int Lq, const Seg* seg,
+                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
+                            float* gpart, int32_t* d_status, hipStream_t st);
 hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
                              const double* d_knots, const double* d_mics, const double* grid, const float* dbar,
                              float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,

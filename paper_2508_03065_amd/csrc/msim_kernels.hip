@@ -11,6 +11,7 @@
 //   reduce      : fixed-order sum of the per-group partial outputs.
 #include "msim_device.h"
 #include "msim_internal.h"
+#include "msim_pair.h"
 
 #include <hip/hip_runtime.h>
 
@@ -228,34 +229,6 @@ size_t synth_lds_bytes(int taps, int Lq, int window)
     return qtab_bytes(taps, Lq) + (size_t)window * sizeof(float4);
 }
 
-// Pointers to row 0 of quad 0 of the three table arrays in LDS.
-struct QTab {
-    const float4* Y;
-    const float4* D1;
-    const uint2* D2;
-};
-
-template <int T>
-__device__ inline QTab qtab_view(const float4* tab, int LP)
-{
-    constexpr int NG = T / 8;
-    return {tab + 1, tab + NG * LP + 1, (const uint2*)(tab + 2 * NG * LP) + 1};
-}
-
-// Stages the source window of a tile: xw[p] = x[ws+p .. ws+p+3], zero outside [0, n_in).
-__device__ inline void stage_window(const float* __restrict__ xs, int n_in, int ws, int W, float4* xw, int nthreads)
-{
-    for (int p = threadIdx.x; p < W; p += nthreads) {
-        const int q = ws + p;
-        float4 v;
-        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
-        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
-        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
-        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
-        xw[p] = v;
-    }
-}
-
 // One output tile of one delay group for one mic: stages the group's source
 // window in LDS (the table must already be there), then one output sample per
 // lane sums every image of the group; writes the group's partial outputs.
@@ -367,19 +340,13 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
     __syncthreads();
 }
 
-// The same tile with two adjacent outputs n, n+1 per lane (NT lanes, 2 NT outputs).
-// Their delays differ by |dD/dn| < 1/Lq of a sample at subsonic-slow speeds
-// (2.7 m/s at Lq = 128), so both take their tap weights from the same table rows:
-// in the frame K = min of the two integer delays, each output's phase mu' = D - K
-// lies in [0, 2) and q' = mu' Lq; the near side reads base row floor(min q'), the
-// far side base row Lq-1-floor(max q') (down to -1), and each output's fractions
-// on the two rows stay within [0, 2] where the quadratic through rows r, r+1, r+2
-// still interpolates.  One table read and one new source quad then serve eight
-// taps of both outputs: half the LDS bytes per tap.  Output n+1's taps are output
-// n's shifted by one source position; its far-side tap -T/2+1 and near-side tap
-// T/2+1 in this frame fall outside or at the kernel's edge, where h is below
-// 1e-3 |mu' - 1| of its peak.  Faster images read on-row extrapolations
-// (fractions past 2), which stay within a few times the interpolation error.
+// The same tile with two adjacent outputs n, n+1 per lane (NT lanes, 2 NT outputs),
+// which take their tap weights from the same table rows (pair_frame, pair_sums):
+// half the LDS bytes per tap.  Output n+1's taps are output n's shifted by one
+// source position; in the shared frame its far-side tap -T/2+1 and near-side tap
+// T/2+1 fall outside or at the kernel's edge, where h is below 1e-3 |mu' - 1| of
+// its peak.  The plan uses it only while the delay drifts by well under two table
+// rows per sample.
 template <int T, int NT, int LC>
 __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int tile, int mic,
                                    const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
@@ -443,9 +410,8 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
                 d1 = fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
                 K0s = K1s = Ka;
             }
-            const float fl0 = floorf(d0), fl1 = floorf(d1);
-            const int i0 = K0s + (int)fl0, i1 = K1s + (int)fl1;
-            const int K = min(i0, i1);
+            const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
+            const int K = fr.K;
             // skip the image when no lane's taps reach a source sample
             if (!__any(n - K + T / 2 >= 0 && n - K - T / 2 < n_in)) return;
             const int p0 = n - K - ws;
@@ -453,73 +419,14 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
                 bad = 1;
                 return;
             }
-            const float q0 = ((d0 - fl0) + (float)(i0 - K)) * Lf;
-            const float q1 = ((d1 - fl1) + (float)(i1 - K)) * Lf;
-            const int kq = min((int)fminf(q0, q1), L - 1);
-            const int kp = max(L - 1 - (int)fmaxf(q0, q1), -1);
-            const float f0 = q0 - (float)kq, f1 = q1 - (float)kq;            // near side
-            const float h0 = (Lf - q0) - (float)kp, h1 = (Lf - q1) - (float)kp; // far side
-            const float4* xq = xw + p0;
-            float A0 = 0.0f, B0 = 0.0f, Bm0 = 0.0f, C0 = 0.0f, Cm0 = 0.0f;
-            float A1 = 0.0f, B1 = 0.0f, Bm1 = 0.0f, C1 = 0.0f, Cm1 = 0.0f;
-            // 2 NG steps, near side then far side, one tap quad each; the table rows
-            // and the new source quad of step st+1 are read while step st is summed
-            // (scheduling barriers keep the pipeline one step deep, so the values
-            // in flight stay within the register budget).
-            float4 xo = xq[0];                  // the previous step's source quad
-            float4 xc = xq[4], Yc = tq.Y[kq], D1c = tq.D1[kq];
-            uint2 D2c = tq.D2[kq];
-#pragma unroll
-            for (int st = 0; st < 2 * NG; ++st) {
-                float4 xnx = xc, Ynx = Yc, D1nx = D1c, x0 = xo;
-                uint2 D2nx = D2c;
-                if (st + 1 == NG) x0 = xq[0];
-                if (st + 1 < 2 * NG) {
-                    const int s1 = st + 1;
-                    const int row = s1 < NG ? s1 * LP + kq : (s1 - NG) * LP + kp;
-                    xnx = s1 < NG ? xq[4 * s1 + 4] : xq[-4 - 4 * (s1 - NG)];
-                    Ynx = tq.Y[row];
-                    D1nx = tq.D1[row];
-                    D2nx = tq.D2[row];
-                }
-                const float c0 = h16_lo(D2c.x), c1 = h16_hi(D2c.x), c2 = h16_lo(D2c.y), c3 = h16_hi(D2c.y);
-                if (st < NG) {
-                    // near side, taps j = -(4gi+e): output n reads x[n-K+4gi+e] (quad 4gi =
-                    // xo, component e), output n+1 the next position (xc = quad 4gi+4)
-                    const float4 xn = xo, xa = xc;
-                    A0 = fmaf(Yc.x, xn.x, A0); B0 = fmaf(D1c.x, xn.x, B0); C0 = fmaf(c0, xn.x, C0);
-                    A1 = fmaf(Yc.x, xn.y, A1); B1 = fmaf(D1c.x, xn.y, B1); C1 = fmaf(c0, xn.y, C1);
-                    A0 = fmaf(Yc.y, xn.y, A0); B0 = fmaf(D1c.y, xn.y, B0); C0 = fmaf(c1, xn.y, C0);
-                    A1 = fmaf(Yc.y, xn.z, A1); B1 = fmaf(D1c.y, xn.z, B1); C1 = fmaf(c1, xn.z, C1);
-                    A0 = fmaf(Yc.z, xn.z, A0); B0 = fmaf(D1c.z, xn.z, B0); C0 = fmaf(c2, xn.z, C0);
-                    A1 = fmaf(Yc.z, xn.w, A1); B1 = fmaf(D1c.z, xn.w, B1); C1 = fmaf(c2, xn.w, C1);
-                    A0 = fmaf(Yc.w, xn.w, A0); B0 = fmaf(D1c.w, xn.w, B0); C0 = fmaf(c3, xn.w, C0);
-                    A1 = fmaf(Yc.w, xa.x, A1); B1 = fmaf(D1c.w, xa.x, B1); C1 = fmaf(c3, xa.x, C1);
-                } else {
-                    // far side, taps j = 1+4gi+e: output n reads x[n-K-1-4gi-e] (quad
-                    // -4-4gi = xc, component 3-e), output n+1 the next position (xo =
-                    // quad -4gi)
-                    const float4 xp = xc, xr = xo;
-                    A0 = fmaf(Yc.x, xp.w, A0); Bm0 = fmaf(D1c.x, xp.w, Bm0); Cm0 = fmaf(c0, xp.w, Cm0);
-                    A1 = fmaf(Yc.x, xr.x, A1); Bm1 = fmaf(D1c.x, xr.x, Bm1); Cm1 = fmaf(c0, xr.x, Cm1);
-                    A0 = fmaf(Yc.y, xp.z, A0); Bm0 = fmaf(D1c.y, xp.z, Bm0); Cm0 = fmaf(c1, xp.z, Cm0);
-                    A1 = fmaf(Yc.y, xp.w, A1); Bm1 = fmaf(D1c.y, xp.w, Bm1); Cm1 = fmaf(c1, xp.w, Cm1);
-                    A0 = fmaf(Yc.z, xp.y, A0); Bm0 = fmaf(D1c.z, xp.y, Bm0); Cm0 = fmaf(c2, xp.y, Cm0);
-                    A1 = fmaf(Yc.z, xp.z, A1); Bm1 = fmaf(D1c.z, xp.z, Bm1); Cm1 = fmaf(c2, xp.z, Cm1);
-                    A0 = fmaf(Yc.w, xp.x, A0); Bm0 = fmaf(D1c.w, xp.x, Bm0); Cm0 = fmaf(c3, xp.x, Cm0);
-                    A1 = fmaf(Yc.w, xp.y, A1); Bm1 = fmaf(D1c.w, xp.y, Bm1); Cm1 = fmaf(c3, xp.y, Cm1);
-                }
-                xo = st + 1 == NG ? x0 : xc;
-                xc = xnx;
-                Yc = Ynx;
-                D1c = D1nx;
-                D2c = D2nx;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), Cm0,
-                                  fmaf(0.5f * f0 * (f0 - 1.0f), C0, fmaf(h0, Bm0, fmaf(f0, B0, A0))));
-            const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), Cm1,
-                                  fmaf(0.5f * f1 * (f1 - 1.0f), C1, fmaf(h1, Bm1, fmaf(f1, B1, A1))));
+            PairSums ps;
+            pair_sums<NG>(tq, LP, fr.kq, fr.kp, xw + p0, ps);
+            const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;                   // near side
+            const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;     // far side
+            const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,
+                                  fmaf(0.5f * f0 * (f0 - 1.0f), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
+            const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), ps.Cm1,
+                                  fmaf(0.5f * f1 * (f1 - 1.0f), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
             acc0 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K0s + d0), s0, acc0);
             acc1 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K1s + d1), s1, acc1);
         };
@@ -548,13 +455,6 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
     __syncthreads();
 }
 
-template <int T>
-__device__ inline void load_table(const float4* __restrict__ table, float4* tab, int Lq, int nthreads)
-{
-    const int n = (int)(qtab_bytes(T, Lq) / 16);
-    for (int i = threadIdx.x; i < n; i += nthreads) tab[i] = table[i];
-}
-
 // Forward kernels; RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
 template <int T, int NT, int LC, int RB>
 __global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
@@ -569,7 +469,7 @@ __global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_fwd(DScene S, con
     extern __shared__ float4 lds[];
     float4* tab = lds;
     float4* xw = lds + qtab_bytes(T, L) / 16;
-    load_table<T>(table, tab, L, NT);
+    load_qtab<T>(table, tab, L, NT);
     const int g = blockIdx.y;
     if constexpr (RB == 1)
         synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
@@ -594,7 +494,7 @@ __global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_persistent(
     __shared__ int s_item;
     float4* tab = lds;
     float4* xw = lds + qtab_bytes(T, L) / 16;
-    load_table<T>(table, tab, L, NT);
+    load_qtab<T>(table, tab, L, NT);
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
         __syncthreads();

@@ -1,0 +1,151 @@
+// The quadratic fractional-delay table in LDS and the two-outputs-per-lane tap
+// sums over it, shared by the forward synthesis and the gain/delay adjoint.
+#pragma once
+
+#include "msim_device.h"
+#include "msim_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace msim {
+
+// Pointers to row 0 of quad 0 of the three table arrays in LDS (qtab_pitch rows
+// per quad, the first of them row -1).
+struct QTab {
+    const float4* Y;
+    const float4* D1;
+    const uint2* D2;
+};
+
+template <int T>
+__device__ __forceinline__ QTab qtab_view(const float4* tab, int LP)
+{
+    constexpr int NG = T / 8;
+    return {tab + 1, tab + NG * LP + 1, (const uint2*)(tab + 2 * NG * LP) + 1};
+}
+
+// Copies the quadratic table (qtab_bytes) from global memory into LDS.
+template <int T>
+__device__ __forceinline__ void load_qtab(const float4* __restrict__ table, float4* tab, int Lq, int nthreads)
+{
+    const int n = (int)(qtab_bytes(T, Lq) / 16);
+    for (int i = threadIdx.x; i < n; i += nthreads) tab[i] = table[i];
+}
+
+// Stages the source window of a tile: xw[p] = x[ws+p .. ws+p+3], zero outside [0, n_in).
+__device__ __forceinline__ void stage_window(const float* __restrict__ xs, int n_in, int ws, int W, float4* xw,
+                                             int nthreads)
+{
+    for (int p = threadIdx.x; p < W; p += nthreads) {
+        const int q = ws + p;
+        float4 v;
+        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
+        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
+        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
+        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
+        xw[p] = v;
+    }
+}
+
+// The frame of a lane's outputs n, n+1 for one image with delays D_m = K_ms + d_m
+// (integer base plus a small FP32 offset).  Both read the table rows of one
+// frame: K, the smaller of the two integer delays, with phases q_m = (D_m - K) Lq
+// in table rows (in [0, 2 Lq)); the near side's base row floor(min q) and the far
+// side's Lq-1-floor(max q) (down to -1), so each output's fractions on those rows,
+// f_m = q_m - kq and h_m = Lq - q_m - kp, stay within [0, 2] while the delay moves
+// by less than one row per sample.
+struct PairFrame {
+    int K;
+    float q0, q1;
+    int kq, kp;
+};
+
+__device__ __forceinline__ PairFrame pair_frame(float d0, int K0s, float d1, int K1s, int L, float Lf)
+{
+    const float fl0 = floorf(d0), fl1 = floorf(d1);
+    const int i0 = K0s + (int)fl0, i1 = K1s + (int)fl1;
+    PairFrame fr;
+    fr.K = min(i0, i1);
+    fr.q0 = ((d0 - fl0) + (float)(i0 - fr.K)) * Lf;
+    fr.q1 = ((d1 - fl1) + (float)(i1 - fr.K)) * Lf;
+    fr.kq = min((int)fminf(fr.q0, fr.q1), L - 1);
+    fr.kp = max(L - 1 - (int)fmaxf(fr.q0, fr.q1), -1);
+    return fr;
+}
+
+// Tap sums of one image for outputs n (0) and n+1 (1) in the frame K, with xq the
+// source window at n - K, written into ps (by reference: returning the sums by
+// value made the register allocator spill).  Near side (taps j = -(4g+e),
+// |u| = 4g+e + mu, base row kq): A += Y x, B += D1 x, C += D2 x; far side (taps
+// j = 1+4g+e, |u| = 4g+e + 1-mu, base row kp): A += Y x, Bm += D1 x, Cm += D2 x.
+// The value is then
+//   s = A + f B + h Bm + f (f-1)/2 C + h (h-1)/2 Cm.
+// Output n reads x[n-K+4g+e] on the near side and x[n-K-1-4g-e] on the far side;
+// output n+1 the next position.  One table read (Y, D1, D2 of four taps) and one
+// new source quad serve eight taps of both outputs.  The 2 T/8 steps are
+// software-pipelined one deep: the rows and the source quad of step st+1 are read
+// while step st is summed, and scheduling barriers keep the pipeline at that depth
+// (so the values in flight stay within the register budget).
+struct PairSums {
+    float A0, B0, Bm0, C0, Cm0;
+    float A1, B1, Bm1, C1, Cm1;
+};
+
+template <int NG>
+__device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp, const float4* xq, PairSums& ps)
+{
+    float& A0 = ps.A0; float& B0 = ps.B0; float& Bm0 = ps.Bm0; float& C0 = ps.C0; float& Cm0 = ps.Cm0;
+    float& A1 = ps.A1; float& B1 = ps.B1; float& Bm1 = ps.Bm1; float& C1 = ps.C1; float& Cm1 = ps.Cm1;
+    A0 = B0 = Bm0 = C0 = Cm0 = A1 = B1 = Bm1 = C1 = Cm1 = 0.0f;
+    float4 xo = xq[0];                  // the previous step's source quad
+    float4 xc = xq[4], Yc = tq.Y[kq], D1c = tq.D1[kq];
+    uint2 D2c = tq.D2[kq];
+#pragma unroll
+    for (int st = 0; st < 2 * NG; ++st) {
+        float4 xnx = xc, Ynx = Yc, D1nx = D1c, x0 = xo;
+        uint2 D2nx = D2c;
+        if (st + 1 == NG) x0 = xq[0];
+        if (st + 1 < 2 * NG) {
+            const int s1 = st + 1;
+            const int row = s1 < NG ? s1 * LP + kq : (s1 - NG) * LP + kp;
+            xnx = s1 < NG ? xq[4 * s1 + 4] : xq[-4 - 4 * (s1 - NG)];
+            Ynx = tq.Y[row];
+            D1nx = tq.D1[row];
+            D2nx = tq.D2[row];
+        }
+        const float c0 = h16_lo(D2c.x), c1 = h16_hi(D2c.x), c2 = h16_lo(D2c.y), c3 = h16_hi(D2c.y);
+        if (st < NG) {
+            // near side: output n reads quad 4g (xo, component e), output n+1 the
+            // next position (the last from quad 4g+4 = xc)
+            const float4 xn = xo, xa = xc;
+            A0 = fmaf(Yc.x, xn.x, A0); B0 = fmaf(D1c.x, xn.x, B0); C0 = fmaf(c0, xn.x, C0);
+            A1 = fmaf(Yc.x, xn.y, A1); B1 = fmaf(D1c.x, xn.y, B1); C1 = fmaf(c0, xn.y, C1);
+            A0 = fmaf(Yc.y, xn.y, A0); B0 = fmaf(D1c.y, xn.y, B0); C0 = fmaf(c1, xn.y, C0);
+            A1 = fmaf(Yc.y, xn.z, A1); B1 = fmaf(D1c.y, xn.z, B1); C1 = fmaf(c1, xn.z, C1);
+            A0 = fmaf(Yc.z, xn.z, A0); B0 = fmaf(D1c.z, xn.z, B0); C0 = fmaf(c2, xn.z, C0);
+            A1 = fmaf(Yc.z, xn.w, A1); B1 = fmaf(D1c.z, xn.w, B1); C1 = fmaf(c2, xn.w, C1);
+            A0 = fmaf(Yc.w, xn.w, A0); B0 = fmaf(D1c.w, xn.w, B0); C0 = fmaf(c3, xn.w, C0);
+            A1 = fmaf(Yc.w, xa.x, A1); B1 = fmaf(D1c.w, xa.x, B1); C1 = fmaf(c3, xa.x, C1);
+        } else {
+            // far side: output n reads quad -4-4g (xc, component 3-e), output n+1
+            // the next position (the first from quad -4g = xo)
+            const float4 xp = xc, xr = xo;
+            A0 = fmaf(Yc.x, xp.w, A0); Bm0 = fmaf(D1c.x, xp.w, Bm0); Cm0 = fmaf(c0, xp.w, Cm0);
+            A1 = fmaf(Yc.x, xr.x, A1); Bm1 = fmaf(D1c.x, xr.x, Bm1); Cm1 = fmaf(c0, xr.x, Cm1);
+            A0 = fmaf(Yc.y, xp.z, A0); Bm0 = fmaf(D1c.y, xp.z, Bm0); Cm0 = fmaf(c1, xp.z, Cm0);
+            A1 = fmaf(Yc.y, xp.w, A1); Bm1 = fmaf(D1c.y, xp.w, Bm1); Cm1 = fmaf(c1, xp.w, Cm1);
+            A0 = fmaf(Yc.z, xp.y, A0); Bm0 = fmaf(D1c.z, xp.y, Bm0); Cm0 = fmaf(c2, xp.y, Cm0);
+            A1 = fmaf(Yc.z, xp.z, A1); Bm1 = fmaf(D1c.z, xp.z, Bm1); Cm1 = fmaf(c2, xp.z, Cm1);
+            A0 = fmaf(Yc.w, xp.x, A0); Bm0 = fmaf(D1c.w, xp.x, Bm0); Cm0 = fmaf(c3, xp.x, Cm0);
+            A1 = fmaf(Yc.w, xp.y, A1); Bm1 = fmaf(D1c.w, xp.y, Bm1); Cm1 = fmaf(c3, xp.y, Cm1);
+        }
+        xo = st + 1 == NG ? x0 : xc;
+        xc = xnx;
+        Yc = Ynx;
+        D1c = D1nx;
+        D2c = D2nx;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+}  // namespace msim
