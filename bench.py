@@ -218,7 +218,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed forward steps first (the GPU clocks take a few hundred ms to settle)")
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--fd", default="table", choices=sorted(FD_KINDS),
                     help="fractional-delay form of the headline measurement (the other is reported beside it)")

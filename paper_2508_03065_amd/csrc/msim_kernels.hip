@@ -380,36 +380,36 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
 
         // Track data for both outputs: one segment when the image is decimated
         // (every decimation is even, so n and n+1 share it), else the two
-        // full-rate delays.  Two buffers in turn, as in the one-output tile.
-        auto fetch = [&](const DImage& im, Seg& q, float& a1, int& K0, int& K1, int& kseg) {
-            if (im.R == 1) {
-                const int k0 = min(n, im.n_seg - 1), k1 = min(n + 1, im.n_seg - 1);
-                q.a0 = sgm[im.seg_off + k0].a0;
-                a1 = sgm[im.seg_off + k1].a0;
-                K0 = sgk[im.seg_off + k0];
-                K1 = sgk[im.seg_off + k1];
-            } else {
-                const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
-                q = sgm[im.seg_off + k];
-                K0 = sgk[im.seg_off + k];
-                kseg = k;
+        // full-rate delays (full-rate segments carry zero cubic terms, so the
+        // segment of n gives D(n) either way).  The lane's segment offsets depend
+        // only on the decimation R: they are kept for the last R seen (images of a
+        // group mostly share a tier) as byte offsets from the image's track, so a
+        // fetch is four loads from a scalar base.  Two buffers in turn, as in the
+        // one-output tile.
+        int cR = 0;
+        uint32_t c0 = 0, c1 = 0;            // byte offsets of the segments of n and n+1
+        float cv = 0.0f;                     // n relative to its segment start
+        auto fetch = [&](const DImage& im, Seg& q, float& a1, int& K0, int& K1, float& v) {
+            if (im.R != cR) {
+                cR = im.R;
+                const int k0 = im.R == 1 ? min(n, im.n_seg - 1) : min(max((int)(fn * im.invR), 0), im.n_seg - 1);
+                const int k1 = im.R == 1 ? min(n + 1, im.n_seg - 1) : k0;
+                c0 = (uint32_t)k0;
+                c1 = (uint32_t)k1;
+                cv = (float)(n - k0 * im.R);
             }
+            const Seg* sb = sgm + im.seg_off;
+            const int32_t* kb = sgk + im.seg_off;
+            q = sb[c0];
+            a1 = sb[c1].a0;
+            K0 = kb[c0];
+            K1 = kb[c1];
+            v = cv;
         };
-        auto body = [&](const DImage& im, const Seg& sg, float a1, int Ka, int Kb, int k) {
-            float d0, d1;
-            int K0s, K1s;
-            if (im.R == 1) {
-                d0 = sg.a0;
-                d1 = a1;
-                K0s = Ka;
-                K1s = Kb;
-            } else {
-                const float v = (float)(n - __mul24(k, im.R));
-                d0 = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
-                const float v1 = v + 1.0f;
-                d1 = fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
-                K0s = K1s = Ka;
-            }
+        auto body = [&](const DImage& im, const Seg& sg, float a1, int K0s, int K1s, float v) {
+            const float d0 = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
+            const float v1 = v + 1.0f;
+            const float d1 = im.R == 1 ? a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
             const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
             const int K = fr.K;
             // skip the image when no lane's taps reach a source sample
@@ -431,8 +431,8 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
             acc1 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K1s + d1), s1, acc1);
         };
         Seg qa{}, qb{};
-        float a1a = 0.0f, a1b = 0.0f;
-        int K0a = 0, K1a = 0, K0b = 0, K1b = 0, ka = 0, kb = 0;
+        float a1a = 0.0f, a1b = 0.0f, ka = 0.0f, kb = 0.0f;
+        int K0a = 0, K1a = 0, K0b = 0, K1b = 0;
         DImage ia = I[G.img_begin], ib;
         fetch(ia, qa, a1a, K0a, K1a, ka);
         int ii = G.img_begin;

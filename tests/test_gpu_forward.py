@@ -167,3 +167,25 @@ def test_fast_scene_keeps_one_output_per_lane(torch_cuda):
     torch_cuda.cuda.synchronize()
     (yv,) = plan.unpack_y(y)
     assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
+
+
+def test_pair_at_the_speed_limit(torch_cuda):
+    # a source moving straight away from and back toward the receiver at 2.1 m/s, the
+    # fastest radial speed at which the plan still pairs outputs (the delay drifts by
+    # 1.2 table rows per sample with the cubic-slope allowance): both outputs' table
+    # fractions reach their widest range here
+    from paper_2508_03065_amd.msim import Plan
+    sc, par = G.small_scene(seed=26, max_order=4, seconds=0.3, taps=64)
+    rcv = np.array([2.5, 2.0, 1.4])
+    sc.rcv = G.Traj.static(rcv)
+    t = np.array([0.0, 0.15, 0.3])
+    p = np.array([[2.9, 2.0, 1.4], [2.9 + 0.315, 2.0, 1.4], [2.9, 2.0, 1.4]])
+    sc.src = G.Traj.pwl(t, p)
+    plan = Plan([sc], par)
+    assert plan.tuning()["outputs_per_lane"] == 2
+    x = plan.pack_x([sc.x])
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    assert plan.device_status() == 0
+    (yv,) = plan.unpack_y(y)
+    assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
