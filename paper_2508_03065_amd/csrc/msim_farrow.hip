@@ -57,7 +57,15 @@ hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_
     return hipGetLastError();
 }
 
-size_t farrow_lds_bytes(int window) { return (size_t)window * kFarrowStride * sizeof(float); }
+// Image descriptors staged in LDS per chunk of a group (one-output tile).
+constexpr int kFarrowDescChunk = 256;
+
+// LDS of the Farrow forward: a chunk of image descriptors, then the window of
+// v_0..v_11 (48 B per source position).
+size_t farrow_lds_bytes(int window)
+{
+    return (size_t)kFarrowDescChunk * 16 + (size_t)window * kFarrowStride * sizeof(float);
+}
 
 // One output tile (TO samples) of one delay group for one mic, Farrow form:
 // stages v_k over the group's source-position window in LDS, then each of the
@@ -65,10 +73,10 @@ size_t farrow_lds_bytes(int window) { return (size_t)window * kFarrowStride * si
 // outputs of a lane share one track segment when the image is decimated (the
 // planner only picks RB > 1 when every decimation is a multiple of RB), so the
 // segment fetch and its index arithmetic are paid once per RB image samples.
-// `hi` selects Horner over all 12 stored coefficients (orders 10-11) instead of
+// HI selects Horner over all 12 stored coefficients (orders 10-11) instead of
 // the first 10.  Ends with a barrier.
-template <int TO, int RB>
-__device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int tile, int mic, int T, bool hi,
+template <int TO, int RB, bool HI>
+__device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int tile, int mic, int T,
                                    const DImage* __restrict__ imgs, float4* vw, const Seg* __restrict__ seg,
                                    const int32_t* __restrict__ segK, const float* __restrict__ v,
                                    float* __restrict__ part, int32_t* __restrict__ status)
@@ -155,7 +163,7 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
                 const float4* vp = vw + __mul24(p, 3);
                 const float4 a = vp[0], b = vp[1];
                 float r;
-                if (hi) {
+                if constexpr (HI) {
                     const float4 c = vp[2];
                     r = fmaf(c.w, s, c.z);
                     r = fmaf(r, s, c.y);
@@ -214,9 +222,136 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
     __syncthreads();
 }
 
-template <int TO, int RB>
+// The same with one output per lane, branch-free per image.  A full-rate track
+// segment carries zero cubic terms, so the decimated formula gives its delay
+// too, and the lane's segment index depends only on the decimation R, so it is
+// kept for the last R seen (images of a group mostly share a tier).  The group's
+// image descriptors (track offset, R, gain factor, segment count) are staged in
+// LDS a chunk at a time: read there, they keep scalar memory loads out of the
+// image loop (a scalar load's wait also drains every LDS read in flight).
+// dsc: kFarrowDescChunk int4 in LDS; vw: the window after it.
+template <int TO, bool HI>
+__device__ inline void farrow_tile1(const DScene& S, const DGroup& G, int g, int tile, int mic, int T,
+                                    const DImage* __restrict__ imgs, int4* dsc, float4* vw,
+                                    const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
+                                    const float* __restrict__ v, float* __restrict__ part,
+                                    int32_t* __restrict__ status)
+{
+    const int tid = threadIdx.x;
+    const int n0 = tile * TO;
+    const int ws = n0 - G.dmax - 4;                    // source position of window slot 0
+    const int W = TO + (G.dmax - G.dmin) + 9;
+    const int plo = -T / 2, phi = (int)S.n_in + T / 2;   // positions with stored v
+    const float4* vs = (const float4*)(v + S.v_off);
+    for (int p = tid; p < W; p += TO) {
+        const int P = ws + p;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+        if (P >= plo && P < phi) {
+            const float4* q = vs + (int64_t)(P + T / 2) * 3;
+            a = q[0];
+            b = q[1];
+            c = q[2];
+        }
+        vw[3 * p] = a;
+        vw[3 * p + 1] = b;
+        vw[3 * p + 2] = c;
+    }
+
+    const int n = n0 + tid;
+    const bool active = n < (int)S.n_out;
+    const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
+    const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
+    const DImage* I = imgs + S.img_begin;
+    float acc = 0.0f;
+    int bad = 0;
+    int cR = 0, ck = 0;
+    float cv = 0.0f;
+    // descriptor j of the chunk: seg_off, R, gfac, n_seg
+    auto fetch = [&](int j, Seg& q, int& K, float& vv, float& gf) {
+        const int4 d = dsc[j];
+        const int R = __builtin_amdgcn_readfirstlane(d.y);
+        if (R != cR) {
+            cR = R;
+            ck = min(n / R, d.w - 1);
+            cv = (float)(n - ck * R);
+        }
+        const int off = __builtin_amdgcn_readfirstlane(d.x);
+        q = sgm[off + ck];
+        K = sgk[off + ck];
+        vv = cv;
+        gf = __int_as_float(d.z);
+    };
+    auto body = [&](const Seg& sg, int Ks, float vv, float gf) {
+        const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+        const float fl = floorf(dl);
+        int p = n - (Ks + (int)fl) - ws;
+        // positions outside the stored range read the window's zeros; a position
+        // outside the window (never, for a correct plan) is flagged and read as
+        // slot 0 with zero gain, without a branch
+        const bool out = (unsigned)p >= (unsigned)W;
+        bad |= out;
+        p = out ? 0 : p;
+        const float s = 2.0f * (dl - fl) - 1.0f;
+        const float4* vp = vw + __mul24(p, 3);
+        const float4 a = vp[0], b = vp[1];
+        float r;
+        if constexpr (HI) {
+            const float4 c = vp[2];
+            r = fmaf(c.w, s, c.z);
+            r = fmaf(r, s, c.y);
+            r = fmaf(r, s, c.x);
+            r = fmaf(r, s, b.w);
+        } else {
+            const float2 c = *(const float2*)&vp[2];
+            r = fmaf(c.y, s, c.x);
+            r = fmaf(r, s, b.w);
+        }
+        r = fmaf(r, s, b.z);
+        r = fmaf(r, s, b.y);
+        r = fmaf(r, s, b.x);
+        r = fmaf(r, s, a.w);
+        r = fmaf(r, s, a.z);
+        r = fmaf(r, s, a.y);
+        r = fmaf(r, s, a.x);
+        acc = fmaf(out ? 0.0f : gf * __builtin_amdgcn_rcpf((float)Ks + dl), r, acc);
+    };
+    for (int c0 = G.img_begin; c0 < G.img_end; c0 += kFarrowDescChunk) {
+        const int nc = min(kFarrowDescChunk, G.img_end - c0);
+        __syncthreads();                 // window staged; the previous chunk's descriptors read
+        for (int i = tid; i < nc; i += TO) {
+            const DImage& im = I[c0 + i];
+            dsc[i] = make_int4(im.seg_off, im.R, __float_as_int(im.gfac), im.n_seg);
+        }
+        __syncthreads();
+        if (!active) continue;
+        // three buffers in turn: image j is summed while j+1 and j+2 are in flight
+        Seg q0{}, q1{}, q2{};
+        int K0 = 0, K1 = 0, K2 = 0;
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        fetch(0, q0, K0, v0, g0);
+        if (nc > 1) fetch(1, q1, K1, v1, g1);
+        int j = 0;
+        for (; j + 2 < nc; j += 3) {
+            fetch(j + 2, q2, K2, v2, g2);
+            body(q0, K0, v0, g0);
+            if (j + 3 < nc) fetch(j + 3, q0, K0, v0, g0);
+            body(q1, K1, v1, g1);
+            if (j + 4 < nc) fetch(j + 4, q1, K1, v1, g1);
+            body(q2, K2, v2, g2);
+        }
+        if (j < nc) body(q0, K0, v0, g0);
+        if (j + 1 < nc) body(q1, K1, v1, g1);
+    }
+    if (active) {
+        if (bad) atomicOr(status, kStatusWindow);
+        part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
+    }
+    __syncthreads();
+}
+
+template <int TO, int RB, bool HI>
 __global__ __launch_bounds__(TO / RB) void k_farrow_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                         const DGroup* __restrict__ groups, int T, int hi,
+                                                         const DGroup* __restrict__ groups, int T,
                                                          const Seg* __restrict__ seg,
                                                          const int32_t* __restrict__ segK,
                                                          const float* __restrict__ v, float* __restrict__ part,
@@ -224,14 +359,18 @@ __global__ __launch_bounds__(TO / RB) void k_farrow_fwd(DScene S, const DImage* 
 {
     extern __shared__ float4 lds[];
     const int g = blockIdx.y;
-    farrow_tile<TO, RB>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, hi != 0, imgs, lds, seg, segK, v,
-                        part, status);
+    if constexpr (RB == 1)
+        farrow_tile1<TO, HI>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, imgs, (int4*)lds,
+                             lds + kFarrowDescChunk, seg, segK, v, part, status);
+    else
+        farrow_tile<TO, RB, HI>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, imgs,
+                                lds + kFarrowDescChunk, seg, segK, v, part, status);
 }
 
-template <int TO, int RB>
+template <int TO, int RB, bool HI>
 __global__ __launch_bounds__(TO / RB) void k_farrow_persistent(const DScene* __restrict__ scenes,
                                                                 const DImage* __restrict__ imgs,
-                                                                const DGroup* __restrict__ groups, int T, int hi,
+                                                                const DGroup* __restrict__ groups, int T,
                                                                 const WorkItem* __restrict__ items, int n_items,
                                                                 int32_t* __restrict__ ticket,
                                                                 const Seg* __restrict__ seg,
@@ -249,8 +388,12 @@ __global__ __launch_bounds__(TO / RB) void k_farrow_persistent(const DScene* __r
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        farrow_tile<TO, RB>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, hi != 0, imgs, lds, seg,
-                            segK, v, part, status);
+        if constexpr (RB == 1)
+            farrow_tile1<TO, HI>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, imgs, (int4*)lds,
+                                 lds + kFarrowDescChunk, seg, segK, v, part, status);
+        else
+            farrow_tile<TO, RB, HI>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, imgs,
+                                    lds + kFarrowDescChunk, seg, segK, v, part, status);
     }
 }
 
@@ -265,11 +408,11 @@ static hipError_t launch_farrow_fwd_t(const DScene& hs, int taps, int hi, const 
                                       float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(hs.window);
-    auto kern = k_farrow_fwd<TO, RB>;
+    auto kern = hi ? k_farrow_fwd<TO, RB, true> : k_farrow_fwd<TO, RB, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(TO / RB), lds, st, hs, d_imgs, d_groups, taps, hi, seg, segK, v, part,
+    hipLaunchKernelGGL(kern, grid, dim3(TO / RB), lds, st, hs, d_imgs, d_groups, taps, seg, segK, v, part,
                        d_status);
     return hipGetLastError();
 }
@@ -281,11 +424,11 @@ static hipError_t launch_farrow_pers_t(int n_wg, int window, int taps, int hi, c
                                        const float* v, float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(window);
-    auto kern = k_farrow_persistent<TO, RB>;
+    auto kern = hi ? k_farrow_persistent<TO, RB, true> : k_farrow_persistent<TO, RB, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, d_scenes, d_imgs, d_groups, taps, hi, items,
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, d_scenes, d_imgs, d_groups, taps, items,
                        n_items, ticket, seg, segK, v, part, d_status);
     return hipGetLastError();
 }
