@@ -26,13 +26,6 @@ namespace msim {
 
 namespace {
 
-__device__ inline float wave_sum(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Delay of image `im` at output n from its track segment.
 struct ImageSample {
     int K;        // integer delay
@@ -426,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
             }
         }
         if (valid) dout[(int64_t)ii * S.n_out] = Db;
-        E = wave_sum(E);
+        E = wave_sum_dpp(E);
         if (lane == 0) gout[(int64_t)ii * nrow] = E;
     }
     if (bad) atomicOr(status, kStatusWindow);
@@ -531,7 +524,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_track2(DScene S, const DImage* __
         }
         if (ok0) dout[(int64_t)ii * S.n_out] = Db0;
         if (ok1) dout[(int64_t)ii * S.n_out + 1] = Db1;
-        E = wave_sum(E);
+        E = wave_sum_dpp(E);
         if (lane == 0) {
             gout[(int64_t)ii * nrow] = E;
             gout[(int64_t)ii * nrow + 1] = 0.0f;

@@ -42,6 +42,26 @@ __device__ __forceinline__ float h16_hi(unsigned v)
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
 }
 
+// Sum over the 64 lanes of a wave by DPP (no LDS traffic): pairs and quads by
+// quad permutes, rows of 16 by mirrors, then rows combined by row broadcasts;
+// lane 63 ends with the total, which is returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float v)
+{
+    v += dpp_mov<0xB1, 0xF>(v);      // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E, 0xF>(v);      // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141, 0xF>(v);     // row_half_mirror
+    v += dpp_mov<0x140, 0xF>(v);     // row_mirror
+    v += dpp_mov<0x142, 0xA>(v);     // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xC>(v);     // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // ------------------------------------------------------------------ geometry
 
 // Segment of a PWL path holding t, T[0] <= t: the largest a <= n-2 with T[a] <= t

@@ -671,7 +671,9 @@ __global__ __launch_bounds__(256) void k_farrow_corr(DScene S, int T, const floa
 }
 
 // Gain and delay adjoints, Farrow form: per image sample r = sum_k v_k s^k and
-// dr/ds by Horner's rule for value and derivative.
+// dr/ds by Horner's rule for value and derivative.  Image descriptors come from
+// LDS (staged per chunk) and track data is fetched one image ahead, as in the
+// forward's one-output tile; the per-wave gain sums reduce by DPP.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage* __restrict__ imgs,
                                                           const DGroup* __restrict__ groups, int T,
@@ -682,51 +684,67 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage*
                                                           float* __restrict__ gpart, int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
-    float4* vw = lds;
+    int4* dsc = (int4*)lds;
+    float4* vw = lds + kFarrowDescChunk;
     constexpr int WAVES = NT / 64;
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const DGroup G = groups[S.grp_begin + g];
-    const int64_t n0 = (int64_t)tile * NT;
-    const int64_t ws = n0 - G.dmax - 4;
+    const int n0 = tile * NT;
+    const int ws = n0 - G.dmax - 4;
     const int W = NT + (G.dmax - G.dmin) + 9;
-    const int64_t plo = -T / 2, phi = S.n_in + T / 2;
+    const int plo = -T / 2, phi = (int)S.n_in + T / 2;
     const float4* vs = (const float4*)(v + S.v_off);
     for (int p = tid; p < W; p += NT) {
-        const int64_t Pp = ws + p;
+        const int Pp = ws + p;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
         if (Pp >= plo && Pp < phi) {
-            a = vs[(Pp + T / 2) * 3];
-            b = vs[(Pp + T / 2) * 3 + 1];
-            c = vs[(Pp + T / 2) * 3 + 2];
+            const float4* q = vs + (int64_t)(Pp + T / 2) * 3;
+            a = q[0];
+            b = q[1];
+            c = q[2];
         }
         vw[3 * p] = a;
         vw[3 * p + 1] = b;
         vw[3 * p + 2] = c;
     }
-    __syncthreads();
-    const int64_t n = n0 + tid;
-    const bool valid = n < S.n_out;
+    const int n_out = (int)S.n_out;
+    const int n = n0 + tid;
+    const bool valid = n < n_out;
     const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
-    const int64_t nc = valid ? n : S.n_out - 1;
-    const int64_t trk = (int64_t)mic * S.seg_per_mic;
+    const int nc = valid ? n : n_out - 1;
+    const Seg* sgm = seg + (int64_t)mic * S.seg_per_mic;
+    const int32_t* sgk = segK + (int64_t)mic * S.seg_per_mic;
     const DImage* I = imgs + S.img_begin;
     float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
     const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * WAVES;
     float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * WAVES + wave;
     int bad = 0;
-    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = I[ii];
-        int K;
-        float off, D;
-        delay_at(im, seg, segK, trk, nc, &K, &off, &D);
-        const int64_t P = nc - K;
-        const int p = (int)(P - ws);
+    int cR = 0, ck = 0;
+    float cv = 0.0f;
+    auto fetch = [&](int j, Seg& q, int& K, float& vv, float& gf) {
+        const int4 d = dsc[j];           // seg_off, R, gfac, n_seg
+        const int R = __builtin_amdgcn_readfirstlane(d.y);
+        if (R != cR) {
+            cR = R;
+            ck = min(nc / R, d.w - 1);
+            cv = (float)(nc - ck * R);
+        }
+        const int off = __builtin_amdgcn_readfirstlane(d.x);
+        q = sgm[off + ck];
+        K = sgk[off + ck];
+        vv = cv;
+        gf = __int_as_float(d.z);
+    };
+    auto body = [&](int ii, const Seg& sg, int Ks, float vv, float gf) {
+        const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+        const float fl = floorf(dl);
+        const int p = nc - (Ks + (int)fl) - ws;
         const bool inb = p >= 0 && p < W;
         if (valid && !inb) bad = 1;
         float E = 0.0f, Db = 0.0f;
         if (valid && inb && wy != 0.0f) {
-            const float s = 2.0f * off - 1.0f;
+            const float s = 2.0f * (dl - fl) - 1.0f;
             const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
             const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
             float r = cf[kFarrowStride - 1], dr = 0.0f;
@@ -735,15 +753,35 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage*
                 dr = fmaf(dr, s, r);
                 r = fmaf(r, s, cf[k]);
             }
-            const float iD = __builtin_amdgcn_rcpf(D);
-            const float gain = im.gfac * iD;
+            const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
             E = wy * r * ghat * iD;
-            Db = wy * gain * fmaf(2.0f, dr, -r * iD);
+            Db = wy * gf * iD * fmaf(2.0f, dr, -r * iD);
         }
         if (valid) dout[(int64_t)ii * S.n_out] = Db;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) E += __shfl_xor(E, o, 64);
+        E = wave_sum_dpp(E);
         if (lane == 0) gout[(int64_t)ii * nrow] = E;
+    };
+    for (int cb = G.img_begin; cb < G.img_end; cb += kFarrowDescChunk) {
+        const int nci = min(kFarrowDescChunk, G.img_end - cb);
+        __syncthreads();                 // window staged; the previous chunk's descriptors read
+        for (int i = tid; i < nci; i += NT) {
+            const DImage& im = I[cb + i];
+            dsc[i] = make_int4(im.seg_off, im.R, __float_as_int(im.gfac), im.n_seg);
+        }
+        __syncthreads();
+        // two buffers in turn: image j is processed while j+1 is in flight
+        Seg qa{}, qb{};
+        int Ka = 0, Kb = 0;
+        float va = 0.0f, vb = 0.0f, ga = 0.0f, gb = 0.0f;
+        fetch(0, qa, Ka, va, ga);
+        int j = 0;
+        for (; j + 1 < nci; j += 2) {
+            fetch(j + 1, qb, Kb, vb, gb);
+            body(cb + j, qa, Ka, va, ga);
+            if (j + 2 < nci) fetch(j + 2, qa, Ka, va, ga);
+            body(cb + j + 1, qb, Kb, vb, gb);
+        }
+        if (j < nci) body(cb + j, qa, Ka, va, ga);
     }
     if (bad) atomicOr(status, kStatusWindow);
 }
