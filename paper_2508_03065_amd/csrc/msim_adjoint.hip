@@ -580,8 +580,10 @@ hipError_t launch_adj_track(int taps, int nthreads, int rb, const DScene& hs, co
 // D_{k-1..k+2} by the Catmull-Rom basis at u = v/R; sum dL/dD(n) times each
 // weight.  One block per run of seg_adj_block_segs(R) segments of one image:
 // the run's outputs are loaded coalesced into LDS (segment stride R+1, so the
-// per-segment reads below fall in distinct banks), then one thread per segment
-// sums its R outputs in order.
+// per-segment reads below fall in distinct banks), then TPS consecutive threads
+// per segment (a power of two, as many as the block holds, at most 64) each sum
+// every TPS-th output of it, and the TPS partial sums are combined in a fixed
+// order within the wave.
 __global__ __launch_bounds__(kSegAdjThreads) void k_seg_adj(DScene S, const DImage* __restrict__ imgs,
                                                             const float* __restrict__ dbar,
                                                             float4* __restrict__ dseg)
@@ -604,26 +606,49 @@ __global__ __launch_bounds__(kSegAdjThreads) void k_seg_adj(DScene S, const DIma
     const int n0 = k0 * R;
     const int nv = min(nseg * R, (int)S.n_out - n0);       // outputs of this run
     const float* Db = dbar + ((int64_t)mic * S.n_img + lo) * S.n_out + n0;
-    for (int i = threadIdx.x; i < nseg * R; i += kSegAdjThreads) {
-        const int kk = i / R, v = i - kk * R;
-        st[kk * (R + 1) + v] = i < nv ? Db[i] : 0.0f;
+    // eight independent loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < nseg * R; i0 += 8 * kSegAdjThreads) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * kSegAdjThreads;
+            t[u] = i < nv ? Db[i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * kSegAdjThreads;
+            if (i < nseg * R) {
+                const int kk = i / R, v = i - kk * R;
+                st[kk * (R + 1) + v] = t[u];
+            }
+        }
     }
     __syncthreads();
-    const int kk = threadIdx.x;
-    if (kk >= nseg) return;
-    const float* row = st + kk * (R + 1);
-    const double iR = 1.0 / (double)R;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int v = 0; v < R; ++v) {
-        const double d = row[v];
-        const double u = v * iR, u2 = u * u, u3 = u2 * u;
-        s0 += d * 0.5 * (-u + 2.0 * u2 - u3);
-        s1 += d * 0.5 * (2.0 - 5.0 * u2 + 3.0 * u3);
-        s2 += d * 0.5 * (u + 4.0 * u2 - 3.0 * u3);
-        s3 += d * 0.5 * (-u2 + u3);
+    int tps = 1;
+    while (tps < 64 && tps * 2 * per <= kSegAdjThreads && tps * 2 <= R) tps *= 2;
+    const int kk = threadIdx.x / tps, j = threadIdx.x % tps;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    if (kk < nseg) {
+        const float* row = st + kk * (R + 1);
+        const float iR = 1.0f / (float)R;
+        for (int v = j; v < R; v += tps) {
+            const float d = row[v];
+            const float u = (float)v * iR;
+            s0 = fmaf(d, 0.5f * u * fmaf(u, 2.0f - u, -1.0f), s0);
+            s1 = fmaf(d, fmaf(u * u, fmaf(1.5f, u, -2.5f), 1.0f), s1);
+            s2 = fmaf(d, 0.5f * u * fmaf(u, fmaf(-3.0f, u, 4.0f), 1.0f), s2);
+            s3 = fmaf(d, 0.5f * u * u * (u - 1.0f), s3);
+        }
     }
-    dseg[(int64_t)mic * S.seg_per_mic + im.seg_off + k0 + kk] =
-        make_float4((float)s0, (float)s1, (float)s2, (float)s3);
+    // groups of tps lanes are aligned within a wave: halve them in a fixed order
+    for (int o = tps / 2; o > 0; o >>= 1) {
+        s0 += __shfl_down(s0, o, 64);
+        s1 += __shfl_down(s1, o, 64);
+        s2 += __shfl_down(s2, o, 64);
+        s3 += __shfl_down(s3, o, 64);
+    }
+    if (kk < nseg && j == 0)
+        dseg[(int64_t)mic * S.seg_per_mic + im.seg_off + k0 + kk] = make_float4(s0, s1, s2, s3);
 }
 
 // Per (mic, grid point k of an image): dL/dtau_k = fs * sum of the segment
