@@ -55,10 +55,12 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b)
 }  // namespace
 
 // The transpose reads the forward's quadratic table, rearranged tap-major:
-// three arrays Y, D1, D2 of [T/2][Lq] floats (a packed {Y, D1, D2, 0} per tap and
-// row, one b96 read instead of three b32, measured 25 % slower); then each wave
-// owns a window of (window - NT + 64) samples: its 64 outputs' taps under every
-// delay of the group.
+// three arrays Y, D1, D2 of [T/2][Lq] floats (a packed
+// {Y, D1, D2, 0} per tap and row, one b96 read instead of three b32, measured 25 %
+// slower); then each wave owns a window of (window - NT + 64) samples: its 64
+// outputs' taps under every delay of the group.  (Two outputs per lane, as in the
+// forward, cut the instructions per tap by a third but halve the waves a CU holds
+// within this LDS, and measured no faster.)
 size_t adj_x_lds_bytes(int taps, int Lq, int window, int nthreads)
 {
     return (size_t)3 * (taps / 2) * (size_t)Lq * sizeof(float) +
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
     float* tD1 = tY + H * LQ;
     float* tD2 = tD1 + H * LQ;
     float* wbase = tD2 + H * LQ;
-    // the interpolated tap weight a Y + b D1 + c D2 at table index i (tap-major)
+    // the interpolated tap weight a Y + b D1 + c D2 at table index i (tap-major;
+    // row r of tap d at d LQ + r)
     auto wt = [&](int i, float a, float b, float c) { return fmaf(a, tY[i], fmaf(b, tD1[i], c * tD2[i])); };
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
@@ -160,12 +163,7 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
         const float f = q - (float)kq;
         const float A = w, Bn = w * f, Bf = w * (1.0f - f), C = w * (0.5f * f * (f - 1.0f));
         const int rf = LQ - 1 - kq;
-        int kmin = K, kmax = K;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            kmin = min(kmin, __shfl_xor(kmin, o, 64));
-            kmax = max(kmax, __shfl_xor(kmax, o, 64));
-        }
+        const int kmin = wave_min_i(K), kmax = wave_max_i(K);
         if (kmax - kmin > 1) {
             // per-tap scatter; lanes sharing a source position (the integer delay
             // stepped between them) take a second pass

@@ -62,6 +62,36 @@ __device__ __forceinline__ float wave_sum_dpp(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Minimum and maximum over the 64 lanes of a wave by DPP (the same pattern;
+// lanes a step does not write keep their own value).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_self_i(int x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xF, false);
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    v = min(v, dpp_self_i<0xB1, 0xF>(v));
+    v = min(v, dpp_self_i<0x4E, 0xF>(v));
+    v = min(v, dpp_self_i<0x141, 0xF>(v));
+    v = min(v, dpp_self_i<0x140, 0xF>(v));
+    v = min(v, dpp_self_i<0x142, 0xA>(v));
+    v = min(v, dpp_self_i<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    v = max(v, dpp_self_i<0xB1, 0xF>(v));
+    v = max(v, dpp_self_i<0x4E, 0xF>(v));
+    v = max(v, dpp_self_i<0x141, 0xF>(v));
+    v = max(v, dpp_self_i<0x140, 0xF>(v));
+    v = max(v, dpp_self_i<0x142, 0xA>(v));
+    v = max(v, dpp_self_i<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // ------------------------------------------------------------------ geometry
 
 // Segment of a PWL path holding t, T[0] <= t: the largest a <= n-2 with T[a] <= t

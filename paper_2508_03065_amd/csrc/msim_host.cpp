@@ -415,17 +415,16 @@ namespace {
 // stored at row index r + 1 of a quad's qtab_pitch(Lq) rows.  Row -1 serves a lane
 // whose two outputs straddle an integer delay (the far side's base row sits one
 // below row 0).  qtable holds the bytes [Y | D1 | D2]; y_out, d1_out and d2_out
-// return rows 0 .. Lq-1 as floats (the fp16 values as rounded).
+// return the same values as floats in the same order (the fp16 values as rounded).
 void build_qtable(std::vector<uint8_t>& out, std::vector<float>& y_out, std::vector<float>& d1_out,
                   std::vector<float>& d2_out, int T, int Lq, double kbeta, double fc)
 {
     const int NG = T / 8, LP = qtab_pitch(Lq);
-    const size_t n = (size_t)NG * Lq * 4, np = (size_t)NG * LP * 4;
+    const size_t np = (size_t)NG * LP * 4;
     const double i0b = bessel_i0(kbeta);
-    y_out.assign(n, 0.0f);
-    d1_out.assign(n, 0.0f);
-    d2_out.assign(n, 0.0f);
-    std::vector<float> yp(np, 0.0f), d1p(np, 0.0f);
+    y_out.assign(np, 0.0f);
+    d1_out.assign(np, 0.0f);
+    d2_out.assign(np, 0.0f);
     std::vector<uint16_t> d2h(np, 0);
     for (int g = 0; g < NG; ++g)
         for (int row = -1; row < Lq; ++row)
@@ -433,35 +432,32 @@ void build_qtable(std::vector<uint8_t>& out, std::vector<float>& y_out, std::vec
                 double y[3];
                 for (int i = 0; i < 3; ++i) y[i] = fd_kernel((4 * g + e) + double(row + i) / Lq, T, kbeta, fc, i0b);
                 const size_t o = ((size_t)g * LP + row + 1) * 4 + e;
-                yp[o] = (float)y[0];
-                d1p[o] = (float)(y[1] - y[0]);
+                y_out[o] = (float)y[0];
+                d1_out[o] = (float)(y[1] - y[0]);
                 const _Float16 h = (_Float16)(y[2] - 2.0 * y[1] + y[0]);
                 std::memcpy(&d2h[o], &h, sizeof h);
-                if (row >= 0) {
-                    const size_t u = ((size_t)g * Lq + row) * 4 + e;
-                    y_out[u] = yp[o];
-                    d1_out[u] = d1p[o];
-                    d2_out[u] = (float)h;
-                }
+                d2_out[o] = (float)h;
             }
     out.resize(np * 4 * 2 + np * 2);
-    std::memcpy(out.data(), yp.data(), np * 4);
-    std::memcpy(out.data() + np * 4, d1p.data(), np * 4);
+    std::memcpy(out.data(), y_out.data(), np * 4);
+    std::memcpy(out.data() + np * 4, d1_out.data(), np * 4);
     std::memcpy(out.data() + np * 8, d2h.data(), np * 2);
 }
 
 void build_table(msim_plan* P)
 {
-    const int T = P->par.taps, Lq = P->par.table_phases;
+    const int T = P->par.taps, Lq = P->par.table_phases, LP = qtab_pitch(Lq);
     std::vector<float> y, d1, d2;
     build_qtable(P->qtable, y, d1, d2, T, Lq, P->par.kaiser_beta, P->par.cutoff);
     // the same values tap-major for the transpose: [Y | D1 | D2] of [T/2][Lq] floats
+    // (rows 0 .. Lq-1)
     P->atable.assign((size_t)3 * (T / 2) * Lq, 0.0f);
     const std::vector<float>* src[3] = {&y, &d1, &d2};
     for (int c = 0; c < 3; ++c)
         for (int d = 0; d < T / 2; ++d)
             for (int r = 0; r < Lq; ++r)
-                P->atable[((size_t)c * (T / 2) + d) * Lq + r] = (*src[c])[((size_t)(d / 4) * Lq + r) * 4 + d % 4];
+                P->atable[((size_t)c * (T / 2) + d) * Lq + r] =
+                    (*src[c])[((size_t)(d / 4) * LP + r + 1) * 4 + d % 4];
 }
 
 // Farrow coefficients: for every tap j = -T/2+1 .. T/2, the degree-M polynomial in
