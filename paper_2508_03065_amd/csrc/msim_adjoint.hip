@@ -69,7 +69,7 @@ size_t adj_x_lds_bytes(int taps, int Lq, int window, int nthreads)
 
 size_t adj_track_lds_bytes(int taps, int Lq, int window)
 {
-    return qtab_bytes(taps, Lq) + (size_t)window * sizeof(float4);
+    return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4);
 }
 
 // ------------------------------------------------------------ transpose delay
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     const float4* tabY = tab + 1;
     const float4* tabD1 = tab + NG * LP + 1;
     const uint2* tabD2 = (const uint2*)(tab + 2 * NG * LP) + 1;
-    float4* xw = lds + NG * LP * 40 / 16;
+    float4* xw = lds + qtab_bytes(T, L) / 16;
 
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
     const int n0 = tile * NT;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
-    for (int i = tid; i < NG * LP * 40 / 16; i += NT) tab[i] = table[i];
+    for (int i = tid; i < (int)(qtab_bytes(T, L) / 16); i += NT) tab[i] = table[i];
     const float* xs = x + S.x_off;
     const int n_in = (int)S.n_in;
     for (int p = tid; p < W; p += NT) {
@@ -457,8 +457,9 @@ __global__ __launch_bounds__(NT, 4) void k_adj_track2(DScene S, const DImage* __
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = TO + (G.dmax - G.dmin) + T + 8;
     const int n_in = (int)S.n_in;
+    const int half = split_half(W);
     load_qtab<T>(table, tab, L, NT);
-    stage_window(x + S.x_off, n_in, ws, W, xw, NT);
+    stage_window_split(x + S.x_off, n_in, ws, W, xw, NT);
     __syncthreads();
 
     const int n_out = (int)S.n_out;
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_track2(DScene S, const DImage* __
             if (act && !inb) bad = 1;
             if (act && inb) {
                 PairSums ps;
-            pair_sums<NG>(tq, LP, fr.kq, fr.kp, xw + p0, ps);
+                pair_sums<NG>(tq, LP, fr.kq, fr.kp, split_at(xw, half, p0), ps);
                 const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;
                 const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;
                 const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,

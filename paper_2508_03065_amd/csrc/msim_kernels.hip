@@ -223,10 +223,11 @@ hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t
 // (g, r), r in [-1, Lq) (qtab_pitch(Lq) rows per quad, row r at index r + 1):
 // Y(r) (float4), Y(r+1) - Y(r) (float4), Y(r+2) - 2 Y(r+1) + Y(r) (four fp16),
 // Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as overlapping
-// quads xw[p] = x[ws+p .. ws+p+3].
+// quads xw[p] = x[ws+p .. ws+p+3] (split by parity at two outputs per lane, one
+// entry more).
 size_t synth_lds_bytes(int taps, int Lq, int window)
 {
-    return qtab_bytes(taps, Lq) + (size_t)window * sizeof(float4);
+    return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4);
 }
 
 // One output tile of one delay group for one mic: stages the group's source
@@ -363,8 +364,9 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
     const int n0 = tile * TO;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = TO + (G.dmax - G.dmin) + T + 8;
+    const int half = split_half(W);
     const int n_in = (int)S.n_in;
-    stage_window(x + S.x_off, n_in, ws, W, xw, NT);
+    stage_window_split(x + S.x_off, n_in, ws, W, xw, NT);
     __syncthreads();
 
     const int n = n0 + 2 * tid;
@@ -420,7 +422,7 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
                 return;
             }
             PairSums ps;
-            pair_sums<NG>(tq, LP, fr.kq, fr.kp, xw + p0, ps);
+            pair_sums<NG>(tq, LP, fr.kq, fr.kp, split_at(xw, half, p0), ps);
             const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;                   // near side
             const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;     // far side
             const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,

@@ -47,6 +47,35 @@ __device__ __forceinline__ void stage_window(const float* __restrict__ xs, int n
     }
 }
 
+// The two-outputs-per-lane window layout.  Lane l's outputs sit two positions
+// after lane l-1's, so with contiguous quads the 16 lanes of a quarter-wave read
+// 32 B apart and meet every bank slot twice.  Even positions are kept in the first
+// half of the entries and odd ones in the second: position p at entry
+// (p & 1) * half + (p >> 1), half = (W + 1) / 2 (W + 1 entries at most).  Positions
+// of one parity 4 apart are then 2 entries apart, and the lanes of a quarter-wave
+// (mostly one parity) read 16 B apart.
+__device__ __forceinline__ int split_half(int W) { return (W + 1) >> 1; }
+
+__device__ __forceinline__ const float4* split_at(const float4* xw, int half, int p)
+{
+    return xw + (p & 1) * half + (p >> 1);
+}
+
+__device__ __forceinline__ void stage_window_split(const float* __restrict__ xs, int n_in, int ws, int W, float4* xw,
+                                                   int nthreads)
+{
+    const int half = split_half(W);
+    for (int p = threadIdx.x; p < W; p += nthreads) {
+        const int q = ws + p;
+        float4 v;
+        v.x = (q >= 0 && q < n_in) ? xs[q] : 0.0f;
+        v.y = (q + 1 >= 0 && q + 1 < n_in) ? xs[q + 1] : 0.0f;
+        v.z = (q + 2 >= 0 && q + 2 < n_in) ? xs[q + 2] : 0.0f;
+        v.w = (q + 3 >= 0 && q + 3 < n_in) ? xs[q + 3] : 0.0f;
+        xw[(p & 1) * half + (p >> 1)] = v;
+    }
+}
+
 // The frame of a lane's outputs n, n+1 for one image with delays D_m = K_ms + d_m
 // (integer base plus a small FP32 offset).  Both read the table rows of one
 // frame: K, the smaller of the two integer delays, with phases q_m = (D_m - K) Lq
@@ -74,14 +103,15 @@ __device__ __forceinline__ PairFrame pair_frame(float d0, int K0s, float d1, int
 }
 
 // Tap sums of one image for outputs n (0) and n+1 (1) in the frame K, with xq the
-// source window at n - K, written into ps (by reference: returning the sums by
+// split source window's entry of position n - K (split_at), written into ps (by reference: returning the sums by
 // value made the register allocator spill).  Near side (taps j = -(4g+e),
 // |u| = 4g+e + mu, base row kq): A += Y x, B += D1 x, C += D2 x; far side (taps
 // j = 1+4g+e, |u| = 4g+e + 1-mu, base row kp): A += Y x, Bm += D1 x, Cm += D2 x.
 // The value is then
 //   s = A + f B + h Bm + f (f-1)/2 C + h (h-1)/2 Cm.
-// Output n reads x[n-K+4g+e] on the near side and x[n-K-1-4g-e] on the far side;
-// output n+1 the next position.  One table read (Y, D1, D2 of four taps) and one
+// Output n reads x[n-K+4g+e] on the near side and x[n-K-1-4g-e] on the far side
+// (quads 4g and -4-4g, entries 2g and -2-2g of the split window); output n+1 the
+// next position.  One table read (Y, D1, D2 of four taps) and one
 // new source quad serve eight taps of both outputs.  The 2 T/8 steps are
 // software-pipelined one deep: the rows and the source quad of step st+1 are read
 // while step st is summed, and scheduling barriers keep the pipeline at that depth
@@ -98,7 +128,7 @@ __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp
     float& A1 = ps.A1; float& B1 = ps.B1; float& Bm1 = ps.Bm1; float& C1 = ps.C1; float& Cm1 = ps.Cm1;
     A0 = B0 = Bm0 = C0 = Cm0 = A1 = B1 = Bm1 = C1 = Cm1 = 0.0f;
     float4 xo = xq[0];                  // the previous step's source quad
-    float4 xc = xq[4], Yc = tq.Y[kq], D1c = tq.D1[kq];
+    float4 xc = xq[2], Yc = tq.Y[kq], D1c = tq.D1[kq];
     uint2 D2c = tq.D2[kq];
 #pragma unroll
     for (int st = 0; st < 2 * NG; ++st) {
@@ -108,7 +138,7 @@ __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp
         if (st + 1 < 2 * NG) {
             const int s1 = st + 1;
             const int row = s1 < NG ? s1 * LP + kq : (s1 - NG) * LP + kp;
-            xnx = s1 < NG ? xq[4 * s1 + 4] : xq[-4 - 4 * (s1 - NG)];
+            xnx = s1 < NG ? xq[2 * s1 + 2] : xq[-2 - 2 * (s1 - NG)];
             Ynx = tq.Y[row];
             D1nx = tq.D1[row];
             D2nx = tq.D2[row];
