@@ -395,18 +395,26 @@ __global__ __launch_bounds__(NT) void k_adj_track(DScene S, const DImage* __rest
                 for (int gi = 0; gi < NG; ++gi) {
                     const float4 xn = xq[4 * gi];
                     const float4 Y = tabY[gi * LP + kq], D1 = tabD1[gi * LP + kq];
-                    const uint2 D2 = tabD2[gi * LP + kq];
-                    A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B); C = fmaf(h16_lo(D2.x), xn.x, C);
-                    A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B); C = fmaf(h16_hi(D2.x), xn.y, C);
-                    A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B); C = fmaf(h16_lo(D2.y), xn.z, C);
-                    A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B); C = fmaf(h16_hi(D2.y), xn.w, C);
+                    A = fmaf(Y.x, xn.x, A); B = fmaf(D1.x, xn.x, B);
+                    A = fmaf(Y.y, xn.y, A); B = fmaf(D1.y, xn.y, B);
+                    A = fmaf(Y.z, xn.z, A); B = fmaf(D1.z, xn.z, B);
+                    A = fmaf(Y.w, xn.w, A); B = fmaf(D1.w, xn.w, B);
+                    if (gi < qcorr_quads(T)) {  // further out the quadratic term is zero
+                        const uint2 D2 = tabD2[gi * LP + kq];
+                        C = fmaf(h16_lo(D2.x), xn.x, C); C = fmaf(h16_hi(D2.x), xn.y, C);
+                        C = fmaf(h16_lo(D2.y), xn.z, C); C = fmaf(h16_hi(D2.y), xn.w, C);
+                    }
                     const float4 xp = xq[-4 - 4 * gi];
                     const float4 Ym = tabY[gi * LP + kp], E1 = tabD1[gi * LP + kp];
-                    const uint2 E2 = tabD2[gi * LP + kp];
-                    A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm); C = fmaf(h16_lo(E2.x), xp.w, C);
-                    A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm); C = fmaf(h16_hi(E2.x), xp.z, C);
-                    A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm); C = fmaf(h16_lo(E2.y), xp.y, C);
-                    A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm); C = fmaf(h16_hi(E2.y), xp.x, C);
+                    A = fmaf(Ym.x, xp.w, A); Bm = fmaf(E1.x, xp.w, Bm);
+                    A = fmaf(Ym.y, xp.z, A); Bm = fmaf(E1.y, xp.z, Bm);
+                    A = fmaf(Ym.z, xp.y, A); Bm = fmaf(E1.z, xp.y, Bm);
+                    A = fmaf(Ym.w, xp.x, A); Bm = fmaf(E1.w, xp.x, Bm);
+                    if (gi < qcorr_quads(T)) {
+                        const uint2 E2 = tabD2[gi * LP + kp];
+                        C = fmaf(h16_lo(E2.x), xp.w, C); C = fmaf(h16_hi(E2.x), xp.z, C);
+                        C = fmaf(h16_lo(E2.y), xp.y, C); C = fmaf(h16_hi(E2.y), xp.x, C);
+                    }
                 }
                 const float s = fmaf(0.5f * f * (f - 1.0f), C, fmaf(1.0f - f, Bm, fmaf(f, B, A)));
                 const float sd = Lf * fmaf(f - 0.5f, C, B - Bm);

@@ -411,7 +411,8 @@ namespace {
 // Quadratic-interpolation half table, grouped by tap quads, as three arrays:
 // for quad g and row r in [-1, Lq), Y(r), Y(r+1) - Y(r) (float4 each) and
 // Y(r+2) - 2 Y(r+1) + Y(r) (four fp16: it is below 1e-3, so fp16 keeps it to
-// ~3e-7 absolute), with Y(r) = h((4g+e) + r/Lq), e = 0..3 (differences in double),
+// ~3e-7 absolute; zero for g >= qcorr_quads(T)), with Y(r) = h((4g+e) + r/Lq),
+// e = 0..3 (differences in double),
 // stored at row index r + 1 of a quad's qtab_pitch(Lq) rows.  Row -1 serves a lane
 // whose two outputs straddle an integer delay (the far side's base row sits one
 // below row 0).  qtable holds the bytes [Y | D1 | D2]; y_out, d1_out and d2_out
@@ -434,7 +435,7 @@ void build_qtable(std::vector<uint8_t>& out, std::vector<float>& y_out, std::vec
                 const size_t o = ((size_t)g * LP + row + 1) * 4 + e;
                 y_out[o] = (float)y[0];
                 d1_out[o] = (float)(y[1] - y[0]);
-                const _Float16 h = (_Float16)(y[2] - 2.0 * y[1] + y[0]);
+                const _Float16 h = g < qcorr_quads(T) ? (_Float16)(y[2] - 2.0 * y[1] + y[0]) : (_Float16)0.0;
                 std::memcpy(&d2h[o], &h, sizeof h);
                 d2_out[o] = (float)h;
             }

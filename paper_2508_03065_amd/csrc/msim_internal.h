@@ -135,6 +135,12 @@ hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int
 hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
                              const float* part, float* y, hipStream_t st);
 
+// Tap quads of the half table that carry the quadratic term: those within 3/4 of
+// the half-width.  Further out the kernel's second differences are below 1.3e-6
+// at 128 phases (taps 3T/8 .. T/2 of a Kaiser-windowed sinc with beta = 8); their
+// term, at most 1.5e-7 of the kernel's energy for fractions in [0, 1], is below the
+// FP32 rounding of the tap sum, and the table stores them as zero.
+__host__ __device__ constexpr int qcorr_quads(int taps) { return taps / 8 - taps / 32; }
 // Rows per tap quad of the quadratic FD table: rows -1 .. Lq-1.
 __host__ __device__ constexpr int qtab_pitch(int Lq) { return Lq + 1; }
 // Bytes of the quadratic FD table ([Y | D1 | D2], 40 B per quad row).

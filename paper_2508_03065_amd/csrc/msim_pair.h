@@ -121,7 +121,7 @@ struct PairSums {
     float A1, B1, Bm1, C1, Cm1;
 };
 
-template <int NG>
+template <int NG, int NC = qcorr_quads(8 * NG)>
 __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp, const float4* xq, PairSums& ps)
 {
     float& A0 = ps.A0; float& B0 = ps.B0; float& Bm0 = ps.Bm0; float& C0 = ps.C0; float& Cm0 = ps.Cm0;
@@ -141,33 +141,47 @@ __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp
             xnx = s1 < NG ? xq[2 * s1 + 2] : xq[-2 - 2 * (s1 - NG)];
             Ynx = tq.Y[row];
             D1nx = tq.D1[row];
-            D2nx = tq.D2[row];
+            if ((s1 < NG ? s1 : s1 - NG) < NC) D2nx = tq.D2[row];
         }
         const float c0 = h16_lo(D2c.x), c1 = h16_hi(D2c.x), c2 = h16_lo(D2c.y), c3 = h16_hi(D2c.y);
+        // quads from NC on have no quadratic term (their table values are zero)
+        const bool qc = (st < NG ? st : st - NG) < NC;
         if (st < NG) {
             // near side: output n reads quad 4g (xo, component e), output n+1 the
             // next position (the last from quad 4g+4 = xc)
             const float4 xn = xo, xa = xc;
-            A0 = fmaf(Yc.x, xn.x, A0); B0 = fmaf(D1c.x, xn.x, B0); C0 = fmaf(c0, xn.x, C0);
-            A1 = fmaf(Yc.x, xn.y, A1); B1 = fmaf(D1c.x, xn.y, B1); C1 = fmaf(c0, xn.y, C1);
-            A0 = fmaf(Yc.y, xn.y, A0); B0 = fmaf(D1c.y, xn.y, B0); C0 = fmaf(c1, xn.y, C0);
-            A1 = fmaf(Yc.y, xn.z, A1); B1 = fmaf(D1c.y, xn.z, B1); C1 = fmaf(c1, xn.z, C1);
-            A0 = fmaf(Yc.z, xn.z, A0); B0 = fmaf(D1c.z, xn.z, B0); C0 = fmaf(c2, xn.z, C0);
-            A1 = fmaf(Yc.z, xn.w, A1); B1 = fmaf(D1c.z, xn.w, B1); C1 = fmaf(c2, xn.w, C1);
-            A0 = fmaf(Yc.w, xn.w, A0); B0 = fmaf(D1c.w, xn.w, B0); C0 = fmaf(c3, xn.w, C0);
-            A1 = fmaf(Yc.w, xa.x, A1); B1 = fmaf(D1c.w, xa.x, B1); C1 = fmaf(c3, xa.x, C1);
+            A0 = fmaf(Yc.x, xn.x, A0); B0 = fmaf(D1c.x, xn.x, B0);
+            A1 = fmaf(Yc.x, xn.y, A1); B1 = fmaf(D1c.x, xn.y, B1);
+            A0 = fmaf(Yc.y, xn.y, A0); B0 = fmaf(D1c.y, xn.y, B0);
+            A1 = fmaf(Yc.y, xn.z, A1); B1 = fmaf(D1c.y, xn.z, B1);
+            A0 = fmaf(Yc.z, xn.z, A0); B0 = fmaf(D1c.z, xn.z, B0);
+            A1 = fmaf(Yc.z, xn.w, A1); B1 = fmaf(D1c.z, xn.w, B1);
+            A0 = fmaf(Yc.w, xn.w, A0); B0 = fmaf(D1c.w, xn.w, B0);
+            A1 = fmaf(Yc.w, xa.x, A1); B1 = fmaf(D1c.w, xa.x, B1);
+            if (qc) {
+                C0 = fmaf(c0, xn.x, C0); C1 = fmaf(c0, xn.y, C1);
+                C0 = fmaf(c1, xn.y, C0); C1 = fmaf(c1, xn.z, C1);
+                C0 = fmaf(c2, xn.z, C0); C1 = fmaf(c2, xn.w, C1);
+                C0 = fmaf(c3, xn.w, C0); C1 = fmaf(c3, xa.x, C1);
+            }
         } else {
             // far side: output n reads quad -4-4g (xc, component 3-e), output n+1
             // the next position (the first from quad -4g = xo)
             const float4 xp = xc, xr = xo;
-            A0 = fmaf(Yc.x, xp.w, A0); Bm0 = fmaf(D1c.x, xp.w, Bm0); Cm0 = fmaf(c0, xp.w, Cm0);
-            A1 = fmaf(Yc.x, xr.x, A1); Bm1 = fmaf(D1c.x, xr.x, Bm1); Cm1 = fmaf(c0, xr.x, Cm1);
-            A0 = fmaf(Yc.y, xp.z, A0); Bm0 = fmaf(D1c.y, xp.z, Bm0); Cm0 = fmaf(c1, xp.z, Cm0);
-            A1 = fmaf(Yc.y, xp.w, A1); Bm1 = fmaf(D1c.y, xp.w, Bm1); Cm1 = fmaf(c1, xp.w, Cm1);
-            A0 = fmaf(Yc.z, xp.y, A0); Bm0 = fmaf(D1c.z, xp.y, Bm0); Cm0 = fmaf(c2, xp.y, Cm0);
-            A1 = fmaf(Yc.z, xp.z, A1); Bm1 = fmaf(D1c.z, xp.z, Bm1); Cm1 = fmaf(c2, xp.z, Cm1);
-            A0 = fmaf(Yc.w, xp.x, A0); Bm0 = fmaf(D1c.w, xp.x, Bm0); Cm0 = fmaf(c3, xp.x, Cm0);
-            A1 = fmaf(Yc.w, xp.y, A1); Bm1 = fmaf(D1c.w, xp.y, Bm1); Cm1 = fmaf(c3, xp.y, Cm1);
+            A0 = fmaf(Yc.x, xp.w, A0); Bm0 = fmaf(D1c.x, xp.w, Bm0);
+            A1 = fmaf(Yc.x, xr.x, A1); Bm1 = fmaf(D1c.x, xr.x, Bm1);
+            A0 = fmaf(Yc.y, xp.z, A0); Bm0 = fmaf(D1c.y, xp.z, Bm0);
+            A1 = fmaf(Yc.y, xp.w, A1); Bm1 = fmaf(D1c.y, xp.w, Bm1);
+            A0 = fmaf(Yc.z, xp.y, A0); Bm0 = fmaf(D1c.z, xp.y, Bm0);
+            A1 = fmaf(Yc.z, xp.z, A1); Bm1 = fmaf(D1c.z, xp.z, Bm1);
+            A0 = fmaf(Yc.w, xp.x, A0); Bm0 = fmaf(D1c.w, xp.x, Bm0);
+            A1 = fmaf(Yc.w, xp.y, A1); Bm1 = fmaf(D1c.w, xp.y, Bm1);
+            if (qc) {
+                Cm0 = fmaf(c0, xp.w, Cm0); Cm1 = fmaf(c0, xr.x, Cm1);
+                Cm0 = fmaf(c1, xp.z, Cm0); Cm1 = fmaf(c1, xp.w, Cm1);
+                Cm0 = fmaf(c2, xp.y, Cm0); Cm1 = fmaf(c2, xp.z, Cm1);
+                Cm0 = fmaf(c3, xp.x, Cm0); Cm1 = fmaf(c3, xp.y, Cm1);
+            }
         }
         xo = st + 1 == NG ? x0 : xc;
         xc = xnx;
