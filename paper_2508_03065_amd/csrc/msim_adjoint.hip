@@ -185,8 +185,17 @@ __global__ __launch_bounds__(NT) void k_adj_x(DScene S, const DImage* __restrict
         // (d = s - H - 1 + dK) pN + (s-H-1) LQ
         const int pF = (1 - dK) * LQ + rf;
         const int pN = dK * LQ + kq;
-        auto far = [&](int s) { return wt(pF + (H - 1 - s) * LQ, A, Bf, C); };
-        auto near = [&](int s) { return wt(pN + (s - H - 1) * LQ, A, Bn, C); };
+        // steps whose taps lie beyond the quadratic term's quads for either dK
+        // (zero second differences) skip that read
+        constexpr int DQ = 4 * qcorr_quads(T);
+        auto far = [&](int s) {
+            const int i = pF + (H - 1 - s) * LQ;
+            return H - 1 - s >= DQ ? fmaf(A, tY[i], Bf * tD1[i]) : wt(i, A, Bf, C);
+        };
+        auto near = [&](int s) {
+            const int i = pN + (s - H - 1) * LQ;
+            return s - H - 1 >= DQ ? fmaf(A, tY[i], Bn * tD1[i]) : wt(i, A, Bn, C);
+        };
         // relative position (to n0w - kmin) of lane l at step s: l + s - H - 1
         const int rel0 = n0w - kmin - wsw;               // window index of relative position 0
         float acc, out = 0.0f;
