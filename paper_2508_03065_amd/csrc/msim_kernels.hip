@@ -379,6 +379,9 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
 
     const int n = n0 + 2 * tid;
     const int n_out = (int)S.n_out;
+    // every lane's taps reach source samples for every image of the group (integer
+    // delays within [dmin, dmax]): the per-image check is skipped
+    const bool all_reach = n0 - G.dmax + T / 2 >= 0 && n0 + TO - G.dmin - T / 2 < n_in;
     if (n < n_out) {
         const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
         const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
@@ -423,7 +426,7 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
             const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
             const int K = fr.K;
             // skip the image when no lane's taps reach a source sample
-            if (!__any(n - K + T / 2 >= 0 && n - K - T / 2 < n_in)) return;
+            if (!all_reach && !__any(n - K + T / 2 >= 0 && n - K - T / 2 < n_in)) return;
             const int p0 = n - K - ws;
             if (p0 < T / 2 || p0 > W - 1 - T / 2) {
                 bad = 1;
@@ -433,10 +436,8 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
             pair_sums<NG>(tq, LP, fr.kq, fr.kp, split_at(xw, half, p0), ps);
             const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;                   // near side
             const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;     // far side
-            const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,
-                                  fmaf(0.5f * f0 * (f0 - 1.0f), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
-            const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), ps.Cm1,
-                                  fmaf(0.5f * f1 * (f1 - 1.0f), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
+            const float s0 = fmaf(qweight(h0), ps.Cm0, fmaf(qweight(f0), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
+            const float s1 = fmaf(qweight(h1), ps.Cm1, fmaf(qweight(f1), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
             acc0 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K0s + d0), s0, acc0);
             acc1 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K1s + d1), s1, acc1);
         };

@@ -58,7 +58,17 @@ __device__ __forceinline__ int split_half(int W) { return (W + 1) >> 1; }
 
 __device__ __forceinline__ const float4* split_at(const float4* xw, int half, int p)
 {
-    return xw + (p & 1) * half + (p >> 1);
+    // byte offset (p >> 1) * 16 + (p & 1) * half * 16, p >= 0
+    const uint32_t up = (uint32_t)p;
+    const uint32_t odd = (uint32_t)(((int)(up << 31)) >> 31);          // all ones for odd p
+    return (const float4*)((const char*)xw + (((up << 3) & ~15u) + (odd & (uint32_t)(half * 16))));
+}
+
+// f (f - 1) / 2, the weight of the quadratic term, in two instructions.
+__device__ __forceinline__ float qweight(float f)
+{
+    const float t = 0.5f * f;
+    return fmaf(t, f, -t);
 }
 
 __device__ __forceinline__ void stage_window_split(const float* __restrict__ xs, int n_in, int ws, int W, float4* xw,
@@ -127,9 +137,16 @@ __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp
     float& A0 = ps.A0; float& B0 = ps.B0; float& Bm0 = ps.Bm0; float& C0 = ps.C0; float& Cm0 = ps.Cm0;
     float& A1 = ps.A1; float& B1 = ps.B1; float& Bm1 = ps.Bm1; float& C1 = ps.C1; float& Cm1 = ps.Cm1;
     A0 = B0 = Bm0 = C0 = Cm0 = A1 = B1 = Bm1 = C1 = Cm1 = 0.0f;
+    // each side's rows of quad 0 (the steps add whole quads, LP rows each)
+    const float4* Yn = tq.Y + kq;
+    const float4* D1n = tq.D1 + kq;
+    const uint2* D2n = tq.D2 + kq;
+    const float4* Yf = tq.Y + kp;          // kp >= -1 (row -1 exists)
+    const float4* D1f = tq.D1 + kp;
+    const uint2* D2f = tq.D2 + kp;
     float4 xo = xq[0];                  // the previous step's source quad
-    float4 xc = xq[2], Yc = tq.Y[kq], D1c = tq.D1[kq];
-    uint2 D2c = tq.D2[kq];
+    float4 xc = xq[2], Yc = Yn[0], D1c = D1n[0];
+    uint2 D2c = D2n[0];
 #pragma unroll
     for (int st = 0; st < 2 * NG; ++st) {
         float4 xnx = xc, Ynx = Yc, D1nx = D1c, x0 = xo;
@@ -137,11 +154,11 @@ __device__ __forceinline__ void pair_sums(const QTab& tq, int LP, int kq, int kp
         if (st + 1 == NG) x0 = xq[0];
         if (st + 1 < 2 * NG) {
             const int s1 = st + 1;
-            const int row = s1 < NG ? s1 * LP + kq : (s1 - NG) * LP + kp;
+            const int g1 = s1 < NG ? s1 : s1 - NG;
             xnx = s1 < NG ? xq[2 * s1 + 2] : xq[-2 - 2 * (s1 - NG)];
-            Ynx = tq.Y[row];
-            D1nx = tq.D1[row];
-            if ((s1 < NG ? s1 : s1 - NG) < NC) D2nx = tq.D2[row];
+            Ynx = s1 < NG ? Yn[g1 * LP] : Yf[g1 * LP];
+            D1nx = s1 < NG ? D1n[g1 * LP] : D1f[g1 * LP];
+            if (g1 < NC) D2nx = s1 < NG ? D2n[g1 * LP] : D2f[g1 * LP];
         }
         const float c0 = h16_lo(D2c.x), c1 = h16_hi(D2c.x), c2 = h16_lo(D2c.y), c3 = h16_hi(D2c.y);
         // quads from NC on have no quadratic term (their table values are zero)
