@@ -527,45 +527,50 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_u(DScene S, const DImage* __r
     const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
     const DGroup G = groups[S.grp_begin + g];
     const int64_t npos = S.n_in + T;
-    const int64_t P0 = (int64_t)tile * NT - T / 2;
-    const int64_t nw = P0 + G.dmin - 4;                 // output sample of gy window slot 0
+    // sample indices fit in 32 bits (outputs and inputs are capped at 2^23 samples)
+    const int P0 = tile * NT - T / 2;
+    const int nw = P0 + G.dmin - 4;                     // output sample of gy window slot 0
     const int W = NT + (G.dmax - G.dmin) + 9;
+    const int n_out = (int)S.n_out;
     const float* gys = gy + S.y_off + (int64_t)mic * S.n_out;
     for (int p = tid; p < W; p += NT) {
-        const int64_t n = nw + p;
-        gw[p] = (n >= 0 && n < S.n_out) ? gys[n] : 0.0f;
+        const int n = nw + p;
+        gw[p] = (n >= 0 && n < n_out) ? gys[n] : 0.0f;
     }
     __syncthreads();
-    const int64_t P = P0 + tid;
-    if (P >= S.n_in + T / 2) return;
+    const int P = P0 + tid;
+    if (P >= (int)S.n_in + T / 2) return;
     const int64_t trk = (int64_t)mic * S.seg_per_mic;
     const DImage* I = imgs + S.img_begin;
-    const int64_t nlast = S.n_out - 1;
+    const int nlast = n_out - 1;
     float u[kFarrowStride];
 #pragma unroll
     for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
     int bad = 0;
+    // the images are sorted by delay: each fixed-point iteration starts from the
+    // integer delay the previous image ended with
+    int Kguess = (G.dmin + G.dmax) / 2;
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
         const DImage im = I[ii];
         // delay at output c, re-reading the track segment only when c leaves it
         int kc = -1, Kseg = 0;
         Seg sg{};
-        auto eval = [&](int64_t c, int* K, float* off, float* D) {
+        auto eval = [&](int c, int* K, float* off, float* D) {
             const int k = min(max((int)(((float)c + 0.5f) * im.invR), 0), im.n_seg - 1);
             if (k != kc) {
                 kc = k;
                 sg = seg[trk + im.seg_off + k];
                 Kseg = segK[trk + im.seg_off + k];
             }
-            const float v = (float)(c - (int64_t)k * im.R);
+            const float v = (float)(c - k * im.R);
             const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
             const float fl = floorf(d);
             *K = Kseg + (int)fl;
             *off = d - fl;
             *D = (float)Kseg + d;
         };
-        auto add = [&](int64_t c, float off, float D) {
-            const int64_t p = c - nw;
+        auto add = [&](int c, float off, float D) {
+            const int p = c - nw;
             if (p < 0 || p >= W) {
                 bad = 1;
                 return;
@@ -580,14 +585,15 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_u(DScene S, const DImage* __r
         };
         int K;
         float off, D;
-        int64_t n = min(max(P + (G.dmin + G.dmax) / 2, (int64_t)0), nlast);
+        int n = min(max(P + Kguess, 0), nlast);
         eval(n, &K, &off, &D);
         for (int it = 0; it < 16; ++it) {
-            const int64_t nn = min(max(P + K, (int64_t)0), nlast);
+            const int nn = min(max(P + K, 0), nlast);
             if (nn == n) break;
             n = nn;
             eval(n, &K, &off, &D);
         }
+        Kguess = K;
         // n - K(n) is nondecreasing with steps of 0, 1 or 2, so the outputs
         // reading P are n itself (when it solves the equation) and its neighbours
         const bool hit = (n - K == P);
