@@ -45,13 +45,6 @@ __device__ inline ImageSample sample_of(const DImage& im, int k, const Seg& sg, 
     return r;
 }
 
-__device__ inline int64_t floordiv(int64_t a, int64_t b)
-{
-    int64_t q = a / b;
-    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-    return q;
-}
-
 }  // namespace
 
 // The transpose reads the forward's quadratic table, rearranged tap-major:
@@ -281,25 +274,25 @@ hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* 
 // Gathers the partial windows that cover each input sample, in a fixed order
 // (mic, group, tile).  Window (mic, g, tile) covers inputs
 // [tile*NT - c_g, tile*NT - c_g + W_g),  c_g = dmax_g + T/2 + 4.
-__global__ __launch_bounds__(256) void k_reduce_x(DScene S, const DGroup* __restrict__ groups, int NT, int T,
+__global__ __launch_bounds__(256) void k_reduce_x(DScene S, const DGroup* __restrict__ groups, int lg_nt, int T,
                                                   const float* __restrict__ xpart, float* __restrict__ gx)
 {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= S.n_in) return;
+    // 32-bit sample indices (inputs are capped at 2^23 samples); NT = 2^lg_nt, so
+    // floor division by NT is an arithmetic shift
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= (int)S.n_in) return;
+    const int NT = 1 << lg_nt;
+    const int nt_last = (int)S.n_tiles - 1;
     float acc = 0.0f;
     for (int mic = 0; mic < S.n_mics; ++mic)
         for (int g = 0; g < S.n_grp; ++g) {
             const DGroup G = groups[S.grp_begin + g];
-            const int64_t cg = G.dmax + T / 2 + 4;
-            const int64_t Wg = NT + (G.dmax - G.dmin) + T + 8;
-            int64_t t_lo = floordiv(m + cg - Wg + 1 + NT - 1, NT);
-            int64_t t_hi = floordiv(m + cg, NT);
-            t_lo = t_lo < 0 ? 0 : t_lo;
-            t_hi = t_hi > S.n_tiles - 1 ? S.n_tiles - 1 : t_hi;
-            for (int64_t t = t_lo; t <= t_hi; ++t) {
-                const int64_t p = m - (t * NT - cg);
-                acc += xpart[(((int64_t)mic * S.n_grp + g) * S.n_tiles + t) * S.window + p];
-            }
+            const int cg = G.dmax + T / 2 + 4;
+            const int Wg = NT + (G.dmax - G.dmin) + T + 8;
+            const int t_lo = max((m + cg - Wg + NT) >> lg_nt, 0);
+            const int t_hi = min((m + cg) >> lg_nt, nt_last);
+            const float* xp = xpart + ((int64_t)mic * S.n_grp + g) * S.n_tiles * S.window;
+            for (int t = t_lo; t <= t_hi; ++t) acc += xp[(int64_t)t * S.window + (m - (t * NT - cg))];
         }
     gx[S.x_off + m] = acc;
 }
@@ -307,8 +300,11 @@ __global__ __launch_bounds__(256) void k_reduce_x(DScene S, const DGroup* __rest
 hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
                            float* gx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)((hs.n_in + 255) / 256)), dim3(256), 0, st, hs, d_groups,
-                       nthreads, taps, xpart, gx);
+    int lg = 0;
+    while ((1 << lg) < nthreads) ++lg;
+    if ((1 << lg) != nthreads) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_x, dim3((unsigned)((hs.n_in + 255) / 256)), dim3(256), 0, st, hs, d_groups, lg,
+                       taps, xpart, gx);
     return hipGetLastError();
 }
 
@@ -525,10 +521,10 @@ __global__ __launch_bounds__(NT, 4) void k_adj_track2(DScene S, const DImage* __
                 pair_sums<NG>(tq, LP, fr.kq, fr.kp, split_at(xw, half, p0), ps);
                 const float f0 = fr.q0 - (float)fr.kq, f1 = fr.q1 - (float)fr.kq;
                 const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;
-                const float s0 = fmaf(0.5f * h0 * (h0 - 1.0f), ps.Cm0,
-                                      fmaf(0.5f * f0 * (f0 - 1.0f), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
-                const float s1 = fmaf(0.5f * h1 * (h1 - 1.0f), ps.Cm1,
-                                      fmaf(0.5f * f1 * (f1 - 1.0f), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
+                const float s0 =
+                    fmaf(qweight(h0), ps.Cm0, fmaf(qweight(f0), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
+                const float s1 =
+                    fmaf(qweight(h1), ps.Cm1, fmaf(qweight(f1), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
                 const float sd0 = Lf * (fmaf(f0 - 0.5f, ps.C0, ps.B0) - fmaf(h0 - 0.5f, ps.Cm0, ps.Bm0));
                 const float sd1 = Lf * (fmaf(f1 - 0.5f, ps.C1, ps.B1) - fmaf(h1 - 0.5f, ps.Cm1, ps.Bm1));
                 const float iD0 = __builtin_amdgcn_rcpf((float)K0s + d0);
@@ -622,6 +618,9 @@ __global__ __launch_bounds__(kSegAdjThreads) void k_seg_adj(DScene S, const DIma
     const int n0 = k0 * R;
     const int nv = min(nseg * R, (int)S.n_out - n0);       // outputs of this run
     const float* Db = dbar + ((int64_t)mic * S.n_img + lo) * S.n_out + n0;
+    // i / R as umulhi(i, ceil(2^32 / R)) for R >= 2 (the constant fits 32 bits there):
+    // exact for i < 2^32 / R (i < kSegAdjStage here); R = 1 is i itself
+    const uint32_t rmag = R > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)R - 1) / (uint64_t)R) : 0u;
     // eight independent loads in flight per thread
     for (int i0 = threadIdx.x; i0 < nseg * R; i0 += 8 * kSegAdjThreads) {
         float t[8];
@@ -634,8 +633,8 @@ __global__ __launch_bounds__(kSegAdjThreads) void k_seg_adj(DScene S, const DIma
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * kSegAdjThreads;
             if (i < nseg * R) {
-                const int kk = i / R, v = i - kk * R;
-                st[kk * (R + 1) + v] = t[u];
+                const int kk = R > 1 ? (int)__umulhi((uint32_t)i, rmag) : i;     // segment of i
+                st[i + kk] = t[u];                                    // row kk, column i - kk R
             }
         }
     }

@@ -680,7 +680,7 @@ __global__ __launch_bounds__(256) void k_farrow_corr(DScene S, int T, const floa
 // dr/ds by Horner's rule for value and derivative.  Image descriptors come from
 // LDS (staged per chunk) and track data is fetched one image ahead, as in the
 // forward's one-output tile; the per-wave gain sums reduce by DPP.
-template <int NT>
+template <int NT, bool HI>
 __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage* __restrict__ imgs,
                                                           const DGroup* __restrict__ groups, int T,
                                                           const Seg* __restrict__ seg,
@@ -753,9 +753,11 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage*
             const float s = 2.0f * (dl - fl) - 1.0f;
             const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
             const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
-            float r = cf[kFarrowStride - 1], dr = 0.0f;
+            // orders up to 9 leave the last two coefficients zero
+            constexpr int KT = HI ? kFarrowStride : 10;
+            float r = cf[KT - 1], dr = 0.0f;
 #pragma unroll
-            for (int k = kFarrowStride - 2; k >= 0; --k) {
+            for (int k = KT - 2; k >= 0; --k) {
                 dr = fmaf(dr, s, r);
                 r = fmaf(r, s, cf[k]);
             }
@@ -793,10 +795,10 @@ __global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage*
 }
 
 template <int NT>
-static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, const DImage* d_imgs, const DGroup* d_groups,
-                                      const Seg* seg, const int32_t* segK, const float* d_coef, const float* v,
-                                      const float* gy, float ghat, float* upart, float* u, float* gx, float* dbar,
-                                      float* gpart, int32_t* d_status, hipStream_t st)
+static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, int order, const DImage* d_imgs,
+                                      const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
+                                      const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
+                                      float* dbar, float* gpart, int32_t* d_status, hipStream_t st)
 {
     if (gx) {
         const int64_t npos = hs.n_in + taps;
@@ -817,7 +819,7 @@ static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, const DImage* 
     }
     if (dbar) {
         const size_t lds = farrow_lds_bytes(hs.window);
-        auto kt = k_farrow_adj_track<NT>;
+        auto kt = order > 9 ? k_farrow_adj_track<NT, true> : k_farrow_adj_track<NT, false>;
         hipError_t e = hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kt, dim3((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics), dim3(NT), lds, st,
@@ -827,17 +829,17 @@ static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, const DImage* 
     return hipSuccess;
 }
 
-hipError_t launch_farrow_adjoint(int nthreads, int taps, const DScene& hs, const DImage* d_imgs,
+hipError_t launch_farrow_adjoint(int nthreads, int taps, int order, const DScene& hs, const DImage* d_imgs,
                                  const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
                                  const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
                                  float* dbar, float* gpart, int32_t* d_status, hipStream_t st)
 {
     if (nthreads == 1024)
-        return launch_farrow_adj_t<1024>(hs, taps, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u, gx, dbar,
-                                         gpart, d_status, st);
+        return launch_farrow_adj_t<1024>(hs, taps, order, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u,
+                                         gx, dbar, gpart, d_status, st);
     if (nthreads == 512)
-        return launch_farrow_adj_t<512>(hs, taps, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u, gx, dbar,
-                                        gpart, d_status, st);
+        return launch_farrow_adj_t<512>(hs, taps, order, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u,
+                                        gx, dbar, gpart, d_status, st);
     return hipErrorInvalidValue;
 }
 

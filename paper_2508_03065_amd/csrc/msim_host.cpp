@@ -1114,7 +1114,7 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
         if (farrow) {
             {
                 LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_farrow_adjoint(P->threads, T, d, P->d_images, P->d_groups, fw.seg, fw.segK, P->d_fcoef,
+                HIP_OK(launch_farrow_adjoint(P->threads, T, P->par.farrow_order, d, P->d_images, P->d_groups, fw.seg, fw.segK, P->d_fcoef,
                                              v, gy, ghat, aw.xpart, aw.u, gx, (gbeta || want_src) ? aw.dbar : nullptr,
                                              aw.gpart, P->d_status, stream));
             }

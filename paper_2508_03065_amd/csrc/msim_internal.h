@@ -198,7 +198,7 @@ hipError_t launch_farrow_persistent(int nthreads, int rb, int n_wg, int window, 
                                     const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
                                     const int32_t* segK, const float* v, float* part, int32_t* d_status,
                                     hipStream_t st);
-hipError_t launch_farrow_adjoint(int nthreads, int taps, const DScene& hs, const DImage* d_imgs,
+hipError_t launch_farrow_adjoint(int nthreads, int taps, int order, const DScene& hs, const DImage* d_imgs,
                                  const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
                                  const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
                                  float* dbar, float* gpart, int32_t* d_status, hipStream_t st);
