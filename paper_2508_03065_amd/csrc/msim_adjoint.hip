@@ -284,16 +284,53 @@ __global__ __launch_bounds__(256) void k_reduce_x(DScene S, const DGroup* __rest
     const int NT = 1 << lg_nt;
     const int nt_last = (int)S.n_tiles - 1;
     float acc = 0.0f;
-    for (int mic = 0; mic < S.n_mics; ++mic)
-        for (int g = 0; g < S.n_grp; ++g) {
-            const DGroup G = groups[S.grp_begin + g];
-            const int cg = G.dmax + T / 2 + 4;
-            const int Wg = NT + (G.dmax - G.dmin) + T + 8;
-            const int t_lo = max((m + cg - Wg + NT) >> lg_nt, 0);
-            const int t_hi = min((m + cg) >> lg_nt, nt_last);
-            const float* xp = xpart + ((int64_t)mic * S.n_grp + g) * S.n_tiles * S.window;
-            for (int t = t_lo; t <= t_hi; ++t) acc += xp[(int64_t)t * S.window + (m - (t * NT - cg))];
+    // the windows of group g that cover m: tiles t_lo .. t_hi
+    auto span = [&](int g, int& t_lo, int& t_hi, int& cg) {
+        const DGroup G = groups[S.grp_begin + g];
+        cg = G.dmax + T / 2 + 4;
+        const int Wg = NT + (G.dmax - G.dmin) + T + 8;
+        t_lo = max((m + cg - Wg + NT) >> lg_nt, 0);
+        t_hi = min((m + cg) >> lg_nt, nt_last);
+    };
+    for (int mic = 0; mic < S.n_mics; ++mic) {
+        const float* xm = xpart + (int64_t)mic * S.n_grp * S.n_tiles * S.window;
+        auto at = [&](int g, int t, int cg) {
+            return xm[((int64_t)g * S.n_tiles + t) * S.window + (m - (t * NT - cg))];
+        };
+        int g = 0;
+        // eight groups at a time with their (at most two) windows' loads issued
+        // together, then added in the plain loop's order (masked loads add zero)
+        for (; g + 8 <= S.n_grp; g += 8) {
+            float a0[8], a1[8];
+            bool wide = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                int t_lo, t_hi, cg;
+                span(g + u, t_lo, t_hi, cg);
+                a0[u] = t_lo <= t_hi ? at(g + u, t_lo, cg) : 0.0f;
+                a1[u] = t_lo + 1 <= t_hi ? at(g + u, t_lo + 1, cg) : 0.0f;
+                wide |= t_hi - t_lo >= 2;
+            }
+            if (!wide) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    acc += a0[u];
+                    acc += a1[u];
+                }
+                continue;
+            }
+            for (int u = 0; u < 8; ++u) {
+                int t_lo, t_hi, cg;
+                span(g + u, t_lo, t_hi, cg);
+                for (int t = t_lo; t <= t_hi; ++t) acc += at(g + u, t, cg);
+            }
         }
+        for (; g < S.n_grp; ++g) {
+            int t_lo, t_hi, cg;
+            span(g, t_lo, t_hi, cg);
+            for (int t = t_lo; t <= t_hi; ++t) acc += at(g, t, cg);
+        }
+    }
     gx[S.x_off + m] = acc;
 }
 
