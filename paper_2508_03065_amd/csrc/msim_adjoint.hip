@@ -869,17 +869,30 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const DScene* __
 #pragma unroll
         for (int j = 0; j < NK; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
         const int64_t total = (S.seg_per_mic + 3 * (int64_t)S.n_img) * S.n_mics;
-        for (int64_t i = (int64_t)b * kRedThreads + t; i < total; i += stride) {
-            const int a = pga[i];
-            if (a < 0) continue;
-            const double4 v = pgc[i];
-            const double wa = 1.0 - v.w, wb = v.w;
+        // four items' loads go out together; the items are added in the plain
+        // grid-stride order
+        for (int64_t i0 = (int64_t)b * kRedThreads + t; i0 < total; i0 += 4 * stride) {
+            int aa[4];
+            double4 vv[4];
 #pragma unroll
-            for (int j = 0; j < NK; ++j) {
-                const double f = (j == a) ? wa : (j == a + 1) ? wb : 0.0;
-                acc[j][0] += f * v.x;
-                acc[j][1] += f * v.y;
-                acc[j][2] += f * v.z;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = i0 + u * stride;
+                aa[u] = i < total ? pga[i] : -1;
+                vv[u] = i < total ? pgc[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = aa[u];
+                if (a < 0) continue;
+                const double4 v = vv[u];
+                const double wa = 1.0 - v.w, wb = v.w;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const double f = (j == a) ? wa : (j == a + 1) ? wb : 0.0;
+                    acc[j][0] += f * v.x;
+                    acc[j][1] += f * v.y;
+                    acc[j][2] += f * v.z;
+                }
             }
         }
 #pragma unroll

@@ -42,6 +42,23 @@ __device__ __forceinline__ float h16_hi(unsigned v)
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
 }
 
+// p[0] + p[stride] + ... + p[(n - 1) stride], added in that order.  The loads go out
+// B at a time so their latencies overlap; slots past n add an exact zero, so the
+// result is the plain loop's (up to the sign of a zero total).
+template <int B>
+__device__ __forceinline__ float strided_sum(const float* __restrict__ p, int n, int64_t stride)
+{
+    float s = 0.0f;
+    for (int g = 0; g < n; g += B) {
+        float t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = g + u < n ? p[(int64_t)(g + u) * stride] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < B; ++u) s += t[u];
+    }
+    return s;
+}
+
 // Sum over the 64 lanes of a wave by DPP (no LDS traffic): pairs and quads by
 // quad permutes, rows of 16 by mirrors, then rows combined by row broadcasts;
 // lane 63 ends with the total, which is returned to every lane.

@@ -622,10 +622,7 @@ __global__ __launch_bounds__(256) void k_farrow_u_reduce(DScene S, int T, const 
     const int64_t npos = S.n_in + T;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npos * kFarrowStride) return;
-    const int64_t rows = (int64_t)S.n_mics * S.n_grp;
-    float acc = 0.0f;
-    for (int64_t r = 0; r < rows; ++r) acc += upart[r * npos * kFarrowStride + i];
-    u[i] = acc;
+    u[i] = strided_sum<16>(upart + i, S.n_mics * S.n_grp, npos * kFarrowStride);
 }
 
 // dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j], taps j = -T/2+1 .. T/2.

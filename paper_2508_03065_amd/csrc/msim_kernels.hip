@@ -607,24 +607,6 @@ hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int
 
 // ------------------------------------------------------------------ reduction
 
-// p[0] + p[stride] + ... + p[(n - 1) stride], added in that order; the loads go out
-// sixteen at a time so their latencies overlap (the order of the adds, and so the
-// result, is that of the plain loop).
-__device__ __forceinline__ float sum_groups(const float* __restrict__ p, int n, int64_t stride)
-{
-    float s = 0.0f;
-    int g = 0;
-    for (; g + 16 <= n; g += 16) {
-        float t[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) t[u] = p[(int64_t)(g + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) s += t[u];
-    }
-    for (; g < n; ++g) s += p[(int64_t)g * stride];
-    return s;
-}
-
 __global__ __launch_bounds__(256) void k_reduce_groups(int64_t n_out, int n_grp, int n_mics,
                                                        const float* __restrict__ part, float* __restrict__ y)
 {
@@ -632,7 +614,7 @@ __global__ __launch_bounds__(256) void k_reduce_groups(int64_t n_out, int n_grp,
     if (i >= n_out * n_mics) return;
     const int mic = (int)(i / n_out);
     const int64_t n = i - (int64_t)mic * n_out;
-    y[i] = sum_groups(part + (int64_t)mic * n_grp * n_out + n, n_grp, n_out);
+    y[i] = strided_sum<16>(part + (int64_t)mic * n_grp * n_out + n, n_grp, n_out);
 }
 
 hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st)
@@ -655,7 +637,7 @@ __global__ __launch_bounds__(256) void k_reduce_all(const DScene* __restrict__ s
     const int64_t j = i - y_prefix[s];
     const int mic = (int)(j / S.n_out);
     const int64_t n = j - (int64_t)mic * S.n_out;
-    y[i] = sum_groups(part + S.part_base + (int64_t)mic * S.n_grp * S.n_out + n, S.n_grp, S.n_out);
+    y[i] = strided_sum<16>(part + S.part_base + (int64_t)mic * S.n_grp * S.n_out + n, S.n_grp, S.n_out);
 }
 
 hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
