@@ -88,7 +88,7 @@ __host__ __device__ constexpr int track_block_segs(int R) { return R == 1 ? kTra
 // Segments one block of the Catmull-Rom transpose sums: its outputs (segments x R)
 // are staged in LDS, at most kSegAdjStage of them.
 constexpr int kSegAdjThreads = 256;
-constexpr int kSegAdjStage = 8192;
+constexpr int kSegAdjStage = 4096;
 static_assert(kSegAdjStage >= 4096, "a segment of the largest decimation (4096) must fit the stage");
 __host__ __device__ constexpr int seg_adj_block_segs(int R)
 {
