@@ -719,7 +719,7 @@ __global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ sce
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per_mic = S.seg_per_mic + 3 * (int64_t)S.n_img;
     if (gid >= per_mic * S.n_mics) return;
-    const int mic = (int)(gid / per_mic);
+    const int mic = S.n_mics == 1 ? 0 : (int)(gid / per_mic);
     const int64_t idx = gid - (int64_t)mic * per_mic;
     const DImage* I = imgs + S.img_begin;
     const int ii = owner(I, S.n_img, idx, 3);
@@ -741,8 +741,8 @@ __global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ sce
         const double tk = (double)(k * im.R) / fs;
         const double tau = grid[gid] / fs;
         const double te = model == 0 ? tk - tau : tk;
-        double q[3], r[3], v[3];
-        traj_pos(S.src, knots, te, q);
+        double q[3], r[3], v[3], lam;
+        pwl_eval(S.src, knots, te, q, v, &a, &lam);        // a PWL path (kind 0)
         mic_pos(S, knots, mics, mic, tk, r);
         double e[3], d2 = 0.0;
         for (int ax = 0; ax < 3; ++ax) {
@@ -751,7 +751,6 @@ __global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ sce
         }
         const double id = 1.0 / sqrt(d2);
         double denom = c;
-        traj_vel(S.src, knots, te, v);
         double sgn[3];
         for (int ax = 0; ax < 3; ++ax) sgn[ax] = (im.m[ax] & 1) ? -1.0 : 1.0;
         if (model == 0)
@@ -760,8 +759,6 @@ __global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ sce
         out.x = sc * sgn[0] * e[0];
         out.y = sc * sgn[1] * e[1];
         out.z = sc * sgn[2] * e[2];
-        double lam;
-        pwl_locate(S.src, knots, te, &a, &lam);
         out.w = lam;
     }
     pgc[gid] = out;

@@ -308,47 +308,36 @@ __device__ inline int owner(const DImage* __restrict__ I, int n_img, int64_t idx
     return lo;
 }
 
-// PWL segment of time t: knot a and weight lam of knot a+1 (lam = 0 when t is
-// outside the knot range or the path is static; then only knot a moves it).
-__device__ inline void pwl_locate(const DTraj& tr, const double* __restrict__ knots, double t, int* a_out,
-                                  double* lam_out)
-{
-    const double* T = knots + tr.knot_off;
-    const int n = tr.n_points;
-    int a = 0;
-    double lam = 0.0;
-    if (n == 1 || t <= T[0]) {
-        a = 0;
-    } else if (t >= T[n - 1]) {
-        a = n - 1;
-    } else {
-        a = pwl_find(T, n, t);
-        lam = (t - T[a]) / (T[a + 1] - T[a]);
-    }
-    *a_out = a;
-    *lam_out = lam;
-}
 
-// Velocity of a trajectory at time t (zero outside a PWL path's knot range).
-__device__ inline void traj_vel(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
+// Position (traj_pos's arithmetic), velocity (zero outside the knot range) and
+// PWL segment of a path at t by one search: knot a and the weight lam of knot a+1
+// (lam = 0 outside the knot range or for a static path; then only knot a moves it).
+__device__ inline void pwl_eval(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
+                                double v[3], int* a_out, double* lam_out)
 {
-    if (tr.kind == 1) {
-        double s, c;
-        sincos(tr.omega * t + tr.phase0, &s, &c);
-        const double v = tr.radius * tr.omega;
-        out[0] = -v * s;
-        out[1] = v * c;
-        out[2] = 0.0;
-        return;
-    }
     const double* T = knots + tr.knot_off;
     const double* P = knots + tr.pos_off;
     const int n = tr.n_points;
-    out[0] = out[1] = out[2] = 0.0;
-    if (n == 1 || t <= T[0] || t >= T[n - 1]) return;
+    if (n == 1 || t <= T[0] || t >= T[n - 1]) {
+        const int a = (n == 1 || t <= T[0]) ? 0 : n - 1;
+        for (int k = 0; k < 3; ++k) {
+            p[k] = P[3 * a + k];
+            v[k] = 0.0;
+        }
+        *a_out = a;
+        *lam_out = 0.0;
+        return;
+    }
     const int a = pwl_find(T, n, t);
+    const double lam = (t - T[a]) / (T[a + 1] - T[a]);
     const double idt = 1.0 / (T[a + 1] - T[a]);
-    for (int k = 0; k < 3; ++k) out[k] = (P[3 * (a + 1) + k] - P[3 * a + k]) * idt;
+    for (int k = 0; k < 3; ++k) {
+        const double dp = P[3 * (a + 1) + k] - P[3 * a + k];
+        p[k] = P[3 * a + k] + lam * dp;
+        v[k] = dp * idt;
+    }
+    *a_out = a;
+    *lam_out = lam;
 }
 
 __device__ inline void mic_pos(const DScene& S, const double* __restrict__ knots, const double* __restrict__ mics,
