@@ -722,7 +722,19 @@ __global__ __launch_bounds__(256) void k_grid_adj(const DScene* __restrict__ sce
     const int mic = S.n_mics == 1 ? 0 : (int)(gid / per_mic);
     const int64_t idx = gid - (int64_t)mic * per_mic;
     const DImage* I = imgs + S.img_begin;
-    const int ii = owner(I, S.n_img, idx, 3);
+    // the lanes of a wave hold consecutive grid points: when they share one mic, one
+    // search for the first active lane's point (wave-uniform), then each lane steps
+    // over the few images that end before its own point
+    int ii;
+    const int mic0 = __builtin_amdgcn_readfirstlane(mic);
+    if (__all(mic == mic0)) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)idx);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)idx >> 32));
+        ii = owner(I, S.n_img, (int64_t)(((uint64_t)hi << 32) | lo), 3);
+        while (ii + 1 < S.n_img && (int64_t)I[ii + 1].seg_off + 3 * (int64_t)(ii + 1) <= idx) ++ii;
+    } else {
+        ii = owner(I, S.n_img, idx, 3);
+    }
     const DImage im = I[ii];
     const int64_t k = idx - ((int64_t)im.seg_off + 3 * (int64_t)ii) - 1;
     const float4* ds = dseg + (int64_t)mic * S.seg_per_mic + im.seg_off;
