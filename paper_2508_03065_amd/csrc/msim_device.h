@@ -350,4 +350,181 @@ __device__ inline void mic_pos(const DScene& S, const double* __restrict__ knots
     r[2] += off[2];
 }
 
+
+// ------------------------------------------------------- retarded delay
+
+// Distance term of the retarded-delay equation at emission time te: returns
+// |p_i(te) - r| and sets ev = (p_i(te) - r) . S p'(te) and the PWL segment of te.
+__device__ __forceinline__ double image_dist(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                    const double r[3], double te, double* ev, int* seg)
+{
+    double q[3], v[3];
+    *seg = traj_pos_vel_seg(S.src, knots, te, q, v);
+    double d2 = 0.0, e_v = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
+        d2 += e * e;
+        e_v += e * ((m[a] & 1) ? -v[a] : v[a]);
+    }
+    *ev = e_v;
+    return sqrt_nr(d2);
+}
+
+// Retarded delay at reception time t for mic position r: the root of
+// f(tau) = tau - |p_i(t - tau) - r| / c, by Newton's method from `tau`
+// (f' = 1 + u . S p'(t - tau) / c, in [0.9, 1.1] for speeds below c/10).  A step
+// below 1e-9 s ends it; so does one below 1e-5 s whose emission time stayed on
+// the same piece of the path: the error left is then the curvature of
+// |p_i(t - tau) - r| (below 0.02 / s for the validated speeds and distances)
+// times the step squared, under 1e-11 s.
+__device__ __forceinline__ double newton_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                    const double r[3], double t, double c, double tau)
+{
+    for (int it = 0; it < 30; ++it) {
+        double ev;
+        int sg0;
+        const double d = image_dist(S, m, knots, r, t - tau, &ev, &sg0);
+        const double step = (c * tau - d) * d * rcp_nr(c * d + ev);
+        tau -= step;
+        const double as = fabs(step);
+        if (as <= 1e-9) break;
+        if (as <= 1e-5 && traj_seg(S.src, knots, t - tau) == sg0) break;
+    }
+    return tau;
+}
+
+// First guess of the retarded delay: the equation solved with the image moving on
+// its tangent at time t, c tau = d - (u . S p'(t)) tau, which is off by
+// O((v/c)^2) tau.  Instantaneous model: d / c exactly.
+__device__ __forceinline__ double first_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                   const double r[3], double t, double c, int model)
+{
+    double ev;
+    int sg;
+    const double d = image_dist(S, m, knots, r, t, &ev, &sg);
+    return model == 1 ? d / c : d * d * rcp_nr(c * d + ev);
+}
+
+
+// ------------------------------------------------------- persistent kernels
+
+// Work-item loop shared by the persistent kernels: takes items from the ticket
+// counter until the list is exhausted and calls fn(item).  Items write disjoint
+// outputs, so the result does not depend on which workgroup ran which item.
+template <typename F>
+__device__ inline void for_each_item(int32_t* ticket, int n_items, F&& fn)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        fn(it);
+    }
+}
+
+// ------------------------------------------------------- tile-local tracks
+
+// The workgroup's track slot: Seg[slot_segs], int32[slot_segs], double[slot_segs
+// + 3 gmax] (grid delays), each part 256-byte aligned, then kernel-specific
+// scratch at slot_extra_off.  Written and read by one workgroup only, through
+// plain (non-restrict) pointers, between barriers.
+__device__ inline Slot slot_at(char* slots, int64_t slot_bytes, int slot_segs, int wg)
+{
+    char* b = slots + (int64_t)wg * slot_bytes;
+    Slot s;
+    s.seg = (Seg*)b;
+    s.K = (int32_t*)(b + slot_al((int64_t)slot_segs * 16));
+    s.grid = (double*)(b + slot_al((int64_t)slot_segs * 16) + slot_al((int64_t)slot_segs * 4));
+    return s;
+}
+
+// k / R for k >= 0 from a float estimate, corrected once (the estimate is within
+// one of the quotient for k < 2^24).
+__device__ __forceinline__ int div_exact(int k, int R, float invR)
+{
+    int q = (int)(((float)k + 0.5f) * invR);
+    const int r = k - q * R;
+    q += r < 0 ? -1 : (r >= R ? 1 : 0);
+    return q;
+}
+
+// Delay tracks of images [ib, ie) of scene S (I: the scene's images), mic `mic`,
+// over outputs [n_lo, n_hi) (n_hi <= n_out): segment k of image ii, k_lo <= k <= k_hi
+// with k_lo = n_lo / R, k_hi = (n_hi - 1) / R, at slot seg[I[ii].loc + k - k_lo]
+// (Seg and integer base, as in the stored form: the exact delay at the audio rate,
+// else the uniform Catmull-Rom cubic through D_{k-1} .. D_{k+2}, Sec. II-C-3), and
+// the exact grid delays D_g, g = g_lo .. g_hi (k_lo - 1 .. k_hi + 2 when R > 1,
+// else k_lo .. k_hi), at grid[I[ii].loc + 3 (ii - ib) + g - g_lo].  Wave w takes
+// images ib + w, ib + w + waves, ...; its lanes walk runs of consecutive grid
+// points, each solved from the delays before it.  Starts and ends with a barrier.
+template <int NT>
+__device__ void tile_tracks(const DScene& S, int mic, const DImage* __restrict__ I, int ib, int ie, int n_lo,
+                            int n_hi, Slot sl, const double* __restrict__ knots, const double* __restrict__ mics,
+                            double c, double fs, int model)
+{
+    constexpr int WAVES = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double inv_fs = 1.0 / fs;
+    __syncthreads();
+    for (int ii = ib + wave; ii < ie; ii += WAVES) {
+        const DImage im = I[ii];
+        const int R = im.R;
+        const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
+        const int g_lo = R == 1 ? k_lo : k_lo - 1, g_hi = R == 1 ? k_hi : k_hi + 2;
+        const int npts = g_hi - g_lo + 1;
+        const int run = (npts + 63) >> 6;
+        double* gd = sl.grid + im.loc + 3 * (ii - ib);
+        double tp1 = 0.0, tp2 = 0.0;
+        for (int w = 0; w < run; ++w) {
+            const int j = lane * run + w;
+            if (j >= npts) break;
+            const int g = g_lo + j;
+            const double t = (double)g * (double)R * inv_fs;
+            double r[3];
+            mic_pos(S, knots, mics, mic, t, r);
+            double tau;
+            if (model == 1 || w == 0) {
+                tau = first_tau(S, im.m, knots, r, t, c, model);
+                if (model == 0) tau = newton_tau(S, im.m, knots, r, t, c, tau);
+            } else {
+                tau = newton_tau(S, im.m, knots, r, t, c, w >= 2 ? 2.0 * tp1 - tp2 : tp1);
+            }
+            tp2 = tp1;
+            tp1 = tau;
+            gd[j] = fs * tau;
+        }
+    }
+    __syncthreads();
+    for (int ii = ib + wave; ii < ie; ii += WAVES) {
+        const DImage im = I[ii];
+        const int R = im.R;
+        const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
+        const double* gd = sl.grid + im.loc + 3 * (ii - ib);
+        Seg* so = sl.seg + im.loc;
+        int32_t* ko = sl.K + im.loc;
+        const double iR = 1.0 / (double)R;
+        for (int j = lane; j <= k_hi - k_lo; j += 64) {
+            if (R == 1) {
+                const double D = gd[j];
+                const double Kd = floor(D);
+                so[j] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
+                ko[j] = (int32_t)Kd;
+            } else {
+                // grid index of D_{k-1} is (k - 1) - g_lo = j
+                const double D0 = gd[j], D1 = gd[j + 1], D2 = gd[j + 2], D3 = gd[j + 3];
+                const double Kd = floor(D1);
+                const double a1 = 0.5 * (D2 - D0);
+                const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D3);
+                const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D3);
+                so[j] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
+                ko[j] = (int32_t)Kd;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 }  // namespace msim

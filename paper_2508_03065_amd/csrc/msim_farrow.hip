@@ -67,28 +67,14 @@ size_t farrow_lds_bytes(int window)
     return (size_t)kFarrowDescChunk * 16 + (size_t)window * kFarrowStride * sizeof(float);
 }
 
-// One output tile (TO samples) of one delay group for one mic, Farrow form:
-// stages v_k over the group's source-position window in LDS, then each of the
-// TO/RB lanes sums the group's images for RB consecutive outputs.  The RB
-// outputs of a lane share one track segment when the image is decimated (the
-// planner only picks RB > 1 when every decimation is a multiple of RB), so the
-// segment fetch and its index arithmetic are paid once per RB image samples.
-// HI selects Horner over all 12 stored coefficients (orders 10-11) instead of
-// the first 10.  Ends with a barrier.
-template <int TO, int RB, bool HI>
-__device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int tile, int mic, int T,
-                                   const DImage* __restrict__ imgs, float4* vw, const Seg* __restrict__ seg,
-                                   const int32_t* __restrict__ segK, const float* __restrict__ v,
-                                   float* __restrict__ part, int32_t* __restrict__ status)
+// Stages v_0..v_11 of source positions [ws, ws + W) in LDS (zero outside the
+// stored positions [-T/2, n_in + T/2)).
+__device__ inline void stage_v(const DScene& S, const float* __restrict__ v, int T, int ws, int W, float4* vw,
+                               int nthreads)
 {
-    constexpr int NT = TO / RB;
-    const int tid = threadIdx.x;
-    const int n0 = tile * TO;
-    const int ws = n0 - G.dmax - 4;                    // source position of window slot 0
-    const int W = TO + (G.dmax - G.dmin) + 9;
-    const int plo = -T / 2, phi = (int)S.n_in + T / 2;   // positions with stored v
+    const int plo = -T / 2, phi = (int)S.n_in + T / 2;
     const float4* vs = (const float4*)(v + S.v_off);
-    for (int p = tid; p < W; p += NT) {
+    for (int p = threadIdx.x; p < W; p += nthreads) {
         const int P = ws + p;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
         if (P >= plo && P < phi) {
@@ -101,37 +87,87 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
         vw[3 * p + 1] = b;
         vw[3 * p + 2] = c;
     }
+}
+
+// Horner's rule for sum_k v_k s^k over the 10 (12 with HI) stored coefficients.
+template <bool HI>
+__device__ __forceinline__ float farrow_horner(const float4* vp, float s)
+{
+    const float4 a = vp[0], b = vp[1];
+    float r;
+    if constexpr (HI) {
+        const float4 c = vp[2];
+        r = fmaf(c.w, s, c.z);
+        r = fmaf(r, s, c.y);
+        r = fmaf(r, s, c.x);
+        r = fmaf(r, s, b.w);
+    } else {
+        const float2 c = *(const float2*)&vp[2];
+        r = fmaf(c.y, s, c.x);
+        r = fmaf(r, s, b.w);
+    }
+    r = fmaf(r, s, b.z);
+    r = fmaf(r, s, b.y);
+    r = fmaf(r, s, b.x);
+    r = fmaf(r, s, a.w);
+    r = fmaf(r, s, a.z);
+    r = fmaf(r, s, a.y);
+    r = fmaf(r, s, a.x);
+    return r;
+}
+
+// One delay group of an output tile [n0, n0 + TO) of one mic, Farrow form:
+// stages v_k over the group's source-position window in LDS, then each of the
+// TO/RB lanes adds the group's images for RB consecutive outputs to acc.  The RB
+// outputs of a lane share one track segment when the image is decimated (the
+// planner only picks RB > 1 when every decimation is a multiple of RB), so the
+// segment fetch and its index arithmetic are paid once per RB image samples.
+// HI selects Horner over all 12 stored coefficients (orders 10-11) instead of
+// the first 10.  Ends with a barrier.
+template <int TO, int RB, bool HI>
+__device__ inline void farrow_group(const DScene& S, const DGroup& G, int n0, int T, Slot sl,
+                                    const DImage* __restrict__ I, float4* vw, const float* __restrict__ v,
+                                    float (&acc)[RB], int& bad)
+{
+    constexpr int NT = TO / RB;
+    const int tid = threadIdx.x;
+    const int ws = n0 - G.dmax - 4;                    // source position of window slot 0
+    const int W = TO + (G.dmax - G.dmin) + 9;
+    stage_v(S, v, T, ws, W, vw, NT);
     __syncthreads();
 
     const int nf = n0 + RB * tid;                       // first output of this lane
     const int n_out = (int)S.n_out;
     if (nf < n_out) {
-        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const DImage* I = imgs + S.img_begin;
-        const float fn = (float)nf + 0.5f;
-        float acc[RB];
+        // slot indices of the lane's segments, kept for the last decimation seen
+        int cR = 0, cl[RB];
+        float cv = 0.0f;
+        auto fetch = [&](const DImage& im, Seg (&q)[RB], int (&K)[RB], float& vv) {
+            if (im.R != cR) {
+                cR = im.R;
+                if (cR == 1) {
 #pragma unroll
-        for (int j = 0; j < RB; ++j) acc[j] = 0.0f;
-        int bad = 0;
-        // Track data of later images is fetched while the current one is summed;
-        // buffers are used in turn, so no registers are copied between images.
-        auto fetch = [&](const DImage& im, Seg (&q)[RB], int (&K)[RB], int& kseg) {
+                    for (int j = 0; j < RB; ++j) cl[j] = min(nf + j, n_out - 1) - n0;
+                    cv = 0.0f;
+                } else {
+                    const int k = div_exact(nf, cR, im.invR);
+                    cl[0] = k - div_exact(n0, cR, im.invR);
+                    cv = (float)(nf - k * cR);
+                }
+            }
             if (im.R == 1) {
 #pragma unroll
                 for (int j = 0; j < RB; ++j) {
-                    const int k = min(nf + j, im.n_seg - 1);
-                    q[j] = sgm[im.seg_off + k];
-                    K[j] = sgk[im.seg_off + k];
+                    q[j] = sl.seg[im.loc + cl[j]];
+                    K[j] = sl.K[im.loc + cl[j]];
                 }
             } else {
-                const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
-                q[0] = sgm[im.seg_off + k];
-                K[0] = sgk[im.seg_off + k];
-                kseg = k;
+                q[0] = sl.seg[im.loc + cl[0]];
+                K[0] = sl.K[im.loc + cl[0]];
             }
+            vv = cv;
         };
-        auto body = [&](const DImage& im, const Seg (&q)[RB], const int (&Kq)[RB], int kq) {
+        auto body = [&](const DImage& im, const Seg (&q)[RB], const int (&Kq)[RB], float v0) {
             float d[RB];
             int Ks[RB];
             if (im.R == 1) {
@@ -142,7 +178,6 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
                 }
             } else {
                 const Seg sg = q[0];
-                const float v0 = (float)(nf - __mul24(kq, im.R));
 #pragma unroll
                 for (int j = 0; j < RB; ++j) {
                     const float vv = v0 + (float)j;
@@ -159,35 +194,14 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
                     bad = 1;
                     continue;
                 }
-                const float s = 2.0f * (d[j] - fl) - 1.0f;
-                const float4* vp = vw + __mul24(p, 3);
-                const float4 a = vp[0], b = vp[1];
-                float r;
-                if constexpr (HI) {
-                    const float4 c = vp[2];
-                    r = fmaf(c.w, s, c.z);
-                    r = fmaf(r, s, c.y);
-                    r = fmaf(r, s, c.x);
-                    r = fmaf(r, s, b.w);
-                } else {
-                    const float2 c = *(const float2*)&vp[2];
-                    r = fmaf(c.y, s, c.x);
-                    r = fmaf(r, s, b.w);
-                }
-                r = fmaf(r, s, b.z);
-                r = fmaf(r, s, b.y);
-                r = fmaf(r, s, b.x);
-                r = fmaf(r, s, a.w);
-                r = fmaf(r, s, a.z);
-                r = fmaf(r, s, a.y);
-                r = fmaf(r, s, a.x);
+                const float r = farrow_horner<HI>(vw + __mul24(p, 3), 2.0f * (d[j] - fl) - 1.0f);
                 acc[j] = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)Ks[j] + d[j]), r, acc[j]);
             }
         };
         // three buffers in turn: image ii is summed while ii+1 and ii+2 are in flight
         Seg q0[RB] = {}, q1[RB] = {}, q2[RB] = {};
         int K0[RB] = {}, K1[RB] = {}, K2[RB] = {};
-        int k0 = 0, k1 = 0, k2 = 0;
+        float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
         const int e = G.img_end;
         DImage i0 = I[G.img_begin], i1 = i0, i2 = i0;
         fetch(i0, q0, K0, k0);
@@ -213,71 +227,45 @@ __device__ inline void farrow_tile(const DScene& S, const DGroup& G, int g, int 
         }
         if (ii < e) body(i0, q0, K0, k0);
         if (ii + 1 < e) body(i1, q1, K1, k1);
-        if (bad) atomicOr(status, kStatusWindow);
-        float* out = part + S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-            if (nf + j < n_out) out[nf + j] = acc[j];
     }
     __syncthreads();
 }
 
 // The same with one output per lane, branch-free per image.  A full-rate track
 // segment carries zero cubic terms, so the decimated formula gives its delay
-// too, and the lane's segment index depends only on the decimation R, so it is
+// too, and the lane's slot index depends only on the decimation R, so it is
 // kept for the last R seen (images of a group mostly share a tier).  The group's
-// image descriptors (track offset, R, gain factor, segment count) are staged in
-// LDS a chunk at a time: read there, they keep scalar memory loads out of the
-// image loop (a scalar load's wait also drains every LDS read in flight).
-// dsc: kFarrowDescChunk int4 in LDS; vw: the window after it.
+// image descriptors (slot offset of the lane's segment base, R, gain factor) are
+// staged in LDS a chunk at a time: read there, they keep scalar memory loads out
+// of the image loop (a scalar load's wait also drains every LDS read in flight).
+// dsc: kFarrowDescChunk int4 in LDS; vw: the window after it.  Ends with a barrier.
 template <int TO, bool HI>
-__device__ inline void farrow_tile1(const DScene& S, const DGroup& G, int g, int tile, int mic, int T,
-                                    const DImage* __restrict__ imgs, int4* dsc, float4* vw,
-                                    const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                    const float* __restrict__ v, float* __restrict__ part,
-                                    int32_t* __restrict__ status)
+__device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, int T, Slot sl,
+                                     const DImage* __restrict__ I, int4* dsc, float4* vw,
+                                     const float* __restrict__ v, float& acc, int& bad)
 {
     const int tid = threadIdx.x;
-    const int n0 = tile * TO;
     const int ws = n0 - G.dmax - 4;                    // source position of window slot 0
     const int W = TO + (G.dmax - G.dmin) + 9;
-    const int plo = -T / 2, phi = (int)S.n_in + T / 2;   // positions with stored v
-    const float4* vs = (const float4*)(v + S.v_off);
-    for (int p = tid; p < W; p += TO) {
-        const int P = ws + p;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
-        if (P >= plo && P < phi) {
-            const float4* q = vs + (int64_t)(P + T / 2) * 3;
-            a = q[0];
-            b = q[1];
-            c = q[2];
-        }
-        vw[3 * p] = a;
-        vw[3 * p + 1] = b;
-        vw[3 * p + 2] = c;
-    }
+    stage_v(S, v, T, ws, W, vw, TO);
 
     const int n = n0 + tid;
     const bool active = n < (int)S.n_out;
-    const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
-    const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
-    const DImage* I = imgs + S.img_begin;
-    float acc = 0.0f;
-    int bad = 0;
-    int cR = 0, ck = 0;
+    int cR = 0, cl = 0;
     float cv = 0.0f;
-    // descriptor j of the chunk: seg_off, R, gfac, n_seg
+    // descriptor j of the chunk: slot offset of segment k_lo, R, gfac, k_lo
     auto fetch = [&](int j, Seg& q, int& K, float& vv, float& gf) {
         const int4 d = dsc[j];
         const int R = __builtin_amdgcn_readfirstlane(d.y);
         if (R != cR) {
             cR = R;
-            ck = min(n / R, d.w - 1);
-            cv = (float)(n - ck * R);
+            const int k = n / R;
+            cl = k - d.w;
+            cv = (float)(n - k * R);
         }
         const int off = __builtin_amdgcn_readfirstlane(d.x);
-        q = sgm[off + ck];
-        K = sgk[off + ck];
+        q = sl.seg[off + cl];
+        K = sl.K[off + cl];
         vv = cv;
         gf = __int_as_float(d.z);
     };
@@ -291,28 +279,7 @@ __device__ inline void farrow_tile1(const DScene& S, const DGroup& G, int g, int
         const bool out = (unsigned)p >= (unsigned)W;
         bad |= out;
         p = out ? 0 : p;
-        const float s = 2.0f * (dl - fl) - 1.0f;
-        const float4* vp = vw + __mul24(p, 3);
-        const float4 a = vp[0], b = vp[1];
-        float r;
-        if constexpr (HI) {
-            const float4 c = vp[2];
-            r = fmaf(c.w, s, c.z);
-            r = fmaf(r, s, c.y);
-            r = fmaf(r, s, c.x);
-            r = fmaf(r, s, b.w);
-        } else {
-            const float2 c = *(const float2*)&vp[2];
-            r = fmaf(c.y, s, c.x);
-            r = fmaf(r, s, b.w);
-        }
-        r = fmaf(r, s, b.z);
-        r = fmaf(r, s, b.y);
-        r = fmaf(r, s, b.x);
-        r = fmaf(r, s, a.w);
-        r = fmaf(r, s, a.z);
-        r = fmaf(r, s, a.y);
-        r = fmaf(r, s, a.x);
+        const float r = farrow_horner<HI>(vw + __mul24(p, 3), 2.0f * (dl - fl) - 1.0f);
         acc = fmaf(out ? 0.0f : gf * __builtin_amdgcn_rcpf((float)Ks + dl), r, acc);
     };
     for (int c0 = G.img_begin; c0 < G.img_end; c0 += kFarrowDescChunk) {
@@ -320,7 +287,8 @@ __device__ inline void farrow_tile1(const DScene& S, const DGroup& G, int g, int
         __syncthreads();                 // window staged; the previous chunk's descriptors read
         for (int i = tid; i < nc; i += TO) {
             const DImage& im = I[c0 + i];
-            dsc[i] = make_int4(im.seg_off, im.R, __float_as_int(im.gfac), im.n_seg);
+            const int klo = n0 / im.R;
+            dsc[i] = make_int4(im.loc, im.R, __float_as_int(im.gfac), klo);
         }
         __syncthreads();
         if (!active) continue;
@@ -342,59 +310,53 @@ __device__ inline void farrow_tile1(const DScene& S, const DGroup& G, int g, int
         if (j < nc) body(q0, K0, v0, g0);
         if (j + 1 < nc) body(q1, K1, v1, g1);
     }
-    if (active) {
-        if (bad) atomicOr(status, kStatusWindow);
-        part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
-    }
     __syncthreads();
 }
 
+// Farrow forward, persistent: work items (scene, mic, tile, supergroup) from the
+// ticket counter; per delay group of the supergroup the tracks over the tile go
+// to the workgroup's slot (tile_tracks) and the group's images are added to the
+// lane's accumulators; the item's sum is written once.
 template <int TO, int RB, bool HI>
-__global__ __launch_bounds__(TO / RB) void k_farrow_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                         const DGroup* __restrict__ groups, int T,
-                                                         const Seg* __restrict__ seg,
-                                                         const int32_t* __restrict__ segK,
-                                                         const float* __restrict__ v, float* __restrict__ part,
-                                                         int32_t* __restrict__ status)
+__global__ __launch_bounds__(TO / RB) void k_farrow(const DScene* __restrict__ scenes,
+                                                     const DImage* __restrict__ imgs,
+                                                     const DGroup* __restrict__ groups, int T,
+                                                     const WorkItem* __restrict__ items, int n_items,
+                                                     int32_t* __restrict__ ticket, TrackArgs ta,
+                                                     const float* __restrict__ v, float* __restrict__ part,
+                                                     int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
-    const int g = blockIdx.y;
-    if constexpr (RB == 1)
-        farrow_tile1<TO, HI>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, imgs, (int4*)lds,
-                             lds + kFarrowDescChunk, seg, segK, v, part, status);
-    else
-        farrow_tile<TO, RB, HI>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, T, imgs,
-                                lds + kFarrowDescChunk, seg, segK, v, part, status);
-}
-
-template <int TO, int RB, bool HI>
-__global__ __launch_bounds__(TO / RB) void k_farrow_persistent(const DScene* __restrict__ scenes,
-                                                                const DImage* __restrict__ imgs,
-                                                                const DGroup* __restrict__ groups, int T,
-                                                                const WorkItem* __restrict__ items, int n_items,
-                                                                int32_t* __restrict__ ticket,
-                                                                const Seg* __restrict__ seg,
-                                                                const int32_t* __restrict__ segK,
-                                                                const float* __restrict__ v, float* __restrict__ part,
-                                                                int32_t* __restrict__ status)
-{
-    extern __shared__ float4 lds[];
-    __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= n_items) break;
+    constexpr int NT = TO / RB;
+    const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
+    for_each_item(ticket, n_items, [&](int it) {
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        if constexpr (RB == 1)
-            farrow_tile1<TO, HI>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, imgs, (int4*)lds,
-                                 lds + kFarrowDescChunk, seg, segK, v, part, status);
-        else
-            farrow_tile<TO, RB, HI>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, T, imgs,
-                                    lds + kFarrowDescChunk, seg, segK, v, part, status);
-    }
+        const DImage* I = imgs + S.img_begin;
+        const int n0 = w.tile * TO;
+        const int n_out = (int)S.n_out;
+        const int n_hi = min(n0 + TO, n_out);
+        const int gb = sg_begin(S.n_grp, S.n_sg, w.sg), ge = sg_begin(S.n_grp, S.n_sg, w.sg + 1);
+        float acc[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[j] = 0.0f;
+        int bad = 0;
+        for (int g = gb; g < ge; ++g) {
+            const DGroup G = groups[S.grp_begin + g];
+            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, sl, ta.knots, ta.mics, ta.c, ta.fs,
+                            ta.model);
+            if constexpr (RB == 1)
+                farrow_group1<TO, HI>(S, G, n0, T, sl, I, (int4*)lds, lds + kFarrowDescChunk, v, acc[0], bad);
+            else
+                farrow_group<TO, RB, HI>(S, G, n0, T, sl, I, lds + kFarrowDescChunk, v, acc, bad);
+        }
+        float* out = part + S.part_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_out;
+        const int nf = n0 + RB * (int)threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if (nf + j < n_out) out[nf + j] = acc[j];
+        if (bad) atomicOr(status, kStatusWindow);
+    });
 }
 
 __global__ void k_zero_ticket(int32_t* p)
@@ -403,33 +365,18 @@ __global__ void k_zero_ticket(int32_t* p)
 }
 
 template <int TO, int RB>
-static hipError_t launch_farrow_fwd_t(const DScene& hs, int taps, int hi, const DImage* d_imgs,
-                                      const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v,
-                                      float* part, int32_t* d_status, hipStream_t st)
-{
-    const size_t lds = farrow_lds_bytes(hs.window);
-    auto kern = hi ? k_farrow_fwd<TO, RB, true> : k_farrow_fwd<TO, RB, false>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(TO / RB), lds, st, hs, d_imgs, d_groups, taps, seg, segK, v, part,
-                       d_status);
-    return hipGetLastError();
-}
-
-template <int TO, int RB>
-static hipError_t launch_farrow_pers_t(int n_wg, int window, int taps, int hi, const DScene* d_scenes,
-                                       const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items,
-                                       int n_items, int32_t* ticket, const Seg* seg, const int32_t* segK,
-                                       const float* v, float* part, int32_t* d_status, hipStream_t st)
+static hipError_t launch_farrow_t(int n_wg, int window, int taps, int hi, const DScene* d_scenes,
+                                  const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
+                                  int32_t* ticket, const TrackArgs& ta, const float* v, float* part,
+                                  int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(window);
-    auto kern = hi ? k_farrow_persistent<TO, RB, true> : k_farrow_persistent<TO, RB, false>;
+    auto kern = hi ? k_farrow<TO, RB, true> : k_farrow<TO, RB, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
     hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, d_scenes, d_imgs, d_groups, taps, items,
-                       n_items, ticket, seg, segK, v, part, d_status);
+                       n_items, ticket, ta, v, part, d_status);
     return hipGetLastError();
 }
 
@@ -445,33 +392,16 @@ int farrow_outputs_per_lane(const int32_t* decim, int n_tiers)
     return 1;
 }
 
-hipError_t launch_farrow_fwd(int nthreads, int rb, int taps, int order, const DScene& hs, const DImage* d_imgs,
-                             const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v, float* part,
-                             int32_t* d_status, hipStream_t st)
+hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const DScene* d_scenes,
+                         const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
+                         int32_t* ticket, const TrackArgs& ta, const float* v, float* part, int32_t* d_status,
+                         hipStream_t st)
 {
+    if (n_items == 0) return hipSuccess;
     const int hi = order > 9;
-#define MSIM_CALL(TO, RB) \
-    launch_farrow_fwd_t<TO, RB>(hs, taps, hi, d_imgs, d_groups, seg, segK, v, part, d_status, st)
-    if (nthreads == 1024 && rb == 4) return MSIM_CALL(1024, 4);
-    if (nthreads == 1024 && rb == 2) return MSIM_CALL(1024, 2);
-    if (nthreads == 1024 && rb == 1) return MSIM_CALL(1024, 1);
-    if (nthreads == 512 && rb == 4) return MSIM_CALL(512, 4);
-    if (nthreads == 512 && rb == 2) return MSIM_CALL(512, 2);
-    if (nthreads == 512 && rb == 1) return MSIM_CALL(512, 1);
-#undef MSIM_CALL
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_farrow_persistent(int nthreads, int rb, int n_wg, int window, int taps, int order,
-                                    const DScene* d_scenes, const DImage* d_imgs, const DGroup* d_groups,
-                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
-                                    const int32_t* segK, const float* v, float* part, int32_t* d_status,
-                                    hipStream_t st)
-{
-    const int hi = order > 9;
-#define MSIM_CALL(TO, RB)                                                                                    \
-    launch_farrow_pers_t<TO, RB>(n_wg, window, taps, hi, d_scenes, d_imgs, d_groups, items, n_items, ticket, \
-                                 seg, segK, v, part, d_status, st)
+#define MSIM_CALL(TO, RB)                                                                                      \
+    launch_farrow_t<TO, RB>(n_wg, window, taps, hi, d_scenes, d_imgs, d_groups, items, n_items, ticket, ta, v, \
+                            part, d_status, st)
     if (nthreads == 1024 && rb == 4) return MSIM_CALL(1024, 4);
     if (nthreads == 1024 && rb == 2) return MSIM_CALL(1024, 2);
     if (nthreads == 1024 && rb == 1) return MSIM_CALL(1024, 1);

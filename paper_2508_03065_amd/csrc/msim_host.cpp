@@ -326,16 +326,20 @@ struct msim_plan {
     std::vector<bool> grad_ok;            // the adjoint's LDS fits this scene's windows
     std::vector<std::vector<std::pair<double, double>>> bounds;   // per scene, per sorted image: delay bounds
     int group_cap = 0;                    // images per delay group (0: chosen from the tile count)
-    // batched path
-    std::vector<DScene> scenes_b;         // with workspace bases set
-    std::vector<int64_t> run_prefix, y_prefix;
-    std::vector<WorkItem> items;
-    int64_t b_run_total = 0, b_seg_total = 0, b_part_total = 0;
+    // work items: every scene's (mic, tile, supergroup) in decreasing-cost order
+    // (batched), and per scene (plain: scene s's items at plain_off[s])
+    std::vector<DScene> scenes_b;         // with batched partial-output bases set
+    std::vector<int64_t> y_prefix;
+    std::vector<WorkItem> items, items_plain;
+    std::vector<int> plain_off, plain_cnt;
+    int64_t b_part_total = 0, max_part = 0;   // partial outputs: all scenes / the largest scene
     int b_window = 0, b_wgs = 0;
+    int slot_segs = 0, gmax = 0;          // track slot: segments, and images of the largest group
     DScene* d_scenes_b = nullptr;
-    int64_t* d_run_prefix = nullptr;
     int64_t* d_y_prefix = nullptr;
+    int64_t* d_zero = nullptr;
     WorkItem* d_items = nullptr;
+    WorkItem* d_items_plain = nullptr;
     // graph of the batched forward, valid for one (x, y, workspace) triple
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -733,42 +737,88 @@ msim_status regroup(msim_plan* P)
         d.window = window;
         P->groups.insert(P->groups.end(), gr.begin(), gr.end());
     }
-    // batched layout
-    P->scenes_b = P->scenes;
-    P->run_prefix.assign(P->n_scenes, 0);
-    P->y_prefix.assign(P->n_scenes, 0);
-    int64_t ro = 0, so = 0, po = 0;
-    int wmax = 0;
-    for (int s = 0; s < P->n_scenes; ++s) {
-        DScene& b = P->scenes_b[s];
-        b.grid_base = 0;            // the batched forward keeps no delay grid
-        b.trk_base = so;
-        b.part_base = po;
-        P->run_prefix[s] = ro;
-        P->y_prefix[s] = b.y_off;
-        ro += b.runs_per_mic * b.n_mics;
-        so += b.seg_per_mic * b.n_mics;
-        po += (int64_t)b.n_mics * b.n_grp * b.n_out;
-        wmax = std::max(wmax, b.window);
-    }
-    P->b_run_total = ro;
-    P->b_seg_total = so;
-    P->b_part_total = po;
-    P->b_window = wmax;
-    std::vector<std::pair<double, WorkItem>> it;
+    // Track slots: the images of a group hold slot_segs_of(R, span) segments each
+    // in group order (span: the group's tile plus its delay spread), so a slot of
+    // slot_segs segments holds any group's tracks over any tile.
+    int slot_segs = 1, gmax = 1;
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
         for (int g = 0; g < d.n_grp; ++g) {
             const DGroup& G = P->groups[d.grp_begin + g];
-            const int W = NT + (G.dmax - G.dmin) + T + 8;
+            const int span = group_span(NT, G.dmin, G.dmax);
+            int64_t loc = 0;
+            for (int i = G.img_begin; i < G.img_end; ++i) {
+                DImage& im = P->images[d.img_begin + i];
+                im.loc = (int32_t)loc;
+                loc += slot_segs_of(im.R, span);
+            }
+            if (loc > INT32_MAX / 2) return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
+            slot_segs = std::max(slot_segs, (int)loc);
+            gmax = std::max(gmax, G.img_end - G.img_begin);
+        }
+    }
+    P->slot_segs = slot_segs;
+    P->gmax = gmax;
+    // Supergroups: a work item sums the groups of one supergroup of one (mic, tile)
+    // in registers and writes one partial output row.  Items enough to fill the
+    // persistent grid several times, partial outputs within 2 GiB.
+    int64_t tm = 0, outs = 0;
+    for (const DScene& d : P->scenes) {
+        tm += (int64_t)d.n_tiles * d.n_mics;
+        outs += (int64_t)d.n_mics * d.n_out;
+    }
+    const int64_t want = 8 * 512;
+    int nsg_par = (int)std::max<int64_t>(1, (want + tm - 1) / std::max<int64_t>(1, tm));
+    const int nsg_mem = (int)std::max<int64_t>(1, ((int64_t)1 << 29) / std::max<int64_t>(1, outs));
+    nsg_par = std::min(nsg_par, nsg_mem);
+    P->scenes_b = P->scenes;
+    P->y_prefix.assign(P->n_scenes, 0);
+    int64_t po = 0, pmax = 0;
+    int wmax = 0;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        DScene& d = P->scenes[s];
+        d.n_sg = std::min(d.n_grp, nsg_par);
+        d.part_base = 0;
+        DScene& b = P->scenes_b[s];
+        b.n_sg = d.n_sg;
+        b.part_base = po;
+        P->y_prefix[s] = b.y_off;
+        const int64_t pr = (int64_t)b.n_mics * b.n_sg * b.n_out;
+        po += pr;
+        pmax = std::max(pmax, pr);
+        wmax = std::max(wmax, b.window);
+    }
+    P->b_part_total = po;
+    P->max_part = pmax;
+    P->b_window = wmax;
+    std::vector<std::pair<double, WorkItem>> it;
+    P->plain_off.assign(P->n_scenes, 0);
+    P->plain_cnt.assign(P->n_scenes, 0);
+    P->items_plain.clear();
+    for (int s = 0; s < P->n_scenes; ++s) {
+        const DScene& d = P->scenes[s];
+        std::vector<std::pair<double, WorkItem>> its;
+        for (int sg = 0; sg < d.n_sg; ++sg) {
+            const int gb = sg_begin(d.n_grp, d.n_sg, sg), ge = sg_begin(d.n_grp, d.n_sg, sg + 1);
+            double per_out = 0.0, stage = 0.0;
+            for (int g = gb; g < ge; ++g) {
+                const DGroup& G = P->groups[d.grp_begin + g];
+                per_out += (double)(G.img_end - G.img_begin) * T;
+                stage += 4.0 * (NT + (G.dmax - G.dmin) + T + 8);
+            }
             for (int m = 0; m < d.n_mics; ++m)
                 for (int t = 0; t < d.n_tiles; ++t) {
                     const int64_t len = std::min<int64_t>(NT, d.n_out - (int64_t)t * NT);
-                    const double cost = (double)(G.img_end - G.img_begin) * len * T + 4.0 * W;
-                    it.push_back({cost, WorkItem{s, m, t, g}});
+                    its.push_back({per_out * len + stage, WorkItem{s, m, t, sg}});
                 }
         }
+        std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        P->plain_off[s] = (int)P->items_plain.size();
+        P->plain_cnt[s] = (int)its.size();
+        for (const auto& e : its) P->items_plain.push_back(e.second);
+        it.insert(it.end(), its.begin(), its.end());
     }
+    if (it.size() > (size_t)INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "too many work items");
     std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     P->items.resize(it.size());
     for (size_t i = 0; i < it.size(); ++i) P->items[i] = it[i].second;
@@ -786,28 +836,47 @@ void free_layout(msim_plan* P)
     (void)hipFree(P->d_scenes);
     (void)hipFree(P->d_groups);
     (void)hipFree(P->d_scenes_b);
-    (void)hipFree(P->d_run_prefix);
     (void)hipFree(P->d_y_prefix);
     (void)hipFree(P->d_items);
+    (void)hipFree(P->d_items_plain);
     P->d_scenes = nullptr;
     P->d_groups = nullptr;
     P->d_scenes_b = nullptr;
-    P->d_run_prefix = P->d_y_prefix = nullptr;
-    P->d_items = nullptr;
+    P->d_y_prefix = nullptr;
+    P->d_items = P->d_items_plain = nullptr;
 }
 
-// (Re)uploads everything regroup() decides: scene descriptors, groups, the
-// batched descriptors, prefix arrays and the work list.
+// (Re)uploads everything regroup() decides: scene descriptors, groups, the images
+// (their slot offsets), the batched descriptors, prefix arrays and the work lists.
 msim_status upload_layout(msim_plan* P)
 {
     free_layout(P);
     msim_status st;
     if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_groups, P->groups)) != MSIM_OK ||
         (st = upload(&P->d_scenes_b, P->scenes_b)) != MSIM_OK ||
-        (st = upload(&P->d_run_prefix, P->run_prefix)) != MSIM_OK ||
-        (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK)
+        (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK ||
+        (st = upload(&P->d_items_plain, P->items_plain)) != MSIM_OK)
         return st;
+    if (P->d_images)
+        HIP_OK(hipMemcpy(P->d_images, P->images.data(), P->images.size() * sizeof(DImage), hipMemcpyHostToDevice));
     return MSIM_OK;
+}
+
+// Bytes of one workgroup's track slot for the forward.
+int64_t fwd_slot_bytes(const msim_plan* P) { return slot_extra_off(P->slot_segs, P->gmax); }
+
+TrackArgs track_args(const msim_plan* P, char* slots, int64_t slot_bytes)
+{
+    TrackArgs ta;
+    ta.knots = P->d_knots;
+    ta.mics = P->d_mics;
+    ta.c = P->par.c;
+    ta.fs = P->par.fs;
+    ta.model = P->par.delay_model;
+    ta.slot_segs = P->slot_segs;
+    ta.slots = slots;
+    ta.slot_bytes = slot_bytes;
+    return ta;
 }
 
 // Forward scratch of one scene, carved from the caller's workspace.
@@ -883,6 +952,79 @@ size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, Adj
     }
     if (partial) *partial = (double*)pr;
     return off;
+}
+
+// Forward workspace: the Farrow-filtered sources (Farrow form), one track slot
+// per persistent workgroup, the partial outputs of every scene (batched) or of the
+// largest scene (plain: scenes run one after another), and the ticket counter.
+struct FwdWs2 {
+    float* v;
+    char* slots;
+    float* part;
+    int32_t* ticket;
+};
+
+size_t carve_fwd_ws(const msim_plan* P, bool batched, char* base, FwdWs2* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    char* v = take(farrow_v_bytes(P));
+    char* sl = take((size_t)P->b_wgs * (size_t)fwd_slot_bytes(P));
+    char* pa = take((size_t)(batched ? P->b_part_total : P->max_part) * sizeof(float));
+    char* t = take(sizeof(int32_t));
+    if (w) {
+        w->v = (float*)v;
+        w->slots = sl;
+        w->part = (float*)pa;
+        w->ticket = (int32_t*)t;
+    }
+    return off;
+}
+
+// The forward's launches: the Farrow filter bank (Farrow form), then the
+// persistent synthesis and the supergroup reduction, over every scene at once
+// (batched) or scene by scene (plain).
+msim_status enqueue_forward(msim_plan* P, const float* x, float* y, const FwdWs2& w, bool batched, hipStream_t st)
+{
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    const TrackArgs ta = track_args(P, w.slots, fwd_slot_bytes(P));
+    if (farrow) {
+        LaunchTimer t(P, kKindFilter, st);
+        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps,
+                                  P->d_fcoef, x, w.v, st));
+    }
+    auto run = [&](const DScene* scenes, const WorkItem* items, int n_items, int n_wg) -> msim_status {
+        LaunchTimer t(P, kKindSynth, st);
+        if (farrow)
+            HIP_OK(launch_farrow(P->threads, P->rb, n_wg, P->b_window, P->par.taps, P->par.farrow_order, scenes,
+                                 P->d_images, P->d_groups, items, n_items, w.ticket, ta, w.v, w.part, P->d_status,
+                                 st));
+        else
+            HIP_OK(launch_synth(P->par.taps, P->threads, P->rb, n_wg, P->b_window, scenes, P->d_images,
+                                P->d_groups, P->d_qtable, P->par.table_phases, items, n_items, w.ticket, ta, x,
+                                w.part, P->d_status, st));
+        return MSIM_OK;
+    };
+    msim_status s;
+    if (batched) {
+        if ((s = run(P->d_scenes_b, P->d_items, (int)P->items.size(), P->b_wgs)) != MSIM_OK) return s;
+        LaunchTimer t(P, kKindReduce, st);
+        HIP_OK(launch_reduce_sg(P->d_scenes_b, P->n_scenes, P->d_y_prefix, P->y_total, w.part, y, st));
+        return MSIM_OK;
+    }
+    for (int sc = 0; sc < P->n_scenes; ++sc) {
+        const int cnt = P->plain_cnt[sc];
+        if ((s = run(P->d_scenes, P->d_items_plain + P->plain_off[sc], cnt, std::min(cnt, P->b_wgs))) != MSIM_OK)
+            return s;
+        const DScene& d = P->scenes[sc];
+        LaunchTimer t(P, kKindReduce, st);
+        HIP_OK(launch_reduce_sg(P->d_scenes + sc, 1, P->d_zero, (int64_t)d.n_mics * d.n_out, w.part, y, st));
+    }
+    return MSIM_OK;
 }
 
 }  // namespace
@@ -1000,7 +1142,7 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
         (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
-        (st = upload(&P->d_status, zero)) != MSIM_OK ||
+        (st = upload(&P->d_status, zero)) != MSIM_OK || (st = upload(&P->d_zero, std::vector<int64_t>(1, 0))) != MSIM_OK ||
         (st = upload(&P->d_qtable, qtab4)) != MSIM_OK || (st = upload(&P->d_atable, P->atable)) != MSIM_OK ||
         (st = upload_layout(P)) != MSIM_OK) {
         msim_plan_destroy(P);
@@ -1029,6 +1171,7 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_fcoef);
     (void)hipFree(P->d_vpos_prefix);
     (void)hipFree(P->d_status);
+    (void)hipFree(P->d_zero);
     delete P;
     return MSIM_OK;
 }
@@ -1057,9 +1200,12 @@ msim_status msim_plan_stats(const msim_plan* P, int64_t* n_images, double* forwa
 msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* bytes)
 {
     if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    if (!with_grad) {
+        *bytes = carve_fwd_ws(P, false, nullptr, nullptr);
+        return MSIM_OK;
+    }
     size_t m = 0;
-    for (const DScene& d : P->scenes)
-        m = std::max(m, with_grad ? carve_adj(P, d, nullptr, nullptr, nullptr, nullptr) : fwd_ws_bytes(P, d));
+    for (const DScene& d : P->scenes) m = std::max(m, carve_adj(P, d, nullptr, nullptr, nullptr, nullptr));
     *bytes = m + farrow_v_bytes(P);
     return MSIM_OK;
 }
@@ -1159,46 +1305,15 @@ msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* 
 msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream)
 {
     if (!P || !x || !y) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    size_t need = 0;
-    msim_workspace_size(P, 0, &need);
+    const size_t need = carve_fwd_ws(P, false, nullptr, nullptr);
     if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
         return fail(MSIM_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned", need);
     int dev = -1;
     HIP_OK(hipGetDevice(&dev));
     if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
-    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
-    float* v = (float*)ws;                       // Farrow-filtered sources, all scenes
-    char* scratch = (char*)ws + farrow_v_bytes(P);
-    if (farrow) {
-        LaunchTimer t(P, kKindFilter, stream);
-        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps, P->d_fcoef, x,
-                                  v, stream));
-    }
-    for (int s = 0; s < P->n_scenes; ++s) {
-        const DScene& d = P->scenes[s];
-        FwdWs w;
-        carve_fwd(d, scratch, &w);
-        {
-            LaunchTimer t(P, kKindTracks, stream);
-            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, nullptr, w.seg, w.segK,
-                                 P->par.c, P->par.fs, P->par.delay_model, stream));
-        }
-        {
-            LaunchTimer t(P, kKindSynth, stream);
-            if (farrow)
-                HIP_OK(launch_farrow_fwd(P->threads, P->rb, P->par.taps, P->par.farrow_order, d, P->d_images,
-                                         P->d_groups, w.seg, w.segK, v, w.part, P->d_status, stream));
-            else
-                HIP_OK(launch_synth_fwd(P->par.taps, P->threads, P->rb, d, P->d_images, P->d_groups, P->d_qtable,
-                                        P->par.table_phases, w.seg, w.segK, x, w.part, P->d_status,
-                                        stream));
-        }
-        {
-            LaunchTimer t(P, kKindReduce, stream);
-            HIP_OK(launch_reduce_groups(d, w.part, y, stream));
-        }
-    }
-    return MSIM_OK;
+    FwdWs2 w;
+    carve_fwd_ws(P, false, (char*)ws, &w);
+    return enqueue_forward(P, x, y, w, false, stream);
 }
 
 msim_status msim_profile_begin(msim_plan* P)
@@ -1246,73 +1361,10 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
 
 namespace {
 
-struct BatchWs {
-    float* v;
-    Seg* seg;
-    int32_t* segK;
-    float* part;
-    int32_t* ticket;
-};
-
-size_t carve_batched(const msim_plan* P, char* base, BatchWs* w)
-{
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char* p = base ? base + off : nullptr;
-        off += align_up(bytes);
-        return p;
-    };
-    char* v = take((size_t)farrow_v_bytes(P));
-    char* s = take((size_t)P->b_seg_total * sizeof(Seg));
-    char* k = take((size_t)P->b_seg_total * sizeof(int32_t));
-    char* p = take((size_t)P->b_part_total * sizeof(float));
-    char* t = take(sizeof(int32_t));
-    if (w) {
-        w->v = (float*)v;
-        w->seg = (Seg*)s;
-        w->segK = (int32_t*)k;
-        w->part = (float*)p;
-        w->ticket = (int32_t*)t;
-    }
-    return off;
-}
-
-msim_status enqueue_batched(msim_plan* P, const float* x, float* y, const BatchWs& w, hipStream_t st)
-{
-    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
-    if (farrow) {
-        LaunchTimer t(P, kKindFilter, st);
-        HIP_OK(launch_farrow_conv(P->d_scenes_b, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps,
-                                  P->d_fcoef, x, w.v, st));
-    }
-    {
-        LaunchTimer t(P, kKindTracks, st);
-        HIP_OK(launch_tracks_all(P->d_scenes_b, P->n_scenes, P->d_run_prefix, P->b_run_total, P->d_images,
-                                 P->d_knots, P->d_mics, w.seg, w.segK, P->par.c, P->par.fs, P->par.delay_model, st));
-    }
-    {
-        LaunchTimer t(P, kKindSynth, st);
-        if (farrow)
-            HIP_OK(launch_farrow_persistent(P->threads, P->rb, P->b_wgs, P->b_window, P->par.taps,
-                                            P->par.farrow_order, P->d_scenes_b,
-                                            P->d_images, P->d_groups, P->d_items, (int)P->items.size(), w.ticket,
-                                            w.seg, w.segK, w.v, w.part, P->d_status, st));
-        else
-            HIP_OK(launch_synth_persistent(P->par.taps, P->threads, P->rb, P->b_wgs, P->b_window, P->d_scenes_b,
-                                           P->d_images, P->d_groups, P->d_qtable, P->par.table_phases,
-                                           P->d_items,
-                                           (int)P->items.size(), w.ticket, w.seg, w.segK, x, w.part, P->d_status,
-                                           st));
-    }
-    LaunchTimer t(P, kKindReduce, st);
-    HIP_OK(launch_reduce_all(P->d_scenes_b, P->n_scenes, P->d_y_prefix, P->y_total, w.part, y, st));
-    return MSIM_OK;
-}
-
 msim_status check_batched_call(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes)
 {
     if (!P || !x || !y) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    const size_t need = carve_batched(P, nullptr, nullptr);
+    const size_t need = carve_fwd_ws(P, true, nullptr, nullptr);
     if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
         return fail(MSIM_E_WORKSPACE, "batched workspace needs %zu bytes, 256-byte aligned", need);
     int dev = -1;
@@ -1365,7 +1417,7 @@ extern "C" {
 msim_status msim_batched_workspace_size(const msim_plan* P, size_t* bytes)
 {
     if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    *bytes = carve_batched(P, nullptr, nullptr);
+    *bytes = carve_fwd_ws(P, true, nullptr, nullptr);
     return MSIM_OK;
 }
 
@@ -1374,9 +1426,9 @@ msim_status msim_forward_batched(msim_plan* P, const float* x, float* y, void* w
 {
     msim_status st = check_batched_call(P, x, y, ws, ws_bytes);
     if (st != MSIM_OK) return st;
-    BatchWs w;
-    carve_batched(P, (char*)ws, &w);
-    if (!use_graph) return enqueue_batched(P, x, y, w, stream);
+    FwdWs2 w;
+    carve_fwd_ws(P, true, (char*)ws, &w);
+    if (!use_graph) return enqueue_forward(P, x, y, w, true, stream);
     const void* key[3] = {x, y, ws};
     if (!P->graph_valid || std::memcmp(key, P->graph_key, sizeof key) != 0) {
         if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
@@ -1388,7 +1440,7 @@ msim_status msim_forward_batched(msim_plan* P, const float* x, float* y, void* w
         const bool prof = P->profiling;
         P->profiling = false;
         HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
-        st = enqueue_batched(P, x, y, w, P->cap_stream);
+        st = enqueue_forward(P, x, y, w, true, P->cap_stream);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
         P->profiling = prof;
@@ -1455,7 +1507,7 @@ msim_status msim_autotune_workspace_size(msim_plan* P, size_t* bytes)
         for (int c : kTuneCaps) {
             P->threads = t;
             P->group_cap = c;
-            if (regroup(P) == MSIM_OK) m = std::max(m, carve_batched(P, nullptr, nullptr));
+            if (regroup(P) == MSIM_OK) m = std::max(m, carve_fwd_ws(P, true, nullptr, nullptr));
         }
     P->threads = ot;
     P->group_cap = oc;
@@ -1485,15 +1537,15 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
                     P->threads = t;
                     P->group_cap = c;
                     P->rb = rb;
-                    if (regroup(P) != MSIM_OK || carve_batched(P, nullptr, nullptr) > ws_bytes) continue;
+                    if (regroup(P) != MSIM_OK || carve_fwd_ws(P, true, nullptr, nullptr) > ws_bytes) continue;
                     msim_status st = upload_layout(P);
                     if (st != MSIM_OK) return st;
-                    BatchWs w;
-                    carve_batched(P, (char*)ws, &w);
-                    if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
+                    FwdWs2 w;
+                    carve_fwd_ws(P, true, (char*)ws, &w);
+                    if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
                     HIP_OK(hipEventRecord(e0, stream));
                     for (int r = 0; r < 3; ++r)
-                        if ((st = enqueue_batched(P, x, y, w, stream)) != MSIM_OK) return st;
+                        if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
                     HIP_OK(hipEventRecord(e1, stream));
                     HIP_OK(hipEventSynchronize(e1));
                     float ms = 0.0f;

@@ -35,6 +35,8 @@ struct DScene {
     int32_t n_img;
     int32_t grp_begin;    // this scene's delay groups
     int32_t n_grp;
+    int32_t n_sg;         // supergroups per mic: contiguous runs of delay groups, one work item each
+    int32_t pad_sg;
     int64_t seg_per_mic;  // track segments of one mic (sum over images)
     int64_t runs_per_mic; // track-kernel blocks of one mic
     int64_t sadj_per_mic; // Catmull-Rom-transpose blocks of one mic
@@ -49,12 +51,22 @@ struct DScene {
     int64_t part_base;
 };
 
-// One unit of the batched forward: an output tile of one delay group of one mic.
+// One work item of the persistent kernels: an output tile of one mic, summed over
+// the delay groups of one supergroup (groups [n_grp sg / n_sg, n_grp (sg+1) / n_sg)).
 struct WorkItem {
     int32_t scene;
     int32_t mic;
     int32_t tile;
-    int32_t group;
+    int32_t sg;
+};
+
+__host__ __device__ inline int sg_begin(int n_grp, int n_sg, int sg) { return (int)((int64_t)n_grp * sg / n_sg); }
+
+// Delay of an image over one grid segment [kR, (k+1)R):
+//   D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)),  v = 0 .. R-1,
+// the uniform Catmull-Rom cubic through the exact delays at (k-1)R .. (k+2)R.
+struct Seg {
+    float a0, b1, b2, b3;
 };
 
 // One image source.  Position of image m of point q, per axis a:
@@ -71,7 +83,37 @@ struct DImage {
     int8_t pad[2];
     int32_t run_off;      // first track-kernel block within one mic
     int32_t sadj_off;     // first Catmull-Rom-transpose block within one mic
+    int32_t loc;          // first segment of this image in a workgroup's track slot: the
+                          // images of a delay group hold slot_segs_of(R, span) segments each,
+                          // in group order (grid delays: 3 more per image)
+    int32_t pad2;
 };
+
+// Segments of decimation R that outputs [n, n + span) touch, for any n: at most this many.
+__host__ __device__ constexpr int slot_segs_of(int R, int span) { return (span - 1) / R + 2; }
+// Outputs a delay group's track slot covers: an output tile plus the group's delay
+// spread and margin (the Farrow dL/dx gather reads the outputs that reach a tile
+// of source positions through any delay of the group).
+__host__ __device__ constexpr int group_span(int tile, int dmin, int dmax) { return tile + (dmax - dmin) + 16; }
+
+// A workgroup's track slot in global memory (one per workgroup of a persistent
+// launch; written and read by that workgroup only): per segment a Seg and its
+// integer base, then the FP64 grid delays.
+struct Slot {
+    Seg* seg;
+    int32_t* K;
+    double* grid;
+};
+
+// Slot layout: Seg[slot_segs], int32[slot_segs], double[slot_segs + 3 gmax] (the
+// grid delays), each part 256-byte aligned; kernel-specific scratch follows at
+// slot_extra_off.
+__host__ __device__ constexpr int64_t slot_al(int64_t b) { return (b + 255) / 256 * 256; }
+__host__ __device__ constexpr int64_t slot_extra_off(int slot_segs, int gmax)
+{
+    return slot_al((int64_t)slot_segs * 16) + slot_al((int64_t)slot_segs * 4) +
+           slot_al(((int64_t)slot_segs + 3 * (int64_t)gmax) * 8);
+}
 
 // Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
 constexpr int kFarrowStride = 12;
@@ -104,12 +146,6 @@ struct DGroup {
     int32_t dmax;
 };
 
-// Delay of an image over one grid segment [kR, (k+1)R):
-//   D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)),  v = 0 .. R-1,
-// the uniform Catmull-Rom cubic through the exact delays at (k-1)R .. (k+2)R.
-struct Seg {
-    float a0, b1, b2, b3;
-};
 
 constexpr int kStatusWindow = 1;
 
@@ -118,22 +154,24 @@ hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, co
                          const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st);
 
-hipError_t launch_synth_fwd(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                            const float4* d_table, int L, const Seg* seg, const int32_t* segK,
-                            const float* x, float* part, int32_t* d_status, hipStream_t st);
+// What a persistent kernel needs to solve its tracks tile by tile: the plan's
+// knots and mic offsets, the physics, and the per-workgroup slots.
+struct TrackArgs {
+    const double* knots;
+    const double* mics;
+    double c, fs;
+    int model;
+    int slot_segs;        // segments per slot
+    char* slots;          // n_wg slots of slot_bytes each
+    int64_t slot_bytes;
+};
 
-hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st);
-
-hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_run_prefix, int64_t run_total,
-                             const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
-                             int32_t* segK, double c, double fs, int delay_model, hipStream_t st);
-hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
-                                   const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
-                                   const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
-                                   const int32_t* segK, const float* x, float* part, int32_t* d_status,
-                                   hipStream_t st);
-hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
-                             const float* part, float* y, hipStream_t st);
+hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
+                        const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
+                        const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* x,
+                        float* part, int32_t* d_status, hipStream_t st);
+hipError_t launch_reduce_sg(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
+                            const float* part, float* y, hipStream_t st);
 
 // Tap quads of the half table that carry the quadratic term: those within 3/4 of
 // the half-width.  Further out the kernel's second differences are below 1.3e-6
@@ -190,14 +228,10 @@ size_t farrow_lds_bytes(int window);
 hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_t* d_vprefix, int64_t total, int taps,
                               const float* d_coef, const float* x, float* v, hipStream_t st);
 int farrow_outputs_per_lane(const int32_t* decim, int n_tiers);
-hipError_t launch_farrow_fwd(int nthreads, int rb, int taps, int order, const DScene& hs, const DImage* d_imgs,
-                             const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* v, float* part,
-                             int32_t* d_status, hipStream_t st);
-hipError_t launch_farrow_persistent(int nthreads, int rb, int n_wg, int window, int taps, int order,
-                                    const DScene* d_scenes, const DImage* d_imgs, const DGroup* d_groups,
-                                    const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
-                                    const int32_t* segK, const float* v, float* part, int32_t* d_status,
-                                    hipStream_t st);
+hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const DScene* d_scenes,
+                         const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
+                         int32_t* ticket, const TrackArgs& ta, const float* v, float* part, int32_t* d_status,
+                         hipStream_t st);
 hipError_t launch_farrow_adjoint(int nthreads, int taps, int order, const DScene& hs, const DImage* d_imgs,
                                  const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
                                  const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,

@@ -19,58 +19,6 @@ namespace msim {
 
 // ------------------------------------------------------------------- tracks
 
-// Distance term of the retarded-delay equation at emission time te: returns
-// |p_i(te) - r| and sets ev = (p_i(te) - r) . S p'(te) and the PWL segment of te.
-__device__ __forceinline__ double image_dist(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
-                                    const double r[3], double te, double* ev, int* seg)
-{
-    double q[3], v[3];
-    *seg = traj_pos_vel_seg(S.src, knots, te, q, v);
-    double d2 = 0.0, e_v = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        const double e = image_coord(m[a], S.size[a], q[a]) - r[a];
-        d2 += e * e;
-        e_v += e * ((m[a] & 1) ? -v[a] : v[a]);
-    }
-    *ev = e_v;
-    return sqrt_nr(d2);
-}
-
-// Retarded delay at reception time t for mic position r: the root of
-// f(tau) = tau - |p_i(t - tau) - r| / c, by Newton's method from `tau`
-// (f' = 1 + u . S p'(t - tau) / c, in [0.9, 1.1] for speeds below c/10).  A step
-// below 1e-9 s ends it; so does one below 1e-5 s whose emission time stayed on
-// the same piece of the path: the error left is then the curvature of
-// |p_i(t - tau) - r| (below 0.02 / s for the validated speeds and distances)
-// times the step squared, under 1e-11 s.
-__device__ __forceinline__ double newton_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
-                                    const double r[3], double t, double c, double tau)
-{
-    for (int it = 0; it < 30; ++it) {
-        double ev;
-        int sg0;
-        const double d = image_dist(S, m, knots, r, t - tau, &ev, &sg0);
-        const double step = (c * tau - d) * d * rcp_nr(c * d + ev);
-        tau -= step;
-        const double as = fabs(step);
-        if (as <= 1e-9) break;
-        if (as <= 1e-5 && traj_seg(S.src, knots, t - tau) == sg0) break;
-    }
-    return tau;
-}
-
-// First guess of the retarded delay: the equation solved with the image moving on
-// its tangent at time t, c tau = d - (u . S p'(t)) tau, which is off by
-// O((v/c)^2) tau.  Instantaneous model: d / c exactly.
-__device__ __forceinline__ double first_tau(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
-                                   const double r[3], double t, double c, int model)
-{
-    double ev;
-    int sg;
-    const double d = image_dist(S, m, knots, r, t, &ev, &sg);
-    return model == 1 ? d / c : d * d * rcp_nr(c * d + ev);
-}
-
 // One block of kTrackThreads threads per (mic, image, block of segments); thread
 // j solves the kTrackWalk consecutive grid points 4j .. 4j+3 of the block in time
 // order, each from the linear extrapolation of the two before (the first from
@@ -180,21 +128,6 @@ __device__ inline int scene_of(const int64_t* __restrict__ prefix, int n, int64_
     return lo;
 }
 
-// Batched form: one launch over every scene; prefix[s] is scene s's first block.
-__global__ __launch_bounds__(kTrackThreads) void k_tracks_all(const DScene* __restrict__ scenes, int n_scenes,
-                                                              const int64_t* __restrict__ prefix,
-                                                              const DImage* __restrict__ imgs,
-                                                              const double* __restrict__ knots,
-                                                              const double* __restrict__ mics, Seg* __restrict__ seg,
-                                                              int32_t* __restrict__ segK, double c, double fs,
-                                                              int model)
-{
-    __shared__ double Dl[kTrackPoints];
-    const int64_t b = blockIdx.x;
-    const int s = scene_of(prefix, n_scenes, b);
-    track_block(scenes[s], b - prefix[s], imgs, knots, mics, nullptr, seg, segK, c, fs, model, Dl);
-}
-
 hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
                          const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
                          double c, double fs, int delay_model, hipStream_t st)
@@ -203,16 +136,6 @@ hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, co
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tracks, dim3((unsigned)n), dim3(kTrackThreads), 0, st, d_scenes, scene, d_imgs, d_knots,
                        d_mics, grid, seg, segK, c, fs, delay_model);
-    return hipGetLastError();
-}
-
-hipError_t launch_tracks_all(const DScene* d_scenes, int n_scenes, const int64_t* d_run_prefix, int64_t run_total,
-                             const DImage* d_imgs, const double* d_knots, const double* d_mics, Seg* seg,
-                             int32_t* segK, double c, double fs, int delay_model, hipStream_t st)
-{
-    if (run_total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tracks_all, dim3((unsigned)run_total), dim3(kTrackThreads), 0, st, d_scenes, n_scenes,
-                       d_run_prefix, d_imgs, d_knots, d_mics, seg, segK, c, fs, delay_model);
     return hipGetLastError();
 }
 
@@ -230,28 +153,25 @@ size_t synth_lds_bytes(int taps, int Lq, int window)
     return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4);
 }
 
-// One output tile of one delay group for one mic: stages the group's source
-// window in LDS (the table must already be there), then one output sample per
-// lane sums every image of the group; writes the group's partial outputs.
-// The tap weights come from the quadratic table: with q = mu Lq = k + f, the
+// One delay group of an output tile [n0, n0 + NT) of one mic: stages the group's
+// source window in LDS (the table must already be there, the group's tracks in
+// the slot), then one output sample per lane adds every image of the group to
+// acc.  The tap weights come from the quadratic table: with q = mu Lq = k + f, the
 // taps on the delay's near side (|u| = 4g+e + mu) read base row k at fraction f,
 // the mirrored ones (|u| = 4g+e + 1 - mu) base row Lq-1-k at fraction 1-f, and
 // both second-difference terms carry the same weight f (f - 1) / 2.  LC is Lq
 // when known at compile time (then every table read has an immediate offset),
-// else 0 and Lr is used.  Ends with a barrier, so the caller may restage LDS
-// right after.
+// else 0 and Lr is used.  Ends with a barrier.
 template <int T, int NT, int LC>
-__device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int tile, int mic,
-                                  const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
-                                  const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                  const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
+__device__ inline void synth_group(const DScene& S, const DGroup& G, int n0, Slot sl, const DImage* __restrict__ I,
+                                   const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc,
+                                   int& bad)
 {
     constexpr int NG = T / 8;          // tap quads per side
     const int L = LC > 0 ? LC : Lr;
     const int LP = LC > 0 ? LC + 1 : Lr + 1;
     const QTab tq = qtab_view<T>(tab, LP);
     const int tid = threadIdx.x;
-    const int n0 = tile * NT;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = NT + (G.dmax - G.dmin) + T + 8;
     const int n_in = (int)S.n_in;
@@ -260,24 +180,24 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
 
     const int n = n0 + tid;
     if (n < (int)S.n_out) {
-        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const DImage* I = imgs + S.img_begin;
-        const float fn = (float)n + 0.5f;
         const float Lf = (float)L;
-        float acc = 0.0f;
-        int bad = 0;
-
-        // Track data of the next image is fetched while the current one is
-        // filtered; two buffers in turn, so no registers are copied between images.
-        auto fetch = [&](const DImage& im, Seg& q, int& K, int& kseg) {
-            const int k = min(max((int)(fn * im.invR), 0), im.n_seg - 1);
-            q = sgm[im.seg_off + k];
-            K = sgk[im.seg_off + k];
-            kseg = k;
+        // The lane's segment (slot index relative to the image's first) and its
+        // offset depend only on the decimation: kept for the last R seen.  Track
+        // data of the next image is fetched while the current one is filtered.
+        int cR = 0, cl = 0;
+        float cv = 0.0f;
+        auto fetch = [&](const DImage& im, Seg& q, int& K, float& v) {
+            if (im.R != cR) {
+                cR = im.R;
+                const int k = div_exact(n, cR, im.invR);
+                cl = k - div_exact(n0, cR, im.invR);
+                cv = (float)(n - k * cR);
+            }
+            q = sl.seg[im.loc + cl];
+            K = sl.K[im.loc + cl];
+            v = cv;
         };
-        auto body = [&](const DImage& im, const Seg& sg, int Ks, int k) {
-            const float v = (float)(n - __mul24(k, im.R));
+        auto body = [&](const DImage& im, const Seg& sg, int Ks, float v) {
             const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
             const float fl = floorf(d);
             const int K = Ks + (int)fl;
@@ -328,40 +248,37 @@ __device__ inline void synth_tile(const DScene& S, const DGroup& G, int g, int t
             acc = fmaf(gain, s, acc);
         };
         Seg qa{}, qb{};
-        int Ka = 0, Kb = 0, ka = 0, kb = 0;
+        int Ka = 0, Kb = 0;
+        float va = 0.0f, vb = 0.0f;
         DImage ia = I[G.img_begin], ib;
-        fetch(ia, qa, Ka, ka);
+        fetch(ia, qa, Ka, va);
         int ii = G.img_begin;
         for (; ii + 1 < G.img_end; ii += 2) {
             ib = I[ii + 1];
-            fetch(ib, qb, Kb, kb);
-            body(ia, qa, Ka, ka);
+            fetch(ib, qb, Kb, vb);
+            body(ia, qa, Ka, va);
             if (ii + 2 < G.img_end) {
                 ia = I[ii + 2];
-                fetch(ia, qa, Ka, ka);
+                fetch(ia, qa, Ka, va);
             }
-            body(ib, qb, Kb, kb);
+            body(ib, qb, Kb, vb);
         }
-        if (ii < G.img_end) body(ia, qa, Ka, ka);
-        if (bad) atomicOr(status, kStatusWindow);
-        part[S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out + n] = acc;
+        if (ii < G.img_end) body(ia, qa, Ka, va);
     }
     __syncthreads();
 }
 
-// The same tile with two adjacent outputs n, n+1 per lane (NT lanes, 2 NT outputs),
-// which take their tap weights from the same table rows (pair_frame, pair_sums):
-// half the LDS bytes per tap.  Output n+1's taps are output n's shifted by one
-// source position; in the shared frame its far-side tap -T/2+1 and near-side tap
-// T/2+1 fall outside or at the kernel's edge, where h is below 1e-3 |mu' - 1| of
-// its peak.  The plan uses it only while the delay drifts by well under two table
-// rows per sample.
+// The same group with two adjacent outputs n, n+1 per lane (NT lanes, 2 NT outputs
+// per tile), which take their tap weights from the same table rows (pair_frame,
+// pair_sums): half the LDS bytes per tap.  Output n+1's taps are output n's shifted
+// by one source position; in the shared frame its far-side tap -T/2+1 and near-side
+// tap T/2+1 fall outside or at the kernel's edge.  The plan uses it only while the
+// delay drifts by well under two table rows per sample and that edge tap's weight
+// is below its accuracy bound.  Ends with a barrier.
 template <int T, int NT, int LC>
-__device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int tile, int mic,
-                                   const DImage* __restrict__ imgs, const float4* tab, float4* xw, int Lr,
-                                   const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                   const float* __restrict__ x, float* __restrict__ part,
-                                   int32_t* __restrict__ status)
+__device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Slot sl, const DImage* __restrict__ I,
+                                    const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc0,
+                                    float& acc1, int& bad)
 {
     constexpr int NG = T / 8;
     constexpr int TO = 2 * NT;
@@ -369,7 +286,6 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
     const int LP = LC > 0 ? LC + 1 : Lr + 1;
     const QTab tq = qtab_view<T>(tab, LP);
     const int tid = threadIdx.x;
-    const int n0 = tile * TO;
     const int ws = n0 - G.dmax - T / 2 - 4;
     const int W = TO + (G.dmax - G.dmin) + T + 8;
     const int half = split_half(W);
@@ -383,36 +299,31 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
     // delays within [dmin, dmax]): the per-image check is skipped
     const bool all_reach = n0 - G.dmax + T / 2 >= 0 && n0 + TO - G.dmin - T / 2 < n_in;
     if (n < n_out) {
-        const Seg* sgm = seg + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const int32_t* sgk = segK + S.trk_base + (int64_t)mic * S.seg_per_mic;
-        const DImage* I = imgs + S.img_begin;
-        const float fn = (float)n + 0.5f;
         const float Lf = (float)L;
-        float acc0 = 0.0f, acc1 = 0.0f;
-        int bad = 0;
-
         // Track data for both outputs: one segment when the image is decimated
         // (every decimation is even, so n and n+1 share it), else the two
         // full-rate delays (full-rate segments carry zero cubic terms, so the
-        // segment of n gives D(n) either way).  The lane's segment offsets depend
-        // only on the decimation R: they are kept for the last R seen (images of a
-        // group mostly share a tier) as byte offsets from the image's track, so a
-        // fetch is four loads from a scalar base.  Two buffers in turn, as in the
-        // one-output tile.
-        int cR = 0;
-        uint32_t c0 = 0, c1 = 0;            // byte offsets of the segments of n and n+1
-        float cv = 0.0f;                     // n relative to its segment start
+        // segment of n gives D(n) either way).  The lane's slot offsets depend
+        // only on the decimation R: they are kept for the last R seen (images of
+        // a group mostly share a tier).  Two buffers in turn, as in the
+        // one-output group.
+        int cR = 0, c0 = 0, c1 = 0;        // slot indices of the segments of n and n+1
+        float cv = 0.0f;                    // n relative to its segment start
         auto fetch = [&](const DImage& im, Seg& q, float& a1, int& K0, int& K1, float& v) {
             if (im.R != cR) {
                 cR = im.R;
-                const int k0 = im.R == 1 ? min(n, im.n_seg - 1) : min(max((int)(fn * im.invR), 0), im.n_seg - 1);
-                const int k1 = im.R == 1 ? min(n + 1, im.n_seg - 1) : k0;
-                c0 = (uint32_t)k0;
-                c1 = (uint32_t)k1;
-                cv = (float)(n - k0 * im.R);
+                if (cR == 1) {
+                    c0 = n - n0;
+                    c1 = min(n + 1, n_out - 1) - n0;
+                    cv = 0.0f;
+                } else {
+                    const int k0 = div_exact(n, cR, im.invR);
+                    c0 = c1 = k0 - div_exact(n0, cR, im.invR);
+                    cv = (float)(n - k0 * cR);
+                }
             }
-            const Seg* sb = sgm + im.seg_off;
-            const int32_t* kb = sgk + im.seg_off;
+            const Seg* sb = sl.seg + im.loc;
+            const int32_t* kb = sl.K + im.loc;
             q = sb[c0];
             a1 = sb[c1].a0;
             K0 = kb[c0];
@@ -458,69 +369,54 @@ __device__ inline void synth_tile2(const DScene& S, const DGroup& G, int g, int 
             body(ib, qb, a1b, K0b, K1b, kb);
         }
         if (ii < G.img_end) body(ia, qa, a1a, K0a, K1a, ka);
-        if (bad) atomicOr(status, kStatusWindow);
-        float* out = part + S.part_base + ((int64_t)mic * S.n_grp + g) * S.n_out;
-        out[n] = acc0;
-        if (n + 1 < n_out) out[n + 1] = acc1;
     }
     __syncthreads();
 }
 
-// Forward kernels; RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
+// Forward synthesis, persistent: a fixed grid of workgroups loads the table once,
+// then takes work items (scene, mic, tile, supergroup).  For each delay group of
+// the item's supergroup it solves the group's delay tracks over the tile into the
+// workgroup's slot (tile_tracks) and adds the group's images to the lane's
+// register accumulators; the item's sum over its groups (in group order) is
+// written once.  RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
 template <int T, int NT, int LC, int RB>
-__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_fwd(DScene S, const DImage* __restrict__ imgs,
-                                                                   const DGroup* __restrict__ groups,
-                                                                   const float4* __restrict__ table, int L,
-                                                                   const Seg* __restrict__ seg,
-                                                                   const int32_t* __restrict__ segK,
-                                                                   const float* __restrict__ x,
-                                                                   float* __restrict__ part,
-                                                                   int32_t* __restrict__ status)
-{
-    extern __shared__ float4 lds[];
-    float4* tab = lds;
-    float4* xw = lds + qtab_bytes(T, L) / 16;
-    load_qtab<T>(table, tab, L, NT);
-    const int g = blockIdx.y;
-    if constexpr (RB == 1)
-        synth_tile<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK, x,
-                              part, status);
-    else
-        synth_tile2<T, NT, LC>(S, groups[S.grp_begin + g], g, blockIdx.x, blockIdx.z, imgs, tab, xw, L, seg, segK,
-                               x, part, status);
-}
-
-// Persistent form: a fixed grid of workgroups loads the table once, then takes
-// work items (scene, mic, tile, group), ordered by decreasing cost, from a
-// ticket counter until the list is exhausted.  Items write disjoint partial
-// outputs, so the result does not depend on which workgroup ran which item.
-template <int T, int NT, int LC, int RB>
-__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth_persistent(
+__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth(
     const DScene* __restrict__ scenes, const DImage* __restrict__ imgs, const DGroup* __restrict__ groups,
     const float4* __restrict__ table, int L, const WorkItem* __restrict__ items, int n_items,
-    int32_t* __restrict__ ticket, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-    const float* __restrict__ x, float* __restrict__ part, int32_t* __restrict__ status)
+    int32_t* __restrict__ ticket, TrackArgs ta, const float* __restrict__ x, float* __restrict__ part,
+    int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
-    __shared__ int s_item;
+    constexpr int TO = NT * RB;
     float4* tab = lds;
     float4* xw = lds + qtab_bytes(T, L) / 16;
     load_qtab<T>(table, tab, L, NT);
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= n_items) break;
+    const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
+    for_each_item(ticket, n_items, [&](int it) {
         const WorkItem w = items[it];
         const DScene& S = scenes[w.scene];
-        if constexpr (RB == 1)
-            synth_tile<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg,
-                                  segK, x, part, status);
-        else
-            synth_tile2<T, NT, LC>(S, groups[S.grp_begin + w.group], w.group, w.tile, w.mic, imgs, tab, xw, L, seg,
-                                   segK, x, part, status);
-    }
+        const DImage* I = imgs + S.img_begin;
+        const int n0 = w.tile * TO;
+        const int n_out = (int)S.n_out;
+        const int n_hi = min(n0 + TO, n_out);
+        const int gb = sg_begin(S.n_grp, S.n_sg, w.sg), ge = sg_begin(S.n_grp, S.n_sg, w.sg + 1);
+        float acc0 = 0.0f, acc1 = 0.0f;
+        int bad = 0;
+        for (int g = gb; g < ge; ++g) {
+            const DGroup G = groups[S.grp_begin + g];
+            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, sl, ta.knots, ta.mics, ta.c, ta.fs,
+                            ta.model);
+            if constexpr (RB == 1)
+                synth_group<T, NT, LC>(S, G, n0, sl, I, tab, xw, L, x, acc0, bad);
+            else
+                synth_group2<T, NT, LC>(S, G, n0, sl, I, tab, xw, L, x, acc0, acc1, bad);
+        }
+        float* out = part + S.part_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_out;
+        const int n = n0 + RB * (int)threadIdx.x;
+        if (n < n_out) out[n] = acc0;
+        if (RB == 2 && n + 1 < n_out) out[n + 1] = acc1;
+        if (bad) atomicOr(status, kStatusWindow);
+    });
 }
 
 __global__ void k_zero_i32(int32_t* p, int n)
@@ -534,101 +430,51 @@ __global__ void k_zero_i32(int32_t* p, int n)
 constexpr int kPhasesCompiled = 128;
 
 template <int T, int TO, int RB>
-static hipError_t launch_fwd_t(const DScene& hs, const DImage* d_imgs, const DGroup* d_groups, const float4* d_table,
-                               int L, const Seg* seg, const int32_t* segK, const float* x, float* part,
-                               int32_t* d_status, hipStream_t st)
-{
-    constexpr int NT = TO / RB;
-    const size_t lds = synth_lds_bytes(T, L, hs.window);
-    auto kern = L == kPhasesCompiled ? k_synth_fwd<T, NT, kPhasesCompiled, RB> : k_synth_fwd<T, NT, 0, RB>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    dim3 grid((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics);
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status);
-    return hipGetLastError();
-}
-
-template <int T, int TO, int RB>
-static hipError_t launch_persistent_t(int n_wg, int window, const DScene* d_scenes, const DImage* d_imgs,
-                                      const DGroup* d_groups, const float4* d_table, int L, const WorkItem* items,
-                                      int n_items, int32_t* ticket, const Seg* seg, const int32_t* segK,
-                                      const float* x, float* part, int32_t* d_status, hipStream_t st)
+static hipError_t launch_synth_t(int n_wg, int window, const DScene* d_scenes, const DImage* d_imgs,
+                                 const DGroup* d_groups, const float4* d_table, int L, const WorkItem* items,
+                                 int n_items, int32_t* ticket, const TrackArgs& ta, const float* x, float* part,
+                                 int32_t* d_status, hipStream_t st)
 {
     constexpr int NT = TO / RB;
     const size_t lds = synth_lds_bytes(T, L, window);
-    auto kern = L == kPhasesCompiled ? k_synth_persistent<T, NT, kPhasesCompiled, RB>
-                                     : k_synth_persistent<T, NT, 0, RB>;
+    auto kern = L == kPhasesCompiled ? k_synth<T, NT, kPhasesCompiled, RB> : k_synth<T, NT, 0, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, ticket, 1);
     hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, d_scenes, d_imgs, d_groups, d_table, L, items,
-                       n_items, ticket, seg, segK, x, part, d_status);
+                       n_items, ticket, ta, x, part, d_status);
     return hipGetLastError();
 }
 
-hipError_t launch_synth_fwd(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs,
-                            const DGroup* d_groups, const float4* d_table, int L, const Seg* seg,
-                            const int32_t* segK, const float* x, float* part, int32_t* d_status, hipStream_t st)
+hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
+                        const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
+                        const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* x,
+                        float* part, int32_t* d_status, hipStream_t st)
 {
-#define MSIM_FWD_CASE(TT, NN, RR)                                                                              \
+    if (n_items == 0) return hipSuccess;
+#define MSIM_SYN_CASE(TT, NN, RR)                                                                              \
     if (taps == TT && nthreads == NN && rb == RR)                                                             \
-        return launch_fwd_t<TT, NN, RR>(hs, d_imgs, d_groups, d_table, L, seg, segK, x, part, d_status, st);
-#define MSIM_FWD_TAPS(TT)                                                                                      \
-    MSIM_FWD_CASE(TT, 512, 1) MSIM_FWD_CASE(TT, 1024, 1) MSIM_FWD_CASE(TT, 512, 2) MSIM_FWD_CASE(TT, 1024, 2)
-    MSIM_FWD_TAPS(32)
-    MSIM_FWD_TAPS(64)
-    MSIM_FWD_TAPS(96)
-    MSIM_FWD_TAPS(128)
-#undef MSIM_FWD_TAPS
-#undef MSIM_FWD_CASE
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_synth_persistent(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
-                                   const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
-                                   const WorkItem* items, int n_items, int32_t* ticket, const Seg* seg,
-                                   const int32_t* segK, const float* x, float* part, int32_t* d_status,
-                                   hipStream_t st)
-{
-#define MSIM_PERS_CASE(TT, NN, RR)                                                                             \
-    if (taps == TT && nthreads == NN && rb == RR)                                                             \
-        return launch_persistent_t<TT, NN, RR>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items,   \
-                                               n_items, ticket, seg, segK, x, part, d_status, st);
-#define MSIM_PERS_TAPS(TT)                                                                                     \
-    MSIM_PERS_CASE(TT, 512, 1) MSIM_PERS_CASE(TT, 1024, 1) MSIM_PERS_CASE(TT, 512, 2) MSIM_PERS_CASE(TT, 1024, 2)
-    MSIM_PERS_TAPS(32)
-    MSIM_PERS_TAPS(64)
-    MSIM_PERS_TAPS(96)
-    MSIM_PERS_TAPS(128)
-#undef MSIM_PERS_TAPS
-#undef MSIM_PERS_CASE
+        return launch_synth_t<TT, NN, RR>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items, n_items, \
+                                          ticket, ta, x, part, d_status, st);
+#define MSIM_SYN_TAPS(TT)                                                                                      \
+    MSIM_SYN_CASE(TT, 512, 1) MSIM_SYN_CASE(TT, 1024, 1) MSIM_SYN_CASE(TT, 512, 2) MSIM_SYN_CASE(TT, 1024, 2)
+    MSIM_SYN_TAPS(32)
+    MSIM_SYN_TAPS(64)
+    MSIM_SYN_TAPS(96)
+    MSIM_SYN_TAPS(128)
+#undef MSIM_SYN_TAPS
+#undef MSIM_SYN_CASE
     return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ reduction
 
-__global__ __launch_bounds__(256) void k_reduce_groups(int64_t n_out, int n_grp, int n_mics,
-                                                       const float* __restrict__ part, float* __restrict__ y)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_out * n_mics) return;
-    const int mic = (int)(i / n_out);
-    const int64_t n = i - (int64_t)mic * n_out;
-    y[i] = strided_sum<16>(part + (int64_t)mic * n_grp * n_out + n, n_grp, n_out);
-}
-
-hipError_t launch_reduce_groups(const DScene& hs, const float* part, float* y, hipStream_t st)
-{
-    const int64_t n = hs.n_out * hs.n_mics;
-    hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hs.n_out, hs.n_grp,
-                       hs.n_mics, part, y + hs.y_off);
-    return hipGetLastError();
-}
-
-// Batched: one thread per output sample of every scene (y packed scene-major).
-__global__ __launch_bounds__(256) void k_reduce_all(const DScene* __restrict__ scenes, int n_scenes,
-                                                    const int64_t* __restrict__ y_prefix, int64_t y_total,
-                                                    const float* __restrict__ part, float* __restrict__ y)
+// Partial outputs [mic][supergroup][n_out] summed in supergroup order, one thread
+// per output sample of every scene (y packed scene-major); prefix[s] is scene s's
+// first output.
+__global__ __launch_bounds__(256) void k_reduce_sg(const DScene* __restrict__ scenes, int n_scenes,
+                                                   const int64_t* __restrict__ y_prefix, int64_t y_total,
+                                                   const float* __restrict__ part, float* __restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= y_total) return;
@@ -637,13 +483,14 @@ __global__ __launch_bounds__(256) void k_reduce_all(const DScene* __restrict__ s
     const int64_t j = i - y_prefix[s];
     const int mic = (int)(j / S.n_out);
     const int64_t n = j - (int64_t)mic * S.n_out;
-    y[i] = strided_sum<16>(part + S.part_base + (int64_t)mic * S.n_grp * S.n_out + n, S.n_grp, S.n_out);
+    y[S.y_off + j] = strided_sum<16>(part + S.part_base + (int64_t)mic * S.n_sg * S.n_out + n, S.n_sg, S.n_out);
 }
 
-hipError_t launch_reduce_all(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
-                             const float* part, float* y, hipStream_t st)
+hipError_t launch_reduce_sg(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
+                            const float* part, float* y, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_all, dim3((unsigned)((y_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
+    if (y_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_sg, dim3((unsigned)((y_total + 255) / 256)), dim3(256), 0, st, d_scenes, n_scenes,
                        d_y_prefix, y_total, part, y);
     return hipGetLastError();
 }
