@@ -123,7 +123,7 @@ __device__ __forceinline__ int pwl_find(const double* __restrict__ T, int n, dou
     return lo;
 }
 
-__device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
+__device__ __forceinline__ void traj_pos(const DTraj& tr, const double* __restrict__ knots, double t, double out[3])
 {
     if (tr.kind == 1) {
         double s, c;
@@ -154,7 +154,7 @@ __device__ inline void traj_pos(const DTraj& tr, const double* __restrict__ knot
 
 // Position and velocity of a trajectory at time t, and the index of the PWL
 // segment holding t (-1 before the first knot, n-1 after the last; 0 for circles).
-__device__ inline int traj_pos_vel_seg(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
+__device__ __forceinline__ int traj_pos_vel_seg(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
                                        double v[3])
 {
     if (tr.kind == 1) {
@@ -192,7 +192,7 @@ __device__ inline int traj_pos_vel_seg(const DTraj& tr, const double* __restrict
 }
 
 // The PWL segment holding t, numbered as traj_pos_vel_seg does (0 for circles).
-__device__ inline int traj_seg(const DTraj& tr, const double* __restrict__ knots, double t)
+__device__ __forceinline__ int traj_seg(const DTraj& tr, const double* __restrict__ knots, double t)
 {
     if (tr.kind == 1) return 0;
     const double* T = knots + tr.knot_off;
@@ -203,12 +203,12 @@ __device__ inline int traj_seg(const DTraj& tr, const double* __restrict__ knots
     return a;
 }
 
-__device__ inline double image_coord(int m, double L, double q)
+__device__ __forceinline__ double image_coord(int m, double L, double q)
 {
     return (m & 1) ? (double)(m + 1) * L - q : (double)m * L + q;
 }
 
-__device__ inline double dist_to(const DScene& S, const int16_t m[3], const double* knots, const double r[3], double te)
+__device__ __forceinline__ double dist_to(const DScene& S, const int16_t m[3], const double* knots, const double r[3], double te)
 {
     double q[3];
     traj_pos(S.src, knots, te, q);
@@ -222,7 +222,7 @@ __device__ inline double dist_to(const DScene& S, const int16_t m[3], const doub
 
 // Position and velocity of a trajectory at time t (velocity zero where a PWL
 // path is held at its end knots).
-__device__ inline void traj_pos_vel(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
+__device__ __forceinline__ void traj_pos_vel(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
                                     double v[3])
 {
     if (tr.kind == 1) {
@@ -263,7 +263,7 @@ __device__ inline void traj_pos_vel(const DTraj& tr, const double* __restrict__ 
 // method from the instantaneous delay; f' = 1 + u . S p'(t - tau) / c lies in
 // [0.9, 1.1] (speeds below c/10 by validation), so the steps contract even
 // across the kinks of a piecewise-linear path.  Instantaneous: |p_i(t) - r(t)| / c.
-__device__ inline double solve_tau(const DScene& S, const int16_t m[3], const double* knots, const double* mics,
+__device__ __forceinline__ double solve_tau(const DScene& S, const int16_t m[3], const double* knots, const double* mics,
                                    int mic, double t, double inv_c, int model)
 {
     double r[3];
@@ -312,7 +312,7 @@ __device__ inline int owner(const DImage* __restrict__ I, int n_img, int64_t idx
 // Position (traj_pos's arithmetic), velocity (zero outside the knot range) and
 // PWL segment of a path at t by one search: knot a and the weight lam of knot a+1
 // (lam = 0 outside the knot range or for a static path; then only knot a moves it).
-__device__ inline void pwl_eval(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
+__device__ __forceinline__ void pwl_eval(const DTraj& tr, const double* __restrict__ knots, double t, double p[3],
                                 double v[3], int* a_out, double* lam_out)
 {
     const double* T = knots + tr.knot_off;
@@ -340,7 +340,7 @@ __device__ inline void pwl_eval(const DTraj& tr, const double* __restrict__ knot
     *lam_out = lam;
 }
 
-__device__ inline void mic_pos(const DScene& S, const double* __restrict__ knots, const double* __restrict__ mics,
+__device__ __forceinline__ void mic_pos(const DScene& S, const double* __restrict__ knots, const double* __restrict__ mics,
                                int mic, double t, double r[3])
 {
     traj_pos(S.rcv, knots, t, r);
@@ -406,13 +406,81 @@ __device__ __forceinline__ double first_tau(const DScene& S, const int16_t m[3],
 }
 
 
+// Retarded delay of a piecewise-linear source, by the closed form on each piece
+// of the path.  On piece a (knots a, a+1) the image moves linearly,
+// S p(t - u) + O - r = W - U u with W the image position extrapolated along the
+// piece to the reception time minus r, and U the image velocity; c u = |W - U u|
+// is the quadratic (|U|^2 - c^2) u^2 - 2 (W.U) u + |W|^2 = 0, whose positive root
+// (|U| < c) is u = |W|^2 / (W.U + sqrt((W.U)^2 + (c^2 - |U|^2) |W|^2)) (a form
+// without cancellation).  Before the first knot and after the last the source is
+// held still (U = 0).  If the emission time t - u falls outside piece a, the next
+// piece towards it is tried; *a carries the piece between calls (-1: before the
+// first knot, n-1: after the last; any value is a valid start).
+__device__ __forceinline__ double pwl_retarded(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                               const double r[3], double t, double c, int* a_io)
+{
+    const double* T = knots + S.src.knot_off;
+    const double* P = knots + S.src.pos_off;
+    const int n = S.src.n_points;
+    double sg[3], of[3];
+    for (int k = 0; k < 3; ++k) {
+        sg[k] = (m[k] & 1) ? -1.0 : 1.0;
+        of[k] = (m[k] & 1) ? (double)(m[k] + 1) * S.size[k] : (double)m[k] * S.size[k];
+    }
+    int a = min(max(*a_io, -1), n - 1);
+    double u = 0.0;
+    for (int it = 0; it < 2 * n + 2; ++it) {
+        double W[3], U[3];
+        if (a < 0 || a >= n - 1) {
+            const int q = a < 0 ? 0 : n - 1;
+            for (int k = 0; k < 3; ++k) {
+                W[k] = sg[k] * P[3 * q + k] + of[k] - r[k];
+                U[k] = 0.0;
+            }
+        } else {
+            const double idt = 1.0 / (T[a + 1] - T[a]);
+            const double dt = t - T[a];
+            for (int k = 0; k < 3; ++k) {
+                const double v = (P[3 * (a + 1) + k] - P[3 * a + k]) * idt;
+                W[k] = sg[k] * (P[3 * a + k] + v * dt) + of[k] - r[k];
+                U[k] = sg[k] * v;
+            }
+        }
+        const double ww = W[0] * W[0] + W[1] * W[1] + W[2] * W[2];
+        const double wu = W[0] * U[0] + W[1] * U[1] + W[2] * U[2];
+        const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+        u = ww / (wu + sqrt_nr(fma(wu, wu, (c * c - uu) * ww)));
+        const double te = t - u;
+        if (a >= 0 && te < T[a]) {
+            --a;                              // emitted on an earlier piece
+        } else if (a < n - 1 && te > T[a + 1]) {
+            ++a;                              // emitted on a later piece
+        } else {
+            break;
+        }
+    }
+    *a_io = a;
+    return u;
+}
+
+// The delay of image m for mic position r at reception time t: the closed form
+// above for a piecewise-linear source with retarded delays, else Newton's method
+// (circles) or the instantaneous distance.  *a: the path piece hint.
+__device__ __forceinline__ double image_delay(const DScene& S, const int16_t m[3], const double* __restrict__ knots,
+                                              const double r[3], double t, double c, int model, int* a)
+{
+    if (model == 0 && S.src.kind == kTrajPwl) return pwl_retarded(S, m, knots, r, t, c, a);
+    const double tau = first_tau(S, m, knots, r, t, c, model);
+    return model == 0 ? newton_tau(S, m, knots, r, t, c, tau) : tau;
+}
+
 // ------------------------------------------------------- persistent kernels
 
 // Work-item loop shared by the persistent kernels: takes items from the ticket
 // counter until the list is exhausted and calls fn(item).  Items write disjoint
 // outputs, so the result does not depend on which workgroup ran which item.
 template <typename F>
-__device__ inline void for_each_item(int32_t* ticket, int n_items, F&& fn)
+__device__ __forceinline__ void for_each_item(int32_t* ticket, int n_items, F&& fn)
 {
     __shared__ int s_item;
     for (;;) {
@@ -457,70 +525,101 @@ __device__ __forceinline__ int div_exact(int k, int R, float invR)
 // (Seg and integer base, as in the stored form: the exact delay at the audio rate,
 // else the uniform Catmull-Rom cubic through D_{k-1} .. D_{k+2}, Sec. II-C-3), and
 // the exact grid delays D_g, g = g_lo .. g_hi (k_lo - 1 .. k_hi + 2 when R > 1,
-// else k_lo .. k_hi), at grid[I[ii].loc + 3 (ii - ib) + g - g_lo].  Wave w takes
-// images ib + w, ib + w + waves, ...; its lanes walk runs of consecutive grid
-// points, each solved from the delays before it.  Starts and ends with a barrier.
+// else k_lo .. k_hi), at grid[I[ii].loc + 3 (ii - ib) + g - g_lo].
+//
+// Image ii holds slot_segs_of(R, span) segments and 3 more grid points, so the
+// group's grid points form one index space (each image's share at its grid
+// offset); every thread takes a run of consecutive indices and solves its points
+// in time order, each from the delays before it.  lsc: 2 (ie - ib) + 2 ints of LDS
+// for the images' grid and segment offsets.  Starts and ends with a barrier.
 template <int NT>
-__device__ void tile_tracks(const DScene& S, int mic, const DImage* __restrict__ I, int ib, int ie, int n_lo,
-                            int n_hi, Slot sl, const double* __restrict__ knots, const double* __restrict__ mics,
-                            double c, double fs, int model)
+__device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DImage* __restrict__ I, int ib, int ie, int n_lo,
+                            int n_hi, int span, Slot sl, int* lsc, const double* __restrict__ knots,
+                            const double* __restrict__ mics, double c, double fs, int model)
 {
-    constexpr int WAVES = NT / 64;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cnt = ie - ib;
+    int* goff = lsc;               // [cnt + 1]: first grid index of each image, then the total
+    int* soff = lsc + cnt + 1;     // [cnt + 1]: first segment index of each image, then the total
     const double inv_fs = 1.0 / fs;
     __syncthreads();
-    for (int ii = ib + wave; ii < ie; ii += WAVES) {
-        const DImage im = I[ii];
-        const int R = im.R;
-        const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
-        const int g_lo = R == 1 ? k_lo : k_lo - 1, g_hi = R == 1 ? k_hi : k_hi + 2;
-        const int npts = g_hi - g_lo + 1;
-        const int run = (npts + 63) >> 6;
-        double* gd = sl.grid + im.loc + 3 * (ii - ib);
-        double tp1 = 0.0, tp2 = 0.0;
-        for (int w = 0; w < run; ++w) {
-            const int j = lane * run + w;
-            if (j >= npts) break;
-            const int g = g_lo + j;
-            const double t = (double)g * (double)R * inv_fs;
-            double r[3];
-            mic_pos(S, knots, mics, mic, t, r);
-            double tau;
-            if (model == 1 || w == 0) {
-                tau = first_tau(S, im.m, knots, r, t, c, model);
-                if (model == 0) tau = newton_tau(S, im.m, knots, r, t, c, tau);
-            } else {
-                tau = newton_tau(S, im.m, knots, r, t, c, w >= 2 ? 2.0 * tp1 - tp2 : tp1);
-            }
-            tp2 = tp1;
-            tp1 = tau;
-            gd[j] = fs * tau;
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+        const DImage& im = I[ib + i];
+        goff[i] = im.loc + 3 * i;
+        soff[i] = im.loc;
+        if (i == cnt - 1) {
+            soff[cnt] = im.loc + slot_segs_of(im.R, span);
+            goff[cnt] = soff[cnt] + 3 * cnt;
         }
     }
     __syncthreads();
-    for (int ii = ib + wave; ii < ie; ii += WAVES) {
-        const DImage im = I[ii];
-        const int R = im.R;
-        const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
-        const double* gd = sl.grid + im.loc + 3 * (ii - ib);
-        Seg* so = sl.seg + im.loc;
-        int32_t* ko = sl.K + im.loc;
-        const double iR = 1.0 / (double)R;
-        for (int j = lane; j <= k_hi - k_lo; j += 64) {
+    // the image of index f in an offset table: the last i with off[i] <= f
+    auto image_at = [&](const int* off, int f) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= f) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    {
+        const int total = goff[cnt];
+        const int run = (total + NT - 1) / NT;
+        const int f0 = threadIdx.x * run, f1 = min(f0 + run, total);
+        int ii = f0 < f1 ? image_at(goff, f0) : 0;
+        int last_j = -2;               // grid point solved before
+        int apiece = 0;                // path piece of its emission time
+        int g_lo = 0, npts = 0, R = 1, cur = -1;
+        int16_t m[3] = {0, 0, 0};
+        for (int f = f0; f < f1; ++f) {
+            while (ii + 1 < cnt && f >= goff[ii + 1]) ++ii;
+            if (ii != cur) {
+                cur = ii;
+                const DImage& im = I[ib + ii];
+                R = im.R;
+                m[0] = im.m[0];
+                m[1] = im.m[1];
+                m[2] = im.m[2];
+                const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
+                g_lo = R == 1 ? k_lo : k_lo - 1;
+                npts = (R == 1 ? k_hi : k_hi + 2) - g_lo + 1;
+                last_j = -2;
+            }
+            const int j = f - goff[ii];
+            if (j >= npts) continue;
+            const double t = (double)(g_lo + j) * (double)R * inv_fs;
+            double r[3];
+            mic_pos(S, knots, mics, mic, t, r);
+            if (last_j != j - 1) apiece = S.src.kind == kTrajPwl ? traj_seg(S.src, knots, t) : 0;
+            const double tau = image_delay(S, m, knots, r, t, c, model, &apiece);
+            last_j = j;
+            sl.grid[f] = fs * tau;
+        }
+    }
+    __syncthreads();
+    {
+        const int total = soff[cnt];
+        for (int f = threadIdx.x; f < total; f += NT) {
+            const int i = image_at(soff, f);
+            const int R = I[ib + i].R;
+            const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
+            const int j = f - soff[i];
+            if (j > k_hi - k_lo) continue;
+            const double* gd = sl.grid + goff[i];
             if (R == 1) {
                 const double D = gd[j];
                 const double Kd = floor(D);
-                so[j] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
-                ko[j] = (int32_t)Kd;
+                sl.seg[f] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
+                sl.K[f] = (int32_t)Kd;
             } else {
                 // grid index of D_{k-1} is (k - 1) - g_lo = j
+                const double iR = 1.0 / (double)R;
                 const double D0 = gd[j], D1 = gd[j + 1], D2 = gd[j + 2], D3 = gd[j + 3];
                 const double Kd = floor(D1);
                 const double a1 = 0.5 * (D2 - D0);
                 const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D3);
                 const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D3);
-                so[j] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
-                ko[j] = (int32_t)Kd;
+                sl.seg[f] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
+                sl.K[f] = (int32_t)Kd;
             }
         }
     }

@@ -343,8 +343,8 @@ __global__ __launch_bounds__(TO / RB) void k_farrow(const DScene* __restrict__ s
         int bad = 0;
         for (int g = gb; g < ge; ++g) {
             const DGroup G = groups[S.grp_begin + g];
-            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, sl, ta.knots, ta.mics, ta.c, ta.fs,
-                            ta.model);
+            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax), sl,
+                            (int*)(lds + kFarrowDescChunk), ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             if constexpr (RB == 1)
                 farrow_group1<TO, HI>(S, G, n0, T, sl, I, (int4*)lds, lds + kFarrowDescChunk, v, acc[0], bad);
             else

@@ -40,6 +40,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxOut = int64_t(1) << 23;
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kMaxGroup = 512;     // images per delay group at most
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -676,6 +677,8 @@ msim_status regroup(msim_plan* P)
             }
             if (P->par.fd_kind != MSIM_FD_FARROW) G = std::max(G, (I + 23) / 24);
         }
+        // a group's slot offsets are staged in LDS while its tracks are solved
+        G = std::max(G, (I + kMaxGroup - 1) / kMaxGroup);
         std::vector<DGroup> gr;
         int window = 0;
         auto split = [&](int ng) {
@@ -760,24 +763,28 @@ msim_status regroup(msim_plan* P)
     P->slot_segs = slot_segs;
     P->gmax = gmax;
     // Supergroups: a work item sums the groups of one supergroup of one (mic, tile)
-    // in registers and writes one partial output row.  Items enough to fill the
-    // persistent grid several times, partial outputs within 2 GiB.
-    int64_t tm = 0, outs = 0;
-    for (const DScene& d : P->scenes) {
-        tm += (int64_t)d.n_tiles * d.n_mics;
-        outs += (int64_t)d.n_mics * d.n_out;
-    }
+    // in registers and writes one partial output row.  Each scene gets items
+    // enough to fill the persistent grid several times on its own (the plain path
+    // runs scenes one at a time), as long as all partial outputs stay within 2 GiB.
     const int64_t want = 8 * 512;
-    int nsg_par = (int)std::max<int64_t>(1, (want + tm - 1) / std::max<int64_t>(1, tm));
-    const int nsg_mem = (int)std::max<int64_t>(1, ((int64_t)1 << 29) / std::max<int64_t>(1, outs));
-    nsg_par = std::min(nsg_par, nsg_mem);
+    std::vector<int> nsg(P->n_scenes);
+    int64_t total = 0;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        const DScene& d = P->scenes[s];
+        const int64_t tm = std::max<int64_t>(1, (int64_t)d.n_tiles * d.n_mics);
+        nsg[s] = (int)std::min<int64_t>(d.n_grp, std::max<int64_t>(1, (want + tm - 1) / tm));
+        total += (int64_t)d.n_mics * d.n_out * nsg[s];
+    }
+    const int64_t budget = (int64_t)1 << 29;
+    if (total > budget)
+        for (int s = 0; s < P->n_scenes; ++s) nsg[s] = (int)std::max<int64_t>(1, (int64_t)nsg[s] * budget / total);
     P->scenes_b = P->scenes;
     P->y_prefix.assign(P->n_scenes, 0);
     int64_t po = 0, pmax = 0;
     int wmax = 0;
     for (int s = 0; s < P->n_scenes; ++s) {
         DScene& d = P->scenes[s];
-        d.n_sg = std::min(d.n_grp, nsg_par);
+        d.n_sg = nsg[s];
         d.part_base = 0;
         DScene& b = P->scenes_b[s];
         b.n_sg = d.n_sg;

@@ -8,6 +8,9 @@
 
 namespace msim {
 
+// Trajectory kinds (as in the C-ABI): piecewise linear, horizontal circle.
+constexpr int kTrajPwl = 0, kTrajCircle = 1;
+
 // A trajectory as the kernels see it: knot times and positions live in the
 // plan's knot array (times at knot_off, xyz triples at pos_off).
 struct DTraj {

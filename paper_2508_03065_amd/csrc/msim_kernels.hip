@@ -380,7 +380,7 @@ __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Sl
 // register accumulators; the item's sum over its groups (in group order) is
 // written once.  RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
 template <int T, int NT, int LC, int RB>
-__global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth(
+__global__ __launch_bounds__(NT, 4) void k_synth(
     const DScene* __restrict__ scenes, const DImage* __restrict__ imgs, const DGroup* __restrict__ groups,
     const float4* __restrict__ table, int L, const WorkItem* __restrict__ items, int n_items,
     int32_t* __restrict__ ticket, TrackArgs ta, const float* __restrict__ x, float* __restrict__ part,
@@ -404,8 +404,8 @@ __global__ __launch_bounds__(NT, RB == 1 ? 8 : 4) void k_synth(
         int bad = 0;
         for (int g = gb; g < ge; ++g) {
             const DGroup G = groups[S.grp_begin + g];
-            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, sl, ta.knots, ta.mics, ta.c, ta.fs,
-                            ta.model);
+            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax), sl,
+                            (int*)xw, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             if constexpr (RB == 1)
                 synth_group<T, NT, LC>(S, G, n0, sl, I, tab, xw, L, x, acc0, bad);
             else
