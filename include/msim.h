@@ -215,6 +215,15 @@ msim_status msim_autotune(msim_plan* plan, const float* x, float* y, void* ws, s
 msim_status msim_backward(msim_plan* plan, const float* x, const float* gy, float* gx, double* gbeta,
                           double* gsrc, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Batched reverse mode: the same gradients as msim_backward (bit for bit: both
+ * sum every partial in the same order), computed by one launch per kernel over
+ * all scenes at once (persistent workgroups taking (scene, mic, tile,
+ * supergroup) items from a ticket counter).  With use_graph != 0 the launches
+ * are captured once into a HIP graph (per argument set: x, gy, gx, gbeta, gsrc,
+ * ws) and replayed on `stream`.  ws holds msim_batched_workspace_size() bytes. */
+msim_status msim_backward_batched(msim_plan* plan, const float* x, const float* gy, float* gx, double* gbeta,
+                                  double* gsrc, void* ws, size_t ws_bytes, hipStream_t stream, int32_t use_graph);
+
 /* Offsets (in knots) of each scene's source knots in gsrc, and their total. */
 msim_status msim_plan_grad_layout(const msim_plan* plan, int64_t* src_off, int64_t* src_total);
 

@@ -71,6 +71,8 @@ SIGNATURES = {
     "msim_device_status": [_PLAN, C.c_void_p, C.POINTER(C.c_int32)],
     "msim_backward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                       C.c_size_t, C.c_void_p],
+    "msim_backward_batched": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_size_t, C.c_void_p, C.c_int32],
     "msim_plan_grad_layout": [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "msim_batched_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
     "msim_forward_batched": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32],

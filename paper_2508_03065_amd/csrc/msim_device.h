@@ -296,19 +296,6 @@ __device__ __forceinline__ double solve_tau(const DScene& S, const int16_t m[3],
 
 // ------------------------------------------------------------------- tracks
 
-// Image owning flat index `idx` within one mic's track, where image ii owns
-// [off(ii), off(ii+1)) and off(ii) = seg_off + extra * ii.
-__device__ inline int owner(const DImage* __restrict__ I, int n_img, int64_t idx, int extra)
-{
-    int lo = 0, hi = n_img - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((int64_t)I[mid].seg_off + (int64_t)extra * mid <= idx) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-
 // Position (traj_pos's arithmetic), velocity (zero outside the knot range) and
 // PWL segment of a path at t by one search: knot a and the weight lam of knot a+1
 // (lam = 0 outside the knot range or for a static path; then only knot a moves it).
@@ -474,6 +461,31 @@ __device__ __forceinline__ double image_delay(const DScene& S, const int16_t m[3
     return model == 0 ? newton_tau(S, m, knots, r, t, c, tau) : tau;
 }
 
+// Last scene whose prefix start is <= i (prefix[0] = 0, ascending).
+__device__ __forceinline__ int scene_of(const int64_t* __restrict__ prefix, int n, int64_t i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Clears a persistent launch's ticket counter (a kernel, so graphs hold no memset).
+static __global__ void k_zero_ticket(int32_t* p)
+{
+    if (threadIdx.x == 0) p[0] = 0;
+}
+
+// Fixed-order butterfly sum over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ------------------------------------------------------- persistent kernels
 
 // Work-item loop shared by the persistent kernels: takes items from the ticket
@@ -519,13 +531,35 @@ __device__ __forceinline__ int div_exact(int k, int R, float invR)
     return q;
 }
 
-// Delay tracks of images [ib, ie) of scene S (I: the scene's images), mic `mic`,
+// The image of index f in a group's offset table off[0 .. cnt): the last i with
+// off[i] <= f.
+__device__ __forceinline__ int off_index(const int* off, int cnt, int f)
+{
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Image k of the plan's group permutation, with its slot offset.
+__device__ __forceinline__ DImage perm_image(const DImage* __restrict__ I, const PermEntry* __restrict__ perm, int k)
+{
+    const PermEntry e = perm[k];
+    DImage im = I[e.img];
+    im.loc = e.loc;
+    return im;
+}
+
+// Delay tracks of images perm[ib .. ie) of scene S (I: the scene's images), mic `mic`,
 // over outputs [n_lo, n_hi) (n_hi <= n_out): segment k of image ii, k_lo <= k <= k_hi
-// with k_lo = n_lo / R, k_hi = (n_hi - 1) / R, at slot seg[I[ii].loc + k - k_lo]
+// with k_lo = n_lo / R, k_hi = (n_hi - 1) / R, at slot seg[loc + k - k_lo] (loc: the
+// image's permutation entry's slot offset)
 // (Seg and integer base, as in the stored form: the exact delay at the audio rate,
 // else the uniform Catmull-Rom cubic through D_{k-1} .. D_{k+2}, Sec. II-C-3), and
 // the exact grid delays D_g, g = g_lo .. g_hi (k_lo - 1 .. k_hi + 2 when R > 1,
-// else k_lo .. k_hi), at grid[I[ii].loc + 3 (ii - ib) + g - g_lo].
+// else k_lo .. k_hi), at grid[loc + 3 (ii - ib) + g - g_lo].
 //
 // Image ii holds slot_segs_of(R, span) segments and 3 more grid points, so the
 // group's grid points form one index space (each image's share at its grid
@@ -533,7 +567,8 @@ __device__ __forceinline__ int div_exact(int k, int R, float invR)
 // in time order, each from the delays before it.  lsc: 2 (ie - ib) + 2 ints of LDS
 // for the images' grid and segment offsets.  Starts and ends with a barrier.
 template <int NT>
-__device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DImage* __restrict__ I, int ib, int ie, int n_lo,
+__device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DImage* __restrict__ I,
+                                            const PermEntry* __restrict__ perm, int ib, int ie, int n_lo,
                             int n_hi, int span, Slot sl, int* lsc, const double* __restrict__ knots,
                             const double* __restrict__ mics, double c, double fs, int model)
 {
@@ -543,24 +578,16 @@ __device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DIma
     const double inv_fs = 1.0 / fs;
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += NT) {
-        const DImage& im = I[ib + i];
-        goff[i] = im.loc + 3 * i;
-        soff[i] = im.loc;
+        const PermEntry e = perm[ib + i];
+        goff[i] = e.loc + 3 * i;
+        soff[i] = e.loc;
         if (i == cnt - 1) {
-            soff[cnt] = im.loc + slot_segs_of(im.R, span);
+            soff[cnt] = e.loc + slot_segs_of(I[e.img].R, span);
             goff[cnt] = soff[cnt] + 3 * cnt;
         }
     }
     __syncthreads();
-    // the image of index f in an offset table: the last i with off[i] <= f
-    auto image_at = [&](const int* off, int f) {
-        int lo = 0, hi = cnt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= f) lo = mid; else hi = mid - 1;
-        }
-        return lo;
-    };
+    auto image_at = [&](const int* off, int f) { return off_index(off, cnt, f); };
     {
         const int total = goff[cnt];
         const int run = (total + NT - 1) / NT;
@@ -574,7 +601,7 @@ __device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DIma
             while (ii + 1 < cnt && f >= goff[ii + 1]) ++ii;
             if (ii != cur) {
                 cur = ii;
-                const DImage& im = I[ib + ii];
+                const DImage& im = I[perm[ib + ii].img];
                 R = im.R;
                 m[0] = im.m[0];
                 m[1] = im.m[1];
@@ -600,7 +627,7 @@ __device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DIma
         const int total = soff[cnt];
         for (int f = threadIdx.x; f < total; f += NT) {
             const int i = image_at(soff, f);
-            const int R = I[ib + i].R;
+            const int R = I[perm[ib + i].img].R;
             const int k_lo = n_lo / R, k_hi = (n_hi - 1) / R;
             const int j = f - soff[i];
             if (j > k_hi - k_lo) continue;
@@ -623,6 +650,198 @@ __device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DIma
             }
         }
     }
+    __syncthreads();
+}
+
+// ---------------------------------------------------- parameter reductions
+
+__device__ inline AdjSlot adj_slot_at(const TrackArgs& ta, int gmax, int TO, int wg)
+{
+    char* b = ta.slots + (int64_t)wg * ta.slot_bytes + slot_extra_off(ta.slot_segs, gmax);
+    AdjSlot a;
+    a.dbar = (float*)b;
+    a.esum = (float*)(b + slot_al((int64_t)gmax * TO * 4));
+    a.dseg = (float4*)(b + slot_al((int64_t)gmax * TO * 4) + slot_al((int64_t)gmax * 16 * 4));
+    return a;
+}
+
+// Per-thread dL/dbeta_w partials of a work item.
+struct ParamAcc {
+    double bw[6];
+};
+
+// Knots summed per pass of the grid-point loop (a group's emission times touch a
+// few path pieces; more take further passes).
+constexpr int kKnotWin = 4;
+
+// pl (LDS): [kMaxGradKnots][3] knot sums, then [16 waves][12] reduction scratch.
+template <int NT>
+__device__ inline void param_item_begin(double* pl, ParamAcc& acc)
+{
+    for (int k = threadIdx.x; k < 3 * kMaxGradKnots; k += NT) pl[k] = 0.0;
+#pragma unroll
+    for (int w = 0; w < 6; ++w) acc.bw[w] = 0.0;
+}
+
+// Adds n values per thread (n <= 12) of the workgroup in a fixed order: each
+// wave's by a butterfly, the waves in order; thread v < n gets total v.
+template <int NT>
+__device__ inline double block_sum12(const double* v, int n, double* red, int v_out)
+{
+    constexpr int WAVES = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < n; ++k) {
+        const double s = wave_sum_d(v[k]);
+        if (lane == 0) red[wave * 12 + k] = s;
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (v_out < n)
+        for (int w = 0; w < WAVES; ++w) t += red[w * 12 + v_out];
+    __syncthreads();
+    return t;
+}
+
+// The in-tile parameter reductions of one delay group (its tracks in the slot,
+// dL/dD of its image samples over the tile [n0, n_hi) in as.dbar, the wave sums
+// of dL/dbeta_i in as.esum; lsc: the group's grid and segment offsets):
+//  1. dL/dbeta_w += (d beta_i / d beta_w) dL/dbeta_i, per image (thread-owned);
+//  2. per segment k of the tile, the Catmull-Rom basis weights at u = (n - kR)/R
+//     times dL/dD(n), summed over the segment's outputs in the tile (as.dseg);
+//  3. per grid point g, dL/dtau_g = fs * the weights of the segments that use
+//     D_g, then dtau_g / d p(t_e) for the source position at the emission time
+//     t_e = t_g - tau_g (retarded: S^T u / (c + u . S p'(t_e)), u the unit vector
+//     mic -> image; instantaneous: S^T u / c), split onto the two knots of t_e's
+//     path piece and summed into the item's knot sums in LDS (pl).
+// The tile's outputs of a segment belong to this item; the other outputs of a
+// segment that straddles the tile belong to the neighbouring item, whose row
+// holds their part.  Starts after and ends with a barrier.
+template <int NT, int TO>
+__device__ inline void param_group(const DScene& S, int mic, const DGroup& G, int n0, int n_hi, Slot sl, AdjSlot as,
+                                   const int* lsc, const DImage* __restrict__ I, const PermEntry* __restrict__ perm,
+                                   const TrackArgs& ta, const ParamArgs& pa, double* pl, ParamAcc& acc)
+{
+    const int tid = threadIdx.x;
+    const int ib = G.img_begin, cnt = G.img_end - ib;
+    const int* goff = lsc;
+    const int* soff = lsc + cnt + 1;
+    constexpr int SL = TO / 64;                 // dL/dbeta_i wave-sum slots per image
+    if (pa.want_beta)
+        for (int i = tid; i < cnt; i += NT) {
+            float e = 0.0f;
+            for (int w = 0; w < SL; ++w) e += as.esum[i * SL + w];
+            const DImage& im = I[perm[ib + i].img];
+            for (int w = 0; w < 6; ++w) {
+                const int h = im.hits[w];
+                if (h == 0) continue;
+                double dv = (double)h;
+                for (int r = 0; r < h - 1; ++r) dv *= S.beta[w];
+                for (int v = 0; v < 6; ++v) {
+                    if (v == w) continue;
+                    for (int r = 0; r < im.hits[v]; ++r) dv *= S.beta[v];
+                }
+                acc.bw[w] += dv * (double)e;
+            }
+        }
+    const bool src = pa.want_src && S.src.kind == kTrajPwl && S.src_knots > 0;
+    if (!src) return;
+    for (int f = tid; f < soff[cnt]; f += NT) {
+        const int i = off_index(soff, cnt, f);
+        const int R = I[perm[ib + i].img].R;
+        const int k_lo = n0 / R, k_hi = (n_hi - 1) / R;
+        const int j = f - soff[i];
+        if (j > k_hi - k_lo) continue;
+        const int k = k_lo + j;
+        const int na = max(k * R, n0), nb = min(k * R + R, n_hi);
+        const float* db = as.dbar + i * TO - n0;
+        const float iR = 1.0f / (float)R;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        for (int n = na; n < nb; ++n) {
+            const float d = db[n];
+            const float u = (float)(n - k * R) * iR;
+            s0 = fmaf(d, 0.5f * u * fmaf(u, 2.0f - u, -1.0f), s0);
+            s1 = fmaf(d, fmaf(u * u, fmaf(1.5f, u, -2.5f), 1.0f), s1);
+            s2 = fmaf(d, 0.5f * u * fmaf(u, fmaf(-3.0f, u, 4.0f), 1.0f), s2);
+            s3 = fmaf(d, 0.5f * u * u * (u - 1.0f), s3);
+        }
+        as.dseg[f] = make_float4(s0, s1, s2, s3);
+    }
+    __syncthreads();
+    // knots this group's emission times can touch
+    const double fs = ta.fs, c = ta.c;
+    const double t_min = ((double)(n0 - 2 * pa.rmax) - (ta.model == 0 ? (double)G.dmax + 1.0 : 0.0)) / fs;
+    const double t_max = ((double)(n_hi + 2 * pa.rmax) - (ta.model == 0 ? (double)G.dmin - 1.0 : 0.0)) / fs;
+    const int nk = S.src.n_points;
+    const int a_lo = max(0, traj_seg(S.src, ta.knots, t_min));
+    const int a_hi = min(nk - 1, max(0, traj_seg(S.src, ta.knots, t_max)) + 1);
+    double* red = pl + 3 * kMaxGradKnots;
+    for (int kb = a_lo; kb <= a_hi; kb += kKnotWin) {
+        double ak[kKnotWin * 3];
+#pragma unroll
+        for (int q = 0; q < kKnotWin * 3; ++q) ak[q] = 0.0;
+        for (int f = tid; f < goff[cnt]; f += NT) {
+            const int i = off_index(goff, cnt, f);
+            const DImage& im = I[perm[ib + i].img];
+            const int R = im.R;
+            const int k_lo = n0 / R, k_hi = (n_hi - 1) / R;
+            const int g_lo = R == 1 ? k_lo : k_lo - 1;
+            const int npts = (R == 1 ? k_hi : k_hi + 2) - g_lo + 1;
+            const int j = f - goff[i];
+            if (j >= npts) continue;
+            const int g = g_lo + j;
+            double dD = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                const int s = g + 1 - q;                 // segment s uses grid point g with basis index q
+                if (s < k_lo || s > k_hi) continue;
+                const float4 w4 = as.dseg[soff[i] + s - k_lo];
+                dD += (double)(q == 0 ? w4.x : q == 1 ? w4.y : q == 2 ? w4.z : w4.w);
+            }
+            if (dD == 0.0) continue;
+            const double taubar = fs * dD;
+            const double tk = (double)g * (double)R / fs;
+            const double te = ta.model == 0 ? tk - sl.grid[f] / fs : tk;
+            double qp[3], vp[3], r[3], lam;
+            int a;
+            pwl_eval(S.src, ta.knots, te, qp, vp, &a, &lam);
+            mic_pos(S, ta.knots, ta.mics, mic, tk, r);
+            double e[3], d2 = 0.0, sgn[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                sgn[ax] = (im.m[ax] & 1) ? -1.0 : 1.0;
+                e[ax] = image_coord(im.m[ax], S.size[ax], qp[ax]) - r[ax];
+                d2 += e[ax] * e[ax];
+            }
+            const double id = 1.0 / sqrt(d2);
+            double denom = c;
+            if (ta.model == 0)
+                for (int ax = 0; ax < 3; ++ax) denom += e[ax] * id * sgn[ax] * vp[ax];
+            const double sc = taubar * id / denom;
+            const double wa = 1.0 - lam, wb = lam;
+#pragma unroll
+            for (int jj = 0; jj < kKnotWin; ++jj) {
+                const int kk = kb + jj;
+                const double fw = (kk == a) ? wa : (kk == a + 1) ? wb : 0.0;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) ak[3 * jj + ax] += fw * (sc * sgn[ax] * e[ax]);
+            }
+        }
+        const double tot = block_sum12<NT>(ak, kKnotWin * 3, red, tid);
+        if (tid < kKnotWin * 3 && kb + tid / 3 < nk && kb + tid / 3 < kMaxGradKnots) pl[3 * kb + tid] += tot;
+        __syncthreads();
+    }
+}
+
+// Writes the item's row of parameter partials: dL/dbeta_w (summed over the
+// workgroup in a fixed order) and the knot sums.
+template <int NT>
+__device__ inline void param_item_end(const DScene& S, const WorkItem& w, double* pl, ParamAcc& acc,
+                                      const ParamArgs& pa)
+{
+    double* red = pl + 3 * kMaxGradKnots;
+    __syncthreads();
+    const double tb = block_sum12<NT>(acc.bw, 6, red, threadIdx.x);
+    double* row = pa.rows + (S.row_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_tiles + w.tile) * kRowWidth;
+    if (threadIdx.x < 6) row[threadIdx.x] = tb;
+    for (int k = threadIdx.x; k < 3 * kMaxGradKnots; k += NT) row[6 + k] = pl[k];
     __syncthreads();
 }
 

@@ -126,7 +126,7 @@ __device__ __forceinline__ float farrow_horner(const float4* vp, float s)
 // the first 10.  Ends with a barrier.
 template <int TO, int RB, bool HI>
 __device__ inline void farrow_group(const DScene& S, const DGroup& G, int n0, int T, Slot sl,
-                                    const DImage* __restrict__ I, float4* vw, const float* __restrict__ v,
+                                    const DImage* __restrict__ I, const PermEntry* __restrict__ perm, float4* vw, const float* __restrict__ v,
                                     float (&acc)[RB], int& bad)
 {
     constexpr int NT = TO / RB;
@@ -203,24 +203,24 @@ __device__ inline void farrow_group(const DScene& S, const DGroup& G, int n0, in
         int K0[RB] = {}, K1[RB] = {}, K2[RB] = {};
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
         const int e = G.img_end;
-        DImage i0 = I[G.img_begin], i1 = i0, i2 = i0;
+        DImage i0 = perm_image(I, perm, G.img_begin), i1 = i0, i2 = i0;
         fetch(i0, q0, K0, k0);
         if (G.img_begin + 1 < e) {
-            i1 = I[G.img_begin + 1];
+            i1 = perm_image(I, perm, G.img_begin + 1);
             fetch(i1, q1, K1, k1);
         }
         int ii = G.img_begin;
         for (; ii + 2 < e; ii += 3) {
-            i2 = I[ii + 2];
+            i2 = perm_image(I, perm, ii + 2);
             fetch(i2, q2, K2, k2);
             body(i0, q0, K0, k0);
             if (ii + 3 < e) {
-                i0 = I[ii + 3];
+                i0 = perm_image(I, perm, ii + 3);
                 fetch(i0, q0, K0, k0);
             }
             body(i1, q1, K1, k1);
             if (ii + 4 < e) {
-                i1 = I[ii + 4];
+                i1 = perm_image(I, perm, ii + 4);
                 fetch(i1, q1, K1, k1);
             }
             body(i2, q2, K2, k2);
@@ -241,7 +241,7 @@ __device__ inline void farrow_group(const DScene& S, const DGroup& G, int n0, in
 // dsc: kFarrowDescChunk int4 in LDS; vw: the window after it.  Ends with a barrier.
 template <int TO, bool HI>
 __device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, int T, Slot sl,
-                                     const DImage* __restrict__ I, int4* dsc, float4* vw,
+                                     const DImage* __restrict__ I, const PermEntry* __restrict__ perm, int4* dsc, float4* vw,
                                      const float* __restrict__ v, float& acc, int& bad)
 {
     const int tid = threadIdx.x;
@@ -286,9 +286,10 @@ __device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, i
         const int nc = min(kFarrowDescChunk, G.img_end - c0);
         __syncthreads();                 // window staged; the previous chunk's descriptors read
         for (int i = tid; i < nc; i += TO) {
-            const DImage& im = I[c0 + i];
+            const PermEntry e = perm[c0 + i];
+            const DImage& im = I[e.img];
             const int klo = n0 / im.R;
-            dsc[i] = make_int4(im.loc, im.R, __float_as_int(im.gfac), klo);
+            dsc[i] = make_int4(e.loc, im.R, __float_as_int(im.gfac), klo);
         }
         __syncthreads();
         if (!active) continue;
@@ -318,11 +319,8 @@ __device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, i
 // to the workgroup's slot (tile_tracks) and the group's images are added to the
 // lane's accumulators; the item's sum is written once.
 template <int TO, int RB, bool HI>
-__global__ __launch_bounds__(TO / RB) void k_farrow(const DScene* __restrict__ scenes,
-                                                     const DImage* __restrict__ imgs,
-                                                     const DGroup* __restrict__ groups, int T,
-                                                     const WorkItem* __restrict__ items, int n_items,
-                                                     int32_t* __restrict__ ticket, TrackArgs ta,
+__global__ __launch_bounds__(TO / RB) void k_farrow(PlanView pv, int T, const WorkItem* __restrict__ items,
+                                                     int n_items, int32_t* __restrict__ ticket, TrackArgs ta,
                                                      const float* __restrict__ v, float* __restrict__ part,
                                                      int32_t* __restrict__ status)
 {
@@ -331,24 +329,26 @@ __global__ __launch_bounds__(TO / RB) void k_farrow(const DScene* __restrict__ s
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     for_each_item(ticket, n_items, [&](int it) {
         const WorkItem w = items[it];
-        const DScene& S = scenes[w.scene];
-        const DImage* I = imgs + S.img_begin;
+        const DScene& S = pv.scenes[w.scene];
+        const DImage* I = pv.imgs + S.img_begin;
+        const DBlock B = pv.blocks[S.blk_begin + w.tile / S.blk_tiles];
         const int n0 = w.tile * TO;
         const int n_out = (int)S.n_out;
         const int n_hi = min(n0 + TO, n_out);
-        const int gb = sg_begin(S.n_grp, S.n_sg, w.sg), ge = sg_begin(S.n_grp, S.n_sg, w.sg + 1);
+        const int gb = sg_begin(B.n_grp, S.n_sg, w.sg), ge = sg_begin(B.n_grp, S.n_sg, w.sg + 1);
         float acc[RB];
 #pragma unroll
         for (int j = 0; j < RB; ++j) acc[j] = 0.0f;
         int bad = 0;
         for (int g = gb; g < ge; ++g) {
-            const DGroup G = groups[S.grp_begin + g];
-            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax), sl,
-                            (int*)(lds + kFarrowDescChunk), ta.knots, ta.mics, ta.c, ta.fs, ta.model);
+            const DGroup G = pv.groups[B.grp_begin + g];
+            tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax),
+                            sl, (int*)(lds + kFarrowDescChunk), ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             if constexpr (RB == 1)
-                farrow_group1<TO, HI>(S, G, n0, T, sl, I, (int4*)lds, lds + kFarrowDescChunk, v, acc[0], bad);
+                farrow_group1<TO, HI>(S, G, n0, T, sl, I, pv.perm, (int4*)lds, lds + kFarrowDescChunk, v, acc[0],
+                                      bad);
             else
-                farrow_group<TO, RB, HI>(S, G, n0, T, sl, I, lds + kFarrowDescChunk, v, acc, bad);
+                farrow_group<TO, RB, HI>(S, G, n0, T, sl, I, pv.perm, lds + kFarrowDescChunk, v, acc, bad);
         }
         float* out = part + S.part_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_out;
         const int nf = n0 + RB * (int)threadIdx.x;
@@ -359,24 +359,18 @@ __global__ __launch_bounds__(TO / RB) void k_farrow(const DScene* __restrict__ s
     });
 }
 
-__global__ void k_zero_ticket(int32_t* p)
-{
-    if (threadIdx.x == 0) p[0] = 0;
-}
-
 template <int TO, int RB>
-static hipError_t launch_farrow_t(int n_wg, int window, int taps, int hi, const DScene* d_scenes,
-                                  const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
-                                  int32_t* ticket, const TrackArgs& ta, const float* v, float* part,
-                                  int32_t* d_status, hipStream_t st)
+static hipError_t launch_farrow_t(int n_wg, int window, int taps, int hi, const PlanView& pv,
+                                  const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta,
+                                  const float* v, float* part, int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_lds_bytes(window);
     auto kern = hi ? k_farrow<TO, RB, true> : k_farrow<TO, RB, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, d_scenes, d_imgs, d_groups, taps, items,
-                       n_items, ticket, ta, v, part, d_status);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(TO / RB), lds, st, pv, taps, items, n_items, ticket, ta, v,
+                       part, d_status);
     return hipGetLastError();
 }
 
@@ -392,16 +386,14 @@ int farrow_outputs_per_lane(const int32_t* decim, int n_tiers)
     return 1;
 }
 
-hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const DScene* d_scenes,
-                         const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
-                         int32_t* ticket, const TrackArgs& ta, const float* v, float* part, int32_t* d_status,
-                         hipStream_t st)
+hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const PlanView& pv,
+                         const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
+                         float* part, int32_t* d_status, hipStream_t st)
 {
     if (n_items == 0) return hipSuccess;
     const int hi = order > 9;
 #define MSIM_CALL(TO, RB)                                                                                      \
-    launch_farrow_t<TO, RB>(n_wg, window, taps, hi, d_scenes, d_imgs, d_groups, items, n_items, ticket, ta, v, \
-                            part, d_status, st)
+    launch_farrow_t<TO, RB>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, part, d_status, st)
     if (nthreads == 1024 && rb == 4) return MSIM_CALL(1024, 4);
     if (nthreads == 1024 && rb == 2) return MSIM_CALL(1024, 2);
     if (nthreads == 1024 && rb == 1) return MSIM_CALL(1024, 1);
@@ -420,154 +412,349 @@ hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, i
 //   dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j]          (the filter bank's transpose),
 //   dL/dbeta_i = sum gy s_i(n) fs/(4 pi c D),  dL/dD = gy g (ds/dD - s/D),  ds/dD = 2 dr/ds.
 
-// Delay of image im at output n from its track: integer part and offset in [0, 1).
-__device__ inline void delay_at(const DImage& im, const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                int64_t trk, int64_t n, int* K, float* off, float* D)
+// (window: the Farrow forward's, TILE + delay spread + 9 positions)
+size_t farrow_gd_lds_bytes(int window)
 {
-    int k = (int)(((float)n + 0.5f) * im.invR);
-    k = min(max(k, 0), im.n_seg - 1);
-    const Seg sg = seg[trk + im.seg_off + k];
-    const int Ks = segK[trk + im.seg_off + k];
-    const float v = (float)(n - (int64_t)k * im.R);
-    const float d = sg.a0 + v * (sg.b1 + v * (sg.b2 + v * sg.b3));
-    const float fl = floorf(d);
-    *K = Ks + (int)fl;
-    *off = d - fl;
-    *D = (float)Ks + d;
+    return (size_t)window * kFarrowStride * sizeof(float) + kLscBytes + kParamLdsBytes;
 }
 
-// One lane per source position P of a tile [P0, P0 + NT) of the positions
-// [-T/2, n_in + T/2), one delay group, one mic.  n - floor(D_i(n)) is
-// nondecreasing in n for a subsonic image (the integer delay moves by at most
-// one per sample), so the outputs that read P form a run of at most two
-// samples (none where the integer delay steps down).  The lane reaches it by the
+size_t farrow_u_lds_bytes(int window) { return (size_t)window * sizeof(float) + kLscBytes; }
+
+// Gain and delay adjoints of one delay group, Farrow form, one output per lane of
+// the tile [n0, n0 + NT): per image sample r = sum_k v_k s^k and dr/ds by Horner's
+// rule for value and derivative; dL/dD to the slot's dbar, the wave sums of
+// dL/dbeta_i to esum.  Ends with a barrier.
+template <int TILE, bool HI>
+__device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0, int T, Slot sl, AdjSlot as,
+                                       const DImage* __restrict__ I, const PermEntry* __restrict__ perm, float4* vw,
+                                       const float* __restrict__ v, const float* __restrict__ gyc, float ghat,
+                                       int& bad)
+{
+    constexpr int NT = kAdjThreads;
+    constexpr int WAVES = NT / 64;
+    constexpr int HV = TILE / NT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ws = n0 - G.dmax - 4;
+    const int W = TILE + (G.dmax - G.dmin) + 9;
+    stage_v(S, v, T, ws, W, vw, NT);
+    __syncthreads();
+    const int n_out = (int)S.n_out;
+    for (int hv = 0; hv < HV; ++hv) {
+        const int n = n0 + hv * NT + tid;
+        const bool valid = n < n_out;
+        const int nc = valid ? n : n_out - 1;
+        const float wy = valid ? gyc[n] : 0.0f;
+        int cR = 0, cl = 0;
+        float cv = 0.0f;
+        for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+            const DImage im = perm_image(I, perm, ii);
+            if (im.R != cR) {
+                cR = im.R;
+                const int k = div_exact(nc, cR, im.invR);
+                cl = k - div_exact(n0, cR, im.invR);
+                cv = (float)(nc - k * cR);
+            }
+            const Seg sg = sl.seg[im.loc + cl];
+            const int Ks = sl.K[im.loc + cl];
+            const float dl = fmaf(cv, fmaf(cv, fmaf(cv, sg.b3, sg.b2), sg.b1), sg.a0);
+            const float fl = floorf(dl);
+            const int p = nc - (Ks + (int)fl) - ws;
+            const bool inb = p >= 0 && p < W;
+            if (valid && !inb) bad = 1;
+            float E = 0.0f, Db = 0.0f;
+            if (valid && inb && wy != 0.0f) {
+                const float s = 2.0f * (dl - fl) - 1.0f;
+                const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
+                const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+                // orders up to 9 leave the last two coefficients zero
+                constexpr int KT = HI ? kFarrowStride : 10;
+                float r = cf[KT - 1], dr = 0.0f;
+#pragma unroll
+                for (int k = KT - 2; k >= 0; --k) {
+                    dr = fmaf(dr, s, r);
+                    r = fmaf(r, s, cf[k]);
+                }
+                const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
+                E = wy * r * ghat * iD;
+                Db = wy * im.gfac * iD * fmaf(2.0f, dr, -r * iD);
+            }
+            const int li = ii - G.img_begin;
+            as.dbar[li * TILE + hv * NT + tid] = valid ? Db : 0.0f;
+            E = wave_sum_dpp(E);
+            if (lane == 0) as.esum[li * (TILE / 64) + hv * WAVES + wave] = E;
+        }
+    }
+    __syncthreads();
+}
+
+// Gain/delay adjoint and parameter partials, Farrow form, persistent over work
+// items (scene, mic, tile, supergroup): one row of parameter partials per item.
+// kAdjThreads lanes, TILE / kAdjThreads outputs per lane in turn.
+template <int TILE, bool HI>
+__global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, const WorkItem* __restrict__ items,
+                                                           int n_items, int32_t* __restrict__ ticket, TrackArgs ta,
+                                                           int window, const float* __restrict__ v,
+                                                           const float* __restrict__ gy, ParamArgs pa,
+                                                           int32_t* __restrict__ status)
+{
+    extern __shared__ float4 lds[];
+    constexpr int NT = kAdjThreads;
+    float4* vw = lds;
+    int* lsc = (int*)(lds + 3 * window);
+    double* pl = (double*)((char*)lsc + kLscBytes);
+    const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
+    const AdjSlot as = adj_slot_at(ta, pa.gmax, TILE, blockIdx.x);
+    for_each_item(ticket, n_items, [&](int it) {
+        const WorkItem w = items[it];
+        const DScene& S = pv.scenes[w.scene];
+        const DImage* I = pv.imgs + S.img_begin;
+        const DBlock B = pv.blocks[S.blk_begin + w.tile / S.blk_tiles];
+        const int n0 = w.tile * TILE;
+        const int n_out = (int)S.n_out;
+        const int n_hi = min(n0 + TILE, n_out);
+        const float* gyc = gy + S.y_off + (int64_t)w.mic * S.n_out;
+        ParamAcc acc;
+        param_item_begin<NT>(pl, acc);
+        const int gb = sg_begin(B.n_grp, S.n_sg, w.sg), ge = sg_begin(B.n_grp, S.n_sg, w.sg + 1);
+        int bad = 0;
+        for (int g = gb; g < ge; ++g) {
+            const DGroup G = pv.groups[B.grp_begin + g];
+            tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi,
+                            group_span(TILE, G.dmin, G.dmax), sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
+            farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, v, gyc, pa.ghat, bad);
+            param_group<NT, TILE>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
+        }
+        param_item_end<NT>(S, w, pl, acc, pa);
+        if (bad) atomicOr(status, kStatusWindow);
+    });
+}
+
+template <int TILE>
+static hipError_t launch_farrow_gd_t(int n_wg, int window, int taps, int hi, const PlanView& pv,
+                                     const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta,
+                                     const float* v, const float* gy, const ParamArgs& pa, int32_t* d_status,
+                                     hipStream_t st)
+{
+    const size_t lds = farrow_gd_lds_bytes(window);
+    auto kern = hi ? k_farrow_gd<TILE, true> : k_farrow_gd<TILE, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(kAdjThreads), lds, st, pv, taps, items, n_items, ticket, ta,
+                       window, v, gy, pa, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order, const PlanView& pv,
+                            const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
+                            const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st)
+{
+    if (n_items == 0) return hipSuccess;
+    const int hi = order > 9;
+    if (tile == 1024)
+        return launch_farrow_gd_t<1024>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa, d_status,
+                                        st);
+    if (tile == 512)
+        return launch_farrow_gd_t<512>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa, d_status,
+                                       st);
+    return hipErrorInvalidValue;
+}
+
+// dL/dx gather, Farrow form, persistent over items (scene, mic, position tile,
+// supergroup of whole-path delay groups).  One lane per source position P of the
+// tile [P0, P0 + NT) of the positions [-T/2, n_in + T/2).  n - floor(D_i(n)) is
+// nondecreasing in n for a subsonic image (the integer delay moves by at most one
+// per sample), so the outputs that read P form a run of at most two samples
+// (none where the integer delay steps down).  The lane reaches it by the
 // fixed-point iteration n <- P + floor(D_i(n)), a contraction with factor
-// |dD/dn| < 1 up to the floor, then tests n-2 .. n+2 and accumulates
-// u_k += gy g s^k in registers.  gy is staged in LDS.
-// upart[((mic*n_grp + g) * (n_in + T) + P + T/2) * 12 + k].
+// |dD/dn| < 1 up to the floor, then tests n-1 .. n+1 and accumulates
+// u_k += gy g s^k in registers over every group of the supergroup.  Per group the
+// tracks cover the outputs that can read the tile, and gy over them is staged in
+// LDS.  upart[S.u_base + ((mic n_sgw + sgw) (n_in + T) + P + T/2) 12 + k].
 template <int NT>
-__global__ __launch_bounds__(NT) void k_farrow_adj_u(DScene S, const DImage* __restrict__ imgs,
-                                                      const DGroup* __restrict__ groups, int T,
-                                                      const Seg* __restrict__ seg, const int32_t* __restrict__ segK,
-                                                      const float* __restrict__ gy, float* __restrict__ upart,
-                                                      int32_t* __restrict__ status)
+__global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, const WorkItem* __restrict__ items, int n_items,
+                                                  int32_t* __restrict__ ticket, TrackArgs ta, int window,
+                                                  const float* __restrict__ gy, float* __restrict__ upart,
+                                                  int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     float* gw = (float*)lds;
-    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
-    const DGroup G = groups[S.grp_begin + g];
-    const int64_t npos = S.n_in + T;
-    // sample indices fit in 32 bits (outputs and inputs are capped at 2^23 samples)
-    const int P0 = tile * NT - T / 2;
-    const int nw = P0 + G.dmin - 4;                     // output sample of gy window slot 0
-    const int W = NT + (G.dmax - G.dmin) + 9;
-    const int n_out = (int)S.n_out;
-    const float* gys = gy + S.y_off + (int64_t)mic * S.n_out;
-    for (int p = tid; p < W; p += NT) {
-        const int n = nw + p;
-        gw[p] = (n >= 0 && n < n_out) ? gys[n] : 0.0f;
-    }
-    __syncthreads();
-    const int P = P0 + tid;
-    if (P >= (int)S.n_in + T / 2) return;
-    const int64_t trk = (int64_t)mic * S.seg_per_mic;
-    const DImage* I = imgs + S.img_begin;
-    const int nlast = n_out - 1;
-    float u[kFarrowStride];
+    const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
+    for_each_item(ticket, n_items, [&](int it) {
+        const WorkItem w = items[it];
+        const DScene& S = pv.scenes[w.scene];
+        const DImage* I = pv.imgs + S.img_begin;
+        const int tid = threadIdx.x;
+        const int P0 = w.tile * NT - T / 2;
+        const int P = P0 + tid;
+        const bool act = P < (int)S.n_in + T / 2;
+        const int n_out = (int)S.n_out;
+        const int gb = sg_begin(S.n_wgrp, S.n_sgw, w.sg), ge = sg_begin(S.n_wgrp, S.n_sgw, w.sg + 1);
+        int* lsc = (int*)(gw + window);
+        float u[kFarrowStride];
 #pragma unroll
-    for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
-    int bad = 0;
-    // the images are sorted by delay: each fixed-point iteration starts from the
-    // integer delay the previous image ended with
-    int Kguess = (G.dmin + G.dmax) / 2;
-    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = I[ii];
-        // delay at output c, re-reading the track segment only when c leaves it
-        int kc = -1, Kseg = 0;
-        Seg sg{};
-        auto eval = [&](int c, int* K, float* off, float* D) {
-            const int k = min(max((int)(((float)c + 0.5f) * im.invR), 0), im.n_seg - 1);
-            if (k != kc) {
-                kc = k;
-                sg = seg[trk + im.seg_off + k];
-                Kseg = segK[trk + im.seg_off + k];
+        for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
+        int bad = 0;
+        for (int g = gb; g < ge; ++g) {
+            const DGroup G = pv.groups[S.wgrp_begin + g];
+            const int nw = P0 + G.dmin - 4;                  // output of gy window slot 0
+            const int W = NT + (G.dmax - G.dmin) + 9;
+            const int n_lo = max(0, nw), n_hi = min(n_out, nw + W);
+            if (n_lo >= n_hi) continue;
+            tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n_lo, n_hi, group_span(NT, G.dmin, G.dmax),
+                            sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
+            const float* gys = gy + S.y_off + (int64_t)w.mic * S.n_out;
+            for (int p = tid; p < W; p += NT) {
+                const int n = nw + p;
+                gw[p] = (n >= 0 && n < n_out) ? gys[n] : 0.0f;
             }
-            const float v = (float)(c - k * im.R);
-            const float d = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
-            const float fl = floorf(d);
-            *K = Kseg + (int)fl;
-            *off = d - fl;
-            *D = (float)Kseg + d;
-        };
-        auto add = [&](int c, float off, float D) {
-            const int p = c - nw;
-            if (p < 0 || p >= W) {
-                bad = 1;
-                return;
-            }
-            const float s = 2.0f * off - 1.0f;
-            float w = gw[p] * im.gfac * __builtin_amdgcn_rcpf(D);
+            __syncthreads();
+            if (act) {
+                // the images are sorted by delay: each fixed-point iteration starts
+                // from the integer delay the previous image ended with
+                int Kguess = (G.dmin + G.dmax) / 2;
+                for (int ii = G.img_begin; ii < G.img_end; ++ii) {
+                    const DImage im = perm_image(I, pv.perm, ii);
+                    const int klo = n_lo / im.R;
+                    // delay at output c (n_lo <= c < n_hi), re-reading the track
+                    // segment only when c leaves it
+                    int kc = -1, Kseg = 0;
+                    Seg sg{};
+                    auto eval = [&](int c, int* K, float* off, float* D) {
+                        const int k = div_exact(c, im.R, im.invR);
+                        if (k != kc) {
+                            kc = k;
+                            sg = sl.seg[im.loc + k - klo];
+                            Kseg = sl.K[im.loc + k - klo];
+                        }
+                        const float vv = (float)(c - k * im.R);
+                        const float d = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+                        const float fl = floorf(d);
+                        *K = Kseg + (int)fl;
+                        *off = d - fl;
+                        *D = (float)Kseg + d;
+                    };
+                    auto add = [&](int c, float off, float D) {
+                        const int p = c - nw;
+                        if (p < 0 || p >= W) {
+                            bad = 1;
+                            return;
+                        }
+                        const float s = 2.0f * off - 1.0f;
+                        float wv = gw[p] * im.gfac * __builtin_amdgcn_rcpf(D);
 #pragma unroll
-            for (int k = 0; k < kFarrowStride; ++k) {
-                u[k] += w;
-                w *= s;
+                        for (int k = 0; k < kFarrowStride; ++k) {
+                            u[k] += wv;
+                            wv *= s;
+                        }
+                    };
+                    int K;
+                    float off, D;
+                    int n = min(max(P + Kguess, n_lo), n_hi - 1);
+                    eval(n, &K, &off, &D);
+                    for (int itr = 0; itr < 16; ++itr) {
+                        const int nn = min(max(P + K, n_lo), n_hi - 1);
+                        if (nn == n) break;
+                        n = nn;
+                        eval(n, &K, &off, &D);
+                    }
+                    Kguess = K;
+                    // n - K(n) is nondecreasing with steps of 0, 1 or 2, so the
+                    // outputs reading P are n itself (when it solves the equation)
+                    // and its neighbours
+                    const bool hit = (n - K == P);
+                    const float off_n = off, D_n = D;
+                    if (n > n_lo) {
+                        eval(n - 1, &K, &off, &D);
+                        if (n - 1 - K == P) add(n - 1, off, D);
+                    }
+                    if (hit) add(n, off_n, D_n);
+                    if (n + 1 < n_hi) {
+                        eval(n + 1, &K, &off, &D);
+                        if (n + 1 - K == P) add(n + 1, off, D);
+                    }
+                }
             }
-        };
-        int K;
-        float off, D;
-        int n = min(max(P + Kguess, 0), nlast);
-        eval(n, &K, &off, &D);
-        for (int it = 0; it < 16; ++it) {
-            const int nn = min(max(P + K, 0), nlast);
-            if (nn == n) break;
-            n = nn;
-            eval(n, &K, &off, &D);
         }
-        Kguess = K;
-        // n - K(n) is nondecreasing with steps of 0, 1 or 2, so the outputs
-        // reading P are n itself (when it solves the equation) and its neighbours
-        const bool hit = (n - K == P);
-        const float off_n = off, D_n = D;
-        if (n > 0) {
-            eval(n - 1, &K, &off, &D);
-            if (n - 1 - K == P) add(n - 1, off, D);
+        if (bad) atomicOr(status, kStatusWindow);
+        if (act) {
+            const int64_t npos = S.n_in + T;
+            float4* out = (float4*)(upart + S.u_base +
+                                    (((int64_t)w.mic * S.n_sgw + w.sg) * npos + (P + T / 2)) * kFarrowStride);
+            out[0] = make_float4(u[0], u[1], u[2], u[3]);
+            out[1] = make_float4(u[4], u[5], u[6], u[7]);
+            out[2] = make_float4(u[8], u[9], u[10], u[11]);
         }
-        if (hit) add(n, off_n, D_n);
-        if (n < nlast) {
-            eval(n + 1, &K, &off, &D);
-            if (n + 1 - K == P) add(n + 1, off, D);
-        }
-    }
-    if (bad) atomicOr(status, kStatusWindow);
-    float4* out = (float4*)(upart + (((int64_t)mic * S.n_grp + g) * npos + (P + T / 2)) * kFarrowStride);
-    out[0] = make_float4(u[0], u[1], u[2], u[3]);
-    out[1] = make_float4(u[4], u[5], u[6], u[7]);
-    out[2] = make_float4(u[8], u[9], u[10], u[11]);
+    });
 }
 
-// u = sum over (mic, group) of the partials, in that order.
-__global__ __launch_bounds__(256) void k_farrow_u_reduce(DScene S, int T, const float* __restrict__ upart,
+template <int NT>
+static hipError_t launch_farrow_u_t(int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+                                    int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
+                                    int32_t* d_status, hipStream_t st)
+{
+    const size_t lds = farrow_u_lds_bytes(window);
+    hipError_t e = hipFuncSetAttribute((const void*)k_farrow_u<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
+    hipLaunchKernelGGL(k_farrow_u<NT>, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, taps, items, n_items, ticket, ta,
+                       window, gy, upart, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+                           int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
+                           int32_t* d_status, hipStream_t st)
+{
+    if (n_items == 0) return hipSuccess;
+    if (nthreads == kAdjThreads)
+        return launch_farrow_u_t<kAdjThreads>(n_wg, window, taps, pv, items, n_items, ticket, ta, gy, upart, d_status,
+                                              st);
+    return hipErrorInvalidValue;
+}
+
+// u = sum over (mic, supergroup) of the partial sums, in that order; one thread per
+// (position, k) of every scene (prefix: first position of each scene).
+__global__ __launch_bounds__(256) void k_farrow_u_reduce(PlanView pv, int n_scenes, const int64_t* __restrict__ prefix,
+                                                         int64_t total, int T, const float* __restrict__ upart,
                                                          float* __restrict__ u)
 {
-    const int64_t npos = S.n_in + T;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npos * kFarrowStride) return;
-    u[i] = strided_sum<16>(upart + i, S.n_mics * S.n_grp, npos * kFarrowStride);
+    if (i >= total * kFarrowStride) return;
+    const int64_t pos = i / kFarrowStride;
+    const int s = scene_of(prefix, n_scenes, pos);
+    const DScene& S = pv.scenes[s];
+    const int64_t npos = S.n_in + T;
+    const int64_t j = i - prefix[s] * kFarrowStride;       // (position, k) within the scene
+    u[S.v_off + j] = strided_sum<16>(upart + S.u_base + j, S.n_mics * S.n_sgw, npos * kFarrowStride);
 }
 
-// dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j], taps j = -T/2+1 .. T/2.
-__global__ __launch_bounds__(256) void k_farrow_corr(DScene S, int T, const float* __restrict__ coef,
+hipError_t launch_farrow_u_reduce(const PlanView& pv, int n_scenes, const int64_t* d_vprefix, int64_t vtotal, int taps,
+                                  const float* upart, float* u, hipStream_t st)
+{
+    const int64_t n = vtotal * kFarrowStride;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_farrow_u_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pv, n_scenes, d_vprefix,
+                       vtotal, taps, upart, u);
+    return hipGetLastError();
+}
+
+// dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j], taps j = -T/2+1 .. T/2; block (x, s):
+// inputs [256 x, 256 x + 256) of scene s0 + s.
+__global__ __launch_bounds__(256) void k_farrow_corr(PlanView pv, int s0, int T, const float* __restrict__ coef,
                                                      const float* __restrict__ u, float* __restrict__ gx)
 {
     __shared__ float c[kFarrowStride * 128];
     __shared__ float4 us[(256 + 128) * 3];
+    const DScene& S = pv.scenes[s0 + blockIdx.y];
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFarrowStride * T; i += blockDim.x) c[i] = coef[i];
     const int64_t m0 = (int64_t)blockIdx.x * 256;
+    if (m0 >= S.n_in) return;
+    for (int i = tid; i < kFarrowStride * T; i += blockDim.x) c[i] = coef[i];
     // positions m0 + j for j in [-T/2+1, 256 + T/2): stored index m + j + T/2
     const int span = 256 + T;
     const int64_t npos = S.n_in + T;
-    const float4* u4 = (const float4*)u;
+    const float4* u4 = (const float4*)(u + S.v_off);
     for (int i = tid; i < span; i += blockDim.x) {
         const int64_t q = m0 + 1 + i;                   // stored index of position m0 - T/2 + 1 + i
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, d = a;
@@ -603,171 +790,13 @@ __global__ __launch_bounds__(256) void k_farrow_corr(DScene S, int T, const floa
     gx[S.x_off + m] = acc;
 }
 
-// Gain and delay adjoints, Farrow form: per image sample r = sum_k v_k s^k and
-// dr/ds by Horner's rule for value and derivative.  Image descriptors come from
-// LDS (staged per chunk) and track data is fetched one image ahead, as in the
-// forward's one-output tile; the per-wave gain sums reduce by DPP.
-template <int NT, bool HI>
-__global__ __launch_bounds__(NT) void k_farrow_adj_track(DScene S, const DImage* __restrict__ imgs,
-                                                          const DGroup* __restrict__ groups, int T,
-                                                          const Seg* __restrict__ seg,
-                                                          const int32_t* __restrict__ segK,
-                                                          const float* __restrict__ v, const float* __restrict__ gy,
-                                                          float ghat, float* __restrict__ dbar,
-                                                          float* __restrict__ gpart, int32_t* __restrict__ status)
+hipError_t launch_farrow_corr(const PlanView& pv, int s0, int n_scenes, int64_t max_in, int taps, const float* d_coef,
+                              const float* u, float* gx, hipStream_t st)
 {
-    extern __shared__ float4 lds[];
-    int4* dsc = (int4*)lds;
-    float4* vw = lds + kFarrowDescChunk;
-    constexpr int WAVES = NT / 64;
-    const int tile = blockIdx.x, g = blockIdx.y, mic = blockIdx.z, tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const DGroup G = groups[S.grp_begin + g];
-    const int n0 = tile * NT;
-    const int ws = n0 - G.dmax - 4;
-    const int W = NT + (G.dmax - G.dmin) + 9;
-    const int plo = -T / 2, phi = (int)S.n_in + T / 2;
-    const float4* vs = (const float4*)(v + S.v_off);
-    for (int p = tid; p < W; p += NT) {
-        const int Pp = ws + p;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
-        if (Pp >= plo && Pp < phi) {
-            const float4* q = vs + (int64_t)(Pp + T / 2) * 3;
-            a = q[0];
-            b = q[1];
-            c = q[2];
-        }
-        vw[3 * p] = a;
-        vw[3 * p + 1] = b;
-        vw[3 * p + 2] = c;
-    }
-    const int n_out = (int)S.n_out;
-    const int n = n0 + tid;
-    const bool valid = n < n_out;
-    const float wy = valid ? gy[S.y_off + (int64_t)mic * S.n_out + n] : 0.0f;
-    const int nc = valid ? n : n_out - 1;
-    const Seg* sgm = seg + (int64_t)mic * S.seg_per_mic;
-    const int32_t* sgk = segK + (int64_t)mic * S.seg_per_mic;
-    const DImage* I = imgs + S.img_begin;
-    float* dout = dbar + (int64_t)mic * S.n_img * S.n_out + n;
-    const int64_t nrow = (int64_t)S.n_mics * S.n_tiles * WAVES;
-    float* gout = gpart + ((int64_t)mic * S.n_tiles + tile) * WAVES + wave;
-    int bad = 0;
-    int cR = 0, ck = 0;
-    float cv = 0.0f;
-    auto fetch = [&](int j, Seg& q, int& K, float& vv, float& gf) {
-        const int4 d = dsc[j];           // seg_off, R, gfac, n_seg
-        const int R = __builtin_amdgcn_readfirstlane(d.y);
-        if (R != cR) {
-            cR = R;
-            ck = min(nc / R, d.w - 1);
-            cv = (float)(nc - ck * R);
-        }
-        const int off = __builtin_amdgcn_readfirstlane(d.x);
-        q = sgm[off + ck];
-        K = sgk[off + ck];
-        vv = cv;
-        gf = __int_as_float(d.z);
-    };
-    auto body = [&](int ii, const Seg& sg, int Ks, float vv, float gf) {
-        const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
-        const float fl = floorf(dl);
-        const int p = nc - (Ks + (int)fl) - ws;
-        const bool inb = p >= 0 && p < W;
-        if (valid && !inb) bad = 1;
-        float E = 0.0f, Db = 0.0f;
-        if (valid && inb && wy != 0.0f) {
-            const float s = 2.0f * (dl - fl) - 1.0f;
-            const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
-            const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
-            // orders up to 9 leave the last two coefficients zero
-            constexpr int KT = HI ? kFarrowStride : 10;
-            float r = cf[KT - 1], dr = 0.0f;
-#pragma unroll
-            for (int k = KT - 2; k >= 0; --k) {
-                dr = fmaf(dr, s, r);
-                r = fmaf(r, s, cf[k]);
-            }
-            const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
-            E = wy * r * ghat * iD;
-            Db = wy * gf * iD * fmaf(2.0f, dr, -r * iD);
-        }
-        if (valid) dout[(int64_t)ii * S.n_out] = Db;
-        E = wave_sum_dpp(E);
-        if (lane == 0) gout[(int64_t)ii * nrow] = E;
-    };
-    for (int cb = G.img_begin; cb < G.img_end; cb += kFarrowDescChunk) {
-        const int nci = min(kFarrowDescChunk, G.img_end - cb);
-        __syncthreads();                 // window staged; the previous chunk's descriptors read
-        for (int i = tid; i < nci; i += NT) {
-            const DImage& im = I[cb + i];
-            dsc[i] = make_int4(im.seg_off, im.R, __float_as_int(im.gfac), im.n_seg);
-        }
-        __syncthreads();
-        // two buffers in turn: image j is processed while j+1 is in flight
-        Seg qa{}, qb{};
-        int Ka = 0, Kb = 0;
-        float va = 0.0f, vb = 0.0f, ga = 0.0f, gb = 0.0f;
-        fetch(0, qa, Ka, va, ga);
-        int j = 0;
-        for (; j + 1 < nci; j += 2) {
-            fetch(j + 1, qb, Kb, vb, gb);
-            body(cb + j, qa, Ka, va, ga);
-            if (j + 2 < nci) fetch(j + 2, qa, Ka, va, ga);
-            body(cb + j + 1, qb, Kb, vb, gb);
-        }
-        if (j < nci) body(cb + j, qa, Ka, va, ga);
-    }
-    if (bad) atomicOr(status, kStatusWindow);
-}
-
-template <int NT>
-static hipError_t launch_farrow_adj_t(const DScene& hs, int taps, int order, const DImage* d_imgs,
-                                      const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
-                                      const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
-                                      float* dbar, float* gpart, int32_t* d_status, hipStream_t st)
-{
-    if (gx) {
-        const int64_t npos = hs.n_in + taps;
-        const int ptiles = (int)((npos + NT - 1) / NT);
-        const size_t lds = (size_t)hs.window * sizeof(float);
-        auto ku = k_farrow_adj_u<NT>;
-        hipError_t e = hipFuncSetAttribute((const void*)ku, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(ku, dim3((unsigned)ptiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics), dim3(NT), lds, st, hs,
-                           d_imgs, d_groups, taps, seg, segK, gy, upart, d_status);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int64_t nu = npos * kFarrowStride;
-        hipLaunchKernelGGL(k_farrow_u_reduce, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st, hs, taps, upart, u);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_farrow_corr, dim3((unsigned)((hs.n_in + 255) / 256)), dim3(256), 0, st, hs, taps, d_coef, u,
-                           gx);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (dbar) {
-        const size_t lds = farrow_lds_bytes(hs.window);
-        auto kt = order > 9 ? k_farrow_adj_track<NT, true> : k_farrow_adj_track<NT, false>;
-        hipError_t e = hipFuncSetAttribute((const void*)kt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kt, dim3((unsigned)hs.n_tiles, (unsigned)hs.n_grp, (unsigned)hs.n_mics), dim3(NT), lds, st,
-                           hs, d_imgs, d_groups, taps, seg, segK, v, gy, ghat, dbar, gpart, d_status);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_farrow_adjoint(int nthreads, int taps, int order, const DScene& hs, const DImage* d_imgs,
-                                 const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
-                                 const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
-                                 float* dbar, float* gpart, int32_t* d_status, hipStream_t st)
-{
-    if (nthreads == 1024)
-        return launch_farrow_adj_t<1024>(hs, taps, order, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u,
-                                         gx, dbar, gpart, d_status, st);
-    if (nthreads == 512)
-        return launch_farrow_adj_t<512>(hs, taps, order, d_imgs, d_groups, seg, segK, d_coef, v, gy, ghat, upart, u,
-                                        gx, dbar, gpart, d_status, st);
-    return hipErrorInvalidValue;
+    if (max_in == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_farrow_corr, dim3((unsigned)((max_in + 255) / 256), (unsigned)n_scenes), dim3(256), 0, st,
+                       pv, s0, taps, d_coef, u, gx);
+    return hipGetLastError();
 }
 
 }  // namespace msim

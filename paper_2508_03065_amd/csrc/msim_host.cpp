@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -39,8 +41,7 @@ msim_status fail(msim_status s, const char* fmt, ...)
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxOut = int64_t(1) << 23;
-constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kMaxGroup = 512;     // images per delay group at most
+constexpr size_t kLdsLimit = 160 * 1024 - 256;   // dynamic LDS (a little is static)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -120,6 +121,43 @@ void traj_at(const msim_traj& tr, double t, double out[3])
     while (k + 2 < n && t >= tr.t[k + 1]) ++k;
     const double lam = (t - tr.t[k]) / (tr.t[k + 1] - tr.t[k]);
     for (int a = 0; a < 3; ++a) out[a] = tr.p[3 * k + a] + lam * (tr.p[3 * (k + 1) + a] - tr.p[3 * k + a]);
+}
+
+// Box of a trajectory over the times [ta, tb]: the end points and the knots in
+// between (PWL), or the arc sampled at 64 steps padded by the sagitta of a step
+// (circle; the whole circle when the arc is a full turn).
+Box traj_box_range(const msim_traj& tr, double ta, double tb)
+{
+    Box b;
+    double q[3];
+    traj_at(tr, ta, q);
+    for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = q[a];
+    auto add = [&](const double* v) {
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = std::min(b.lo[a], v[a]);
+            b.hi[a] = std::max(b.hi[a], v[a]);
+        }
+    };
+    if (tr.kind == MSIM_TRAJ_CIRCLE) {
+        const double w = tr.speed / tr.radius, span = (tb - ta) * w;
+        if (span >= 2.0 * kPi) return traj_box(tr);
+        const int steps = 64;
+        for (int k = 1; k <= steps; ++k) {
+            traj_at(tr, ta + (tb - ta) * k / steps, q);
+            add(q);
+        }
+        const double dth = span / steps, sag = tr.radius * dth * dth / 8.0 + 1e-9;
+        for (int a = 0; a < 2; ++a) {
+            b.lo[a] -= sag;
+            b.hi[a] += sag;
+        }
+        return b;
+    }
+    traj_at(tr, tb, q);
+    add(q);
+    for (int k = 0; k < tr.n_points; ++k)
+        if (tr.t[k] > ta && tr.t[k] < tb) add(tr.p + 3 * k);
+    return b;
 }
 
 msim_status check_traj(const msim_traj& tr, const double L[3], double c, const char* what)
@@ -304,9 +342,34 @@ void image_interval(int m, double L, double lo, double hi, double* out_lo, doubl
     }
 }
 
+// Delay bounds (samples) of image m for a source in box sb and mics in box mb:
+// the nearest and farthest points of the image box from the mic box.
+void image_bounds(const int m[3], const double L[3], const Box& sb, const Box& mb, double fs, double c, double* dlo,
+                  double* dhi)
+{
+    double dmin2 = 0.0, dmax2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double lo, hi;
+        image_interval(m[a], L[a], sb.lo[a], sb.hi[a], &lo, &hi);
+        const double gap = std::max(0.0, std::max(lo - mb.hi[a], mb.lo[a] - hi));
+        const double far = std::max(std::fabs(hi - mb.lo[a]), std::fabs(mb.hi[a] - lo));
+        dmin2 += gap * gap;
+        dmax2 += far * far;
+    }
+    *dlo = fs * std::sqrt(dmin2) / c;
+    *dhi = fs * std::sqrt(dmax2) / c;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- the plan
+
+// One delay block of a scene: its images sorted by the lower bound of their
+// delay over the block, with both bounds (samples).
+struct BlockOrder {
+    std::vector<int32_t> idx;
+    std::vector<float> lo, hi;
+};
 
 struct msim_plan {
     msim_params par{};
@@ -325,7 +388,36 @@ struct msim_plan {
     std::vector<int64_t> n_img;
     int64_t src_grad_total = 0;           // knots in the packed d/dsource array
     std::vector<bool> grad_ok;            // the adjoint's LDS fits this scene's windows
-    std::vector<std::vector<std::pair<double, double>>> bounds;   // per scene, per sorted image: delay bounds
+    std::vector<std::vector<std::pair<double, double>>> bounds;   // per scene, per image: delay bounds over the whole path
+    // Delay blocks: every blk_len outputs of a scene, the images sorted by a lower
+    // bound of their delay over the block (from the source's box over the
+    // emission times and the mics' box over the block), grouped per tuning.
+    int64_t blk_len = 0;
+    std::vector<std::vector<BlockOrder>> orders;   // per scene, per block
+    std::vector<DBlock> blocks;
+    std::vector<PermEntry> perm;
+    DBlock* d_blocks = nullptr;
+    PermEntry* d_perm = nullptr;
+    // whole-path delay groups (the Farrow dL/dx gather over source positions) and
+    // their items; supergroup delay bounds per block (table dL/dx windows)
+    std::vector<DGroup> wgroups;
+    std::vector<PermEntry> wperm;
+    std::vector<WorkItem> uitems, uitems_plain;
+    std::vector<int> uplain_off, uplain_cnt;
+    std::vector<int2> sgb;
+    int sgb_stride = 1, uwin = 0, rmax = 1;
+    int64_t b_rows = 0, max_rows = 0, b_xw = 0, max_xw = 0, b_upart = 0, max_upart = 0;
+    int adj_wgs = 0;
+    DGroup* d_wgroups = nullptr;
+    PermEntry* d_wperm = nullptr;
+    WorkItem* d_uitems = nullptr;
+    WorkItem* d_uitems_plain = nullptr;
+    int2* d_sgb = nullptr;
+    int64_t* d_x_prefix = nullptr;
+    // graph of the batched backward, valid for one argument set
+    hipGraphExec_t bgraph_exec = nullptr;
+    bool bgraph_valid = false;
+    const void* bgraph_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int group_cap = 0;                    // images per delay group (0: chosen from the tile count)
     // work items: every scene's (mic, tile, supergroup) in decreasing-cost order
     // (batched), and per scene (plain: scene s's items at plain_off[s])
@@ -597,7 +689,6 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     d.y_off = y_off;
     d.img_begin = (int)P->images.size();
     d.n_img = I;
-    int64_t seg = 0, runs = 0, sadj = 0;
     for (const HostImage& h : imgs) {
         DImage di{};
         for (int a = 0; a < 3; ++a) di.m[a] = (int16_t)h.m[a];
@@ -605,24 +696,14 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
         di.R = h.R;
         di.invR = 1.0f / (float)h.R;
         di.gfac = (float)(h.beta * p.fs / (4.0 * kPi * p.c));
-        di.seg_off = (int32_t)seg;
         di.n_seg = (int32_t)((s.n_out + h.R - 1) / h.R);
         for (int w = 0; w < 6; ++w) di.hits[w] = (int8_t)h.hits[w];
-        di.run_off = (int32_t)runs;
-        di.sadj_off = (int32_t)sadj;
-        seg += di.n_seg;
-        runs += (di.n_seg + track_block_segs(di.R) - 1) / track_block_segs(di.R);
-        sadj += (di.n_seg + seg_adj_block_segs(di.R) - 1) / seg_adj_block_segs(di.R);
         P->images.push_back(di);
     }
-    d.runs_per_mic = runs;
-    d.sadj_per_mic = sadj;
     for (int w = 0; w < 6; ++w) d.beta[w] = s.beta[w];
     d.src_grad_off = (int32_t)P->src_grad_total;
     d.src_knots = s.src.kind == MSIM_TRAJ_PWL ? s.src.n_points : 0;
     P->src_grad_total += d.src_knots;
-    if (seg > INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "scene %d: track too long", si);
-    d.seg_per_mic = seg;
     P->scenes.push_back(d);
     P->n_img.push_back(I);
     std::vector<std::pair<double, double>> bnd((size_t)I);
@@ -632,98 +713,159 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     return MSIM_OK;
 }
 
-// Splits every scene's delay-sorted images into groups for the current tile
-// size (threads) and group cap, sizes the LDS windows, and lays out the batched
-// path: workspace bases, prefix arrays and the cost-ordered work list.
+// Host view of a device trajectory (its knots in the plan's knot array).
+msim_traj host_traj(const msim_plan* P, const DTraj& d)
+{
+    msim_traj t{};
+    t.kind = d.kind;
+    t.n_points = d.kind == MSIM_TRAJ_PWL ? d.n_points : 0;
+    t.t = d.kind == MSIM_TRAJ_PWL ? P->knots.data() + d.knot_off : nullptr;
+    t.p = d.kind == MSIM_TRAJ_PWL ? P->knots.data() + d.pos_off : nullptr;
+    for (int a = 0; a < 3; ++a) t.center[a] = d.center[a];
+    t.radius = d.radius;
+    t.speed = d.omega * d.radius;
+    t.phase0 = d.phase0;
+    return t;
+}
+
+// Orders the images of scene si in each of its delay blocks.  The delay of an
+// image at an output of block [t0, t1) (interpolated from grid delays up to two
+// decimations outside it) lies within the bounds from the mics' box over the
+// padded block and the source's box over the emission times the image's
+// whole-path bounds allow.
+void order_blocks(msim_plan* P, int si)
+{
+    const DScene& d = P->scenes[si];
+    const msim_traj src = host_traj(P, d.src), rcv = host_traj(P, d.rcv);
+    const double fs = P->par.fs, c = P->par.c;
+    const int I = d.n_img;
+    const int nb = (int)((d.n_out + P->blk_len - 1) / P->blk_len);
+    int rmax = 1;
+    for (int i = 0; i < I; ++i) rmax = std::max(rmax, P->images[d.img_begin + i].R);
+    const double pad = 2.0 * rmax / fs + 1e-6;
+    double olo[3], ohi[3];
+    for (int a = 0; a < 3; ++a) {
+        olo[a] = 1e300;
+        ohi[a] = -1e300;
+        for (int m = 0; m < d.n_mics; ++m) {
+            olo[a] = std::min(olo[a], P->mics[3 * (d.mic_off + m) + a]);
+            ohi[a] = std::max(ohi[a], P->mics[3 * (d.mic_off + m) + a]);
+        }
+    }
+    const auto& whole = P->bounds[si];
+    std::vector<BlockOrder>& out = P->orders[si];
+    out.assign(nb, BlockOrder{});
+    std::vector<std::pair<double, int>> key(I);
+    std::vector<double> hi(I);
+    for (int b = 0; b < nb; ++b) {
+        const double t0 = (double)((int64_t)b * P->blk_len) / fs - pad;
+        const double t1 = (double)std::min<int64_t>(d.n_out, (int64_t)(b + 1) * P->blk_len) / fs + pad;
+        Box mb = traj_box_range(rcv, t0, t1);
+        for (int a = 0; a < 3; ++a) {
+            mb.lo[a] += olo[a];
+            mb.hi[a] += ohi[a];
+        }
+        for (int i = 0; i < I; ++i) {
+            const DImage& im = P->images[d.img_begin + i];
+            const Box sb = traj_box_range(src, t0 - whole[i].second / fs - 1e-6, t1 - whole[i].first / fs + 1e-6);
+            const int m[3] = {im.m[0], im.m[1], im.m[2]};
+            double lo, h;
+            image_bounds(m, d.size, sb, mb, fs, c, &lo, &h);
+            key[i] = {std::max(lo, whole[i].first), i};
+            hi[i] = std::min(h, whole[i].second);
+        }
+        std::sort(key.begin(), key.end());
+        BlockOrder& o = out[b];
+        o.idx.resize(I);
+        o.lo.resize(I);
+        o.hi.resize(I);
+        for (int j = 0; j < I; ++j) {
+            o.idx[j] = key[j].second;
+            o.lo[j] = (float)key[j].first;
+            o.hi[j] = (float)hi[key[j].second];
+        }
+    }
+}
+
+// Splits every delay block's sorted images into groups for the current tile
+// size (threads) and group cap, sizes the LDS windows and track slots, and lays
+// out the work items: supergroups, partial-output bases and the cost-ordered
+// work lists.
 msim_status regroup(msim_plan* P)
 {
     const int NT = P->threads, T = P->par.taps, L = P->par.table_phases;
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
     P->groups.clear();
+    P->blocks.clear();
+    P->perm.clear();
+    P->wgroups.clear();
+    P->wperm.clear();
+    P->uwin = 0;
     P->grad_ok.clear();
+    int slot_segs = 1, gmax = 1;
     for (int s = 0; s < P->n_scenes; ++s) {
         DScene& d = P->scenes[s];
-        const auto& bnd = P->bounds[s];
         const int I = d.n_img;
         d.n_tiles = (int)((d.n_out + NT - 1) / NT);
+        d.blk_tiles = (int)(P->blk_len / NT);
+        d.blk_begin = (int)P->blocks.size();
+        d.n_blk = (int)P->orders[s].size();
         // Group windows are sized so the adjoint's LDS (the table beside the source
         // window, or beside the per-wave windows) fits too; failing that, the forward's alone.
         bool grad_fit = true;
         auto fits = [&](int window) {
-            if (P->par.fd_kind == MSIM_FD_FARROW) return farrow_lds_bytes(window) <= kLdsLimit;
+            if (farrow) return farrow_lds_bytes(window) <= kLdsLimit;
             if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
             return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
                    adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
         };
-        int G = 1;
-        if (P->group_cap > 0) {
-            G = std::max(1, (I + P->group_cap - 1) / P->group_cap);
-        } else {
-            // enough workgroups to fill the 256 CUs several times, in nearly whole
-            // rounds; the table form also keeps groups to at most 24 images (it
-            // measured fastest at 16-40 on the paper-scale scene: smaller groups
-            // balance tiles of uneven cost), the Farrow form, whose per-group
-            // window costs three times the LDS and staging, does not.
-            const int64_t base = (int64_t)d.n_tiles * d.n_mics;
-            double best = -1.0;
-            for (int g = 1; g <= std::min(I, 128); ++g) {
-                const int64_t wgs = base * g;
-                const double rounds = std::ceil(wgs / 256.0);
-                const double eff = wgs / (rounds * 256.0) - (wgs < 3 * 256 ? 1.0 : 0.0);
-                if (eff > best + 1e-9) {
-                    best = eff;
-                    G = g;
-                }
-                if (wgs >= 16 * 256) break;
-            }
-            if (P->par.fd_kind != MSIM_FD_FARROW) G = std::max(G, (I + 23) / 24);
-        }
-        // a group's slot offsets are staged in LDS while its tracks are solved
-        G = std::max(G, (I + kMaxGroup - 1) / kMaxGroup);
-        std::vector<DGroup> gr;
         int window = 0;
-        auto split = [&](int ng) {
-            gr.clear();
-            window = 0;
-            for (int g = 0; g < ng; ++g) {
-                const int b = (int)((int64_t)I * g / ng), e = (int)((int64_t)I * (g + 1) / ng);
-                if (b == e) continue;
-                double lo = 1e300, hi = -1e300;
-                for (int i = b; i < e; ++i) {
-                    lo = std::min(lo, bnd[i].first);
-                    hi = std::max(hi, bnd[i].second);
+        for (int b = 0; b < d.n_blk; ++b) {
+            const BlockOrder& o = P->orders[s][b];
+            // the table form keeps groups to at most 24 images (16-40 measured
+            // fastest on the paper-scale scene); the Farrow form, whose 48-byte
+            // window costs more to stage, to 256
+            int G = P->group_cap > 0 ? (I + P->group_cap - 1) / P->group_cap : (I + (farrow ? 255 : 23)) / (farrow ? 256 : 24);
+            G = std::max(G, (I + kMaxGroup - 1) / kMaxGroup);
+            G = std::max(1, std::min(G, I));
+            std::vector<DGroup> gr;
+            int bw = 0;
+            auto split = [&](int ng) {
+                gr.clear();
+                bw = 0;
+                for (int g = 0; g < ng; ++g) {
+                    const int ib = (int)((int64_t)I * g / ng), ie = (int)((int64_t)I * (g + 1) / ng);
+                    if (ib == ie) continue;
+                    double lo = 1e300, hi = -1e300;
+                    for (int i = ib; i < ie; ++i) {
+                        lo = std::min(lo, (double)o.lo[i]);
+                        hi = std::max(hi, (double)o.hi[i]);
+                    }
+                    gr.push_back(DGroup{ib, ie, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4});
+                    bw = std::max(bw, NT + (gr.back().dmax - gr.back().dmin) + T + 8);
                 }
-                DGroup dg{b, e, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4};
-                gr.push_back(dg);
-                window = std::max(window, NT + (dg.dmax - dg.dmin) + T + 8);
+            };
+            for (;;) {
+                split(G);
+                if (fits(bw)) break;
+                if (G >= I) {
+                    if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                    grad_fit = false;
+                    continue;
+                }
+                G = std::min(I, G * 2);
             }
-        };
-        for (;;) {
-            split(G);
-            if (fits(window)) break;
-            if (G >= I) {
-                if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
-                grad_fit = false;
-                continue;
-            }
-            G = std::min(I, G * 2);
-        }
-        // Table form: an automatic group count is raised (by 25 % steps, to groups
-        // of at least four images and at most 1 GB of partial outputs) to the first
-        // that lets two workgroups share one CU's LDS: at one per CU the kernel is
-        // latency-bound.  When no such count exists the first is kept.  (The Farrow
-        // form restages its 48-byte window per group, which more groups cost more
-        // than its occupancy gains.)
-        if (P->group_cap == 0 && P->par.fd_kind != MSIM_FD_FARROW) {
-            auto lds_of = [&](int w) { return synth_lds_bytes(T, L, w); };
-            const int g_mem = (int)std::min<int64_t>(I, ((int64_t)1 << 30) / ((int64_t)d.n_mics * d.n_out * 4 + 1));
-            const int g_max = std::min(std::max(1, I / 4), std::max(g_mem, G));
-            if (lds_of(window) > kLdsLimit / 2 && G < g_max) {
-                const int g0 = G;
+            // Table form: an automatic group count is raised (by 25 % steps, to
+            // groups of at least four images) to the first that lets two
+            // workgroups share one CU's LDS: at one per CU the kernel is
+            // latency-bound.  When no such count exists the first is kept.
+            if (P->group_cap == 0 && !farrow && synth_lds_bytes(T, L, bw) > kLdsLimit / 2) {
+                const int g0 = G, g_max = std::max(G, I / 4);
                 bool ok = false;
                 while (G < g_max) {
                     G = std::min(g_max, G + std::max(1, G / 4));
                     split(G);
-                    if (lds_of(window) <= kLdsLimit / 2 && fits(window)) {
+                    if (synth_lds_bytes(T, L, bw) <= kLdsLimit / 2 && fits(bw)) {
                         ok = true;
                         break;
                     }
@@ -733,31 +875,84 @@ msim_status regroup(msim_plan* P)
                     split(G);
                 }
             }
-        }
-        P->grad_ok.push_back(grad_fit);
-        d.grp_begin = (int)P->groups.size();
-        d.n_grp = (int)gr.size();
-        d.window = window;
-        P->groups.insert(P->groups.end(), gr.begin(), gr.end());
-    }
-    // Track slots: the images of a group hold slot_segs_of(R, span) segments each
-    // in group order (span: the group's tile plus its delay spread), so a slot of
-    // slot_segs segments holds any group's tracks over any tile.
-    int slot_segs = 1, gmax = 1;
-    for (int s = 0; s < P->n_scenes; ++s) {
-        const DScene& d = P->scenes[s];
-        for (int g = 0; g < d.n_grp; ++g) {
-            const DGroup& G = P->groups[d.grp_begin + g];
-            const int span = group_span(NT, G.dmin, G.dmax);
-            int64_t loc = 0;
-            for (int i = G.img_begin; i < G.img_end; ++i) {
-                DImage& im = P->images[d.img_begin + i];
-                im.loc = (int32_t)loc;
-                loc += slot_segs_of(im.R, span);
+            window = std::max(window, bw);
+            P->blocks.push_back(DBlock{(int)P->groups.size(), (int)gr.size()});
+            // permutation entries with their slot offsets: slot_segs_of(R, span)
+            // segments per image, span the group's tile plus its delay spread
+            for (DGroup g : gr) {
+                const int span = group_span(NT, g.dmin, g.dmax);
+                const int base = (int)P->perm.size();
+                int64_t loc = 0;
+                for (int i = g.img_begin; i < g.img_end; ++i) {
+                    const int img = o.idx[i];
+                    P->perm.push_back(PermEntry{img, (int32_t)loc});
+                    loc += slot_segs_of(P->images[d.img_begin + img].R, span);
+                }
+                if (loc > INT32_MAX / 4)
+                    return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
+                slot_segs = std::max(slot_segs, (int)loc);
+                gmax = std::max(gmax, g.img_end - g.img_begin);
+                g.img_end = base + (g.img_end - g.img_begin);
+                g.img_begin = base;
+                P->groups.push_back(g);
             }
-            if (loc > INT32_MAX / 2) return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
-            slot_segs = std::max(slot_segs, (int)loc);
-            gmax = std::max(gmax, G.img_end - G.img_begin);
+        }
+        if (P->perm.size() > (size_t)INT32_MAX) return fail(MSIM_E_UNSUPPORTED, "too many delay-block entries");
+        P->grad_ok.push_back(grad_fit);
+        d.window = window;
+        d.dlo_all = INT32_MAX;
+        d.dhi_all = INT32_MIN;
+        for (int g = P->blocks[d.blk_begin].grp_begin; g < (int)P->groups.size(); ++g) {
+            d.dlo_all = std::min(d.dlo_all, P->groups[g].dmin);
+            d.dhi_all = std::max(d.dhi_all, P->groups[g].dmax);
+        }
+        // Farrow form: whole-path groups for the dL/dx gather over source positions
+        // (its items reach outputs across blocks), in the images' whole-path order
+        d.wgrp_begin = (int)P->wgroups.size();
+        d.n_wgrp = 0;
+        if (farrow) {
+            const auto& bnd = P->bounds[s];
+            int G = std::max((I + 255) / 256, (I + kMaxGroup - 1) / kMaxGroup);
+            for (;;) {
+                std::vector<DGroup> gr;
+                int uw = 0;
+                for (int g = 0; g < G; ++g) {
+                    const int ib = (int)((int64_t)I * g / G), ie = (int)((int64_t)I * (g + 1) / G);
+                    if (ib == ie) continue;
+                    double lo = 1e300, hi = -1e300;
+                    for (int i = ib; i < ie; ++i) {
+                        lo = std::min(lo, bnd[i].first);
+                        hi = std::max(hi, bnd[i].second);
+                    }
+                    gr.push_back(DGroup{ib, ie, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4});
+                    uw = std::max(uw, kAdjThreads + (gr.back().dmax - gr.back().dmin) + 9);
+                }
+                if (farrow_u_lds_bytes(uw) > kLdsLimit && G < I) {
+                    G = std::min(I, 2 * G);
+                    continue;
+                }
+                if (farrow_u_lds_bytes(uw) > kLdsLimit)
+                    return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                P->uwin = std::max(P->uwin, uw);
+                for (DGroup g : gr) {
+                    const int span = group_span(NT, g.dmin, g.dmax);
+                    const int base = (int)P->wperm.size();
+                    int64_t loc = 0;
+                    for (int i = g.img_begin; i < g.img_end; ++i) {
+                        P->wperm.push_back(PermEntry{i, (int32_t)loc});
+                        loc += slot_segs_of(P->images[d.img_begin + i].R, span);
+                    }
+                    if (loc > INT32_MAX / 4)
+                        return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
+                    slot_segs = std::max(slot_segs, (int)loc);
+                    gmax = std::max(gmax, g.img_end - g.img_begin);
+                    g.img_end = base + (g.img_end - g.img_begin);
+                    g.img_begin = base;
+                    P->wgroups.push_back(g);
+                }
+                d.n_wgrp = (int)gr.size();
+                break;
+            }
         }
     }
     P->slot_segs = slot_segs;
@@ -772,7 +967,9 @@ msim_status regroup(msim_plan* P)
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
         const int64_t tm = std::max<int64_t>(1, (int64_t)d.n_tiles * d.n_mics);
-        nsg[s] = (int)std::min<int64_t>(d.n_grp, std::max<int64_t>(1, (want + tm - 1) / tm));
+        int min_grp = INT32_MAX;
+        for (int b = 0; b < d.n_blk; ++b) min_grp = std::min(min_grp, P->blocks[d.blk_begin + b].n_grp);
+        nsg[s] = (int)std::min<int64_t>(min_grp, std::max<int64_t>(1, (want + tm - 1) / tm));
         total += (int64_t)d.n_mics * d.n_out * nsg[s];
     }
     const int64_t budget = (int64_t)1 << 29;
@@ -805,19 +1002,19 @@ msim_status regroup(msim_plan* P)
     for (int s = 0; s < P->n_scenes; ++s) {
         const DScene& d = P->scenes[s];
         std::vector<std::pair<double, WorkItem>> its;
-        for (int sg = 0; sg < d.n_sg; ++sg) {
-            const int gb = sg_begin(d.n_grp, d.n_sg, sg), ge = sg_begin(d.n_grp, d.n_sg, sg + 1);
-            double per_out = 0.0, stage = 0.0;
-            for (int g = gb; g < ge; ++g) {
-                const DGroup& G = P->groups[d.grp_begin + g];
-                per_out += (double)(G.img_end - G.img_begin) * T;
-                stage += 4.0 * (NT + (G.dmax - G.dmin) + T + 8);
-            }
-            for (int m = 0; m < d.n_mics; ++m)
-                for (int t = 0; t < d.n_tiles; ++t) {
-                    const int64_t len = std::min<int64_t>(NT, d.n_out - (int64_t)t * NT);
-                    its.push_back({per_out * len + stage, WorkItem{s, m, t, sg}});
+        for (int t = 0; t < d.n_tiles; ++t) {
+            const DBlock& B = P->blocks[d.blk_begin + t / d.blk_tiles];
+            const int64_t len = std::min<int64_t>(NT, d.n_out - (int64_t)t * NT);
+            for (int sg = 0; sg < d.n_sg; ++sg) {
+                const int gb = sg_begin(B.n_grp, d.n_sg, sg), ge = sg_begin(B.n_grp, d.n_sg, sg + 1);
+                double per_out = 0.0, stage = 0.0;
+                for (int g = gb; g < ge; ++g) {
+                    const DGroup& G = P->groups[B.grp_begin + g];
+                    per_out += (double)(G.img_end - G.img_begin) * T;
+                    stage += 4.0 * (NT + (G.dmax - G.dmin) + T + 8);
                 }
+                for (int m = 0; m < d.n_mics; ++m) its.push_back({per_out * len + stage, WorkItem{s, m, t, sg}});
+            }
         }
         std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         P->plain_off[s] = (int)P->items_plain.size();
@@ -834,7 +1031,110 @@ msim_status regroup(msim_plan* P)
     const int wg_threads = NT / P->rb;
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / wg_threads, kLdsLimit / lds));
     P->b_wgs = (int)std::min<int64_t>((int64_t)256 * per_cu, (int64_t)P->items.size());
+
+    // ---- backward layout
+    // supergroup delay bounds per block (the table dL/dx windows)
+    P->sgb_stride = 1;
+    for (const DScene& d : P->scenes) P->sgb_stride = std::max(P->sgb_stride, d.n_sg);
+    P->sgb.assign(P->blocks.size() * (size_t)P->sgb_stride, make_int2(0, 0));
+    P->rmax = 1;
+    for (const DImage& im : P->images) P->rmax = std::max(P->rmax, im.R);
+    int64_t rows = 0, xw = 0, up = 0;
+    P->max_rows = P->max_xw = P->max_upart = 0;
+    P->uitems.clear();
+    P->uitems_plain.clear();
+    P->uplain_off.assign(P->n_scenes, 0);
+    P->uplain_cnt.assign(P->n_scenes, 0);
+    std::vector<std::pair<double, WorkItem>> uit;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        DScene& d = P->scenes[s];
+        DScene& b = P->scenes_b[s];
+        int xs = 0;
+        for (int k = 0; k < d.n_blk; ++k) {
+            const DBlock& B = P->blocks[d.blk_begin + k];
+            for (int sg = 0; sg < d.n_sg; ++sg) {
+                const int gb = sg_begin(B.n_grp, d.n_sg, sg), ge = sg_begin(B.n_grp, d.n_sg, sg + 1);
+                int lo = INT32_MAX, hi = INT32_MIN;
+                for (int g = gb; g < ge; ++g) {
+                    lo = std::min(lo, P->groups[B.grp_begin + g].dmin);
+                    hi = std::max(hi, P->groups[B.grp_begin + g].dmax);
+                }
+                P->sgb[(size_t)(d.blk_begin + k) * P->sgb_stride + sg] = make_int2(lo, hi);
+                xs = std::max(xs, NT + (hi - lo) + T + 8);
+            }
+        }
+        d.sgb_stride = b.sgb_stride = P->sgb_stride;
+        d.xw_stride = b.xw_stride = xs;
+        const int64_t nr = (int64_t)d.n_mics * d.n_sg * d.n_tiles;
+        const int64_t nx = farrow ? 0 : nr * xs;
+        // Farrow dL/dx gather: supergroups of whole-path groups, items per position tile
+        d.n_ptiles = b.n_ptiles = (int)((d.n_in + T + kAdjThreads - 1) / kAdjThreads);
+        int nsgw = 0;
+        if (farrow) {
+            const int64_t tm = std::max<int64_t>(1, (int64_t)d.n_ptiles * d.n_mics);
+            nsgw = (int)std::min<int64_t>(d.n_wgrp, std::max<int64_t>(1, (want + tm - 1) / tm));
+            const int64_t per = (int64_t)d.n_mics * (d.n_in + T) * kFarrowStride;
+            nsgw = (int)std::max<int64_t>(1, std::min<int64_t>(nsgw, budget / std::max<int64_t>(1, per * P->n_scenes)));
+        }
+        d.n_sgw = b.n_sgw = nsgw;
+        const int64_t nu = farrow ? (int64_t)d.n_mics * nsgw * (d.n_in + T) * kFarrowStride : 0;
+        d.row_base = 0;
+        d.xw_base = 0;
+        d.u_base = 0;
+        b.row_base = rows;
+        b.xw_base = xw;
+        b.u_base = up;
+        rows += nr;
+        xw += nx;
+        up += nu;
+        P->max_rows = std::max(P->max_rows, nr);
+        P->max_xw = std::max(P->max_xw, nx);
+        P->max_upart = std::max(P->max_upart, nu);
+        if (farrow) {
+            std::vector<std::pair<double, WorkItem>> its;
+            for (int sg = 0; sg < nsgw; ++sg) {
+                const int gb = sg_begin(d.n_wgrp, nsgw, sg), ge = sg_begin(d.n_wgrp, nsgw, sg + 1);
+                double cost = 0.0;
+                for (int g = gb; g < ge; ++g) {
+                    const DGroup& G = P->wgroups[d.wgrp_begin + g];
+                    cost += (double)(G.img_end - G.img_begin) * kAdjThreads + 4.0 * (kAdjThreads + G.dmax - G.dmin);
+                }
+                for (int m = 0; m < d.n_mics; ++m)
+                    for (int t = 0; t < d.n_ptiles; ++t) its.push_back({cost, WorkItem{s, m, t, sg}});
+            }
+            std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+            P->uplain_off[s] = (int)P->uitems_plain.size();
+            P->uplain_cnt[s] = (int)its.size();
+            for (const auto& e : its) P->uitems_plain.push_back(e.second);
+            uit.insert(uit.end(), its.begin(), its.end());
+        }
+        b.dlo_all = d.dlo_all;
+        b.dhi_all = d.dhi_all;
+        b.wgrp_begin = d.wgrp_begin;
+        b.n_wgrp = d.n_wgrp;
+    }
+    std::stable_sort(uit.begin(), uit.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+    for (const auto& e : uit) P->uitems.push_back(e.second);
+    P->b_rows = rows;
+    P->b_xw = xw;
+    P->b_upart = up;
+    // persistent grid of the backward kernels: the largest any of them runs
+    {
+        auto grid = [&](size_t l, int threads) {
+            return 256 * (int)std::max<size_t>(1, std::min<size_t>(2048 / threads, kLdsLimit / std::max<size_t>(1, l)));
+        };
+        int g = 1;
+        if (farrow) {
+            g = std::max(g, grid(farrow_gd_lds_bytes(wmax), kAdjThreads));
+            g = std::max(g, grid(farrow_u_lds_bytes(std::max(1, P->uwin)), kAdjThreads));
+        } else {
+            g = std::max(g, grid(adj_x_lds_bytes(T, L, wmax, NT), kAdjThreads));
+            g = std::max(g, grid(adj_track_lds_bytes(T, L, wmax), P->rb == 1 ? kAdjThreads : NT / 2));
+        }
+        P->adj_wgs = g;
+    }
     P->graph_valid = false;
+    P->bgraph_valid = false;
     return MSIM_OK;
 }
 
@@ -846,6 +1146,19 @@ void free_layout(msim_plan* P)
     (void)hipFree(P->d_y_prefix);
     (void)hipFree(P->d_items);
     (void)hipFree(P->d_items_plain);
+    (void)hipFree(P->d_blocks);
+    (void)hipFree(P->d_perm);
+    (void)hipFree(P->d_wgroups);
+    (void)hipFree(P->d_wperm);
+    (void)hipFree(P->d_uitems);
+    (void)hipFree(P->d_uitems_plain);
+    (void)hipFree(P->d_sgb);
+    P->d_blocks = nullptr;
+    P->d_perm = nullptr;
+    P->d_wgroups = nullptr;
+    P->d_wperm = nullptr;
+    P->d_uitems = P->d_uitems_plain = nullptr;
+    P->d_sgb = nullptr;
     P->d_scenes = nullptr;
     P->d_groups = nullptr;
     P->d_scenes_b = nullptr;
@@ -862,11 +1175,20 @@ msim_status upload_layout(msim_plan* P)
     if ((st = upload(&P->d_scenes, P->scenes)) != MSIM_OK || (st = upload(&P->d_groups, P->groups)) != MSIM_OK ||
         (st = upload(&P->d_scenes_b, P->scenes_b)) != MSIM_OK ||
         (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK ||
-        (st = upload(&P->d_items_plain, P->items_plain)) != MSIM_OK)
+        (st = upload(&P->d_items_plain, P->items_plain)) != MSIM_OK ||
+        (st = upload(&P->d_blocks, P->blocks)) != MSIM_OK || (st = upload(&P->d_perm, P->perm)) != MSIM_OK ||
+        (st = upload(&P->d_wgroups, P->wgroups)) != MSIM_OK || (st = upload(&P->d_wperm, P->wperm)) != MSIM_OK ||
+        (st = upload(&P->d_uitems, P->uitems)) != MSIM_OK ||
+        (st = upload(&P->d_uitems_plain, P->uitems_plain)) != MSIM_OK || (st = upload(&P->d_sgb, P->sgb)) != MSIM_OK)
         return st;
     if (P->d_images)
         HIP_OK(hipMemcpy(P->d_images, P->images.data(), P->images.size() * sizeof(DImage), hipMemcpyHostToDevice));
     return MSIM_OK;
+}
+
+PlanView plan_view(const msim_plan* P, const DScene* scenes)
+{
+    return PlanView{scenes, P->d_images, P->d_blocks, P->d_groups, P->d_perm};
 }
 
 // Bytes of one workgroup's track slot for the forward.
@@ -886,79 +1208,10 @@ TrackArgs track_args(const msim_plan* P, char* slots, int64_t slot_bytes)
     return ta;
 }
 
-// Forward scratch of one scene, carved from the caller's workspace.
-struct FwdWs {
-    double* grid;     // exact delays on each image's grid, per mic
-    Seg* seg;         // per-segment cubic offsets
-    int32_t* segK;    // per-segment integer base
-    float* part;      // per-group partial outputs [mic][group][n_out]
-};
-
-size_t carve_fwd(const DScene& d, char* base, FwdWs* w, bool with_grid = false)
-{
-    const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
-    const size_t grid = with_grid ? ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics : 0;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char* p = base ? base + off : nullptr;
-        off += align_up(bytes);
-        return p;
-    };
-    char* g = take(grid * sizeof(double));
-    char* s = take(segs * sizeof(Seg));
-    char* k = take(segs * sizeof(int32_t));
-    char* p = take((size_t)d.n_mics * d.n_grp * d.n_out * sizeof(float));
-    if (w) {
-        w->grid = (double*)g;
-        w->seg = (Seg*)s;
-        w->segK = (int32_t*)k;
-        w->part = (float*)p;
-    }
-    return off;
-}
-
-size_t fwd_ws_bytes(const msim_plan*, const DScene& d) { return carve_fwd(d, nullptr, nullptr); }
-
 // Farrow-filtered source signals of every scene, ahead of the per-scene scratch.
 size_t farrow_v_bytes(const msim_plan* P)
 {
     return P->par.fd_kind == MSIM_FD_FARROW ? align_up((size_t)P->vpos_total * kFarrowStride * sizeof(float)) : 0;
-}
-
-// Adjoint scratch of one scene, after the forward's (whose tracks it reuses).
-size_t carve_adj(const msim_plan* P, const DScene& d, char* base, FwdWs* fw, AdjBufs* aw, double** partial)
-{
-    size_t off = carve_fwd(d, base, fw, true);
-    auto take = [&](size_t bytes) {
-        char* p = base ? base + off : nullptr;
-        off += align_up(bytes);
-        return p;
-    };
-    const size_t segs = (size_t)d.seg_per_mic * d.n_mics;
-    const size_t gpts = ((size_t)d.seg_per_mic + 3 * (size_t)d.n_img) * d.n_mics;
-    const size_t waves = (size_t)P->threads / 64;
-    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
-    const size_t npos = (size_t)(d.n_in + P->par.taps);
-    char* xp = take(farrow ? (size_t)d.n_mics * d.n_grp * npos * kFarrowStride * sizeof(float)
-                           : (size_t)d.n_mics * d.n_grp * d.n_tiles * d.window * sizeof(float));
-    char* uu = take(farrow ? npos * kFarrowStride * sizeof(float) : 0);
-    char* db = take((size_t)d.n_mics * d.n_img * d.n_out * sizeof(float));
-    char* gp = take((size_t)d.n_mics * d.n_tiles * waves * d.n_img * sizeof(float));
-    char* ds = take(segs * sizeof(float4));
-    char* pc = take(gpts * sizeof(double4));
-    char* pa = take(gpts * sizeof(int32_t));
-    char* pr = take(reduce_partial_bytes(d));
-    if (aw) {
-        aw->xpart = (float*)xp;
-        aw->u = (float*)uu;
-        aw->dbar = (float*)db;
-        aw->gpart = (float*)gp;
-        aw->dseg = (float4*)ds;
-        aw->pgc = (double4*)pc;
-        aw->pga = (int32_t*)pa;
-    }
-    if (partial) *partial = (double*)pr;
-    return off;
 }
 
 // Forward workspace: the Farrow-filtered sources (Farrow form), one track slot
@@ -1006,14 +1259,13 @@ msim_status enqueue_forward(msim_plan* P, const float* x, float* y, const FwdWs2
     }
     auto run = [&](const DScene* scenes, const WorkItem* items, int n_items, int n_wg) -> msim_status {
         LaunchTimer t(P, kKindSynth, st);
+        const PlanView pv = plan_view(P, scenes);
         if (farrow)
-            HIP_OK(launch_farrow(P->threads, P->rb, n_wg, P->b_window, P->par.taps, P->par.farrow_order, scenes,
-                                 P->d_images, P->d_groups, items, n_items, w.ticket, ta, w.v, w.part, P->d_status,
-                                 st));
+            HIP_OK(launch_farrow(P->threads, P->rb, n_wg, P->b_window, P->par.taps, P->par.farrow_order, pv, items,
+                                 n_items, w.ticket, ta, w.v, w.part, P->d_status, st));
         else
-            HIP_OK(launch_synth(P->par.taps, P->threads, P->rb, n_wg, P->b_window, scenes, P->d_images,
-                                P->d_groups, P->d_qtable, P->par.table_phases, items, n_items, w.ticket, ta, x,
-                                w.part, P->d_status, st));
+            HIP_OK(launch_synth(P->par.taps, P->threads, P->rb, n_wg, P->b_window, pv, P->d_qtable,
+                                P->par.table_phases, items, n_items, w.ticket, ta, x, w.part, P->d_status, st));
         return MSIM_OK;
     };
     msim_status s;
@@ -1030,6 +1282,141 @@ msim_status enqueue_forward(msim_plan* P, const float* x, float* y, const FwdWs2
         const DScene& d = P->scenes[sc];
         LaunchTimer t(P, kKindReduce, st);
         HIP_OK(launch_reduce_sg(P->d_scenes + sc, 1, P->d_zero, (int64_t)d.n_mics * d.n_out, w.part, y, st));
+    }
+    return MSIM_OK;
+}
+
+// Backward workspace: the Farrow-filtered sources and the gathered sums u
+// (Farrow form), one adjoint slot per persistent workgroup, the dL/dx windows
+// (table form) or the partial sums u (Farrow form), the rows of parameter
+// partials, and the ticket counter; all scenes' (batched) or the largest scene's
+// (plain).
+struct BwdWs {
+    float* v;
+    float* u;
+    char* slots;
+    float* xwin;
+    float* upart;
+    double* rows;
+    int32_t* ticket;
+};
+
+int64_t adj_slot_size(const msim_plan* P) { return adj_slot_bytes(P->slot_segs, P->gmax, P->threads); }
+
+size_t carve_bwd_ws(const msim_plan* P, bool batched, char* base, BwdWs* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    char* v = take(farrow_v_bytes(P));
+    char* u = take(farrow_v_bytes(P));
+    char* sl = take((size_t)P->adj_wgs * (size_t)adj_slot_size(P));
+    char* xw = take((size_t)(batched ? P->b_xw : P->max_xw) * sizeof(float));
+    char* up = take((size_t)(batched ? P->b_upart : P->max_upart) * sizeof(float));
+    char* r = take((size_t)(batched ? P->b_rows : P->max_rows) * kRowWidth * sizeof(double));
+    char* t = take(sizeof(int32_t));
+    if (w) {
+        w->v = (float*)v;
+        w->u = (float*)u;
+        w->slots = sl;
+        w->xwin = (float*)xw;
+        w->upart = (float*)up;
+        w->rows = (double*)r;
+        w->ticket = (int32_t*)t;
+    }
+    return off;
+}
+
+msim_status check_backward(msim_plan* P, const float* x, const float* gy, double* gsrc)
+{
+    if (!P || !x || !gy) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    for (int s = 0; s < P->n_scenes; ++s) {
+        if (!P->grad_ok[s]) return fail(MSIM_E_UNSUPPORTED, "scene %d: adjoint LDS does not fit its delay groups", s);
+        if (gsrc && P->scenes[s].src_knots > max_grad_knots())
+            return fail(MSIM_E_UNSUPPORTED, "scene %d: more than %d source knots", s, max_grad_knots());
+    }
+    return MSIM_OK;
+}
+
+// The backward's launches, over every scene at once (batched) or scene by scene
+// (plain): dL/dx (table: the transpose delay into windows, then their gather;
+// Farrow: the gathered sums u, their reduction and the transposed filter bank),
+// then the gain/delay adjoint with the in-tile parameter reductions and the
+// reduction of the rows.
+msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, float* gx, double* gbeta, double* gsrc,
+                             const BwdWs& w, bool batched, hipStream_t st)
+{
+    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    const int T = P->par.taps, L = P->par.table_phases, NT = P->threads;
+    const TrackArgs ta = track_args(P, w.slots, adj_slot_size(P));
+    ParamArgs pa;
+    pa.rows = w.rows;
+    pa.gmax = P->gmax;
+    pa.rmax = P->rmax;
+    pa.ghat = (float)(P->par.fs / (4.0 * kPi * P->par.c));
+    pa.want_beta = gbeta != nullptr;
+    pa.want_src = gsrc != nullptr;
+    const bool want_p = gbeta || gsrc;
+    if (farrow && want_p) {
+        LaunchTimer t(P, kKindFilter, st);
+        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, T, P->d_fcoef, x, w.v,
+                                  st));
+    }
+    const int ns = batched ? 1 : P->n_scenes;
+    for (int k = 0; k < ns; ++k) {
+        const DScene* scenes = batched ? P->d_scenes_b : P->d_scenes + k;
+        const PlanView pv = plan_view(P, batched ? P->d_scenes_b : P->d_scenes);
+        const int nsc = batched ? P->n_scenes : 1;
+        const int64_t* xpre = batched ? P->d_x_prefix : P->d_zero;
+        const int64_t xtot = batched ? P->x_total : P->scenes[k].n_in;
+        PlanView one = pv;
+        one.scenes = scenes;
+        if (gx) {
+            LaunchTimer t(P, kKindAdjoint, st);
+            if (farrow) {
+                PlanView wv = pv;
+                wv.groups = P->d_wgroups;
+                wv.perm = P->d_wperm;
+                const WorkItem* it = batched ? P->d_uitems : P->d_uitems_plain + P->uplain_off[k];
+                const int n = batched ? (int)P->uitems.size() : P->uplain_cnt[k];
+                HIP_OK(launch_farrow_u(kAdjThreads, std::min(n, P->adj_wgs), P->uwin, T, wv, it, n, w.ticket, ta, gy,
+                                       w.upart, P->d_status, st));
+                const int64_t vtot = batched ? P->vpos_total : P->scenes[k].n_in + T;
+                HIP_OK(launch_farrow_u_reduce(one, nsc, batched ? P->d_vpos_prefix : P->d_zero, vtot, T, w.upart,
+                                              w.u, st));
+                int64_t max_in = 0;
+                for (int s = 0; s < P->n_scenes; ++s)
+                    if (batched || s == k) max_in = std::max(max_in, P->scenes[s].n_in);
+                HIP_OK(launch_farrow_corr(pv, batched ? 0 : k, nsc, max_in, T, P->d_fcoef, w.u, gx, st));
+            } else {
+                const WorkItem* it = batched ? P->d_items : P->d_items_plain + P->plain_off[k];
+                const int n = batched ? (int)P->items.size() : P->plain_cnt[k];
+                HIP_OK(launch_adjx(T, NT, std::min(n, P->adj_wgs), P->b_window, pv, P->d_atable, L, it, n, w.ticket,
+                                   ta, gy, w.xwin, P->d_status, st));
+                HIP_OK(launch_reduce_x(one, nsc, xpre, xtot, NT, T, P->d_sgb, w.xwin, gx, st));
+            }
+        }
+        if (want_p) {
+            const WorkItem* it = batched ? P->d_items : P->d_items_plain + P->plain_off[k];
+            const int n = batched ? (int)P->items.size() : P->plain_cnt[k];
+            {
+                LaunchTimer t(P, kKindAdjoint, st);
+                if (farrow)
+                    HIP_OK(launch_farrow_gd(NT, std::min(n, P->adj_wgs), P->b_window, T, P->par.farrow_order, pv, it, n,
+                                            w.ticket, ta, w.v, gy, pa, P->d_status, st));
+                else
+                    HIP_OK(launch_adjp(T, NT, P->rb, std::min(n, P->adj_wgs), P->b_window, pv, P->d_qtable, L, it, n,
+                                       w.ticket, ta, x, gy, pa, P->d_status, st));
+            }
+            LaunchTimer t(P, kKindParams, st);
+            HIP_OK(launch_reduce_rows(one, nsc, batched ? 0 : k, w.rows, gbeta, gsrc, st));
+        }
     }
     return MSIM_OK;
 }
@@ -1124,6 +1511,19 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     }
     P->x_total = xo;
     P->y_total = yo;
+    // delay blocks of about a quarter second, a whole number of 1024-output tiles
+    P->blk_len = std::max<int64_t>(1024, (int64_t)std::llround(0.25 * p->fs / 1024.0) * 1024);
+    P->orders.assign(n_scenes, {});
+    {
+        const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        std::atomic<int> next{0};
+        for (unsigned k = 0; k < hw; ++k)
+            pool.emplace_back([&] {
+                for (int s = next++; s < n_scenes; s = next++) order_blocks(P, s);
+            });
+        for (auto& th : pool) th.join();
+    }
     // Farrow-filtered source positions [-T/2, n_in + T/2) of every scene, packed
     int64_t vo = 0;
     P->vpos_prefix.assign(n_scenes, 0);
@@ -1146,10 +1546,13 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     std::vector<float4> qtab4((P->qtable.size() + 15) / 16);
     std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size());
     std::vector<int32_t> zero(1, 0);
+    std::vector<int64_t> x_prefix(n_scenes);
+    for (int sc = 0; sc < n_scenes; ++sc) x_prefix[sc] = P->scenes[sc].x_off;
     if ((st = upload(&P->d_fcoef, P->fcoef)) != MSIM_OK || (st = upload(&P->d_vpos_prefix, P->vpos_prefix)) != MSIM_OK ||
         (st = upload(&P->d_images, P->images)) != MSIM_OK ||
         (st = upload(&P->d_knots, P->knots)) != MSIM_OK || (st = upload(&P->d_mics, P->mics)) != MSIM_OK ||
         (st = upload(&P->d_status, zero)) != MSIM_OK || (st = upload(&P->d_zero, std::vector<int64_t>(1, 0))) != MSIM_OK ||
+        (st = upload(&P->d_x_prefix, x_prefix)) != MSIM_OK ||
         (st = upload(&P->d_qtable, qtab4)) != MSIM_OK || (st = upload(&P->d_atable, P->atable)) != MSIM_OK ||
         (st = upload_layout(P)) != MSIM_OK) {
         msim_plan_destroy(P);
@@ -1179,6 +1582,8 @@ msim_status msim_plan_destroy(msim_plan* P)
     (void)hipFree(P->d_vpos_prefix);
     (void)hipFree(P->d_status);
     (void)hipFree(P->d_zero);
+    (void)hipFree(P->d_x_prefix);
+    if (P->bgraph_exec) (void)hipGraphExecDestroy(P->bgraph_exec);
     delete P;
     return MSIM_OK;
 }
@@ -1211,9 +1616,7 @@ msim_status msim_workspace_size(const msim_plan* P, int32_t with_grad, size_t* b
         *bytes = carve_fwd_ws(P, false, nullptr, nullptr);
         return MSIM_OK;
     }
-    size_t m = 0;
-    for (const DScene& d : P->scenes) m = std::max(m, carve_adj(P, d, nullptr, nullptr, nullptr, nullptr));
-    *bytes = m + farrow_v_bytes(P);
+    *bytes = carve_bwd_ws(P, false, nullptr, nullptr);
     return MSIM_OK;
 }
 
@@ -1229,84 +1632,14 @@ msim_status msim_plan_grad_layout(const msim_plan* P, int64_t* src_off, int64_t*
 msim_status msim_backward(msim_plan* P, const float* x, const float* gy, float* gx, double* gbeta, double* gsrc,
                           void* ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (!P || !x || !gy) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    size_t need = 0;
-    msim_workspace_size(P, 1, &need);
+    msim_status st = check_backward(P, x, gy, gsrc);
+    if (st != MSIM_OK) return st;
+    const size_t need = carve_bwd_ws(P, false, nullptr, nullptr);
     if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
         return fail(MSIM_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned", need);
-    int dev = -1;
-    HIP_OK(hipGetDevice(&dev));
-    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
-    for (int s = 0; s < P->n_scenes; ++s) {
-        if (!P->grad_ok[s]) return fail(MSIM_E_UNSUPPORTED, "scene %d: adjoint LDS does not fit its delay groups", s);
-        if (gsrc && P->scenes[s].src_knots > max_grad_knots())
-            return fail(MSIM_E_UNSUPPORTED, "scene %d: more than %d source knots", s, max_grad_knots());
-    }
-    const int T = P->par.taps, L = P->par.table_phases;
-    const float ghat = (float)(P->par.fs / (4.0 * kPi * P->par.c));
-    const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
-    float* v = (float*)ws;                       // Farrow-filtered sources, all scenes
-    char* scratch = (char*)ws + farrow_v_bytes(P);
-    if (farrow && (gbeta || gsrc)) {
-        LaunchTimer t(P, kKindFilter, stream);
-        HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, T, P->d_fcoef, x, v,
-                                  stream));
-    }
-    for (int s = 0; s < P->n_scenes; ++s) {
-        const DScene& d = P->scenes[s];
-        FwdWs fw;
-        AdjBufs aw;
-        double* partial = nullptr;
-        carve_adj(P, d, scratch, &fw, &aw, &partial);
-        {
-            LaunchTimer t(P, kKindTracks, stream);
-            HIP_OK(launch_tracks(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, fw.seg, fw.segK,
-                                 P->par.c, P->par.fs, P->par.delay_model, stream));
-        }
-        const bool want_src = gsrc && d.src_knots > 0;
-        if (farrow) {
-            {
-                LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_farrow_adjoint(P->threads, T, P->par.farrow_order, d, P->d_images, P->d_groups, fw.seg, fw.segK, P->d_fcoef,
-                                             v, gy, ghat, aw.xpart, aw.u, gx, (gbeta || want_src) ? aw.dbar : nullptr,
-                                             aw.gpart, P->d_status, stream));
-            }
-            if (gbeta || want_src) {
-                LaunchTimer t(P, kKindParams, stream);
-                if (want_src)
-                    HIP_OK(launch_adj_params(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, aw.dbar,
-                                             aw.dseg, aw.pgc, aw.pga, P->par.c, P->par.fs, P->par.delay_model, 1,
-                                             stream));
-                HIP_OK(launch_reduce_params(P->d_scenes, s, d, P->d_images, aw.gpart, d.n_tiles * (P->threads / 64),
-                                            aw.pgc, aw.pga, partial, gbeta, want_src ? gsrc : nullptr, stream));
-            }
-            continue;
-        }
-        if (gx) {
-            {
-                LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_adj_x(T, P->threads, d, P->d_images, P->d_groups, P->d_atable, L, fw.seg,
-                                    fw.segK, gy, aw.xpart, P->d_status, stream));
-            }
-            LaunchTimer t(P, kKindReduce, stream);
-            HIP_OK(launch_reduce_x(d, P->d_groups, P->threads, T, aw.xpart, gx, stream));
-        }
-        if (gbeta || want_src) {
-            {
-                LaunchTimer t(P, kKindAdjoint, stream);
-                HIP_OK(launch_adj_track(T, P->threads, P->rb, d, P->d_images, P->d_groups, P->d_qtable, L, fw.seg, fw.segK,
-                                        x, gy, ghat, aw.dbar, aw.gpart, P->d_status, stream));
-            }
-            LaunchTimer t(P, kKindParams, stream);
-            if (want_src)
-                HIP_OK(launch_adj_params(P->d_scenes, s, d, P->d_images, P->d_knots, P->d_mics, fw.grid, aw.dbar,
-                                         aw.dseg, aw.pgc, aw.pga, P->par.c, P->par.fs, P->par.delay_model, 1,
-                                         stream));
-            HIP_OK(launch_reduce_params(P->d_scenes, s, d, P->d_images, aw.gpart, d.n_tiles * (P->threads / 64),
-                                        aw.pgc, aw.pga, partial, gbeta, want_src ? gsrc : nullptr, stream));
-        }
-    }
-    return MSIM_OK;
+    BwdWs w;
+    carve_bwd_ws(P, false, (char*)ws, &w);
+    return enqueue_backward(P, x, gy, gx, gbeta, gsrc, w, false, stream);
 }
 
 msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream)
@@ -1424,7 +1757,7 @@ extern "C" {
 msim_status msim_batched_workspace_size(const msim_plan* P, size_t* bytes)
 {
     if (!P || !bytes) return fail(MSIM_E_INVALID_ARG, "NULL argument");
-    *bytes = carve_fwd_ws(P, true, nullptr, nullptr);
+    *bytes = std::max(carve_fwd_ws(P, true, nullptr, nullptr), carve_bwd_ws(P, true, nullptr, nullptr));
     return MSIM_OK;
 }
 
@@ -1464,6 +1797,48 @@ msim_status msim_forward_batched(msim_plan* P, const float* x, float* y, void* w
     }
     LaunchTimer t(P, kKindGraph, stream);
     HIP_OK(hipGraphLaunch(P->graph_exec, stream));
+    return MSIM_OK;
+}
+
+msim_status msim_backward_batched(msim_plan* P, const float* x, const float* gy, float* gx, double* gbeta,
+                                  double* gsrc, void* ws, size_t ws_bytes, hipStream_t stream, int32_t use_graph)
+{
+    msim_status st = check_backward(P, x, gy, gsrc);
+    if (st != MSIM_OK) return st;
+    const size_t need = carve_bwd_ws(P, true, nullptr, nullptr);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
+        return fail(MSIM_E_WORKSPACE, "batched workspace needs %zu bytes, 256-byte aligned", need);
+    BwdWs w;
+    carve_bwd_ws(P, true, (char*)ws, &w);
+    if (!use_graph) return enqueue_backward(P, x, gy, gx, gbeta, gsrc, w, true, stream);
+    const void* key[6] = {x, gy, gx, gbeta, gsrc, ws};
+    if (!P->bgraph_valid || std::memcmp(key, P->bgraph_key, sizeof key) != 0) {
+        if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        if (P->bgraph_exec) {
+            HIP_OK(hipGraphExecDestroy(P->bgraph_exec));
+            P->bgraph_exec = nullptr;
+        }
+        P->bgraph_valid = false;
+        const bool prof = P->profiling;
+        P->profiling = false;
+        HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+        st = enqueue_backward(P, x, gy, gx, gbeta, gsrc, w, true, P->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+        P->profiling = prof;
+        if (st != MSIM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(MSIM_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&P->bgraph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(MSIM_E_HIP, "graph instantiate: %s", hipGetErrorString(e2));
+        std::memcpy(P->bgraph_key, key, sizeof key);
+        P->bgraph_valid = true;
+    }
+    LaunchTimer t(P, kKindGraph, stream);
+    HIP_OK(hipGraphLaunch(P->bgraph_exec, stream));
     return MSIM_OK;
 }
 

@@ -38,20 +38,28 @@ struct DScene {
     int32_t n_img;
     int32_t grp_begin;    // this scene's delay groups
     int32_t n_grp;
-    int32_t n_sg;         // supergroups per mic: contiguous runs of delay groups, one work item each
-    int32_t pad_sg;
-    int64_t seg_per_mic;  // track segments of one mic (sum over images)
-    int64_t runs_per_mic; // track-kernel blocks of one mic
-    int64_t sadj_per_mic; // Catmull-Rom-transpose blocks of one mic
+    int32_t n_sg;         // supergroups per mic and block: contiguous runs of a block's delay groups
+    int32_t blk_begin;    // this scene's delay blocks in the plan's block table
+    int32_t n_blk;
+    int32_t blk_tiles;    // output tiles per delay block
     int32_t n_tiles;
     int32_t window;       // LDS source window (positions) the plan sized for this scene
     double beta[6];       // wall coefficients (for d/dbeta)
     int32_t src_grad_off; // this scene's first knot in the packed d/dsource array
     int32_t src_knots;    // source knots with a gradient (PWL sources; 0 for circles)
     int64_t v_off;        // this scene's Farrow-filtered source v_k in the workspace (floats)
-    int64_t grid_base;    // offsets of this scene's delay grid, track segments and partial
-    int64_t trk_base;     //   outputs in the workspace (0 when scenes run one at a time)
-    int64_t part_base;
+    int64_t part_base;    // this scene's partial outputs [mic][sg][n_out] in the workspace
+    int64_t xw_base;      // its dL/dx windows [mic][sg][tile][xw_stride] (table form)
+    int64_t row_base;     // its first row of parameter partials ([mic][sg][tile])
+    int64_t u_base;       // its Farrow dL/dx sums [mic][sgw][position][12]
+    int32_t xw_stride;    // floats per dL/dx window
+    int32_t sgb_stride;   // supergroup bounds per delay block (the plan's stride)
+    int32_t dlo_all;      // delay bounds of every group of every block (samples)
+    int32_t dhi_all;
+    int32_t wgrp_begin;   // whole-path delay groups (the Farrow dL/dx gather), and
+    int32_t n_wgrp;       //   their supergroups
+    int32_t n_sgw;
+    int32_t n_ptiles;     // source-position tiles of the Farrow dL/dx gather
 };
 
 // One work item of the persistent kernels: an output tile of one mic, summed over
@@ -80,15 +88,10 @@ struct DImage {
     int32_t R;            // decimation of its delay grid
     float invR;
     float gfac;           // beta_i * fs / (4 pi c): gain = gfac / D
-    int32_t seg_off;      // first track segment within one mic's track
     int32_t n_seg;        // ceil(n_out / R)
     int8_t hits[6];       // reflections on each wall (beta_i = prod beta_w^hits_w)
     int8_t pad[2];
-    int32_t run_off;      // first track-kernel block within one mic
-    int32_t sadj_off;     // first Catmull-Rom-transpose block within one mic
-    int32_t loc;          // first segment of this image in a workgroup's track slot: the
-                          // images of a delay group hold slot_segs_of(R, span) segments each,
-                          // in group order (grid delays: 3 more per image)
+    int32_t loc;          // kernels: the image's slot offset (from its PermEntry)
     int32_t pad2;
 };
 
@@ -118,30 +121,36 @@ __host__ __device__ constexpr int64_t slot_extra_off(int slot_segs, int gmax)
            slot_al(((int64_t)slot_segs + 3 * (int64_t)gmax) * 8);
 }
 
+// Adjoint slot, after the tracks: dL/dD of the group's image samples over the
+// tile (floats, [gmax][TO]), the per-wave sums of dL/dbeta_i ([gmax][16]), and
+// the Catmull-Rom transpose sums of every segment (float4 per slot segment).
+__host__ __device__ constexpr int64_t adj_slot_bytes(int slot_segs, int gmax, int TO)
+{
+    return slot_extra_off(slot_segs, gmax) + slot_al((int64_t)gmax * TO * 4) + slot_al((int64_t)gmax * 16 * 4) +
+           slot_al((int64_t)slot_segs * 16);
+}
+
+// Threads of the backward kernels' workgroups (their register budget needs it).
+constexpr int kAdjThreads = 512;
+
+// Images per delay group at most (their slot offsets are staged in LDS).
+constexpr int kMaxGroup = 512;
+// LDS for a group's slot offsets (grid and segment offsets, with totals).
+constexpr size_t kLscBytes = (size_t)8 * (kMaxGroup + 2);
+// Source knots with a gradient per scene at most, and a parameter row: dL/dbeta_w
+// (6) then dL/d(knot j, axis a) at 6 + 3 j + a.
+constexpr int kMaxGradKnots = 32;
+constexpr int kRowWidth = 6 + 3 * kMaxGradKnots;
+// LDS of the parameter accumulators: the knots' sums, then per wave 12 doubles
+// of block-reduction scratch.
+constexpr size_t kParamLdsBytes = (size_t)8 * (3 * kMaxGradKnots + 16 * 12);
+
 // Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
 constexpr int kFarrowStride = 12;
 
-// A track-kernel block: kTrackThreads threads, each solving kTrackWalk
-// consecutive grid points in time order.  A block emits every segment of an
-// audio-rate image (R = 1) it solves, and all but three of a decimated image's,
-// whose cubics also need the next two grid points and the one before.
-constexpr int kTrackThreads = 256;
-constexpr int kTrackWalk = 4;
-constexpr int kTrackPoints = kTrackThreads * kTrackWalk;
-__host__ __device__ constexpr int track_block_segs(int R) { return R == 1 ? kTrackPoints : kTrackPoints - 3; }
-
-// Segments one block of the Catmull-Rom transpose sums: its outputs (segments x R)
-// are staged in LDS, at most kSegAdjStage of them.
-constexpr int kSegAdjThreads = 256;
-constexpr int kSegAdjStage = 4096;
-static_assert(kSegAdjStage >= 4096, "a segment of the largest decimation (4096) must fit the stage");
-__host__ __device__ constexpr int seg_adj_block_segs(int R)
-{
-    return R * kSegAdjThreads <= kSegAdjStage ? kSegAdjThreads : (kSegAdjStage / R > 0 ? kSegAdjStage / R : 1);
-}
-
-// Images [img_begin, img_end) of a scene (sorted by delay) whose delays, in
-// samples, are bounded by [dmin, dmax] for every mic at every time.
+// A delay group: the images perm[img_begin .. img_end) of the plan's permutation
+// (consecutive in the block's delay order) whose delays, in samples, are bounded
+// by [dmin, dmax] for every mic at every output of the block.
 struct DGroup {
     int32_t img_begin;
     int32_t img_end;
@@ -149,13 +158,33 @@ struct DGroup {
     int32_t dmax;
 };
 
+// A delay block of a scene (blk_tiles output tiles): its delay groups.
+struct DBlock {
+    int32_t grp_begin;
+    int32_t n_grp;
+};
+
+// An image of a delay group: its index among the scene's images, and its first
+// segment in a workgroup's track slot (the images of a group hold
+// slot_segs_of(R, span) segments each, in group order).
+struct PermEntry {
+    int32_t img;
+    int32_t loc;
+};
+
 
 constexpr int kStatusWindow = 1;
 
 // ---- kernel launchers (msim_kernels.hip) ----
-hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                         const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
-                         double c, double fs, int delay_model, hipStream_t st);
+// The plan's device tables the kernels read: scenes, images, delay blocks, delay
+// groups and the groups' image permutation.
+struct PlanView {
+    const DScene* scenes;
+    const DImage* imgs;
+    const DBlock* blocks;
+    const DGroup* groups;
+    const PermEntry* perm;
+};
 
 // What a persistent kernel needs to solve its tracks tile by tile: the plan's
 // knots and mic offsets, the physics, and the per-workgroup slots.
@@ -169,10 +198,28 @@ struct TrackArgs {
     int64_t slot_bytes;
 };
 
-hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
-                        const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
-                        const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* x,
-                        float* part, int32_t* d_status, hipStream_t st);
+// The adjoint part of a workgroup's slot.
+struct AdjSlot {
+    float* dbar;
+    float* esum;
+    float4* dseg;
+};
+
+// What the parameter reductions need: the rows of partials, the largest group,
+// the largest decimation, dL/dbeta_i's constant fs / (4 pi c), and which
+// gradients are wanted.
+struct ParamArgs {
+    double* rows;
+    int gmax;
+    int rmax;
+    float ghat;
+    int want_beta;
+    int want_src;
+};
+
+hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const PlanView& pv,
+                        const float4* d_table, int L, const WorkItem* items, int n_items, int32_t* ticket,
+                        const TrackArgs& ta, const float* x, float* part, int32_t* d_status, hipStream_t st);
 hipError_t launch_reduce_sg(const DScene* d_scenes, int n_scenes, const int64_t* d_y_prefix, int64_t y_total,
                             const float* part, float* y, hipStream_t st);
 
@@ -192,38 +239,19 @@ __host__ __device__ constexpr size_t qtab_bytes(int taps, int Lq)
 size_t synth_lds_bytes(int taps, int Lq, int window);
 
 // ---- adjoint launchers (msim_adjoint.hip) ----
-// Scratch of the adjoint of one scene (all carved from the caller's workspace).
-struct AdjBufs {
-    float* xpart;     // table: [mic][group][tile][window], transpose-delay partial windows;
-                      // Farrow: [mic][group][position][12], per-group sums u_k
-    float* u;         // Farrow: [position][12], u_k summed over mics and groups
-    float* dbar;      // [mic][image][n_out]: d loss / d D_i(n)
-    float* gpart;     // [mic][tile * waves][image]: partial sums of d loss / d beta_i
-    float4* dseg;     // [mic][segment]: Catmull-Rom transpose weights summed per segment
-    double4* pgc;     // [mic][grid point]: d loss / d source position at emission time, and lambda
-    int32_t* pga;     // [mic][grid point]: knot index of that emission time
-};
-
-size_t adj_x_lds_bytes(int taps, int L, int window, int nthreads);
+size_t adj_x_lds_bytes(int taps, int L, int window, int tile);
 size_t adj_track_lds_bytes(int taps, int Lq, int window);
-
-hipError_t launch_adj_x(int taps, int nthreads, const DScene& hs, const DImage* d_imgs, const DGroup* d_groups,
-                        const float* d_atab, int Lq, const Seg* seg, const int32_t* segK, const float* gy,
-                        float* xpart, int32_t* d_status, hipStream_t st);
-hipError_t launch_reduce_x(const DScene& hs, const DGroup* d_groups, int nthreads, int taps, const float* xpart,
-                           float* gx, hipStream_t st);
-hipError_t launch_adj_track(int taps, int nthreads, int rb, const DScene& hs, const DImage* d_imgs,
-                            const DGroup* d_groups, const float4* d_qtable, int Lq, const Seg* seg,
-                            const int32_t* segK, const float* x, const float* gy, float ghat, float* dbar,
-                            float* gpart, int32_t* d_status, hipStream_t st);
-hipError_t launch_adj_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                             const double* d_knots, const double* d_mics, const double* grid, const float* dbar,
-                             float4* dseg, double4* pgc, int32_t* pga, double c, double fs, int delay_model,
-                             int want_src, hipStream_t st);
-hipError_t launch_reduce_params(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                                const float* gpart, int gpart_stride, const double4* pgc, const int32_t* pga,
-                                double* partial, double* gbeta, double* gsrc, hipStream_t st);
-size_t reduce_partial_bytes(const DScene& hs);
+hipError_t launch_adjx(int taps, int tile, int n_wg, int window, const PlanView& pv, const float* d_atab, int Lq,
+                       const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy,
+                       float* xwin, int32_t* d_status, hipStream_t st);
+hipError_t launch_reduce_x(const PlanView& pv, int n_scenes, const int64_t* d_x_prefix, int64_t x_total, int nthreads,
+                           int taps, const int2* d_sgb, const float* xwin, float* gx, hipStream_t st);
+hipError_t launch_adjp(int taps, int nthreads, int rb, int n_wg, int window, const PlanView& pv,
+                       const float4* d_qtable, int Lq, const WorkItem* items, int n_items, int32_t* ticket,
+                       const TrackArgs& ta, const float* x, const float* gy, const ParamArgs& pa, int32_t* d_status,
+                       hipStream_t st);
+hipError_t launch_reduce_rows(const PlanView& pv, int n_scenes, int scene0, const double* rows, double* gbeta,
+                              double* gsrc, hipStream_t st);
 int max_grad_knots();
 
 // ---- Farrow launchers (msim_farrow.hip) ----
@@ -231,13 +259,24 @@ size_t farrow_lds_bytes(int window);
 hipError_t launch_farrow_conv(const DScene* d_scenes, int n_scenes, const int64_t* d_vprefix, int64_t total, int taps,
                               const float* d_coef, const float* x, float* v, hipStream_t st);
 int farrow_outputs_per_lane(const int32_t* decim, int n_tiers);
-hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const DScene* d_scenes,
-                         const DImage* d_imgs, const DGroup* d_groups, const WorkItem* items, int n_items,
-                         int32_t* ticket, const TrackArgs& ta, const float* v, float* part, int32_t* d_status,
-                         hipStream_t st);
-hipError_t launch_farrow_adjoint(int nthreads, int taps, int order, const DScene& hs, const DImage* d_imgs,
-                                 const DGroup* d_groups, const Seg* seg, const int32_t* segK, const float* d_coef,
-                                 const float* v, const float* gy, float ghat, float* upart, float* u, float* gx,
-                                 float* dbar, float* gpart, int32_t* d_status, hipStream_t st);
+hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, int order, const PlanView& pv,
+                         const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
+                         float* part, int32_t* d_status, hipStream_t st);
+// LDS of the Farrow gain/delay adjoint and of the dL/dx gather.
+size_t farrow_gd_lds_bytes(int window);
+size_t farrow_u_lds_bytes(int window);
+hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order, const PlanView& pv,
+                            const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
+                            const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st);
+// The dL/dx gather runs over whole-path delay groups: pv.groups / pv.perm are
+// those groups and their permutation.
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+                           int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
+                           int32_t* d_status, hipStream_t st);
+hipError_t launch_farrow_u_reduce(const PlanView& pv, int n_scenes, const int64_t* d_vprefix, int64_t vtotal, int taps,
+                                  const float* upart, float* u, hipStream_t st);
+// scenes s0 .. s0 + n_scenes - 1 (max_in: their largest input length)
+hipError_t launch_farrow_corr(const PlanView& pv, int s0, int n_scenes, int64_t max_in, int taps, const float* d_coef,
+                              const float* u, float* gx, hipStream_t st);
 
 }  // namespace msim

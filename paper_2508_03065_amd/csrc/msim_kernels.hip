@@ -17,128 +17,6 @@
 
 namespace msim {
 
-// ------------------------------------------------------------------- tracks
-
-// One block of kTrackThreads threads per (mic, image, block of segments); thread
-// j solves the kTrackWalk consecutive grid points 4j .. 4j+3 of the block in time
-// order, each from the linear extrapolation of the two before (the first from
-// first_tau), the block shares the delays through LDS and writes its segments
-// with consecutive threads on consecutive segments.  Segment k covers outputs
-// [kR, (k+1)R): D(kR + v) = K + a0 + v (b1 + v (b2 + v b3)), integer base K and
-// FP32 offsets: the exact delay at the audio rate (R = 1), else the uniform
-// Catmull-Rom cubic through the grid delays D_{k-1} .. D_{k+2} (grid point g at
-// output gR, g = -1 .. n_seg + 1).  With grid != NULL the block also stores the
-// delays it owns (grid index g + 1 within the image's n_seg + 3 slots), for the
-// adjoint.
-__device__ __forceinline__ void track_block(const DScene& S, int64_t bid, const DImage* __restrict__ imgs,
-                                   const double* __restrict__ knots, const double* __restrict__ mics,
-                                   double* __restrict__ grid, Seg* __restrict__ seg, int32_t* __restrict__ segK,
-                                   double c, double fs, int model, double* Dl)
-{
-    const int64_t per_mic = S.runs_per_mic;
-    const int mic = (int)(bid / per_mic);
-    const int64_t ridx = bid - (int64_t)mic * per_mic;
-    const DImage* I = imgs + S.img_begin;
-    int lo = 0, hi = S.n_img - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (I[mid].run_off <= ridx) lo = mid; else hi = mid - 1;
-    }
-    const int ii = lo;
-    const DImage im = I[ii];
-    const int R = im.R;
-    const int per = track_block_segs(R);
-    const int64_t k0 = (ridx - im.run_off) * per;
-    const int64_t k1 = min((int64_t)im.n_seg, k0 + per);
-    const int64_t gbase = (R == 1) ? k0 : k0 - 1;       // grid point of LDS slot 0
-    const int64_t glast = (R == 1) ? k1 - 1 : k1 + 1;
-    const int64_t trk = S.trk_base + (int64_t)mic * S.seg_per_mic + im.seg_off;
-    double* gout = grid ? grid + S.grid_base + (int64_t)mic * (S.seg_per_mic + 3 * (int64_t)S.n_img) + im.seg_off +
-                              3 * (int64_t)ii + 1
-                        : nullptr;
-    const double inv_fs = 1.0 / fs;
-    double tp1 = 0.0, tp2 = 0.0;
-    for (int w = 0; w < kTrackWalk; ++w) {
-        const int slot = kTrackWalk * (int)threadIdx.x + w;
-        const int64_t g = gbase + slot;
-        double D = 0.0;
-        if (g <= glast) {
-            const double t = (double)(g * R) * inv_fs;
-            double r[3];
-            mic_pos(S, knots, mics, mic, t, r);
-            double tau;
-            if (model == 1 || w == 0) {
-                tau = first_tau(S, im.m, knots, r, t, c, model);
-                if (model == 0) tau = newton_tau(S, im.m, knots, r, t, c, tau);
-            } else {
-                tau = newton_tau(S, im.m, knots, r, t, c, w >= 2 ? 2.0 * tp1 - tp2 : tp1);
-            }
-            tp2 = tp1;
-            tp1 = tau;
-            D = fs * tau;
-            if (gout) {
-                const bool own = (g >= k0 && g < k1) || (R > 1 && k0 == 0 && g < 0) ||
-                                 (R > 1 && k1 == im.n_seg && g >= k1);
-                if (own) gout[g] = D;
-            }
-        }
-        Dl[slot] = D;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < per; q += kTrackThreads) {
-        const int64_t k = k0 + q;
-        if (k >= k1) break;
-        if (R == 1) {
-            const double D = Dl[q];
-            const double Kd = floor(D);
-            seg[trk + k] = Seg{(float)(D - Kd), 0.0f, 0.0f, 0.0f};
-            segK[trk + k] = (int32_t)Kd;
-        } else {
-            const double D0 = Dl[q], D1 = Dl[q + 1], D2 = Dl[q + 2], D3 = Dl[q + 3];
-            const double Kd = floor(D1);
-            const double a1 = 0.5 * (D2 - D0);
-            const double a2 = 0.5 * (2.0 * D0 - 5.0 * D1 + 4.0 * D2 - D3);
-            const double a3 = 0.5 * (3.0 * D1 - D0 - 3.0 * D2 + D3);
-            const double iR = 1.0 / (double)R;
-            seg[trk + k] = Seg{(float)(D1 - Kd), (float)(a1 * iR), (float)(a2 * iR * iR), (float)(a3 * iR * iR * iR)};
-            segK[trk + k] = (int32_t)Kd;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kTrackThreads) void k_tracks(const DScene* __restrict__ scenes, int scene,
-                                                          const DImage* __restrict__ imgs,
-                                                          const double* __restrict__ knots,
-                                                          const double* __restrict__ mics, double* __restrict__ grid,
-                                                          Seg* __restrict__ seg, int32_t* __restrict__ segK, double c,
-                                                          double fs, int model)
-{
-    __shared__ double Dl[kTrackPoints];
-    track_block(scenes[scene], blockIdx.x, imgs, knots, mics, grid, seg, segK, c, fs, model, Dl);
-}
-
-// Last scene whose prefix start is <= i (prefix[0] = 0, ascending).
-__device__ inline int scene_of(const int64_t* __restrict__ prefix, int n, int64_t i)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-hipError_t launch_tracks(const DScene* d_scenes, int scene, const DScene& hs, const DImage* d_imgs,
-                         const double* d_knots, const double* d_mics, double* grid, Seg* seg, int32_t* segK,
-                         double c, double fs, int delay_model, hipStream_t st)
-{
-    const int64_t n = hs.runs_per_mic * hs.n_mics;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tracks, dim3((unsigned)n), dim3(kTrackThreads), 0, st, d_scenes, scene, d_imgs, d_knots,
-                       d_mics, grid, seg, segK, c, fs, delay_model);
-    return hipGetLastError();
-}
-
 // -------------------------------------------------------------- forward synth
 
 // LDS: the half table of h(v) = h(-v), v in [0, T/2], for quadratic
@@ -164,7 +42,7 @@ size_t synth_lds_bytes(int taps, int Lq, int window)
 // else 0 and Lr is used.  Ends with a barrier.
 template <int T, int NT, int LC>
 __device__ inline void synth_group(const DScene& S, const DGroup& G, int n0, Slot sl, const DImage* __restrict__ I,
-                                   const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc,
+                                   const PermEntry* __restrict__ perm, const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc,
                                    int& bad)
 {
     constexpr int NG = T / 8;          // tap quads per side
@@ -250,15 +128,15 @@ __device__ inline void synth_group(const DScene& S, const DGroup& G, int n0, Slo
         Seg qa{}, qb{};
         int Ka = 0, Kb = 0;
         float va = 0.0f, vb = 0.0f;
-        DImage ia = I[G.img_begin], ib;
+        DImage ia = perm_image(I, perm, G.img_begin), ib;
         fetch(ia, qa, Ka, va);
         int ii = G.img_begin;
         for (; ii + 1 < G.img_end; ii += 2) {
-            ib = I[ii + 1];
+            ib = perm_image(I, perm, ii + 1);
             fetch(ib, qb, Kb, vb);
             body(ia, qa, Ka, va);
             if (ii + 2 < G.img_end) {
-                ia = I[ii + 2];
+                ia = perm_image(I, perm, ii + 2);
                 fetch(ia, qa, Ka, va);
             }
             body(ib, qb, Kb, vb);
@@ -277,7 +155,7 @@ __device__ inline void synth_group(const DScene& S, const DGroup& G, int n0, Slo
 // is below its accuracy bound.  Ends with a barrier.
 template <int T, int NT, int LC>
 __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Slot sl, const DImage* __restrict__ I,
-                                    const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc0,
+                                    const PermEntry* __restrict__ perm, const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc0,
                                     float& acc1, int& bad)
 {
     constexpr int NG = T / 8;
@@ -355,15 +233,15 @@ __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Sl
         Seg qa{}, qb{};
         float a1a = 0.0f, a1b = 0.0f, ka = 0.0f, kb = 0.0f;
         int K0a = 0, K1a = 0, K0b = 0, K1b = 0;
-        DImage ia = I[G.img_begin], ib;
+        DImage ia = perm_image(I, perm, G.img_begin), ib;
         fetch(ia, qa, a1a, K0a, K1a, ka);
         int ii = G.img_begin;
         for (; ii + 1 < G.img_end; ii += 2) {
-            ib = I[ii + 1];
+            ib = perm_image(I, perm, ii + 1);
             fetch(ib, qb, a1b, K0b, K1b, kb);
             body(ia, qa, a1a, K0a, K1a, ka);
             if (ii + 2 < G.img_end) {
-                ia = I[ii + 2];
+                ia = perm_image(I, perm, ii + 2);
                 fetch(ia, qa, a1a, K0a, K1a, ka);
             }
             body(ib, qb, a1b, K0b, K1b, kb);
@@ -380,11 +258,11 @@ __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Sl
 // register accumulators; the item's sum over its groups (in group order) is
 // written once.  RB outputs per lane (1 or 2), NT lanes, NT * RB outputs per tile.
 template <int T, int NT, int LC, int RB>
-__global__ __launch_bounds__(NT, 4) void k_synth(
-    const DScene* __restrict__ scenes, const DImage* __restrict__ imgs, const DGroup* __restrict__ groups,
-    const float4* __restrict__ table, int L, const WorkItem* __restrict__ items, int n_items,
-    int32_t* __restrict__ ticket, TrackArgs ta, const float* __restrict__ x, float* __restrict__ part,
-    int32_t* __restrict__ status)
+__global__ __launch_bounds__(NT, 4) void k_synth(PlanView pv, const float4* __restrict__ table, int L,
+                                                 const WorkItem* __restrict__ items, int n_items,
+                                                 int32_t* __restrict__ ticket, TrackArgs ta,
+                                                 const float* __restrict__ x, float* __restrict__ part,
+                                                 int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
     constexpr int TO = NT * RB;
@@ -394,22 +272,23 @@ __global__ __launch_bounds__(NT, 4) void k_synth(
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     for_each_item(ticket, n_items, [&](int it) {
         const WorkItem w = items[it];
-        const DScene& S = scenes[w.scene];
-        const DImage* I = imgs + S.img_begin;
+        const DScene& S = pv.scenes[w.scene];
+        const DImage* I = pv.imgs + S.img_begin;
+        const DBlock B = pv.blocks[S.blk_begin + w.tile / S.blk_tiles];
         const int n0 = w.tile * TO;
         const int n_out = (int)S.n_out;
         const int n_hi = min(n0 + TO, n_out);
-        const int gb = sg_begin(S.n_grp, S.n_sg, w.sg), ge = sg_begin(S.n_grp, S.n_sg, w.sg + 1);
+        const int gb = sg_begin(B.n_grp, S.n_sg, w.sg), ge = sg_begin(B.n_grp, S.n_sg, w.sg + 1);
         float acc0 = 0.0f, acc1 = 0.0f;
         int bad = 0;
         for (int g = gb; g < ge; ++g) {
-            const DGroup G = groups[S.grp_begin + g];
-            tile_tracks<NT>(S, w.mic, I, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax), sl,
-                            (int*)xw, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
+            const DGroup G = pv.groups[B.grp_begin + g];
+            tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi, group_span(TO, G.dmin, G.dmax),
+                            sl, (int*)xw, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             if constexpr (RB == 1)
-                synth_group<T, NT, LC>(S, G, n0, sl, I, tab, xw, L, x, acc0, bad);
+                synth_group<T, NT, LC>(S, G, n0, sl, I, pv.perm, tab, xw, L, x, acc0, bad);
             else
-                synth_group2<T, NT, LC>(S, G, n0, sl, I, tab, xw, L, x, acc0, acc1, bad);
+                synth_group2<T, NT, LC>(S, G, n0, sl, I, pv.perm, tab, xw, L, x, acc0, acc1, bad);
         }
         float* out = part + S.part_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_out;
         const int n = n0 + RB * (int)threadIdx.x;
@@ -419,43 +298,35 @@ __global__ __launch_bounds__(NT, 4) void k_synth(
     });
 }
 
-__global__ void k_zero_i32(int32_t* p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 // The default phase count of the quadratic table is compiled in (immediate table
 // offsets); others run the same kernel with the phase count read at run time.
 constexpr int kPhasesCompiled = 128;
 
 template <int T, int TO, int RB>
-static hipError_t launch_synth_t(int n_wg, int window, const DScene* d_scenes, const DImage* d_imgs,
-                                 const DGroup* d_groups, const float4* d_table, int L, const WorkItem* items,
-                                 int n_items, int32_t* ticket, const TrackArgs& ta, const float* x, float* part,
-                                 int32_t* d_status, hipStream_t st)
+static hipError_t launch_synth_t(int n_wg, int window, const PlanView& pv, const float4* d_table, int L,
+                                 const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta,
+                                 const float* x, float* part, int32_t* d_status, hipStream_t st)
 {
     constexpr int NT = TO / RB;
     const size_t lds = synth_lds_bytes(T, L, window);
     auto kern = L == kPhasesCompiled ? k_synth<T, NT, kPhasesCompiled, RB> : k_synth<T, NT, 0, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, ticket, 1);
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, d_scenes, d_imgs, d_groups, d_table, L, items,
-                       n_items, ticket, ta, x, part, d_status);
+    hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, d_table, L, items, n_items, ticket, ta, x,
+                       part, d_status);
     return hipGetLastError();
 }
 
-hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const DScene* d_scenes,
-                        const DImage* d_imgs, const DGroup* d_groups, const float4* d_table, int L,
-                        const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* x,
-                        float* part, int32_t* d_status, hipStream_t st)
+hipError_t launch_synth(int taps, int nthreads, int rb, int n_wg, int window, const PlanView& pv,
+                        const float4* d_table, int L, const WorkItem* items, int n_items, int32_t* ticket,
+                        const TrackArgs& ta, const float* x, float* part, int32_t* d_status, hipStream_t st)
 {
     if (n_items == 0) return hipSuccess;
 #define MSIM_SYN_CASE(TT, NN, RR)                                                                              \
     if (taps == TT && nthreads == NN && rb == RR)                                                             \
-        return launch_synth_t<TT, NN, RR>(n_wg, window, d_scenes, d_imgs, d_groups, d_table, L, items, n_items, \
-                                          ticket, ta, x, part, d_status, st);
+        return launch_synth_t<TT, NN, RR>(n_wg, window, pv, d_table, L, items, n_items, ticket, ta, x, part,   \
+                                          d_status, st);
 #define MSIM_SYN_TAPS(TT)                                                                                      \
     MSIM_SYN_CASE(TT, 512, 1) MSIM_SYN_CASE(TT, 1024, 1) MSIM_SYN_CASE(TT, 512, 2) MSIM_SYN_CASE(TT, 1024, 2)
     MSIM_SYN_TAPS(32)

@@ -203,9 +203,10 @@ class Plan:
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
 
     def backward(self, x: torch.Tensor, gy: torch.Tensor, want_x: bool = True, want_beta: bool = True,
-                 want_src: bool = True, stream=None):
+                 want_src: bool = True, stream=None, batched: bool = False, graph: bool = True):
         """(dL/dx [x_total] f32, dL/dbeta [n_scenes, 6] f64, dL/dknots [src_total, 3] f64) for
-        gy = dL/dy; entries not requested are None."""
+        gy = dL/dy; entries not requested are None.  batched=True runs every scene in one
+        persistent launch per kernel (replayed from a HIP graph when graph=True)."""
         assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
         assert gy.is_cuda and gy.dtype == torch.float32 and gy.is_contiguous() and gy.numel() == self.y_total
         dev = x.device
@@ -213,10 +214,16 @@ class Plan:
         gb = torch.empty((self.n_scenes, 6), dtype=torch.float64, device=dev) if want_beta else None
         gs = (torch.zeros((max(self.src_total, 1), 3), dtype=torch.float64, device=dev)
               if want_src else None)
-        ws = self.workspace(True, dev)
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
-        check(_lib.load().msim_backward(self._ptr, ptr(x), ptr(gy), ptr(gx), ptr(gb), ptr(gs),
-                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        if batched:
+            ws = self.batched_workspace(dev)
+            check(_lib.load().msim_backward_batched(self._ptr, ptr(x), ptr(gy), ptr(gx), ptr(gb), ptr(gs),
+                                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream),
+                                                    int(graph)))
+        else:
+            ws = self.workspace(True, dev)
+            check(_lib.load().msim_backward(self._ptr, ptr(x), ptr(gy), ptr(gx), ptr(gb), ptr(gs),
+                                            C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         if gs is not None:
             gs = gs[: self.src_total]
         return gx, gb, gs
