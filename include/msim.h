@@ -152,6 +152,18 @@ msim_status msim_workspace_size(const msim_plan* plan, int32_t with_grad, size_t
  * x: device [x_total] FP32; y: device [y_total] FP32, fully overwritten. */
 msim_status msim_forward(msim_plan* plan, const float* x, float* y, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): msim_forward without a
+ * caller workspace.  Its scratch (track slots, partial outputs, the ticket
+ * counter) is a fixed 64 MiB array on each GPU, held from the first plan
+ * created on that GPU until the process ends; the call allocates nothing.
+ * MSIM_E_WORKSPACE when the plan needs more than that (msim_workspace_size(plan,
+ * 0) > 64 MiB).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two host threads) race and must be
+ * serialised by the caller.  Everything a call reads from the array it first
+ * writes in the same call.  Same result as msim_forward, bit for bit. */
+msim_status msim_forward_noalloc(msim_plan* plan, const float* x, float* y, hipStream_t stream);
+
 /* Batched forward: the same result as msim_forward (bit for bit: both sum every
  * delay group in the same order), computed by three launches over all scenes
  * at once: the delay tracks of every scene, one persistent synthesis kernel

@@ -68,6 +68,7 @@ SIGNATURES = {
     "msim_plan_stats": [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "msim_workspace_size": [_PLAN, C.c_int32, C.POINTER(C.c_size_t)],
     "msim_forward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
+    "msim_forward_noalloc": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p],
     "msim_device_status": [_PLAN, C.c_void_p, C.POINTER(C.c_int32)],
     "msim_backward": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                       C.c_size_t, C.c_void_p],

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstdarg>
@@ -42,8 +43,38 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxOut = int64_t(1) << 23;
 constexpr size_t kLdsLimit = 160 * 1024 - 256;   // dynamic LDS (a little is static)
+constexpr int kSlotSegCap = 4096;                   // track segments per workgroup slot (unless one image needs more)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+// Scratch of msim_forward_noalloc: a fixed array on every GPU the library runs
+// on, held until the process ends.  Host code uses only its per-device address
+// from hipGetSymbolAddress (the array's name is a host-side stand-in).
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on device dev (which must be current), looked up once.
+msim_status scratch_on(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(MSIM_E_UNSUPPORTED, "device %d: beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(MSIM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MSIM_OK;
+}
 
 // Modified Bessel function I0 by its power series sum_k ((x/2)^k / k!)^2.
 double bessel_i0(double x)
@@ -875,6 +906,31 @@ msim_status regroup(msim_plan* P)
                     split(G);
                 }
             }
+            // groups whose tracks exceed a slot of kSlotSegCap segments (audio-rate
+            // images hold a tile's worth each) are split into consecutive parts
+            {
+                std::vector<DGroup> out;
+                for (const DGroup& g : gr) {
+                    const int span = group_span(NT, g.dmin, g.dmax);
+                    int ib = g.img_begin;
+                    int64_t segs = 0;
+                    for (int i = g.img_begin; i <= g.img_end; ++i) {
+                        const int add = i < g.img_end ? slot_segs_of(P->images[d.img_begin + o.idx[i]].R, span) : 0;
+                        if (i == g.img_end || (segs + add > kSlotSegCap && i > ib)) {
+                            double lo = 1e300, hi = -1e300;
+                            for (int k = ib; k < i; ++k) {
+                                lo = std::min(lo, (double)o.lo[k]);
+                                hi = std::max(hi, (double)o.hi[k]);
+                            }
+                            out.push_back(DGroup{ib, i, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4});
+                            ib = i;
+                            segs = 0;
+                        }
+                        segs += add;
+                    }
+                }
+                gr.swap(out);
+            }
             window = std::max(window, bw);
             P->blocks.push_back(DBlock{(int)P->groups.size(), (int)gr.size()});
             // permutation entries with their slot offsets: slot_segs_of(R, span)
@@ -1543,6 +1599,13 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
     }
+    {
+        void* sp = nullptr;
+        if ((st = scratch_on(P->device, &sp)) != MSIM_OK) {
+            delete P;
+            return st;
+        }
+    }
     std::vector<float4> qtab4((P->qtable.size() + 15) / 16);
     std::memcpy(qtab4.data(), P->qtable.data(), P->qtable.size());
     std::vector<int32_t> zero(1, 0);
@@ -1654,6 +1717,30 @@ msim_status msim_forward(msim_plan* P, const float* x, float* y, void* ws, size_
     FwdWs2 w;
     carve_fwd_ws(P, false, (char*)ws, &w);
     return enqueue_forward(P, x, y, w, false, stream);
+}
+
+msim_status msim_forward_noalloc(msim_plan* P, const float* x, float* y, hipStream_t stream)
+{
+    if (!P || !x || !y) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    const size_t need = carve_fwd_ws(P, false, nullptr, nullptr);
+    if (need > kNoAllocBytes)
+        return fail(MSIM_E_WORKSPACE,
+                    "msim_forward_noalloc: this plan needs %zu bytes of scratch, the fixed per-GPU scratch holds %zu",
+                    need, kNoAllocBytes);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(MSIM_E_INVALID_ARG, "plan was created on device %d, current is %d", P->device, dev);
+    void* sp = nullptr;
+    msim_status st = scratch_on(dev, &sp);
+    if (st != MSIM_OK) return st;
+    FwdWs2 w;
+    carve_fwd_ws(P, false, (char*)sp, &w);
+    // no per-launch timing events here: they would be created on the first use
+    const bool prof = P->profiling;
+    P->profiling = false;
+    st = enqueue_forward(P, x, y, w, false, stream);
+    P->profiling = prof;
+    return st;
 }
 
 msim_status msim_profile_begin(msim_plan* P)

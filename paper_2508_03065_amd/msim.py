@@ -157,6 +157,15 @@ class Plan:
                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return y
 
+    def forward_noalloc(self, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+        """The forward with the library's fixed per-GPU scratch instead of a workspace
+        (msim_forward_noalloc): nothing is allocated, y is written in place."""
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
+        assert y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.numel() == self.y_total
+        check(_lib.load().msim_forward_noalloc(self._ptr, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                               _stream_handle(stream)))
+        return y
+
     def batched_workspace(self, device=None) -> torch.Tensor:
         b = C.c_size_t()
         check(_lib.load().msim_batched_workspace_size(self._ptr, C.byref(b)))
