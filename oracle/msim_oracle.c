@@ -381,6 +381,11 @@ int orc_forward(const orc_scene* s, const orc_params* p, const double* x,
     return 0;
 }
 
+/* With few non-zero output gradients the tier-emulating delays are evaluated
+ * where needed (tau_at: the same Catmull-Rom of the same exact grid delays)
+ * instead of over every grid point first. */
+static int sparse_ok(const orc_scene* s, int64_t n_nz) { return n_nz * 64 < s->n_out; }
+
 /* Exact transpose of the forward map x -> y:
  * gx[m] = sum_{mic,i,n} gy[mic][n] g_i(n) h(j - mu_i(n)) where m = n - floor(D_i(n)) - j. */
 int orc_adjoint_x(const orc_scene* s, const orc_params* p, const double* gy, double* gx)
@@ -388,18 +393,24 @@ int orc_adjoint_x(const orc_scene* s, const orc_params* p, const double* gy, dou
     img_set I = make_images(s, p);
     int T = p->taps;
     memset(gx, 0, sizeof(double) * s->n_in);
+    int64_t* nz = (int64_t*)malloc(sizeof(int64_t) * (s->n_out > 0 ? s->n_out : 1));
     for (int mic = 0; mic < s->n_mics; ++mic) {
-        delay_src ds = {s, p, NULL, NULL};
-        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
         const double* g_y = gy + (int64_t)mic * s->n_out;
+        /* the outputs with a non-zero gradient, in increasing n */
+        int64_t n_nz = 0;
+        for (int64_t n = 0; n < s->n_out; ++n)
+            if (g_y[n] != 0.0) nz[n_nz++] = n;
+        if (n_nz == 0) continue;
+        delay_src ds = {s, p, NULL, NULL};
+        if (p->n_tiers > 0 && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
 #pragma omp parallel
         {
             double* part = (double*)calloc(s->n_in, sizeof(double));
 #pragma omp for schedule(dynamic, 4)
             for (int64_t i = 0; i < I.n_img; ++i) {
                 if (I.beta[i] == 0.0) continue;
-                for (int64_t n = 0; n < s->n_out; ++n) {
-                    if (g_y[n] == 0.0) continue;
+                for (int64_t q = 0; q < n_nz; ++q) {
+                    const int64_t n = nz[q];
                     double tau = delay_of(&ds, &I, i, mic, n);
                     double g = I.beta[i] / (4.0 * M_PI * p->c * tau);
                     double D = p->fs * tau;
@@ -418,6 +429,7 @@ int orc_adjoint_x(const orc_scene* s, const orc_params* p, const double* gy, dou
         }
         free_grids(&ds, I.n_img);
     }
+    free(nz);
     free_images(&I);
     return 0;
 }
@@ -430,15 +442,20 @@ int orc_grad_beta(const orc_scene* s, const orc_params* p, const double* x, cons
 {
     img_set I = make_images(s, p);
     double* G = (double*)calloc(I.n_img, sizeof(double));
+    int64_t* nz = (int64_t*)malloc(sizeof(int64_t) * (s->n_out > 0 ? s->n_out : 1));
     for (int mic = 0; mic < s->n_mics; ++mic) {
-        delay_src ds = {s, p, NULL, NULL};
-        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
         const double* g_y = gy + (int64_t)mic * s->n_out;
+        int64_t n_nz = 0;
+        for (int64_t n = 0; n < s->n_out; ++n)
+            if (g_y[n] != 0.0) nz[n_nz++] = n;
+        if (n_nz == 0) continue;
+        delay_src ds = {s, p, NULL, NULL};
+        if (p->n_tiers > 0 && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
 #pragma omp parallel for schedule(dynamic, 4)
         for (int64_t i = 0; i < I.n_img; ++i) {
             double acc = 0.0;
-            for (int64_t n = 0; n < s->n_out; ++n) {
-                if (g_y[n] == 0.0) continue;
+            for (int64_t q = 0; q < n_nz; ++q) {
+                const int64_t n = nz[q];
                 double tau = delay_of(&ds, &I, i, mic, n);
                 acc += g_y[n] * filtered(p, x, s->n_in, n, tau) / (4.0 * M_PI * p->c * tau);
             }
@@ -446,6 +463,7 @@ int orc_grad_beta(const orc_scene* s, const orc_params* p, const double* x, cons
         }
         free_grids(&ds, I.n_img);
     }
+    free(nz);
     for (int w = 0; w < 6; ++w) {
         double acc = 0.0;
         for (int64_t i = 0; i < I.n_img; ++i) {

@@ -116,3 +116,29 @@ def test_config3_sampled(torch_cuda):
     for s in (0, 1, 97, 255):
         idx = np.sort(rng.choice(scenes[s].n_out, 60, replace=False))
         assert rel(ys[s][:, idx].cpu().numpy(), O.forward(scenes[s], par, idx=idx)) <= 1e-5, s
+
+
+@pytest.mark.parametrize("fd", [0, 1])
+def test_backward_batched_equals_plain(torch_cuda, fd):
+    """The batched backward (one persistent launch per kernel over every scene,
+    direct and graph-replayed, with eager work between the replays) equals the
+    plain per-scene backward bit for bit, for both fractional-delay forms."""
+    import dataclasses
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes(6)
+    par = dataclasses.replace(par, fd_kind=fd)
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    gy = torch.randn(plan.y_total, generator=torch.Generator().manual_seed(9)).cuda()
+    ref = [t.clone() for t in plan.backward(x, gy)]
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    for graph in (False, True, True, True):
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        got = plan.backward(x, gy, batched=True, graph=graph)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), graph
+        assert torch.isfinite(junk)
+    assert plan.device_status() == 0

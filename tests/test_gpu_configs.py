@@ -8,10 +8,13 @@ evaluate one by one (its output-subset mode solves the delays it needs locally).
   sampled outputs of scenes 0 and 1, so the oracle's adjoints and its central
   differences for the knots stay cheap.  Scenes with dL/dy = 0 must get exactly
   zero gradients.
-* one scene of the large workload (12x9x4 m, 48 kHz, 10 s, moving source and
-  receiver, 8-mic array, K = 20 -> 11 521 images, T = 96) through the plain
-  forward: the 64-scene batch does not fit one GPU's memory (its delay tracks
-  alone take ~1.2 GB per scene and mic), one scene per call does."""
+* the large workload (64 scenes of 12x9x4 m, 48 kHz, 10 s, moving source and
+  receiver, 8-mic array, K = 20 -> 11 521 images, T = 96): the batched forward
+  of all 64 scenes (one persistent launch, graph-replayed), checked on sampled
+  outputs of 4 scenes x 8 mics; the batched backward of all 64 scenes for a loss
+  whose gradient is non-zero on a few outputs of scenes 0 and 5: dL/dbeta
+  against the oracle, dL/dx against its exact transpose, the knots against FP64
+  central differences, and exactly zero for every other scene."""
 import dataclasses
 
 import numpy as np
@@ -103,23 +106,64 @@ def test_config4_batched_forward_and_gradients(torch_cuda, config4_case, form):
 
 @pytest.fixture(scope="module")
 def config5_case():
-    scenes, par = G.config5(n_scenes=1)
-    idx = np.sort(np.random.default_rng(55).choice(scenes[0].n_out, 24, replace=False))
-    return scenes, par, idx, O.forward(scenes[0], par, idx=idx)
+    scenes, par = G.config5()
+    rng = np.random.default_rng(55)
+    check = (0, 21, 42, 63)
+    idx = {s: np.sort(rng.choice(scenes[s].n_out, 8, replace=False)) for s in check}
+    ref = {s: O.forward(scenes[s], par, idx=idx[s]) for s in check}
+    sparse, dense = {}, {}
+    for s in (0, 5):
+        ii = np.sort(rng.choice(scenes[s].n_out - 2000, 6, replace=False)) + 1000
+        sparse[s] = (ii, rng.standard_normal((scenes[s].n_mics, 6)))
+        g = np.zeros((scenes[s].n_mics, scenes[s].n_out))
+        g[:, ii] = sparse[s][1]
+        dense[s] = g
+    gb = {s: O.grad_beta(scenes[s], par, dense[s]) for s in (0, 5)}
+    gx0 = O.adjoint_x(scenes[0], par, dense[0])
+    sc = scenes[0]
+    ii, w = sparse[0]
+    fd = np.zeros_like(sc.src.p)
+    h = 1e-6
+    for k in range(sc.src.p.shape[0]):
+        for a in range(3):
+            sp, sm = sc.copy(), sc.copy()
+            sp.src.p[k, a] += h
+            sm.src.p[k, a] -= h
+            fd[k, a] = (np.sum(O.forward(sp, par, idx=ii) * w) - np.sum(O.forward(sm, par, idx=ii) * w)) / (2 * h)
+    return scenes, par, idx, ref, dense, gb, gx0, fd
 
 
 @pytest.mark.parametrize("form", sorted(FORMS))
-def test_config5_scene_sampled(torch_cuda, config5_case, form):
+def test_config5_batched_forward_and_gradients(torch_cuda, config5_case, form):
     torch = torch_cuda
     from paper_2508_03065_amd.msim import Plan
-    scenes, par0, idx, ref = config5_case
+    scenes, par0, idx, ref, dense, gb_ref, gx0_ref, fd = config5_case
     par = dataclasses.replace(par0, fd_kind=FORMS[form])
-    print("config5:", form, "one scene, 8 mics, K=20, 48 kHz, 10 s", flush=True)
+    print("config5:", form, "64 scenes x 8 mics, K=20, 48 kHz, 10 s: batched forward + backward", flush=True)
     plan = Plan(scenes, par)
-    assert int(plan.n_images[0]) == 11521
-    x = plan.pack_x([scenes[0].x])
-    y = plan.forward(x)
+    assert all(int(n) == 11521 for n in plan.n_images)
+    x = plan.pack_x([s.x for s in scenes])
+    y = plan.forward_batched(x, graph=True)
     torch.cuda.synchronize()
     assert plan.device_status() == 0
-    (yv,) = plan.unpack_y(y)
-    assert rel(yv[:, idx].cpu().numpy(), ref) <= 1e-5
+    ys = plan.unpack_y(y)
+    for s, ii in idx.items():
+        assert rel(ys[s][:, ii].cpu().numpy(), ref[s]) <= 1e-5, s
+    del y, ys
+    gy = torch.zeros(plan.y_total, dtype=torch.float32, device="cuda")
+    for s, g in dense.items():
+        gy[plan.y_off[s]:plan.y_off[s] + g.size] = torch.from_numpy(g.reshape(-1).astype(np.float32)).cuda()
+    print("config5:", form, "batched backward", flush=True)
+    gx, gb, gs = plan.backward(x, gy, batched=True, graph=True)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    gx, gb, gs = gx.cpu().numpy(), gb.cpu().numpy(), gs.cpu().numpy()
+    for s in (0, 5):
+        assert rel(gb[s], gb_ref[s]) <= 1e-4, s
+    assert rel(gx[plan.x_off[0]:plan.x_off[0] + scenes[0].n_in], gx0_ref) <= 1e-5
+    k0 = scenes[0].src.p.shape[0]
+    assert rel(gs[:k0], fd) <= 1e-3
+    others = [s for s in range(len(scenes)) if s not in (0, 5)]
+    assert not np.any(gb[others])
+    assert not np.any(gx[plan.x_off[1]:plan.x_off[5]]) and not np.any(gx[plan.x_off[6]:])
+    assert not np.any(gs[plan.src_off[6]:])
