@@ -360,12 +360,33 @@ int orc_forward(const orc_scene* s, const orc_params* p, const double* x,
 {
     img_set I = make_images(s, p);
     int64_t ny = idx ? n_idx : s->n_out;
+    if (idx) {
+        /* listed outputs: every (mic, output) pair is one task (delays solved where
+         * needed); each output's sum over images runs in image order */
+        delay_src ds = {s, p, NULL, NULL};
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t t = 0; t < (int64_t)s->n_mics * ny; ++t) {
+            const int mic = (int)(t / ny);
+            const int64_t k = t - (int64_t)mic * ny;
+            const int64_t n = idx[k];
+            double acc = 0.0;
+            for (int64_t i = 0; i < I.n_img; ++i) {
+                if (I.beta[i] == 0.0) continue;
+                double tau = delay_of(&ds, &I, i, mic, n);
+                double g = I.beta[i] / (4.0 * M_PI * p->c * tau);
+                acc += g * filtered(p, x, s->n_in, n, tau);
+            }
+            y[(int64_t)mic * ny + k] = acc;
+        }
+        free_images(&I);
+        return 0;
+    }
     for (int mic = 0; mic < s->n_mics; ++mic) {
         delay_src ds = {s, p, NULL, NULL};
-        if (!idx && p->n_tiers > 0) build_grids(&ds, &I, mic);
+        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t k = 0; k < ny; ++k) {
-            int64_t n = idx ? idx[k] : k;
+            int64_t n = k;
             double acc = 0.0;
             for (int64_t i = 0; i < I.n_img; ++i) {
                 if (I.beta[i] == 0.0) continue;

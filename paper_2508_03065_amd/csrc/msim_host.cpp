@@ -33,10 +33,15 @@ msim_status fail(msim_status s, const char* fmt, ...)
     return s;
 }
 
+// A failed HIP call is reported as MSIM_E_HIP and HIP's last-error state is
+// cleared, so the caller's next HIP call does not see it again.
 #define HIP_OK(expr)                                                                               \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(MSIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return fail(MSIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));                      \
+        }                                                                                          \
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846;
@@ -845,7 +850,8 @@ msim_status regroup(msim_plan* P)
         // window, or beside the per-wave windows) fits too; failing that, the forward's alone.
         bool grad_fit = true;
         auto fits = [&](int window) {
-            if (farrow) return farrow_lds_bytes(window) <= kLdsLimit;
+            if (farrow)
+                return farrow_lds_bytes(window) <= kLdsLimit && (!grad_fit || farrow_gd_lds_bytes(window) <= kLdsLimit);
             if (!grad_fit) return synth_lds_bytes(T, L, window) <= kLdsLimit;
             return adj_track_lds_bytes(T, L, window) <= kLdsLimit &&
                    adj_x_lds_bytes(T, L, window, NT) <= kLdsLimit;
