@@ -362,8 +362,9 @@ hipError_t launch_reduce_x(const PlanView& pv, int n_scenes, const int64_t* d_x_
 //   ds/dmu = Lq (B - Bm + (f - 1/2) C)
 // (the near side's fraction is f, the far side's 1 - f and runs the other way).
 // Then dL/dbeta_i += gy s fs / (4 pi c D) and dL/dD = gy g (ds/dmu - s / D).
-// One output per lane; dL/dD goes to the slot's dbar[(ii - ib) TO + n - n0], the
-// wave sums of dL/dbeta_i to esum[(ii - ib) WAVES + wave].  Ends with a barrier.
+// One output per lane; dL/dD goes into the image's Catmull-Rom partials in the
+// slot (cr_partials), the wave sums of dL/dbeta_i to esum[(ii - ib) WAVES + wave].
+// Ends with a barrier.
 template <int T, int TILE, int LC>
 __device__ inline void gd_group(const DScene& S, const DGroup& G, int n0, Slot sl, AdjSlot as,
                                 const DImage* __restrict__ I, const PermEntry* __restrict__ perm, const float4* tab,
@@ -392,13 +393,16 @@ __device__ inline void gd_group(const DScene& S, const DGroup& G, int n0, Slot s
     const float wy = valid ? gyc[n] : 0.0f;
     int cR = 0, cl = 0;
     float cv = 0.0f;
+    CrLane<1> crl;
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
         const DImage im = perm_image(I, perm, ii);
         if (im.R != cR) {
             cR = im.R;
             const int k = div_exact(nc, cR, im.invR);
-            cl = k - div_exact(n0, cR, im.invR);
+            const int k_lo = div_exact(n0, cR, im.invR);
+            cl = k - k_lo;
             cv = (float)(nc - k * cR);
+            cr_lane<1>(crl, n, nc, n_out, cR, im.invR, k, k_lo, hv * WAVES + wave, lane);
         }
         const Seg sg = sl.seg[im.loc + cl];
         const int Ks = sl.K[im.loc + cl];
@@ -453,7 +457,8 @@ __device__ inline void gd_group(const DScene& S, const DGroup& G, int n0, Slot s
             }
         }
         const int li = ii - G.img_begin;
-        as.dbar[li * TILE + hv * NT + tid] = valid ? Db : 0.0f;
+        const float db[1] = {valid ? Db : 0.0f};
+        cr_partials<1>(crl, db, as.dpart + im.loc + li * (TILE / 64));
         E = wave_sum_dpp(E);
         if (lane == 0) as.esum[li * (TILE / 64) + hv * WAVES + wave] = E;
     }
@@ -493,6 +498,7 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
     const float Lf = (float)L;
     int cR = 0, c0 = 0, c1 = 0;
     float cv = 0.0f;
+    CrLane<2> crl;
     for (int ii = G.img_begin; ii < G.img_end; ++ii) {
         const DImage im = perm_image(I, perm, ii);
         if (im.R != cR) {
@@ -501,10 +507,13 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
                 c0 = nc - n0;
                 c1 = min(nc + 1, n_out - 1) - n0;
                 cv = 0.0f;
+                cr_lane<2>(crl, n, nc, n_out, 1, 1.0f, nc, n0, wave, lane);
             } else {
                 const int k0 = div_exact(nc, cR, im.invR);
-                c0 = c1 = k0 - div_exact(n0, cR, im.invR);
+                const int k_lo = div_exact(n0, cR, im.invR);
+                c0 = c1 = k0 - k_lo;
                 cv = (float)(nc - k0 * cR);
+                cr_lane<2>(crl, n, nc, n_out, cR, im.invR, k0, k_lo, wave, lane);
             }
         }
         const Seg sg = sl.seg[im.loc + c0];
@@ -540,7 +549,8 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
             }
         }
         const int li = ii - G.img_begin;
-        *(float2*)&as.dbar[li * TO + 2 * tid] = make_float2(ok0 ? Db0 : 0.0f, ok1 ? Db1 : 0.0f);
+        const float db[2] = {ok0 ? Db0 : 0.0f, ok1 ? Db1 : 0.0f};
+        cr_partials<2>(crl, db, as.dpart + im.loc + li * (TO / 128));
         E = wave_sum_dpp(E);
         if (lane == 0) {
             as.esum[li * (TO / 64) + 2 * wave] = E;
@@ -595,7 +605,7 @@ __global__ __launch_bounds__(RB == 1 ? kAdjThreads : TO / 2) void k_adjp(
                 const float wy1 = n + 1 < n_out ? gyc[n + 1] : 0.0f;
                 gd_group2<T, NT, LC>(S, G, n0, sl, as, I, pv.perm, tab, xw, L, x, wy0, wy1, pa.ghat, bad);
             }
-            param_group<NT, TO>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
+            param_group<NT, TO, RB>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
         }
         param_item_end<NT>(S, w, pl, acc, pa);
         if (bad) atomicOr(status, kStatusWindow);

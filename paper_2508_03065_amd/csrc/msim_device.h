@@ -658,11 +658,92 @@ __device__ __forceinline__ void tile_tracks(const DScene& S, int mic, const DIma
 __device__ inline AdjSlot adj_slot_at(const TrackArgs& ta, int gmax, int TO, int wg)
 {
     char* b = ta.slots + (int64_t)wg * ta.slot_bytes + slot_extra_off(ta.slot_segs, gmax);
+    const int64_t np = slot_al(((int64_t)ta.slot_segs + (int64_t)gmax * (TO / 64)) * 16);
     AdjSlot a;
-    a.dbar = (float*)b;
-    a.esum = (float*)(b + slot_al((int64_t)gmax * TO * 4));
-    a.dseg = (float4*)(b + slot_al((int64_t)gmax * TO * 4) + slot_al((int64_t)gmax * 16 * 4));
+    a.dpart = (float4*)b;
+    a.esum = (float*)(b + np);
+    a.dseg = (float4*)(b + np + slot_al((int64_t)gmax * 16 * 4));
     return a;
+}
+
+// Catmull-Rom transpose partials.  The track parameters need, per segment k of
+// an image (outputs n in [kR, kR + R)), the sums
+//   S_q(k) = sum_n w_q(u_n) dL/dD(n),  u_n = (n - kR) / R,  q = 0..3,
+// w_q the uniform Catmull-Rom basis weights of D_{k-1} .. D_{k+2}.  The gain and
+// delay adjoints hold dL/dD with one lane per output, or per pair of outputs
+// (RB = 2: the second output of a pair that starts the next segment is taken at
+// u = 1 of the first one's, which weights the same grid point).  Over a chunk of
+// 64 lanes the lanes' segment index does not decrease, so a segmented inclusive
+// scan by DPP leaves the sum of each run of equal segments in the run's last
+// lane, which stores it as the (segment, chunk) partial at index (k - k_lo) + c
+// of the image's partials: consecutive chunks share at most one segment, so
+// distinct pairs get distinct indices.  The per-lane state depends only on the
+// lane's output, R and the tile, and is kept while consecutive images share R.
+template <int RB>
+struct CrLane {
+    float w[RB][4];   // basis weights at the lane's outputs
+    float m[6];       // scan masks: 1 where the step's source lane is in this lane's segment
+    int pidx;         // partial index (k - k_lo) + chunk, or -1 when the lane ends no run
+};
+
+__device__ __forceinline__ void cr_weights(float u, float* w)
+{
+    w[0] = 0.5f * u * fmaf(u, 2.0f - u, -1.0f);
+    w[1] = fmaf(u * u, fmaf(1.5f, u, -2.5f), 1.0f);
+    w[2] = 0.5f * u * fmaf(u, fmaf(-3.0f, u, 4.0f), 1.0f);
+    w[3] = 0.5f * u * u * (u - 1.0f);
+}
+
+// State of the lane whose first output is n (unclamped; nc = min(n, n_out - 1)),
+// in chunk c of the tile, for an image at rate R: k = nc / R its segment, k_lo
+// the tile's first, cv = nc - kR.
+template <int RB>
+__device__ __forceinline__ void cr_lane(CrLane<RB>& L, int n, int nc, int n_out, int R, float invR, int k, int k_lo,
+                                        int c, int lane)
+{
+    const float cv = (float)(nc - k * R);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) cr_weights((cv + (float)r) * invR, L.w[r]);
+    // source lane l - s is in this lane's segment iff its first output n - s RB
+    // (clamped like n) is >= kR, i.e. iff n - kR >= s RB
+    const int jj = n - k * R;
+    L.m[0] = jj >= RB ? 1.0f : 0.0f;
+    L.m[1] = jj >= 2 * RB ? 1.0f : 0.0f;
+    L.m[2] = jj >= 4 * RB ? 1.0f : 0.0f;
+    L.m[3] = jj >= 8 * RB ? 1.0f : 0.0f;
+    L.m[4] = jj >= ((lane & 15) + 1) * RB ? 1.0f : 0.0f;   // from lane 15 of the row before (rows 1, 3)
+    L.m[5] = jj >= (lane - 31) * RB ? 1.0f : 0.0f;         // from lane 31 (rows 2, 3)
+    const int nn = min(n + RB, n_out - 1);
+    const bool end = lane == 63 || nn - k * R >= R;
+    L.pidx = end ? (k - k_lo) + c : -1;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void cr_step(float (&v)[4], float m)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = fmaf(dpp_mov<CTRL, ROW_MASK>(v[q]), m, v[q]);
+}
+
+// Adds the lane's dL/dD values db[r] (its RB outputs) into the image's partials
+// (dpart: the image's first partial).
+template <int RB>
+__device__ __forceinline__ void cr_partials(const CrLane<RB>& L, const float* db, float4* dpart)
+{
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = L.w[0][q] * db[0];
+#pragma unroll
+        for (int r = 1; r < RB; ++r) v[q] = fmaf(L.w[r][q], db[r], v[q]);
+    }
+    cr_step<0x111, 0xF>(v, L.m[0]);   // row_shr:1
+    cr_step<0x112, 0xF>(v, L.m[1]);   // row_shr:2
+    cr_step<0x114, 0xF>(v, L.m[2]);   // row_shr:4
+    cr_step<0x118, 0xF>(v, L.m[3]);   // row_shr:8
+    cr_step<0x142, 0xA>(v, L.m[4]);   // row_bcast:15 into rows 1 and 3
+    cr_step<0x143, 0xC>(v, L.m[5]);   // row_bcast:31 into rows 2 and 3
+    if (L.pidx >= 0) dpart[L.pidx] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // Per-thread dL/dbeta_w partials of a work item.
@@ -674,11 +755,13 @@ struct ParamAcc {
 // few path pieces; more take further passes).
 constexpr int kKnotWin = 4;
 
-// pl (LDS): [kMaxGradKnots][3] knot sums, then [16 waves][12] reduction scratch.
+// pl (LDS): per wave [3 kMaxGradKnots] knot sums (each wave adds its own), then
+// [waves][12] reduction scratch.
 template <int NT>
 __device__ inline void param_item_begin(double* pl, ParamAcc& acc)
 {
-    for (int k = threadIdx.x; k < 3 * kMaxGradKnots; k += NT) pl[k] = 0.0;
+    static_assert(NT / 64 <= kParamWaves, "parameter LDS holds kParamWaves waves");
+    for (int k = threadIdx.x; k < (NT / 64) * 3 * kMaxGradKnots; k += NT) pl[k] = 0.0;
 #pragma unroll
     for (int w = 0; w < 6; ++w) acc.bw[w] = 0.0;
 }
@@ -703,24 +786,26 @@ __device__ inline double block_sum12(const double* v, int n, double* red, int v_
 }
 
 // The in-tile parameter reductions of one delay group (its tracks in the slot,
-// dL/dD of its image samples over the tile [n0, n_hi) in as.dbar, the wave sums
-// of dL/dbeta_i in as.esum; lsc: the group's grid and segment offsets):
+// the Catmull-Rom partials of its images over the tile [n0, n_hi) in as.dpart,
+// the wave sums of dL/dbeta_i in as.esum; lsc: the group's grid and segment
+// offsets; RB outputs per lane in the adjoint that wrote the partials):
 //  1. dL/dbeta_w += (d beta_i / d beta_w) dL/dbeta_i, per image (thread-owned);
-//  2. per segment k of the tile, the Catmull-Rom basis weights at u = (n - kR)/R
-//     times dL/dD(n), summed over the segment's outputs in the tile (as.dseg);
+//  2. per segment k of the tile, S_q(k) = the sum of its (segment, chunk)
+//     partials in chunk order (as.dseg);
 //  3. per grid point g, dL/dtau_g = fs * the weights of the segments that use
 //     D_g, then dtau_g / d p(t_e) for the source position at the emission time
 //     t_e = t_g - tau_g (retarded: S^T u / (c + u . S p'(t_e)), u the unit vector
 //     mic -> image; instantaneous: S^T u / c), split onto the two knots of t_e's
-//     path piece and summed into the item's knot sums in LDS (pl).
+//     path piece and summed by each wave into its knot sums in LDS (pl).
 // The tile's outputs of a segment belong to this item; the other outputs of a
 // segment that straddles the tile belong to the neighbouring item, whose row
 // holds their part.  Starts after and ends with a barrier.
-template <int NT, int TO>
+template <int NT, int TO, int RB>
 __device__ inline void param_group(const DScene& S, int mic, const DGroup& G, int n0, int n_hi, Slot sl, AdjSlot as,
                                    const int* lsc, const DImage* __restrict__ I, const PermEntry* __restrict__ perm,
                                    const TrackArgs& ta, const ParamArgs& pa, double* pl, ParamAcc& acc)
 {
+    constexpr int NCH = TO / (64 * RB);         // 64-lane chunks of the tile
     const int tid = threadIdx.x;
     const int ib = G.img_begin, cnt = G.img_end - ib;
     const int* goff = lsc;
@@ -745,26 +830,39 @@ __device__ inline void param_group(const DScene& S, int mic, const DGroup& G, in
         }
     const bool src = pa.want_src && S.src.kind == kTrajPwl && S.src_knots > 0;
     if (!src) return;
-    for (int f = tid; f < soff[cnt]; f += NT) {
-        const int i = off_index(soff, cnt, f);
-        const int R = I[perm[ib + i].img].R;
-        const int k_lo = n0 / R, k_hi = (n_hi - 1) / R;
-        const int j = f - soff[i];
-        if (j > k_hi - k_lo) continue;
-        const int k = k_lo + j;
-        const int na = max(k * R, n0), nb = min(k * R + R, n_hi);
-        const float* db = as.dbar + i * TO - n0;
-        const float iR = 1.0f / (float)R;
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-        for (int n = na; n < nb; ++n) {
-            const float d = db[n];
-            const float u = (float)(n - k * R) * iR;
-            s0 = fmaf(d, 0.5f * u * fmaf(u, 2.0f - u, -1.0f), s0);
-            s1 = fmaf(d, fmaf(u * u, fmaf(1.5f, u, -2.5f), 1.0f), s1);
-            s2 = fmaf(d, 0.5f * u * fmaf(u, fmaf(-3.0f, u, 4.0f), 1.0f), s2);
-            s3 = fmaf(d, 0.5f * u * u * (u - 1.0f), s3);
+    const int n_out = (int)S.n_out;
+    {
+        // each thread a run of consecutive segments, walking the image index
+        const int total = soff[cnt];
+        const int run = (total + NT - 1) / NT;
+        const int f0 = tid * run, f1 = min(f0 + run, total);
+        int i = f0 < f1 ? off_index(soff, cnt, f0) : 0;
+        for (int f = f0; f < f1; ++f) {
+            while (i + 1 < cnt && f >= soff[i + 1]) ++i;
+            const int R = I[perm[ib + i].img].R;
+            const int k_lo = n0 / R, k_hi = (n_hi - 1) / R;
+            const int j = f - soff[i];
+            if (j > k_hi - k_lo) continue;
+            const int k = k_lo + j;
+            // chunk c holds the lanes with first outputs n0 + 64 RB c + RB l; it has
+            // a partial of segment k iff one of them lies in [kR, kR + R)
+            const float4* dp = as.dpart + soff[i] + i * NCH + j;
+            float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int c = max(0, (k * R - n0 - 63 * RB) / (64 * RB)); c < NCH; ++c) {
+                const int first = n0 + 64 * RB * c;
+                if (first > k * R + R - 1 || first >= n_hi) break;
+                const int last = min(first + 63 * RB, n_out - 1);
+                const int a = max(k * R, first), b = min(k * R + R - 1, last);
+                const int na = RB == 1 ? a : a + ((first - a) % RB + RB) % RB;
+                if (na > b) continue;
+                const float4 p = dp[c];
+                t.x += p.x;
+                t.y += p.y;
+                t.z += p.z;
+                t.w += p.w;
+            }
+            as.dseg[f] = t;
         }
-        as.dseg[f] = make_float4(s0, s1, s2, s3);
     }
     __syncthreads();
     // knots this group's emission times can touch
@@ -774,13 +872,19 @@ __device__ inline void param_group(const DScene& S, int mic, const DGroup& G, in
     const int nk = S.src.n_points;
     const int a_lo = max(0, traj_seg(S.src, ta.knots, t_min));
     const int a_hi = min(nk - 1, max(0, traj_seg(S.src, ta.knots, t_max)) + 1);
-    double* red = pl + 3 * kMaxGradKnots;
+    const int wave = tid >> 6, lane = tid & 63;
+    double* pw = pl + wave * 3 * kMaxGradKnots;
+    const int total = goff[cnt];
+    const int run = (total + NT - 1) / NT;
+    const int f0 = tid * run, f1 = min(f0 + run, total);
+    const int i0 = f0 < f1 ? off_index(goff, cnt, f0) : 0;
     for (int kb = a_lo; kb <= a_hi; kb += kKnotWin) {
         double ak[kKnotWin * 3];
 #pragma unroll
         for (int q = 0; q < kKnotWin * 3; ++q) ak[q] = 0.0;
-        for (int f = tid; f < goff[cnt]; f += NT) {
-            const int i = off_index(goff, cnt, f);
+        int i = i0;
+        for (int f = f0; f < f1; ++f) {
+            while (i + 1 < cnt && f >= goff[i + 1]) ++i;
             const DImage& im = I[perm[ib + i].img];
             const int R = im.R;
             const int k_lo = n0 / R, k_hi = (n_hi - 1) / R;
@@ -824,24 +928,35 @@ __device__ inline void param_group(const DScene& S, int mic, const DGroup& G, in
                 for (int ax = 0; ax < 3; ++ax) ak[3 * jj + ax] += fw * (sc * sgn[ax] * e[ax]);
             }
         }
-        const double tot = block_sum12<NT>(ak, kKnotWin * 3, red, tid);
-        if (tid < kKnotWin * 3 && kb + tid / 3 < nk && kb + tid / 3 < kMaxGradKnots) pl[3 * kb + tid] += tot;
-        __syncthreads();
+        // the wave's sums into its own knot sums (no other wave writes them)
+#pragma unroll
+        for (int q = 0; q < kKnotWin * 3; ++q) {
+            const int kk = kb + q / 3;
+            if (kk >= nk || kk >= kMaxGradKnots) break;
+            const double s = wave_sum_d(ak[q]);
+            if (lane == 0) pw[3 * kb + q] += s;
+        }
     }
+    __syncthreads();
 }
 
 // Writes the item's row of parameter partials: dL/dbeta_w (summed over the
-// workgroup in a fixed order) and the knot sums.
+// workgroup in a fixed order) and the knot sums (the waves' in order).
 template <int NT>
 __device__ inline void param_item_end(const DScene& S, const WorkItem& w, double* pl, ParamAcc& acc,
                                       const ParamArgs& pa)
 {
-    double* red = pl + 3 * kMaxGradKnots;
+    constexpr int WAVES = NT / 64;
+    double* red = pl + WAVES * 3 * kMaxGradKnots;
     __syncthreads();
     const double tb = block_sum12<NT>(acc.bw, 6, red, threadIdx.x);
     double* row = pa.rows + (S.row_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_tiles + w.tile) * kRowWidth;
     if (threadIdx.x < 6) row[threadIdx.x] = tb;
-    for (int k = threadIdx.x; k < 3 * kMaxGradKnots; k += NT) row[6 + k] = pl[k];
+    for (int k = threadIdx.x; k < 3 * kMaxGradKnots; k += NT) {
+        double t = 0.0;
+        for (int v = 0; v < WAVES; ++v) t += pl[v * 3 * kMaxGradKnots + k];
+        row[6 + k] = t;
+    }
     __syncthreads();
 }
 

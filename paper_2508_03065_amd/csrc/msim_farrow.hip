@@ -422,8 +422,9 @@ size_t farrow_u_lds_bytes(int window) { return (size_t)window * sizeof(float) + 
 
 // Gain and delay adjoints of one delay group, Farrow form, one output per lane of
 // the tile [n0, n0 + NT): per image sample r = sum_k v_k s^k and dr/ds by Horner's
-// rule for value and derivative; dL/dD to the slot's dbar, the wave sums of
-// dL/dbeta_i to esum.  Ends with a barrier.
+// rule for value and derivative; dL/dD into the image's Catmull-Rom partials in
+// the slot (cr_partials), the wave sums of dL/dbeta_i to esum.  Ends with a
+// barrier.
 template <int TILE, bool HI>
 __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0, int T, Slot sl, AdjSlot as,
                                        const DImage* __restrict__ I, const PermEntry* __restrict__ perm, float4* vw,
@@ -446,13 +447,16 @@ __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0,
         const float wy = valid ? gyc[n] : 0.0f;
         int cR = 0, cl = 0;
         float cv = 0.0f;
+        CrLane<1> crl;
         for (int ii = G.img_begin; ii < G.img_end; ++ii) {
             const DImage im = perm_image(I, perm, ii);
             if (im.R != cR) {
                 cR = im.R;
                 const int k = div_exact(nc, cR, im.invR);
-                cl = k - div_exact(n0, cR, im.invR);
+                const int k_lo = div_exact(n0, cR, im.invR);
+                cl = k - k_lo;
                 cv = (float)(nc - k * cR);
+                cr_lane<1>(crl, n, nc, n_out, cR, im.invR, k, k_lo, hv * WAVES + wave, lane);
             }
             const Seg sg = sl.seg[im.loc + cl];
             const int Ks = sl.K[im.loc + cl];
@@ -479,7 +483,8 @@ __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0,
                 Db = wy * im.gfac * iD * fmaf(2.0f, dr, -r * iD);
             }
             const int li = ii - G.img_begin;
-            as.dbar[li * TILE + hv * NT + tid] = valid ? Db : 0.0f;
+            const float db[1] = {valid ? Db : 0.0f};
+            cr_partials<1>(crl, db, as.dpart + im.loc + li * (TILE / 64));
             E = wave_sum_dpp(E);
             if (lane == 0) as.esum[li * (TILE / 64) + hv * WAVES + wave] = E;
         }
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, c
             tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi,
                             group_span(TILE, G.dmin, G.dmax), sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, v, gyc, pa.ghat, bad);
-            param_group<NT, TILE>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
+            param_group<NT, TILE, 1>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
         }
         param_item_end<NT>(S, w, pl, acc, pa);
         if (bad) atomicOr(status, kStatusWindow);

@@ -121,13 +121,15 @@ __host__ __device__ constexpr int64_t slot_extra_off(int slot_segs, int gmax)
            slot_al(((int64_t)slot_segs + 3 * (int64_t)gmax) * 8);
 }
 
-// Adjoint slot, after the tracks: dL/dD of the group's image samples over the
-// tile (floats, [gmax][TO]), the per-wave sums of dL/dbeta_i ([gmax][16]), and
-// the Catmull-Rom transpose sums of every segment (float4 per slot segment).
+// Adjoint slot, after the tracks: the Catmull-Rom transpose partials of the
+// group's images, one float4 per (segment, 64-lane chunk of the tile) pair an
+// image touches (at most its slot segments plus TO / 64 more), the per-wave sums
+// of dL/dbeta_i ([gmax][16]), and the segments' transpose sums (float4 per slot
+// segment).
 __host__ __device__ constexpr int64_t adj_slot_bytes(int slot_segs, int gmax, int TO)
 {
-    return slot_extra_off(slot_segs, gmax) + slot_al((int64_t)gmax * TO * 4) + slot_al((int64_t)gmax * 16 * 4) +
-           slot_al((int64_t)slot_segs * 16);
+    return slot_extra_off(slot_segs, gmax) + slot_al(((int64_t)slot_segs + (int64_t)gmax * (TO / 64)) * 16) +
+           slot_al((int64_t)gmax * 16 * 4) + slot_al((int64_t)slot_segs * 16);
 }
 
 // Threads of the backward kernels' workgroups (their register budget needs it).
@@ -141,9 +143,10 @@ constexpr size_t kLscBytes = (size_t)8 * (kMaxGroup + 2);
 // (6) then dL/d(knot j, axis a) at 6 + 3 j + a.
 constexpr int kMaxGradKnots = 32;
 constexpr int kRowWidth = 6 + 3 * kMaxGradKnots;
-// LDS of the parameter accumulators: the knots' sums, then per wave 12 doubles
-// of block-reduction scratch.
-constexpr size_t kParamLdsBytes = (size_t)8 * (3 * kMaxGradKnots + 16 * 12);
+// LDS of the parameter accumulators: per wave its knot sums, then per wave 12
+// doubles of block-reduction scratch (backward workgroups have at most 8 waves).
+constexpr int kParamWaves = 8;
+constexpr size_t kParamLdsBytes = (size_t)8 * kParamWaves * (3 * kMaxGradKnots + 12);
 
 // Floats per source position of the Farrow-filtered signals (v_0..v_11, zero padded).
 constexpr int kFarrowStride = 12;
@@ -200,7 +203,7 @@ struct TrackArgs {
 
 // The adjoint part of a workgroup's slot.
 struct AdjSlot {
-    float* dbar;
+    float4* dpart;
     float* esum;
     float4* dseg;
 };
