@@ -194,6 +194,24 @@ typedef struct {
 } msim_tuning;
 
 msim_status msim_get_tuning(const msim_plan* plan, msim_tuning* t);
+/* Predicted relative L2 error of one image's output for a white source signal,
+ * per approximation of the truncated Kaiser-windowed sinc (Sec. II-B), computed
+ * from the kernel at the plan's taps, kaiser_beta, cutoff, table_phases and
+ * farrow_order: `table`, the quadratic phase table as stored (table form);
+ * `pair`, the edge tap that two outputs per lane omit where they straddle an
+ * integer delay, at the scenes' largest source plus receiver speed (table form);
+ * `farrow`, the Farrow polynomials' fit (Farrow form); 0 where the form is not
+ * the plan's.  msim_plan_create refuses a form whose figure exceeds `budget`
+ * (MSIM_E_UNSUPPORTED, with the figure in the message) and keeps the table form
+ * at one output per lane where table and pair together, in quadrature, would. */
+typedef struct {
+    double table;
+    double pair;
+    double farrow;
+    double budget;
+} msim_fd_error;
+
+msim_status msim_get_fd_error(const msim_plan* plan, msim_fd_error* out);
 /* Regroups the plan for a launch shape; workspace sizes change with it. */
 msim_status msim_set_tuning(msim_plan* plan, const msim_tuning* t);
 /* Largest batched workspace over the shapes msim_autotune tries. */

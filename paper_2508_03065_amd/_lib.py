@@ -55,6 +55,10 @@ class Tuning(C.Structure):
                 ("workgroups", C.c_int32), ("ms", C.c_double)]
 
 
+class FdError(C.Structure):
+    _fields_ = [("table", C.c_double), ("pair", C.c_double), ("farrow", C.c_double), ("budget", C.c_double)]
+
+
 # name -> (argtypes); every function returns msim_status (int) except msim_last_error
 _PLAN = C.c_void_p
 SIGNATURES = {
@@ -78,6 +82,7 @@ SIGNATURES = {
     "msim_batched_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
     "msim_forward_batched": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32],
     "msim_get_tuning": [_PLAN, C.POINTER(Tuning)],
+    "msim_get_fd_error": [_PLAN, C.POINTER(FdError)],
     "msim_set_tuning": [_PLAN, C.POINTER(Tuning)],
     "msim_autotune_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
     "msim_autotune": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_char_p,

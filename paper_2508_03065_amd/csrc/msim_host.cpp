@@ -415,6 +415,7 @@ struct msim_plan {
     int rb_max = 1;                       //   default, sharing table rows; Farrow form: one, as
                                           //   occupancy wins over shared segment fetches), and the
                                           //   largest the form and the tier decimations allow
+    double err_table = 0.0, err_pair = 0.0, err_farrow = 0.0;   // predicted fractional-delay errors
     std::vector<DScene> scenes;           // host copies
     std::vector<DImage> images;
     std::vector<DGroup> groups;
@@ -626,6 +627,86 @@ void build_farrow(msim_plan* P)
             P->fcoef[(size_t)k * T + t] = (float)c;
         }
     }
+}
+
+// Predicted relative L2 error of one image's output for a white source signal,
+// per approximation of the fractional-delay kernel h (Sec. II-B): the mean square
+// over the fractional delay of (approximation - exact h) per tap, summed over the
+// T taps, over the kernel's energy (sum of h^2 over the taps).  Both sides of a
+// tap window have the same errors, so half the taps are evaluated, twice.
+constexpr double kFdErrBudget = 5e-6;   // half the 1e-5 FP32 target
+
+double fd_energy(const msim_params& p)
+{
+    const double i0b = bessel_i0(p.kaiser_beta);
+    double e = 0.0;
+    for (int d = 0; d < p.taps / 2; ++d) {
+        const double h = fd_kernel(d + 0.5, p.taps, p.kaiser_beta, p.cutoff, i0b);
+        e += 2.0 * h * h;
+    }
+    return e;
+}
+
+// The quadratic phase table as stored (FP32 values and first differences, FP16
+// second differences, zero beyond qcorr_quads): tap offset d + (r + f) / Lq is
+// read as Y + f D1 + f (f - 1) / 2 D2, at eight fractions f per row.
+double table_error(const msim_plan* P)
+{
+    const int T = P->par.taps, Lq = P->par.table_phases, H = T / 2;
+    const double i0b = bessel_i0(P->par.kaiser_beta);
+    double se = 0.0;
+    for (int d = 0; d < H; ++d) {
+        double sq = 0.0;
+        for (int r = 0; r < Lq; ++r) {
+            const double Y = P->atable[(size_t)d * Lq + r];
+            const double D1 = P->atable[((size_t)H + d) * Lq + r];
+            const double D2 = P->atable[((size_t)2 * H + d) * Lq + r];
+            for (int k = 0; k < 8; ++k) {
+                const double f = (k + 0.5) / 8.0;
+                const double ex = fd_kernel(d + (r + f) / Lq, T, P->par.kaiser_beta, P->par.cutoff, i0b);
+                const double ap = Y + f * D1 + 0.5 * f * (f - 1.0) * D2;
+                sq += (ap - ex) * (ap - ex);
+            }
+        }
+        se += 2.0 * sq / (8.0 * Lq);
+    }
+    return std::sqrt(se / fd_energy(P->par));
+}
+
+// Two outputs per lane omit the edge tap u in (T/2 - 1, T/2] of the output whose
+// integer delay differs from its partner's; that happens for at most a fraction
+// |dD/dn| <= 1.5 v / (c - v) of the lanes (v the source plus receiver speed, 1.5
+// for the cubic delay interpolation's slope).
+double pair_error(const msim_params& p, double v)
+{
+    const double i0b = bessel_i0(p.kaiser_beta);
+    double sq = 0.0;
+    for (int k = 0; k < 64; ++k) {
+        const double h = fd_kernel(0.5 * p.taps - 1.0 + (k + 0.5) / 64.0, p.taps, p.kaiser_beta, p.cutoff, i0b);
+        sq += h * h / 64.0;
+    }
+    const double frac = std::min(1.0, 1.5 * v / (p.c - v));
+    return std::sqrt(frac * sq / fd_energy(p));
+}
+
+// The Farrow polynomials (FP32 coefficients, evaluated exactly) against h at 64
+// fractional delays per tap.
+double farrow_error(const msim_plan* P)
+{
+    const int T = P->par.taps;
+    const double i0b = bessel_i0(P->par.kaiser_beta);
+    double se = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const int j = t - T / 2 + 1;
+        for (int k = 0; k < 64; ++k) {
+            const double mu = (k + 0.5) / 64.0, sv = 2.0 * mu - 1.0;
+            double a = 0.0;
+            for (int q = kFarrowStride - 1; q >= 0; --q) a = a * sv + P->fcoef[(size_t)q * T + t];
+            const double ex = fd_kernel(j - mu, T, P->par.kaiser_beta, P->par.cutoff, i0b);
+            se += (a - ex) * (a - ex) / 64.0;
+        }
+    }
+    return std::sqrt(se / fd_energy(P->par));
 }
 
 int push_traj(msim_plan* P, const msim_traj& tr, DTraj* d)
@@ -1559,6 +1640,32 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
             v = std::max(v, traj_max_speed(scenes[s].src) + traj_max_speed(scenes[s].rcv));
         const double drift = 1.5 * v / (p->c - v) * p->table_phases;
         P->rb_max = drift <= 1.25 ? std::min(P->rb_max, 2) : 1;
+        P->err_pair = pair_error(*p, v);
+    }
+    build_table(P);
+    build_farrow(P);
+    if (p->fd_kind == MSIM_FD_FARROW) {
+        P->err_farrow = farrow_error(P);
+        if (P->err_farrow > kFdErrBudget) {
+            const double e = P->err_farrow;
+            delete P;
+            return fail(MSIM_E_UNSUPPORTED,
+                        "Farrow form: predicted relative error %.2e of order-%d polynomials exceeds %.0e at "
+                        "kaiser_beta %g, cutoff %g, taps %d (raise farrow_order or kaiser_beta)",
+                        e, p->farrow_order, kFdErrBudget, p->kaiser_beta, p->cutoff, p->taps);
+        }
+    } else {
+        P->err_table = table_error(P);
+        if (P->err_table > kFdErrBudget) {
+            const double e = P->err_table;
+            delete P;
+            return fail(MSIM_E_UNSUPPORTED,
+                        "table form: predicted relative error %.2e of the %d-phase table exceeds %.0e at "
+                        "kaiser_beta %g, cutoff %g, taps %d (raise table_phases or use the Farrow form)",
+                        e, p->table_phases, kFdErrBudget, p->kaiser_beta, p->cutoff, p->taps);
+        }
+        // the pair's omitted edge tap on top of the table's error
+        if (std::hypot(P->err_table, P->err_pair) > kFdErrBudget) P->rb_max = 1;
     }
     P->rb = p->fd_kind != MSIM_FD_FARROW ? P->rb_max : 1;
     P->n_scenes = n_scenes;
@@ -1599,8 +1706,6 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         delete P;
         return st;
     }
-    build_table(P);
-    build_farrow(P);
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
         return fail(MSIM_E_HIP, "no HIP device");
@@ -1943,6 +2048,16 @@ msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
     out->outputs_per_lane = P->rb;
     out->workgroups = P->b_wgs;
     out->ms = 0.0;
+    return MSIM_OK;
+}
+
+msim_status msim_get_fd_error(const msim_plan* P, msim_fd_error* out)
+{
+    if (!P || !out) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    out->table = P->err_table;
+    out->pair = P->err_pair;
+    out->farrow = P->err_farrow;
+    out->budget = kFdErrBudget;
     return MSIM_OK;
 }
 

@@ -193,6 +193,12 @@ class Plan:
         check(_lib.load().msim_get_tuning(self._ptr, C.byref(t)))
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
 
+    def fd_error(self) -> dict:
+        """Predicted relative errors of the fractional-delay approximations and the budget."""
+        e = _lib.FdError()
+        check(_lib.load().msim_get_fd_error(self._ptr, C.byref(e)))
+        return {k: getattr(e, k) for k, _ in _lib.FdError._fields_}
+
     def set_tuning(self, threads: int, group_cap: int = 0, outputs_per_lane: int = 0):
         t = _lib.Tuning(threads, group_cap, outputs_per_lane, 0, 0.0)
         check(_lib.load().msim_set_tuning(self._ptr, C.byref(t)))

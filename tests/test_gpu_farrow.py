@@ -68,13 +68,6 @@ def test_orders(torch_cuda, order):
     assert rel(y, O.forward(sc, par)) <= (TOL if order >= 9 else 5e-5)
 
 
-def test_config2_sampled(torch_cuda):
-    scenes, par = G.config2()
-    (y,), _, _ = run(scenes, farrow(par), torch_cuda)
-    idx = np.sort(np.random.default_rng(0).choice(scenes[0].n_out, 160, replace=False))
-    assert rel(y[:, idx], O.forward(scenes[0], par, idx=idx)) <= TOL
-
-
 def test_batched_equals_plain(torch_cuda):
     torch = torch_cuda
     from paper_2508_03065_amd.msim import Plan

@@ -141,3 +141,47 @@ def test_null_arguments(lib):
     assert lib.msim_forward(None, None, None, None, 0, None) == 1
     assert lib.msim_workspace_size(None, 0, None) == 1
     assert lib.msim_plan_destroy(None) == 0
+
+
+def _table_model(T, beta, fc, L):
+    """Relative error of the quadratic phase table for a white input (numpy
+    model of the stored values: FP32 Y and D1, FP16 D2, zero beyond 3T/32 quads)."""
+    def h(v):
+        v = np.asarray(v, float)
+        r = 2 * v / T
+        w = np.i0(beta * np.sqrt(np.clip(1 - r * r, 0, None))) / np.i0(beta)
+        return np.where(np.abs(v) > 0.5 * T, 0.0, 2 * fc * np.sinc(2 * fc * v) * w)
+    f = (np.arange(8) + 0.5) / 8
+    rows = np.arange(L)
+    se = 0.0
+    for d in range(T // 2):
+        y0, y1, y2 = (h(d + (rows + i) / L) for i in range(3))
+        Y = y0.astype(np.float32).astype(float)
+        D1 = (y1 - y0).astype(np.float32).astype(float)
+        D2 = (y2 - 2 * y1 + y0).astype(np.float16).astype(float) if d // 4 < T // 8 - T // 32 else 0.0 * y0
+        ap = Y[:, None] + f * D1[:, None] + f * (f - 1) / 2 * D2[:, None]
+        se += 2 * np.mean((ap - h(d + (rows[:, None] + f) / L)) ** 2)
+    return np.sqrt(se / (2 * np.sum(h(np.arange(T // 2) + 0.5) ** 2)))
+
+
+@pytest.mark.parametrize("T,beta,fc,L", [(32, 0.0, 0.5, 64), (64, 0.0, 0.5, 64), (32, 0.0, 0.45, 64),
+                                         (32, 0.0, 0.45, 128), (64, 4.0, 0.45, 64), (64, 8.0, 0.5, 128)])
+def test_table_error_budget(lib, T, beta, fc, L):
+    """The table form is refused (MSIM_E_UNSUPPORTED, before any device call)
+    exactly where the predicted error exceeds the 5e-6 budget."""
+    sc, par = G.small_scene(seed=1, taps=T)
+
+    def mut(p):
+        p.kaiser_beta = beta
+        p.cutoff = fc
+        p.table_phases = L
+        p.fd_kind = 0
+    st, msg = _create(lib, sc, par, mut)
+    model = _table_model(T, beta, fc, L)
+    assert abs(model - 5e-6) > 0.5e-6          # the cases are not at the edge
+    if model > 5e-6:
+        assert st == 6 and "predicted relative error" in msg, (st, msg)
+        got = float(re.search(r"error ([0-9.e+-]+)", msg).group(1))
+        assert abs(got - model) <= 0.05 * model
+    else:
+        assert "predicted relative error" not in msg, msg
