@@ -1,23 +1,29 @@
 """Throughput of the moving image-source synthesis on one MI355X.
 
-A step is one forward synthesis of the whole workload (delay tracks, gather-
-reduce over images x outputs x taps, group reduction) with the source signal
-already resident in HBM.  Prints one JSON line.
+Headline workload: the large batched configuration (64 scenes of a 12x9x4 m
+room, 48 kHz, 10 s sources, moving source and receiver, 8-mic circular array,
+every image up to order 20 (11521 per scene), tiers 48 k / 3 k / 300 Hz, 96-tap
+sinc).  A step is one batched forward (one persistent launch per kernel, replayed
+from a HIP graph) over a batch of --scenes of those 64 scenes with the source
+signals already in HBM; a whole 64-scene batch takes about 16 such steps, longer
+than the driver's 20 timed steps allow.  Prints one JSON line.
 
 Metric: image-sample taps/s = sum over scenes, mics, images of (n_in + T - 1) * T
-taps per step / seconds per step.  Forward+backward counts four tap chains
-per forward tap (forward, dL/dx, the h chain and the h' chain of the gain and
+taps per step / seconds per step.  Forward+backward counts four tap chains per
+forward tap (forward, dL/dx, and the value and derivative chains of the gain and
 delay adjoints).  The Farrow form computes the same output (within the same
 tolerance) without visiting every tap; its rate is quoted in the same
-equivalent taps/s, and its kernel roofline uses the work it really does.
+equivalent taps/s, and its kernel rooflines count the work it really does.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -30,7 +36,10 @@ from paper_2508_03065_amd import scenegen as G  # noqa: E402
 
 PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
 PEAK_LDS = 256 * 256 * 2.4e9   # LDS reads, B/s: 256 CUs x 256 B/clk (b128) x 2.4 GHz
-FLOPS_PER_TAP = 4         # table form: two FMAs per tap (the interpolated coefficient, the multiply-add)
+
+# Algorithmic flops per tap (table form) or per image sample (Farrow form, order M).
+FLOPS_PER_TAP = 4             # forward, dL/dx: the interpolated coefficient and the multiply-add (2 FMAs)
+FLOPS_PER_TAP_GD = 8          # gain/delay adjoint: the value and the derivative chains
 
 
 def table_lds_per_tap(outputs_per_lane: int) -> float:
@@ -45,36 +54,46 @@ def farrow_lds_per_sample(order: int) -> int:
     return 40 if order <= 9 else 48
 
 
-def farrow_flops_per_sample(order: int) -> int:
-    """Farrow form, per image sample: Horner of degree M (M FMAs), the cubic delay
-    offset (3 FMAs), and the gain times the polynomial added to the output (1 FMA)."""
-    return 2 * (order + 3 + 1)
+def farrow_flops(order: int) -> dict:
+    """Farrow form, per image sample: forward = Horner of degree M (M FMAs), the cubic
+    delay offset (3 FMAs), the gain times the polynomial added to the output (1 FMA);
+    dL/dx gather = the M+1 sums u_k += (gy g) s^k and the M powers of s; gain/delay
+    adjoint = Horner for the value and its derivative (2M FMAs), the delay offset
+    (3) and the dL/dbeta_i and dL/dD products (3)."""
+    return {"fwd": 2 * (order + 4), "adjx": 2 * (2 * order + 1), "adjp": 2 * (2 * order + 6)}
 
 
 WORKLOADS = {
+    "config5": ("large batched: 12x9x4 m room, 48 kHz, 10 s, moving source and receiver (PWL, <= 2 m/s), "
+                "8-mic circular array r=5 cm, K=20 (11521 images), tiers 48k/3k/300 Hz, T=96", G.config5),
     "config2": ("paper-scale plain: 8x6x3.5 m room, K=12 (2625 images), 4 s at 16 kHz, "
                 "tiers 16k/1k/100 Hz, T=64, 1 mic", G.config2),
-    "config1": ("tiny plain: 5x4x3 m room, K=2 (25 images), 1 s at 16 kHz, full rate, T=32, 1 mic", G.config1),
 }
 FD_KINDS = {"table": 0, "farrow": 1}
-KERNEL_OF = {"table": ("k_synth_fwd", "msim_kernels.hip"), "farrow": ("k_farrow_fwd", "msim_farrow.hip")}
+KERNEL_OF = {"table": {"fwd": ("k_synth", "msim_kernels.hip"), "adjx": ("k_adjx", "msim_adjoint.hip"),
+                       "adjp": ("k_adjp", "msim_adjoint.hip")},
+             "farrow": {"fwd": ("k_farrow", "msim_farrow.hip"), "adjx": ("k_farrow_u", "msim_farrow.hip"),
+                        "adjp": ("k_farrow_gd", "msim_farrow.hip")}}
+PROFILE_KEY = {"fwd": "synth", "adjx": "adjx", "adjp": "adjp"}
 
 
 def with_fd(par, fd: str):
-    import dataclasses
     return dataclasses.replace(par, fd_kind=FD_KINDS[fd])
 
 
 def source_sha(fname: str) -> str:
-    with open(os.path.join(ROOT, "paper_2508_03065_amd", "csrc", fname), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for f in (fname, "msim_device.h", "msim_internal.h"):
+        with open(os.path.join(ROOT, "paper_2508_03065_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def pmc_traffic(kernel: str, workload: str, src: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     profiles/<kernel>__<workload>__hbm_pmc.md (FETCH_SIZE and WRITE_SIZE, scaled by
     the copy-kernel factors recorded there), or None when there is none or the
-    kernel's source has changed since the counters were taken."""
+    kernel's sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s__%s__hbm_pmc.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -86,14 +105,39 @@ def pmc_traffic(kernel: str, workload: str, src: str):
     return float(tb.group(1))
 
 
-def cpu_baseline(scenes, par, target_s: float = 15.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_SAMPLE = """
+import sys, time, json, numpy as np
+sys.path.insert(0, {root!r})
+from oracle import oracle as O
+from paper_2508_03065_amd import scenegen as G
+scenes, par = G.{gen}(n_scenes=1) if {gen!r} == "config5" else G.{gen}()
+sc = scenes[0]
+idx = np.sort(np.random.default_rng(7).choice(sc.n_out, {n}, replace=False))
+t0 = time.perf_counter()
+O.forward(sc, par, idx=idx)
+print(json.dumps({{"s": time.perf_counter() - t0}}))
+"""
+
+
+def cpu_baseline(workload: str, scenes, par, target_s: float = 15.0):
     """The FP64 oracle on the host cores, on a bounded sample of output samples
-    of the first scene (tier-emulating mode, every image, exact kernel)."""
+    of the first scene (tier-emulating mode, every image, exact kernel), and the
+    same on one core in a child process (OMP_NUM_THREADS=1) on a smaller sample."""
     from oracle import oracle as O
     sc = scenes[0]
     rng = np.random.default_rng(123)
     n_img = O.count_images(sc.max_order)
-    n, dt = 256, 0.0
+    n, dt = 16, 0.0
     while True:
         idx = np.sort(rng.choice(sc.n_out, n, replace=False))
         t0 = time.perf_counter()
@@ -102,11 +146,24 @@ def cpu_baseline(scenes, par, target_s: float = 15.0):
         if dt >= 0.6 * target_s or n >= sc.n_out:
             break
         n = int(min(sc.n_out, max(2 * n, n * target_s / max(dt, 1e-3))))
-    taps = float(n) * sc.n_mics * n_img * par.taps
+    per_out = float(sc.n_mics) * n_img * par.taps
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": taps / dt, "unit": "taps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random output samples x %d images x %d taps of the first scene "
-                      "(FP64, exact kernel, tier-emulating delays), %.1f s" % (n, n_img, par.taps, dt)}
+    out = {"value": n * per_out / dt, "unit": "taps/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "%d random output samples x %d mics x %d images x %d taps of the first scene "
+                     "(FP64, exact kernel, tier-emulating delays), %.1f s" % (n, sc.n_mics, n_img, par.taps, dt)}
+    n1 = max(4, int(n / max(cores, 1) / 2))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    gen = WORKLOADS[workload][1].__name__
+    try:
+        r = subprocess.run([sys.executable, "-c", _ORACLE_SAMPLE.format(root=ROOT, gen=gen, n=n1)], env=env,
+                           capture_output=True, text=True, timeout=300)
+        s1 = json.loads(r.stdout.strip().splitlines()[-1])["s"]
+        out["one_core"] = {"value": n1 * per_out / s1, "unit": "taps/s", "cores": 1,
+                           "sample": "%d random output samples of the same scene, %.1f s" % (n1, s1)}
+    except Exception as e:  # the one-core figure is context only
+        out["one_core"] = {"error": str(e)[:200]}
+    return out
 
 
 def timed(fn, steps, torch):
@@ -118,98 +175,138 @@ def timed(fn, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def measure_forward(plan, x, y, steps, torch):
-    """Seconds per plain forward step, and the per-kernel HIP-event profile."""
-    plan.profile_begin()
-    sec_prof = timed(lambda: plan.forward(x, y), steps, torch)
-    prof = plan.profile_end()
-    sec = min(sec_prof, timed(lambda: plan.forward(x, y), steps, torch))
-    return sec, prof
-
-
-def synth_roofline(plan, prof, steps, fd, par, workload):
-    kernel, src = KERNEL_OF[fd]
-    taps = plan.forward_taps
-    kms = prof["synth_ms"] / max(1, prof["synth_launches"])
-    per_step = prof["synth_launches"] / steps
-    if fd == "table":
-        flops = taps / per_step * FLOPS_PER_TAP
-        lds = taps / per_step * table_lds_per_tap(plan.tuning()["outputs_per_lane"])
-    else:
-        flops = taps / par.taps / per_step * farrow_flops_per_sample(par.farrow_order)
-        lds = taps / par.taps / per_step * farrow_lds_per_sample(par.farrow_order)
-    achieved = flops / (kms * 1e-3)
-    traffic = pmc_traffic(kernel, workload, src)
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kernel, "kernel_ms": kms,
-            "flops_per_launch": flops,
-            "lds": {"achieved": lds / (kms * 1e-3) / 1e12, "peak": PEAK_LDS / 1e12, "unit": "TB/s",
-                    "frac": lds / (kms * 1e-3) / PEAK_LDS, "bytes_per_launch": lds}}
-
-
-def measure_fwd_bwd(plan, x, y, steps, torch):
-    gy = torch.randn(plan.y_total, generator=torch.Generator().manual_seed(1)).cuda()
-
-    def fwd_bwd():
-        plan.forward(x, y)
-        plan.backward(x, gy)
-    fwd_bwd()
-    plan.profile_begin()
-    sec = timed(fwd_bwd, steps, torch)
-    pb = plan.profile_end()
-    return {"value": 4 * plan.forward_taps / sec, "unit": "taps/s", "ms_per_step": sec * 1e3,
-            "phases_ms_per_step": {k[:-3]: pb[k] / steps for k in
-                                   ("tracks_ms", "synth_ms", "reduce_ms", "adjoint_ms", "params_ms", "filter_ms")}}
-
-
-def measure_batched(scenes, par, steps, torch):
-    from paper_2508_03065_amd.msim import Plan
-    plan = Plan(scenes, par)
-    x = plan.pack_x([s.x for s in scenes])
-    tune = plan.autotune(x)
-    torch.cuda.empty_cache()
-    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
-    plan.forward_batched(x, y)
-    sec_b = timed(lambda: plan.forward_batched(x, y), steps, torch)
-    plan.profile_begin()
-    timed(lambda: plan.forward_batched(x, y, graph=False), 2, torch)
-    pb = plan.profile_end()
-    plan.forward(x, y)
-    sec_p = timed(lambda: plan.forward(x, y), 2, torch)
-    t = plan.forward_taps
-    out = {"images": int(plan.n_images.sum()), "taps_per_step": t,
-           "value": t / sec_b, "unit": "taps/s", "ms_per_step": sec_b * 1e3,
-           "plain_value": t / sec_p, "plain_ms_per_step": sec_p * 1e3, "speedup_vs_plain": sec_p / sec_b,
-           "persistent_kernel_ms": pb["synth_ms"] / max(1, pb["synth_launches"]), "tuning": tune}
-    del plan, x, y
-    torch.cuda.empty_cache()
+def kernel_roofline(fd, kind, prof, work_flops, workload, lds_bytes=None):
+    """Roofline of one kernel kind from the plan's HIP-event profile: achieved
+    FLOP/s = algorithmic flops per launch / average launch duration."""
+    kernel, src = KERNEL_OF[fd][kind]
+    key = PROFILE_KEY[kind]
+    n = max(1, prof[key + "_launches"])
+    kms = prof[key + "_ms"] / n
+    achieved = work_flops / (kms * 1e-3)
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32, "traffic": pmc_traffic(kernel, workload, src), "kernel": kernel,
+           "kernel_ms": kms, "flops_per_launch": work_flops}
+    if lds_bytes is not None:
+        out["lds"] = {"achieved": lds_bytes / (kms * 1e-3) / 1e12, "peak": PEAK_LDS / 1e12, "unit": "TB/s",
+                      "frac": lds_bytes / (kms * 1e-3) / PEAK_LDS, "bytes_per_launch": lds_bytes}
     return out
 
 
-def measure_differentiation(fd, steps, torch):
-    """Forward (batched, graph-replayed) + backward of the 32-scene differentiation
-    workload with L = 0.5 ||y - target||^2: gradients for x, the 6 wall
-    coefficients of every scene and the 8 source knots of every scene."""
-    from paper_2508_03065_amd.msim import Plan
-    scenes, par = G.config4()
-    plan = Plan(scenes, with_fd(par, fd))
-    x = plan.pack_x([s.x for s in scenes])
-    g = torch.Generator().manual_seed(4)
-    target = (0.01 * torch.randn(plan.y_total, generator=g)).cuda()
-    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+def image_samples(plan, par):
+    return plan.forward_taps / par.taps
 
-    def step():
+
+def fwd_work(plan, par, fd):
+    if fd == "table":
+        t = plan.forward_taps
+        return t * FLOPS_PER_TAP, t * table_lds_per_tap(plan.tuning()["outputs_per_lane"])
+    s = image_samples(plan, par)
+    return s * farrow_flops(par.farrow_order)["fwd"], s * farrow_lds_per_sample(par.farrow_order)
+
+
+def bwd_work(plan, par, fd):
+    """Algorithmic flops of one launch of the dL/dx kernel and of the gain/delay kernel."""
+    if fd == "table":
+        t = plan.forward_taps
+        return {"adjx": t * FLOPS_PER_TAP, "adjp": t * FLOPS_PER_TAP_GD}
+    s = image_samples(plan, par)
+    f = farrow_flops(par.farrow_order)
+    return {"adjx": s * f["adjx"], "adjp": s * f["adjp"]}
+
+
+def measure_batched_form(scenes, par, fd, steps, warmup, fb_steps, torch, workload):
+    """Batched forward (graph replays) and forward+backward of one plan, with
+    rooflines of its kernels from a profiled pass without the graph."""
+    from paper_2508_03065_amd.msim import Plan
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
         plan.forward_batched(x, y)
-        plan.backward(x, y - target)
-    step()
+    torch.cuda.synchronize()
+    if plan.device_status() != 0:
+        raise RuntimeError("device status flags set")
+    sec = timed(lambda: plan.forward_batched(x, y), steps, torch)
     plan.profile_begin()
-    sec = timed(step, steps, torch)
+    timed(lambda: plan.forward_batched(x, y, graph=False), 1, torch)
+    pf = plan.profile_end()
+    flops, lds = fwd_work(plan, par, fd)
+    taps = plan.forward_taps
+    rec = {"value": taps / sec, "unit": "taps/s", "ms_per_step": sec * 1e3, "steps": steps,
+           "scenes": len(scenes), "images": int(plan.n_images.sum()), "taps_per_step": taps,
+           "outputs_per_lane": plan.tuning()["outputs_per_lane"],
+           "phases_ms_per_step": {k[:-3]: pf[k] for k in ("synth_ms", "reduce_ms", "filter_ms")},
+           "roofline": kernel_roofline(fd, "fwd", pf, flops, workload, lds)}
+    # forward + backward: dense dL/dy, every gradient (x, the walls, the source knots)
+    g = torch.Generator().manual_seed(5)
+    gy = torch.randn(plan.y_total, generator=g).cuda()
+    plan.backward(x, gy, batched=True)
+    out = plan.last_backward_buffers
+
+    def fwd_bwd():
+        plan.forward_batched(x, y)
+        plan.backward(x, gy, batched=True, out=out)
+    fwd_bwd()
+    sfb = timed(fwd_bwd, fb_steps, torch)
+    plan.profile_begin()
+    plan.forward_batched(x, y, graph=False)
+    plan.backward(x, gy, batched=True, graph=False, out=out)
+    torch.cuda.synchronize()
     pb = plan.profile_end()
-    out = {"value": 4 * plan.forward_taps / sec, "unit": "taps/s", "ms_per_step": sec * 1e3,
-           "scenes": len(scenes), "images": int(plan.n_images.sum()), "taps_per_step": 4 * plan.forward_taps,
-           "phases_ms_per_step": {k[:-3]: pb[k] / steps for k in
-                                  ("graph_ms", "tracks_ms", "adjoint_ms", "params_ms", "reduce_ms", "filter_ms")}}
-    del plan, x, y, target
+    bw = bwd_work(plan, par, fd)
+    kern = sum(pb[k] for k in ("synth_ms", "reduce_ms", "adjx_ms", "adjp_ms", "params_ms", "filter_ms"))
+    step_flops = flops + bw["adjx"] + bw["adjp"]
+    rec["fwd_bwd"] = {
+        "value": 4 * taps / sfb, "unit": "taps/s", "ms_per_step": sfb * 1e3, "steps": fb_steps,
+        "phases_ms_per_step": {k[:-3]: pb[k] for k in
+                               ("synth_ms", "reduce_ms", "adjx_ms", "adjp_ms", "params_ms", "filter_ms")},
+        "roofline": {"bound": "alu", "achieved": step_flops / (kern * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": step_flops / (kern * 1e-3) / PEAK_FP32,
+                     "flops_per_step": step_flops, "kernel_ms_per_step": kern,
+                     "kernels": {"adjx": kernel_roofline(fd, "adjx", pb, bw["adjx"], workload),
+                                 "adjp": kernel_roofline(fd, "adjp", pb, bw["adjp"], workload)}}}
+    del plan, x, y, gy, out
+    torch.cuda.empty_cache()
+    return rec
+
+
+def measure_batched_vs_plain(scenes, par, steps, torch, with_backward):
+    """Seconds per step of the batched path (graph replays) and of the plain
+    path (launches per scene) on the same plan."""
+    from paper_2508_03065_amd.msim import Plan
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+    out = {"scenes": len(scenes), "images": int(plan.n_images.sum())}
+    if with_backward:
+        gy = torch.randn(plan.y_total, generator=torch.Generator().manual_seed(4)).cuda()
+        plan.backward(x, gy, batched=True)
+        bufs = plan.last_backward_buffers
+        plan.backward(x, gy)
+        pbufs = plan.last_backward_buffers
+
+        def b():
+            plan.forward_batched(x, y)
+            plan.backward(x, gy, batched=True, out=bufs)
+
+        def p():
+            plan.forward(x, y)
+            plan.backward(x, gy, out=pbufs)
+        taps = 4 * plan.forward_taps
+    else:
+        def b():
+            plan.forward_batched(x, y)
+
+        def p():
+            plan.forward(x, y)
+        taps = plan.forward_taps
+    b()
+    p()
+    sb = timed(b, steps, torch)
+    sp = timed(p, steps, torch)
+    out.update({"taps_per_step": taps, "value": taps / sb, "unit": "taps/s", "ms_per_step": sb * 1e3,
+                "plain_value": taps / sp, "plain_ms_per_step": sp * 1e3, "speedup_vs_plain": sp / sb})
+    del plan, x, y
     torch.cuda.empty_cache()
     return out
 
@@ -218,13 +315,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=500,
-                    help="untimed forward steps first (the GPU clocks take a few hundred ms to settle)")
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="config5", choices=sorted(WORKLOADS))
+    ap.add_argument("--scenes", type=int, default=4, help="scenes per step (config5: a batch of its 64 scenes)")
     ap.add_argument("--fd", default="table", choices=sorted(FD_KINDS),
                     help="fractional-delay form of the headline measurement (the other is reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the other form, fwd+bwd and batched measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="the headline form only: its forward and forward+backward (no other form or workload)")
+    ap.add_argument("--fwd-only", action="store_true", help="with --no-extra: the forward only")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB: the reference kernel that "
                          "scales the HBM byte counters of a profiler run")
@@ -235,74 +334,89 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2508_03065_amd.msim import Plan
+    t_start = time.perf_counter()
+
+    def note(msg):
+        print("[bench %6.1f s] %s" % (time.perf_counter() - t_start, msg), file=sys.stderr, flush=True)
 
     desc, gen = WORKLOADS[args.workload]
-    scenes, par0 = gen()
-    par = with_fd(par0, args.fd)
-    plan = Plan(scenes, par)
-    x = plan.pack_x([s.x for s in scenes])
-    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
-    for _ in range(args.warmup):
-        plan.forward(x, y)
-    torch.cuda.synchronize()
-    if plan.device_status() != 0:
-        raise RuntimeError("device status flags set")
+    if args.workload == "config5":
+        all_scenes, par0 = gen(n_scenes=max(args.scenes, 1))
+    else:
+        all_scenes, par0 = gen()
+    scenes = all_scenes[: args.scenes]
+    other = "farrow" if args.fd == "table" else "table"
+    fb_steps = max(1, args.steps // 10)
 
-    sec, prof = measure_forward(plan, x, y, args.steps, torch)
-    taps = plan.forward_taps
+    note("headline: %s, %d scenes, %s form" % (args.workload, len(scenes), args.fd))
+    from paper_2508_03065_amd.msim import Plan
+    par = with_fd(par0, args.fd)
+    if args.fwd_only:
+        plan = Plan(scenes, par)
+        x = plan.pack_x([s.x for s in scenes])
+        y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup):
+            plan.forward_batched(x, y)
+        sec = timed(lambda: plan.forward_batched(x, y), args.steps, torch)
+        plan.profile_begin()
+        timed(lambda: plan.forward_batched(x, y, graph=False), 1, torch)
+        pf = plan.profile_end()
+        flops, lds = fwd_work(plan, par, args.fd)
+        head = {"value": plan.forward_taps / sec, "ms_per_step": sec * 1e3, "images": int(plan.n_images.sum()),
+                "taps_per_step": plan.forward_taps, "outputs_per_lane": plan.tuning()["outputs_per_lane"],
+                "roofline": kernel_roofline(args.fd, "fwd", pf, flops, args.workload, lds),
+                "phases_ms_per_step": {k[:-3]: pf[k] for k in ("synth_ms", "reduce_ms", "filter_ms")}}
+        del plan, x, y
+        torch.cuda.empty_cache()
+    else:
+        head = measure_batched_form(scenes, par, args.fd, args.steps, args.warmup, fb_steps, torch, args.workload)
     rec = {
-        "metric": "image-sample taps/s (forward synthesis, plain path, %s form of the fractional delay)" % args.fd,
-        "value": taps / sec,
+        "metric": "image-sample taps/s (batched forward, %s form of the fractional delay)" % args.fd,
+        "value": head["value"],
         "unit": "taps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded N(0,1) source, seeded trajectories and walls)",
-        "config": {"workload": args.workload + ": " + desc, "fd": args.fd, "scenes": len(scenes),
-                   "images": int(plan.n_images.sum()), "taps_per_step": taps},
-        "phases_ms_per_step": {k[:-3]: prof[k] / args.steps
-                               for k in ("tracks_ms", "synth_ms", "reduce_ms", "filter_ms")},
-        "roofline": synth_roofline(plan, prof, args.steps, args.fd, par, args.workload),
+        "data": "synthetic (seeded N(0,1) sources, seeded trajectories and walls)",
+        "config": {"workload": args.workload + ": " + desc, "fd": args.fd, "scenes_per_step": len(scenes),
+                   "scenes_in_workload": 64 if args.workload == "config5" else len(all_scenes),
+                   "images": head["images"], "taps_per_step": head["taps_per_step"],
+                   "outputs_per_lane": head["outputs_per_lane"]},
+        "phases_ms_per_step": head["phases_ms_per_step"],
+        "roofline": head["roofline"],
     }
+    if "fwd_bwd" in head:
+        rec["fwd_bwd"] = head["fwd_bwd"]
 
     if not args.no_extra:
-        nfb = max(3, args.steps // 4)
-        rec["fwd_bwd"] = measure_fwd_bwd(plan, x, y, nfb, torch)
-        del plan
-        torch.cuda.empty_cache()
-        # the other fractional-delay form on the same workload
-        other = "farrow" if args.fd == "table" else "table"
-        po = with_fd(par0, other)
-        plan = Plan(scenes, po)
-        for _ in range(args.warmup):
-            plan.forward(x, y)
-        so, pro = measure_forward(plan, x, y, args.steps, torch)
-        rec[other] = {"value": taps / so, "unit": "taps/s", "ms_per_step": so * 1e3,
-                      "phases_ms_per_step": {k[:-3]: pro[k] / args.steps
-                                             for k in ("tracks_ms", "synth_ms", "reduce_ms", "filter_ms")},
-                      "roofline": synth_roofline(plan, pro, args.steps, other, po, args.workload),
-                      "fwd_bwd": measure_fwd_bwd(plan, x, y, nfb, torch)}
-        del plan, x, y
-        torch.cuda.empty_cache()
-
-        # batched vs plain on the 256-scene workload, both forms
+        note("other form: %s" % other)
+        rec[other] = measure_batched_form(scenes, with_fd(par0, other), other, max(3, args.steps // 4), 1,
+                                          fb_steps, torch, args.workload)
+        del all_scenes, scenes
+        note("batched vs plain: config4 forward+backward")
+        s4, p4 = G.config4()
+        rec["batched_vs_plain"] = {
+            "config4_fwd_bwd": {"workload": "config4: 32 scenes, 6x5x3 m, K=10 (1561 images), 2 s at 16 kHz, "
+                                            "8-knot source paths, tiers, T=64; forward + backward (dL/dx, "
+                                            "dL/dbeta_w, dL/dknots)"}}
+        for fd in ("table", "farrow"):
+            rec["batched_vs_plain"]["config4_fwd_bwd"][fd] = measure_batched_vs_plain(
+                s4, with_fd(p4, fd), max(2, args.steps // 5), torch, True)
+        del s4
+        note("batched vs plain: config3 forward")
         s3, p3 = G.config3()
-        rec["batched"] = {"workload": "config3: 256 scenes, rooms U(3,10)xU(3,8)xU(2.5,4) m, Sabine orders "
-                                      "6-18, 1-8 s at 16 kHz, lines and circles, tiers, T=64"}
-        for fd in (args.fd, other):
-            rec["batched"][fd] = measure_batched(s3, with_fd(p3, fd), nfb, torch)
+        rec["batched_vs_plain"]["config3_fwd"] = {
+            "workload": "config3: 256 scenes, rooms U(3,10)xU(3,8)xU(2.5,4) m, Sabine orders 6-18, "
+                        "1-8 s at 16 kHz, lines and circles, tiers, T=64"}
+        for fd in ("table", "farrow"):
+            rec["batched_vs_plain"]["config3_fwd"][fd] = measure_batched_vs_plain(
+                s3, with_fd(p3, fd), max(2, args.steps // 5), torch, False)
         del s3
-        rec["differentiation"] = {"workload": "config4: 32 scenes, 6x5x3 m, K=10 (1561 images), 2 s at 16 kHz, "
-                                              "8-knot source paths, tiers, T=64; batched forward + backward "
-                                              "(dL/dx, dL/dbeta_w, dL/dknots)"}
-        for fd in (args.fd, other):
-            rec["differentiation"][fd] = measure_differentiation(fd, 3, torch)
 
     if args.copy_mib > 0:
         a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -313,7 +427,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(scenes, par0)
+        note("cpu baseline")
+        cs, cp = (G.config5(n_scenes=1) if args.workload == "config5" else G.config2())
+        rec["cpu_baseline"] = cpu_baseline(args.workload, cs, cp)
+    note("done")
     print(json.dumps(rec), flush=True)
 
 

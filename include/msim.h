@@ -266,12 +266,15 @@ msim_status msim_device_status(msim_plan* plan, hipStream_t stream, int32_t* fla
  * msim_profile_end waits for them and returns the summed durations (ms) and
  * launch counts per kernel kind.  Profiling adds host work per launch only. */
 typedef struct {
-    double tracks_ms, synth_ms, reduce_ms, adjoint_ms, params_ms;
-    int32_t tracks_launches, synth_launches, reduce_launches, adjoint_launches, params_launches;
-    double graph_ms;           /* replays of the batched forward's graph */
-    int32_t graph_launches;
+    double synth_ms;           /* forward synthesis (k_synth, k_farrow; tracks solved inside) */
+    double reduce_ms;          /* the forward's supergroup reduction */
+    double adjx_ms;            /* dL/dx: k_adjx or k_farrow_u with their reductions */
+    double adjp_ms;            /* gain/delay adjoints with the in-tile parameter sums (k_adjp, k_farrow_gd) */
+    double params_ms;          /* reduction of the parameter rows */
+    double graph_ms;           /* replays of a batched graph */
     double filter_ms;          /* the Farrow filter bank v_k = x * c_k */
-    int32_t filter_launches;
+    int32_t synth_launches, reduce_launches, adjx_launches, adjp_launches, params_launches, graph_launches,
+        filter_launches;
 } msim_profile;
 
 msim_status msim_profile_begin(msim_plan* plan);

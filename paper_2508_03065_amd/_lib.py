@@ -42,12 +42,12 @@ class Params(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("tracks_ms", C.c_double), ("synth_ms", C.c_double), ("reduce_ms", C.c_double),
-                ("adjoint_ms", C.c_double), ("params_ms", C.c_double),
-                ("tracks_launches", C.c_int32), ("synth_launches", C.c_int32), ("reduce_launches", C.c_int32),
-                ("adjoint_launches", C.c_int32), ("params_launches", C.c_int32),
-                ("graph_ms", C.c_double), ("graph_launches", C.c_int32),
-                ("filter_ms", C.c_double), ("filter_launches", C.c_int32)]
+    _fields_ = [("synth_ms", C.c_double), ("reduce_ms", C.c_double), ("adjx_ms", C.c_double),
+                ("adjp_ms", C.c_double), ("params_ms", C.c_double), ("graph_ms", C.c_double),
+                ("filter_ms", C.c_double),
+                ("synth_launches", C.c_int32), ("reduce_launches", C.c_int32), ("adjx_launches", C.c_int32),
+                ("adjp_launches", C.c_int32), ("params_launches", C.c_int32), ("graph_launches", C.c_int32),
+                ("filter_launches", C.c_int32)]
 
 
 class Tuning(C.Structure):

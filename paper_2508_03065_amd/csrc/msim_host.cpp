@@ -504,7 +504,7 @@ struct msim_plan {
 
 namespace {
 
-enum { kKindTracks = 0, kKindSynth, kKindReduce, kKindAdjoint, kKindParams, kKindGraph, kKindFilter, kKinds };
+enum { kKindSynth = 0, kKindReduce, kKindAdjX, kKindAdjP, kKindParams, kKindGraph, kKindFilter, kKinds };
 
 hipEvent_t pool_event(msim_plan* P)
 {
@@ -940,58 +940,66 @@ msim_status regroup(msim_plan* P)
         int window = 0;
         for (int b = 0; b < d.n_blk; ++b) {
             const BlockOrder& o = P->orders[s][b];
-            // the table form keeps groups to at most 24 images (16-40 measured
-            // fastest on the paper-scale scene); the Farrow form, whose 48-byte
-            // window costs more to stage, to 256
-            int G = P->group_cap > 0 ? (I + P->group_cap - 1) / P->group_cap : (I + (farrow ? 255 : 23)) / (farrow ? 256 : 24);
-            G = std::max(G, (I + kMaxGroup - 1) / kMaxGroup);
-            G = std::max(1, std::min(G, I));
+            // Greedy groups in the block's delay order: an image joins the current
+            // group while the group keeps to the image cap (table form 24 images,
+            // 16-40 measured fastest on the paper-scale scene; Farrow form, whose
+            // 48-byte window costs more to stage, 256) and its window (tile, delay
+            // spread, filter) to the preferred limit: the largest that lets two
+            // workgroups share one CU's LDS, unless that leaves more than 2.5 times
+            // the cap's group count (a long filter's table leaves room for little
+            // delay spread), then the LDS limit.  A gap in the delays (the sparse
+            // early reflections) so ends a group where it occurs, and every other
+            // group stays full.  An image whose own window exceeds the preferred
+            // limit gets a group of its own, up to the LDS limit.
+            const int cap = std::min(kMaxGroup, P->group_cap > 0 ? P->group_cap : (farrow ? 256 : 24));
+            auto window_of = [&](double lo, double hi) {
+                return NT + (((int)std::ceil(hi) + 4) - ((int)std::floor(lo) - 4)) + T + 8;
+            };
+            auto largest = [&](auto ok) {   // largest window ok() accepts (ok is monotone)
+                int lo_w = 0, hi_w = 1 << 22;
+                while (lo_w < hi_w) {
+                    const int mid = lo_w + (hi_w - lo_w + 1) / 2;
+                    if (ok(mid)) lo_w = mid; else hi_w = mid - 1;
+                }
+                return lo_w;
+            };
             std::vector<DGroup> gr;
             int bw = 0;
-            auto split = [&](int ng) {
-                gr.clear();
-                bw = 0;
-                for (int g = 0; g < ng; ++g) {
-                    const int ib = (int)((int64_t)I * g / ng), ie = (int)((int64_t)I * (g + 1) / ng);
-                    if (ib == ie) continue;
-                    double lo = 1e300, hi = -1e300;
-                    for (int i = ib; i < ie; ++i) {
-                        lo = std::min(lo, (double)o.lo[i]);
-                        hi = std::max(hi, (double)o.hi[i]);
-                    }
-                    gr.push_back(DGroup{ib, ie, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4});
-                    bw = std::max(bw, NT + (gr.back().dmax - gr.back().dmin) + T + 8);
-                }
-            };
             for (;;) {
-                split(G);
-                if (fits(bw)) break;
-                if (G >= I) {
-                    if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
-                    grad_fit = false;
-                    continue;
-                }
-                G = std::min(I, G * 2);
-            }
-            // Table form: an automatic group count is raised (by 25 % steps, to
-            // groups of at least four images) to the first that lets two
-            // workgroups share one CU's LDS: at one per CU the kernel is
-            // latency-bound.  When no such count exists the first is kept.
-            if (P->group_cap == 0 && !farrow && synth_lds_bytes(T, L, bw) > kLdsLimit / 2) {
-                const int g0 = G, g_max = std::max(G, I / 4);
-                bool ok = false;
-                while (G < g_max) {
-                    G = std::min(g_max, G + std::max(1, G / 4));
-                    split(G);
-                    if (synth_lds_bytes(T, L, bw) <= kLdsLimit / 2 && fits(bw)) {
-                        ok = true;
-                        break;
+                const int w_full = largest([&](int w) { return fits(w); });
+                const int w_half = largest([&](int w) {
+                    return fits(w) && (farrow ? farrow_lds_bytes(w) : synth_lds_bytes(T, L, w)) <= kLdsLimit / 2;
+                });
+                bool ok = true;
+                auto greedy = [&](int w_pref) {
+                    gr.clear();
+                    bw = 0;
+                    ok = true;
+                    int ib = 0;
+                    double glo = o.lo[0], ghi = o.hi[0];
+                    for (int i = 1; i <= I; ++i) {
+                        const bool join =
+                            i < I && i - ib < cap && window_of(glo, std::max(ghi, (double)o.hi[i])) <= w_pref;
+                        if (join) {
+                            ghi = std::max(ghi, (double)o.hi[i]);
+                            continue;
+                        }
+                        const int wg = window_of(glo, ghi);
+                        if (wg > w_full) ok = false;
+                        gr.push_back(DGroup{ib, i, (int)std::floor(glo) - 4, (int)std::ceil(ghi) + 4});
+                        bw = std::max(bw, wg);
+                        if (i < I) {
+                            ib = i;
+                            glo = o.lo[i];
+                            ghi = o.hi[i];
+                        }
                     }
-                }
-                if (!ok) {
-                    G = g0;
-                    split(G);
-                }
+                };
+                greedy(w_half);
+                if (gr.size() * 2 > (size_t)5 * ((I + cap - 1) / cap)) greedy(w_full);
+                if (ok) break;
+                if (!grad_fit) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                grad_fit = false;
             }
             // groups whose tracks exceed a slot of kSlotSegCap segments (audio-rate
             // images hold a tile's worth each) are split into consecutive parts
@@ -1521,7 +1529,7 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
         PlanView one = pv;
         one.scenes = scenes;
         if (gx) {
-            LaunchTimer t(P, kKindAdjoint, st);
+            LaunchTimer t(P, kKindAdjX, st);
             if (farrow) {
                 PlanView wv = pv;
                 wv.groups = P->d_wgroups;
@@ -1549,7 +1557,7 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
             const WorkItem* it = batched ? P->d_items : P->d_items_plain + P->plain_off[k];
             const int n = batched ? (int)P->items.size() : P->plain_cnt[k];
             {
-                LaunchTimer t(P, kKindAdjoint, st);
+                LaunchTimer t(P, kKindAdjP, st);
                 if (farrow)
                     HIP_OK(launch_farrow_gd(NT, std::min(n, P->adj_wgs), P->b_window, T, P->par.farrow_order, pv, it, n,
                                             w.ticket, ta, w.v, gy, pa, P->d_status, st));
@@ -1878,19 +1886,19 @@ msim_status msim_profile_end(msim_plan* P, msim_profile* out)
         P->pool.push_back(r.b);
     }
     P->recs.clear();
-    out->tracks_ms = ms[kKindTracks];
     out->synth_ms = ms[kKindSynth];
     out->reduce_ms = ms[kKindReduce];
-    out->adjoint_ms = ms[kKindAdjoint];
+    out->adjx_ms = ms[kKindAdjX];
+    out->adjp_ms = ms[kKindAdjP];
     out->params_ms = ms[kKindParams];
-    out->tracks_launches = cnt[kKindTracks];
+    out->graph_ms = ms[kKindGraph];
+    out->filter_ms = ms[kKindFilter];
     out->synth_launches = cnt[kKindSynth];
     out->reduce_launches = cnt[kKindReduce];
-    out->adjoint_launches = cnt[kKindAdjoint];
+    out->adjx_launches = cnt[kKindAdjX];
+    out->adjp_launches = cnt[kKindAdjP];
     out->params_launches = cnt[kKindParams];
-    out->graph_ms = ms[kKindGraph];
     out->graph_launches = cnt[kKindGraph];
-    out->filter_ms = ms[kKindFilter];
     out->filter_launches = cnt[kKindFilter];
     return st;
 }

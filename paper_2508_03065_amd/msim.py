@@ -218,17 +218,24 @@ class Plan:
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
 
     def backward(self, x: torch.Tensor, gy: torch.Tensor, want_x: bool = True, want_beta: bool = True,
-                 want_src: bool = True, stream=None, batched: bool = False, graph: bool = True):
+                 want_src: bool = True, stream=None, batched: bool = False, graph: bool = True, out=None):
         """(dL/dx [x_total] f32, dL/dbeta [n_scenes, 6] f64, dL/dknots [src_total, 3] f64) for
         gy = dL/dy; entries not requested are None.  batched=True runs every scene in one
-        persistent launch per kernel (replayed from a HIP graph when graph=True)."""
+        persistent launch per kernel (replayed from a HIP graph when graph=True; a graph
+        is kept per set of buffers, so a loop passes the same `out`, as from a first call's
+        return, to replay it)."""
         assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == self.x_total
         assert gy.is_cuda and gy.dtype == torch.float32 and gy.is_contiguous() and gy.numel() == self.y_total
         dev = x.device
-        gx = torch.empty(self.x_total, dtype=torch.float32, device=dev) if want_x else None
-        gb = torch.empty((self.n_scenes, 6), dtype=torch.float64, device=dev) if want_beta else None
-        gs = (torch.zeros((max(self.src_total, 1), 3), dtype=torch.float64, device=dev)
-              if want_src else None)
+        if out is not None:
+            gx, gb, gs = out
+            if gs is not None and gs.shape[0] != max(self.src_total, 1):
+                raise ValueError("out[2] must be the full [max(src_total, 1), 3] buffer")
+        else:
+            gx = torch.empty(self.x_total, dtype=torch.float32, device=dev) if want_x else None
+            gb = torch.empty((self.n_scenes, 6), dtype=torch.float64, device=dev) if want_beta else None
+            gs = (torch.zeros((max(self.src_total, 1), 3), dtype=torch.float64, device=dev)
+                  if want_src else None)
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
         if batched:
             ws = self.batched_workspace(dev)
@@ -239,6 +246,7 @@ class Plan:
             ws = self.workspace(True, dev)
             check(_lib.load().msim_backward(self._ptr, ptr(x), ptr(gy), ptr(gx), ptr(gb), ptr(gs),
                                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        self.last_backward_buffers = (gx, gb, gs)
         if gs is not None:
             gs = gs[: self.src_total]
         return gx, gb, gs
