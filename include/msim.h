@@ -100,6 +100,8 @@ typedef struct {
     int32_t delay_model;        /* MSIM_DELAY_RETARDED (emission-time delay) or _INSTANTANEOUS */
     int32_t fd_kind;            /* MSIM_FD_TABLE (default) or MSIM_FD_FARROW */
     int32_t farrow_order;       /* M, 4..11: degree of the Farrow polynomial in the fractional delay */
+    double knot_slack;          /* m, 0..10: how far msim_plan_update may move a source knot from the
+                                   plan's path (every delay bound is planned that much wider) */
 } msim_params;
 
 /* How the T-tap Kaiser-windowed sinc h(j - mu) is applied.
@@ -212,6 +214,20 @@ typedef struct {
 } msim_fd_error;
 
 msim_status msim_get_fd_error(const msim_plan* plan, msim_fd_error* out);
+
+/* Replaces the wall reflection coefficients (beta [n_scenes*6], or NULL) and the
+ * PWL source knot positions (knots [src_total*3] in the gradient layout of
+ * msim_plan_grad_layout, or NULL; knot times stay) of every scene in place,
+ * without planning again: the image gains beta_i = prod_w beta_w^hits_w (Sec.
+ * II-A) and the knots are rewritten in the plan's device buffers on `stream`
+ * (synchronised before return), so captured graphs stay valid.  The delay
+ * groups keep the bounds planned for the original path widened by
+ * params.knot_slack: a knot moved further than that from the plan's original
+ * position gives MSIM_E_UNSUPPORTED (plan again); coefficients outside [0, 1],
+ * knots leaving the room or moving at >= c/10 give the statuses of
+ * msim_plan_create.  On any error nothing changes.  Calls that overlap a
+ * launch on another stream race with it. */
+msim_status msim_plan_update(msim_plan* plan, const double* beta, const double* knots, hipStream_t stream);
 /* Regroups the plan for a launch shape; workspace sizes change with it. */
 msim_status msim_set_tuning(msim_plan* plan, const msim_tuning* t);
 /* Largest batched workspace over the shapes msim_autotune tries. */

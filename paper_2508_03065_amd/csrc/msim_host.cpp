@@ -269,6 +269,8 @@ msim_status check_params(const msim_params* p)
     if (p->fd_kind != MSIM_FD_TABLE && p->fd_kind != MSIM_FD_FARROW) return fail(MSIM_E_INVALID_ARG, "unknown fd_kind");
     if (p->fd_kind == MSIM_FD_FARROW && (p->farrow_order < 4 || p->farrow_order > 11))
         return fail(MSIM_E_INVALID_ARG, "farrow_order must be 4..11");
+    if (!(p->knot_slack >= 0.0 && p->knot_slack <= 10.0))
+        return fail(MSIM_E_INVALID_ARG, "knot_slack must be in [0, 10] m");
     return MSIM_OK;
 }
 
@@ -420,6 +422,7 @@ struct msim_plan {
     std::vector<DImage> images;
     std::vector<DGroup> groups;
     std::vector<double> knots, mics;
+    std::vector<double> knots_ref;        // knot positions the delay bounds were planned for
     std::vector<uint8_t> qtable;          // the quadratic FD table: [Y | D1 | D2] bytes
     std::vector<float> atable;            // the same values tap-major (Y, D1, D2 of [T/2][Lq]) for the transpose
     std::vector<int64_t> n_img;
@@ -747,6 +750,10 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     std::vector<HostImage> imgs;
     imgs.reserve((size_t)count_images(K));
     Box sb = traj_box(s.src), rb = traj_box(s.rcv);
+    for (int a = 0; a < 3; ++a) {   // knots may later move by up to the slack
+        sb.lo[a] -= p.knot_slack;
+        sb.hi[a] += p.knot_slack;
+    }
     // receiver box grown by the mic offsets
     Box mb = rb;
     for (int a = 0; a < 3; ++a) {
@@ -884,7 +891,11 @@ void order_blocks(msim_plan* P, int si)
         }
         for (int i = 0; i < I; ++i) {
             const DImage& im = P->images[d.img_begin + i];
-            const Box sb = traj_box_range(src, t0 - whole[i].second / fs - 1e-6, t1 - whole[i].first / fs + 1e-6);
+            Box sb = traj_box_range(src, t0 - whole[i].second / fs - 1e-6, t1 - whole[i].first / fs + 1e-6);
+            for (int a = 0; a < 3; ++a) {
+                sb.lo[a] -= P->par.knot_slack;
+                sb.hi[a] += P->par.knot_slack;
+            }
             const int m[3] = {im.m[0], im.m[1], im.m[2]};
             double lo, h;
             image_bounds(m, d.size, sb, mb, fs, c, &lo, &h);
@@ -1600,6 +1611,7 @@ msim_status msim_default_params(msim_params* p)
     p->delay_model = MSIM_DELAY_RETARDED;
     p->fd_kind = MSIM_FD_TABLE;
     p->farrow_order = 9;
+    p->knot_slack = 0.0;
     return MSIM_OK;
 }
 
@@ -1688,6 +1700,7 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
     }
     P->x_total = xo;
     P->y_total = yo;
+    P->knots_ref = P->knots;
     // delay blocks of about a quarter second, a whole number of 1024-output tiles
     P->blk_len = std::max<int64_t>(1024, (int64_t)std::llround(0.25 * p->fs / 1024.0) * 1024);
     P->orders.assign(n_scenes, {});
@@ -2056,6 +2069,88 @@ msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
     out->outputs_per_lane = P->rb;
     out->workgroups = P->b_wgs;
     out->ms = 0.0;
+    return MSIM_OK;
+}
+
+msim_status msim_plan_update(msim_plan* P, const double* beta, const double* knots, hipStream_t stream)
+{
+    if (!P) return fail(MSIM_E_INVALID_ARG, "plan is NULL");
+    if (!beta && !knots) return MSIM_OK;
+    std::vector<DScene> sc = P->scenes, scb = P->scenes_b;
+    std::vector<double> kn = P->knots;
+    for (int s = 0; s < P->n_scenes; ++s) {
+        DScene& d = sc[s];
+        if (beta)
+            for (int w = 0; w < 6; ++w) d.beta[w] = beta[6 * s + w];
+        if (knots && d.src_knots > 0) {
+            for (int k = 0; k < d.src_knots; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    const double v = knots[3 * ((int64_t)d.src_grad_off + k) + a];
+                    const double ref = P->knots_ref[d.src.pos_off + 3 * k + a];
+                    if (!(std::fabs(v - ref) <= P->par.knot_slack))
+                        return fail(MSIM_E_UNSUPPORTED,
+                                    "scene %d: knot %d moved %.3g m from the planned path, beyond knot_slack %.3g m "
+                                    "(create a new plan)",
+                                    s, k, std::fabs(v - ref), P->par.knot_slack);
+                    kn[d.src.pos_off + 3 * k + a] = v;
+                }
+        }
+        // the scene as updated passes the same checks as at plan creation
+        msim_scene h{};
+        for (int a = 0; a < 3; ++a) h.size[a] = d.size[a];
+        for (int w = 0; w < 6; ++w) h.beta[w] = d.beta[w];
+        msim_traj src{}, rcv{};
+        {
+            std::swap(P->knots, kn);
+            src = host_traj(P, d.src);
+            rcv = host_traj(P, d.rcv);
+            std::swap(P->knots, kn);
+        }
+        std::vector<double> tk(src.t ? src.t : nullptr, src.t ? src.t + src.n_points : nullptr);
+        std::vector<double> pk(kn.begin() + (src.kind == MSIM_TRAJ_PWL ? d.src.pos_off : 0),
+                               kn.begin() + (src.kind == MSIM_TRAJ_PWL ? d.src.pos_off + 3 * src.n_points : 0));
+        std::vector<double> tr(rcv.t ? rcv.t : nullptr, rcv.t ? rcv.t + rcv.n_points : nullptr);
+        std::vector<double> pr(rcv.p ? rcv.p : nullptr, rcv.p ? rcv.p + 3 * rcv.n_points : nullptr);
+        if (src.kind == MSIM_TRAJ_PWL) {
+            src.t = tk.data();
+            src.p = pk.data();
+        }
+        if (rcv.kind == MSIM_TRAJ_PWL) {
+            rcv.t = tr.data();
+            rcv.p = pr.data();
+        }
+        h.src = src;
+        h.rcv = rcv;
+        h.n_mics = d.n_mics;
+        h.mic_offset = P->mics.data() + 3 * (size_t)d.mic_off;
+        h.max_order = 0;
+        h.n_in = d.n_in;
+        h.n_out = d.n_out;
+        msim_status st = check_scene(h, &P->par, s);
+        if (st != MSIM_OK) return st;
+        for (int w = 0; w < 6; ++w) scb[s].beta[w] = d.beta[w];
+    }
+    std::vector<DImage> im = P->images;
+    if (beta)
+        for (int s = 0; s < P->n_scenes; ++s)
+            for (int i = sc[s].img_begin; i < sc[s].img_begin + sc[s].n_img; ++i) {
+                double b = 1.0;
+                for (int w = 0; w < 6; ++w) b *= std::pow(sc[s].beta[w], im[i].hits[w]);
+                im[i].gfac = (float)(b * P->par.fs / (4.0 * kPi * P->par.c));
+            }
+    P->scenes.swap(sc);
+    P->scenes_b.swap(scb);
+    P->knots.swap(kn);
+    P->images.swap(im);
+    auto put = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+    };
+    const bool ok = put(P->d_scenes, P->scenes.data(), P->scenes.size() * sizeof(DScene)) &&
+                    put(P->d_scenes_b, P->scenes_b.data(), P->scenes_b.size() * sizeof(DScene)) &&
+                    put(P->d_knots, P->knots.data(), P->knots.size() * sizeof(double)) &&
+                    put(P->d_images, P->images.data(), P->images.size() * sizeof(DImage)) &&
+                    hipStreamSynchronize(stream) == hipSuccess;
+    if (!ok) return fail(MSIM_E_HIP, "plan update upload failed");
     return MSIM_OK;
 }
 

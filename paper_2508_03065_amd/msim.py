@@ -66,6 +66,7 @@ def params_struct(par, table_phases: int = 128) -> _lib.Params:
     p.delay_model = int(par.delay_model)
     p.fd_kind = int(getattr(par, "fd_kind", 0))
     p.farrow_order = int(getattr(par, "farrow_order", 9))
+    p.knot_slack = float(getattr(par, "knot_slack", 0.0))
     return p
 
 
@@ -192,6 +193,16 @@ class Plan:
         t = _lib.Tuning()
         check(_lib.load().msim_get_tuning(self._ptr, C.byref(t)))
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
+
+    def update(self, beta=None, knots=None, stream=None):
+        """Replace the walls' coefficients (beta [n_scenes, 6]) and the PWL source knot
+        positions (knots [src_total, 3], the gradient layout) in place (msim_plan_update)."""
+        b = None if beta is None else np.ascontiguousarray(np.asarray(beta, np.float64).reshape(self.n_scenes, 6))
+        k = None if knots is None else np.ascontiguousarray(np.asarray(knots, np.float64).reshape(-1, 3))
+        if k is not None and k.shape[0] != self.src_total:
+            raise ValueError("knots must hold src_total = %d rows" % self.src_total)
+        ptr = lambda a: C.c_void_p(a.ctypes.data) if a is not None else None
+        check(_lib.load().msim_plan_update(self._ptr, ptr(b), ptr(k), _stream_handle(stream)))
 
     def fd_error(self) -> dict:
         """Predicted relative errors of the fractional-delay approximations and the budget."""

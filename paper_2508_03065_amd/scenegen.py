@@ -88,6 +88,7 @@ class Params:
     delay_model: int = 0                      # 0 retarded, 1 instantaneous
     fd_kind: int = 0                          # how the library applies the kernel: 0 table, 1 Farrow
     farrow_order: int = 9
+    knot_slack: float = 0.0                   # m a plan lets its source knots move (msim_plan_update)
 
 
 PAPER_TIERS = ((2, 1), (6, 16), (1 << 20, 160))
