@@ -19,24 +19,41 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is built
+# as usual: the flags apply to the host pass only).
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = LIB) -> str:
+    """Compiles every source and links `out` (sanitize: the host code with ASan
+    and UBSan, for CPU-side tests that preload the clang runtime)."""
     objs = []
+    tag = ".san" if sanitize else ""
+    extra = SANITIZE_FLAGS if sanitize else []
+    cmds = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", "-c", *FLAGS, os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(os.path.dirname(out), src.rsplit(".", 1)[0] + tag + ".%d.o" % os.getpid())
+        cmds.append([HIPCC, "-x", "hip", "-c", *FLAGS, *extra, os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # the sources compile side by side (one hipcc each)
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+        procs.append(subprocess.Popen(cmd))
+    bad = [c for p, c in zip(procs, cmds) if p.wait() != 0]
+    if bad:
+        raise subprocess.CalledProcessError(1, bad[0])
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *extra, *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

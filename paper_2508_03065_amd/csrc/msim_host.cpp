@@ -2216,59 +2216,85 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
     if (!P || !x || !y || !ws) return fail(MSIM_E_INVALID_ARG, "NULL argument");
     const std::string key = tune_key(P);
     int bt = 0, bc = 0, brb = 1;
-    double best = 1e300;
-    if (!cache_lookup(cache_path, key, &bt, &bc, &brb)) {
-        hipEvent_t e0, e1;
-        HIP_OK(hipEventCreate(&e0));
-        HIP_OK(hipEventCreate(&e1));
-        const bool prof = P->profiling;
-        P->profiling = false;
-        for (int t : kTuneThreads)
-            for (int c : kTuneCaps)
-                for (int rb : {1, 2, 4}) {
-                    if (P->rb_max % rb != 0) continue;
-                    P->threads = t;
-                    P->group_cap = c;
-                    P->rb = rb;
-                    if (regroup(P) != MSIM_OK || carve_fwd_ws(P, true, nullptr, nullptr) > ws_bytes) continue;
-                    msim_status st = upload_layout(P);
-                    if (st != MSIM_OK) return st;
-                    FwdWs2 w;
-                    carve_fwd_ws(P, true, (char*)ws, &w);
-                    if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
-                    HIP_OK(hipEventRecord(e0, stream));
-                    for (int r = 0; r < 3; ++r)
-                        if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
-                    HIP_OK(hipEventRecord(e1, stream));
-                    HIP_OK(hipEventSynchronize(e1));
-                    float ms = 0.0f;
-                    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms / 3.0 < best) {
-                        best = ms / 3.0;
-                        bt = t;
-                        bc = c;
-                        brb = rb;
-                    }
-                }
-        P->profiling = prof;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (bt == 0) return fail(MSIM_E_WORKSPACE, "no tuning candidate fits the workspace");
-        if (cache_path) {
-            FILE* f = fopen(cache_path, "a");
-            if (f) {
-                fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"group_cap\": %d, \"outputs_per_lane\": %d, "
-                        "\"ms\": %.4f}\n", key.c_str(), bt, bc, brb, best);
-                fclose(f);
-            }
+    // a cached shape this plan accepts is used as it is; one it refuses (another
+    // build's limits, a hand-edited line) is timed again
+    if (cache_lookup(cache_path, key, &bt, &bc, &brb)) {
+        msim_tuning t{bt, bc, brb, 0, 0.0};
+        if (msim_set_tuning(P, &t) == MSIM_OK) {
+            if (best_out) msim_get_tuning(P, best_out);
+            return MSIM_OK;
         }
     }
-    msim_tuning t{bt, bc, brb, 0, best < 1e299 ? best : 0.0};
+    // Every exit restores the plan's launch shape (regrouped and uploaded) and
+    // its profiling flag, and frees the events, unless a tuning was applied.
+    struct Guard {
+        msim_plan* P;
+        int t, c, rb;
+        bool prof, applied = false;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        explicit Guard(msim_plan* p) : P(p), t(p->threads), c(p->group_cap), rb(p->rb), prof(p->profiling) {}
+        ~Guard()
+        {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            P->profiling = prof;
+            if (!applied) {
+                P->threads = t;
+                P->group_cap = c;
+                P->rb = rb;
+                if (regroup(P) == MSIM_OK) (void)upload_layout(P);
+            }
+        }
+    } guard(P);
+    HIP_OK(hipEventCreate(&guard.e0));
+    HIP_OK(hipEventCreate(&guard.e1));
+    P->profiling = false;
+    double best = 1e300;
+    bt = 0;
+    for (int t : kTuneThreads)
+        for (int c : kTuneCaps)
+            for (int rb : {1, 2, 4}) {
+                if (P->rb_max % rb != 0) continue;
+                P->threads = t;
+                P->group_cap = c;
+                P->rb = rb;
+                if (regroup(P) != MSIM_OK || carve_fwd_ws(P, true, nullptr, nullptr) > ws_bytes) continue;
+                msim_status st = upload_layout(P);
+                if (st != MSIM_OK) return st;
+                FwdWs2 w;
+                carve_fwd_ws(P, true, (char*)ws, &w);
+                if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
+                HIP_OK(hipEventRecord(guard.e0, stream));
+                for (int r = 0; r < 3; ++r)
+                    if ((st = enqueue_forward(P, x, y, w, true, stream)) != MSIM_OK) return st;
+                HIP_OK(hipEventRecord(guard.e1, stream));
+                HIP_OK(hipEventSynchronize(guard.e1));
+                float ms = 0.0f;
+                HIP_OK(hipEventElapsedTime(&ms, guard.e0, guard.e1));
+                if (ms / 3.0 < best) {
+                    best = ms / 3.0;
+                    bt = t;
+                    bc = c;
+                    brb = rb;
+                }
+            }
+    if (bt == 0) return fail(MSIM_E_WORKSPACE, "no tuning candidate fits the workspace");
+    msim_tuning t{bt, bc, brb, 0, best};
+    P->profiling = guard.prof;
     msim_status st = msim_set_tuning(P, &t);
     if (st != MSIM_OK) return st;
+    guard.applied = true;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"group_cap\": %d, \"outputs_per_lane\": %d, "
+                    "\"ms\": %.4f}\n", key.c_str(), bt, bc, brb, best);
+            fclose(f);
+        }
+    }
     if (best_out) {
         msim_get_tuning(P, best_out);
-        best_out->ms = t.ms;
+        best_out->ms = best;
     }
     return MSIM_OK;
 }

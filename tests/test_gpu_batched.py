@@ -142,3 +142,39 @@ def test_backward_batched_equals_plain(torch_cuda, fd):
             assert torch.equal(a, b), graph
         assert torch.isfinite(junk)
     assert plan.device_status() == 0
+
+
+def test_autotune_corrupt_cache_falls_back_to_timing(torch_cuda, tmp_path):
+    """Malformed lines, and a line for this plan with a shape it refuses, are
+    passed over: the tuner times the candidates, applies the best, appends a
+    good line, and a plan that then reads the cache takes that line."""
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    scenes, par = mixed_scenes(5)
+    plan = Plan(scenes, par)
+    x = plan.pack_x([s.x for s in scenes])
+    cache = tmp_path / "tune.jsonl"
+    with open(cache, "w") as f:
+        f.write('{"key": "gfx950/F0/M9/T64\n')                     # truncated
+        f.write("not json at all\n")
+        f.write('{"key": 5, "threads": "many"}\n')
+    # the plan's own key with a shape outside the allowed set, and one it refuses
+    key_probe = Plan(scenes, par).autotune(x, cache_path=str(tmp_path / "probe.jsonl"))
+    lines = open(tmp_path / "probe.jsonl").read().splitlines()
+    key = lines[-1].split('"key": "')[1].split('"')[0]
+    with open(cache, "a") as f:
+        f.write('{"key": "%s", "threads": 7, "group_cap": 0, "outputs_per_lane": 1, "ms": 1.0}\n' % key)
+        f.write('{"key": "%s", "threads": 512, "group_cap": 0, "outputs_per_lane": 4, "ms": 1.0}\n' % key)
+    before = open(cache).read()
+    best = plan.autotune(x, cache_path=str(cache))
+    assert best["ms"] > 0                                   # timed, not read
+    after = open(cache).read()
+    assert after.startswith(before) and after.count("\n") == before.count("\n") + 1
+    again = Plan(scenes, par).autotune(x, cache_path=str(cache))
+    assert (again["threads"], again["group_cap"], again["outputs_per_lane"]) == \
+        (best["threads"], best["group_cap"], best["outputs_per_lane"])
+    assert key_probe["threads"] in (512, 1024)
+    y = plan.forward_batched(x)
+    torch.cuda.synchronize()
+    for s, yv in enumerate(plan.unpack_y(y)):
+        assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5
