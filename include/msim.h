@@ -55,6 +55,7 @@ typedef enum {
 
 enum { MSIM_TRAJ_PWL = 0, MSIM_TRAJ_CIRCLE = 1 };
 enum { MSIM_DELAY_RETARDED = 0, MSIM_DELAY_INSTANTANEOUS = 1 };
+enum { MSIM_TIER_ORDER = 0, MSIM_TIER_ADAPTIVE = 1 };
 
 /* A trajectory.  PWL: positions p[3k..3k+2] at strictly increasing times t[k],
  * linear in between, held constant before t[0] and after t[n_points-1]; one knot
@@ -102,6 +103,12 @@ typedef struct {
     int32_t farrow_order;       /* M, 4..11: degree of the Farrow polynomial in the fractional delay */
     double knot_slack;          /* m, 0..10: how far msim_plan_update may move a source knot from the
                                    plan's path (every delay bound is planned that much wider) */
+    int32_t tier_mode;          /* MSIM_TIER_ORDER: decimations by reflection order (n_tiers ...);
+                                   MSIM_TIER_ADAPTIVE: per image, from a bound on its delay track's
+                                   third derivative (Sec. II-C-1/2: the motion's bandwidth, and the
+                                   near field of a close image), see msim_plan_create */
+    double tier_tol;            /* adaptive: bound on the interpolated delay's error, samples (> 0) */
+    int32_t tier_rmax;          /* adaptive: largest decimation, 1..4096 */
 } msim_params;
 
 /* How the T-tap Kaiser-windowed sinc h(j - mu) is applied.
@@ -130,6 +137,25 @@ msim_status msim_count_images(int32_t max_order, int64_t* n);
 /* An output length that holds every contribution: n_in + ceil(fs * d_max / c) + T,
  * with d_max the largest distance from the room to an image cell of order <= K. */
 msim_status msim_suggest_n_out(const msim_scene* scene, const msim_params* p, int64_t* n_out);
+
+/* Adaptive decimation (tier_mode MSIM_TIER_ADAPTIVE).  Image i may err in its
+ * delay by delta_i = tier_tol * max(d_i, 0.1 m) / beta_i samples: tier_tol for an
+ * image as loud as a unit source at 1 m, more for a fainter one (its gain is
+ * beta_i / (4 pi d)), d_i the smallest distance from the image's box over the
+ * path to the mics' box.  The delay d_i(t) = |S_i p(t) - r(t)| / c has a third
+ * derivative of at most
+ *   K3_i = ( (2/sqrt 3) u^3 / d_i^2 + 3 u a / d_i + j ) / (1 - u/c)^3      (m/s^3)
+ * with u, a, j the source's plus the receiver's largest speed, acceleration and
+ * jerk (a circle: v, v^2/r, v^3/r^2; a PWL path read as samples of a smooth
+ * path: the piece speeds, the velocity change at each inner knot over the mean
+ * of its two pieces' durations, no jerk): the near field (small d_i) raises it,
+ * far images keep the motion's own bandwidth (Sec. II-C-1/2).  Uniform
+ * Catmull-Rom through decimation R errs by at most about R^3 D3_i / 24 samples,
+ * D3_i = K3_i / (c fs^2), on smooth motion, and by up to (3/16) R dv / (c - u) at
+ * a knot whose velocity changes by dv (the largest inner-knot change of the
+ * source plus the receiver).  Image i takes the largest R of 1, 4, 8, 16, ...
+ * (not above tier_rmax) that keeps both within delta_i.  The paths' first and
+ * last knots (where motion starts and stops) are not counted. */
 
 /* Validates the scenes, enumerates their images, sorts them by delay, builds the
  * fractional-delay table and uploads the plan's device descriptors.  Runs on the
@@ -214,6 +240,11 @@ typedef struct {
 } msim_fd_error;
 
 msim_status msim_get_fd_error(const msim_plan* plan, msim_fd_error* out);
+
+/* The images of scene `scene` (plan order): out[4 i .. 4 i + 3] = (mx, my, mz,
+ * decimation R of the image's delay track); *n_img gets the count.  With
+ * out = NULL only the count is written; else capacity must hold n_img rows. */
+msim_status msim_get_images(const msim_plan* plan, int32_t scene, int32_t* out, int64_t capacity, int64_t* n_img);
 
 /* Replaces the wall reflection coefficients (beta [n_scenes*6], or NULL) and the
  * PWL source knot positions (knots [src_total*3] in the gradient layout of

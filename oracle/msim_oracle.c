@@ -70,6 +70,10 @@ typedef struct {
     int32_t tier_max_order[4];
     int32_t tier_decim[4];
     int32_t delay_model;     /* 0: retarded (emission-time) delay, 1: instantaneous */
+    int32_t tier_mode;       /* 0: decimation by reflection order (tiers above); 1: per image from
+                                the delay track's third-derivative bound (see adaptive_decim) */
+    double tier_tol;         /* mode 1: allowed error of the interpolated delay, samples */
+    int32_t tier_rmax;       /* mode 1: largest decimation */
 } orc_params;
 
 /* ----------------------------------------------------- image enumeration */
@@ -237,9 +241,127 @@ double orc_catmull_rom(const double v[4], double u)
 
 static int order_of(const int32_t m[3]) { return abs(m[0]) + abs(m[1]) + abs(m[2]); }
 
-/* Decimation factor of an image: the first tier whose max order covers it. */
-static int decim_of(const orc_params* p, const int32_t m[3])
+/* Whether delays are decimated at all (tier-emulating mode). */
+static int tiered(const orc_params* p) { return p->n_tiers > 0 || p->tier_mode == 1; }
+
+/* Bounding box of a path: its knots, or the circle's square in its plane. */
+static void path_box(const orc_traj* tr, double lo[3], double hi[3])
 {
+    if (tr->kind == 1) {
+        for (int a = 0; a < 2; ++a) {
+            lo[a] = tr->center[a] - tr->radius;
+            hi[a] = tr->center[a] + tr->radius;
+        }
+        lo[2] = hi[2] = tr->center[2];
+        return;
+    }
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = tr->p[a];
+    for (int k = 1; k < tr->n_points; ++k)
+        for (int a = 0; a < 3; ++a) {
+            if (tr->p[3 * k + a] < lo[a]) lo[a] = tr->p[3 * k + a];
+            if (tr->p[3 * k + a] > hi[a]) hi[a] = tr->p[3 * k + a];
+        }
+}
+
+/* Largest speed v, acceleration acc and jerk jrk of a path, and its largest
+ * velocity change dv at an inner knot.  A circle of radius r at speed v: v,
+ * v^2/r, v^3/r^2, no knots.  A PWL path, read as samples of a smooth path: the
+ * largest piece speed; at each inner knot the change of velocity divided by half
+ * the time between its neighbouring knots; no jerk. */
+static void path_kinematics(const orc_traj* tr, double* v, double* acc, double* jrk, double* dv)
+{
+    *v = *acc = *jrk = *dv = 0.0;
+    if (tr->kind == 1) {
+        *v = tr->speed;
+        *acc = tr->speed * tr->speed / tr->radius;
+        *jrk = *acc * tr->speed / tr->radius;
+        return;
+    }
+    for (int k = 0; k + 1 < tr->n_points; ++k) {
+        double w = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double va = (tr->p[3 * (k + 1) + a] - tr->p[3 * k + a]) / (tr->t[k + 1] - tr->t[k]);
+            w += va * va;
+        }
+        if (sqrt(w) > *v) *v = sqrt(w);
+        if (k == 0) continue;
+        double ch = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double v1 = (tr->p[3 * (k + 1) + a] - tr->p[3 * k + a]) / (tr->t[k + 1] - tr->t[k]);
+            double v0 = (tr->p[3 * k + a] - tr->p[3 * (k - 1) + a]) / (tr->t[k] - tr->t[k - 1]);
+            ch += (v1 - v0) * (v1 - v0);
+        }
+        ch = sqrt(ch);
+        if (ch > *dv) *dv = ch;
+        if (ch / (0.5 * (tr->t[k + 1] - tr->t[k - 1])) > *acc) *acc = ch / (0.5 * (tr->t[k + 1] - tr->t[k - 1]));
+    }
+}
+
+/* Adaptive decimation (mode 1), the reading of Sec. II-C-1/2 that the delay of
+ * a far image carries the motion's own bandwidth while a close image (near
+ * field) needs a higher rate, and that faint (high-order) images can be sampled
+ * sparsely.  Image m may err in delay by tier_tol * max(d, 0.1 m) / beta_m
+ * samples (its gain beta_m / (4 pi d) against that of a unit source at 1 m),
+ * d the gap between the image's box over the path and the mics' box.  For
+ * d(t) = |r(t)|, r the image-to-mic vector, the third derivative is at most
+ * (2/sqrt 3) u^3/d^2 + 3 u a/d + j (u, a, j: relative speed, acceleration and
+ * jerk bounds; the first term is the largest value of 3 u^3 sin^2 cos / d^2, the
+ * straight-motion case), divided by (1 - u/c)^3 for the emission-time reading.
+ * In samples the bound is D3 = K3 / (c fs^2); uniform Catmull-Rom at decimation R
+ * errs by at most about R^3 D3 / 24 on smooth motion, and by up to 3/16 of R
+ * times the delay slope's jump dv / (c - u) at a knot (the largest error of the
+ * interpolated ramp max(0, x) at unit spacing is 3/16).  Take the largest R of
+ * 1, 4, 8, 16, ... up to tier_rmax that keeps both within the budget. */
+static int adaptive_decim(const orc_scene* s, const orc_params* p, const int32_t m[3])
+{
+    double slo[3], shi[3], rlo[3], rhi[3];
+    path_box(&s->src, slo, shi);
+    path_box(&s->rcv, rlo, rhi);
+    double d2 = 0.0, beta_m = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        int n_near, n_far;
+        axis_hits(m[a], &n_near, &n_far);
+        for (int r = 0; r < n_near; ++r) beta_m *= s->beta[2 * a];
+        for (int r = 0; r < n_far; ++r) beta_m *= s->beta[2 * a + 1];
+        double olo = s->mic_offset[a], ohi = s->mic_offset[a];
+        for (int c = 1; c < s->n_mics; ++c) {
+            if (s->mic_offset[3 * c + a] < olo) olo = s->mic_offset[3 * c + a];
+            if (s->mic_offset[3 * c + a] > ohi) ohi = s->mic_offset[3 * c + a];
+        }
+        double mlo = rlo[a] + olo, mhi = rhi[a] + ohi;
+        double L = s->size[a], ilo, ihi;
+        if (m[a] % 2 == 0) { ilo = m[a] * L + slo[a]; ihi = m[a] * L + shi[a]; }
+        else               { ilo = (m[a] + 1) * L - shi[a]; ihi = (m[a] + 1) * L - slo[a]; }
+        double gap = 0.0;
+        if (ilo - mhi > gap) gap = ilo - mhi;
+        if (mlo - ihi > gap) gap = mlo - ihi;
+        d2 += gap * gap;
+    }
+    int top = 1;
+    for (int r = 4; r <= p->tier_rmax; r *= 2) top = r;
+    if (beta_m == 0.0) return top;
+    double d = sqrt(d2);
+    if (!(d > 0.0)) return 1;
+    double budget = p->tier_tol * (d > 0.1 ? d : 0.1) / beta_m;
+    double vs, as, js, dvs, vr, ar, jr, dvr;
+    path_kinematics(&s->src, &vs, &as, &js, &dvs);
+    path_kinematics(&s->rcv, &vr, &ar, &jr, &dvr);
+    double u = vs + vr, acc = as + ar, jrk = js + jr;
+    double k3 = (2.0 / sqrt(3.0)) * u * u * u / (d * d) + 3.0 * u * acc / d + jrk;
+    k3 /= pow(1.0 - u / p->c, 3);
+    double d3 = k3 / (p->c * p->fs * p->fs);
+    double kink = 0.1875 * (dvs + dvr) / (p->c - u);
+    int R = 1;
+    for (int r = 4; r <= p->tier_rmax; r *= 2)
+        if ((double)r * r * r * d3 <= 24.0 * budget && (double)r * kink <= budget) R = r;
+    return R;
+}
+
+/* Decimation factor of an image: by order, the first tier whose max order
+ * covers it; adaptive, from its distance and the motion. */
+static int decim_of(const orc_scene* s, const orc_params* p, const int32_t m[3])
+{
+    if (p->tier_mode == 1) return adaptive_decim(s, p, m);
     if (p->n_tiers <= 0) return 0;
     int o = order_of(m);
     for (int k = 0; k < p->n_tiers; ++k)
@@ -247,11 +369,17 @@ static int decim_of(const orc_params* p, const int32_t m[3])
     return p->tier_decim[p->n_tiers - 1];
 }
 
+/* Exported for the tests: the decimation the oracle uses for image m. */
+int32_t orc_image_decim(const orc_scene* s, const orc_params* p, const int32_t* m)
+{
+    return decim_of(s, p, m);
+}
+
 /* Delay of image m at output sample n: exact (full rate) or Catmull-Rom of the
  * exact delays at grid samples kR (tier-emulating). */
 static double tau_at(const orc_scene* s, const orc_params* p, const int32_t m[3], int mic, int64_t n)
 {
-    int R = decim_of(p, m);
+    int R = decim_of(s, p, m);
     if (R <= 1) return orc_tau(s, p, m, mic, (double)n / p->fs);
     int64_t k = n / R;
     double u = (double)(n - k * R) / (double)R;
@@ -319,7 +447,7 @@ static void build_grids(delay_src* ds, const img_set* I, int mic)
     ds->R = (int*)calloc(I->n_img, sizeof(int));
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < I->n_img; ++i) {
-        int R = decim_of(ds->p, I->m + 3 * i);
+        int R = decim_of(ds->s, ds->p, I->m + 3 * i);
         ds->R[i] = R;
         if (R > 1) {
             int64_t len;
@@ -383,7 +511,7 @@ int orc_forward(const orc_scene* s, const orc_params* p, const double* x,
     }
     for (int mic = 0; mic < s->n_mics; ++mic) {
         delay_src ds = {s, p, NULL, NULL};
-        if (p->n_tiers > 0) build_grids(&ds, &I, mic);
+        if (tiered(p)) build_grids(&ds, &I, mic);
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t k = 0; k < ny; ++k) {
             int64_t n = k;
@@ -423,7 +551,7 @@ int orc_adjoint_x(const orc_scene* s, const orc_params* p, const double* gy, dou
             if (g_y[n] != 0.0) nz[n_nz++] = n;
         if (n_nz == 0) continue;
         delay_src ds = {s, p, NULL, NULL};
-        if (p->n_tiers > 0 && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
+        if (tiered(p) && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
 #pragma omp parallel
         {
             double* part = (double*)calloc(s->n_in, sizeof(double));
@@ -471,7 +599,7 @@ int orc_grad_beta(const orc_scene* s, const orc_params* p, const double* x, cons
             if (g_y[n] != 0.0) nz[n_nz++] = n;
         if (n_nz == 0) continue;
         delay_src ds = {s, p, NULL, NULL};
-        if (p->n_tiers > 0 && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
+        if (tiered(p) && sparse_ok(s, n_nz) == 0) build_grids(&ds, &I, mic);
 #pragma omp parallel for schedule(dynamic, 4)
         for (int64_t i = 0; i < I.n_img; ++i) {
             double acc = 0.0;

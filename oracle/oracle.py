@@ -43,7 +43,8 @@ class _Params(C.Structure):
     _fields_ = [("c", C.c_double), ("fs", C.c_double), ("max_order", C.c_int32), ("taps", C.c_int32),
                 ("kaiser_beta", C.c_double), ("cutoff", C.c_double), ("n_tiers", C.c_int32),
                 ("tier_max_order", C.c_int32 * 4), ("tier_decim", C.c_int32 * 4),
-                ("delay_model", C.c_int32)]
+                ("delay_model", C.c_int32), ("tier_mode", C.c_int32), ("tier_tol", C.c_double),
+                ("tier_rmax", C.c_int32)]
 
 
 _lib = None
@@ -80,6 +81,8 @@ def lib():
         L.orc_adjoint_x.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), dp, dp]
         L.orc_grad_beta.restype = C.c_int
         L.orc_grad_beta.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), dp, dp, dp]
+        L.orc_image_decim.restype = C.c_int32
+        L.orc_image_decim.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(C.c_int32)]
         L.orc_delays.restype = C.c_int
         L.orc_delays.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.c_int, C.c_int64,
                                  C.POINTER(C.c_int64), dp]
@@ -150,6 +153,9 @@ def _params(par, max_order: int) -> _Params:
     p.tier_max_order = (C.c_int32 * 4)(*mo)
     p.tier_decim = (C.c_int32 * 4)(*de)
     p.delay_model = int(par.delay_model)
+    p.tier_mode = int(getattr(par, "tier_mode", 0))
+    p.tier_tol = float(getattr(par, "tier_tol", 1e-3))
+    p.tier_rmax = int(getattr(par, "tier_rmax", 1024))
     return p
 
 
@@ -247,6 +253,15 @@ def grad_beta(sc, par, gy: np.ndarray, x: Optional[np.ndarray] = None) -> np.nda
     gb = np.zeros(6)
     lib().orc_grad_beta(C.byref(s), C.byref(p), _dptr(xx), _dptr(g), _dptr(gb))
     return gb
+
+
+def image_decim(sc, par, m) -> int:
+    """The decimation the oracle's tier-emulating mode uses for image m (0: full rate)."""
+    keep = _Keep()
+    s = _scene(sc, keep)
+    p = _params(par, sc.max_order)
+    mm = np.ascontiguousarray(np.asarray(m, np.int32))
+    return int(lib().orc_image_decim(C.byref(s), C.byref(p), mm.ctypes.data_as(C.POINTER(C.c_int32))))
 
 
 def delays(sc, par, mic: int, idx: Sequence[int]) -> np.ndarray:

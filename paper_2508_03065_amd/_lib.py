@@ -38,7 +38,8 @@ class Params(C.Structure):
     _fields_ = [("c", C.c_double), ("fs", C.c_double), ("taps", C.c_int32), ("kaiser_beta", C.c_double),
                 ("cutoff", C.c_double), ("table_phases", C.c_int32), ("n_tiers", C.c_int32),
                 ("tier_max_order", C.c_int32 * 4), ("tier_decim", C.c_int32 * 4), ("delay_model", C.c_int32),
-                ("fd_kind", C.c_int32), ("farrow_order", C.c_int32), ("knot_slack", C.c_double)]
+                ("fd_kind", C.c_int32), ("farrow_order", C.c_int32), ("knot_slack", C.c_double),
+                ("tier_mode", C.c_int32), ("tier_tol", C.c_double), ("tier_rmax", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -84,6 +85,7 @@ SIGNATURES = {
     "msim_get_tuning": [_PLAN, C.POINTER(Tuning)],
     "msim_get_fd_error": [_PLAN, C.POINTER(FdError)],
     "msim_plan_update": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p],
+    "msim_get_images": [_PLAN, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)],
     "msim_set_tuning": [_PLAN, C.POINTER(Tuning)],
     "msim_autotune_workspace_size": [_PLAN, C.POINTER(C.c_size_t)],
     "msim_autotune": [_PLAN, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_char_p,

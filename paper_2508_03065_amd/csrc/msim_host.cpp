@@ -271,6 +271,10 @@ msim_status check_params(const msim_params* p)
         return fail(MSIM_E_INVALID_ARG, "farrow_order must be 4..11");
     if (!(p->knot_slack >= 0.0 && p->knot_slack <= 10.0))
         return fail(MSIM_E_INVALID_ARG, "knot_slack must be in [0, 10] m");
+    if (p->tier_mode != MSIM_TIER_ORDER && p->tier_mode != MSIM_TIER_ADAPTIVE)
+        return fail(MSIM_E_INVALID_ARG, "tier_mode must be MSIM_TIER_ORDER or MSIM_TIER_ADAPTIVE");
+    if (p->tier_mode == MSIM_TIER_ADAPTIVE && (!(p->tier_tol > 0.0) || p->tier_rmax < 1 || p->tier_rmax > 4096))
+        return fail(MSIM_E_INVALID_ARG, "adaptive tiers need tier_tol > 0 and tier_rmax in 1..4096");
     return MSIM_OK;
 }
 
@@ -366,6 +370,72 @@ int tier_of(const msim_params* p, int order, int* R)
         }
     *R = p->tier_decim[p->n_tiers - 1];
     return p->n_tiers - 1;
+}
+
+// Largest of the adaptive decimations 1, 4, 8, 16, ... not above rmax.
+int largest_ladder(int rmax)
+{
+    int R = 1;
+    for (int r = 4; r <= rmax; r *= 2) R = r;
+    return R;
+}
+
+// Largest speed, acceleration and jerk of a path, and its largest velocity
+// change at an inner knot (a PWL path read as samples of a smooth one: that
+// change spread over the mean of its two pieces' durations is the acceleration;
+// no jerk; a circle: v, v^2/r, v^3/r^2 and no knots).
+struct Kin {
+    double v = 0.0, a = 0.0, j = 0.0, dv = 0.0;
+};
+
+Kin traj_kin(const msim_traj& tr)
+{
+    Kin k;
+    if (tr.kind == MSIM_TRAJ_CIRCLE) {
+        k.v = tr.speed;
+        k.a = tr.speed * tr.speed / tr.radius;
+        k.j = k.a * tr.speed / tr.radius;
+        return k;
+    }
+    std::vector<double> vel;
+    for (int i = 0; i + 1 < tr.n_points; ++i) {
+        const double dt = tr.t[i + 1] - tr.t[i];
+        double s2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double v = (tr.p[3 * (i + 1) + a] - tr.p[3 * i + a]) / dt;
+            vel.push_back(v);
+            s2 += v * v;
+        }
+        k.v = std::max(k.v, std::sqrt(s2));
+    }
+    for (int i = 1; i + 1 < tr.n_points; ++i) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double e = vel[3 * i + a] - vel[3 * (i - 1) + a];
+            d2 += e * e;
+        }
+        k.dv = std::max(k.dv, std::sqrt(d2));
+        k.a = std::max(k.a, std::sqrt(d2) / (0.5 * (tr.t[i + 1] - tr.t[i - 1])));
+    }
+    return k;
+}
+
+// Decimation of an image (MSIM_TIER_ADAPTIVE, documented at msim_plan_create):
+// d its distance bound (m), beta_i its reflection product; u, a, j, dv the
+// relative motion bounds and the largest velocity change at a knot.
+int adaptive_decim(const msim_params& p, double u, double a, double j, double dv, double d, double beta_i)
+{
+    if (beta_i == 0.0) return largest_ladder(p.tier_rmax);
+    if (!(d > 0.0)) return 1;
+    const double tol = p.tier_tol * std::max(d, 0.1) / beta_i;       // this image's error budget
+    const double k3 = ((2.0 / std::sqrt(3.0)) * u * u * u / (d * d) + 3.0 * u * a / d + j) /
+                      std::pow(1.0 - u / p.c, 3);
+    const double d3 = k3 / (p.c * p.fs * p.fs);
+    const double kink = 0.1875 * dv / (p.c - u);
+    int R = 1;
+    for (int r = 4; r <= p.tier_rmax; r *= 2)
+        if ((double)r * r * r * d3 <= 24.0 * tol && (double)r * kink <= tol) R = r;
+    return R;
 }
 
 // Interval of image coordinates along one axis for source coordinates in [lo, hi].
@@ -750,6 +820,8 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
     std::vector<HostImage> imgs;
     imgs.reserve((size_t)count_images(K));
     Box sb = traj_box(s.src), rb = traj_box(s.rcv);
+    const Box sb0 = sb;             // the path itself (adaptive decimations)
+    const Kin ks = traj_kin(s.src), kr = traj_kin(s.rcv);
     for (int a = 0; a < 3; ++a) {   // knots may later move by up to the slack
         sb.lo[a] -= p.knot_slack;
         sb.hi[a] += p.knot_slack;
@@ -781,7 +853,19 @@ msim_status plan_scene(msim_plan* P, const msim_scene& s, int si, int64_t x_off,
                     b *= std::pow(s.beta[2 * a], near) * std::pow(s.beta[2 * a + 1], far);
                 }
                 h.beta = b;
-                h.tier = tier_of(&p, std::abs(mx) + std::abs(my) + std::abs(mz), &h.R);
+                if (p.tier_mode == MSIM_TIER_ADAPTIVE) {
+                    double g2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double lo, hi;
+                        image_interval(h.m[a], s.size[a], sb0.lo[a], sb0.hi[a], &lo, &hi);
+                        const double gap = std::max(0.0, std::max(lo - mb.hi[a], mb.lo[a] - hi));
+                        g2 += gap * gap;
+                    }
+                    h.tier = 0;
+                    h.R = adaptive_decim(p, ks.v + kr.v, ks.a + kr.a, ks.j + kr.j, ks.dv + kr.dv, std::sqrt(g2), b);
+                } else {
+                    h.tier = tier_of(&p, std::abs(mx) + std::abs(my) + std::abs(mz), &h.R);
+                }
                 double dmin2 = 0.0, dmax2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
                     double lo, hi;
@@ -1612,6 +1696,9 @@ msim_status msim_default_params(msim_params* p)
     p->fd_kind = MSIM_FD_TABLE;
     p->farrow_order = 9;
     p->knot_slack = 0.0;
+    p->tier_mode = MSIM_TIER_ORDER;
+    p->tier_tol = 1e-3;
+    p->tier_rmax = 1024;
     return MSIM_OK;
 }
 
@@ -1647,7 +1734,12 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         if ((st = check_scene(scenes[s], p, s)) != MSIM_OK) return st;
     msim_plan* P = new msim_plan();
     P->par = *p;
-    P->rb_max = farrow_outputs_per_lane(p->tier_decim, p->n_tiers);
+    {
+        // adaptive decimations are 1 or multiples of 4
+        const int32_t four[1] = {4};
+        P->rb_max = p->tier_mode == MSIM_TIER_ADAPTIVE ? farrow_outputs_per_lane(four, 1)
+                                                        : farrow_outputs_per_lane(p->tier_decim, p->n_tiers);
+    }
     if (p->fd_kind != MSIM_FD_FARROW) {
         // Two outputs per lane read the table rows of the earlier one: fine while
         // the delay drifts by well under two rows per sample.  An image moves no
@@ -2151,6 +2243,24 @@ msim_status msim_plan_update(msim_plan* P, const double* beta, const double* kno
                     put(P->d_images, P->images.data(), P->images.size() * sizeof(DImage)) &&
                     hipStreamSynchronize(stream) == hipSuccess;
     if (!ok) return fail(MSIM_E_HIP, "plan update upload failed");
+    return MSIM_OK;
+}
+
+msim_status msim_get_images(const msim_plan* P, int32_t scene, int32_t* out, int64_t capacity, int64_t* n_img)
+{
+    if (!P || !n_img) return fail(MSIM_E_INVALID_ARG, "NULL argument");
+    if (scene < 0 || scene >= P->n_scenes) return fail(MSIM_E_INVALID_ARG, "scene %d out of range", scene);
+    const DScene& d = P->scenes[scene];
+    *n_img = d.n_img;
+    if (!out) return MSIM_OK;
+    if (capacity < d.n_img) return fail(MSIM_E_INVALID_ARG, "capacity %lld < %d images", (long long)capacity, d.n_img);
+    for (int i = 0; i < d.n_img; ++i) {
+        const DImage& im = P->images[d.img_begin + i];
+        out[4 * i] = im.m[0];
+        out[4 * i + 1] = im.m[1];
+        out[4 * i + 2] = im.m[2];
+        out[4 * i + 3] = im.R;
+    }
     return MSIM_OK;
 }
 

@@ -67,6 +67,9 @@ def params_struct(par, table_phases: int = 128) -> _lib.Params:
     p.fd_kind = int(getattr(par, "fd_kind", 0))
     p.farrow_order = int(getattr(par, "farrow_order", 9))
     p.knot_slack = float(getattr(par, "knot_slack", 0.0))
+    p.tier_mode = int(getattr(par, "tier_mode", 0))
+    p.tier_tol = float(getattr(par, "tier_tol", 1e-3))
+    p.tier_rmax = int(getattr(par, "tier_rmax", 1024))
     return p
 
 
@@ -203,6 +206,14 @@ class Plan:
             raise ValueError("knots must hold src_total = %d rows" % self.src_total)
         ptr = lambda a: C.c_void_p(a.ctypes.data) if a is not None else None
         check(_lib.load().msim_plan_update(self._ptr, ptr(b), ptr(k), _stream_handle(stream)))
+
+    def images(self, scene: int) -> np.ndarray:
+        """[n_img, 4] int32: (mx, my, mz, decimation R) of the scene's images (plan order)."""
+        n = C.c_int64()
+        check(_lib.load().msim_get_images(self._ptr, int(scene), None, 0, C.byref(n)))
+        out = np.zeros((n.value, 4), np.int32)
+        check(_lib.load().msim_get_images(self._ptr, int(scene), C.c_void_p(out.ctypes.data), n.value, C.byref(n)))
+        return out
 
     def fd_error(self) -> dict:
         """Predicted relative errors of the fractional-delay approximations and the budget."""

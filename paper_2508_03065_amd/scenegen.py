@@ -89,6 +89,9 @@ class Params:
     fd_kind: int = 0                          # how the library applies the kernel: 0 table, 1 Farrow
     farrow_order: int = 9
     knot_slack: float = 0.0                   # m a plan lets its source knots move (msim_plan_update)
+    tier_mode: int = 0                        # 0: tiers by order; 1: adaptive per image (tier_tol, tier_rmax)
+    tier_tol: float = 1e-3                    # adaptive: delay interpolation error bound, samples
+    tier_rmax: int = 1024                     # adaptive: largest decimation
 
 
 PAPER_TIERS = ((2, 1), (6, 16), (1 << 20, 160))

@@ -5,9 +5,9 @@ evaluate one by one (its output-subset mode solves the delays it needs locally).
 * 32-scene differentiation workload (6x5x3 m, K = 10, 2 s, 8-knot paths): the
   batched forward of all scenes, checked on sampled outputs of two scenes; the
   backward of all scenes for a loss whose gradient dL/dy is non-zero only on
-  sampled outputs of scenes 0 and 1, so the oracle's adjoints and its central
-  differences for the knots stay cheap.  Scenes with dL/dy = 0 must get exactly
-  zero gradients.
+  sampled outputs of scenes 0-3, so the oracle's adjoints and its FP64 central
+  differences (step 1e-6) for the knots and the wall coefficients of those four
+  scenes stay cheap.  Scenes with dL/dy = 0 must get exactly zero gradients.
 * the large workload (64 scenes of 12x9x4 m, 48 kHz, 10 s, moving source and
   receiver, 8-mic array, K = 20 -> 11 521 images, T = 96): the batched forward
   of all 64 scenes (one persistent launch, graph-replayed), checked on sampled
@@ -46,21 +46,35 @@ def config4_case():
     scenes, par = G.config4()
     rng = np.random.default_rng(44)
     sparse = {}
-    for s in (0, 1):
+    for s in range(4):
         idx = np.sort(rng.choice(scenes[s].n_out, 48, replace=False))
         sparse[s] = (idx, rng.standard_normal((scenes[s].n_mics, 48)))
-    # central differences of L = <gy, y> in the source knots of scene 0 (oracle, FP64)
-    sc = scenes[0]
-    idx, w = sparse[0]
-    fd = np.zeros_like(sc.src.p)
+    # FP64 central differences (step 1e-6) of L = <gy, y> in the source knots and
+    # the wall coefficients of scenes 0-3 (the oracle's output-subset mode)
     h = 1e-6
-    for k in range(sc.src.p.shape[0]):
-        for a in range(3):
+    fd_knots, fd_beta = {}, {}
+    for s in range(4):
+        sc = scenes[s]
+        idx, w = sparse[s]
+        loss = lambda c: np.sum(O.forward(c, par, idx=idx) * w)
+        g = np.zeros_like(sc.src.p)
+        for k in range(sc.src.p.shape[0]):
+            for a in range(3):
+                sp, sm = sc.copy(), sc.copy()
+                sp.src.p[k, a] += h
+                sm.src.p[k, a] -= h
+                g[k, a] = (loss(sp) - loss(sm)) / (2 * h)
+        fd_knots[s] = g
+        b = np.zeros(6)
+        for wall in range(6):
             sp, sm = sc.copy(), sc.copy()
-            sp.src.p[k, a] += h
-            sm.src.p[k, a] -= h
-            fd[k, a] = (np.sum(O.forward(sp, par, idx=idx) * w) - np.sum(O.forward(sm, par, idx=idx) * w)) / (2 * h)
-    return scenes, par, sparse, fd
+            sp.beta = sc.beta.copy()
+            sm.beta = sc.beta.copy()
+            sp.beta[wall] += h
+            sm.beta[wall] -= h
+            b[wall] = (loss(sp) - loss(sm)) / (2 * h)
+        fd_beta[s] = b
+    return scenes, par, sparse, (fd_knots, fd_beta)
 
 
 @pytest.mark.parametrize("form", sorted(FORMS))
@@ -88,20 +102,22 @@ def test_config4_batched_forward_and_gradients(torch_cuda, config4_case, form):
         g[:, idx] = w
         dense[s] = g
         gy_full[plan.y_off[s]:plan.y_off[s] + g.size] = g.reshape(-1)
-    gx, gb, gs = plan.backward(x, torch.from_numpy(gy_full).cuda())
+    gx, gb, gs = plan.backward(x, torch.from_numpy(gy_full).cuda(), batched=True)
     torch.cuda.synchronize()
     assert plan.device_status() == 0
     gx, gb, gs = gx.cpu().numpy(), gb.cpu().numpy(), gs.cpu().numpy()
-    for s in (0, 1):
+    fd_knots, fd_beta = fd
+    for s in range(4):
         assert rel(gb[s], O.grad_beta(scenes[s], par0, dense[s])) <= 1e-4, s
-    o = plan.x_off[0]
-    assert rel(gx[o:o + scenes[0].n_in], O.adjoint_x(scenes[0], par0, dense[0])) <= 1e-5
-    k0 = scenes[0].src.p.shape[0]
-    assert rel(gs[:k0], fd) <= 1e-3
+        assert rel(gb[s], fd_beta[s]) <= 1e-3, s
+        o = plan.x_off[s]
+        assert rel(gx[o:o + scenes[s].n_in], O.adjoint_x(scenes[s], par0, dense[s])) <= 1e-5, s
+        k0 = plan.src_off[s]
+        assert rel(gs[k0:k0 + scenes[s].src.p.shape[0]], fd_knots[s]) <= 1e-3, s
     # scenes without loss gradient get exactly zero
-    assert not np.any(gb[2:])
-    assert not np.any(gx[plan.x_off[2]:])
-    assert not np.any(gs[plan.src_off[2]:])
+    assert not np.any(gb[4:])
+    assert not np.any(gx[plan.x_off[4]:])
+    assert not np.any(gs[plan.src_off[4]:])
 
 
 @pytest.fixture(scope="module")
