@@ -270,6 +270,24 @@ def measure_batched_form(scenes, par, fd, steps, warmup, fb_steps, torch, worklo
     return rec
 
 
+def measure_full_batch(scenes, par, steps, torch):
+    """Batched forward of every scene of the workload in one launch (graph replays)."""
+    from paper_2508_03065_amd.msim import Plan
+    t0 = time.perf_counter()
+    plan = Plan(scenes, par)
+    t_plan = time.perf_counter() - t0
+    x = plan.pack_x([s.x for s in scenes])
+    y = torch.empty(plan.y_total, dtype=torch.float32, device="cuda")
+    plan.forward_batched(x, y)
+    sec = timed(lambda: plan.forward_batched(x, y), steps, torch)
+    out = {"fd": "farrow", "scenes": len(scenes), "images": int(plan.n_images.sum()), "steps": steps,
+           "taps_per_step": plan.forward_taps, "value": plan.forward_taps / sec, "unit": "taps/s",
+           "ms_per_step": sec * 1e3, "plan_s": t_plan}
+    del plan, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_batched_vs_plain(scenes, par, steps, torch, with_backward):
     """Seconds per step of the batched path (graph replays) and of the plain
     path (launches per scene) on the same plan."""
@@ -398,6 +416,12 @@ def main():
         rec[other] = measure_batched_form(scenes, with_fd(par0, other), other, max(3, args.steps // 4), 1,
                                           fb_steps, torch, args.workload)
         del all_scenes, scenes
+        if args.workload == "config5":
+            # the whole 64-scene batch as one launch, in the faster form
+            note("all 64 scenes, farrow form")
+            s64, p64 = G.config5()
+            rec["full_batch"] = measure_full_batch(s64, with_fd(p64, "farrow"), 2, torch)
+            del s64
         note("batched vs plain: config4 forward+backward")
         s4, p4 = G.config4()
         rec["batched_vs_plain"] = {
