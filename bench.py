@@ -175,10 +175,10 @@ def timed(fn, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def kernel_roofline(fd, kind, prof, work_flops, workload, lds_bytes=None):
+def kernel_roofline(fd, kind, prof, work_flops, workload, lds_bytes=None, gather=False):
     """Roofline of one kernel kind from the plan's HIP-event profile: achieved
     FLOP/s = algorithmic flops per launch / average launch duration."""
-    kernel, src = KERNEL_OF[fd][kind]
+    kernel, src = KERNEL_OF["farrow" if kind == "adjx" and gather else fd][kind]
     key = PROFILE_KEY[kind]
     n = max(1, prof[key + "_launches"])
     kms = prof[key + "_ms"] / n
@@ -205,13 +205,14 @@ def fwd_work(plan, par, fd):
 
 
 def bwd_work(plan, par, fd):
-    """Algorithmic flops of one launch of the dL/dx kernel and of the gain/delay kernel."""
-    if fd == "table":
-        t = plan.forward_taps
-        return {"adjx": t * FLOPS_PER_TAP, "adjp": t * FLOPS_PER_TAP_GD}
+    """Algorithmic flops of one launch of the dL/dx kernel (the table form's own
+    transpose, or the Farrow gather that both forms use by default) and of the
+    gain/delay kernel."""
     s = image_samples(plan, par)
     f = farrow_flops(par.farrow_order)
-    return {"adjx": s * f["adjx"], "adjp": s * f["adjp"]}
+    t = plan.forward_taps
+    adjx = s * f["adjx"] if plan.tuning()["adjx_gather"] else t * FLOPS_PER_TAP
+    return {"adjx": adjx, "adjp": t * FLOPS_PER_TAP_GD if fd == "table" else s * f["adjp"]}
 
 
 def measure_batched_form(scenes, par, fd, steps, warmup, fb_steps, torch, workload):
@@ -263,7 +264,8 @@ def measure_batched_form(scenes, par, fd, steps, warmup, fb_steps, torch, worklo
         "roofline": {"bound": "alu", "achieved": step_flops / (kern * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": step_flops / (kern * 1e-3) / PEAK_FP32,
                      "flops_per_step": step_flops, "kernel_ms_per_step": kern,
-                     "kernels": {"adjx": kernel_roofline(fd, "adjx", pb, bw["adjx"], workload),
+                     "kernels": {"adjx": kernel_roofline(fd, "adjx", pb, bw["adjx"], workload,
+                                                         gather=bool(plan.tuning()["adjx_gather"])),
                                  "adjp": kernel_roofline(fd, "adjp", pb, bw["adjp"], workload)}}}
     del plan, x, y, gy, out
     torch.cuda.empty_cache()

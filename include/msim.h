@@ -56,6 +56,7 @@ typedef enum {
 enum { MSIM_TRAJ_PWL = 0, MSIM_TRAJ_CIRCLE = 1 };
 enum { MSIM_DELAY_RETARDED = 0, MSIM_DELAY_INSTANTANEOUS = 1 };
 enum { MSIM_TIER_ORDER = 0, MSIM_TIER_ADAPTIVE = 1 };
+enum { MSIM_ADJX_GATHER = 0, MSIM_ADJX_TRANSPOSE = 1 };
 
 /* A trajectory.  PWL: positions p[3k..3k+2] at strictly increasing times t[k],
  * linear in between, held constant before t[0] and after t[n_points-1]; one knot
@@ -109,6 +110,14 @@ typedef struct {
                                    near field of a close image), see msim_plan_create */
     double tier_tol;            /* adaptive: bound on the interpolated delay's error, samples (> 0) */
     int32_t tier_rmax;          /* adaptive: largest decimation, 1..4096 */
+    int32_t adjx_mode;          /* dL/dx in the backward.  MSIM_ADJX_GATHER (default): every
+                                   source position gathers the image samples that read it and
+                                   the Farrow filter bank is transposed (Sec. II-B, Eq. 3-5;
+                                   in the table form this is the transpose of the Farrow fit of
+                                   the same kernel, within its error of the table's); taken
+                                   unless the Farrow fit exceeds the error budget or a
+                                   whole-path window does not fit LDS.  MSIM_ADJX_TRANSPOSE:
+                                   the table form's exact transpose.  farrow_order 4..11. */
 } msim_params;
 
 /* How the T-tap Kaiser-windowed sinc h(j - mu) is applied.
@@ -219,6 +228,7 @@ typedef struct {
     int32_t outputs_per_lane;
     int32_t workgroups;   /* output only */
     double ms;            /* output only: the batched forward time that chose it */
+    int32_t adjx_gather;  /* output only: 1 when the backward's dL/dx is the Farrow gather */
 } msim_tuning;
 
 msim_status msim_get_tuning(const msim_plan* plan, msim_tuning* t);

@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("cutoff", C.c_double), ("table_phases", C.c_int32), ("n_tiers", C.c_int32),
                 ("tier_max_order", C.c_int32 * 4), ("tier_decim", C.c_int32 * 4), ("delay_model", C.c_int32),
                 ("fd_kind", C.c_int32), ("farrow_order", C.c_int32), ("knot_slack", C.c_double),
-                ("tier_mode", C.c_int32), ("tier_tol", C.c_double), ("tier_rmax", C.c_int32)]
+                ("tier_mode", C.c_int32), ("tier_tol", C.c_double), ("tier_rmax", C.c_int32),
+                ("adjx_mode", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -53,7 +54,7 @@ class Profile(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("group_cap", C.c_int32), ("outputs_per_lane", C.c_int32),
-                ("workgroups", C.c_int32), ("ms", C.c_double)]
+                ("workgroups", C.c_int32), ("ms", C.c_double), ("adjx_gather", C.c_int32)]
 
 
 class FdError(C.Structure):

@@ -267,10 +267,11 @@ msim_status check_params(const msim_params* p)
     if (p->delay_model != MSIM_DELAY_RETARDED && p->delay_model != MSIM_DELAY_INSTANTANEOUS)
         return fail(MSIM_E_INVALID_ARG, "unknown delay_model");
     if (p->fd_kind != MSIM_FD_TABLE && p->fd_kind != MSIM_FD_FARROW) return fail(MSIM_E_INVALID_ARG, "unknown fd_kind");
-    if (p->fd_kind == MSIM_FD_FARROW && (p->farrow_order < 4 || p->farrow_order > 11))
-        return fail(MSIM_E_INVALID_ARG, "farrow_order must be 4..11");
+    if (p->farrow_order < 4 || p->farrow_order > 11) return fail(MSIM_E_INVALID_ARG, "farrow_order must be 4..11");
     if (!(p->knot_slack >= 0.0 && p->knot_slack <= 10.0))
         return fail(MSIM_E_INVALID_ARG, "knot_slack must be in [0, 10] m");
+    if (p->adjx_mode != MSIM_ADJX_GATHER && p->adjx_mode != MSIM_ADJX_TRANSPOSE)
+        return fail(MSIM_E_INVALID_ARG, "adjx_mode must be MSIM_ADJX_GATHER or MSIM_ADJX_TRANSPOSE");
     if (p->tier_mode != MSIM_TIER_ORDER && p->tier_mode != MSIM_TIER_ADAPTIVE)
         return fail(MSIM_E_INVALID_ARG, "tier_mode must be MSIM_TIER_ORDER or MSIM_TIER_ADAPTIVE");
     if (p->tier_mode == MSIM_TIER_ADAPTIVE && (!(p->tier_tol > 0.0) || p->tier_rmax < 1 || p->tier_rmax > 4096))
@@ -488,6 +489,8 @@ struct msim_plan {
                                           //   occupancy wins over shared segment fetches), and the
                                           //   largest the form and the tier decimations allow
     double err_table = 0.0, err_pair = 0.0, err_farrow = 0.0;   // predicted fractional-delay errors
+    bool ugather = false;                 // dL/dx by the Farrow gather (both forms; else the table transpose)
+    int slot_segs_fwd = 1, gmax_fwd = 1;  // the forward's slots (block groups only)
     std::vector<DScene> scenes;           // host copies
     std::vector<DImage> images;
     std::vector<DGroup> groups;
@@ -1007,6 +1010,11 @@ msim_status regroup(msim_plan* P)
 {
     const int NT = P->threads, T = P->par.taps, L = P->par.table_phases;
     const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
+    // dL/dx through the Farrow gather: always in the Farrow form; in the table form
+    // unless asked for its own transpose, or the Farrow fit misses the budget, or a
+    // whole-path window does not fit LDS (then the table's transpose is used)
+    P->ugather = farrow || (P->par.adjx_mode == MSIM_ADJX_GATHER && P->err_farrow <= kFdErrBudget);
+    bool ugather = P->ugather;
     P->groups.clear();
     P->blocks.clear();
     P->perm.clear();
@@ -1014,7 +1022,7 @@ msim_status regroup(msim_plan* P)
     P->wperm.clear();
     P->uwin = 0;
     P->grad_ok.clear();
-    int slot_segs = 1, gmax = 1;
+    int slot_segs = 1, gmax = 1, slot_segs_fwd = 1, gmax_fwd = 1;
     for (int s = 0; s < P->n_scenes; ++s) {
         DScene& d = P->scenes[s];
         const int I = d.n_img;
@@ -1136,8 +1144,8 @@ msim_status regroup(msim_plan* P)
                 }
                 if (loc > INT32_MAX / 4)
                     return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
-                slot_segs = std::max(slot_segs, (int)loc);
-                gmax = std::max(gmax, g.img_end - g.img_begin);
+                slot_segs_fwd = std::max(slot_segs_fwd, (int)loc);
+                gmax_fwd = std::max(gmax_fwd, g.img_end - g.img_begin);
                 g.img_end = base + (g.img_end - g.img_begin);
                 g.img_begin = base;
                 P->groups.push_back(g);
@@ -1156,7 +1164,7 @@ msim_status regroup(msim_plan* P)
         // (its items reach outputs across blocks), in the images' whole-path order
         d.wgrp_begin = (int)P->wgroups.size();
         d.n_wgrp = 0;
-        if (farrow) {
+        if (ugather) {
             const auto& bnd = P->bounds[s];
             int G = std::max((I + 255) / 256, (I + kMaxGroup - 1) / kMaxGroup);
             for (;;) {
@@ -1177,8 +1185,11 @@ msim_status regroup(msim_plan* P)
                     G = std::min(I, 2 * G);
                     continue;
                 }
-                if (farrow_u_lds_bytes(uw) > kLdsLimit)
-                    return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                if (farrow_u_lds_bytes(uw) > kLdsLimit) {
+                    if (farrow) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
+                    ugather = false;   // the table form falls back to its own transpose
+                    break;
+                }
                 P->uwin = std::max(P->uwin, uw);
                 for (DGroup g : gr) {
                     const int span = group_span(NT, g.dmin, g.dmax);
@@ -1201,8 +1212,20 @@ msim_status regroup(msim_plan* P)
             }
         }
     }
-    P->slot_segs = slot_segs;
-    P->gmax = gmax;
+    if (P->ugather && !ugather) {
+        P->ugather = false;
+        P->wgroups.clear();
+        P->wperm.clear();
+        P->uwin = 0;
+        for (DScene& d : P->scenes) {
+            d.wgrp_begin = 0;
+            d.n_wgrp = 0;
+        }
+    }
+    P->slot_segs = std::max(slot_segs, slot_segs_fwd);
+    P->gmax = std::max(gmax, gmax_fwd);
+    P->slot_segs_fwd = slot_segs_fwd;
+    P->gmax_fwd = gmax_fwd;
     // Supergroups: a work item sums the groups of one supergroup of one (mic, tile)
     // in registers and writes one partial output row.  Each scene gets items
     // enough to fill the persistent grid several times on its own (the plain path
@@ -1312,18 +1335,18 @@ msim_status regroup(msim_plan* P)
         d.sgb_stride = b.sgb_stride = P->sgb_stride;
         d.xw_stride = b.xw_stride = xs;
         const int64_t nr = (int64_t)d.n_mics * d.n_sg * d.n_tiles;
-        const int64_t nx = farrow ? 0 : nr * xs;
+        const int64_t nx = P->ugather ? 0 : nr * xs;
         // Farrow dL/dx gather: supergroups of whole-path groups, items per position tile
         d.n_ptiles = b.n_ptiles = (int)((d.n_in + T + kAdjThreads - 1) / kAdjThreads);
         int nsgw = 0;
-        if (farrow) {
+        if (P->ugather) {
             const int64_t tm = std::max<int64_t>(1, (int64_t)d.n_ptiles * d.n_mics);
             nsgw = (int)std::min<int64_t>(d.n_wgrp, std::max<int64_t>(1, (want + tm - 1) / tm));
             const int64_t per = (int64_t)d.n_mics * (d.n_in + T) * kFarrowStride;
             nsgw = (int)std::max<int64_t>(1, std::min<int64_t>(nsgw, budget / std::max<int64_t>(1, per * P->n_scenes)));
         }
         d.n_sgw = b.n_sgw = nsgw;
-        const int64_t nu = farrow ? (int64_t)d.n_mics * nsgw * (d.n_in + T) * kFarrowStride : 0;
+        const int64_t nu = P->ugather ? (int64_t)d.n_mics * nsgw * (d.n_in + T) * kFarrowStride : 0;
         d.row_base = 0;
         d.xw_base = 0;
         d.u_base = 0;
@@ -1336,7 +1359,7 @@ msim_status regroup(msim_plan* P)
         P->max_rows = std::max(P->max_rows, nr);
         P->max_xw = std::max(P->max_xw, nx);
         P->max_upart = std::max(P->max_upart, nu);
-        if (farrow) {
+        if (P->ugather) {
             std::vector<std::pair<double, WorkItem>> its;
             for (int sg = 0; sg < nsgw; ++sg) {
                 const int gb = sg_begin(d.n_wgrp, nsgw, sg), ge = sg_begin(d.n_wgrp, nsgw, sg + 1);
@@ -1370,13 +1393,14 @@ msim_status regroup(msim_plan* P)
             return 256 * (int)std::max<size_t>(1, std::min<size_t>(2048 / threads, kLdsLimit / std::max<size_t>(1, l)));
         };
         int g = 1;
-        if (farrow) {
-            g = std::max(g, grid(farrow_gd_lds_bytes(wmax), kAdjThreads));
+        if (P->ugather)
             g = std::max(g, grid(farrow_u_lds_bytes(std::max(1, P->uwin)), kAdjThreads));
-        } else {
+        else
             g = std::max(g, grid(adj_x_lds_bytes(T, L, wmax, NT), kAdjThreads));
+        if (farrow)
+            g = std::max(g, grid(farrow_gd_lds_bytes(wmax), kAdjThreads));
+        else
             g = std::max(g, grid(adj_track_lds_bytes(T, L, wmax), P->rb == 1 ? kAdjThreads : NT / 2));
-        }
         P->adj_wgs = g;
     }
     P->graph_valid = false;
@@ -1438,9 +1462,9 @@ PlanView plan_view(const msim_plan* P, const DScene* scenes)
 }
 
 // Bytes of one workgroup's track slot for the forward.
-int64_t fwd_slot_bytes(const msim_plan* P) { return slot_extra_off(P->slot_segs, P->gmax); }
+int64_t fwd_slot_bytes(const msim_plan* P) { return slot_extra_off(P->slot_segs_fwd, P->gmax_fwd); }
 
-TrackArgs track_args(const msim_plan* P, char* slots, int64_t slot_bytes)
+TrackArgs track_args(const msim_plan* P, char* slots, int64_t slot_bytes, bool fwd)
 {
     TrackArgs ta;
     ta.knots = P->d_knots;
@@ -1448,7 +1472,7 @@ TrackArgs track_args(const msim_plan* P, char* slots, int64_t slot_bytes)
     ta.c = P->par.c;
     ta.fs = P->par.fs;
     ta.model = P->par.delay_model;
-    ta.slot_segs = P->slot_segs;
+    ta.slot_segs = fwd ? P->slot_segs_fwd : P->slot_segs;
     ta.slots = slots;
     ta.slot_bytes = slot_bytes;
     return ta;
@@ -1497,7 +1521,7 @@ size_t carve_fwd_ws(const msim_plan* P, bool batched, char* base, FwdWs2* w)
 msim_status enqueue_forward(msim_plan* P, const float* x, float* y, const FwdWs2& w, bool batched, hipStream_t st)
 {
     const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
-    const TrackArgs ta = track_args(P, w.slots, fwd_slot_bytes(P));
+    const TrackArgs ta = track_args(P, w.slots, fwd_slot_bytes(P), true);
     if (farrow) {
         LaunchTimer t(P, kKindFilter, st);
         HIP_OK(launch_farrow_conv(P->d_scenes, P->n_scenes, P->d_vpos_prefix, P->vpos_total, P->par.taps,
@@ -1558,7 +1582,7 @@ size_t carve_bwd_ws(const msim_plan* P, bool batched, char* base, BwdWs* w)
         return p;
     };
     char* v = take(farrow_v_bytes(P));
-    char* u = take(farrow_v_bytes(P));
+    char* u = take(P->ugather ? align_up((size_t)P->vpos_total * kFarrowStride * sizeof(float)) : 0);
     char* sl = take((size_t)P->adj_wgs * (size_t)adj_slot_size(P));
     char* xw = take((size_t)(batched ? P->b_xw : P->max_xw) * sizeof(float));
     char* up = take((size_t)(batched ? P->b_upart : P->max_upart) * sizeof(float));
@@ -1600,7 +1624,7 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
 {
     const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
     const int T = P->par.taps, L = P->par.table_phases, NT = P->threads;
-    const TrackArgs ta = track_args(P, w.slots, adj_slot_size(P));
+    const TrackArgs ta = track_args(P, w.slots, adj_slot_size(P), false);
     ParamArgs pa;
     pa.rows = w.rows;
     pa.gmax = P->gmax;
@@ -1625,7 +1649,7 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
         one.scenes = scenes;
         if (gx) {
             LaunchTimer t(P, kKindAdjX, st);
-            if (farrow) {
+            if (P->ugather) {
                 PlanView wv = pv;
                 wv.groups = P->d_wgroups;
                 wv.perm = P->d_wperm;
@@ -1699,6 +1723,7 @@ msim_status msim_default_params(msim_params* p)
     p->tier_mode = MSIM_TIER_ORDER;
     p->tier_tol = 1e-3;
     p->tier_rmax = 1024;
+    p->adjx_mode = MSIM_ADJX_GATHER;
     return MSIM_OK;
 }
 
@@ -1768,6 +1793,7 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         }
     } else {
         P->err_table = table_error(P);
+        P->err_farrow = farrow_error(P);   // its dL/dx goes through the Farrow gather
         if (P->err_table > kFdErrBudget) {
             const double e = P->err_table;
             delete P;
@@ -2161,6 +2187,7 @@ msim_status msim_get_tuning(const msim_plan* P, msim_tuning* out)
     out->outputs_per_lane = P->rb;
     out->workgroups = P->b_wgs;
     out->ms = 0.0;
+    out->adjx_gather = P->ugather ? 1 : 0;
     return MSIM_OK;
 }
 
@@ -2329,7 +2356,7 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
     // a cached shape this plan accepts is used as it is; one it refuses (another
     // build's limits, a hand-edited line) is timed again
     if (cache_lookup(cache_path, key, &bt, &bc, &brb)) {
-        msim_tuning t{bt, bc, brb, 0, 0.0};
+        msim_tuning t{bt, bc, brb, 0, 0.0, 0};
         if (msim_set_tuning(P, &t) == MSIM_OK) {
             if (best_out) msim_get_tuning(P, best_out);
             return MSIM_OK;
@@ -2389,7 +2416,7 @@ msim_status msim_autotune(msim_plan* P, const float* x, float* y, void* ws, size
                 }
             }
     if (bt == 0) return fail(MSIM_E_WORKSPACE, "no tuning candidate fits the workspace");
-    msim_tuning t{bt, bc, brb, 0, best};
+    msim_tuning t{bt, bc, brb, 0, best, 0};
     P->profiling = guard.prof;
     msim_status st = msim_set_tuning(P, &t);
     if (st != MSIM_OK) return st;

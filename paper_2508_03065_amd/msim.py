@@ -70,6 +70,7 @@ def params_struct(par, table_phases: int = 128) -> _lib.Params:
     p.tier_mode = int(getattr(par, "tier_mode", 0))
     p.tier_tol = float(getattr(par, "tier_tol", 1e-3))
     p.tier_rmax = int(getattr(par, "tier_rmax", 1024))
+    p.adjx_mode = int(getattr(par, "adjx_mode", 0))
     return p
 
 
@@ -222,7 +223,7 @@ class Plan:
         return {k: getattr(e, k) for k, _ in _lib.FdError._fields_}
 
     def set_tuning(self, threads: int, group_cap: int = 0, outputs_per_lane: int = 0):
-        t = _lib.Tuning(threads, group_cap, outputs_per_lane, 0, 0.0)
+        t = _lib.Tuning(threads, group_cap, outputs_per_lane, 0, 0.0, 0)
         check(_lib.load().msim_set_tuning(self._ptr, C.byref(t)))
 
     def autotune(self, x: torch.Tensor, cache_path: Optional[str] = None, stream=None) -> dict:

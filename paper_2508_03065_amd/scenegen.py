@@ -92,6 +92,7 @@ class Params:
     tier_mode: int = 0                        # 0: tiers by order; 1: adaptive per image (tier_tol, tier_rmax)
     tier_tol: float = 1e-3                    # adaptive: delay interpolation error bound, samples
     tier_rmax: int = 1024                     # adaptive: largest decimation
+    adjx_mode: int = 0                        # dL/dx: 0 Farrow gather, 1 the table form's own transpose
 
 
 PAPER_TIERS = ((2, 1), (6, 16), (1 << 20, 160))
