@@ -349,7 +349,7 @@ def main():
                          "scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(scenes or output tiles would shard with no exchange)", file=sys.stderr)
         sys.exit(2)
 

@@ -48,7 +48,7 @@ typedef enum {
     MSIM_E_TOO_CLOSE = 3,     /* source and a mic closer than 1 mm at a knot time */
     MSIM_E_SUPERSONIC = 4,    /* a trajectory segment faster than c/10 */
     MSIM_E_WORKSPACE = 5,     /* workspace NULL or smaller than msim_workspace_size() */
-    MSIM_E_UNSUPPORTED = 6,   /* a valid request this build does not implement */
+    MSIM_E_UNSUPPORTED = 6,   /* a valid request the library does not implement */
     MSIM_E_HIP = 7,           /* a HIP runtime call failed */
     MSIM_E_DEVICE = 8         /* a device-side check failed (see msim_device_status) */
 } msim_status;

@@ -251,7 +251,7 @@ msim_status check_params(const msim_params* p)
     if (p->taps < 8 || p->taps > 128 || p->taps % 8 != 0)
         return fail(MSIM_E_INVALID_ARG, "taps must be a multiple of 8 in 8..128 (got %d)", p->taps);
     if (p->taps != 32 && p->taps != 64 && p->taps != 96 && p->taps != 128)
-        return fail(MSIM_E_UNSUPPORTED, "this build is compiled for taps 32, 64, 96, 128 (got %d)", p->taps);
+        return fail(MSIM_E_UNSUPPORTED, "the library is compiled for taps 32, 64, 96, 128 (got %d)", p->taps);
     if (!(p->kaiser_beta >= 0.0) || !(p->cutoff > 0.0 && p->cutoff <= 0.5))
         return fail(MSIM_E_INVALID_ARG, "kaiser_beta >= 0 and cutoff in (0, 0.5] required");
     const int L = p->table_phases;
