@@ -577,8 +577,8 @@ hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order,
 // tracks cover the outputs that can read the tile, and gy over them is staged in
 // LDS.  upart[S.u_base + ((mic n_sgw + sgw) (n_in + T) + P + T/2) 12 + k].
 template <int NT>
-__global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, const WorkItem* __restrict__ items, int n_items,
-                                                  int32_t* __restrict__ ticket, TrackArgs ta, int window,
+__global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_tile, const WorkItem* __restrict__ items,
+                                                  int n_items, int32_t* __restrict__ ticket, TrackArgs ta, int window,
                                                   const float* __restrict__ gy, float* __restrict__ upart,
                                                   int32_t* __restrict__ status)
 {
@@ -594,24 +594,32 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, const WorkI
         const int P = P0 + tid;
         const bool act = P < (int)S.n_in + T / 2;
         const int n_out = (int)S.n_out;
-        const int gb = sg_begin(S.n_wgrp, S.n_sgw, w.sg), ge = sg_begin(S.n_wgrp, S.n_sgw, w.sg + 1);
         int* lsc = (int*)(gw + window);
         float u[kFarrowStride];
 #pragma unroll
         for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
         int bad = 0;
+        // the outputs that can read the tile, and the delay blocks holding them
+        const int blk_len = S.blk_tiles * fwd_tile;
+        const int r_lo = max(0, P0 + S.dlo_all - 4), r_hi = min(n_out, P0 + NT + S.dhi_all + 5);
+        const int b0 = r_lo / blk_len, b1 = r_lo < r_hi ? min(S.n_blk - 1, (r_hi - 1) / blk_len) : -1;
+        for (int b = b0; b <= b1; ++b) {
+        const DBlock B = pv.blocks[S.blk_begin + b];
+        const int bl = b * blk_len, bh = min(n_out, bl + blk_len);
+        const int gb = sg_begin(B.n_grp, S.n_sgw, w.sg), ge = sg_begin(B.n_grp, S.n_sgw, w.sg + 1);
         for (int g = gb; g < ge; ++g) {
-            const DGroup G = pv.groups[S.wgrp_begin + g];
+            const DGroup G = pv.groups[B.grp_begin + g];
             const int nw = P0 + G.dmin - 4;                  // output of gy window slot 0
             const int W = NT + (G.dmax - G.dmin) + 9;
-            const int n_lo = max(0, nw), n_hi = min(n_out, nw + W);
+            // this block's outputs only: every output is gathered in its own block
+            const int n_lo = max(bl, nw), n_hi = min(bh, nw + W);
             if (n_lo >= n_hi) continue;
             tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n_lo, n_hi, group_span(NT, G.dmin, G.dmax),
                             sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
             const float* gys = gy + S.y_off + (int64_t)w.mic * S.n_out;
             for (int p = tid; p < W; p += NT) {
                 const int n = nw + p;
-                gw[p] = (n >= 0 && n < n_out) ? gys[n] : 0.0f;
+                gw[p] = (n >= n_lo && n < n_hi) ? gys[n] : 0.0f;
             }
             __syncthreads();
             if (act) {
@@ -681,6 +689,7 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, const WorkI
                 }
             }
         }
+        }
         if (bad) atomicOr(status, kStatusWindow);
         if (act) {
             const int64_t npos = S.n_in + T;
@@ -694,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, const WorkI
 }
 
 template <int NT>
-static hipError_t launch_farrow_u_t(int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+static hipError_t launch_farrow_u_t(int n_wg, int window, int taps, int fwd_tile, const PlanView& pv, const WorkItem* items,
                                     int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
                                     int32_t* d_status, hipStream_t st)
 {
@@ -702,19 +711,20 @@ static hipError_t launch_farrow_u_t(int n_wg, int window, int taps, const PlanVi
     hipError_t e = hipFuncSetAttribute((const void*)k_farrow_u<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
-    hipLaunchKernelGGL(k_farrow_u<NT>, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, taps, items, n_items, ticket, ta,
-                       window, gy, upart, d_status);
+    hipLaunchKernelGGL(k_farrow_u<NT>, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, taps, fwd_tile, items, n_items,
+                       ticket, ta, window, gy, upart, d_status);
     return hipGetLastError();
 }
 
-hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int fwd_tile, const PlanView& pv,
+                           const WorkItem* items,
                            int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
                            int32_t* d_status, hipStream_t st)
 {
     if (n_items == 0) return hipSuccess;
     if (nthreads == kAdjThreads)
-        return launch_farrow_u_t<kAdjThreads>(n_wg, window, taps, pv, items, n_items, ticket, ta, gy, upart, d_status,
-                                              st);
+        return launch_farrow_u_t<kAdjThreads>(n_wg, window, taps, fwd_tile, pv, items, n_items, ticket, ta, gy, upart,
+                                              d_status, st);
     return hipErrorInvalidValue;
 }
 

@@ -513,16 +513,12 @@ struct msim_plan {
     PermEntry* d_perm = nullptr;
     // whole-path delay groups (the Farrow dL/dx gather over source positions) and
     // their items; supergroup delay bounds per block (table dL/dx windows)
-    std::vector<DGroup> wgroups;
-    std::vector<PermEntry> wperm;
     std::vector<WorkItem> uitems, uitems_plain;
     std::vector<int> uplain_off, uplain_cnt;
     std::vector<int2> sgb;
     int sgb_stride = 1, uwin = 0, rmax = 1;
     int64_t b_rows = 0, max_rows = 0, b_xw = 0, max_xw = 0, b_upart = 0, max_upart = 0;
     int adj_wgs = 0;
-    DGroup* d_wgroups = nullptr;
-    PermEntry* d_wperm = nullptr;
     WorkItem* d_uitems = nullptr;
     WorkItem* d_uitems_plain = nullptr;
     int2* d_sgb = nullptr;
@@ -1018,8 +1014,6 @@ msim_status regroup(msim_plan* P)
     P->groups.clear();
     P->blocks.clear();
     P->perm.clear();
-    P->wgroups.clear();
-    P->wperm.clear();
     P->uwin = 0;
     P->grad_ok.clear();
     int slot_segs = 1, gmax = 1, slot_segs_fwd = 1, gmax_fwd = 1;
@@ -1160,67 +1154,20 @@ msim_status regroup(msim_plan* P)
             d.dlo_all = std::min(d.dlo_all, P->groups[g].dmin);
             d.dhi_all = std::max(d.dhi_all, P->groups[g].dmax);
         }
-        // Farrow form: whole-path groups for the dL/dx gather over source positions
-        // (its items reach outputs across blocks), in the images' whole-path order
-        d.wgrp_begin = (int)P->wgroups.size();
-        d.n_wgrp = 0;
-        if (ugather) {
-            const auto& bnd = P->bounds[s];
-            int G = std::max((I + 255) / 256, (I + kMaxGroup - 1) / kMaxGroup);
-            for (;;) {
-                std::vector<DGroup> gr;
-                int uw = 0;
-                for (int g = 0; g < G; ++g) {
-                    const int ib = (int)((int64_t)I * g / G), ie = (int)((int64_t)I * (g + 1) / G);
-                    if (ib == ie) continue;
-                    double lo = 1e300, hi = -1e300;
-                    for (int i = ib; i < ie; ++i) {
-                        lo = std::min(lo, bnd[i].first);
-                        hi = std::max(hi, bnd[i].second);
-                    }
-                    gr.push_back(DGroup{ib, ie, (int)std::floor(lo) - 4, (int)std::ceil(hi) + 4});
-                    uw = std::max(uw, kAdjThreads + (gr.back().dmax - gr.back().dmin) + 9);
-                }
-                if (farrow_u_lds_bytes(uw) > kLdsLimit && G < I) {
-                    G = std::min(I, 2 * G);
-                    continue;
-                }
-                if (farrow_u_lds_bytes(uw) > kLdsLimit) {
-                    if (farrow) return fail(MSIM_E_UNSUPPORTED, "scene %d: one image's delay span exceeds LDS", s);
-                    ugather = false;   // the table form falls back to its own transpose
-                    break;
-                }
-                P->uwin = std::max(P->uwin, uw);
-                for (DGroup g : gr) {
-                    const int span = group_span(NT, g.dmin, g.dmax);
-                    const int base = (int)P->wperm.size();
-                    int64_t loc = 0;
-                    for (int i = g.img_begin; i < g.img_end; ++i) {
-                        P->wperm.push_back(PermEntry{i, (int32_t)loc});
-                        loc += slot_segs_of(P->images[d.img_begin + i].R, span);
-                    }
-                    if (loc > INT32_MAX / 4)
-                        return fail(MSIM_E_UNSUPPORTED, "scene %d: a delay group's tracks exceed a slot", s);
-                    slot_segs = std::max(slot_segs, (int)loc);
-                    gmax = std::max(gmax, g.img_end - g.img_begin);
-                    g.img_end = base + (g.img_end - g.img_begin);
-                    g.img_begin = base;
-                    P->wgroups.push_back(g);
-                }
-                d.n_wgrp = (int)gr.size();
-                break;
-            }
-        }
+        // the dL/dx gather takes the block groups too: per position tile, the
+        // outputs of each block that can read it; its window is the group's spread
+        // plus the position tile
+        if (ugather)
+            for (int g = P->blocks[d.blk_begin].grp_begin; g < (int)P->groups.size(); ++g)
+                P->uwin = std::max(P->uwin, kAdjThreads + (P->groups[g].dmax - P->groups[g].dmin) + 9);
+    }
+    if (farrow_u_lds_bytes(std::max(1, P->uwin)) > kLdsLimit) {
+        if (farrow) return fail(MSIM_E_UNSUPPORTED, "a delay group's gather window exceeds LDS");
+        ugather = false;   // the table form falls back to its own transpose
     }
     if (P->ugather && !ugather) {
         P->ugather = false;
-        P->wgroups.clear();
-        P->wperm.clear();
         P->uwin = 0;
-        for (DScene& d : P->scenes) {
-            d.wgrp_begin = 0;
-            d.n_wgrp = 0;
-        }
     }
     P->slot_segs = std::max(slot_segs, slot_segs_fwd);
     P->gmax = std::max(gmax, gmax_fwd);
@@ -1336,12 +1283,14 @@ msim_status regroup(msim_plan* P)
         d.xw_stride = b.xw_stride = xs;
         const int64_t nr = (int64_t)d.n_mics * d.n_sg * d.n_tiles;
         const int64_t nx = P->ugather ? 0 : nr * xs;
-        // Farrow dL/dx gather: supergroups of whole-path groups, items per position tile
+        // dL/dx gather: items per (mic, position tile, share of each block's groups)
         d.n_ptiles = b.n_ptiles = (int)((d.n_in + T + kAdjThreads - 1) / kAdjThreads);
         int nsgw = 0;
         if (P->ugather) {
+            int gmax_blk = 1;
+            for (int k = 0; k < d.n_blk; ++k) gmax_blk = std::max(gmax_blk, P->blocks[d.blk_begin + k].n_grp);
             const int64_t tm = std::max<int64_t>(1, (int64_t)d.n_ptiles * d.n_mics);
-            nsgw = (int)std::min<int64_t>(d.n_wgrp, std::max<int64_t>(1, (want + tm - 1) / tm));
+            nsgw = (int)std::min<int64_t>(gmax_blk, std::max<int64_t>(1, (want + tm - 1) / tm));
             const int64_t per = (int64_t)d.n_mics * (d.n_in + T) * kFarrowStride;
             nsgw = (int)std::max<int64_t>(1, std::min<int64_t>(nsgw, budget / std::max<int64_t>(1, per * P->n_scenes)));
         }
@@ -1361,17 +1310,9 @@ msim_status regroup(msim_plan* P)
         P->max_upart = std::max(P->max_upart, nu);
         if (P->ugather) {
             std::vector<std::pair<double, WorkItem>> its;
-            for (int sg = 0; sg < nsgw; ++sg) {
-                const int gb = sg_begin(d.n_wgrp, nsgw, sg), ge = sg_begin(d.n_wgrp, nsgw, sg + 1);
-                double cost = 0.0;
-                for (int g = gb; g < ge; ++g) {
-                    const DGroup& G = P->wgroups[d.wgrp_begin + g];
-                    cost += (double)(G.img_end - G.img_begin) * kAdjThreads + 4.0 * (kAdjThreads + G.dmax - G.dmin);
-                }
+            for (int sg = 0; sg < nsgw; ++sg)
                 for (int m = 0; m < d.n_mics; ++m)
-                    for (int t = 0; t < d.n_ptiles; ++t) its.push_back({cost, WorkItem{s, m, t, sg}});
-            }
-            std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+                    for (int t = 0; t < d.n_ptiles; ++t) its.push_back({(double)d.n_img, WorkItem{s, m, t, sg}});
             P->uplain_off[s] = (int)P->uitems_plain.size();
             P->uplain_cnt[s] = (int)its.size();
             for (const auto& e : its) P->uitems_plain.push_back(e.second);
@@ -1379,8 +1320,6 @@ msim_status regroup(msim_plan* P)
         }
         b.dlo_all = d.dlo_all;
         b.dhi_all = d.dhi_all;
-        b.wgrp_begin = d.wgrp_begin;
-        b.n_wgrp = d.n_wgrp;
     }
     std::stable_sort(uit.begin(), uit.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
     for (const auto& e : uit) P->uitems.push_back(e.second);
@@ -1418,15 +1357,11 @@ void free_layout(msim_plan* P)
     (void)hipFree(P->d_items_plain);
     (void)hipFree(P->d_blocks);
     (void)hipFree(P->d_perm);
-    (void)hipFree(P->d_wgroups);
-    (void)hipFree(P->d_wperm);
     (void)hipFree(P->d_uitems);
     (void)hipFree(P->d_uitems_plain);
     (void)hipFree(P->d_sgb);
     P->d_blocks = nullptr;
     P->d_perm = nullptr;
-    P->d_wgroups = nullptr;
-    P->d_wperm = nullptr;
     P->d_uitems = P->d_uitems_plain = nullptr;
     P->d_sgb = nullptr;
     P->d_scenes = nullptr;
@@ -1447,7 +1382,6 @@ msim_status upload_layout(msim_plan* P)
         (st = upload(&P->d_y_prefix, P->y_prefix)) != MSIM_OK || (st = upload(&P->d_items, P->items)) != MSIM_OK ||
         (st = upload(&P->d_items_plain, P->items_plain)) != MSIM_OK ||
         (st = upload(&P->d_blocks, P->blocks)) != MSIM_OK || (st = upload(&P->d_perm, P->perm)) != MSIM_OK ||
-        (st = upload(&P->d_wgroups, P->wgroups)) != MSIM_OK || (st = upload(&P->d_wperm, P->wperm)) != MSIM_OK ||
         (st = upload(&P->d_uitems, P->uitems)) != MSIM_OK ||
         (st = upload(&P->d_uitems_plain, P->uitems_plain)) != MSIM_OK || (st = upload(&P->d_sgb, P->sgb)) != MSIM_OK)
         return st;
@@ -1650,12 +1584,10 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
         if (gx) {
             LaunchTimer t(P, kKindAdjX, st);
             if (P->ugather) {
-                PlanView wv = pv;
-                wv.groups = P->d_wgroups;
-                wv.perm = P->d_wperm;
+                const PlanView& wv = pv;
                 const WorkItem* it = batched ? P->d_uitems : P->d_uitems_plain + P->uplain_off[k];
                 const int n = batched ? (int)P->uitems.size() : P->uplain_cnt[k];
-                HIP_OK(launch_farrow_u(kAdjThreads, std::min(n, P->adj_wgs), P->uwin, T, wv, it, n, w.ticket, ta, gy,
+                HIP_OK(launch_farrow_u(kAdjThreads, std::min(n, P->adj_wgs), P->uwin, T, NT, wv, it, n, w.ticket, ta, gy,
                                        w.upart, P->d_status, st));
                 const int64_t vtot = batched ? P->vpos_total : P->scenes[k].n_in + T;
                 HIP_OK(launch_farrow_u_reduce(one, nsc, batched ? P->d_vpos_prefix : P->d_zero, vtot, T, w.upart,

@@ -56,9 +56,7 @@ struct DScene {
     int32_t sgb_stride;   // supergroup bounds per delay block (the plan's stride)
     int32_t dlo_all;      // delay bounds of every group of every block (samples)
     int32_t dhi_all;
-    int32_t wgrp_begin;   // whole-path delay groups (the Farrow dL/dx gather), and
-    int32_t n_wgrp;       //   their supergroups
-    int32_t n_sgw;
+    int32_t n_sgw;        // shares of each block's groups in the dL/dx gather's items
     int32_t n_ptiles;     // source-position tiles of the Farrow dL/dx gather
 };
 
@@ -273,7 +271,7 @@ hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order,
                             const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st);
 // The dL/dx gather runs over whole-path delay groups: pv.groups / pv.perm are
 // those groups and their permutation.
-hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, const PlanView& pv, const WorkItem* items,
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int fwd_tile, const PlanView& pv, const WorkItem* items,
                            int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
                            int32_t* d_status, hipStream_t st);
 hipError_t launch_farrow_u_reduce(const PlanView& pv, int n_scenes, const int64_t* d_vprefix, int64_t vtotal, int taps,
