@@ -95,7 +95,9 @@ typedef struct {
     double kaiser_beta;         /* Kaiser window shape */
     double cutoff;              /* normalised cutoff in (0, 0.5] cycles/sample */
     int32_t table_phases;       /* L: phases per unit delay of the FD table, interpolated
-                                   quadratically (power of two, 16..1024; 128 by default) */
+                                   quadratically (power of two, 16..1024), or 0 (the
+                                   default): the planner takes 128, or 64 where that lets
+                                   two outputs share a lane within the error budget */
     int32_t n_tiers;            /* 0: every image at the audio rate; 1..4 tiers below */
     int32_t tier_max_order[4];  /* tier k holds orders <= tier_max_order[k] not in an earlier tier */
     int32_t tier_decim[4];      /* decimation of tier k's delay grid (1 = audio rate), 1..4096 */
@@ -247,6 +249,8 @@ typedef struct {
     double pair;
     double farrow;
     double budget;
+    int32_t table_phases;   /* the table's phase count (the planner's choice when
+                               table_phases was 0) */
 } msim_fd_error;
 
 msim_status msim_get_fd_error(const msim_plan* plan, msim_fd_error* out);

@@ -58,7 +58,8 @@ class Tuning(C.Structure):
 
 
 class FdError(C.Structure):
-    _fields_ = [("table", C.c_double), ("pair", C.c_double), ("farrow", C.c_double), ("budget", C.c_double)]
+    _fields_ = [("table", C.c_double), ("pair", C.c_double), ("farrow", C.c_double), ("budget", C.c_double),
+                ("table_phases", C.c_int32)]
 
 
 # name -> (argtypes); every function returns msim_status (int) except msim_last_error

@@ -620,7 +620,9 @@ static hipError_t launch_adjp_t(int n_wg, int window, const PlanView& pv, const 
 {
     constexpr int NT = RB == 1 ? kAdjThreads : TO / 2;
     const size_t lds = adj_track_lds_bytes(T, Lq, window);
-    auto kern = Lq == 128 ? k_adjp<T, TO, 128, RB> : k_adjp<T, TO, 0, RB>;
+    auto kern = Lq == kTablePhases ? k_adjp<T, TO, kTablePhases, RB> : k_adjp<T, TO, 0, RB>;
+    if constexpr (RB == 2)
+        if (Lq == kPairTablePhases) kern = k_adjp<T, TO, kPairTablePhases, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);

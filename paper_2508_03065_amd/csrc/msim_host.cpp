@@ -255,8 +255,8 @@ msim_status check_params(const msim_params* p)
     if (!(p->kaiser_beta >= 0.0) || !(p->cutoff > 0.0 && p->cutoff <= 0.5))
         return fail(MSIM_E_INVALID_ARG, "kaiser_beta >= 0 and cutoff in (0, 0.5] required");
     const int L = p->table_phases;
-    if (L < 16 || L > 1024 || (L & (L - 1)) != 0)
-        return fail(MSIM_E_INVALID_ARG, "table_phases must be a power of two in 16..1024");
+    if (L != 0 && (L < 16 || L > 1024 || (L & (L - 1)) != 0))
+        return fail(MSIM_E_INVALID_ARG, "table_phases must be 0 (chosen by the planner) or a power of two in 16..1024");
     if (p->n_tiers < 0 || p->n_tiers > 4) return fail(MSIM_E_INVALID_ARG, "n_tiers must be 0..4");
     for (int k = 0; k < p->n_tiers; ++k) {
         if (p->tier_decim[k] < 1 || p->tier_decim[k] > 4096)
@@ -1640,7 +1640,7 @@ msim_status msim_default_params(msim_params* p)
     p->taps = 64;
     p->kaiser_beta = 8.0;
     p->cutoff = 0.5;
-    p->table_phases = 128;
+    p->table_phases = 0;
     p->n_tiers = 3;
     p->tier_max_order[0] = 2;
     p->tier_decim[0] = 1;
@@ -1707,9 +1707,21 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         double v = 0.0;
         for (int s = 0; s < n_scenes; ++s)
             v = std::max(v, traj_max_speed(scenes[s].src) + traj_max_speed(scenes[s].rcv));
-        const double drift = 1.5 * v / (p->c - v) * p->table_phases;
-        P->rb_max = drift <= 1.25 ? std::min(P->rb_max, 2) : 1;
+        auto pair_fits = [&](int L) { return 1.5 * v / (p->c - v) * L <= 1.25; };
         P->err_pair = pair_error(*p, v);
+        if (p->table_phases == 0) {
+            // Phases chosen by the planner: 128 (compiled in) where the pair fits
+            // there; else 64 where the pair fits at 64 and the coarser table plus the
+            // pair's edge tap stay within the error budget (the pair halves the
+            // table and source reads per tap); else 128 at one output per lane.
+            P->par.table_phases = kTablePhases;
+            if (P->rb_max >= 2 && !pair_fits(kTablePhases) && pair_fits(kPairTablePhases)) {
+                P->par.table_phases = kPairTablePhases;
+                build_table(P);
+                if (std::hypot(table_error(P), P->err_pair) > kFdErrBudget) P->par.table_phases = kTablePhases;
+            }
+        }
+        P->rb_max = pair_fits(P->par.table_phases) ? std::min(P->rb_max, 2) : 1;
     }
     build_table(P);
     build_farrow(P);
@@ -1728,11 +1740,12 @@ msim_status msim_plan_create(const msim_scene* scenes, int32_t n_scenes, const m
         P->err_farrow = farrow_error(P);   // its dL/dx goes through the Farrow gather
         if (P->err_table > kFdErrBudget) {
             const double e = P->err_table;
+            const int L = P->par.table_phases;
             delete P;
             return fail(MSIM_E_UNSUPPORTED,
                         "table form: predicted relative error %.2e of the %d-phase table exceeds %.0e at "
                         "kaiser_beta %g, cutoff %g, taps %d (raise table_phases or use the Farrow form)",
-                        e, p->table_phases, kFdErrBudget, p->kaiser_beta, p->cutoff, p->taps);
+                        e, L, kFdErrBudget, p->kaiser_beta, p->cutoff, p->taps);
         }
         // the pair's omitted edge tap on top of the table's error
         if (std::hypot(P->err_table, P->err_pair) > kFdErrBudget) P->rb_max = 1;
@@ -2230,6 +2243,7 @@ msim_status msim_get_fd_error(const msim_plan* P, msim_fd_error* out)
     out->pair = P->err_pair;
     out->farrow = P->err_farrow;
     out->budget = kFdErrBudget;
+    out->table_phases = P->par.table_phases;
     return MSIM_OK;
 }
 

@@ -230,6 +230,11 @@ hipError_t launch_reduce_sg(const DScene* d_scenes, int n_scenes, const int64_t*
 // term, at most 1.5e-7 of the kernel's energy for fractions in [0, 1], is below the
 // FP32 rounding of the tap sum, and the table stores them as zero.
 __host__ __device__ constexpr int qcorr_quads(int taps) { return taps / 8 - taps / 32; }
+// Phase counts of the quadratic FD table compiled into the kernels (immediate
+// table offsets; other counts read it at run time): the default, and the coarser
+// one the planner may take so that two outputs per lane fit a faster path.
+constexpr int kTablePhases = 128;
+constexpr int kPairTablePhases = 64;
 // Rows per tap quad of the quadratic FD table: rows -1 .. Lq-1.
 __host__ __device__ constexpr int qtab_pitch(int Lq) { return Lq + 1; }
 // Bytes of the quadratic FD table ([Y | D1 | D2], 40 B per quad row).

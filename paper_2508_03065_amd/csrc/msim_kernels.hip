@@ -298,10 +298,6 @@ __global__ __launch_bounds__(NT, 4) void k_synth(PlanView pv, const float4* __re
     });
 }
 
-// The default phase count of the quadratic table is compiled in (immediate table
-// offsets); others run the same kernel with the phase count read at run time.
-constexpr int kPhasesCompiled = 128;
-
 template <int T, int TO, int RB>
 static hipError_t launch_synth_t(int n_wg, int window, const PlanView& pv, const float4* d_table, int L,
                                  const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta,
@@ -309,7 +305,9 @@ static hipError_t launch_synth_t(int n_wg, int window, const PlanView& pv, const
 {
     constexpr int NT = TO / RB;
     const size_t lds = synth_lds_bytes(T, L, window);
-    auto kern = L == kPhasesCompiled ? k_synth<T, NT, kPhasesCompiled, RB> : k_synth<T, NT, 0, RB>;
+    auto kern = L == kTablePhases ? k_synth<T, NT, kTablePhases, RB> : k_synth<T, NT, 0, RB>;
+    if constexpr (RB == 2)
+        if (L == kPairTablePhases) kern = k_synth<T, NT, kPairTablePhases, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);

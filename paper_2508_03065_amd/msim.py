@@ -48,7 +48,7 @@ def _scene(sc, keep) -> _lib.Scene:
     return s
 
 
-def params_struct(par, table_phases: int = 128) -> _lib.Params:
+def params_struct(par, table_phases: int = 0) -> _lib.Params:
     p = _lib.Params()
     p.c = float(par.c)
     p.fs = float(par.fs)
@@ -97,7 +97,7 @@ def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
 class Plan:
     """A validated, uploaded synthesis plan for a list of scenes."""
 
-    def __init__(self, scenes: Sequence, par, table_phases: int = 128):
+    def __init__(self, scenes: Sequence, par, table_phases: int = 0):
         L = _lib.load()
         self._keep: list = []
         arr = (_lib.Scene * len(scenes))()

@@ -86,3 +86,49 @@ def test_refused_table_is_refused_on_gpu(torch_cuda):
     y = plan.forward(x)
     torch_cuda.cuda.synchronize()
     assert rel_l2(plan.unpack_y(y)[0].cpu().numpy(), O.forward(sc, par)) <= TOL
+
+
+def _vmax(tr):
+    if tr.p.shape[0] < 2:
+        return 0.0
+    return float(np.max(np.linalg.norm(np.diff(tr.p, axis=0), axis=1) / np.diff(tr.t)))
+
+
+# (seed, moving receiver, expected phases, expected outputs per lane): a slow scene
+# keeps 128 phases with pairs; source and receiver moving together (2.7-3.4 m/s)
+# drift too far per sample for a pair at 128 phases, and the planner halves the
+# table; with kaiser_beta 4 the coarser table misses the budget, and it stays at
+# 128 with one output per lane
+PLANNER_CASES = [(50, True, 8.0, 128, 2), (40, True, 8.0, 64, 2), (42, True, 8.0, 64, 2),
+                 (42, True, 4.0, 128, 1), (43, False, 8.0, 128, 2)]
+
+
+@pytest.mark.parametrize("case", PLANNER_CASES, ids=lambda c: "seed%d_beta%g" % (c[0], c[2]))
+def test_planner_table_phases(torch_cuda, case):
+    """table_phases 0: the planner's choice follows the pair's drift limit (1.25
+    table rows per sample at 1.5 v / (c - v) rows per unit phase count) and the
+    error budget, and the forward at the chosen table matches the oracle."""
+    from paper_2508_03065_amd.msim import Plan
+    seed, mrcv, beta, L_exp, rb_exp = case
+    sc, par = G.small_scene(seed=seed, max_order=3, seconds=0.1, taps=64, moving_rcv=mrcv, n_mics=2)
+    par = dataclasses.replace(par, kaiser_beta=beta)
+    v = _vmax(sc.src) + _vmax(sc.rcv)
+    fits = {L: 1.5 * v / (par.c - v) * L <= 1.25 for L in (128, 64)}
+    print("planner", case, "v %.3f" % v, fits, flush=True)
+    assert fits[128] == (L_exp == 128 and rb_exp == 2) or beta != 8.0
+    plan = Plan([sc], par)
+    err = plan.fd_error()
+    assert err["table_phases"] == L_exp
+    assert plan.tuning()["outputs_per_lane"] == rb_exp
+    if rb_exp == 2:
+        assert math.hypot(err["table"], err["pair"]) <= err["budget"]
+    x = plan.pack_x([sc.x])
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    assert plan.device_status() == 0
+    ref = O.forward(sc, par)
+    e = rel_l2(plan.unpack_y(y)[0].cpu().numpy(), ref)
+    print("  L %d rb %d measured %.2e (%s)" % (L_exp, rb_exp, e, err), flush=True)
+    assert e <= TOL
+    # an explicit phase count is kept as given
+    assert Plan([sc], par, table_phases=128).fd_error()["table_phases"] == 128

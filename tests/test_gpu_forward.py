@@ -172,14 +172,16 @@ def test_outputs_per_lane(torch_cuda, case, rb):
 
 
 def test_fast_scene_keeps_one_output_per_lane(torch_cuda):
-    # source 3 m/s plus receiver 1 m/s: the delay drifts too fast for shared
-    # table rows, so the plan keeps one output per lane and refuses two
+    # source 3 m/s plus receiver 1 m/s: at 128 table phases the delay drifts too
+    # fast for shared table rows, so that plan keeps one output per lane and
+    # refuses two; the planner's own choice halves the table and pairs
     from paper_2508_03065_amd._lib import MsimError
     from paper_2508_03065_amd.msim import Plan
     sc, par = G.small_scene(seed=25, max_order=3, seconds=0.2, taps=64)
     sc.src = G.Traj.pwl(np.array([0.0, 0.2]), np.array([[1.0, 1.0, 1.5], [1.6, 1.0, 1.5]]))
     sc.rcv = G.Traj.pwl(np.array([0.0, 0.2]), np.array([[3.5, 2.5, 1.2], [3.5, 2.7, 1.2]]))
-    plan = Plan([sc], par)
+    ref = O.forward(sc, par)
+    plan = Plan([sc], par, table_phases=128)
     assert plan.tuning()["outputs_per_lane"] == 1
     with pytest.raises(MsimError):
         plan.set_tuning(1024, 0, 2)
@@ -187,7 +189,13 @@ def test_fast_scene_keeps_one_output_per_lane(torch_cuda):
     y = plan.forward(x)
     torch_cuda.cuda.synchronize()
     (yv,) = plan.unpack_y(y)
-    assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
+    assert rel_l2(yv.cpu().numpy(), ref) <= TOL
+    plan = Plan([sc], par)
+    assert plan.fd_error()["table_phases"] == 64 and plan.tuning()["outputs_per_lane"] == 2
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    (yv,) = plan.unpack_y(y)
+    assert rel_l2(yv.cpu().numpy(), ref) <= TOL
 
 
 def test_pair_at_the_speed_limit(torch_cuda):
@@ -203,6 +211,27 @@ def test_pair_at_the_speed_limit(torch_cuda):
     p = np.array([[2.9, 2.0, 1.4], [2.9 + 0.315, 2.0, 1.4], [2.9, 2.0, 1.4]])
     sc.src = G.Traj.pwl(t, p)
     plan = Plan([sc], par)
+    assert plan.tuning()["outputs_per_lane"] == 2
+    x = plan.pack_x([sc.x])
+    y = plan.forward(x)
+    torch_cuda.cuda.synchronize()
+    assert plan.device_status() == 0
+    (yv,) = plan.unpack_y(y)
+    assert rel_l2(yv.cpu().numpy(), O.forward(sc, par)) <= TOL
+
+
+def test_pair_at_the_speed_limit_of_the_coarse_table(torch_cuda):
+    # the same back-and-forth path at 4.3 m/s, near the pair's limit for the
+    # 64-phase table the planner takes above 2.2 m/s (1.23 table rows per sample
+    # with the cubic-slope allowance)
+    from paper_2508_03065_amd.msim import Plan
+    sc, par = G.small_scene(seed=26, max_order=4, seconds=0.3, taps=64)
+    sc.rcv = G.Traj.static(np.array([2.5, 2.0, 1.4]))
+    t = np.array([0.0, 0.15, 0.3])
+    p = np.array([[2.9, 2.0, 1.4], [2.9 + 0.645, 2.0, 1.4], [2.9, 2.0, 1.4]])
+    sc.src = G.Traj.pwl(t, p)
+    plan = Plan([sc], par)
+    assert plan.fd_error()["table_phases"] == 64
     assert plan.tuning()["outputs_per_lane"] == 2
     x = plan.pack_x([sc.x])
     y = plan.forward(x)

@@ -58,7 +58,7 @@ def test_count_images_closed_form(lib):
 def test_default_params(lib):
     p = _lib.Params()
     assert lib.msim_default_params(C.byref(p)) == 0
-    assert p.taps == 64 and p.table_phases == 128 and p.n_tiers == 3
+    assert p.taps == 64 and p.table_phases == 0 and p.n_tiers == 3
     assert list(p.tier_decim)[:3] == [1, 16, 160] and list(p.tier_max_order)[:2] == [2, 6]
 
 
