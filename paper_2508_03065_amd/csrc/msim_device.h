@@ -521,6 +521,14 @@ __device__ inline Slot slot_at(char* slots, int64_t slot_bytes, int slot_segs, i
     return s;
 }
 
+// p[i] through a 32-bit byte offset from a base that is the same for the whole
+// block (the load then takes the scalar-base, vector-offset form).
+template <class T>
+__device__ __forceinline__ T ld_at(const T* p, uint32_t i)
+{
+    return *(const T*)((const char*)p + i * (uint32_t)sizeof(T));
+}
+
 // k / R for k >= 0 from a float estimate, corrected once (the estimate is within
 // one of the quotient for k < 2^24).
 __device__ __forceinline__ int div_exact(int k, int R, float invR)

@@ -418,7 +418,13 @@ size_t farrow_gd_lds_bytes(int window)
     return (size_t)window * kFarrowStride * sizeof(float) + kLscBytes + kParamLdsBytes;
 }
 
-size_t farrow_u_lds_bytes(int window) { return (size_t)window * sizeof(float) + kLscBytes; }
+// LDS of the dL/dx gather: the gy window, the track offsets, then the image
+// descriptors of a chunk (two int4 each).
+constexpr int kUDescChunk = 256;
+size_t farrow_u_lds_bytes(int window)
+{
+    return (size_t)window * sizeof(float) + kLscBytes + (size_t)kUDescChunk * 2 * sizeof(int4);
+}
 
 // Gain and delay adjoints of one delay group, Farrow form, one output per lane of
 // the tile [n0, n0 + NT): per image sample r = sum_k v_k s^k and dr/ds by Horner's
@@ -566,23 +572,27 @@ hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order,
 }
 
 // dL/dx gather, Farrow form, persistent over items (scene, mic, position tile,
-// supergroup of whole-path delay groups).  One lane per source position P of the
-// tile [P0, P0 + NT) of the positions [-T/2, n_in + T/2).  n - floor(D_i(n)) is
-// nondecreasing in n for a subsonic image (the integer delay moves by at most one
-// per sample), so the outputs that read P form a run of at most two samples
-// (none where the integer delay steps down).  The lane reaches it by the
-// fixed-point iteration n <- P + floor(D_i(n)), a contraction with factor
-// |dD/dn| < 1 up to the floor, then tests n-1 .. n+1 and accumulates
-// u_k += gy g s^k in registers over every group of the supergroup.  Per group the
-// tracks cover the outputs that can read the tile, and gy over them is staged in
-// LDS.  upart[S.u_base + ((mic n_sgw + sgw) (n_in + T) + P + T/2) 12 + k].
-template <int NT>
+// supergroup of each delay block's groups).  One lane per source position P of
+// the tile [P0, P0 + NT) of the positions [-T/2, n_in + T/2).  The outputs of
+// image i that read P are the n with n - floor(D_i(n)) = P; n - D_i(n) increases
+// for a subsonic image, so they form a band of at most two consecutive samples
+// (none where the integer delay steps down).  Per image the lane takes one
+// Newton step on n - D_i(n) = P - 1/2 from the previous image's integer delay
+// (the images are sorted by delay), evaluates the rounded solution and its two
+// neighbours on the (at most two) track segments they lie on, and moves one
+// sample at a time in the rare case the band is not inside them.  It
+// accumulates u_k += gy g s^k in registers over every group of the supergroup.
+// Per group the tracks cover the outputs of the block that can read the tile,
+// and gy over them is staged in LDS.
+// upart[S.u_base + ((mic n_sgw + sgw) (n_in + T) + P + T/2) 12 + k].
+template <int NT, bool HI>
 __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_tile, const WorkItem* __restrict__ items,
                                                   int n_items, int32_t* __restrict__ ticket, TrackArgs ta, int window,
                                                   const float* __restrict__ gy, float* __restrict__ upart,
                                                   int32_t* __restrict__ status)
 {
     extern __shared__ float4 lds[];
+    constexpr int NU = HI ? kFarrowStride : 10;       // polynomial orders summed
     float* gw = (float*)lds;
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     for_each_item(ticket, n_items, [&](int it) {
@@ -595,6 +605,7 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_til
         const bool act = P < (int)S.n_in + T / 2;
         const int n_out = (int)S.n_out;
         int* lsc = (int*)(gw + window);
+        int4* dsc = (int4*)((char*)lsc + kLscBytes);
         float u[kFarrowStride];
 #pragma unroll
         for (int k = 0; k < kFarrowStride; ++k) u[k] = 0.0f;
@@ -621,70 +632,117 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_til
                 const int n = nw + p;
                 gw[p] = (n >= n_lo && n < n_hi) ? gys[n] : 0.0f;
             }
-            __syncthreads();
-            if (act) {
-                // the images are sorted by delay: each fixed-point iteration starts
-                // from the integer delay the previous image ended with
-                int Kguess = (G.dmin + G.dmax) / 2;
-                for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-                    const DImage im = perm_image(I, pv.perm, ii);
-                    const int klo = n_lo / im.R;
-                    // delay at output c (n_lo <= c < n_hi), re-reading the track
-                    // segment only when c leaves it
-                    int kc = -1, Kseg = 0;
-                    Seg sg{};
-                    auto eval = [&](int c, int* K, float* off, float* D) {
-                        const int k = div_exact(c, im.R, im.invR);
-                        if (k != kc) {
-                            kc = k;
-                            sg = sl.seg[im.loc + k - klo];
-                            Kseg = sl.K[im.loc + k - klo];
-                        }
-                        const float vv = (float)(c - k * im.R);
-                        const float d = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
-                        const float fl = floorf(d);
-                        *K = Kseg + (int)fl;
-                        *off = d - fl;
-                        *D = (float)Kseg + d;
-                    };
-                    auto add = [&](int c, float off, float D) {
-                        const int p = c - nw;
-                        if (p < 0 || p >= W) {
-                            bad = 1;
-                            return;
-                        }
-                        const float s = 2.0f * off - 1.0f;
-                        float wv = gw[p] * im.gfac * __builtin_amdgcn_rcpf(D);
+            // the images are sorted by delay: each search starts from the integer
+            // delay the previous image ended with
+            int Kguess = (G.dmin + G.dmax) / 2;
+            for (int c0 = G.img_begin; c0 < G.img_end; c0 += kUDescChunk) {
+                const int nc = min(kUDescChunk, G.img_end - c0);
+                if (c0 > G.img_begin) __syncthreads();      // the previous chunk's descriptors read
+                // per image: first segment's slot index minus k_lo, R, gain factor,
+                // 1/R; then k_lo, k_hi - k_lo
+                for (int i = tid; i < nc; i += NT) {
+                    const PermEntry e = pv.perm[c0 + i];
+                    const DImage& im = I[e.img];
+                    const int klo = n_lo / im.R, khi = (n_hi - 1) / im.R;
+                    dsc[2 * i] = make_int4(e.loc - klo, im.R, __float_as_int(im.gfac), __float_as_int(im.invR));
+                    dsc[2 * i + 1] = make_int4(klo, khi, 0, 0);
+                }
+                __syncthreads();
+                if (!act) continue;
+                // image j's descriptor, read from LDS as wave-uniform values
+                struct Desc {
+                    int base, R, klo, khi;
+                    float gfac, invR;
+                };
+                auto desc = [&](int j) {
+                    const int4 d0 = dsc[2 * j], d1 = dsc[2 * j + 1];
+                    Desc d;
+                    d.base = __builtin_amdgcn_readfirstlane(d0.x);
+                    d.R = __builtin_amdgcn_readfirstlane(d0.y);
+                    d.gfac = __int_as_float(d0.z);
+                    d.invR = __int_as_float(d0.w);
+                    d.klo = __builtin_amdgcn_readfirstlane(d1.x);
+                    d.khi = __builtin_amdgcn_readfirstlane(d1.y);
+                    return d;
+                };
+                // segment k of an image (klo <= k <= khi): slot entry base + k
+                auto seg = [&](const Desc& d, int k) { return ld_at(sl.seg, (uint32_t)(d.base + k)); };
+                auto kint = [&](const Desc& d, int k) { return ld_at(sl.K, (uint32_t)(d.base + k)); };
+                // integer delay, offset and delay of output c on its segment k
+                auto at = [&](const Desc& d, const Seg& sg, int Kb, int k, int c, int& K, float& off, float& D) {
+                    const float vv = (float)(c - k * d.R);
+                    const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+                    const float fl = floorf(dl);
+                    K = Kb + (int)fl;
+                    off = dl - fl;
+                    D = (float)Kb + dl;
+                };
+                auto clampn = [&](int n) { return min(max(n, n_lo), n_hi - 1); };
+                for (int j = 0; j < nc; ++j) {
+                    const Desc d = desc(j);
+                    // u_k += gy g s^k for output c (n_lo <= c < n_hi: inside the gy window)
+                    auto add = [&](int c, float off, float D, bool hit = true) {
+                        const float sv = 2.0f * off - 1.0f;
+                        float wv = hit ? gw[c - nw] * d.gfac * __builtin_amdgcn_rcpf(D) : 0.0f;
 #pragma unroll
-                        for (int k = 0; k < kFarrowStride; ++k) {
+                        for (int k = 0; k < NU; ++k) {
                             u[k] += wv;
-                            wv *= s;
+                            wv *= sv;
                         }
                     };
-                    int K;
-                    float off, D;
-                    int n = min(max(P + Kguess, n_lo), n_hi - 1);
-                    eval(n, &K, &off, &D);
-                    for (int itr = 0; itr < 16; ++itr) {
-                        const int nn = min(max(P + K, n_lo), n_hi - 1);
-                        if (nn == n) break;
-                        n = nn;
-                        eval(n, &K, &off, &D);
+                    // The outputs reading P are the integers n with n - D(n) in
+                    // (P - 1, P]: a band of width 1 / (1 - dD/dn) around the solution
+                    // x of x - D(x) = P - 1/2.  One Newton step from the guess n0
+                    // (the previous image's integer delay) puts n1 = round(x)
+                    // within a fraction of a sample of it for a smooth track, so
+                    // the band lies in n1 - 1 .. n1 + 1 (it holds at most two
+                    // outputs below |dD/dn| = 1/2).
+                    const int n0 = clampn(P + Kguess);
+                    int n1;
+                    {
+                        const int k0 = div_exact(n0, d.R, d.invR);
+                        const Seg sg = seg(d, k0);
+                        const int Kb = kint(d, k0);
+                        const float vv = (float)(n0 - k0 * d.R);
+                        const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
+                        const float dd = fmaf(vv, fmaf(vv, 3.0f * sg.b3, 2.0f * sg.b2), sg.b1);
+                        const float e = (float)(n0 - Kb - P) - dl + 0.5f;   // x - D(x) - (P - 1/2) at n0
+                        n1 = clampn(n0 + (int)floorf(0.5f - e * __builtin_amdgcn_rcpf(1.0f - dd)));
                     }
-                    Kguess = K;
-                    // n - K(n) is nondecreasing with steps of 0, 1 or 2, so the
-                    // outputs reading P are n itself (when it solves the equation)
-                    // and its neighbours
-                    const bool hit = (n - K == P);
-                    const float off_n = off, D_n = D;
-                    if (n > n_lo) {
-                        eval(n - 1, &K, &off, &D);
-                        if (n - 1 - K == P) add(n - 1, off, D);
-                    }
-                    if (hit) add(n, off_n, D_n);
-                    if (n + 1 < n_hi) {
-                        eval(n + 1, &K, &off, &D);
-                        if (n + 1 - K == P) add(n + 1, off, D);
+                    // n1 - 1 .. n1 + 1 on two segments (three when R = 1); outside
+                    // [n_lo, n_hi) a candidate reads nothing (position -inf / +inf)
+                    for (int itr = 0;; ++itr) {
+                        const int q = div_exact(n1, d.R, d.invR), r = n1 - q * d.R;
+                        const int ka = max(r == 0 ? q - 1 : q, d.klo), kb = min(r == d.R - 1 ? q + 1 : q, d.khi);
+                        const Seg sa = seg(d, ka), sb = seg(d, kb);
+                        const int Ka = kint(d, ka), Kb = kint(d, kb);
+                        Seg sm = r == 0 ? sb : sa;
+                        int Km = r == 0 ? Kb : Ka;
+                        if (d.R == 1) {
+                            sm = seg(d, q);
+                            Km = kint(d, q);
+                        }
+                        int Kc, Km1, Kp1;
+                        float offc, Dc, offm, Dm, offp, Dp;
+                        at(d, sm, Km, q, n1, Kc, offc, Dc);
+                        at(d, sa, Ka, ka, n1 - 1, Km1, offm, Dm);
+                        at(d, sb, Kb, kb, n1 + 1, Kp1, offp, Dp);
+                        const int pc = n1 - Kc;
+                        const int pm = n1 > n_lo ? n1 - 1 - Km1 : INT_MIN;
+                        const int pp = n1 + 1 < n_hi ? n1 + 1 - Kp1 : INT_MAX;
+                        // the band is inside the candidates when n1 is in it (it then
+                        // holds n1 and at most one neighbour), or when it falls
+                        // strictly between n1 - 1 and n1 + 1 without n1 (empty)
+                        const bool inside = pc == P || (pm < P && pp > P);
+                        if (inside || itr == 8) {
+                            bad |= !inside;
+                            Kguess = Kc;
+                            add(n1, offc, Dc, pc == P);
+                            const bool hm = pm == P, hp = pp == P;
+                            if (hm || hp) add(hm ? n1 - 1 : n1 + 1, hm ? offm : offp, hm ? Dm : Dp);
+                            break;
+                        }
+                        n1 = clampn(pc < P ? n1 + 1 : n1 - 1);
                     }
                 }
             }
@@ -702,30 +760,32 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_til
     });
 }
 
-template <int NT>
+template <int NT, bool HI>
 static hipError_t launch_farrow_u_t(int n_wg, int window, int taps, int fwd_tile, const PlanView& pv, const WorkItem* items,
                                     int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
                                     int32_t* d_status, hipStream_t st)
 {
     const size_t lds = farrow_u_lds_bytes(window);
-    hipError_t e = hipFuncSetAttribute((const void*)k_farrow_u<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    auto kern = k_farrow_u<NT, HI>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
-    hipLaunchKernelGGL(k_farrow_u<NT>, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, taps, fwd_tile, items, n_items,
-                       ticket, ta, window, gy, upart, d_status);
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(NT), lds, st, pv, taps, fwd_tile, items, n_items, ticket, ta,
+                       window, gy, upart, d_status);
     return hipGetLastError();
 }
 
-hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int fwd_tile, const PlanView& pv,
-                           const WorkItem* items,
-                           int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
-                           int32_t* d_status, hipStream_t st)
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int order, int fwd_tile, const PlanView& pv,
+                           const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy,
+                           float* upart, int32_t* d_status, hipStream_t st)
 {
     if (n_items == 0) return hipSuccess;
-    if (nthreads == kAdjThreads)
-        return launch_farrow_u_t<kAdjThreads>(n_wg, window, taps, fwd_tile, pv, items, n_items, ticket, ta, gy, upart,
-                                              d_status, st);
-    return hipErrorInvalidValue;
+    if (nthreads != kAdjThreads) return hipErrorInvalidValue;
+    if (order > 9)
+        return launch_farrow_u_t<kAdjThreads, true>(n_wg, window, taps, fwd_tile, pv, items, n_items, ticket, ta, gy,
+                                                    upart, d_status, st);
+    return launch_farrow_u_t<kAdjThreads, false>(n_wg, window, taps, fwd_tile, pv, items, n_items, ticket, ta, gy,
+                                                 upart, d_status, st);
 }
 
 // u = sum over (mic, supergroup) of the partial sums, in that order; one thread per

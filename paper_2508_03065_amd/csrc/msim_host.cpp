@@ -1584,11 +1584,10 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
         if (gx) {
             LaunchTimer t(P, kKindAdjX, st);
             if (P->ugather) {
-                const PlanView& wv = pv;
                 const WorkItem* it = batched ? P->d_uitems : P->d_uitems_plain + P->uplain_off[k];
                 const int n = batched ? (int)P->uitems.size() : P->uplain_cnt[k];
-                HIP_OK(launch_farrow_u(kAdjThreads, std::min(n, P->adj_wgs), P->uwin, T, NT, wv, it, n, w.ticket, ta, gy,
-                                       w.upart, P->d_status, st));
+                HIP_OK(launch_farrow_u(kAdjThreads, std::min(n, P->adj_wgs), P->uwin, T, P->par.farrow_order, NT, pv,
+                                       it, n, w.ticket, ta, gy, w.upart, P->d_status, st));
                 const int64_t vtot = batched ? P->vpos_total : P->scenes[k].n_in + T;
                 HIP_OK(launch_farrow_u_reduce(one, nsc, batched ? P->d_vpos_prefix : P->d_zero, vtot, T, w.upart,
                                               w.u, st));

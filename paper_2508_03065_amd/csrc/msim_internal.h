@@ -274,11 +274,10 @@ size_t farrow_u_lds_bytes(int window);
 hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order, const PlanView& pv,
                             const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
                             const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st);
-// The dL/dx gather runs over whole-path delay groups: pv.groups / pv.perm are
-// those groups and their permutation.
-hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int fwd_tile, const PlanView& pv, const WorkItem* items,
-                           int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy, float* upart,
-                           int32_t* d_status, hipStream_t st);
+// The dL/dx gather over the delay blocks' groups; order: the Farrow degree M.
+hipError_t launch_farrow_u(int nthreads, int n_wg, int window, int taps, int order, int fwd_tile, const PlanView& pv,
+                           const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* gy,
+                           float* upart, int32_t* d_status, hipStream_t st);
 hipError_t launch_farrow_u_reduce(const PlanView& pv, int n_scenes, const int64_t* d_vprefix, int64_t vtotal, int taps,
                                   const float* upart, float* u, hipStream_t st);
 // scenes s0 .. s0 + n_scenes - 1 (max_in: their largest input length)
