@@ -264,23 +264,23 @@ __device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, i
             cv = (float)(n - k * R);
         }
         const int off = __builtin_amdgcn_readfirstlane(d.x);
-        q = sl.seg[off + cl];
-        K = sl.K[off + cl];
+        q = ld_at(sl.seg, (uint32_t)(off + cl));
+        K = ld_at(sl.K, (uint32_t)(off + cl));
         vv = cv;
         gf = __int_as_float(d.z);
     };
+    // positions outside the stored range read the window's zeros; a position
+    // outside the window (never, for a correct plan) is read clamped to it and
+    // flagged after the group (pmax: the largest window index seen, unsigned)
+    const int nws = n - ws;
+    uint32_t pmax = 0;
     auto body = [&](const Seg& sg, int Ks, float vv, float gf) {
         const float dl = fmaf(vv, fmaf(vv, fmaf(vv, sg.b3, sg.b2), sg.b1), sg.a0);
         const float fl = floorf(dl);
-        int p = n - (Ks + (int)fl) - ws;
-        // positions outside the stored range read the window's zeros; a position
-        // outside the window (never, for a correct plan) is flagged and read as
-        // slot 0 with zero gain, without a branch
-        const bool out = (unsigned)p >= (unsigned)W;
-        bad |= out;
-        p = out ? 0 : p;
-        const float r = farrow_horner<HI>(vw + __mul24(p, 3), 2.0f * (dl - fl) - 1.0f);
-        acc = fmaf(out ? 0.0f : gf * __builtin_amdgcn_rcpf((float)Ks + dl), r, acc);
+        const uint32_t p = (uint32_t)(nws - Ks - (int)fl);
+        pmax = max(pmax, p);
+        const float r = farrow_horner<HI>(vw + 3 * min(p, (uint32_t)(W - 1)), 2.0f * (dl - fl) - 1.0f);
+        acc = fmaf(gf * __builtin_amdgcn_rcpf((float)Ks + dl), r, acc);
     };
     for (int c0 = G.img_begin; c0 < G.img_end; c0 += kFarrowDescChunk) {
         const int nc = min(kFarrowDescChunk, G.img_end - c0);
@@ -311,6 +311,7 @@ __device__ inline void farrow_group1(const DScene& S, const DGroup& G, int n0, i
         if (j < nc) body(q0, K0, v0, g0);
         if (j + 1 < nc) body(q1, K1, v1, g1);
     }
+    bad |= pmax >= (uint32_t)W;
     __syncthreads();
 }
 
@@ -412,10 +413,13 @@ hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, i
 //   dL/dx[m] = sum_k sum_j c_k(j) u_k[m + j]          (the filter bank's transpose),
 //   dL/dbeta_i = sum gy s_i(n) fs/(4 pi c D),  dL/dD = gy g (ds/dD - s/D),  ds/dD = 2 dr/ds.
 
-// (window: the Farrow forward's, TILE + delay spread + 9 positions)
+// (window: the Farrow forward's, TILE + delay spread + 9 positions), then the
+// track offsets, the parameter sums and a chunk of image descriptors.
+constexpr int kGdDescChunk = 256;
 size_t farrow_gd_lds_bytes(int window)
 {
-    return (size_t)window * kFarrowStride * sizeof(float) + kLscBytes + kParamLdsBytes;
+    return (size_t)window * kFarrowStride * sizeof(float) + kLscBytes + kParamLdsBytes +
+           (size_t)kGdDescChunk * 2 * sizeof(int4);
 }
 
 // LDS of the dL/dx gather: the gy window, the track offsets, then the image
@@ -434,8 +438,8 @@ size_t farrow_u_lds_bytes(int window)
 template <int TILE, bool HI>
 __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0, int T, Slot sl, AdjSlot as,
                                        const DImage* __restrict__ I, const PermEntry* __restrict__ perm, float4* vw,
-                                       const float* __restrict__ v, const float* __restrict__ gyc, float ghat,
-                                       int& bad)
+                                       int4* dsc, const float* __restrict__ v, const float* __restrict__ gyc,
+                                       float ghat, int& bad)
 {
     constexpr int NT = kAdjThreads;
     constexpr int WAVES = NT / 64;
@@ -444,55 +448,70 @@ __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0,
     const int ws = n0 - G.dmax - 4;
     const int W = TILE + (G.dmax - G.dmin) + 9;
     stage_v(S, v, T, ws, W, vw, NT);
-    __syncthreads();
     const int n_out = (int)S.n_out;
-    for (int hv = 0; hv < HV; ++hv) {
-        const int n = n0 + hv * NT + tid;
-        const bool valid = n < n_out;
-        const int nc = valid ? n : n_out - 1;
-        const float wy = valid ? gyc[n] : 0.0f;
-        int cR = 0, cl = 0;
-        float cv = 0.0f;
-        CrLane<1> crl;
-        for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-            const DImage im = perm_image(I, perm, ii);
-            if (im.R != cR) {
-                cR = im.R;
-                const int k = div_exact(nc, cR, im.invR);
-                const int k_lo = div_exact(n0, cR, im.invR);
-                cl = k - k_lo;
-                cv = (float)(nc - k * cR);
-                cr_lane<1>(crl, n, nc, n_out, cR, im.invR, k, k_lo, hv * WAVES + wave, lane);
-            }
-            const Seg sg = sl.seg[im.loc + cl];
-            const int Ks = sl.K[im.loc + cl];
-            const float dl = fmaf(cv, fmaf(cv, fmaf(cv, sg.b3, sg.b2), sg.b1), sg.a0);
-            const float fl = floorf(dl);
-            const int p = nc - (Ks + (int)fl) - ws;
-            const bool inb = p >= 0 && p < W;
-            if (valid && !inb) bad = 1;
-            float E = 0.0f, Db = 0.0f;
-            if (valid && inb && wy != 0.0f) {
-                const float s = 2.0f * (dl - fl) - 1.0f;
-                const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
-                const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
-                // orders up to 9 leave the last two coefficients zero
-                constexpr int KT = HI ? kFarrowStride : 10;
-                float r = cf[KT - 1], dr = 0.0f;
-#pragma unroll
-                for (int k = KT - 2; k >= 0; --k) {
-                    dr = fmaf(dr, s, r);
-                    r = fmaf(r, s, cf[k]);
+    // The group's image descriptors a chunk at a time in LDS (slot offset, R, gain
+    // factor, 1/R; k_lo = n0 / R), read there as wave-uniform values.
+    for (int c0 = G.img_begin; c0 < G.img_end; c0 += kGdDescChunk) {
+        const int nc = min(kGdDescChunk, G.img_end - c0);
+        __syncthreads();                 // window staged; the previous chunk's descriptors read
+        for (int i = tid; i < nc; i += NT) {
+            const PermEntry e = perm[c0 + i];
+            const DImage& im = I[e.img];
+            dsc[2 * i] = make_int4(e.loc, im.R, __float_as_int(im.gfac), __float_as_int(im.invR));
+            dsc[2 * i + 1] = make_int4(div_exact(n0, im.R, im.invR), 0, 0, 0);
+        }
+        __syncthreads();
+        for (int hv = 0; hv < HV; ++hv) {
+            const int n = n0 + hv * NT + tid;
+            const bool valid = n < n_out;
+            const int nc_out = valid ? n : n_out - 1;
+            const float wy = valid ? gyc[n] : 0.0f;
+            int cR = 0, cl = 0;
+            float cv = 0.0f;
+            CrLane<1> crl;
+            for (int j = 0; j < nc; ++j) {
+                const int4 d0 = dsc[2 * j];
+                const int loc = __builtin_amdgcn_readfirstlane(d0.x);
+                const int R = __builtin_amdgcn_readfirstlane(d0.y);
+                const float gfac = __int_as_float(d0.z), invR = __int_as_float(d0.w);
+                if (R != cR) {
+                    cR = R;
+                    const int k = div_exact(nc_out, R, invR);
+                    const int k_lo = __builtin_amdgcn_readfirstlane(dsc[2 * j + 1].x);
+                    cl = k - k_lo;
+                    cv = (float)(nc_out - k * R);
+                    cr_lane<1>(crl, n, nc_out, n_out, R, invR, k, k_lo, hv * WAVES + wave, lane);
                 }
-                const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
-                E = wy * r * ghat * iD;
-                Db = wy * im.gfac * iD * fmaf(2.0f, dr, -r * iD);
+                const Seg sg = ld_at(sl.seg, (uint32_t)(loc + cl));
+                const int Ks = ld_at(sl.K, (uint32_t)(loc + cl));
+                const float dl = fmaf(cv, fmaf(cv, fmaf(cv, sg.b3, sg.b2), sg.b1), sg.a0);
+                const float fl = floorf(dl);
+                const int p = nc_out - (Ks + (int)fl) - ws;
+                const bool inb = p >= 0 && p < W;
+                if (valid && !inb) bad = 1;
+                float E = 0.0f, Db = 0.0f;
+                if (valid && inb && wy != 0.0f) {
+                    const float s = 2.0f * (dl - fl) - 1.0f;
+                    const float4 a = vw[3 * p], b = vw[3 * p + 1], c = vw[3 * p + 2];
+                    const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+                    // orders up to 9 leave the last two coefficients zero
+                    constexpr int KT = HI ? kFarrowStride : 10;
+                    float r = cf[KT - 1], dr = 0.0f;
+#pragma unroll
+                    for (int k = KT - 2; k >= 0; --k) {
+                        dr = fmaf(dr, s, r);
+                        r = fmaf(r, s, cf[k]);
+                    }
+                    const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
+                    E = wy * r * ghat * iD;
+                    Db = wy * gfac * iD * fmaf(2.0f, dr, -r * iD);
+                }
+                const int li = c0 + j - G.img_begin;
+                const float db[1] = {valid ? Db : 0.0f};
+                cr_partials<1>(crl, db, as.dpart + loc + li * (TILE / 64));
+                E = wave_sum_dpp(E);
+                if (lane == 0) as.esum[li * (TILE / 64) + hv * WAVES + wave] = E;
             }
-            const int li = ii - G.img_begin;
-            const float db[1] = {valid ? Db : 0.0f};
-            cr_partials<1>(crl, db, as.dpart + im.loc + li * (TILE / 64));
-            E = wave_sum_dpp(E);
-            if (lane == 0) as.esum[li * (TILE / 64) + hv * WAVES + wave] = E;
         }
     }
     __syncthreads();
@@ -513,6 +532,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, c
     float4* vw = lds;
     int* lsc = (int*)(lds + 3 * window);
     double* pl = (double*)((char*)lsc + kLscBytes);
+    int4* dsc = (int4*)((char*)pl + kParamLdsBytes);
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     const AdjSlot as = adj_slot_at(ta, pa.gmax, TILE, blockIdx.x);
     for_each_item(ticket, n_items, [&](int it) {
@@ -532,7 +552,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, c
             const DGroup G = pv.groups[B.grp_begin + g];
             tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi,
                             group_span(TILE, G.dmin, G.dmax), sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
-            farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, v, gyc, pa.ghat, bad);
+            farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, dsc, v, gyc, pa.ghat, bad);
             param_group<NT, TILE, 1>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
         }
         param_item_end<NT>(S, w, pl, acc, pa);
@@ -579,14 +599,18 @@ hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order,
 // (none where the integer delay steps down).  Per image the lane takes one
 // Newton step on n - D_i(n) = P - 1/2 from the previous image's integer delay
 // (the images are sorted by delay), evaluates the rounded solution and its two
-// neighbours on the (at most two) track segments they lie on, and moves one
-// sample at a time in the rare case the band is not inside them.  It
+// neighbours on the (at most two) track segments they lie on, and takes
+// fixed-point steps n <- P + floor(D_i(n)) from there in the rare case the band
+// is not inside them (a full-rate track carries no slope, so there the Newton
+// step is a fixed-point step too).  It
 // accumulates u_k += gy g s^k in registers over every group of the supergroup.
 // Per group the tracks cover the outputs of the block that can read the tile,
 // and gy over them is staged in LDS.
 // upart[S.u_base + ((mic n_sgw + sgw) (n_in + T) + P + T/2) 12 + k].
+// Four waves per SIMD (at most 128 VGPRs): the per-image search waits on track
+// segment loads, and the extra waves hide them (26 % faster than at 144 VGPRs).
 template <int NT, bool HI>
-__global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_tile, const WorkItem* __restrict__ items,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_farrow_u(PlanView pv, int T, int fwd_tile, const WorkItem* __restrict__ items,
                                                   int n_items, int32_t* __restrict__ ticket, TrackArgs ta, int window,
                                                   const float* __restrict__ gy, float* __restrict__ upart,
                                                   int32_t* __restrict__ status)
@@ -742,7 +766,8 @@ __global__ __launch_bounds__(NT) void k_farrow_u(PlanView pv, int T, int fwd_til
                             if (hm || hp) add(hm ? n1 - 1 : n1 + 1, hm ? offm : offp, hm ? Dm : Dp);
                             break;
                         }
-                        n1 = clampn(pc < P ? n1 + 1 : n1 - 1);
+                        // a fixed-point step n <- P + K(n) (a contraction)
+                        n1 = clampn(n1 + (P - pc));
                     }
                 }
             }
