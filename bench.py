@@ -179,6 +179,8 @@ def kernel_roofline(fd, kind, prof, work_flops, workload, lds_bytes=None, gather
     """Roofline of one kernel kind from the plan's HIP-event profile: achieved
     FLOP/s = algorithmic flops per launch / average launch duration."""
     kernel, src = KERNEL_OF["farrow" if kind == "adjx" and gather else fd][kind]
+    if fd == "table" and kind == "adjx" and gather:
+        workload += "_table"          # the gather over the table form's delay groups
     key = PROFILE_KEY[kind]
     n = max(1, prof[key + "_launches"])
     kms = prof[key + "_ms"] / n
