@@ -517,10 +517,110 @@ __device__ inline void farrow_gd_group(const DScene& S, const DGroup& G, int n0,
     __syncthreads();
 }
 
+// The same with two consecutive outputs per lane (n0 + 2 tid and the next) over
+// a tile of 2 kAdjThreads outputs: both lie on one track segment (every
+// decimation is 1 or even), so they share the image's descriptor, segment fetch
+// and Catmull-Rom lane state, and one segmented scan and one wave sum serve both.
+// wy0, wy1: dL/dy at the lane's outputs (0 past the end).  Ends with a barrier.
+template <bool HI>
+__device__ inline void farrow_gd_group2(const DScene& S, const DGroup& G, int n0, int T, Slot sl, AdjSlot as,
+                                        const DImage* __restrict__ I, const PermEntry* __restrict__ perm,
+                                        float4* vw, int4* dsc, const float* __restrict__ v, float wy0, float wy1,
+                                        float ghat, int& bad)
+{
+    constexpr int NT = kAdjThreads;
+    constexpr int TO = 2 * NT;
+    constexpr int WAVES = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ws = n0 - G.dmax - 4;
+    const int W = TO + (G.dmax - G.dmin) + 9;
+    stage_v(S, v, T, ws, W, vw, NT);
+    const int n_out = (int)S.n_out;
+    const int n = n0 + 2 * tid;
+    const bool ok0 = n < n_out, ok1 = n + 1 < n_out;
+    const int nc = ok0 ? n : n_out - 1;           // lanes past the end follow the last output
+    const int nc1 = min(nc + 1, n_out - 1);
+    for (int c0 = G.img_begin; c0 < G.img_end; c0 += kGdDescChunk) {
+        const int nchunk = min(kGdDescChunk, G.img_end - c0);
+        __syncthreads();                 // window staged; the previous chunk's descriptors read
+        for (int i = tid; i < nchunk; i += NT) {
+            const PermEntry e = perm[c0 + i];
+            const DImage& im = I[e.img];
+            dsc[2 * i] = make_int4(e.loc, im.R, __float_as_int(im.gfac), __float_as_int(im.invR));
+            dsc[2 * i + 1] = make_int4(div_exact(n0, im.R, im.invR), 0, 0, 0);
+        }
+        __syncthreads();
+        int cR = 0, cs0 = 0, cs1 = 0;
+        float cv = 0.0f;
+        CrLane<2> crl;
+        for (int j = 0; j < nchunk; ++j) {
+            const int4 d0 = dsc[2 * j];
+            const int loc = __builtin_amdgcn_readfirstlane(d0.x);
+            const int R = __builtin_amdgcn_readfirstlane(d0.y);
+            const float gfac = __int_as_float(d0.z), invR = __int_as_float(d0.w);
+            if (R != cR) {
+                cR = R;
+                if (R == 1) {
+                    cs0 = nc - n0;
+                    cs1 = nc1 - n0;
+                    cv = 0.0f;
+                    cr_lane<2>(crl, n, nc, n_out, 1, 1.0f, nc, n0, wave, lane);
+                } else {
+                    const int k = div_exact(nc, R, invR);
+                    const int k_lo = __builtin_amdgcn_readfirstlane(dsc[2 * j + 1].x);
+                    cs0 = cs1 = k - k_lo;
+                    cv = (float)(nc - k * R);
+                    cr_lane<2>(crl, n, nc, n_out, R, invR, k, k_lo, wave, lane);
+                }
+            }
+            const Seg sg = ld_at(sl.seg, (uint32_t)(loc + cs0));
+            const float a1 = ld_at(sl.seg, (uint32_t)(loc + cs1)).a0;
+            const int K0s = ld_at(sl.K, (uint32_t)(loc + cs0)), K1s = ld_at(sl.K, (uint32_t)(loc + cs1));
+            const float dl0 = fmaf(cv, fmaf(cv, fmaf(cv, sg.b3, sg.b2), sg.b1), sg.a0);
+            const float v1 = cv + 1.0f;
+            const float dl1 = R == 1 ? a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
+            // value r and dr/ds of one output; E and dL/dD accumulate its terms
+            float E = 0.0f, Db[2] = {0.0f, 0.0f};
+            auto one = [&](int c, int Ks, float dl, float wy, bool ok, int r) {
+                const float fl = floorf(dl);
+                const int p = c - (Ks + (int)fl) - ws;
+                const bool inb = p >= 0 && p < W;
+                if (ok && !inb) bad = 1;
+                if (ok && inb && wy != 0.0f) {
+                    const float s = 2.0f * (dl - fl) - 1.0f;
+                    const float4 a = vw[3 * p], b = vw[3 * p + 1], cc = vw[3 * p + 2];
+                    const float cf[kFarrowStride] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, cc.x, cc.y, cc.z, cc.w};
+                    constexpr int KT = HI ? kFarrowStride : 10;
+                    float rv = cf[KT - 1], dr = 0.0f;
+#pragma unroll
+                    for (int k = KT - 2; k >= 0; --k) {
+                        dr = fmaf(dr, s, rv);
+                        rv = fmaf(rv, s, cf[k]);
+                    }
+                    const float iD = __builtin_amdgcn_rcpf((float)Ks + dl);
+                    E = fmaf(wy * rv * ghat, iD, E);
+                    Db[r] = wy * gfac * iD * fmaf(2.0f, dr, -rv * iD);
+                }
+            };
+            one(nc, K0s, dl0, wy0, ok0, 0);
+            one(nc1, K1s, dl1, wy1, ok1, 1);
+            const int li = c0 + j - G.img_begin;
+            cr_partials<2>(crl, Db, as.dpart + loc + li * (TO / 128));
+            E = wave_sum_dpp(E);
+            if (lane == 0) {
+                as.esum[li * (TO / 64) + 2 * wave] = E;
+                as.esum[li * (TO / 64) + 2 * wave + 1] = 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Gain/delay adjoint and parameter partials, Farrow form, persistent over work
 // items (scene, mic, tile, supergroup): one row of parameter partials per item.
-// kAdjThreads lanes, TILE / kAdjThreads outputs per lane in turn.
-template <int TILE, bool HI>
+// kAdjThreads lanes, TILE / kAdjThreads outputs per lane in turn (RB 1), or two
+// consecutive outputs per lane at once (RB 2, TILE = 2 kAdjThreads).
+template <int TILE, bool HI, int RB>
 __global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, const WorkItem* __restrict__ items,
                                                            int n_items, int32_t* __restrict__ ticket, TrackArgs ta,
                                                            int window, const float* __restrict__ v,
@@ -552,22 +652,30 @@ __global__ __launch_bounds__(kAdjThreads) void k_farrow_gd(PlanView pv, int T, c
             const DGroup G = pv.groups[B.grp_begin + g];
             tile_tracks<NT>(S, w.mic, I, pv.perm, G.img_begin, G.img_end, n0, n_hi,
                             group_span(TILE, G.dmin, G.dmax), sl, lsc, ta.knots, ta.mics, ta.c, ta.fs, ta.model);
-            farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, dsc, v, gyc, pa.ghat, bad);
-            param_group<NT, TILE, 1>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
+            if constexpr (RB == 1) {
+                farrow_gd_group<TILE, HI>(S, G, n0, T, sl, as, I, pv.perm, vw, dsc, v, gyc, pa.ghat, bad);
+            } else {
+                static_assert(TILE == 2 * NT, "two outputs per lane cover the tile");
+                const int n = n0 + 2 * (int)threadIdx.x;
+                const float wy0 = n < n_out ? gyc[n] : 0.0f;
+                const float wy1 = n + 1 < n_out ? gyc[n + 1] : 0.0f;
+                farrow_gd_group2<HI>(S, G, n0, T, sl, as, I, pv.perm, vw, dsc, v, wy0, wy1, pa.ghat, bad);
+            }
+            param_group<NT, TILE, RB>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
         }
         param_item_end<NT>(S, w, pl, acc, pa);
         if (bad) atomicOr(status, kStatusWindow);
     });
 }
 
-template <int TILE>
+template <int TILE, int RB>
 static hipError_t launch_farrow_gd_t(int n_wg, int window, int taps, int hi, const PlanView& pv,
                                      const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta,
                                      const float* v, const float* gy, const ParamArgs& pa, int32_t* d_status,
                                      hipStream_t st)
 {
     const size_t lds = farrow_gd_lds_bytes(window);
-    auto kern = hi ? k_farrow_gd<TILE, true> : k_farrow_gd<TILE, false>;
+    auto kern = hi ? k_farrow_gd<TILE, true, RB> : k_farrow_gd<TILE, false, RB>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(64), 0, st, ticket);
@@ -576,18 +684,21 @@ static hipError_t launch_farrow_gd_t(int n_wg, int window, int taps, int hi, con
     return hipGetLastError();
 }
 
-hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order, const PlanView& pv,
+hipError_t launch_farrow_gd(int tile, int rb, int n_wg, int window, int taps, int order, const PlanView& pv,
                             const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
                             const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st)
 {
     if (n_items == 0) return hipSuccess;
     const int hi = order > 9;
-    if (tile == 1024)
-        return launch_farrow_gd_t<1024>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa, d_status,
-                                        st);
-    if (tile == 512)
-        return launch_farrow_gd_t<512>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa, d_status,
-                                       st);
+    if (tile == 2 * kAdjThreads && rb == 2)
+        return launch_farrow_gd_t<2 * kAdjThreads, 2>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy,
+                                                      pa, d_status, st);
+    if (tile == 1024 && rb == 1)
+        return launch_farrow_gd_t<1024, 1>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa,
+                                           d_status, st);
+    if (tile == 512 && rb == 1)
+        return launch_farrow_gd_t<512, 1>(n_wg, window, taps, hi, pv, items, n_items, ticket, ta, v, gy, pa,
+                                          d_status, st);
     return hipErrorInvalidValue;
 }
 

@@ -1507,6 +1507,14 @@ struct BwdWs {
 
 int64_t adj_slot_size(const msim_plan* P) { return adj_slot_bytes(P->slot_segs, P->gmax, P->threads); }
 
+// Outputs per lane of the Farrow gain/delay adjoint: two where the tile is two
+// lanes' worth and every decimation is 1 or even (a lane's outputs then share a
+// track segment), else one.
+int farrow_gd_rb(const msim_plan* P)
+{
+    return P->threads == 2 * kAdjThreads && P->rb_max % 2 == 0 ? 2 : 1;
+}
+
 size_t carve_bwd_ws(const msim_plan* P, bool batched, char* base, BwdWs* w)
 {
     size_t off = 0;
@@ -1609,8 +1617,9 @@ msim_status enqueue_backward(msim_plan* P, const float* x, const float* gy, floa
             {
                 LaunchTimer t(P, kKindAdjP, st);
                 if (farrow)
-                    HIP_OK(launch_farrow_gd(NT, std::min(n, P->adj_wgs), P->b_window, T, P->par.farrow_order, pv, it, n,
-                                            w.ticket, ta, w.v, gy, pa, P->d_status, st));
+                    HIP_OK(launch_farrow_gd(NT, farrow_gd_rb(P), std::min(n, P->adj_wgs), P->b_window, T,
+                                            P->par.farrow_order, pv, it, n, w.ticket, ta, w.v, gy, pa, P->d_status,
+                                            st));
                 else
                     HIP_OK(launch_adjp(T, NT, P->rb, std::min(n, P->adj_wgs), P->b_window, pv, P->d_qtable, L, it, n,
                                        w.ticket, ta, x, gy, pa, P->d_status, st));

@@ -271,7 +271,8 @@ hipError_t launch_farrow(int nthreads, int rb, int n_wg, int window, int taps, i
 // LDS of the Farrow gain/delay adjoint and of the dL/dx gather.
 size_t farrow_gd_lds_bytes(int window);
 size_t farrow_u_lds_bytes(int window);
-hipError_t launch_farrow_gd(int tile, int n_wg, int window, int taps, int order, const PlanView& pv,
+// rb: outputs per lane (2 needs tile = 2 kAdjThreads and every decimation 1 or even).
+hipError_t launch_farrow_gd(int tile, int rb, int n_wg, int window, int taps, int order, const PlanView& pv,
                             const WorkItem* items, int n_items, int32_t* ticket, const TrackArgs& ta, const float* v,
                             const float* gy, const ParamArgs& pa, int32_t* d_status, hipStream_t st);
 // The dL/dx gather over the delay blocks' groups; order: the Farrow degree M.
