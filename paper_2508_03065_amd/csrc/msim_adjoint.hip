@@ -43,11 +43,17 @@ size_t adj_x_lds_bytes(int taps, int Lq, int window, int tile)
            (size_t)(kAdjThreads / 64) * (size_t)(window - tile + 64 * h) * sizeof(float) + kLscBytes;
 }
 
-// The gain/delay kernels: the forward's LDS, then the slot offsets and the
-// parameter accumulators.
+// Image descriptors staged in LDS at a time by the table form's gain/delay
+// kernel at two outputs per lane (one chunk covers a delay group at the table
+// form's default cap of 24 images).
+constexpr int kAdjDescChunk = 32;
+
+// The gain/delay kernels: the forward's LDS, then the slot offsets, the
+// parameter accumulators and a chunk of image descriptors.
 size_t adj_track_lds_bytes(int taps, int Lq, int window)
 {
-    return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4) + kLscBytes + kParamLdsBytes;
+    return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4) + kLscBytes + kParamLdsBytes +
+           (size_t)kAdjDescChunk * 2 * sizeof(int4);
 }
 
 // ------------------------------------------------------------ transpose delay
@@ -475,8 +481,8 @@ __device__ inline void gd_group(const DScene& S, const DGroup& G, int n0, Slot s
 template <int T, int NT, int LC>
 __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot sl, AdjSlot as,
                                  const DImage* __restrict__ I, const PermEntry* __restrict__ perm, const float4* tab,
-                                 float4* xw, int Lr, const float* __restrict__ x, float wy0, float wy1, float ghat,
-                                 int& bad)
+                                 float4* xw, int4* dsc, int Lr, const float* __restrict__ x, float wy0, float wy1,
+                                 float ghat, int& bad)
 {
     constexpr int NG = T / 8;
     constexpr int TO = 2 * NT;
@@ -490,38 +496,52 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
     const int n_in = (int)S.n_in;
     const int half = split_half(W);
     stage_window_split(x + S.x_off, n_in, ws, W, xw, NT);
-    __syncthreads();
     const int n_out = (int)S.n_out;
     const int n = n0 + 2 * tid;
     const bool ok0 = n < n_out, ok1 = n + 1 < n_out;
     const int nc = ok0 ? n : n_out - 1;           // lanes past the end follow the last output
     const float Lf = (float)L;
+    // the group's image descriptors a chunk at a time in LDS (slot offset, R, gain
+    // factor, 1/R; k_lo = n0 / R), read there as wave-uniform values
+    for (int cb = G.img_begin; cb < G.img_end; cb += kAdjDescChunk) {
+    const int nch = min(kAdjDescChunk, G.img_end - cb);
+    __syncthreads();                 // window staged; the previous chunk's descriptors read
+    for (int i = tid; i < nch; i += NT) {
+        const PermEntry e = perm[cb + i];
+        const DImage& im = I[e.img];
+        dsc[2 * i] = make_int4(e.loc, im.R, __float_as_int(im.gfac), __float_as_int(im.invR));
+        dsc[2 * i + 1] = make_int4(div_exact(n0, im.R, im.invR), 0, 0, 0);
+    }
+    __syncthreads();
     int cR = 0, c0 = 0, c1 = 0;
     float cv = 0.0f;
     CrLane<2> crl;
-    for (int ii = G.img_begin; ii < G.img_end; ++ii) {
-        const DImage im = perm_image(I, perm, ii);
-        if (im.R != cR) {
-            cR = im.R;
+    for (int j = 0; j < nch; ++j) {
+        const int4 dd = dsc[2 * j];
+        const int loc = __builtin_amdgcn_readfirstlane(dd.x);
+        const int R = __builtin_amdgcn_readfirstlane(dd.y);
+        const float gfac = __int_as_float(dd.z), invR = __int_as_float(dd.w);
+        if (R != cR) {
+            cR = R;
             if (cR == 1) {
                 c0 = nc - n0;
                 c1 = min(nc + 1, n_out - 1) - n0;
                 cv = 0.0f;
                 cr_lane<2>(crl, n, nc, n_out, 1, 1.0f, nc, n0, wave, lane);
             } else {
-                const int k0 = div_exact(nc, cR, im.invR);
-                const int k_lo = div_exact(n0, cR, im.invR);
+                const int k0 = div_exact(nc, cR, invR);
+                const int k_lo = __builtin_amdgcn_readfirstlane(dsc[2 * j + 1].x);
                 c0 = c1 = k0 - k_lo;
                 cv = (float)(nc - k0 * cR);
-                cr_lane<2>(crl, n, nc, n_out, cR, im.invR, k0, k_lo, wave, lane);
+                cr_lane<2>(crl, n, nc, n_out, cR, invR, k0, k_lo, wave, lane);
             }
         }
-        const Seg sg = sl.seg[im.loc + c0];
-        const float a1 = sl.seg[im.loc + c1].a0;
-        const int K0s = sl.K[im.loc + c0], K1s = sl.K[im.loc + c1];
+        const Seg sg = ld_at(sl.seg, (uint32_t)(loc + c0));
+        const float a1 = ld_at(sl.seg, (uint32_t)(loc + c1)).a0;
+        const int K0s = ld_at(sl.K, (uint32_t)(loc + c0)), K1s = ld_at(sl.K, (uint32_t)(loc + c1));
         const float d0 = fmaf(cv, fmaf(cv, fmaf(cv, sg.b3, sg.b2), sg.b1), sg.a0);
         const float v1 = cv + 1.0f;
-        const float d1 = im.R == 1 ? a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
+        const float d1 = R == 1 ? a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
         const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
         const int K = fr.K;
         const bool act = (wy0 != 0.0f || wy1 != 0.0f) && nc - K + T / 2 >= 0 && nc - K - T / 2 < n_in;
@@ -544,18 +564,19 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
                 const float iD0 = __builtin_amdgcn_rcpf((float)K0s + d0);
                 const float iD1 = __builtin_amdgcn_rcpf((float)K1s + d1);
                 E = ghat * fmaf(wy0 * s0, iD0, wy1 * s1 * iD1);
-                Db0 = wy0 * im.gfac * iD0 * fmaf(-s0, iD0, sd0);
-                Db1 = wy1 * im.gfac * iD1 * fmaf(-s1, iD1, sd1);
+                Db0 = wy0 * gfac * iD0 * fmaf(-s0, iD0, sd0);
+                Db1 = wy1 * gfac * iD1 * fmaf(-s1, iD1, sd1);
             }
         }
-        const int li = ii - G.img_begin;
+        const int li = cb + j - G.img_begin;
         const float db[2] = {ok0 ? Db0 : 0.0f, ok1 ? Db1 : 0.0f};
-        cr_partials<2>(crl, db, as.dpart + im.loc + li * (TO / 128));
+        cr_partials<2>(crl, db, as.dpart + loc + li * (TO / 128));
         E = wave_sum_dpp(E);
         if (lane == 0) {
             as.esum[li * (TO / 64) + 2 * wave] = E;
             as.esum[li * (TO / 64) + 2 * wave + 1] = 0.0f;
         }
+    }
     }
     __syncthreads();
 }
@@ -576,6 +597,7 @@ __global__ __launch_bounds__(RB == 1 ? kAdjThreads : TO / 2) void k_adjp(
     float4* xw = lds + qtab_bytes(T, L) / 16;
     int* lsc = (int*)(xw + window + 1);
     double* pl = (double*)((char*)lsc + kLscBytes);
+    int4* dsc = (int4*)((char*)pl + kParamLdsBytes);
     load_qtab<T>(table, tab, L, NT);
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     const AdjSlot as = adj_slot_at(ta, pa.gmax, TO, blockIdx.x);
@@ -603,7 +625,7 @@ __global__ __launch_bounds__(RB == 1 ? kAdjThreads : TO / 2) void k_adjp(
                 const int n = n0 + 2 * (int)threadIdx.x;
                 const float wy0 = n < n_out ? gyc[n] : 0.0f;
                 const float wy1 = n + 1 < n_out ? gyc[n + 1] : 0.0f;
-                gd_group2<T, NT, LC>(S, G, n0, sl, as, I, pv.perm, tab, xw, L, x, wy0, wy1, pa.ghat, bad);
+                gd_group2<T, NT, LC>(S, G, n0, sl, as, I, pv.perm, tab, xw, dsc, L, x, wy0, wy1, pa.ghat, bad);
             }
             param_group<NT, TO, RB>(S, w.mic, G, n0, n_hi, sl, as, lsc, I, pv.perm, ta, pa, pl, acc);
         }
