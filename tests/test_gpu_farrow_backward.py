@@ -59,6 +59,11 @@ CASES = [
     dict(seed=41, max_order=3, seconds=0.1, taps=32),
     dict(seed=42, max_order=4, seconds=0.12, taps=64, n_mics=2, moving_rcv=True),
     dict(seed=43, max_order=5, seconds=0.12, taps=96, n_knots=4, tiers=((2, 1), (4, 16), (99, 160))),
+    # odd decimations: the gain/delay kernel keeps one output per lane, and the
+    # gather's neighbouring outputs fall on two segments in most lanes
+    dict(seed=49, max_order=3, seconds=0.1, taps=64, tiers=((1, 1), (2, 5), (99, 15))),
+    # every image at the audio rate: one track segment per output
+    dict(seed=50, max_order=2, seconds=0.06, taps=32, tiers=()),
 ]
 
 
