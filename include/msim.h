@@ -118,7 +118,8 @@ typedef struct {
                                    in the table form this is the transpose of the Farrow fit of
                                    the same kernel, within its error of the table's); taken
                                    unless the Farrow fit exceeds the error budget or a
-                                   whole-path window does not fit LDS.  MSIM_ADJX_TRANSPOSE:
+                                   delay group's gather window does not fit LDS.
+                                   MSIM_ADJX_TRANSPOSE:
                                    the table form's exact transpose.  farrow_order 4..11. */
 } msim_params;
 

@@ -511,8 +511,8 @@ struct msim_plan {
     std::vector<PermEntry> perm;
     DBlock* d_blocks = nullptr;
     PermEntry* d_perm = nullptr;
-    // whole-path delay groups (the Farrow dL/dx gather over source positions) and
-    // their items; supergroup delay bounds per block (table dL/dx windows)
+    // work items of the Farrow dL/dx gather (scene, mic, position tile, supergroup of
+    // each block's groups); supergroup delay bounds per block (table dL/dx windows)
     std::vector<WorkItem> uitems, uitems_plain;
     std::vector<int> uplain_off, uplain_cnt;
     std::vector<int2> sgb;
@@ -1008,7 +1008,7 @@ msim_status regroup(msim_plan* P)
     const bool farrow = P->par.fd_kind == MSIM_FD_FARROW;
     // dL/dx through the Farrow gather: always in the Farrow form; in the table form
     // unless asked for its own transpose, or the Farrow fit misses the budget, or a
-    // whole-path window does not fit LDS (then the table's transpose is used)
+    // delay group's gather window does not fit LDS (then the table's transpose is used)
     P->ugather = farrow || (P->par.adjx_mode == MSIM_ADJX_GATHER && P->err_farrow <= kFdErrBudget);
     bool ugather = P->ugather;
     P->groups.clear();
