@@ -486,7 +486,6 @@ __device__ inline void gd_group2(const DScene& S, const DGroup& G, int n0, Slot 
 {
     constexpr int NG = T / 8;
     constexpr int TO = 2 * NT;
-    constexpr int WAVES = NT / 64;
     const int L = LC > 0 ? LC : Lr;
     const int LP = LC > 0 ? LC + 1 : Lr + 1;
     const QTab tq = qtab_view<T>(tab, LP);

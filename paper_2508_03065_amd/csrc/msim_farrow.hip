@@ -530,7 +530,6 @@ __device__ inline void farrow_gd_group2(const DScene& S, const DGroup& G, int n0
 {
     constexpr int NT = kAdjThreads;
     constexpr int TO = 2 * NT;
-    constexpr int WAVES = NT / 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ws = n0 - G.dmax - 4;
     const int W = TO + (G.dmax - G.dmin) + 9;
