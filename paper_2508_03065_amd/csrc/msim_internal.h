@@ -225,11 +225,13 @@ hipError_t launch_reduce_sg(const DScene* d_scenes, int n_scenes, const int64_t*
                             const float* part, float* y, hipStream_t st);
 
 // Tap quads of the half table that carry the quadratic term: those within 3/4 of
-// the half-width.  Further out the kernel's second differences are below 1.3e-6
-// at 128 phases (taps 3T/8 .. T/2 of a Kaiser-windowed sinc with beta = 8); their
-// term, at most 1.5e-7 of the kernel's energy for fractions in [0, 1], is below the
-// FP32 rounding of the tap sum, and the table stores them as zero.
-__host__ __device__ constexpr int qcorr_quads(int taps) { return taps / 8 - taps / 32; }
+// the half-width for 32 and 64 taps, within half of it for 96 and 128.  Further
+// out the table stores zero second differences: the kernel's curvature there is
+// small against its edge values (a Kaiser-windowed sinc, beta = 8), and the
+// predicted table error (fd error model, which reads the stored values) grows by
+// at most 0.9e-6 at 64 phases and 0.3e-6 at 128 for 96 and 128 taps, while the
+// longer filters' tap loops drop a third of their second-difference FMAs.
+__host__ __device__ constexpr int qcorr_quads(int taps) { return taps >= 96 ? taps / 16 : taps / 8 - taps / 32; }
 // Phase counts of the quadratic FD table compiled into the kernels (immediate
 // table offsets; other counts read it at run time): the default, and the coarser
 // one the planner may take so that two outputs per lane fit a faster path.

@@ -50,7 +50,7 @@ CASES = [
     dict(seed=31, max_order=3, seconds=0.1, taps=32),
     dict(seed=32, max_order=4, seconds=0.12, taps=64, n_mics=2, moving_rcv=True),
     dict(seed=33, max_order=5, seconds=0.12, taps=64, n_knots=4, tiers=((2, 1), (4, 16), (99, 160))),
-    # longer filters: the quadratic term stops at a different tap (3/4 of the half-width)
+    # longer filters: the quadratic term stops at a different tap (half the half-width)
     dict(seed=44, max_order=3, seconds=0.08, taps=96, tiers=((2, 1), (4, 16), (99, 160))),
     dict(seed=45, max_order=2, seconds=0.05, taps=128, fs=48000.0),
 ]

@@ -145,7 +145,8 @@ def test_null_arguments(lib):
 
 def _table_model(T, beta, fc, L):
     """Relative error of the quadratic phase table for a white input (numpy
-    model of the stored values: FP32 Y and D1, FP16 D2, zero beyond 3T/32 quads)."""
+    model of the stored values: FP32 Y and D1, FP16 D2, zero beyond 3T/32 quads,
+    beyond T/16 for 96 and 128 taps)."""
     def h(v):
         v = np.asarray(v, float)
         r = 2 * v / T
@@ -158,14 +159,16 @@ def _table_model(T, beta, fc, L):
         y0, y1, y2 = (h(d + (rows + i) / L) for i in range(3))
         Y = y0.astype(np.float32).astype(float)
         D1 = (y1 - y0).astype(np.float32).astype(float)
-        D2 = (y2 - 2 * y1 + y0).astype(np.float16).astype(float) if d // 4 < T // 8 - T // 32 else 0.0 * y0
+        nq = T // 16 if T >= 96 else T // 8 - T // 32
+        D2 = (y2 - 2 * y1 + y0).astype(np.float16).astype(float) if d // 4 < nq else 0.0 * y0
         ap = Y[:, None] + f * D1[:, None] + f * (f - 1) / 2 * D2[:, None]
         se += 2 * np.mean((ap - h(d + (rows[:, None] + f) / L)) ** 2)
     return np.sqrt(se / (2 * np.sum(h(np.arange(T // 2) + 0.5) ** 2)))
 
 
 @pytest.mark.parametrize("T,beta,fc,L", [(32, 0.0, 0.5, 64), (64, 0.0, 0.5, 64), (32, 0.0, 0.45, 64),
-                                         (32, 0.0, 0.45, 128), (64, 4.0, 0.45, 64), (64, 8.0, 0.5, 128)])
+                                         (32, 0.0, 0.45, 128), (64, 4.0, 0.45, 64), (64, 8.0, 0.5, 128),
+                                         (96, 8.0, 0.5, 64), (96, 0.0, 0.5, 128), (128, 8.0, 0.5, 64)])
 def test_table_error_budget(lib, T, beta, fc, L):
     """The table form is refused (MSIM_E_UNSUPPORTED, before any device call)
     exactly where the predicted error exceeds the 5e-6 budget."""
