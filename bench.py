@@ -42,11 +42,15 @@ FLOPS_PER_TAP = 4             # forward, dL/dx: the interpolated coefficient and
 FLOPS_PER_TAP_GD = 8          # gain/delay adjoint: the value and the derivative chains
 
 
-def table_lds_per_tap(outputs_per_lane: int) -> float:
-    """Table form, LDS bytes per tap: the source sample and the row's two FP32 and one
-    FP16 quadratic-table values (14 B); with two adjacent outputs per lane one table
-    read and one new source quad serve both outputs' taps (7 B)."""
-    return 14.0 / outputs_per_lane
+def table_lds_per_tap(outputs_per_lane: int, taps: int) -> float:
+    """Table form, LDS bytes per tap: the source sample and the row's two FP32
+    quadratic-table values (12 B), and its FP16 second difference (2 B) on the tap
+    quads that carry one (3/4 of the half-width for up to 64 taps, half of it for
+    96 and 128); with two adjacent outputs per lane one table read and one new
+    source quad serve both outputs' taps."""
+    quads = taps // 8
+    with_d2 = taps // 16 if taps >= 96 else taps // 8 - taps // 32
+    return (12.0 + 2.0 * with_d2 / quads) / outputs_per_lane
 
 
 def farrow_lds_per_sample(order: int) -> int:
@@ -201,7 +205,7 @@ def image_samples(plan, par):
 def fwd_work(plan, par, fd):
     if fd == "table":
         t = plan.forward_taps
-        return t * FLOPS_PER_TAP, t * table_lds_per_tap(plan.tuning()["outputs_per_lane"])
+        return t * FLOPS_PER_TAP, t * table_lds_per_tap(plan.tuning()["outputs_per_lane"], par.taps)
     s = image_samples(plan, par)
     return s * farrow_flops(par.farrow_order)["fwd"], s * farrow_lds_per_sample(par.farrow_order)
 
