@@ -222,9 +222,9 @@ msim_status msim_forward_batched(msim_plan* plan, const float* x, float* y, void
  * forward (a lane's samples share one track segment, so every tier decimation
  * must be 1 or a multiple of it; the table form takes 1 or 2 and its two samples
  * also share table rows, which needs the delay to drift by at most ~0.8 table rows
- * per sample: source plus receiver speed below 2.2 m/s at 128 phases; the Farrow
- * form takes 1, 2 or 4; 0: the form's default, 2 for the table form where allowed,
- * else 1), and the persistent grid size it implies. */
+ * per sample: source plus receiver speed below 2.2 m/s at 128 phases, 4.4 m/s at
+ * 64; the Farrow form takes 1, 2 or 4; 0: the form's default, 2 for the table form
+ * where allowed, else 1), and the persistent grid size it implies. */
 typedef struct {
     int32_t threads;
     int32_t group_cap;
