@@ -26,9 +26,13 @@ namespace msim {
 // Y(r) = (h((4g+e) + r/Lq)), e = 0..3; then the source window as overlapping
 // quads xw[p] = x[ws+p .. ws+p+3] (split by parity at two outputs per lane, one
 // entry more).
+// Image descriptors of a delay group staged in LDS at a time by the two-outputs
+// kernel (one chunk covers a group at the table form's default cap of 24 images).
+constexpr int kSynDescChunk = 32;
+
 size_t synth_lds_bytes(int taps, int Lq, int window)
 {
-    return qtab_bytes(taps, Lq) + (size_t)(window + 1) * sizeof(float4);
+    return qtab_bytes(taps, Lq) + (size_t)kSynDescChunk * 2 * sizeof(int4) + (size_t)(window + 1) * sizeof(float4);
 }
 
 // One delay group of an output tile [n0, n0 + NT) of one mic: stages the group's
@@ -155,8 +159,8 @@ __device__ inline void synth_group(const DScene& S, const DGroup& G, int n0, Slo
 // is below its accuracy bound.  Ends with a barrier.
 template <int T, int NT, int LC>
 __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Slot sl, const DImage* __restrict__ I,
-                                    const PermEntry* __restrict__ perm, const float4* tab, float4* xw, int Lr, const float* __restrict__ x, float& acc0,
-                                    float& acc1, int& bad)
+                                    const PermEntry* __restrict__ perm, const float4* tab, float4* xw, int4* dsc,
+                                    int Lr, const float* __restrict__ x, float& acc0, float& acc1, int& bad)
 {
     constexpr int NG = T / 8;
     constexpr int TO = 2 * NT;
@@ -169,50 +173,79 @@ __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Sl
     const int half = split_half(W);
     const int n_in = (int)S.n_in;
     stage_window_split(x + S.x_off, n_in, ws, W, xw, NT);
-    __syncthreads();
 
     const int n = n0 + 2 * tid;
     const int n_out = (int)S.n_out;
+    const bool active = n < n_out;
     // every lane's taps reach source samples for every image of the group (integer
     // delays within [dmin, dmax]): the per-image check is skipped
     const bool all_reach = n0 - G.dmax + T / 2 >= 0 && n0 + TO - G.dmin - T / 2 < n_in;
-    if (n < n_out) {
-        const float Lf = (float)L;
-        // Track data for both outputs: one segment when the image is decimated
-        // (every decimation is even, so n and n+1 share it), else the two
-        // full-rate delays (full-rate segments carry zero cubic terms, so the
-        // segment of n gives D(n) either way).  The lane's slot offsets depend
-        // only on the decimation R: they are kept for the last R seen (images of
-        // a group mostly share a tier).  Two buffers in turn, as in the
-        // one-output group.
+    const float Lf = (float)L;
+    // The group's image descriptors a chunk at a time in LDS (slot offset, R, gain
+    // factor, 1/R; k_lo = n0 / R), read there as wave-uniform values.  Track data
+    // for both outputs: one segment when the image is decimated (every decimation
+    // is even, so n and n+1 share it), else the two full-rate delays (full-rate
+    // segments carry zero cubic terms, so the segment of n gives D(n) either way).
+    // The lane's slot offsets depend only on the decimation R: they are kept for
+    // the last R seen (images of a group mostly share a tier).  Two buffers in
+    // turn, as in the one-output group.
+    for (int cb = G.img_begin; cb < G.img_end; cb += kSynDescChunk) {
+        const int nch = min(kSynDescChunk, G.img_end - cb);
+        __syncthreads();                 // window staged; the previous chunk's descriptors read
+        for (int i = tid; i < nch; i += NT) {
+            const PermEntry e = perm[cb + i];
+            const DImage& im = I[e.img];
+            dsc[2 * i] = make_int4(e.loc, im.R, __float_as_int(im.gfac), __float_as_int(im.invR));
+            dsc[2 * i + 1] = make_int4(div_exact(n0, im.R, im.invR), 0, 0, 0);
+        }
+        __syncthreads();
+        if (!active) continue;
         int cR = 0, c0 = 0, c1 = 0;        // slot indices of the segments of n and n+1
         float cv = 0.0f;                    // n relative to its segment start
-        auto fetch = [&](const DImage& im, Seg& q, float& a1, int& K0, int& K1, float& v) {
-            if (im.R != cR) {
-                cR = im.R;
-                if (cR == 1) {
+        struct Img {
+            int R;
+            float gfac;
+            Seg q;
+            float a1;
+            int K0, K1;
+            float v;
+        };
+        auto fetch = [&](int j, Img& m) {
+            const int4 d0 = dsc[2 * j];
+            const int loc = __builtin_amdgcn_readfirstlane(d0.x);
+            const int R = __builtin_amdgcn_readfirstlane(d0.y);
+            if (R != cR) {
+                cR = R;
+                if (R == 1) {
                     c0 = n - n0;
                     c1 = min(n + 1, n_out - 1) - n0;
                     cv = 0.0f;
                 } else {
-                    const int k0 = div_exact(n, cR, im.invR);
-                    c0 = c1 = k0 - div_exact(n0, cR, im.invR);
-                    cv = (float)(n - k0 * cR);
+                    const int k0 = div_exact(n, R, __int_as_float(d0.w));
+                    c0 = c1 = k0 - __builtin_amdgcn_readfirstlane(dsc[2 * j + 1].x);
+                    cv = (float)(n - k0 * R);
                 }
             }
-            const Seg* sb = sl.seg + im.loc;
-            const int32_t* kb = sl.K + im.loc;
-            q = sb[c0];
-            a1 = sb[c1].a0;
-            K0 = kb[c0];
-            K1 = kb[c1];
-            v = cv;
+            m.R = R;
+            m.gfac = __int_as_float(d0.z);
+            m.q = ld_at(sl.seg, (uint32_t)(loc + c0));
+            m.K0 = ld_at(sl.K, (uint32_t)(loc + c0));
+            if (R == 1) {
+                m.a1 = ld_at(sl.seg, (uint32_t)(loc + c1)).a0;
+                m.K1 = ld_at(sl.K, (uint32_t)(loc + c1));
+            } else {
+                m.a1 = 0.0f;
+                m.K1 = m.K0;
+            }
+            m.v = cv;
         };
-        auto body = [&](const DImage& im, const Seg& sg, float a1, int K0s, int K1s, float v) {
+        auto body = [&](const Img& m) {
+            const Seg& sg = m.q;
+            const float v = m.v;
             const float d0 = fmaf(v, fmaf(v, fmaf(v, sg.b3, sg.b2), sg.b1), sg.a0);
             const float v1 = v + 1.0f;
-            const float d1 = im.R == 1 ? a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
-            const PairFrame fr = pair_frame(d0, K0s, d1, K1s, L, Lf);
+            const float d1 = m.R == 1 ? m.a1 : fmaf(v1, fmaf(v1, fmaf(v1, sg.b3, sg.b2), sg.b1), sg.a0);
+            const PairFrame fr = pair_frame(d0, m.K0, d1, m.K1, L, Lf);
             const int K = fr.K;
             // skip the image when no lane's taps reach a source sample
             if (!all_reach && !__any(n - K + T / 2 >= 0 && n - K - T / 2 < n_in)) return;
@@ -227,26 +260,19 @@ __device__ inline void synth_group2(const DScene& S, const DGroup& G, int n0, Sl
             const float h0 = (Lf - fr.q0) - (float)fr.kp, h1 = (Lf - fr.q1) - (float)fr.kp;     // far side
             const float s0 = fmaf(qweight(h0), ps.Cm0, fmaf(qweight(f0), ps.C0, fmaf(h0, ps.Bm0, fmaf(f0, ps.B0, ps.A0))));
             const float s1 = fmaf(qweight(h1), ps.Cm1, fmaf(qweight(f1), ps.C1, fmaf(h1, ps.Bm1, fmaf(f1, ps.B1, ps.A1))));
-            acc0 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K0s + d0), s0, acc0);
-            acc1 = fmaf(im.gfac * __builtin_amdgcn_rcpf((float)K1s + d1), s1, acc1);
+            acc0 = fmaf(m.gfac * __builtin_amdgcn_rcpf((float)m.K0 + d0), s0, acc0);
+            acc1 = fmaf(m.gfac * __builtin_amdgcn_rcpf((float)m.K1 + d1), s1, acc1);
         };
-        Seg qa{}, qb{};
-        float a1a = 0.0f, a1b = 0.0f, ka = 0.0f, kb = 0.0f;
-        int K0a = 0, K1a = 0, K0b = 0, K1b = 0;
-        DImage ia = perm_image(I, perm, G.img_begin), ib;
-        fetch(ia, qa, a1a, K0a, K1a, ka);
-        int ii = G.img_begin;
-        for (; ii + 1 < G.img_end; ii += 2) {
-            ib = perm_image(I, perm, ii + 1);
-            fetch(ib, qb, a1b, K0b, K1b, kb);
-            body(ia, qa, a1a, K0a, K1a, ka);
-            if (ii + 2 < G.img_end) {
-                ia = perm_image(I, perm, ii + 2);
-                fetch(ia, qa, a1a, K0a, K1a, ka);
-            }
-            body(ib, qb, a1b, K0b, K1b, kb);
+        Img ia, ib;
+        fetch(0, ia);
+        int j = 0;
+        for (; j + 1 < nch; j += 2) {
+            fetch(j + 1, ib);
+            body(ia);
+            if (j + 2 < nch) fetch(j + 2, ia);
+            body(ib);
         }
-        if (ii < G.img_end) body(ia, qa, a1a, K0a, K1a, ka);
+        if (j < nch) body(ia);
     }
     __syncthreads();
 }
@@ -267,7 +293,8 @@ __global__ __launch_bounds__(NT, 4) void k_synth(PlanView pv, const float4* __re
     extern __shared__ float4 lds[];
     constexpr int TO = NT * RB;
     float4* tab = lds;
-    float4* xw = lds + qtab_bytes(T, L) / 16;
+    int4* dsc = (int4*)(lds + qtab_bytes(T, L) / 16);
+    float4* xw = (float4*)(dsc + 2 * kSynDescChunk);
     load_qtab<T>(table, tab, L, NT);
     const Slot sl = slot_at(ta.slots, ta.slot_bytes, ta.slot_segs, blockIdx.x);
     for_each_item(ticket, n_items, [&](int it) {
@@ -288,7 +315,7 @@ __global__ __launch_bounds__(NT, 4) void k_synth(PlanView pv, const float4* __re
             if constexpr (RB == 1)
                 synth_group<T, NT, LC>(S, G, n0, sl, I, pv.perm, tab, xw, L, x, acc0, bad);
             else
-                synth_group2<T, NT, LC>(S, G, n0, sl, I, pv.perm, tab, xw, L, x, acc0, acc1, bad);
+                synth_group2<T, NT, LC>(S, G, n0, sl, I, pv.perm, tab, xw, dsc, L, x, acc0, acc1, bad);
         }
         float* out = part + S.part_base + ((int64_t)w.mic * S.n_sg + w.sg) * S.n_out;
         const int n = n0 + RB * (int)threadIdx.x;
