@@ -45,8 +45,8 @@ size_t adj_x_lds_bytes(int taps, int Lq, int window, int tile)
 
 // Image descriptors staged in LDS at a time by the table form's gain/delay
 // kernel at two outputs per lane (one chunk covers a delay group at the table
-// form's default cap of 24 images).
-constexpr int kAdjDescChunk = 32;
+// form's default cap of 96 images).
+constexpr int kAdjDescChunk = 96;
 
 // The gain/delay kernels: the forward's LDS, then the slot offsets, the
 // parameter accumulators and a chunk of image descriptors.

@@ -1038,8 +1038,9 @@ msim_status regroup(msim_plan* P)
         for (int b = 0; b < d.n_blk; ++b) {
             const BlockOrder& o = P->orders[s][b];
             // Greedy groups in the block's delay order: an image joins the current
-            // group while the group keeps to the image cap (table form 24 images,
-            // 16-40 measured fastest on the paper-scale scene; Farrow form, whose
+            // group while the group keeps to the image cap (table form 96 images:
+            // against 24, the large workload's forward 2 %, dL/dx 7 % and gain/delay
+            // 15 % faster, the paper-scale scene's forward 9 %; Farrow form, whose
             // 48-byte window costs more to stage, 256) and its window (tile, delay
             // spread, filter) to the preferred limit: the largest that lets two
             // workgroups share one CU's LDS, unless that leaves more than 2.5 times
@@ -1048,7 +1049,7 @@ msim_status regroup(msim_plan* P)
             // early reflections) so ends a group where it occurs, and every other
             // group stays full.  An image whose own window exceeds the preferred
             // limit gets a group of its own, up to the LDS limit.
-            const int cap = std::min(kMaxGroup, P->group_cap > 0 ? P->group_cap : (farrow ? 256 : 24));
+            const int cap = std::min(kMaxGroup, P->group_cap > 0 ? P->group_cap : (farrow ? 256 : 96));
             auto window_of = [&](double lo, double hi) {
                 return NT + (((int)std::ceil(hi) + 4) - ((int)std::floor(lo) - 4)) + T + 8;
             };

@@ -27,8 +27,8 @@ namespace msim {
 // quads xw[p] = x[ws+p .. ws+p+3] (split by parity at two outputs per lane, one
 // entry more).
 // Image descriptors of a delay group staged in LDS at a time by the two-outputs
-// kernel (one chunk covers a group at the table form's default cap of 24 images).
-constexpr int kSynDescChunk = 32;
+// kernel (one chunk covers a group at the table form's default cap of 96 images).
+constexpr int kSynDescChunk = 96;
 
 size_t synth_lds_bytes(int taps, int Lq, int window)
 {
