@@ -218,7 +218,7 @@ msim_status msim_forward_batched(msim_plan* plan, const float* x, float* y, void
                                  hipStream_t stream, int32_t use_graph);
 
 /* Launch shape: output samples per workgroup (512 or 1024), images per delay
- * group (0: chosen from the tile count), adjacent output samples per lane of the
+ * group (0: the form's default, 96 table / 256 Farrow), adjacent output samples per lane of the
  * forward (a lane's samples share one track segment, so every tier decimation
  * must be 1 or a multiple of it; the table form takes 1 or 2 and its two samples
  * also share table rows, which needs the delay to drift by at most ~0.8 table rows

@@ -527,7 +527,7 @@ struct msim_plan {
     hipGraphExec_t bgraph_exec = nullptr;
     bool bgraph_valid = false;
     const void* bgraph_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int group_cap = 0;                    // images per delay group (0: chosen from the tile count)
+    int group_cap = 0;                    // images per delay group (0: the form's default)
     // work items: every scene's (mic, tile, supergroup) in decreasing-cost order
     // (batched), and per scene (plain: scene s's items at plain_off[s])
     std::vector<DScene> scenes_b;         // with batched partial-output bases set
