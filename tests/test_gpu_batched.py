@@ -178,3 +178,37 @@ def test_autotune_corrupt_cache_falls_back_to_timing(torch_cuda, tmp_path):
     torch.cuda.synchronize()
     for s, yv in enumerate(plan.unpack_y(y)):
         assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5
+
+
+@pytest.mark.parametrize("fd", [0, 1])
+def test_large_groups_forward_and_backward(torch_cuda, fd):
+    """Delay groups up to 512 images (more than one LDS chunk of image
+    descriptors in every kernel that stages them): forward, dL/dx and dL/dbeta
+    against the oracle, in the batched launch."""
+    import dataclasses
+    torch = torch_cuda
+    from paper_2508_03065_amd.msim import Plan
+    a, par = G.small_scene(seed=131, max_order=7, seconds=0.05, taps=64, n_mics=2)
+    b, _ = G.small_scene(seed=132, max_order=6, seconds=0.04, taps=64, moving_rcv=True)
+    scenes = [a, b]
+    par = dataclasses.replace(par, fd_kind=fd)
+    plan = Plan(scenes, par)
+    plan.set_tuning(1024, 512)
+    print("large groups, fd", fd, flush=True)
+    x = plan.pack_x([s.x for s in scenes])
+    y = plan.forward_batched(x)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    for s, yv in enumerate(plan.unpack_y(y)):
+        assert rel(yv.cpu().numpy(), O.forward(scenes[s], par)) <= 1e-5, s
+    rng = np.random.default_rng(17)
+    gys = [rng.standard_normal((s.n_mics, s.n_out)) for s in scenes]
+    gy = torch.from_numpy(np.concatenate([g.reshape(-1) for g in gys]).astype(np.float32)).cuda()
+    gx, gb, _ = plan.backward(x, gy, batched=True, want_src=False)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    gx, gb = gx.cpu().numpy(), gb.cpu().numpy()
+    for s, sc in enumerate(scenes):
+        o = plan.x_off[s]
+        assert rel(gx[o:o + sc.n_in], O.adjoint_x(sc, par, gys[s])) <= 1e-5, s
+        assert rel(gb[s], O.grad_beta(sc, par, gys[s])) <= 1e-4, s
